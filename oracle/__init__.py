@@ -1,0 +1,323 @@
+"""CPU oracle for the fast kernel-method path (TEST INFRASTRUCTURE ONLY).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the GPU
+library: its arithmetic is plain C in ``orc_*.c`` (built with gcc into
+``liborc.so``) plus the exact-rational brute-force layer in ``brute.py``.
+
+What it computes, and what pins each part (tests marked ``not gpu``):
+
+=====================  =====================================================
+lattice points         Sec. 4.2; natural == linear order element-wise via
+                       R_m(i) and as sets (stated in Sec. 4.2); g = 1 gives
+                       the van der Corput sequence
+net points             Sec. 4.3; GF(2) brute force on unpacked digits;
+                       stratification of the leading m digits; identity C
+                       gives van der Corput; Gray order vs Table 1
+SI factor              Sec. 5.2; truncated Fourier series with a tail bound;
+                       special values pi^2/3, -pi^2/6, pi^4/45, ...
+DSI factors a=2,3,4    Theorem 1; exact-rational Walsh series (eq. DSI_kernel)
+                       organised as in Appendix B; s~_4(0) = 1/294 (App. B);
+                       Walsh convention pinned by the Lemma of App. B
+DSI factor a=1         PARITY UNPINNED (reading K_1 = 1 - 3 t_1); pinned only
+                       by its own Walsh series
+FWHT / FFTBR / IFFTBR  Figure 3; direct O(n^2) Hadamard and W^{k R(j)} matrices;
+                       numpy FFT of the linear-order sequence; involution /
+                       inverse
+eig                    Sec. 5.4; closed-form Walsh / Fourier aliasing sums for
+                       d = 1; circulant / RSBT structure of the dense Gram
+solve, matvec, logdet  Sec. 5.4; dense Gram + Cholesky (numpy) at n <= 2^10
+update_double          Sec. 5.4 / eq. (ft_next_parts); equals the fresh
+                       transform of length 2n
+=====================  =====================================================
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liborc.so")
+_SRC = ["orc_points.c", "orc_kernels.c", "orc_algebra.c"]
+
+LATTICE, DNET = 0, 1
+NATURAL, LINEAR, GRAY = 0, 1, 2
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc into oracle/liborc.so."""
+    if force or not os.path.exists(_SO):
+        cmd = ["gcc", "-O2", "-std=gnu11", "-Wall", "-fPIC", "-shared", "-o", _SO + ".tmp"]
+        cmd += [os.path.join(_HERE, s) for s in _SRC] + ["-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        newest_src = max(os.path.getmtime(os.path.join(_HERE, s))
+                         for s in _SRC + ["orc.h", "orc_algebra.inc"])
+        if not os.path.exists(_SO) or os.path.getmtime(_SO) < newest_src:
+            build()
+        L = C.CDLL(_SO)
+        P = C.c_void_p
+        i32, i64, f64 = C.c_int, C.c_int64, C.c_double
+        sig = {
+            "orc_lattice_points": [i32, i32, i32, i32, i64, i64, P, P, P],
+            "orc_dnet_points": [i32, i32, i32, i32, i64, i64, P, P, P, P],
+            "orc_lms": [i32, i32, P, P, P],
+            "orc_kernel_column": [i32, i32, i32, i64, P, P, P, P, f64, P],
+            "orc_fwht": [i64, P], "orc_fftbr": [i64, P], "orc_ifftbr": [i64, P],
+            "orc_transform": [i32, i32, i32, i32, P, P],
+            "orc_transform_ld": [i32, i32, i32, i32, P, P],
+            "orc_eig": [i32, i32, i32, P, P, P], "orc_eig_ld": [i32, i32, i32, P, P],
+            "orc_solve": [i32, i32, i32, i32, P, f64, P, P],
+            "orc_solve_ld": [i32, i32, i32, i32, P, f64, P, P],
+            "orc_matvec": [i32, i32, i32, i32, P, P, P],
+            "orc_matvec_ld": [i32, i32, i32, i32, P, P, P],
+            "orc_logdet": [i32, i32, P, f64, P], "orc_logdet_ld": [i32, i32, P, f64, P],
+            "orc_update_double": [i32, i32, i32, P, P, P],
+            "orc_eig_update_double": [i32, i32, i32, P, P, P],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = C.c_int if name not in ("orc_fwht", "orc_fftbr", "orc_ifftbr") else None
+        L.orc_si_factor.argtypes = [i32, C.c_uint64]
+        L.orc_si_factor.restype = f64
+        L.orc_dsi_factor.argtypes = [i32, C.c_uint64]
+        L.orc_dsi_factor.restype = f64
+        L.orc_gray.argtypes = [C.c_uint64]
+        L.orc_gray.restype = C.c_uint64
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray | None):
+    return None if a is None else a.ctypes.data
+
+
+def _c(a, dtype):
+    return None if a is None else np.ascontiguousarray(a, dtype=dtype)
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise ValueError(f"oracle {what} failed with status {rc}")
+
+
+def kind_code(kind) -> int:
+    return {"lattice": LATTICE, "dnet": DNET, LATTICE: LATTICE, DNET: DNET}[kind]
+
+
+def order_code(order) -> int:
+    return {"natural": NATURAL, "linear": LINEAR, "gray": GRAY,
+            NATURAL: NATURAL, LINEAR: LINEAR, GRAY: GRAY}[order]
+
+
+# ---------------------------------------------------------------------------
+# Points
+# ---------------------------------------------------------------------------
+
+def lattice_points(g, shift, m: int, n_min: int, n_max: int, order="natural") -> np.ndarray:
+    g = _c(g, np.uint64)
+    shift = _c(shift, np.uint64)
+    R = 1 if shift is None else shift.shape[0]
+    d = g.shape[0]
+    out = np.empty((R, n_max - n_min, d), dtype=np.uint64)
+    _check(lib().orc_lattice_points(R, d, m, order_code(order), n_min, n_max, _p(g),
+                                    _p(shift), _p(out)), "lattice_points")
+    return out
+
+
+def dnet_points(C_, S, shift, m_max: int, n_min: int, n_max: int, order="natural",
+                R: int | None = None) -> np.ndarray:
+    C_ = _c(C_, np.uint64)
+    S = _c(S, np.uint64)
+    shift = _c(shift, np.uint64)
+    d = C_.shape[0]
+    if R is None:
+        R = S.shape[0] if S is not None else (shift.shape[0] if shift is not None else 1)
+    out = np.empty((R, n_max - n_min, d), dtype=np.uint64)
+    _check(lib().orc_dnet_points(R, d, m_max, order_code(order), n_min, n_max, _p(C_),
+                                 _p(S), _p(shift), _p(out)), "dnet_points")
+    return out
+
+
+def lms(C_, S1) -> np.ndarray:
+    """Scrambled generating matrices S_j C_j for one replication (S1: [d][64])."""
+    C_ = _c(C_, np.uint64)
+    S1 = _c(S1, np.uint64)
+    out = np.empty_like(C_)
+    _check(lib().orc_lms(C_.shape[0], C_.shape[1], _p(C_), _p(S1), _p(out)), "lms")
+    return out
+
+
+def gray(i: int) -> int:
+    return int(lib().orc_gray(i))
+
+
+def points(w: dict, n_min: int = 0, n_max: int | None = None, order=None) -> np.ndarray:
+    """Points of a workload dict (see ``workloads``)."""
+    m_max = w.get("m_max", w["m"])
+    n_max = 2 ** w["m"] if n_max is None else n_max
+    order = order or w.get("order", "natural")
+    if w["kind"] == "lattice":
+        return lattice_points(w["gen"], w["shift"], m_max, n_min, n_max, order)
+    return dnet_points(w["gen"], w["lms"], w["shift"], m_max, n_min, n_max, order,
+                       R=w["R"])
+
+
+# ---------------------------------------------------------------------------
+# Kernels
+# ---------------------------------------------------------------------------
+
+def si_factor(alpha: int, delta: int) -> float:
+    return lib().orc_si_factor(alpha, int(delta))
+
+
+def dsi_factor(alpha: int, delta: int) -> float:
+    return lib().orc_dsi_factor(alpha, int(delta))
+
+
+def kernel_column(kind, pts, x0, alpha, gamma, zeta: float) -> np.ndarray:
+    pts = _c(pts, np.uint64)
+    x0 = _c(x0, np.uint64)
+    R, n, d = pts.shape
+    alpha = _c(alpha, np.int32)
+    gamma = _c(gamma, np.float64)
+    out = np.empty((R, n), dtype=np.float64)
+    _check(lib().orc_kernel_column(kind_code(kind), R, d, n, _p(pts), _p(x0), _p(alpha),
+                                   _p(gamma), float(zeta), _p(out)), "kernel_column")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Transforms and Gram algebra
+# ---------------------------------------------------------------------------
+
+def fwht(x) -> np.ndarray:
+    x = np.array(x, dtype=np.float64, copy=True)
+    lib().orc_fwht(x.shape[-1], _p(x))
+    return x
+
+
+def fftbr(x) -> np.ndarray:
+    x = np.array(x, dtype=np.complex128, copy=True)
+    lib().orc_fftbr(x.shape[-1], _p(x))
+    return x
+
+
+def ifftbr(x) -> np.ndarray:
+    x = np.array(x, dtype=np.complex128, copy=True)
+    lib().orc_ifftbr(x.shape[-1], _p(x))
+    return x
+
+
+def transform(kind, x, inverse: bool = False, precise: bool = False) -> np.ndarray:
+    """Batched FFTBR/IFFTBR (lattice, complex) or FWHT (net, real) over the last axis."""
+    k = kind_code(kind)
+    dt = np.complex128 if k == LATTICE else np.float64
+    x = _c(x, dt)
+    n = x.shape[-1]
+    m = n.bit_length() - 1
+    B = x.size // n
+    out = np.empty_like(x)
+    fn = lib().orc_transform_ld if precise else lib().orc_transform
+    _check(fn(k, -1 if inverse else 1, B, m, _p(x), _p(out)), "transform")
+    return out
+
+
+def eig(kind, k1, precise: bool = False):
+    k1 = _c(k1, np.float64)
+    R, n = k1.shape
+    m = n.bit_length() - 1
+    lam = np.empty_like(k1)
+    if precise:
+        _check(lib().orc_eig_ld(kind_code(kind), R, m, _p(k1), _p(lam)), "eig_ld")
+        return lam
+    mi = np.zeros(1)
+    _check(lib().orc_eig(kind_code(kind), R, m, _p(k1), _p(lam), _p(mi)), "eig")
+    return lam, float(mi[0])
+
+
+def solve(kind, lam, sigma2: float, y, precise: bool = False) -> np.ndarray:
+    lam = _c(lam, np.float64)
+    y = _c(y, np.float64)
+    R, nrhs, n = y.shape
+    m = n.bit_length() - 1
+    c = np.empty_like(y)
+    fn = lib().orc_solve_ld if precise else lib().orc_solve
+    _check(fn(kind_code(kind), R, nrhs, m, _p(lam), float(sigma2), _p(y), _p(c)), "solve")
+    return c
+
+
+def matvec(kind, lam, y, precise: bool = False) -> np.ndarray:
+    lam = _c(lam, np.float64)
+    y = _c(y, np.float64)
+    R, nrhs, n = y.shape
+    m = n.bit_length() - 1
+    out = np.empty_like(y)
+    fn = lib().orc_matvec_ld if precise else lib().orc_matvec
+    _check(fn(kind_code(kind), R, nrhs, m, _p(lam), _p(y), _p(out)), "matvec")
+    return out
+
+
+def logdet(lam, sigma2: float, precise: bool = False) -> np.ndarray:
+    lam = _c(lam, np.float64)
+    R, n = lam.shape
+    m = n.bit_length() - 1
+    out = np.empty(R, dtype=np.float64)
+    fn = lib().orc_logdet_ld if precise else lib().orc_logdet
+    rc = fn(R, m, _p(lam), float(sigma2), _p(out))
+    if rc not in (0, -4):
+        _check(rc, "logdet")
+    return out
+
+
+def update_double(kind, yt_old, y_new) -> np.ndarray:
+    k = kind_code(kind)
+    y_new = _c(y_new, np.float64)
+    B, n = y_new.shape
+    m = n.bit_length() - 1
+    yt_old = _c(yt_old, np.complex128 if k == LATTICE else np.float64)
+    out = np.empty((B, 2 * n), dtype=yt_old.dtype)
+    _check(lib().orc_update_double(k, B, m, _p(yt_old), _p(y_new), _p(out)), "update_double")
+    return out
+
+
+def eig_update_double(kind, lam_old, k1_new) -> np.ndarray:
+    lam_old = _c(lam_old, np.float64)
+    k1_new = _c(k1_new, np.float64)
+    R, n = lam_old.shape
+    m = n.bit_length() - 1
+    out = np.empty((R, 2 * n), dtype=np.float64)
+    _check(lib().orc_eig_update_double(kind_code(kind), R, m, _p(lam_old), _p(k1_new),
+                                       _p(out)), "eig_update_double")
+    return out
+
+
+def fit_solve(w: dict, y=None, precise: bool = False) -> dict:
+    """Whole path for one workload: points -> k1 -> lambda -> c, logdet."""
+    pts = points(w)
+    x0 = points(w, 0, 1)[:, 0, :]
+    k1 = kernel_column(w["kind"], pts, x0, w["alpha"], w["gamma"], w["zeta"])
+    lam, mi = eig(w["kind"], k1)
+    y = w["y"] if y is None else y
+    c = solve(w["kind"], lam, w["sigma2"], y)
+    ld = logdet(lam, w["sigma2"])
+    out = dict(pts=pts, k1=k1, lam=lam, max_imag=mi, c=c, logdet=ld)
+    if precise:
+        lam_ld = eig(w["kind"], k1, precise=True)
+        out["lam_ld"] = lam_ld
+        out["c_ld"] = solve(w["kind"], lam_ld, w["sigma2"], y, precise=True)
+        out["logdet_ld"] = logdet(lam_ld, w["sigma2"], precise=True)
+    return out

@@ -1,0 +1,79 @@
+/*
+ * Oracle for the fast kernel-method path: plain, slow, obviously correct CPU
+ * code in FP64 (and an 80-bit long-double twin of the transforms used only
+ * to measure the FP64 oracle's own rounding error).
+ *
+ * THIS IS TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load it.  It shares no code, header,
+ * table or constant with the GPU library, and neither side includes or
+ * links the other.
+ *
+ * Parity status of each function (what pins it) is listed in the Python
+ * wrapper's module docstring; the DSI order-1 factor is "parity unpinned"
+ * against the paper (it is a stated reading, pinned only by its own Walsh
+ * series).
+ *
+ * Conventions: a coordinate is a uint64 u holding the first 64 base-2 digits
+ * of x in [0,1), digit t (weight 2^-t, t = 1..64) at bit 64 - t; its FP64
+ * value is (u >> 11) * 2^-53 (exact truncation).
+ */
+#ifndef LDK_ORACLE_ORC_H
+#define LDK_ORACLE_ORC_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_LATTICE = 0, ORC_DNET = 1 };
+enum { ORC_NATURAL = 0, ORC_LINEAR = 1, ORC_GRAY = 2 };
+
+/* Sec. 4.2 */
+int orc_lattice_points(int R, int d, int m, int order, int64_t n_min, int64_t n_max,
+                       const uint64_t *g, const uint64_t *shift, uint64_t *out);
+/* Sec. 4.3 (b = 2): LMS, digital shift, natural or Gray order */
+int orc_dnet_points(int R, int d, int m_max, int order, int64_t n_min, int64_t n_max,
+                    const uint64_t *C, const uint64_t *S, const uint64_t *shift,
+                    uint64_t *out);
+int orc_lms(int d, int m, const uint64_t *C, const uint64_t *S, uint64_t *Ct);
+uint64_t orc_gray(uint64_t i);
+
+/* Sec. 5.2 (Bernoulli SI factor) and Sec. 5.3 / Theorem 1 (DSI factor) */
+double orc_si_factor(int alpha, uint64_t delta);
+double orc_dsi_factor(int alpha, uint64_t delta);
+int orc_kernel_column(int kind, int R, int d, int64_t n, const uint64_t *pts,
+                      const uint64_t *x0, const int *alpha, const double *gamma,
+                      double zeta, double *k1);
+
+/* Figure 3 transforms, orthonormal, in place. Complex = interleaved (re, im). */
+void orc_fwht(int64_t n, double *x);
+void orc_fftbr(int64_t n, double *xc);
+void orc_ifftbr(int64_t n, double *xc);
+
+/* Sec. 5.4 fast Gram algebra, batched over rows.  All arrays double.
+ * kind selects FFTBR (lattice, complex spectra) or FWHT (net, real). */
+int orc_transform(int kind, int dir, int B, int m, const double *in, double *out);
+int orc_eig(int kind, int R, int m, const double *k1, double *lam, double *max_imag);
+int orc_solve(int kind, int R, int nrhs, int m, const double *lam, double sigma2,
+              const double *y, double *c);
+int orc_matvec(int kind, int R, int nrhs, int m, const double *lam, const double *y,
+               double *out);
+int orc_logdet(int R, int m, const double *lam, double sigma2, double *out);
+int orc_update_double(int kind, int B, int m, const double *yt_old, const double *y_new,
+                      double *yt_full);
+int orc_eig_update_double(int kind, int R, int m, const double *lam_old,
+                          const double *k1_new, double *lam_full);
+
+/* Long-double twins (inputs/outputs double, arithmetic in long double). */
+int orc_eig_ld(int kind, int R, int m, const double *k1, double *lam);
+int orc_solve_ld(int kind, int R, int nrhs, int m, const double *lam, double sigma2,
+                 const double *y, double *c);
+int orc_matvec_ld(int kind, int R, int nrhs, int m, const double *lam, const double *y,
+                  double *out);
+int orc_logdet_ld(int R, int m, const double *lam, double sigma2, double *out);
+int orc_transform_ld(int kind, int dir, int B, int m, const double *in, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,194 @@
+"""Seeded synthetic inputs for the fast kernel-method path.
+
+This module is shared by the oracle-side tests and the GPU-side tests and
+benchmark.  It only draws random numbers and lays them out; it holds none of
+the method's arithmetic (no point generation, no kernel, no transform).
+
+Layouts (all little-endian, row-major):
+
+* lattice generating vector ``g``: ``uint64[d]``, odd, ``< 2**m_max``
+  (Sec. 4.2: rank-1 lattice with generating vector g).
+* digital-net generating matrices ``C``: ``uint64[d][m_max]``, one word per
+  column k; the digit of weight ``2**-(t+1)`` (row t) is bit ``63 - t``
+  (Sec. 4.3: generating matrices C_j in {0,1}^{t_max x m}, t_max = 64).
+* linear matrix scrambling ``S``: ``uint64[R][d][64]``, one word per row t;
+  entry (t, s) is bit ``63 - s``; unit lower-triangular (Matousek, Sec. 4.3).
+* shifts: ``uint64[R][d]``; a digital shift's digit t is bit ``63 - t``; a
+  lattice shift is the 64-bit fixed-point value ``Delta * 2**64``.
+
+The five named workloads follow the shapes of the fast-kernel experiments:
+the seed of ``workload(k)`` is ``k``; draw order is generating vector or
+matrices, then S, then shifts, then responses, looping over replications or
+instances in index order.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+U64 = np.uint64
+
+
+def _u64(rng: np.random.Generator, shape) -> np.ndarray:
+    return rng.integers(0, 2**64, size=shape, dtype=np.uint64, endpoint=False)
+
+
+def lattice_generating_vector(rng: np.random.Generator, d: int, m: int) -> np.ndarray:
+    """Random odd integers in [1, 2**m): g_j = 2*U{0..2**(m-1)-1} + 1."""
+    if m == 0:
+        return np.ones(d, dtype=np.uint64)
+    half = rng.integers(0, 2 ** (m - 1), size=d, dtype=np.uint64)
+    return (half * U64(2) + U64(1)).astype(np.uint64)
+
+
+def net_generating_matrices(rng: np.random.Generator, d: int, m: int) -> np.ndarray:
+    """Random 64 x m matrices, unit upper-triangular in their top m rows.
+
+    Rows 0..m-1 form a unit upper-triangular m x m block (random bits above
+    the diagonal, zeros below); rows m..63 are random bits.  Returned as
+    ``uint64[d][m]`` columns with row t at bit 63 - t.
+    """
+    cols = np.zeros((d, m), dtype=np.uint64)
+    for j in range(d):
+        for k in range(m):
+            w = int(_u64(rng, 1)[0])
+            # keep rows t < k (bits 63..64-k) random, set row k, clear rows k+1..m-1,
+            # keep rows >= m random
+            keep_top = ((1 << k) - 1) << (64 - k) if k > 0 else 0
+            keep_low = (1 << (64 - m)) - 1 if m < 64 else 0
+            w = (w & (keep_top | keep_low)) | (1 << (63 - k))
+            cols[j, k] = w
+    return cols
+
+
+def lms_matrices(rng: np.random.Generator, R: int, d: int) -> np.ndarray:
+    """Unit lower-triangular 64 x 64 scrambles (Matousek), ``uint64[R][d][64]`` rows."""
+    out = np.zeros((R, d, 64), dtype=np.uint64)
+    for r in range(R):
+        for j in range(d):
+            words = _u64(rng, 64)
+            for t in range(64):
+                below = ((1 << t) - 1) << (64 - t) if t > 0 else 0  # columns s < t
+                out[r, j, t] = (int(words[t]) & below) | (1 << (63 - t))
+    return out
+
+
+def shifts(rng: np.random.Generator, R: int, d: int) -> np.ndarray:
+    """Uniform 64-bit shifts ``uint64[R][d]`` (digital or fixed-point)."""
+    return _u64(rng, (R, d))
+
+
+def to_unit_f64(u: np.ndarray) -> np.ndarray:
+    """Float view of 64-bit fixed-point coordinates: (u >> 11) * 2**-53 (exact)."""
+    return (np.asarray(u, dtype=np.uint64) >> U64(11)).astype(np.float64) * 2.0**-53
+
+
+def sine_response(x: np.ndarray, eps: np.ndarray) -> np.ndarray:
+    """y = sum_j sin(2 pi x_j) / j + eps for points x of shape (..., n, d)."""
+    d = x.shape[-1]
+    w = 1.0 / np.arange(1, d + 1, dtype=np.float64)
+    return np.sin(2.0 * math.pi * x) @ w + eps
+
+
+# ---------------------------------------------------------------------------
+# Named workloads
+# ---------------------------------------------------------------------------
+
+def workload(k: int) -> dict:
+    """The five workloads: 1 parity net, 2 lattice n=2^20, 3 net n=2^20,
+    4 batched mixed instances, 5 marginal-likelihood gradient."""
+    return {1: _w1, 2: _w2, 3: _w3, 4: _w4, 5: _w5}[k]()
+
+
+def _w1() -> dict:
+    rng = np.random.default_rng(1)
+    m, d, R = 10, 4, 1
+    C = net_generating_matrices(rng, d, m)
+    S = lms_matrices(rng, R, d)
+    D = shifts(rng, R, d)
+    y = rng.standard_normal((R, 1, 2**m))
+    return dict(name="net_m10_d4_dsi1", kind="dnet", order="natural", m=m, d=d, R=R,
+                gen=C, lms=S, shift=D, alpha=np.full(d, 1, np.int32),
+                gamma=np.ones(d), zeta=1.0, sigma2=1e-8, y=y, nrhs=1)
+
+
+def _w2() -> dict:
+    rng = np.random.default_rng(2)
+    m, d, R = 20, 32, 1
+    g = lattice_generating_vector(rng, d, m)
+    D = shifts(rng, R, d)
+    eps = rng.normal(0.0, math.sqrt(1e-3), size=(R, 1, 2**m))
+    return dict(name="lattice_m20_d32_si2", kind="lattice", order="natural", m=m, d=d, R=R,
+                gen=g, lms=None, shift=D, alpha=np.full(d, 2, np.int32),
+                gamma=1.0 / np.arange(1, d + 1, dtype=np.float64) ** 2, zeta=1.0,
+                sigma2=1e-3, eps=eps, nrhs=1)
+
+
+def _w3() -> dict:
+    rng = np.random.default_rng(3)
+    m, d, R = 20, 32, 1
+    C = net_generating_matrices(rng, d, m)
+    S = lms_matrices(rng, R, d)
+    D = shifts(rng, R, d)
+    y = rng.standard_normal((R, 1, 2**m))
+    return dict(name="net_m20_d32_dsi4", kind="dnet", order="natural", m=m, d=d, R=R,
+                gen=C, lms=S, shift=D, alpha=np.full(d, 4, np.int32),
+                gamma=0.5 ** np.arange(1, d + 1, dtype=np.float64), zeta=1.0,
+                sigma2=1e-8, y=y, nrhs=1)
+
+
+def _w4() -> dict:
+    rng = np.random.default_rng(4)
+    n_inst, d, nrhs, mmax = 256, 16, 8, 18
+    m_r = rng.integers(12, 19, size=n_inst)
+    kinds = rng.integers(0, 2, size=n_inst)  # 0 lattice, 1 net
+    g = lattice_generating_vector(rng, d, mmax)
+    C = net_generating_matrices(rng, d, mmax)
+    inst = []
+    for r in range(n_inst):
+        S = lms_matrices(rng, 1, d) if kinds[r] == 1 else None
+        D = shifts(rng, 1, d)
+        y = rng.standard_normal((1, nrhs, 2 ** int(m_r[r])))
+        inst.append(dict(kind="dnet" if kinds[r] == 1 else "lattice", m=int(m_r[r]), lms=S,
+                         shift=D, y=y))
+    return dict(name="batched_256_mixed_d16", d=d, nrhs=nrhs, m_max=mmax, lattice_gen=g,
+                net_gen=C, alpha=np.full(d, 2, np.int32),
+                gamma=1.0 / np.arange(1, d + 1, dtype=np.float64) ** 2, zeta=1.0,
+                sigma2=1e-8, instances=inst)
+
+
+def _w5() -> dict:
+    rng = np.random.default_rng(5)
+    m, d, R = 16, 64, 64
+    C = net_generating_matrices(rng, d, m)
+    S = lms_matrices(rng, R, d)
+    D = shifts(rng, R, d)
+    y = rng.standard_normal((R, 1, 2**m))
+    return dict(name="net_m16_d64_r64_dsi2_grad", kind="dnet", order="natural", m=m, d=d,
+                R=R, gen=C, lms=S, shift=D, alpha=np.full(d, 2, np.int32),
+                gamma=1.0 / np.arange(1, d + 1, dtype=np.float64) ** 2, zeta=1.0,
+                sigma2=1e-3, y=y, nrhs=1)
+
+
+def small_net(seed: int, m: int, d: int, R: int = 1, m_max: int | None = None,
+              nrhs: int = 1) -> dict:
+    """A random net instance of any size (LMS + digital shift)."""
+    rng = np.random.default_rng(seed)
+    mm = m if m_max is None else m_max
+    C = net_generating_matrices(rng, d, mm)
+    S = lms_matrices(rng, R, d)
+    D = shifts(rng, R, d)
+    y = rng.standard_normal((R, nrhs, 2**m))
+    return dict(kind="dnet", m=m, m_max=mm, d=d, R=R, gen=C, lms=S, shift=D, y=y)
+
+
+def small_lattice(seed: int, m: int, d: int, R: int = 1, m_max: int | None = None,
+                  nrhs: int = 1) -> dict:
+    """A random shifted-lattice instance of any size."""
+    rng = np.random.default_rng(seed)
+    mm = m if m_max is None else m_max
+    g = lattice_generating_vector(rng, d, mm)
+    D = shifts(rng, R, d)
+    y = rng.standard_normal((R, nrhs, 2**m))
+    return dict(kind="lattice", m=m, m_max=mm, d=d, R=R, gen=g, lms=None, shift=D, y=y)
