@@ -1,0 +1,209 @@
+/*
+ * ldk.h -- C ABI of the MI355X (gfx950) fast kernel-method library.
+ *
+ * Fast Gram-matrix algebra on randomized low-discrepancy point sets, after
+ * "QMCPy: randomized low-discrepancy sequences, quasi-Monte Carlo, and fast
+ * kernel methods" (arXiv 2502.14256):
+ *   - randomized rank-1 lattices and base-2 digital nets as exact 64-digit
+ *     words (Sec. 4.2, 4.3);
+ *   - the first column of product-weight shift-invariant (SI, lattice) or
+ *     digitally-shift-invariant (DSI, net) Gram matrices (Sec. 5.2, 5.3,
+ *     Theorem 1);
+ *   - eigenvalues, matvec, solve and log-det through FFTBR/IFFTBR (lattice)
+ *     or the FWHT (net), and the transform update that doubles n (Sec. 5.4).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every data pointer is a DEVICE pointer owned by the caller (HIP device
+ *    memory on the current device).  Struct arguments themselves live in
+ *    host memory.  The library never allocates or frees caller memory.
+ *  - Calls validate their arguments on the host, then enqueue kernels on
+ *    `stream` and return without synchronising; outputs are valid once the
+ *    stream has reached that point.  An invalid call enqueues nothing.
+ *  - Return value: LDK_OK (0) or a negative ldk_status.  After LDK_EDEVICE
+ *    the HIP error of the failing call is available from ldk_last_hip_error()
+ *    (per host thread).  No C++ exception crosses this boundary.
+ *  - Sizes: transforms act on n = 2^m entries, 0 <= m <= LDK_MAX_M (the
+ *    update entry points need m + 1 <= LDK_MAX_M).  Arrays are contiguous and
+ *    row-major; batch dimensions come first.
+ *  - A coordinate is a uint64 word u holding the first 64 base-2 digits of
+ *    x in [0,1): digit t (weight 2^-t, t = 1..64) is bit 64 - t.  Floating
+ *    kernels use x = u * 2^-64 rounded to nearest.
+ *  - Real data are double (LDK_F64) or float (LDK_F32) as selected by
+ *    `dtype`; complex data are interleaved (re, im) pairs of that type.  The
+ *    nugget sigma^2 is added, and divided by, in FP64 for either dtype.
+ *  - Calls are reentrant.  Twiddle tables are built once per device by
+ *    ldk_init() (called implicitly by the first entry point that needs it;
+ *    call it explicitly before capturing calls into a HIP graph).
+ */
+#ifndef LDK_H
+#define LDK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Opaque stream handle: pass a hipStream_t (or 0 for the null stream). */
+typedef void *ldk_stream;
+
+#define LDK_MAX_M 26 /* largest transform length log2(n) (eig, solve, ...) */
+#define LDK_MAX_D 4096 /* largest supported dimension */
+
+typedef enum {
+    LDK_OK = 0,
+    LDK_EINVAL = -1,  /* bad argument (nothing enqueued) */
+    LDK_ENOTSUP = -2, /* valid but unsupported combination */
+    LDK_EDEVICE = -3, /* a HIP call failed; see ldk_last_hip_error() */
+    LDK_ENOTSPD = -4  /* some lambda_k + sigma^2 <= 0 (checked entry points) */
+} ldk_status;
+
+typedef enum { LDK_LATTICE = 0, LDK_DNET_B2 = 1 } ldk_kind;
+typedef enum { LDK_NATURAL = 0, LDK_LINEAR = 1, LDK_GRAY = 2 } ldk_order;
+typedef enum { LDK_F64 = 0, LDK_F32 = 1 } ldk_dtype;
+
+/* A randomized low-discrepancy point set (host struct, device arrays).
+ *  kind  LDK_LATTICE: rank-1 lattice sequence z_i = v(i) g mod 1 (Sec. 4.2,
+ *        van der Corput v of Sec. 4.1), shifted x_i = (z_i + Delta) mod 1.
+ *        order NATURAL (radical inverse, extensible) or LINEAR (fixed
+ *        n = 2^m_max: z_i = i g / n mod 1).
+ *        gen = g[d] (uint64; only g mod 2^64 matters).
+ *  kind  LDK_DNET_B2: base-2 digital net z_ij = F(C_j D(i) mod 2) (Sec. 4.3),
+ *        with linear matrix scrambling Ct_j = S_j C_j mod 2 and digital shift
+ *        x_ij = z_ij XOR Delta_j.  order NATURAL or GRAY (point i uses the
+ *        digit vector of i XOR (i >> 1); Table 1).
+ *        gen = C[d][m_max]: one word per column k, row t at bit 63 - t.
+ *        lms = S[R][d][64]: one word per row t, entry (t, s) at bit 63 - s,
+ *        or NULL for no scrambling.
+ *  shift = Delta[R][d] (digital shift digits, or the 64-bit fixed-point
+ *        lattice shift), or NULL for none.
+ *  R     number of independent randomizations (replications), >= 1.
+ *  m_max points exist for indices 0 <= i < 2^m_max (nets, linear lattices);
+ *        natural-order lattices accept any i < 2^62. */
+typedef struct {
+    int32_t kind;
+    int32_t order;
+    int32_t R;
+    int32_t d;
+    int32_t m_max;
+    int32_t reserved;
+    const uint64_t *gen;
+    const uint64_t *lms;
+    const uint64_t *shift;
+} ldk_pointset;
+
+/* Product-weight kernel  K(x, x') = zeta prod_j (1 + gamma_j K_{alpha_j}(x_j (-) x'_j)).
+ *  kind  LDK_LATTICE: SI factor (Sec. 5.2, eq. K_SI_prod)
+ *        K_a(x) = (2 pi)^{2a} / ((-1)^{a+1} (2a)!) B_{2a}(x), x = (u - u') mod 1,
+ *        alpha_j in {1, 2, 3}.
+ *  kind  LDK_DNET_B2: DSI factor (Sec. 5.3, Theorem 1), x = u XOR u',
+ *        alpha_j in {1, 2, 3, 4}; alpha = 1 is the order-1 kernel
+ *        K_1(x) = 1 - 3 * 2^{-beta(x)} (a reading: the paper defers its form
+ *        to the literature).
+ *  alpha = device int32[d]; gamma = device double[d]; zeta > 0.  The alpha
+ *  values are read on the device: an unsupported order yields NaN entries. */
+typedef struct {
+    int32_t kind;
+    int32_t d;
+    const int32_t *alpha;
+    const double *gamma;
+    double zeta;
+} ldk_kernel;
+
+/* Build the per-device twiddle tables (once per device; thread safe).
+ * Synchronous.  Returns LDK_OK or LDK_EDEVICE. */
+int ldk_init(void);
+
+/* Points i = n_min .. n_max-1 of every replication (Sec. 4.2, 4.3).
+ * out = uint64[R][n_max - n_min][d].  Requires 0 <= n_min <= n_max and, for
+ * nets and linear lattices, n_max <= 2^m_max. */
+int ldk_gen_points(const ldk_pointset *ps, int64_t n_min, int64_t n_max, uint64_t *out,
+                   ldk_stream stream);
+
+/* First Gram column k1_i = K(x_i, x_0) for i = n_min .. n_max-1 (Sec. 5.4:
+ * only the first column is stored).  Points come from `pts` =
+ * uint64[R][n_max - n_min][d] with anchor rows x0 = uint64[R][d] (x0 may be
+ * NULL when n_min == 0: row 0 of pts is then the anchor), or, when pts is
+ * NULL, are regenerated on the fly from `ps` with the anchor at index 0.
+ * ps must be given in both cases (it supplies R, d and kind).
+ * k->kind must equal ps->kind.  out = dtype[R][n_max - n_min]. */
+int ldk_kernel_column(const ldk_kernel *k, const ldk_pointset *ps, const uint64_t *pts,
+                      const uint64_t *x0, int64_t n_min, int64_t n_max, int dtype,
+                      void *out, ldk_stream stream);
+
+/* Orthonormal transform of B rows of length n = 2^m (Figure 3, Sec. 5.2-5.3).
+ *  LDK_LATTICE: complex rows; dir = +1 FFTBR  y_k = n^-1/2 sum_j x_j W^{k R_m(j)},
+ *               dir = -1 IFFTBR (its inverse), W = exp(-2 pi i / n).
+ *  LDK_DNET_B2: real rows; FWHT  y_k = n^-1/2 sum_j (-1)^{popcount(j & k)} x_j
+ *               (dir ignored: the FWHT is its own inverse).
+ * in and out may alias exactly (in place).  ws: workspace of
+ * ldk_workspace_bytes(LDK_OP_TRANSFORM, ...) bytes (may be NULL if 0). */
+int ldk_transform(int kind, int dir, int B, int m, int dtype, const void *in, void *out,
+                  void *ws, ldk_stream stream);
+
+/* Eigenvalues lambda = sqrt(n) conj(V_m) k1 (Sec. 5.4): sqrt(n) FFTBR(k1)
+ * (lattice; real since K is real symmetric) or sqrt(n) FWHT(k1) (net).
+ * k1, lam = real dtype[R][n], natural frequency / Walsh order. */
+int ldk_eig(int kind, int R, int m, int dtype, const void *k1, void *lam, void *ws,
+            ldk_stream stream);
+
+/* Solve (K + sigma^2 I) c = y:  c = V (conj(V) y (/) (lambda + sigma^2)) (Sec. 5.4).
+ * lam = dtype[R][n], y, c = dtype[R][nrhs][n] (y and c may alias exactly).
+ * sigma2 >= 0; the division is done in FP64. */
+int ldk_solve(int kind, int R, int nrhs, int m, int dtype, const void *lam, double sigma2,
+              const void *y, void *c, void *ws, ldk_stream stream);
+
+/* Matvec K y = V (conj(V) y (.) lambda) (Sec. 5.4); layout as ldk_solve. */
+int ldk_matvec(int kind, int R, int nrhs, int m, int dtype, const void *lam, const void *y,
+               void *out, void *ws, ldk_stream stream);
+
+/* log det(K + sigma^2 I) = sum_k log(lambda_k + sigma^2) (V unitary, Sec. 5.4),
+ * accumulated in FP64 in a fixed order.  out = device double[R]; a row with
+ * some lambda_k + sigma^2 <= 0 yields NaN.  ws: ldk_workspace_bytes(LDK_OP_LOGDET). */
+int ldk_logdet(int R, int m, int dtype, const void *lam, double sigma2, double *out,
+               void *ws, ldk_stream stream);
+
+/* Transform update when n doubles (Sec. 5.4, eq. ft_next_parts and its listings):
+ *   yt_full = 2^-1/2 [ yt_old + w (.) FT_m(y_new) ; yt_old - w (.) FT_m(y_new) ],
+ * w_k = exp(-pi i k / n) (lattice, FT = FFTBR) or 1 (net, FT = FWHT).
+ * yt_old = [B][n] (complex for lattice, real for net), y_new = real [B][n],
+ * yt_full = [B][2n] (complex for lattice, real for net).
+ * Equals FT_{m+1} of the concatenation [y_old ; y_new]. */
+int ldk_update_double(int kind, int B, int m, int dtype, const void *yt_old,
+                      const void *y_new, void *yt_full, void *ws, ldk_stream stream);
+
+/* Eigenvalue update when n doubles:  with lh = sqrt(n) FT_m(k1_new),
+ *   lam_full = [ lam_old + Re(w (.) lh) ; lam_old - Re(w (.) lh) ],
+ * k1_new = first-column entries of points n .. 2n-1.  lam_old, k1_new =
+ * real [R][n]; lam_full = real [R][2n]. */
+int ldk_eig_update_double(int kind, int R, int m, int dtype, const void *lam_old,
+                          const void *k1_new, void *lam_full, void *ws, ldk_stream stream);
+
+typedef enum {
+    LDK_OP_TRANSFORM = 0,
+    LDK_OP_EIG = 1,
+    LDK_OP_SOLVE = 2,
+    LDK_OP_MATVEC = 3,
+    LDK_OP_LOGDET = 4,
+    LDK_OP_UPDATE_DOUBLE = 5,
+    LDK_OP_EIG_UPDATE_DOUBLE = 6
+} ldk_op;
+
+/* Workspace bytes needed by `op` for B rows (or R * nrhs rows) of 2^m. */
+size_t ldk_workspace_bytes(int op, int kind, int64_t B, int m, int dtype);
+
+/* Human-readable status string (static storage). */
+const char *ldk_strerror(int status);
+
+/* hipError_t of the last failing HIP call on this host thread (0 if none). */
+int ldk_last_hip_error(void);
+
+/* Library version, "major.minor.patch". */
+const char *ldk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LDK_H */

@@ -1,0 +1,308 @@
+"""Fast kernel methods on randomized low-discrepancy point sets, on MI355X.
+
+Python binding of ``libldk.so`` (C ABI in ``include/ldk.h``).  The binding
+only marshals arguments: every step runs in the library's HIP kernels, on
+the current torch stream.  Torch tensors provide device memory; 64-bit
+coordinate words are held in ``torch.int64`` tensors (bit patterns; view
+them as uint64 on the host).
+
+Raises ``LdkError`` if the library is missing or a call fails: there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libldk.so")
+
+LATTICE, DNET_B2 = 0, 1
+NATURAL, LINEAR, GRAY = 0, 1, 2
+F64, F32 = 0, 1
+OP_TRANSFORM, OP_EIG, OP_SOLVE, OP_MATVEC, OP_LOGDET, OP_UPDATE_DOUBLE, OP_EIG_UPDATE_DOUBLE = range(7)
+
+EXPORTS = [
+    "ldk_init", "ldk_gen_points", "ldk_kernel_column", "ldk_transform", "ldk_eig", "ldk_solve",
+    "ldk_matvec", "ldk_logdet", "ldk_update_double", "ldk_eig_update_double",
+    "ldk_workspace_bytes", "ldk_strerror", "ldk_last_hip_error", "ldk_version",
+]
+
+
+class LdkError(RuntimeError):
+    pass
+
+
+class _Pointset(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("order", C.c_int32), ("R", C.c_int32), ("d", C.c_int32),
+                ("m_max", C.c_int32), ("reserved", C.c_int32), ("gen", C.c_void_p),
+                ("lms", C.c_void_p), ("shift", C.c_void_p)]
+
+
+class _Kernel(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("d", C.c_int32), ("alpha", C.c_void_p),
+                ("gamma", C.c_void_p), ("zeta", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libldk.so (built by ``paper_2502_14256_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise LdkError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        P, i32, i64, f64 = C.c_void_p, C.c_int, C.c_int64, C.c_double
+        sig = {
+            "ldk_init": ([], i32),
+            "ldk_gen_points": ([P, i64, i64, P, P], i32),
+            "ldk_kernel_column": ([P, P, P, P, i64, i64, i32, P, P], i32),
+            "ldk_transform": ([i32, i32, i32, i32, i32, P, P, P, P], i32),
+            "ldk_eig": ([i32, i32, i32, i32, P, P, P, P], i32),
+            "ldk_solve": ([i32, i32, i32, i32, i32, P, f64, P, P, P, P], i32),
+            "ldk_matvec": ([i32, i32, i32, i32, i32, P, P, P, P, P], i32),
+            "ldk_logdet": ([i32, i32, i32, P, f64, P, P, P], i32),
+            "ldk_update_double": ([i32, i32, i32, i32, P, P, P, P, P], i32),
+            "ldk_eig_update_double": ([i32, i32, i32, i32, P, P, P, P, P], i32),
+            "ldk_workspace_bytes": ([i32, i32, i64, i32, i32], C.c_size_t),
+            "ldk_strerror": ([i32], C.c_char_p),
+            "ldk_last_hip_error": ([], i32),
+            "ldk_version": ([], C.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        msg = lib().ldk_strerror(rc).decode()
+        raise LdkError(f"{what}: {msg} (status {rc}, hip error {lib().ldk_last_hip_error()})")
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dtype_code(dt: torch.dtype) -> int:
+    if dt in (torch.float64, torch.complex128):
+        return F64
+    if dt in (torch.float32, torch.complex64):
+        return F32
+    raise LdkError(f"unsupported dtype {dt}")
+
+
+def _real(dtype_code: int):
+    return torch.float64 if dtype_code == F64 else torch.float32
+
+
+def _cplx(dtype_code: int):
+    return torch.complex128 if dtype_code == F64 else torch.complex64
+
+
+def _need(t: torch.Tensor, name: str):
+    if not t.is_cuda or not t.is_contiguous():
+        raise LdkError(f"{name} must be a contiguous device tensor")
+
+
+def _kind(kind) -> int:
+    return {"lattice": LATTICE, "dnet": DNET_B2, LATTICE: LATTICE, DNET_B2: DNET_B2}[kind]
+
+
+def _order(order) -> int:
+    return {"natural": NATURAL, "linear": LINEAR, "gray": GRAY,
+            NATURAL: NATURAL, LINEAR: LINEAR, GRAY: GRAY}[order]
+
+
+def _workspace(op: int, kind: int, rows: int, m: int, dt: int, device):
+    nbytes = lib().ldk_workspace_bytes(op, kind, rows, m, dt)
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device) if nbytes else None
+
+
+def init():
+    _check(lib().ldk_init(), "ldk_init")
+
+
+@dataclass
+class PointSet:
+    """A randomized point set (Sec. 4.2 lattice / Sec. 4.3 base-2 net).
+
+    gen: int64 device tensor, lattice g[d] or net columns C[d][m_max];
+    lms: net scrambles S[R][d][64] or None; shift: [R][d] or None."""
+
+    kind: str
+    R: int
+    d: int
+    m_max: int
+    gen: torch.Tensor
+    lms: torch.Tensor | None = None
+    shift: torch.Tensor | None = None
+    order: str = "natural"
+
+    def _c(self) -> _Pointset:
+        for name in ("gen", "lms", "shift"):
+            t = getattr(self, name)
+            if t is not None:
+                _need(t, name)
+        return _Pointset(_kind(self.kind), _order(self.order), self.R, self.d, self.m_max, 0,
+                         _ptr(self.gen), _ptr(self.lms), _ptr(self.shift))
+
+
+@dataclass
+class Kernel:
+    """Product-weight SI (lattice) or DSI (net) kernel; alpha int32[d], gamma float64[d]."""
+
+    kind: str
+    alpha: torch.Tensor
+    gamma: torch.Tensor
+    zeta: float = 1.0
+
+    def _c(self) -> _Kernel:
+        _need(self.alpha, "alpha")
+        _need(self.gamma, "gamma")
+        return _Kernel(_kind(self.kind), int(self.alpha.numel()), _ptr(self.alpha),
+                       _ptr(self.gamma), float(self.zeta))
+
+
+def gen_points(ps: PointSet, n_min: int, n_max: int, out: torch.Tensor | None = None):
+    dev = ps.gen.device
+    if out is None:
+        out = torch.empty((ps.R, n_max - n_min, ps.d), dtype=torch.int64, device=dev)
+    _check(lib().ldk_gen_points(C.byref(ps._c()), n_min, n_max, _ptr(out), _stream()),
+           "ldk_gen_points")
+    return out
+
+
+def kernel_column(k: Kernel, ps: PointSet, n_min: int, n_max: int, pts=None, x0=None,
+                  dtype=torch.float64, out=None):
+    dt = _dtype_code(dtype)
+    if out is None:
+        out = torch.empty((ps.R, n_max - n_min), dtype=_real(dt), device=ps.gen.device)
+    if pts is not None:
+        _need(pts, "pts")
+    if x0 is not None:
+        _need(x0, "x0")
+    _check(lib().ldk_kernel_column(C.byref(k._c()), C.byref(ps._c()), _ptr(pts), _ptr(x0), n_min,
+                                   n_max, dt, _ptr(out), _stream()), "ldk_kernel_column")
+    return out
+
+
+def _m_of(n: int) -> int:
+    m = n.bit_length() - 1
+    if n != 1 << m:
+        raise LdkError(f"length {n} is not a power of two")
+    return m
+
+
+def transform(kind, x: torch.Tensor, inverse: bool = False, out=None):
+    """FFTBR / IFFTBR (lattice, complex rows) or FWHT (net, real rows) over the last axis."""
+    kd = _kind(kind)
+    _need(x, "x")
+    dt = _dtype_code(x.dtype)
+    if (kd == LATTICE) != x.is_complex():
+        raise LdkError("lattice transforms take complex rows, net transforms real rows")
+    n = x.shape[-1]
+    m = _m_of(n)
+    B = x.numel() // n
+    out = torch.empty_like(x) if out is None else out
+    ws = _workspace(OP_TRANSFORM, kd, B, m, dt, x.device)
+    _check(lib().ldk_transform(kd, -1 if inverse else 1, B, m, dt, _ptr(x), _ptr(out), _ptr(ws),
+                               _stream()), "ldk_transform")
+    return out
+
+
+def eig(kind, k1: torch.Tensor, out=None):
+    kd = _kind(kind)
+    _need(k1, "k1")
+    dt = _dtype_code(k1.dtype)
+    R, n = k1.shape
+    m = _m_of(n)
+    out = torch.empty_like(k1) if out is None else out
+    ws = _workspace(OP_EIG, kd, R, m, dt, k1.device)
+    _check(lib().ldk_eig(kd, R, m, dt, _ptr(k1), _ptr(out), _ptr(ws), _stream()), "ldk_eig")
+    return out
+
+
+def solve(kind, lam: torch.Tensor, sigma2: float, y: torch.Tensor, out=None, ws=None):
+    kd = _kind(kind)
+    _need(lam, "lam")
+    _need(y, "y")
+    dt = _dtype_code(y.dtype)
+    R, nrhs, n = y.shape
+    m = _m_of(n)
+    out = torch.empty_like(y) if out is None else out
+    if ws is None:
+        ws = _workspace(OP_SOLVE, kd, R * nrhs, m, dt, y.device)
+    _check(lib().ldk_solve(kd, R, nrhs, m, dt, _ptr(lam), float(sigma2), _ptr(y), _ptr(out),
+                           _ptr(ws), _stream()), "ldk_solve")
+    return out
+
+
+def matvec(kind, lam: torch.Tensor, y: torch.Tensor, out=None, ws=None):
+    kd = _kind(kind)
+    _need(lam, "lam")
+    _need(y, "y")
+    dt = _dtype_code(y.dtype)
+    R, nrhs, n = y.shape
+    m = _m_of(n)
+    out = torch.empty_like(y) if out is None else out
+    if ws is None:
+        ws = _workspace(OP_MATVEC, kd, R * nrhs, m, dt, y.device)
+    _check(lib().ldk_matvec(kd, R, nrhs, m, dt, _ptr(lam), _ptr(y), _ptr(out), _ptr(ws),
+                            _stream()), "ldk_matvec")
+    return out
+
+
+def logdet(lam: torch.Tensor, sigma2: float, out=None, ws=None):
+    _need(lam, "lam")
+    dt = _dtype_code(lam.dtype)
+    R, n = lam.shape
+    m = _m_of(n)
+    out = torch.empty(R, dtype=torch.float64, device=lam.device) if out is None else out
+    if ws is None:
+        ws = _workspace(OP_LOGDET, DNET_B2, R, m, dt, lam.device)
+    _check(lib().ldk_logdet(R, m, dt, _ptr(lam), float(sigma2), _ptr(out), _ptr(ws), _stream()),
+           "ldk_logdet")
+    return out
+
+
+def update_double(kind, yt_old: torch.Tensor, y_new: torch.Tensor, out=None):
+    kd = _kind(kind)
+    _need(yt_old, "yt_old")
+    _need(y_new, "y_new")
+    dt = _dtype_code(y_new.dtype)
+    B, n = y_new.shape
+    m = _m_of(n)
+    if out is None:
+        out = torch.empty((B, 2 * n), dtype=yt_old.dtype, device=y_new.device)
+    ws = _workspace(OP_UPDATE_DOUBLE, kd, B, m, dt, y_new.device)
+    _check(lib().ldk_update_double(kd, B, m, dt, _ptr(yt_old), _ptr(y_new), _ptr(out), _ptr(ws),
+                                   _stream()), "ldk_update_double")
+    return out
+
+
+def eig_update_double(kind, lam_old: torch.Tensor, k1_new: torch.Tensor, out=None):
+    kd = _kind(kind)
+    _need(lam_old, "lam_old")
+    _need(k1_new, "k1_new")
+    dt = _dtype_code(lam_old.dtype)
+    R, n = lam_old.shape
+    m = _m_of(n)
+    if out is None:
+        out = torch.empty((R, 2 * n), dtype=lam_old.dtype, device=lam_old.device)
+    ws = _workspace(OP_EIG_UPDATE_DOUBLE, kd, R, m, dt, lam_old.device)
+    _check(lib().ldk_eig_update_double(kd, R, m, dt, _ptr(lam_old), _ptr(k1_new), _ptr(out),
+                                       _ptr(ws), _stream()), "ldk_eig_update_double")
+    return out

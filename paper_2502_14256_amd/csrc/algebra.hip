@@ -1,0 +1,506 @@
+// Structured Gram algebra of Sec. 5.4 on top of the pass engine:
+//   K = V Lambda conj(V),  lambda = sqrt(n) conj(V) k1,
+//   K y = V (conj(V) y (.) lambda),  (K + s2 I)^-1 y = V (conj(V) y (/) (lambda + s2)),
+//   log det(K + s2 I) = sum log(lambda + s2),
+// with V = T_m / sqrt(n) (lattice, FFTBR / IFFTBR) or H_m / sqrt(n) (net, FWHT),
+// and the update that doubles n (eq. ft_next_parts).
+#include <cmath>
+
+#include "transform.hpp"
+
+namespace ldk {
+
+namespace {
+
+constexpr int LOGDET_THREADS = 256;
+constexpr int LOGDET_CHUNK = 16384;  // elements per partial sum
+
+size_t esize(int dtype) { return dtype == LDK_F64 ? 8 : 4; }
+
+bool valid_kind(int kind) { return kind == LDK_LATTICE || kind == LDK_DNET_B2; }
+bool valid_dtype(int dtype) { return dtype == LDK_F64 || dtype == LDK_F32; }
+bool valid_m(int m) { return m >= 0 && m <= TW_MAX_LOG; }
+
+// Workspace for the complex intermediate of the lattice transforms.
+size_t cplx_rows_bytes(int64_t rows, int m, int dtype) { return (size_t)rows * ((size_t)2 << m) * esize(dtype); }
+
+// ---------------------------------------------------------------------------
+// n = 1 (m = 0): every transform is the identity.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void k_scalar_apply(const R *lam, const R *y, R *c, int64_t rows, int nrhs,
+                               double sigma2, int mode)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows) return;
+    const double l = (double)lam[i / nrhs];
+    const double v = (double)y[i];
+    c[i] = (R)(mode == 0 ? v / (l + sigma2) : v * l);
+}
+
+// ---------------------------------------------------------------------------
+// log det: fixed-order FP64 tree sums (deterministic run to run)
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(LOGDET_THREADS) void k_logdet_partial(const R *lam, int64_t n,
+                                                                   double sigma2, int chunks,
+                                                                   double *partial)
+{
+    __shared__ double red[LOGDET_THREADS];
+    const int r = blockIdx.y, ch = blockIdx.x, t = threadIdx.x;
+    const R *row = lam + (int64_t)r * n;
+    const int64_t lo = (int64_t)ch * LOGDET_CHUNK;
+    const int64_t hi = lo + LOGDET_CHUNK < n ? lo + LOGDET_CHUNK : n;
+    double acc = 0.0;
+    for (int64_t k = lo + t; k < hi; k += LOGDET_THREADS) {
+        const double s = (double)row[k] + sigma2;
+        acc += s > 0.0 ? log(s) : __builtin_nan("");
+    }
+    red[t] = acc;
+    __syncthreads();
+    for (int w = LOGDET_THREADS / 2; w > 0; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    if (t == 0) partial[(int64_t)r * chunks + ch] = red[0];
+}
+
+__global__ __launch_bounds__(LOGDET_THREADS) void k_logdet_final(const double *partial, int chunks,
+                                                                 double *out)
+{
+    __shared__ double red[LOGDET_THREADS];
+    const int r = blockIdx.x, t = threadIdx.x;
+    double acc = 0.0;
+    for (int c = t; c < chunks; c += LOGDET_THREADS) acc += partial[(int64_t)r * chunks + c];
+    red[t] = acc;
+    __syncthreads();
+    for (int w = LOGDET_THREADS / 2; w > 0; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    if (t == 0) out[r] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// Update combine.  The size-n unnormalised transform U of the new half sits
+// in the second half of each output row.
+//   ytilde: full[k] = h (old[k] + c w_k U[k]), full[n+k] = h (old[k] - c w_k U[k])
+//           with h = 2^-1/2, c = n^-1/2;
+//   lambda: full[k] = old[k] + Re(w_k U[k]), full[n+k] = old[k] - Re(w_k U[k]).
+// w_k = W_{2n}^k (lattice) or 1 (net).
+// ---------------------------------------------------------------------------
+template <typename R, bool CPLX, bool U_REAL>
+__global__ void k_update_combine(const void *old_, void *full_, const void *u_, int64_t u_row,
+                                 int64_t rows, int m, double c)
+{
+    const int64_t n = (int64_t)1 << m;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= rows * n) return;
+    const int64_t row = gid >> m, k = gid & (n - 1);
+    const R h = (R)0.70710678118654752440;
+    if constexpr (CPLX) {
+        const cplx<R> *old = static_cast<const cplx<R> *>(old_) + row * n;
+        cplx<R> *full = static_cast<cplx<R> *>(full_) + row * 2 * n;
+        cplx<R> uk;
+        if constexpr (U_REAL)
+            uk = {static_cast<const R *>(u_)[row * u_row + k], (R)0};
+        else
+            uk = static_cast<const cplx<R> *>(u_)[row * u_row + k];
+        cplx<R> w = cmul(uk, tw_any<R>((uint64_t)k, m + 1));
+        w = {w.re * (R)c, w.im * (R)c};
+        const cplx<R> o = old[k];
+        full[k] = {h * (o.re + w.re), h * (o.im + w.im)};
+        full[n + k] = {h * (o.re - w.re), h * (o.im - w.im)};
+    } else {
+        const R *old = static_cast<const R *>(old_) + row * n;
+        R *full = static_cast<R *>(full_) + row * 2 * n;
+        const R *u = static_cast<const R *>(u_) + row * u_row;
+        const R w = u[k] * (R)c;
+        const R o = old[k];
+        full[k] = h * (o + w);
+        full[n + k] = h * (o - w);
+    }
+}
+
+template <typename R, bool CPLX>
+__global__ void k_eig_update_combine(const R *old, R *full, const void *u_, int64_t u_row,
+                                     int64_t rows, int m)
+{
+    const int64_t n = (int64_t)1 << m;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= rows * n) return;
+    const int64_t row = gid >> m, k = gid & (n - 1);
+    R part;
+    if constexpr (CPLX) {
+        const cplx<R> u = static_cast<const cplx<R> *>(u_)[row * u_row + k];
+        part = cmul(u, tw_any<R>((uint64_t)k, m + 1)).re;
+    } else {
+        part = static_cast<const R *>(u_)[row * u_row + k];
+    }
+    const R o = old[row * n + k];
+    full[row * 2 * n + k] = o + part;
+    full[row * 2 * n + n + k] = o - part;
+}
+
+unsigned blocks_for(int64_t work, int threads) { return (unsigned)((work + threads - 1) / threads); }
+
+// Forward transform of `rows` rows through all passes: src (real or complex)
+// -> dst.  dst_real keeps the real part at the last pass.  `scale` is applied
+// at the last store.
+int forward_all(int kind, int dtype, int m, int64_t rows, const void *src, int64_t src_row,
+                bool src_real, void *dst, int64_t dst_row, bool dst_real, void *tmp,
+                int64_t tmp_row, double scale, hipStream_t s)
+{
+    const Plan pl = make_plan(m, log_tile_for(kind, dtype));
+    for (int p = 0; p < pl.P; ++p) {
+        const bool first = p == 0, last = p == pl.P - 1;
+        PassArgs a{};
+        a.src = first ? src : tmp;
+        a.src_row = first ? src_row : tmp_row;
+        a.dst = last ? dst : tmp;
+        a.dst_row = last ? dst_row : tmp_row;
+        a.rows = rows;
+        a.m = m;
+        a.g = pl.pass[p];
+        a.nrhs = 1;
+        a.global_tw = p > 0;
+        a.scale = last ? scale : 1.0;
+        const int st = launch_pass(kind, dtype, PM_FWD, first && src_real, last && dst_real, a, s);
+        if (st) return st;
+    }
+    return LDK_OK;
+}
+
+// Solve / matvec through all passes: src (real rows) -> dst (real rows);
+// complex intermediates (lattice, more than one pass) live in tmp.
+int apply_all(int kind, int dtype, int mode, int m, int64_t rows, int nrhs, const void *lam,
+              double sigma2, const void *src, void *dst, void *tmp, hipStream_t s)
+{
+    const Plan pl = make_plan(m, log_tile_for(kind, dtype));
+    const int64_t n = (int64_t)1 << m;
+    const bool lat = kind == LDK_LATTICE;
+    void *work = (lat && pl.P > 1) ? tmp : dst;
+    const double scale = 1.0 / (double)n;
+    // forward passes below the top one
+    for (int p = 0; p < pl.P - 1; ++p) {
+        PassArgs a{};
+        a.src = p == 0 ? src : work;
+        a.dst = work;
+        a.src_row = a.dst_row = n;
+        a.rows = rows;
+        a.m = m;
+        a.g = pl.pass[p];
+        a.nrhs = nrhs;
+        a.global_tw = p > 0;
+        a.scale = 1.0;
+        const int st = launch_pass(kind, dtype, PM_FWD, lat && p == 0, false, a, s);
+        if (st) return st;
+    }
+    {
+        const int p = pl.P - 1;
+        PassArgs a{};
+        a.src = p == 0 ? src : work;
+        a.dst = p == 0 ? dst : work;
+        a.src_row = a.dst_row = n;
+        a.rows = rows;
+        a.m = m;
+        a.g = pl.pass[p];
+        a.lam = lam;
+        a.nrhs = nrhs;
+        a.global_tw = p > 0;
+        a.sigma2 = sigma2;
+        a.scale = scale;
+        const int st = launch_pass(kind, dtype, mode, lat && p == 0, lat && p == 0, a, s);
+        if (st) return st;
+    }
+    for (int p = pl.P - 2; p >= 0; --p) {
+        PassArgs a{};
+        a.src = work;
+        a.dst = p == 0 ? dst : work;
+        a.src_row = a.dst_row = n;
+        a.rows = rows;
+        a.m = m;
+        a.g = pl.pass[p];
+        a.nrhs = nrhs;
+        a.global_tw = p > 0;
+        a.scale = 1.0;
+        const int st = launch_pass(kind, dtype, PM_INV, false, lat && p == 0, a, s);
+        if (st) return st;
+    }
+    return LDK_OK;
+}
+
+size_t ws_bytes(int op, int kind, int64_t B, int m, int dtype)
+{
+    if (m == 0) return op == LDK_OP_LOGDET ? (size_t)B * sizeof(double) : 0;
+    const bool lat = kind == LDK_LATTICE;
+    const int P = make_plan(m, log_tile_for(kind, dtype)).P;
+    switch (op) {
+    case LDK_OP_TRANSFORM: return 0;
+    case LDK_OP_EIG: return (lat && P > 1) ? cplx_rows_bytes(B, m, dtype) : 0;
+    case LDK_OP_SOLVE:
+    case LDK_OP_MATVEC: return (lat && P > 1) ? cplx_rows_bytes(B, m, dtype) : 0;
+    case LDK_OP_LOGDET: {
+        const int64_t n = (int64_t)1 << m;
+        const int64_t chunks = (n + LOGDET_CHUNK - 1) / LOGDET_CHUNK;
+        return (size_t)B * chunks * sizeof(double);
+    }
+    case LDK_OP_UPDATE_DOUBLE: return 0;
+    case LDK_OP_EIG_UPDATE_DOUBLE: return lat ? cplx_rows_bytes(B, m, dtype) : 0;
+    default: return 0;
+    }
+}
+
+}  // namespace
+
+}  // namespace ldk
+
+using namespace ldk;
+
+extern "C" {
+
+size_t ldk_workspace_bytes(int op, int kind, int64_t B, int m, int dtype)
+{
+    if (!valid_kind(kind) || !valid_dtype(dtype) || !valid_m(m) || B < 0) return 0;
+    return ws_bytes(op, kind, B, m, dtype);
+}
+
+int ldk_transform(int kind, int dir, int B, int m, int dtype, const void *in, void *out, void *ws,
+                  ldk_stream stream)
+{
+    (void)ws;
+    if (!valid_kind(kind) || !valid_dtype(dtype) || !valid_m(m) || B < 0 || !in || !out)
+        return LDK_EINVAL;
+    if (kind == LDK_LATTICE && dir != 1 && dir != -1) return LDK_EINVAL;
+    if (B == 0) return LDK_OK;
+    int st = ensure_init();
+    if (st) return st;
+    hipStream_t s = as_stream(stream);
+    const int64_t n = (int64_t)1 << m;
+    const size_t row_bytes = (size_t)n * esize(dtype) * (kind == LDK_LATTICE ? 2 : 1);
+    if (m == 0) {
+        if (in != out) LDK_HIP_CHECK(hipMemcpyAsync(out, in, row_bytes * B, hipMemcpyDeviceToDevice, s));
+        return LDK_OK;
+    }
+    const double scale = 1.0 / std::sqrt((double)n);
+    if (kind == LDK_DNET_B2 || dir == 1)
+        return forward_all(kind, dtype, m, B, in, n, false, out, n, false, out, n, scale, s);
+    // inverse FFTBR: passes from the top down
+    const Plan pl = make_plan(m, log_tile_for(kind, dtype));
+    for (int p = pl.P - 1; p >= 0; --p) {
+        PassArgs a{};
+        a.src = p == pl.P - 1 ? in : out;
+        a.dst = out;
+        a.src_row = a.dst_row = n;
+        a.rows = B;
+        a.m = m;
+        a.g = pl.pass[p];
+        a.nrhs = 1;
+        a.global_tw = p > 0;
+        a.scale = p == 0 ? scale : 1.0;
+        st = launch_pass(kind, dtype, PM_INV, false, false, a, s);
+        if (st) return st;
+    }
+    return LDK_OK;
+}
+
+int ldk_eig(int kind, int R, int m, int dtype, const void *k1, void *lam, void *ws,
+            ldk_stream stream)
+{
+    if (!valid_kind(kind) || !valid_dtype(dtype) || !valid_m(m) || R < 0 || !k1 || !lam)
+        return LDK_EINVAL;
+    if (R == 0) return LDK_OK;
+    if (ws_bytes(LDK_OP_EIG, kind, R, m, dtype) && !ws) return LDK_EINVAL;
+    int st = ensure_init();
+    if (st) return st;
+    hipStream_t s = as_stream(stream);
+    const int64_t n = (int64_t)1 << m;
+    if (m == 0) {
+        if (k1 != lam) LDK_HIP_CHECK(hipMemcpyAsync(lam, k1, esize(dtype) * R, hipMemcpyDeviceToDevice, s));
+        return LDK_OK;
+    }
+    const bool lat = kind == LDK_LATTICE;
+    // lambda = sqrt(n) * orthonormal transform = unnormalised transform
+    return forward_all(kind, dtype, m, R, k1, n, lat, lam, n, lat, lat ? ws : lam, n, 1.0, s);
+}
+
+static int apply_entry(int mode, int kind, int R, int nrhs, int m, int dtype, const void *lam,
+                       double sigma2, const void *y, void *c, void *ws, ldk_stream stream)
+{
+    if (!valid_kind(kind) || !valid_dtype(dtype) || !valid_m(m) || R < 0 || nrhs < 0 || !lam ||
+        !y || !c)
+        return LDK_EINVAL;
+    if (!(sigma2 >= 0.0)) return LDK_EINVAL;
+    const int64_t rows = (int64_t)R * nrhs;
+    if (rows == 0) return LDK_OK;
+    if (ws_bytes(LDK_OP_SOLVE, kind, rows, m, dtype) && !ws) return LDK_EINVAL;
+    int st = ensure_init();
+    if (st) return st;
+    hipStream_t s = as_stream(stream);
+    if (m == 0) {
+        if (dtype == LDK_F64)
+            hipLaunchKernelGGL(k_scalar_apply<double>, dim3(blocks_for(rows, 256)), dim3(256), 0, s,
+                               (const double *)lam, (const double *)y, (double *)c, rows, nrhs,
+                               sigma2, mode == PM_SOLVE ? 0 : 1);
+        else
+            hipLaunchKernelGGL(k_scalar_apply<float>, dim3(blocks_for(rows, 256)), dim3(256), 0, s,
+                               (const float *)lam, (const float *)y, (float *)c, rows, nrhs,
+                               sigma2, mode == PM_SOLVE ? 0 : 1);
+        LDK_LAUNCH_CHECK();
+        return LDK_OK;
+    }
+    return apply_all(kind, dtype, mode, m, rows, nrhs, lam, sigma2, y, c, ws, s);
+}
+
+int ldk_solve(int kind, int R, int nrhs, int m, int dtype, const void *lam, double sigma2,
+              const void *y, void *c, void *ws, ldk_stream stream)
+{
+    return apply_entry(PM_SOLVE, kind, R, nrhs, m, dtype, lam, sigma2, y, c, ws, stream);
+}
+
+int ldk_matvec(int kind, int R, int nrhs, int m, int dtype, const void *lam, const void *y,
+               void *out, void *ws, ldk_stream stream)
+{
+    return apply_entry(PM_MATVEC, kind, R, nrhs, m, dtype, lam, 0.0, y, out, ws, stream);
+}
+
+int ldk_logdet(int R, int m, int dtype, const void *lam, double sigma2, double *out, void *ws,
+               ldk_stream stream)
+{
+    if (!valid_dtype(dtype) || !valid_m(m) || R < 0 || R > 65535 || !lam || !out || !(sigma2 >= 0.0))
+        return LDK_EINVAL;
+    if (R == 0) return LDK_OK;
+    if (!ws) return LDK_EINVAL;
+    hipStream_t s = as_stream(stream);
+    const int64_t n = (int64_t)1 << m;
+    const int chunks = (int)((n + LOGDET_CHUNK - 1) / LOGDET_CHUNK);
+    double *partial = static_cast<double *>(ws);
+    if (dtype == LDK_F64)
+        hipLaunchKernelGGL(k_logdet_partial<double>, dim3(chunks, R), dim3(LOGDET_THREADS), 0, s,
+                           (const double *)lam, n, sigma2, chunks, partial);
+    else
+        hipLaunchKernelGGL(k_logdet_partial<float>, dim3(chunks, R), dim3(LOGDET_THREADS), 0, s,
+                           (const float *)lam, n, sigma2, chunks, partial);
+    LDK_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_logdet_final, dim3(R), dim3(LOGDET_THREADS), 0, s, partial, chunks, out);
+    LDK_LAUNCH_CHECK();
+    return LDK_OK;
+}
+
+int ldk_update_double(int kind, int B, int m, int dtype, const void *yt_old, const void *y_new,
+                      void *yt_full, void *ws, ldk_stream stream)
+{
+    (void)ws;
+    if (!valid_kind(kind) || !valid_dtype(dtype) || !valid_m(m) || m + 1 > TW_MAX_LOG || B < 0 ||
+        !yt_old || !y_new || !yt_full)
+        return LDK_EINVAL;
+    if (B == 0) return LDK_OK;
+    int st = ensure_init();
+    if (st) return st;
+    hipStream_t s = as_stream(stream);
+    const int64_t n = (int64_t)1 << m;
+    const bool lat = kind == LDK_LATTICE;
+    const size_t eb = esize(dtype) * (lat ? 2 : 1);
+    // U = unnormalised FT_m(y_new), written into the second half of each output row
+    void *u = static_cast<unsigned char *>(yt_full) + n * eb;
+    if (m == 0) {
+        // FT_0 is the identity: combine directly with y_new
+        if (lat) {
+            if (dtype == LDK_F64)
+                hipLaunchKernelGGL((k_update_combine<double, true, true>), dim3(blocks_for(B, 256)),
+                                   dim3(256), 0, s, yt_old, yt_full, y_new, (int64_t)1, (int64_t)B, 0, 1.0);
+            else
+                hipLaunchKernelGGL((k_update_combine<float, true, true>), dim3(blocks_for(B, 256)),
+                                   dim3(256), 0, s, yt_old, yt_full, y_new, (int64_t)1, (int64_t)B, 0, 1.0);
+        } else {
+            if (dtype == LDK_F64)
+                hipLaunchKernelGGL((k_update_combine<double, false, true>), dim3(blocks_for(B, 256)),
+                                   dim3(256), 0, s, yt_old, yt_full, y_new, (int64_t)1, (int64_t)B, 0, 1.0);
+            else
+                hipLaunchKernelGGL((k_update_combine<float, false, true>), dim3(blocks_for(B, 256)),
+                                   dim3(256), 0, s, yt_old, yt_full, y_new, (int64_t)1, (int64_t)B, 0, 1.0);
+        }
+        LDK_LAUNCH_CHECK();
+        return LDK_OK;
+    }
+    // intermediates of a multi-pass plan also live in the output rows (stride 2n)
+    st = forward_all(kind, dtype, m, B, y_new, n, lat, u, 2 * n, false, u, 2 * n, 1.0, s);
+    if (st) return st;
+    const double c = 1.0 / std::sqrt((double)n);
+    const int64_t work = (int64_t)B * n;
+    if (lat) {
+        if (dtype == LDK_F64)
+            hipLaunchKernelGGL((k_update_combine<double, true, false>), dim3(blocks_for(work, 256)), dim3(256),
+                               0, s, yt_old, yt_full, (const void *)u, 2 * n, (int64_t)B, m, c);
+        else
+            hipLaunchKernelGGL((k_update_combine<float, true, false>), dim3(blocks_for(work, 256)), dim3(256),
+                               0, s, yt_old, yt_full, (const void *)u, 2 * n, (int64_t)B, m, c);
+    } else {
+        if (dtype == LDK_F64)
+            hipLaunchKernelGGL((k_update_combine<double, false, false>), dim3(blocks_for(work, 256)), dim3(256),
+                               0, s, yt_old, yt_full, (const void *)u, 2 * n, (int64_t)B, m, c);
+        else
+            hipLaunchKernelGGL((k_update_combine<float, false, false>), dim3(blocks_for(work, 256)), dim3(256),
+                               0, s, yt_old, yt_full, (const void *)u, 2 * n, (int64_t)B, m, c);
+    }
+    LDK_LAUNCH_CHECK();
+    return LDK_OK;
+}
+
+int ldk_eig_update_double(int kind, int R, int m, int dtype, const void *lam_old,
+                          const void *k1_new, void *lam_full, void *ws, ldk_stream stream)
+{
+    if (!valid_kind(kind) || !valid_dtype(dtype) || !valid_m(m) || m + 1 > TW_MAX_LOG || R < 0 ||
+        !lam_old || !k1_new || !lam_full)
+        return LDK_EINVAL;
+    if (R == 0) return LDK_OK;
+    const bool lat = kind == LDK_LATTICE;
+    if (ws_bytes(LDK_OP_EIG_UPDATE_DOUBLE, kind, R, m, dtype) && !ws) return LDK_EINVAL;
+    int st = ensure_init();
+    if (st) return st;
+    hipStream_t s = as_stream(stream);
+    const int64_t n = (int64_t)1 << m;
+    const void *u;
+    int64_t u_row;
+    bool u_cplx = lat;
+    if (m == 0) {
+        u = k1_new;  // FT_0 is the identity and w_0 = 1
+        u_row = 1;
+        u_cplx = false;
+    } else if (lat) {
+        st = forward_all(kind, dtype, m, R, k1_new, n, true, ws, n, false, ws, n, 1.0, s);
+        if (st) return st;
+        u = ws;
+        u_row = n;
+    } else {
+        void *dst = static_cast<unsigned char *>(lam_full) + n * esize(dtype);
+        st = forward_all(kind, dtype, m, R, k1_new, n, false, dst, 2 * n, false, dst, 2 * n, 1.0, s);
+        if (st) return st;
+        u = dst;
+        u_row = 2 * n;
+    }
+    const int64_t work = (int64_t)R * n;
+    if (dtype == LDK_F64) {
+        if (u_cplx)
+            hipLaunchKernelGGL((k_eig_update_combine<double, true>), dim3(blocks_for(work, 256)),
+                               dim3(256), 0, s, (const double *)lam_old, (double *)lam_full, u,
+                               u_row, (int64_t)R, m);
+        else
+            hipLaunchKernelGGL((k_eig_update_combine<double, false>), dim3(blocks_for(work, 256)),
+                               dim3(256), 0, s, (const double *)lam_old, (double *)lam_full, u,
+                               u_row, (int64_t)R, m);
+    } else {
+        if (u_cplx)
+            hipLaunchKernelGGL((k_eig_update_combine<float, true>), dim3(blocks_for(work, 256)),
+                               dim3(256), 0, s, (const float *)lam_old, (float *)lam_full, u, u_row,
+                               (int64_t)R, m);
+        else
+            hipLaunchKernelGGL((k_eig_update_combine<float, false>), dim3(blocks_for(work, 256)),
+                               dim3(256), 0, s, (const float *)lam_old, (float *)lam_full, u, u_row,
+                               (int64_t)R, m);
+    }
+    LDK_LAUNCH_CHECK();
+    return LDK_OK;
+}
+
+}  // extern "C"

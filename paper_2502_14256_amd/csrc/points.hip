@@ -1,0 +1,154 @@
+// Randomized low-discrepancy point sets as exact 64-digit words:
+// shifted rank-1 lattices (Sec. 4.2) and LMS + digitally shifted base-2
+// digital nets in natural or Gray order (Sec. 4.3).
+#include "pointset.hpp"
+
+namespace ldk {
+
+namespace {
+constexpr int GEN_THREADS = 256;
+constexpr int GEN_DIM_CHUNK = 32;  // dimensions per block
+constexpr int GEN_ITERS = 32;      // points per thread
+}  // namespace
+
+int validate_pointset(const ldk_pointset *ps, PointsetArgs *out)
+{
+    if (!ps || !out) return LDK_EINVAL;
+    if (ps->R < 1 || ps->R > 65535 || ps->d < 1 || ps->d > LDK_MAX_D) return LDK_EINVAL;
+    if (ps->m_max < 0 || ps->m_max > 62 || !ps->gen) return LDK_EINVAL;
+    if (ps->kind == LDK_LATTICE) {
+        if (ps->order != LDK_NATURAL && ps->order != LDK_LINEAR) return LDK_EINVAL;
+        if (ps->lms) return LDK_EINVAL;  // scrambling matrices belong to nets
+    } else if (ps->kind == LDK_DNET_B2) {
+        if (ps->order != LDK_NATURAL && ps->order != LDK_GRAY) return LDK_EINVAL;
+    } else {
+        return LDK_EINVAL;
+    }
+    *out = PointsetArgs{ps->kind, ps->order, ps->R, ps->d, ps->m_max, ps->gen, ps->lms, ps->shift};
+    return LDK_OK;
+}
+
+// Largest power of two P with P * dims <= GEN_THREADS.
+static int point_lanes(int dims)
+{
+    int P = 1;
+    while (2 * P * dims <= GEN_THREADS) P *= 2;
+    return P;
+}
+
+// Block: one replication r, dims [j0, j0 + DB), points
+// [n_min + blockIdx.x * P * GEN_ITERS, ...).  Thread (p, jj) walks the points
+// i = tile + p + P * k, k < GEN_ITERS.
+__global__ __launch_bounds__(GEN_THREADS) void k_gen_net(PointsetArgs a, int64_t n_min,
+                                                         int64_t n_max, int P, int logP,
+                                                         uint64_t *__restrict__ out)
+{
+    __shared__ uint64_t ct[GEN_DIM_CHUNK][64];
+    __shared__ uint64_t step[GEN_DIM_CHUNK][64];
+    const int r = blockIdx.z;
+    const int j0 = blockIdx.y * GEN_DIM_CHUNK;
+    const int DB = min(GEN_DIM_CHUNK, a.d - j0);
+    const int m = a.m_max;
+    const int t = threadIdx.x;
+
+    for (int w = t; w < DB * m; w += GEN_THREADS) {
+        const int jj = w / m, k = w % m;
+        const uint64_t col = a.gen[(size_t)(j0 + jj) * m + k];
+        ct[jj][k] = a.lms ? lms_column(a.lms + ((size_t)r * a.d + j0 + jj) * 64, col) : col;
+    }
+    __syncthreads();
+    const int s = logP;
+    for (int w = t; w < DB * 64; w += GEN_THREADS) {
+        const int jj = w / 64, c = w % 64;
+        uint64_t v = 0;
+        if (s + c < m) {
+            if (a.order == LDK_GRAY) {
+                v = ct[jj][s + c] ^ (s >= 1 ? ct[jj][s - 1] : 0);
+            } else {
+                for (int k = s; k <= s + c; ++k) v ^= ct[jj][k];
+            }
+        }
+        step[jj][c] = v;
+    }
+    __syncthreads();
+
+    const int p = t / DB, jj = t % DB;
+    if (p >= P) return;
+    const int j = j0 + jj;
+    const int64_t cnt = n_max - n_min;
+    const int64_t first = n_min + (int64_t)blockIdx.x * P * GEN_ITERS + p;
+    if (first >= n_max) return;
+    const uint64_t delta = a.shift ? a.shift[(size_t)r * a.d + j] : 0;
+    const uint64_t code0 = a.order == LDK_GRAY ? gray_code((uint64_t)first) : (uint64_t)first;
+    uint64_t z = net_point(ct[jj], m, code0);
+    uint64_t *dst = out + ((size_t)r * cnt + (first - n_min)) * a.d + j;
+    const size_t dstep = (size_t)P * a.d;
+    int64_t i = first;
+    for (int k = 0; k < GEN_ITERS; ++k) {
+        *dst = z ^ delta;
+        const int64_t next = i + P;
+        if (next >= n_max || k + 1 == GEN_ITERS) break;
+        z ^= step[jj][ctz64(((uint64_t)i >> s) + 1)];
+        i = next;
+        dst += dstep;
+    }
+}
+
+__global__ __launch_bounds__(GEN_THREADS) void k_gen_lattice(PointsetArgs a, int64_t n_min,
+                                                             int64_t n_max, int P,
+                                                             uint64_t *__restrict__ out)
+{
+    const int r = blockIdx.z;
+    const int j0 = blockIdx.y * GEN_DIM_CHUNK;
+    const int DB = min(GEN_DIM_CHUNK, a.d - j0);
+    const int t = threadIdx.x;
+    const int p = t / DB, jj = t % DB;
+    if (p >= P) return;
+    const int j = j0 + jj;
+    const int64_t cnt = n_max - n_min;
+    const uint64_t g = a.gen[j];
+    const uint64_t delta = a.shift ? a.shift[(size_t)r * a.d + j] : 0;
+    const int64_t first = n_min + (int64_t)blockIdx.x * P * GEN_ITERS + p;
+    uint64_t *dst = out + ((size_t)r * cnt + (first - n_min)) * a.d + j;
+    const size_t dstep = (size_t)P * a.d;
+    int64_t i = first;
+    for (int k = 0; k < GEN_ITERS && i < n_max; ++k) {
+        *dst = lattice_point(g, (uint64_t)i, a.order, a.m_max) + delta;
+        i += P;
+        dst += dstep;
+    }
+}
+
+}  // namespace ldk
+
+using namespace ldk;
+
+extern "C" int ldk_gen_points(const ldk_pointset *ps, int64_t n_min, int64_t n_max,
+                              uint64_t *out, ldk_stream stream)
+{
+    PointsetArgs a;
+    int st = validate_pointset(ps, &a);
+    if (st) return st;
+    if (n_min < 0 || n_max < n_min) return LDK_EINVAL;
+    const int64_t lim = (a.kind == LDK_LATTICE && a.order == LDK_NATURAL)
+                            ? ((int64_t)1 << 62)
+                            : ((int64_t)1 << a.m_max);
+    if (n_max > lim) return LDK_EINVAL;
+    if (n_max == n_min) return LDK_OK;  // empty window: out may be NULL
+    if (!out) return LDK_EINVAL;
+    const int dims = a.d < GEN_DIM_CHUNK ? a.d : GEN_DIM_CHUNK;
+    const int P = point_lanes(dims);
+    int logP = 0;
+    while ((1 << logP) < P) ++logP;
+    const int64_t tiles = (n_max - n_min + (int64_t)P * GEN_ITERS - 1) / ((int64_t)P * GEN_ITERS);
+    if (tiles > 0x7fffffff) return LDK_ENOTSUP;
+    dim3 grid((unsigned)tiles, (unsigned)((a.d + GEN_DIM_CHUNK - 1) / GEN_DIM_CHUNK), (unsigned)a.R);
+    if (a.kind == LDK_LATTICE)
+        hipLaunchKernelGGL(k_gen_lattice, grid, dim3(GEN_THREADS), 0, as_stream(stream), a, n_min,
+                           n_max, P, out);
+    else
+        hipLaunchKernelGGL(k_gen_net, grid, dim3(GEN_THREADS), 0, as_stream(stream), a, n_min,
+                           n_max, P, logP, out);
+    LDK_LAUNCH_CHECK();
+    return LDK_OK;
+}

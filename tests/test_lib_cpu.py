@@ -1,0 +1,107 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point include/ldk.h declares, and rejects invalid arguments
+before enqueueing anything."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_2502_14256_amd as ldk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "ldk.h")).read()
+    return sorted(set(re.findall(r"\b(ldk_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    assert _declared() == sorted(ldk.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = ldk.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_version_and_strerror():
+    L = ldk.lib()
+    assert L.ldk_version().decode().count(".") == 2
+    for code in (0, -1, -2, -3, -4):
+        assert L.ldk_strerror(code).decode()
+    assert L.ldk_strerror(-99).decode() == "unknown status"
+
+
+FAKE = C.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
+
+
+def _ps(**kw):
+    base = dict(kind=ldk.DNET_B2, order=ldk.NATURAL, R=1, d=4, m_max=10, reserved=0,
+                gen=FAKE, lms=None, shift=None)
+    base.update(kw)
+    return ldk._Pointset(**base)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(R=0), dict(d=0), dict(d=5000), dict(m_max=63), dict(kind=7), dict(gen=None),
+    dict(order=ldk.LINEAR), dict(kind=ldk.LATTICE, order=ldk.GRAY),
+    dict(kind=ldk.LATTICE, lms=FAKE),
+])
+def test_gen_points_rejects_bad_pointsets(kw):
+    L = ldk.lib()
+    assert L.ldk_gen_points(C.byref(_ps(**kw)), 0, 4, FAKE, None) == -1
+
+
+def test_gen_points_rejects_bad_ranges():
+    L = ldk.lib()
+    assert L.ldk_gen_points(C.byref(_ps()), 5, 4, FAKE, None) == -1
+    assert L.ldk_gen_points(C.byref(_ps()), -1, 4, FAKE, None) == -1
+    assert L.ldk_gen_points(C.byref(_ps()), 0, 2**10 + 1, FAKE, None) == -1  # beyond 2^m_max
+    assert L.ldk_gen_points(C.byref(_ps()), 0, 4, None, None) == -1
+    # empty range: valid, nothing to do
+    assert L.ldk_gen_points(C.byref(_ps()), 3, 3, FAKE, None) == 0
+
+
+def test_kernel_column_rejects_mismatch():
+    L = ldk.lib()
+    k = ldk._Kernel(ldk.LATTICE, 4, FAKE, FAKE, 1.0)
+    assert L.ldk_kernel_column(C.byref(k), C.byref(_ps()), None, None, 0, 4, 0, FAKE, None) == -1
+    k = ldk._Kernel(ldk.DNET_B2, 4, FAKE, FAKE, 0.0)  # zeta must be > 0
+    assert L.ldk_kernel_column(C.byref(k), C.byref(_ps()), None, None, 0, 4, 0, FAKE, None) == -1
+    k = ldk._Kernel(ldk.DNET_B2, 4, FAKE, FAKE, 1.0)
+    assert L.ldk_kernel_column(C.byref(k), C.byref(_ps()), None, None, 0, 4, 9, FAKE, None) == -1
+    # pts given with n_min > 0 needs an explicit anchor
+    assert L.ldk_kernel_column(C.byref(k), C.byref(_ps()), FAKE, None, 2, 4, 0, FAKE, None) == -1
+
+
+def test_algebra_rejects_bad_arguments():
+    L = ldk.lib()
+    assert L.ldk_transform(5, 1, 1, 4, 0, FAKE, FAKE, None, None) == -1
+    assert L.ldk_transform(ldk.LATTICE, 0, 1, 4, 0, FAKE, FAKE, None, None) == -1
+    assert L.ldk_transform(ldk.DNET_B2, 1, 1, 27, 0, FAKE, FAKE, None, None) == -1
+    assert L.ldk_transform(ldk.DNET_B2, 1, 1, 4, 3, FAKE, FAKE, None, None) == -1
+    assert L.ldk_transform(ldk.DNET_B2, 1, 0, 4, 0, FAKE, FAKE, None, None) == 0  # B = 0
+    assert L.ldk_solve(ldk.DNET_B2, 1, 1, 4, 0, FAKE, -1.0, FAKE, FAKE, None, None) == -1
+    assert L.ldk_solve(ldk.DNET_B2, 1, 1, 4, 0, None, 0.1, FAKE, FAKE, None, None) == -1
+    assert L.ldk_solve(ldk.DNET_B2, 0, 1, 4, 0, FAKE, 0.1, FAKE, FAKE, None, None) == 0
+    # lattice solve with more than one pass needs its workspace
+    assert L.ldk_solve(ldk.LATTICE, 1, 1, 20, 0, FAKE, 0.1, FAKE, FAKE, None, None) == -1
+    assert L.ldk_logdet(1, 4, 0, FAKE, 0.1, FAKE, None, None) == -1  # workspace missing
+    assert L.ldk_logdet(1, 4, 0, FAKE, float("nan"), FAKE, FAKE, None) == -1
+    assert L.ldk_update_double(ldk.DNET_B2, 1, 26, 0, FAKE, FAKE, FAKE, None, None) == -1
+    assert L.ldk_eig(ldk.LATTICE, 1, 20, 0, FAKE, FAKE, None, None) == -1
+
+
+def test_workspace_sizes():
+    L = ldk.lib()
+    ws = L.ldk_workspace_bytes
+    assert ws(ldk.OP_TRANSFORM, ldk.DNET_B2, 4, 20, 0) == 0
+    assert ws(ldk.OP_SOLVE, ldk.DNET_B2, 4, 20, 0) == 0
+    assert ws(ldk.OP_SOLVE, ldk.LATTICE, 4, 20, 0) == 4 * 2**20 * 16
+    assert ws(ldk.OP_SOLVE, ldk.LATTICE, 4, 20, 1) == 4 * 2**20 * 8
+    assert ws(ldk.OP_SOLVE, ldk.LATTICE, 4, 10, 0) == 0  # one pass, no intermediate
+    assert ws(ldk.OP_LOGDET, ldk.DNET_B2, 3, 20, 0) == 3 * 64 * 8
+    assert ws(ldk.OP_EIG, 9, 1, 4, 0) == 0
