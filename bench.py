@@ -1,0 +1,229 @@
+"""Benchmark of the fast kernel-method hot path on one MI355X.
+
+A step is one pass of the whole path over the rank-1 lattice workload
+(n = 2^20, d = 32, order-2 SI kernel, gamma_j = 1/j^2, sigma^2 = 1e-3):
+  gen_points -> kernel_column -> eig (FFTBR) -> solve -> logdet,
+with the generating vector, shift and responses already resident in HBM.
+The metric counts one Gram solve (K + sigma^2 I)^-1 y per step.
+
+Printed: one JSON line with the metric, per-op timings (HIP events on the
+library's stream), the roofline of the dominant kernel, the solve's own
+roofline, and the CPU oracle timed on the host as a baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=50)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--dtype", choices=["f64", "f32"], default="f64",
+                   help="arithmetic of the per-solve data (y, c, solve transforms); the first "
+                        "column and the eigenvalues stay FP64")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=10.0)
+    p.add_argument("--copy-probe", action="store_true",
+                   help="also run a plain device copy of known size (counter calibration)")
+    return p.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(independent replications would shard with no communication)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2502_14256_amd as ldk
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    ldk.init()
+    dt = torch.float64 if args.dtype == "f64" else torch.float32
+    esz = 8 if args.dtype == "f64" else 4
+
+    w = W.workload(2)
+    n, d, R, m = 2 ** w["m"], w["d"], w["R"], w["m"]
+
+    def dev_u64(a):
+        return torch.from_numpy(np.ascontiguousarray(a, np.uint64).view(np.int64).copy()).cuda()
+
+    ps = ldk.PointSet("lattice", R, d, m, dev_u64(w["gen"]), None, dev_u64(w["shift"]))
+    kern = ldk.Kernel("lattice", torch.tensor(w["alpha"], dtype=torch.int32, device="cuda"),
+                      torch.tensor(w["gamma"], dtype=torch.float64, device="cuda"), w["zeta"])
+    # responses y = sum_j sin(2 pi x_j)/j + noise at the points (input synthesis, untimed)
+    pts0 = ldk.gen_points(ps, 0, n)
+    x = W.to_unit_f64(pts0.cpu().numpy().view(np.uint64))
+    y_host = np.ascontiguousarray(W.sine_response(x, w["eps"][:, 0, :])[:, None, :])
+    del pts0, x
+    y = torch.from_numpy(y_host).to(device="cuda", dtype=dt)
+
+    # outputs and workspaces, allocated once
+    pts = torch.empty((R, n, d), dtype=torch.int64, device="cuda")
+    k1 = torch.empty((R, n), dtype=torch.float64, device="cuda")
+    lam = torch.empty((R, n), dtype=torch.float64, device="cuda")
+    c = torch.empty_like(y)
+    ld = torch.empty(R, dtype=torch.float64, device="cuda")
+    ws_solve = ldk._workspace(ldk.OP_SOLVE, ldk.LATTICE, R, m, ldk._dtype_code(dt), "cuda")
+    ws_ld = ldk._workspace(ldk.OP_LOGDET, ldk.LATTICE, R, m, ldk.F64, "cuda")
+    ws_eig = ldk._workspace(ldk.OP_EIG, ldk.LATTICE, R, m, ldk.F64, "cuda")
+
+    ops = ["gen_points", "kernel_column", "eig", "solve", "logdet"]
+    stream = torch.cuda.current_stream()
+
+    def step(evs=None):
+        if evs is not None:
+            evs[0].record(stream)
+        ldk.gen_points(ps, 0, n, out=pts)
+        if evs is not None:
+            evs[1].record(stream)
+        ldk.kernel_column(kern, ps, 0, n, dtype=torch.float64, out=k1)
+        if evs is not None:
+            evs[2].record(stream)
+        ldk.eig("lattice", k1, out=lam, ws=ws_eig)
+        if evs is not None:
+            evs[3].record(stream)
+        ldk.solve("lattice", lam, w["sigma2"], y, out=c, ws=ws_solve)
+        if evs is not None:
+            evs[4].record(stream)
+        ldk.logdet(lam, w["sigma2"], out=ld, ws=ws_ld)
+        if evs is not None:
+            evs[5].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    K = args.steps
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(ops) + 1)] for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for s in range(K):
+        step(evs[s])
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms = start.elapsed_time(stop)
+    per_op = {op: float(np.mean([evs[s][i].elapsed_time(evs[s][i + 1]) for s in range(K)]))
+              for i, op in enumerate(ops)}
+
+    # algorithmic bytes per op (one launch of each op per step)
+    alg = {
+        "gen_points": 8 * n * d * R,              # write the point words
+        "kernel_column": 8 * n * R,               # write k1 (points regenerated in registers)
+        "eig": 2 * 8 * n * R,                     # read k1, write lambda (FP64)
+        "solve": (2 * esz + 8) * n * R,           # read y, read lambda (FP64), write c
+        "logdet": 8 * n * R,                      # read lambda
+    }
+    op_rows = {op: {"ms": round(per_op[op], 5),
+                    "alg_bytes": alg[op],
+                    "GB_s": round(alg[op] / (per_op[op] * 1e-3) / 1e9, 1),
+                    "hbm_frac": round(alg[op] / (per_op[op] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+               for op in ops}
+    dom = max(ops, key=lambda o: per_op[o])
+    roof_dom = {"kernel": dom, "bound": "hbm", "achieved": op_rows[dom]["GB_s"],
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": op_rows[dom]["hbm_frac"],
+                "traffic": None}
+    ms_per_step = total_ms / K
+    solves_per_s = R * K / (total_ms * 1e-3)
+
+    out = {
+        "metric": "Gram solves/s and GB/s (% HBM peak) at n=2^20,d=32; batched+grad vs plain",
+        "value": round(solves_per_s, 2),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": "lattice_m20_d32_si2 (rank-1 lattice n=2^20 d=32, order-2 SI "
+                               "kernel, gamma_j=1/j^2, sigma^2=1e-3, one RHS): gen_points + "
+                               "kernel_column + eig + solve + logdet per step",
+                   "n": n, "d": d, "R": R, "nrhs": 1},
+        "roofline": roof_dom,
+        "solve_roofline": {"bound": "hbm", "achieved": op_rows["solve"]["GB_s"],
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": op_rows["solve"]["hbm_frac"],
+                           "solves_per_s_cached_lambda": round(1e3 / per_op["solve"], 1)},
+        "ops": op_rows,
+        "wall_s_timed": round(wall, 4),
+    }
+
+    if args.copy_probe:
+        src = torch.empty(32 * 2**20, dtype=torch.float64, device="cuda").uniform_()
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(10):
+            dst.copy_(src)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / 10
+        out["copy_probe"] = {"bytes_read": src.numel() * 8, "bytes_written": dst.numel() * 8,
+                             "ms": round(ms, 5),
+                             "GB_s": round(2 * src.numel() * 8 / (ms * 1e-3) / 1e9, 1)}
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(w, budget_s):
+    """The oracle (single-threaded C, FP64) running the same whole step on the
+    host until about budget_s seconds have passed (at least one step).  The
+    responses y are synthesised once, outside the timed loop."""
+    import numpy as np
+
+    import oracle
+    import workloads as W
+
+    oracle.lib()
+    pts = oracle.points(w)
+    y = np.ascontiguousarray(W.sine_response(W.to_unit_f64(pts), w["eps"][:, 0, :])[:, None, :])
+    del pts
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        pts = oracle.points(w)
+        k1 = oracle.kernel_column("lattice", pts, pts[:, 0], w["alpha"], w["gamma"], w["zeta"])
+        lam, _ = oracle.eig("lattice", k1)
+        oracle.solve("lattice", lam, w["sigma2"], y)
+        oracle.logdet(lam, w["sigma2"])
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return {"value": round(steps / el, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} whole step(s) of the same workload (points, first column, "
+                      f"FFTBR eigenvalues, solve, log-det at n=2^20, d=32) in the "
+                      f"single-threaded C oracle, FP64, {el:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -30,8 +30,12 @@
  *    x in [0,1): digit t (weight 2^-t, t = 1..64) is bit 64 - t.  Floating
  *    kernels use x = u * 2^-64 rounded to nearest.
  *  - Real data are double (LDK_F64) or float (LDK_F32) as selected by
- *    `dtype`; complex data are interleaved (re, im) pairs of that type.  The
- *    nugget sigma^2 is added, and divided by, in FP64 for either dtype.
+ *    `dtype`; complex data are interleaved (re, im) pairs of that type.
+ *  - Eigenvalues are always FP64 (double): the small ones carry an absolute
+ *    rounding error of about u ||k1|| and decide lambda + sigma^2, so they are
+ *    never held in FP32.  `dtype` selects the storage and transform
+ *    arithmetic of the per-solve data (k1, y, c, transformed responses); the
+ *    nugget sigma^2 is added, and divided by, in FP64.
  *  - Calls are reentrant.  Twiddle tables are built once per device by
  *    ldk_init() (called implicitly by the first entry point that needs it;
  *    call it explicitly before capturing calls into a HIP graph).
@@ -145,25 +149,30 @@ int ldk_transform(int kind, int dir, int B, int m, int dtype, const void *in, vo
 
 /* Eigenvalues lambda = sqrt(n) conj(V_m) k1 (Sec. 5.4): sqrt(n) FFTBR(k1)
  * (lattice; real since K is real symmetric) or sqrt(n) FWHT(k1) (net).
- * k1, lam = real dtype[R][n], natural frequency / Walsh order. */
-int ldk_eig(int kind, int R, int m, int dtype, const void *k1, void *lam, void *ws,
+ * k1 = real dtype[R][n]; lam = double[R][n], natural frequency / Walsh
+ * order.  The transform runs in FP64 for either input dtype.
+ * ws: ldk_workspace_bytes(LDK_OP_EIG, ...) bytes (lattice only). */
+int ldk_eig(int kind, int R, int m, int dtype, const void *k1, double *lam, void *ws,
             ldk_stream stream);
 
 /* Solve (K + sigma^2 I) c = y:  c = V (conj(V) y (/) (lambda + sigma^2)) (Sec. 5.4).
- * lam = dtype[R][n], y, c = dtype[R][nrhs][n] (y and c may alias exactly).
- * sigma2 >= 0; the division is done in FP64. */
-int ldk_solve(int kind, int R, int nrhs, int m, int dtype, const void *lam, double sigma2,
+ * lam = double[R][n]; y, c = dtype[R][nrhs][n] (y and c may alias exactly;
+ * right-hand side q of replication r uses row r of lam).  sigma2 >= 0; the
+ * division is done in FP64.  ws: ldk_workspace_bytes(LDK_OP_SOLVE, kind,
+ * R * nrhs, m, dtype) bytes (lattice with n > 2^11 only). */
+int ldk_solve(int kind, int R, int nrhs, int m, int dtype, const double *lam, double sigma2,
               const void *y, void *c, void *ws, ldk_stream stream);
 
 /* Matvec K y = V (conj(V) y (.) lambda) (Sec. 5.4); layout as ldk_solve. */
-int ldk_matvec(int kind, int R, int nrhs, int m, int dtype, const void *lam, const void *y,
+int ldk_matvec(int kind, int R, int nrhs, int m, int dtype, const double *lam, const void *y,
                void *out, void *ws, ldk_stream stream);
 
 /* log det(K + sigma^2 I) = sum_k log(lambda_k + sigma^2) (V unitary, Sec. 5.4),
- * accumulated in FP64 in a fixed order.  out = device double[R]; a row with
- * some lambda_k + sigma^2 <= 0 yields NaN.  ws: ldk_workspace_bytes(LDK_OP_LOGDET). */
-int ldk_logdet(int R, int m, int dtype, const void *lam, double sigma2, double *out,
-               void *ws, ldk_stream stream);
+ * accumulated in FP64 in a fixed order (bit-reproducible run to run).
+ * lam = double[R][n]; out = device double[R]; a row with some
+ * lambda_k + sigma^2 <= 0 yields NaN.  ws: ldk_workspace_bytes(LDK_OP_LOGDET). */
+int ldk_logdet(int R, int m, const double *lam, double sigma2, double *out, void *ws,
+               ldk_stream stream);
 
 /* Transform update when n doubles (Sec. 5.4, eq. ft_next_parts and its listings):
  *   yt_full = 2^-1/2 [ yt_old + w (.) FT_m(y_new) ; yt_old - w (.) FT_m(y_new) ],
@@ -176,10 +185,11 @@ int ldk_update_double(int kind, int B, int m, int dtype, const void *yt_old,
 
 /* Eigenvalue update when n doubles:  with lh = sqrt(n) FT_m(k1_new),
  *   lam_full = [ lam_old + Re(w (.) lh) ; lam_old - Re(w (.) lh) ],
- * k1_new = first-column entries of points n .. 2n-1.  lam_old, k1_new =
- * real [R][n]; lam_full = real [R][2n]. */
-int ldk_eig_update_double(int kind, int R, int m, int dtype, const void *lam_old,
-                          const void *k1_new, void *lam_full, void *ws, ldk_stream stream);
+ * k1_new = first-column entries of points n .. 2n-1 (dtype [R][n]);
+ * lam_old = double[R][n]; lam_full = double[R][2n].  FP64 arithmetic.
+ * ws: ldk_workspace_bytes(LDK_OP_EIG_UPDATE_DOUBLE, ...) bytes (lattice). */
+int ldk_eig_update_double(int kind, int R, int m, int dtype, const double *lam_old,
+                          const void *k1_new, double *lam_full, void *ws, ldk_stream stream);
 
 typedef enum {
     LDK_OP_TRANSFORM = 0,

@@ -66,7 +66,7 @@ def lib():
             "ldk_eig": ([i32, i32, i32, i32, P, P, P, P], i32),
             "ldk_solve": ([i32, i32, i32, i32, i32, P, f64, P, P, P, P], i32),
             "ldk_matvec": ([i32, i32, i32, i32, i32, P, P, P, P, P], i32),
-            "ldk_logdet": ([i32, i32, i32, P, f64, P, P, P], i32),
+            "ldk_logdet": ([i32, i32, P, f64, P, P, P], i32),
             "ldk_update_double": ([i32, i32, i32, i32, P, P, P, P, P], i32),
             "ldk_eig_update_double": ([i32, i32, i32, i32, P, P, P, P, P], i32),
             "ldk_workspace_bytes": ([i32, i32, i64, i32, i32], C.c_size_t),
@@ -223,21 +223,30 @@ def transform(kind, x: torch.Tensor, inverse: bool = False, out=None):
     return out
 
 
-def eig(kind, k1: torch.Tensor, out=None):
+def _need_f64(t: torch.Tensor, name: str):
+    _need(t, name)
+    if t.dtype != torch.float64:
+        raise LdkError(f"{name} must be float64 (eigenvalues are always FP64)")
+
+
+def eig(kind, k1: torch.Tensor, out=None, ws=None):
+    """lambda = sqrt(n) FT(k1) in FP64 (k1 may be float32 or float64)."""
     kd = _kind(kind)
     _need(k1, "k1")
     dt = _dtype_code(k1.dtype)
     R, n = k1.shape
     m = _m_of(n)
-    out = torch.empty_like(k1) if out is None else out
-    ws = _workspace(OP_EIG, kd, R, m, dt, k1.device)
+    out = torch.empty((R, n), dtype=torch.float64, device=k1.device) if out is None else out
+    _need_f64(out, "out")
+    if ws is None:
+        ws = _workspace(OP_EIG, kd, R, m, dt, k1.device)
     _check(lib().ldk_eig(kd, R, m, dt, _ptr(k1), _ptr(out), _ptr(ws), _stream()), "ldk_eig")
     return out
 
 
 def solve(kind, lam: torch.Tensor, sigma2: float, y: torch.Tensor, out=None, ws=None):
     kd = _kind(kind)
-    _need(lam, "lam")
+    _need_f64(lam, "lam")
     _need(y, "y")
     dt = _dtype_code(y.dtype)
     R, nrhs, n = y.shape
@@ -252,7 +261,7 @@ def solve(kind, lam: torch.Tensor, sigma2: float, y: torch.Tensor, out=None, ws=
 
 def matvec(kind, lam: torch.Tensor, y: torch.Tensor, out=None, ws=None):
     kd = _kind(kind)
-    _need(lam, "lam")
+    _need_f64(lam, "lam")
     _need(y, "y")
     dt = _dtype_code(y.dtype)
     R, nrhs, n = y.shape
@@ -266,14 +275,13 @@ def matvec(kind, lam: torch.Tensor, y: torch.Tensor, out=None, ws=None):
 
 
 def logdet(lam: torch.Tensor, sigma2: float, out=None, ws=None):
-    _need(lam, "lam")
-    dt = _dtype_code(lam.dtype)
+    _need_f64(lam, "lam")
     R, n = lam.shape
     m = _m_of(n)
     out = torch.empty(R, dtype=torch.float64, device=lam.device) if out is None else out
     if ws is None:
-        ws = _workspace(OP_LOGDET, DNET_B2, R, m, dt, lam.device)
-    _check(lib().ldk_logdet(R, m, dt, _ptr(lam), float(sigma2), _ptr(out), _ptr(ws), _stream()),
+        ws = _workspace(OP_LOGDET, DNET_B2, R, m, F64, lam.device)
+    _check(lib().ldk_logdet(R, m, _ptr(lam), float(sigma2), _ptr(out), _ptr(ws), _stream()),
            "ldk_logdet")
     return out
 
@@ -295,13 +303,13 @@ def update_double(kind, yt_old: torch.Tensor, y_new: torch.Tensor, out=None):
 
 def eig_update_double(kind, lam_old: torch.Tensor, k1_new: torch.Tensor, out=None):
     kd = _kind(kind)
-    _need(lam_old, "lam_old")
+    _need_f64(lam_old, "lam_old")
     _need(k1_new, "k1_new")
-    dt = _dtype_code(lam_old.dtype)
+    dt = _dtype_code(k1_new.dtype)
     R, n = lam_old.shape
     m = _m_of(n)
     if out is None:
-        out = torch.empty((R, 2 * n), dtype=lam_old.dtype, device=lam_old.device)
+        out = torch.empty((R, 2 * n), dtype=torch.float64, device=lam_old.device)
     ws = _workspace(OP_EIG_UPDATE_DOUBLE, kd, R, m, dt, lam_old.device)
     _check(lib().ldk_eig_update_double(kd, R, m, dt, _ptr(lam_old), _ptr(k1_new), _ptr(out),
                                        _ptr(ws), _stream()), "ldk_eig_update_double")

@@ -28,12 +28,12 @@ size_t cplx_rows_bytes(int64_t rows, int m, int dtype) { return (size_t)rows * (
 // n = 1 (m = 0): every transform is the identity.
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ void k_scalar_apply(const R *lam, const R *y, R *c, int64_t rows, int nrhs,
+__global__ void k_scalar_apply(const double *lam, const R *y, R *c, int64_t rows, int nrhs,
                                double sigma2, int mode)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= rows) return;
-    const double l = (double)lam[i / nrhs];
+    const double l = lam[i / nrhs];
     const double v = (double)y[i];
     c[i] = (R)(mode == 0 ? v / (l + sigma2) : v * l);
 }
@@ -41,19 +41,18 @@ __global__ void k_scalar_apply(const R *lam, const R *y, R *c, int64_t rows, int
 // ---------------------------------------------------------------------------
 // log det: fixed-order FP64 tree sums (deterministic run to run)
 // ---------------------------------------------------------------------------
-template <typename R>
-__global__ __launch_bounds__(LOGDET_THREADS) void k_logdet_partial(const R *lam, int64_t n,
+__global__ __launch_bounds__(LOGDET_THREADS) void k_logdet_partial(const double *lam, int64_t n,
                                                                    double sigma2, int chunks,
                                                                    double *partial)
 {
     __shared__ double red[LOGDET_THREADS];
     const int r = blockIdx.y, ch = blockIdx.x, t = threadIdx.x;
-    const R *row = lam + (int64_t)r * n;
+    const double *row = lam + (int64_t)r * n;
     const int64_t lo = (int64_t)ch * LOGDET_CHUNK;
     const int64_t hi = lo + LOGDET_CHUNK < n ? lo + LOGDET_CHUNK : n;
     double acc = 0.0;
     for (int64_t k = lo + t; k < hi; k += LOGDET_THREADS) {
-        const double s = (double)row[k] + sigma2;
+        const double s = row[k] + sigma2;
         acc += s > 0.0 ? log(s) : __builtin_nan("");
     }
     red[t] = acc;
@@ -122,24 +121,33 @@ __global__ void k_update_combine(const void *old_, void *full_, const void *u_, 
     }
 }
 
-template <typename R, bool CPLX>
-__global__ void k_eig_update_combine(const R *old, R *full, const void *u_, int64_t u_row,
+// U: complex double (lattice, transformed) or real U_T (net, or n = 1).
+template <bool CPLX, typename U_T>
+__global__ void k_eig_update_combine(const double *old, double *full, const void *u_, int64_t u_row,
                                      int64_t rows, int m)
 {
     const int64_t n = (int64_t)1 << m;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= rows * n) return;
     const int64_t row = gid >> m, k = gid & (n - 1);
-    R part;
+    double part;
     if constexpr (CPLX) {
-        const cplx<R> u = static_cast<const cplx<R> *>(u_)[row * u_row + k];
-        part = cmul(u, tw_any<R>((uint64_t)k, m + 1)).re;
+        const cplx<double> u = static_cast<const cplx<double> *>(u_)[row * u_row + k];
+        part = cmul(u, tw_any<double>((uint64_t)k, m + 1)).re;
     } else {
-        part = static_cast<const R *>(u_)[row * u_row + k];
+        part = (double)static_cast<const U_T *>(u_)[row * u_row + k];
     }
-    const R o = old[row * n + k];
+    const double o = old[row * n + k];
     full[row * 2 * n + k] = o + part;
     full[row * 2 * n + n + k] = o - part;
+}
+
+// n = 1 eigenvalues: lambda = k1 (widened to FP64).
+template <typename R>
+__global__ void k_widen(const R *in, double *out, int64_t count)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) out[i] = (double)in[i];
 }
 
 unsigned blocks_for(int64_t work, int threads) { return (unsigned)((work + threads - 1) / threads); }
@@ -149,7 +157,7 @@ unsigned blocks_for(int64_t work, int threads) { return (unsigned)((work + threa
 // at the last store.
 int forward_all(int kind, int dtype, int m, int64_t rows, const void *src, int64_t src_row,
                 bool src_real, void *dst, int64_t dst_row, bool dst_real, void *tmp,
-                int64_t tmp_row, double scale, hipStream_t s)
+                int64_t tmp_row, double scale, hipStream_t s, bool src_f32 = false)
 {
     const Plan pl = make_plan(m, log_tile_for(kind, dtype));
     for (int p = 0; p < pl.P; ++p) {
@@ -165,7 +173,8 @@ int forward_all(int kind, int dtype, int m, int64_t rows, const void *src, int64
         a.nrhs = 1;
         a.global_tw = p > 0;
         a.scale = last ? scale : 1.0;
-        const int st = launch_pass(kind, dtype, PM_FWD, first && src_real, last && dst_real, a, s);
+        const int st = launch_pass(kind, dtype, PM_FWD, first && src_real, last && dst_real, a, s,
+                                   first && src_f32);
         if (st) return st;
     }
     return LDK_OK;
@@ -173,7 +182,7 @@ int forward_all(int kind, int dtype, int m, int64_t rows, const void *src, int64
 
 // Solve / matvec through all passes: src (real rows) -> dst (real rows);
 // complex intermediates (lattice, more than one pass) live in tmp.
-int apply_all(int kind, int dtype, int mode, int m, int64_t rows, int nrhs, const void *lam,
+int apply_all(int kind, int dtype, int mode, int m, int64_t rows, int nrhs, const double *lam,
               double sigma2, const void *src, void *dst, void *tmp, hipStream_t s)
 {
     const Plan pl = make_plan(m, log_tile_for(kind, dtype));
@@ -237,7 +246,11 @@ size_t ws_bytes(int op, int kind, int64_t B, int m, int dtype)
     const int P = make_plan(m, log_tile_for(kind, dtype)).P;
     switch (op) {
     case LDK_OP_TRANSFORM: return 0;
-    case LDK_OP_EIG: return (lat && P > 1) ? cplx_rows_bytes(B, m, dtype) : 0;
+    case LDK_OP_EIG: {
+        // FP64 transform whatever the input dtype
+        const int P64 = make_plan(m, log_tile_for(kind, LDK_F64)).P;
+        return (lat && P64 > 1) ? cplx_rows_bytes(B, m, LDK_F64) : 0;
+    }
     case LDK_OP_SOLVE:
     case LDK_OP_MATVEC: return (lat && P > 1) ? cplx_rows_bytes(B, m, dtype) : 0;
     case LDK_OP_LOGDET: {
@@ -246,7 +259,7 @@ size_t ws_bytes(int op, int kind, int64_t B, int m, int dtype)
         return (size_t)B * chunks * sizeof(double);
     }
     case LDK_OP_UPDATE_DOUBLE: return 0;
-    case LDK_OP_EIG_UPDATE_DOUBLE: return lat ? cplx_rows_bytes(B, m, dtype) : 0;
+    case LDK_OP_EIG_UPDATE_DOUBLE: return lat ? cplx_rows_bytes(B, m, LDK_F64) : 0;
     default: return 0;
     }
 }
@@ -304,7 +317,7 @@ int ldk_transform(int kind, int dir, int B, int m, int dtype, const void *in, vo
     return LDK_OK;
 }
 
-int ldk_eig(int kind, int R, int m, int dtype, const void *k1, void *lam, void *ws,
+int ldk_eig(int kind, int R, int m, int dtype, const void *k1, double *lam, void *ws,
             ldk_stream stream)
 {
     if (!valid_kind(kind) || !valid_dtype(dtype) || !valid_m(m) || R < 0 || !k1 || !lam)
@@ -316,15 +329,22 @@ int ldk_eig(int kind, int R, int m, int dtype, const void *k1, void *lam, void *
     hipStream_t s = as_stream(stream);
     const int64_t n = (int64_t)1 << m;
     if (m == 0) {
-        if (k1 != lam) LDK_HIP_CHECK(hipMemcpyAsync(lam, k1, esize(dtype) * R, hipMemcpyDeviceToDevice, s));
+        if (dtype == LDK_F64)
+            hipLaunchKernelGGL(k_widen<double>, dim3(blocks_for(R, 256)), dim3(256), 0, s,
+                               (const double *)k1, lam, (int64_t)R);
+        else
+            hipLaunchKernelGGL(k_widen<float>, dim3(blocks_for(R, 256)), dim3(256), 0, s,
+                               (const float *)k1, lam, (int64_t)R);
+        LDK_LAUNCH_CHECK();
         return LDK_OK;
     }
     const bool lat = kind == LDK_LATTICE;
-    // lambda = sqrt(n) * orthonormal transform = unnormalised transform
-    return forward_all(kind, dtype, m, R, k1, n, lat, lam, n, lat, lat ? ws : lam, n, 1.0, s);
+    // lambda = sqrt(n) * orthonormal transform = unnormalised transform, in FP64
+    return forward_all(kind, LDK_F64, m, R, k1, n, lat, lam, n, lat, lat ? ws : (void *)lam, n, 1.0,
+                       s, dtype == LDK_F32);
 }
 
-static int apply_entry(int mode, int kind, int R, int nrhs, int m, int dtype, const void *lam,
+static int apply_entry(int mode, int kind, int R, int nrhs, int m, int dtype, const double *lam,
                        double sigma2, const void *y, void *c, void *ws, ldk_stream stream)
 {
     if (!valid_kind(kind) || !valid_dtype(dtype) || !valid_m(m) || R < 0 || nrhs < 0 || !lam ||
@@ -340,11 +360,11 @@ static int apply_entry(int mode, int kind, int R, int nrhs, int m, int dtype, co
     if (m == 0) {
         if (dtype == LDK_F64)
             hipLaunchKernelGGL(k_scalar_apply<double>, dim3(blocks_for(rows, 256)), dim3(256), 0, s,
-                               (const double *)lam, (const double *)y, (double *)c, rows, nrhs,
+                               lam, (const double *)y, (double *)c, rows, nrhs,
                                sigma2, mode == PM_SOLVE ? 0 : 1);
         else
             hipLaunchKernelGGL(k_scalar_apply<float>, dim3(blocks_for(rows, 256)), dim3(256), 0, s,
-                               (const float *)lam, (const float *)y, (float *)c, rows, nrhs,
+                               lam, (const float *)y, (float *)c, rows, nrhs,
                                sigma2, mode == PM_SOLVE ? 0 : 1);
         LDK_LAUNCH_CHECK();
         return LDK_OK;
@@ -352,35 +372,30 @@ static int apply_entry(int mode, int kind, int R, int nrhs, int m, int dtype, co
     return apply_all(kind, dtype, mode, m, rows, nrhs, lam, sigma2, y, c, ws, s);
 }
 
-int ldk_solve(int kind, int R, int nrhs, int m, int dtype, const void *lam, double sigma2,
+int ldk_solve(int kind, int R, int nrhs, int m, int dtype, const double *lam, double sigma2,
               const void *y, void *c, void *ws, ldk_stream stream)
 {
     return apply_entry(PM_SOLVE, kind, R, nrhs, m, dtype, lam, sigma2, y, c, ws, stream);
 }
 
-int ldk_matvec(int kind, int R, int nrhs, int m, int dtype, const void *lam, const void *y,
+int ldk_matvec(int kind, int R, int nrhs, int m, int dtype, const double *lam, const void *y,
                void *out, void *ws, ldk_stream stream)
 {
     return apply_entry(PM_MATVEC, kind, R, nrhs, m, dtype, lam, 0.0, y, out, ws, stream);
 }
 
-int ldk_logdet(int R, int m, int dtype, const void *lam, double sigma2, double *out, void *ws,
+int ldk_logdet(int R, int m, const double *lam, double sigma2, double *out, void *ws,
                ldk_stream stream)
 {
-    if (!valid_dtype(dtype) || !valid_m(m) || R < 0 || R > 65535 || !lam || !out || !(sigma2 >= 0.0))
-        return LDK_EINVAL;
+    if (!valid_m(m) || R < 0 || R > 65535 || !lam || !out || !(sigma2 >= 0.0)) return LDK_EINVAL;
     if (R == 0) return LDK_OK;
     if (!ws) return LDK_EINVAL;
     hipStream_t s = as_stream(stream);
     const int64_t n = (int64_t)1 << m;
     const int chunks = (int)((n + LOGDET_CHUNK - 1) / LOGDET_CHUNK);
     double *partial = static_cast<double *>(ws);
-    if (dtype == LDK_F64)
-        hipLaunchKernelGGL(k_logdet_partial<double>, dim3(chunks, R), dim3(LOGDET_THREADS), 0, s,
-                           (const double *)lam, n, sigma2, chunks, partial);
-    else
-        hipLaunchKernelGGL(k_logdet_partial<float>, dim3(chunks, R), dim3(LOGDET_THREADS), 0, s,
-                           (const float *)lam, n, sigma2, chunks, partial);
+    hipLaunchKernelGGL(k_logdet_partial, dim3(chunks, R), dim3(LOGDET_THREADS), 0, s, lam, n, sigma2,
+                       chunks, partial);
     LDK_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_logdet_final, dim3(R), dim3(LOGDET_THREADS), 0, s, partial, chunks, out);
     LDK_LAUNCH_CHECK();
@@ -447,8 +462,8 @@ int ldk_update_double(int kind, int B, int m, int dtype, const void *yt_old, con
     return LDK_OK;
 }
 
-int ldk_eig_update_double(int kind, int R, int m, int dtype, const void *lam_old,
-                          const void *k1_new, void *lam_full, void *ws, ldk_stream stream)
+int ldk_eig_update_double(int kind, int R, int m, int dtype, const double *lam_old,
+                          const void *k1_new, double *lam_full, void *ws, ldk_stream stream)
 {
     if (!valid_kind(kind) || !valid_dtype(dtype) || !valid_m(m) || m + 1 > TW_MAX_LOG || R < 0 ||
         !lam_old || !k1_new || !lam_full)
@@ -460,44 +475,34 @@ int ldk_eig_update_double(int kind, int R, int m, int dtype, const void *lam_old
     if (st) return st;
     hipStream_t s = as_stream(stream);
     const int64_t n = (int64_t)1 << m;
-    const void *u;
-    int64_t u_row;
-    bool u_cplx = lat;
-    if (m == 0) {
-        u = k1_new;  // FT_0 is the identity and w_0 = 1
-        u_row = 1;
-        u_cplx = false;
-    } else if (lat) {
-        st = forward_all(kind, dtype, m, R, k1_new, n, true, ws, n, false, ws, n, 1.0, s);
-        if (st) return st;
-        u = ws;
-        u_row = n;
-    } else {
-        void *dst = static_cast<unsigned char *>(lam_full) + n * esize(dtype);
-        st = forward_all(kind, dtype, m, R, k1_new, n, false, dst, 2 * n, false, dst, 2 * n, 1.0, s);
-        if (st) return st;
-        u = dst;
-        u_row = 2 * n;
-    }
     const int64_t work = (int64_t)R * n;
-    if (dtype == LDK_F64) {
-        if (u_cplx)
-            hipLaunchKernelGGL((k_eig_update_combine<double, true>), dim3(blocks_for(work, 256)),
-                               dim3(256), 0, s, (const double *)lam_old, (double *)lam_full, u,
-                               u_row, (int64_t)R, m);
+    const dim3 grid(blocks_for(work, 256)), block(256);
+    if (m == 0) {
+        // FT_0 is the identity and w_0 = 1: the new half is k1_new itself
+        if (dtype == LDK_F64)
+            hipLaunchKernelGGL((k_eig_update_combine<false, double>), grid, block, 0, s, lam_old,
+                               lam_full, k1_new, (int64_t)1, (int64_t)R, 0);
         else
-            hipLaunchKernelGGL((k_eig_update_combine<double, false>), dim3(blocks_for(work, 256)),
-                               dim3(256), 0, s, (const double *)lam_old, (double *)lam_full, u,
-                               u_row, (int64_t)R, m);
+            hipLaunchKernelGGL((k_eig_update_combine<false, float>), grid, block, 0, s, lam_old,
+                               lam_full, k1_new, (int64_t)1, (int64_t)R, 0);
+        LDK_LAUNCH_CHECK();
+        return LDK_OK;
+    }
+    if (lat) {
+        // complex FP64 transform of the new half in the workspace
+        st = forward_all(kind, LDK_F64, m, R, k1_new, n, true, ws, n, false, ws, n, 1.0, s,
+                         dtype == LDK_F32);
+        if (st) return st;
+        hipLaunchKernelGGL((k_eig_update_combine<true, double>), grid, block, 0, s, lam_old, lam_full,
+                           (const void *)ws, n, (int64_t)R, m);
     } else {
-        if (u_cplx)
-            hipLaunchKernelGGL((k_eig_update_combine<float, true>), dim3(blocks_for(work, 256)),
-                               dim3(256), 0, s, (const float *)lam_old, (float *)lam_full, u, u_row,
-                               (int64_t)R, m);
-        else
-            hipLaunchKernelGGL((k_eig_update_combine<float, false>), dim3(blocks_for(work, 256)),
-                               dim3(256), 0, s, (const float *)lam_old, (float *)lam_full, u, u_row,
-                               (int64_t)R, m);
+        // real FP64 transform of the new half, staged in the second half of lam_full
+        double *dst = lam_full + n;
+        st = forward_all(kind, LDK_F64, m, R, k1_new, n, false, dst, 2 * n, false, dst, 2 * n, 1.0, s,
+                         dtype == LDK_F32);
+        if (st) return st;
+        hipLaunchKernelGGL((k_eig_update_combine<false, double>), grid, block, 0, s, lam_old,
+                           lam_full, (const void *)dst, 2 * n, (int64_t)R, m);
     }
     LDK_LAUNCH_CHECK();
     return LDK_OK;

@@ -15,7 +15,9 @@ int validate_pointset(const ldk_pointset *ps, PointsetArgs *out)
 {
     if (!ps || !out) return LDK_EINVAL;
     if (ps->R < 1 || ps->R > 65535 || ps->d < 1 || ps->d > LDK_MAX_D) return LDK_EINVAL;
-    if (ps->m_max < 0 || ps->m_max > 62 || !ps->gen) return LDK_EINVAL;
+    if (ps->m_max < 0 || ps->m_max > 62) return LDK_EINVAL;
+    // a net with m_max = 0 has no generating-matrix columns
+    if (!ps->gen && !(ps->kind == LDK_DNET_B2 && ps->m_max == 0)) return LDK_EINVAL;
     if (ps->kind == LDK_LATTICE) {
         if (ps->order != LDK_NATURAL && ps->order != LDK_LINEAR) return LDK_EINVAL;
         if (ps->lms) return LDK_EINVAL;  // scrambling matrices belong to nets

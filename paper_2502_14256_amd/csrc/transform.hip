@@ -174,15 +174,19 @@ __device__ __forceinline__ void lds_write(const T (&v)[E], T *lds, int t, int gs
     for (int i = 0; i < E; ++i) lds[lds_idx(group_q(t, i, gs, pos, T_))] = v[i];
 }
 
-template <typename T>
+// SRC_F32: the source holds floats (real, or complex when !src_real) that are
+// widened to the FP64 working type.
+template <typename T, bool SRC_F32>
 __device__ __forceinline__ T load_elem(const void *p, int64_t idx, bool src_real)
 {
+    using R = typename real_of<T>::type;
+    using S = typename std::conditional<SRC_F32, float, R>::type;
     if constexpr (std::is_floating_point<T>::value) {
-        return static_cast<const T *>(p)[idx];
+        return (R) static_cast<const S *>(p)[idx];
     } else {
-        using R = typename real_of<T>::type;
-        if (src_real) return T{static_cast<const R *>(p)[idx], (R)0};
-        return static_cast<const T *>(p)[idx];
+        if (src_real) return T{(R) static_cast<const S *>(p)[idx], (R)0};
+        const cplx<S> v = static_cast<const cplx<S> *>(p)[idx];
+        return T{(R)v.re, (R)v.im};
     }
 }
 template <typename T>
@@ -200,7 +204,7 @@ __device__ __forceinline__ void store_elem(void *p, int64_t idx, T v, bool dst_r
 }
 
 // One pass over a tile: rows = 2^a along the axis, W = 2^logW columns.
-template <typename T, int LOGE, int MODE, bool SRC_REAL, bool DST_REAL>
+template <typename T, int LOGE, int MODE, bool SRC_REAL, bool DST_REAL, bool SRC_F32>
 __global__ __launch_bounds__(256) void k_pass(PassArgs a)
 {
     using R = typename real_of<T>::type;
@@ -238,7 +242,7 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a)
     // ---- load (coalesced: q = t + Tn * i; the registers hold the top group)
 #pragma unroll
     for (int i = 0; i < E; ++i)
-        v[i] = load_elem<T>(a.src, row * a.src_row + gidx(t + Tn * i), SRC_REAL);
+        v[i] = load_elem<T, SRC_F32>(a.src, row * a.src_row + gidx(t + Tn * i), SRC_REAL);
 
     if constexpr (MODE != PM_INV) {
         if constexpr (FFT) {
@@ -273,10 +277,10 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a)
     }
 
     if constexpr (MODE == PM_SOLVE || MODE == PM_MATVEC) {
-        const R *lam = static_cast<const R *>(a.lam) + (row / a.nrhs) * ((int64_t)1 << a.m);
+        const double *lam = a.lam + (row / a.nrhs) * ((int64_t)1 << a.m);
 #pragma unroll
         for (int i = 0; i < E; ++i) {
-            const double l = (double)lam[gidx(t + Tn * i)];
+            const double l = lam[gidx(t + Tn * i)];
             const double f = MODE == PM_SOLVE ? a.scale / (l + a.sigma2) : a.scale * l;
             v[i] = scl(v[i], (R)f);
         }
@@ -324,7 +328,7 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a)
     }
 }
 
-template <typename T, int LOGE, int MODE>
+template <typename T, int LOGE, int MODE, bool SRC_F32>
 int launch_t(bool src_real, bool dst_real, const PassArgs &a, hipStream_t s)
 {
     const int S = 1 << (a.g.a + a.g.logW);
@@ -333,34 +337,34 @@ int launch_t(bool src_real, bool dst_real, const PassArgs &a, hipStream_t s)
     if (blocks > 0x7fffffff || threads > 256 || threads < 1) return LDK_ENOTSUP;
     const size_t lds = (size_t)(S + (S >> LDS_PAD_SHIFT)) * sizeof(T);
     if constexpr (std::is_floating_point<T>::value) {
-        hipLaunchKernelGGL((k_pass<T, LOGE, MODE, false, false>), dim3((unsigned)blocks),
+        hipLaunchKernelGGL((k_pass<T, LOGE, MODE, false, false, SRC_F32>), dim3((unsigned)blocks),
                            dim3(threads), lds, s, a);
     } else {
         if (src_real && dst_real)
-            hipLaunchKernelGGL((k_pass<T, LOGE, MODE, true, true>), dim3((unsigned)blocks),
+            hipLaunchKernelGGL((k_pass<T, LOGE, MODE, true, true, SRC_F32>), dim3((unsigned)blocks),
                                dim3(threads), lds, s, a);
         else if (src_real)
-            hipLaunchKernelGGL((k_pass<T, LOGE, MODE, true, false>), dim3((unsigned)blocks),
+            hipLaunchKernelGGL((k_pass<T, LOGE, MODE, true, false, SRC_F32>), dim3((unsigned)blocks),
                                dim3(threads), lds, s, a);
         else if (dst_real)
-            hipLaunchKernelGGL((k_pass<T, LOGE, MODE, false, true>), dim3((unsigned)blocks),
+            hipLaunchKernelGGL((k_pass<T, LOGE, MODE, false, true, SRC_F32>), dim3((unsigned)blocks),
                                dim3(threads), lds, s, a);
         else
-            hipLaunchKernelGGL((k_pass<T, LOGE, MODE, false, false>), dim3((unsigned)blocks),
+            hipLaunchKernelGGL((k_pass<T, LOGE, MODE, false, false, SRC_F32>), dim3((unsigned)blocks),
                                dim3(threads), lds, s, a);
     }
     LDK_LAUNCH_CHECK();
     return LDK_OK;
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, bool SRC_F32>
 int launch_e(bool src_real, bool dst_real, const PassArgs &a, hipStream_t s)
 {
     switch (a.g.logE) {
-    case 1: return launch_t<T, 1, MODE>(src_real, dst_real, a, s);
-    case 2: return launch_t<T, 2, MODE>(src_real, dst_real, a, s);
-    case 3: return launch_t<T, 3, MODE>(src_real, dst_real, a, s);
-    case 4: return launch_t<T, 4, MODE>(src_real, dst_real, a, s);
+    case 1: return launch_t<T, 1, MODE, SRC_F32>(src_real, dst_real, a, s);
+    case 2: return launch_t<T, 2, MODE, SRC_F32>(src_real, dst_real, a, s);
+    case 3: return launch_t<T, 3, MODE, SRC_F32>(src_real, dst_real, a, s);
+    case 4: return launch_t<T, 4, MODE, SRC_F32>(src_real, dst_real, a, s);
     default: return LDK_ENOTSUP;
     }
 }
@@ -369,10 +373,10 @@ template <typename T>
 int launch_m(int mode, bool src_real, bool dst_real, const PassArgs &a, hipStream_t s)
 {
     switch (mode) {
-    case PM_FWD: return launch_e<T, PM_FWD>(src_real, dst_real, a, s);
-    case PM_INV: return launch_e<T, PM_INV>(src_real, dst_real, a, s);
-    case PM_SOLVE: return launch_e<T, PM_SOLVE>(src_real, dst_real, a, s);
-    case PM_MATVEC: return launch_e<T, PM_MATVEC>(src_real, dst_real, a, s);
+    case PM_FWD: return launch_e<T, PM_FWD, false>(src_real, dst_real, a, s);
+    case PM_INV: return launch_e<T, PM_INV, false>(src_real, dst_real, a, s);
+    case PM_SOLVE: return launch_e<T, PM_SOLVE, false>(src_real, dst_real, a, s);
+    case PM_MATVEC: return launch_e<T, PM_MATVEC, false>(src_real, dst_real, a, s);
     default: return LDK_EINVAL;
     }
 }
@@ -413,8 +417,14 @@ Plan make_plan(int m, int log_tile)
 int log_tile_for(int kind, int dtype) { return (kind == LDK_LATTICE && dtype == LDK_F64) ? 11 : 12; }
 
 int launch_pass(int kind, int dtype, int mode, bool src_real, bool dst_real, const PassArgs &a,
-                hipStream_t s)
+                hipStream_t s, bool src_f32)
 {
+    if (src_f32) {
+        // FP64 forward transform of float data (eigenvalues from an FP32 column)
+        if (dtype != LDK_F64 || mode != PM_FWD) return LDK_EINVAL;
+        if (kind == LDK_DNET_B2) return launch_e<double, PM_FWD, true>(false, false, a, s);
+        return launch_e<cplx<double>, PM_FWD, true>(src_real, dst_real, a, s);
+    }
     if (kind == LDK_DNET_B2) {
         if (dtype == LDK_F64) return launch_m<double>(mode, false, false, a, s);
         return launch_m<float>(mode, false, false, a, s);

@@ -48,7 +48,7 @@ struct PassArgs {
     int64_t rows;     // batch rows
     int m;
     PassGeom g;
-    const void *lam;  // eigenvalues [rows / nrhs][2^m] (solve / matvec)
+    const double *lam;  // eigenvalues [rows / nrhs][2^m] (solve / matvec), FP64
     int nrhs;
     int global_tw;    // apply the inter-pass FFT twiddle (column passes)
     double sigma2;
@@ -57,9 +57,11 @@ struct PassArgs {
 };
 
 // kind: LDK_LATTICE (complex FFTBR) or LDK_DNET_B2 (real FWHT).
+// dtype: working precision of the pass.
 // src_real: rows of src are real (promoted to complex) -- lattice only.
 // dst_real: keep only the real part when storing -- lattice only.
+// src_f32: src holds floats widened to the FP64 working type (PM_FWD only).
 int launch_pass(int kind, int dtype, int mode, bool src_real, bool dst_real, const PassArgs &a,
-                hipStream_t s);
+                hipStream_t s, bool src_f32 = false);
 
 }  // namespace ldk

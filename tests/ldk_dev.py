@@ -70,3 +70,13 @@ def solve_tol(lam, sigma2, y, c, m, eps):
     ratio = max(dmax[r] * np.linalg.norm(y[r]) / max(np.linalg.norm(c[r]), 1e-300)
                 for r in range(R))
     return 4.0 * (2 * m + 2) * eps * ratio
+
+
+def record(name, **vals):
+    """Append measured errors to gpurun_out/parity_errors.jsonl (when present)."""
+    import json
+    import os
+    d = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+    if os.path.isdir(d):
+        with open(os.path.join(d, "parity_errors.jsonl"), "a") as f:
+            f.write(json.dumps({"case": name, **{k: float(v) for k, v in vals.items()}}) + "\n")

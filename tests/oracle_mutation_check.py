@@ -1,0 +1,42 @@
+"""Mutation check of the oracle pins (run by hand on the CPU: python tests/oracle_mutation_check.py).
+
+Plants one plausible mistake at a time in the C oracle, runs the CPU test
+suite, and reports whether the pins catch it; the sources are restored after
+each run.  Not collected by pytest."""
+import subprocess, sys, os
+os.chdir(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+muts = [
+ ("oracle/orc_kernels.c", "(701.0 / 294.0)", "(701.0 / 295.0)"),
+ ("oracle/orc_kernels.c", "return -1.0 + b * x * x - 5.0", "return -1.0 - b * x * x - 5.0"),
+ ("oracle/orc_kernels.c", "return -1.0 - b * x + 2.5 * (1.0 - t1);", "return -1.0 + b * x + 2.5 * (1.0 - t1);"),
+ ("oracle/orc_kernels.c", "series / 48.0", "series / 47.0"),
+ ("oracle/orc_kernels.c", "(digit(delta, a + 1) ? -1.0 : 1.0)", "(digit(delta, a + 2) ? -1.0 : 1.0)"),
+ ("oracle/orc_kernels.c", "const double sign = (alpha % 2 == 1) ? 1.0 : -1.0;", "const double sign = 1.0;"),
+ ("oracle/orc_kernels.c", "1.0 / 42.0};", "1.0 / 41.0};"),
+ ("oracle/orc_kernels.c", "return 1.0 - 3.0 * t1;", "return 1.0 - 2.0 * t1;"),
+ ("oracle/orc_algebra.inc", "const REAL ang = -2 * PI_R", "const REAL ang = 2 * PI_R"),
+ ("oracle/orc_algebra.inc", "x[k + j + half] = w * (a - b) * h;", "x[k + j + half] = (a - b) * h;"),
+ ("oracle/orc_algebra.inc", "for (int64_t half = 1; half < n; half *= 2)", "for (int64_t half = 1; half < n / 2; half *= 2)"),
+ ("oracle/orc_algebra.inc", "x[k + j + half] = (a - b) * h;\n            }\n}", "x[k + j + half] = (b - a) * h;\n            }\n}"),
+ ("oracle/orc_algebra.inc", "w[k] / (l + (REAL)sigma2)", "w[k] / (l - (REAL)sigma2)"),
+ ("oracle/orc_algebra.inc", "const REAL sn = RSQRT((REAL)n);", "const REAL sn = (REAL)n;"),
+ ("oracle/orc_algebra.c", "const double ang = -M_PI * (double)k / (double)n;\n                const double complex om = cos(ang) + sin(ang) * I;\n                const double complex a", "const double ang = M_PI * (double)k / (double)n;\n                const double complex om = cos(ang) + sin(ang) * I;\n                const double complex a"),
+ ("oracle/orc_points.c", "if (digit) z += (t == 64) ? g[j] : (g[j] << (64 - t));", "if (digit) z += (t == 64) ? g[j] : (g[j] << (63 - t));"),
+ ("oracle/orc_points.c", "acc += s_ts * col_bit(C[(size_t)j * m + k], s);", "acc += (int)((S[(size_t)j * 64 + s] >> (63 - t)) & 1u) * col_bit(C[(size_t)j * m + k], s);"),
+ ("oracle/orc_points.c", "out[((size_t)r * cnt + ii) * d + j] = z ^ delta;", "out[((size_t)r * cnt + ii) * d + j] = z + delta;"),
+ ("oracle/orc_points.c", "uint64_t orc_gray(uint64_t i) { return i ^ (i >> 1); }", "uint64_t orc_gray(uint64_t i) { return i ^ (i << 1); }"),
+]
+res = []
+for f, a, b in muts:
+    src = open(f).read()
+    assert src.count(a) >= 1, (f, a)
+    open(f, 'w').write(src.replace(a, b, 1))
+    try:
+        r = subprocess.run([sys.executable, '-m', 'pytest', 'tests/', '-q', '-x', '-p', 'no:cacheprovider'], capture_output=True, text=True, timeout=600)
+        caught = r.returncode != 0
+    finally:
+        open(f, 'w').write(src)
+    res.append((caught, f, b[:60]))
+    print('CAUGHT ' if caught else 'MISSED ', f, repr(b[:70]), flush=True)
+subprocess.run([sys.executable, '-c', 'import sys; sys.path.insert(0,"."); import oracle; oracle.build()'])
+print(sum(c for c,_,_ in res), 'of', len(res), 'caught')

@@ -9,7 +9,7 @@ import torch
 
 import workloads as W
 import paper_2502_14256_amd as ldk
-from ldk_dev import (F32_EPS, U64_EPS, dev_u64, host_u64, kernel, kernel_scale, pointset, rel,
+from ldk_dev import (F32_EPS, U64_EPS, host_u64, kernel, kernel_scale, pointset, record, rel,
                      solve_tol)
 
 pytestmark = pytest.mark.gpu
@@ -144,26 +144,27 @@ def test_eig_solve_matvec_logdet(orc, kind, m, nrhs, dtype):
     eps = U64_EPS if dtype == F64 else F32_EPS
     np_dt = np.float64 if dtype == F64 else np.float32
     k1 = _kcol(orc, w).astype(np_dt)
-    # eig
+    # eig: FP64 transform of the (possibly FP32) column
     lam_ref = orc.eig(kind, k1.astype(np.float64), precise=True)
     lam = ldk.eig(kind, torch.from_numpy(k1).cuda())
-    tol_eig = 1e-12 if dtype == F64 else 2e-6
-    assert rel(lam.cpu().numpy(), lam_ref) < tol_eig
-    # solve / matvec with identical lambda on both sides
-    lam_in = lam_ref.astype(np_dt)
-    lam64 = lam_in.astype(np.float64)
+    assert lam.dtype == torch.float64
+    assert rel(lam.cpu().numpy(), lam_ref) < 1e-12
+    # solve / matvec with identical (FP64) lambda on both sides; y, c in dtype
     y = w["y"].astype(np_dt)
+    lam_d = torch.from_numpy(lam_ref).cuda()
     for s2 in (1e-2, 1e-8):
-        c_ref = orc.solve(kind, lam64, s2, y.astype(np.float64), precise=True)
-        c = ldk.solve(kind, torch.from_numpy(lam_in).cuda(), s2, torch.from_numpy(y).cuda())
-        tol = max(1e-12 if dtype == F64 else 1e-5, solve_tol(lam64, s2, y, c_ref, m, eps))
-        assert rel(c.cpu().numpy(), c_ref) < tol, (s2, tol)
-    mv_ref = orc.matvec(kind, lam64, y.astype(np.float64), precise=True)
-    mv = ldk.matvec(kind, torch.from_numpy(lam_in).cuda(), torch.from_numpy(y).cuda())
+        c_ref = orc.solve(kind, lam_ref, s2, y.astype(np.float64), precise=True)
+        c = ldk.solve(kind, lam_d, s2, torch.from_numpy(y).cuda())
+        tol = max(1e-12 if dtype == F64 else 1e-5, solve_tol(lam_ref, s2, y, c_ref, m, eps))
+        err = rel(c.cpu().numpy(), c_ref)
+        record(f"solve_{kind}_m{m}_{np_dt.__name__}_s2={s2}", err=err, tol=tol)
+        assert err < tol, (s2, err, tol)
+    mv_ref = orc.matvec(kind, lam_ref, y.astype(np.float64), precise=True)
+    mv = ldk.matvec(kind, lam_d, torch.from_numpy(y).cuda())
     assert rel(mv.cpu().numpy(), mv_ref) < (1e-12 if dtype == F64 else 2e-6)
-    # logdet (FP64 accumulation for both dtypes)
-    ld_ref = orc.logdet(lam64, 1e-3, precise=True)
-    ld = ldk.logdet(torch.from_numpy(lam_in).cuda(), 1e-3).cpu().numpy()
+    # logdet (FP64 throughout)
+    ld_ref = orc.logdet(lam_ref, 1e-3, precise=True)
+    ld = ldk.logdet(lam_d, 1e-3).cpu().numpy()
     assert np.all(np.abs(ld - ld_ref) <= 1e-12 * np.maximum(1.0, np.abs(ld_ref)) + 2**m * 1e-16)
 
 
@@ -218,8 +219,9 @@ def test_eig_update_double(orc, kind, m, dtype):
     np_dt = np.float64 if dtype == F64 else np.float32
     k1 = _kcol(orc, w).astype(np_dt)
     n = 2**m
-    lam_half = orc.eig(kind, k1[:, :n].astype(np.float64), precise=True).astype(np_dt)
+    lam_half = orc.eig(kind, k1[:, :n].astype(np.float64), precise=True)
     fresh = orc.eig(kind, k1.astype(np.float64), precise=True)
     got = ldk.eig_update_double(kind, torch.from_numpy(lam_half).cuda(),
                                 torch.from_numpy(np.ascontiguousarray(k1[:, n:])).cuda())
-    assert rel(got.cpu().numpy(), fresh) < (1e-12 if dtype == F64 else 2e-6)
+    assert got.dtype == torch.float64
+    assert rel(got.cpu().numpy(), fresh) < 1e-12

@@ -89,8 +89,8 @@ def test_algebra_rejects_bad_arguments():
     assert L.ldk_solve(ldk.DNET_B2, 0, 1, 4, 0, FAKE, 0.1, FAKE, FAKE, None, None) == 0
     # lattice solve with more than one pass needs its workspace
     assert L.ldk_solve(ldk.LATTICE, 1, 1, 20, 0, FAKE, 0.1, FAKE, FAKE, None, None) == -1
-    assert L.ldk_logdet(1, 4, 0, FAKE, 0.1, FAKE, None, None) == -1  # workspace missing
-    assert L.ldk_logdet(1, 4, 0, FAKE, float("nan"), FAKE, FAKE, None) == -1
+    assert L.ldk_logdet(1, 4, FAKE, 0.1, FAKE, None, None) == -1  # workspace missing
+    assert L.ldk_logdet(1, 4, FAKE, float("nan"), FAKE, FAKE, None) == -1
     assert L.ldk_update_double(ldk.DNET_B2, 1, 26, 0, FAKE, FAKE, FAKE, None, None) == -1
     assert L.ldk_eig(ldk.LATTICE, 1, 20, 0, FAKE, FAKE, None, None) == -1
 
@@ -105,3 +105,5 @@ def test_workspace_sizes():
     assert ws(ldk.OP_SOLVE, ldk.LATTICE, 4, 10, 0) == 0  # one pass, no intermediate
     assert ws(ldk.OP_LOGDET, ldk.DNET_B2, 3, 20, 0) == 3 * 64 * 8
     assert ws(ldk.OP_EIG, 9, 1, 4, 0) == 0
+    # eigenvalue transforms run in FP64 whatever the input dtype
+    assert ws(ldk.OP_EIG, ldk.LATTICE, 2, 20, 1) == 2 * 2**20 * 16
