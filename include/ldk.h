@@ -106,8 +106,9 @@ typedef struct {
  *        alpha_j in {1, 2, 3, 4}; alpha = 1 is the order-1 kernel
  *        K_1(x) = 1 - 3 * 2^{-beta(x)} (a reading: the paper defers its form
  *        to the literature).
- *  alpha = device int32[d]; gamma = device double[d]; zeta > 0.  The alpha
- *  values are read on the device: an unsupported order yields NaN entries. */
+ *  alpha = HOST int32[d] (orders are configuration: validated on the host,
+ *  an order outside the range above gives LDK_EINVAL, and uniform orders get
+ *  specialised kernels); gamma = device double[d]; zeta > 0. */
 typedef struct {
     int32_t kind;
     int32_t d;

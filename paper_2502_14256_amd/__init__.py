@@ -162,18 +162,27 @@ class PointSet:
 
 @dataclass
 class Kernel:
-    """Product-weight SI (lattice) or DSI (net) kernel; alpha int32[d], gamma float64[d]."""
+    """Product-weight SI (lattice) or DSI (net) kernel.
+
+    alpha: per-dimension orders (host sequence of ints; kept on the host);
+    gamma: float64[d] device tensor of product weights; zeta > 0."""
 
     kind: str
-    alpha: torch.Tensor
+    alpha: object
     gamma: torch.Tensor
     zeta: float = 1.0
 
+    def __post_init__(self):
+        import numpy as np
+
+        a = self.alpha.cpu().numpy() if isinstance(self.alpha, torch.Tensor) else self.alpha
+        self._alpha_host = np.ascontiguousarray(np.asarray(a, dtype=np.int32).ravel())
+
     def _c(self) -> _Kernel:
-        _need(self.alpha, "alpha")
         _need(self.gamma, "gamma")
-        return _Kernel(_kind(self.kind), int(self.alpha.numel()), _ptr(self.alpha),
-                       _ptr(self.gamma), float(self.zeta))
+        return _Kernel(_kind(self.kind), int(self._alpha_host.size),
+                       C.c_void_p(self._alpha_host.ctypes.data), _ptr(self.gamma),
+                       float(self.zeta))
 
 
 def gen_points(ps: PointSet, n_min: int, n_max: int, out: torch.Tensor | None = None):

@@ -13,7 +13,7 @@ namespace ldk {
 namespace {
 
 constexpr int LOGDET_THREADS = 256;
-constexpr int LOGDET_CHUNK = 16384;  // elements per partial sum
+constexpr int LOGDET_CHUNK = 2048;  // eigenvalues per partial sum (one workgroup)
 
 size_t esize(int dtype) { return dtype == LDK_F64 ? 8 : 4; }
 

@@ -3,108 +3,71 @@
 // with SI factors (Sec. 5.2, Bernoulli polynomials) for lattices and DSI
 // factors (Sec. 5.3, Theorem 1) for base-2 digital nets.  This op is
 // ALU-bound: the points are either read once or regenerated in registers.
+#include <type_traits>
+
 #include "pointset.hpp"
 
 namespace ldk {
 
 namespace {
 constexpr int KC_THREADS = 256;
+constexpr int KC_LOG_THREADS = 8;
 constexpr int KC_ITERS = 8;       // points per thread (spaced KC_THREADS apart)
 constexpr int KC_DIM_CHUNK = 32;  // dimensions whose net tables sit in LDS at once
+constexpr int KC_TILE = KC_THREADS * KC_ITERS;
+constexpr int KC_CODE_WORDS = LDK_MAX_D / 32;  // 2-bit order codes, 32 per word
 }  // namespace
 
 // ---- SI factor, Sec. 5.2:  K_a(x) = (2 pi)^{2a} / ((-1)^{a+1} (2a)!) B_{2a}(x) ----
-// B_2 = x^2 - x + 1/6, B_4 = x^2 (1-x)^2 - 1/30, B_6 = x^6 - 3x^5 + 5/2 x^4 - 1/2 x^2 + 1/42.
-template <typename R>
-__device__ __forceinline__ R si_factor(int alpha, R x)
+// With w = x^2 - x the Bernoulli polynomials are cubics in w:
+//   B_2 = w + 1/6,  B_4 = w^2 - 1/30,  B_6 = w^3 - w^2/2 + 1/42,
+// so 1 + gamma K_a(x) = c0 + c1 w + c2 w^2 + c3 w^3 with per-dimension c.
+struct SiPoly {
+    double c0, c1, c2, c3;
+};
+__device__ __forceinline__ SiPoly si_poly(int alpha, double gamma)
 {
-    const R pi2 = (R)9.8696044010893586188344909998761511;  // pi^2
-    if (alpha < 1) return (R)__builtin_nan("");
-    if (alpha == 1) return (R)2 * pi2 * ((x - (R)1) * x + (R)(1.0 / 6.0));
-    const R x2 = x * x;
-    if (alpha == 2) {
-        const R w = (x - (R)1) * x;  // x^2 - x
-        return (R)(-2.0 / 3.0) * pi2 * pi2 * (w * w - (R)(1.0 / 30.0));
+    const double pi2 = 9.8696044010893586188344909998761511;
+    if (alpha == 1) {  // 2 pi^2 B_2
+        const double a = 2.0 * pi2 * gamma;
+        return {1.0 + a * (1.0 / 6.0), a, 0.0, 0.0};
     }
-    if (alpha != 3) return (R)__builtin_nan("");  // unsupported order: poison the column
-    // alpha == 3: (x^6 - 3x^5 + 5/2 x^4 - 1/2 x^2 + 1/42) * 4 pi^6 / 45
-    const R b6 = (((((x - (R)3) * x + (R)2.5) * x) * x - (R)0.5) * x2 + (R)(1.0 / 42.0));
-    return (R)(4.0 / 45.0) * pi2 * pi2 * pi2 * b6;
+    if (alpha == 2) {  // -2 pi^4 / 3 B_4
+        const double a = (-2.0 / 3.0) * pi2 * pi2 * gamma;
+        return {1.0 - a * (1.0 / 30.0), 0.0, a, 0.0};
+    }
+    const double a = (4.0 / 45.0) * pi2 * pi2 * pi2 * gamma;  // 4 pi^6 / 45 B_6
+    return {1.0 + a * (1.0 / 42.0), 0.0, -0.5 * a, a};
 }
-
-// sum_{a=0}^{20} (-1)^{xi_{a+1}} 8^{-a}: 21 leading digits of delta spread to
-// every third bit (bit i of the digit field lands at bit 3 i), so that
-// sum_{xi_{a+1} = 1} 8^{-a} = spread * 2^-60 exactly before rounding.
-__device__ __forceinline__ uint64_t spread3_21(uint64_t b)
+// ALPHA = 0: generic cubic (mixed orders); 1, 2: only the nonzero terms.
+template <typename R, int ALPHA>
+__device__ __forceinline__ R si_weighted(R x, R c0, R c1, R c2, R c3)
 {
-    b &= 0x1fffffull;
-    b = (b | (b << 32)) & 0x1f00000000ffffull;
-    b = (b | (b << 16)) & 0x1f0000ff0000ffull;
-    b = (b | (b << 8)) & 0x100f00f00f00f00full;
-    b = (b | (b << 4)) & 0x10c30c30c30c30c3ull;
-    b = (b | (b << 2)) & 0x1249249249249249ull;
-    return b;
+    const R w = x * x - x;
+    if constexpr (ALPHA == 1) return c1 * w + c0;
+    else if constexpr (ALPHA == 2) return (c2 * w) * w + c0;
+    else return ((c3 * w + c2) * w + c1) * w + c0;
 }
 
 // ---- DSI factor, Sec. 5.3 / Theorem 1 (base 2), alpha = 1 .. 4 ----
 // beta = index of the first nonzero digit (clz + 1), t_nu = 2^{-nu beta},
 // both 0 at x = 0; "-1+-" in the theorem read as "-1-".
 // alpha = 1: K_1 = 1 - 3 t_1 (reading; the paper defers this form).
-template <typename R>
-__device__ __forceinline__ R dsi_factor(int alpha, uint64_t delta);
-
-template <>
-__device__ __forceinline__ double dsi_factor<double>(int alpha, uint64_t delta)
+// The alpha = 4 series sum_{a>=0} (-1)^{xi_{a+1}} 8^{-a} is kept to 21 digits
+// (the rest is below 2^-62) and read from three 128-entry tables of 7 digits:
+// series = 8/7 - 2 (T0[d1..d7] + T1[d8..d14] + T2[d15..d21]).
+struct DsiTables {
+    double t[3][128];
+};
+__device__ __forceinline__ void fill_dsi_tables(DsiTables &tab, int t, int nthreads)
 {
-    int beta = 0;
-    double x = 0.0;
-    if (delta) {
-        beta = clz64(delta) + 1;
-        x = unit_f64(delta);
+    for (int w = t; w < 3 * 128; w += nthreads) {
+        const int chunk = w >> 7, v = w & 127;
+        double acc = 0.0;
+        for (int b = 0; b < 7; ++b)  // bit 6 - b of v is digit 7 chunk + b + 1
+            if ((v >> (6 - b)) & 1) acc += ldexp(1.0, -3 * (7 * chunk + b));
+        tab.t[chunk][v] = acc;
     }
-    const double b = (double)beta;
-    const double t1 = beta ? ldexp(1.0, -beta) : 0.0;
-    if (alpha == 1) return 1.0 - 3.0 * t1;
-    if (alpha == 2) return -1.0 - b * x + 2.5 * (1.0 - t1);
-    if (alpha < 1) return __builtin_nan("");
-    const double t2 = t1 * t1;
-    if (alpha == 3) return -1.0 + b * x * x - 5.0 * (1.0 - t1) * x + (43.0 / 18.0) * (1.0 - t2);
-    if (alpha != 4) return __builtin_nan("");  // unsupported order: poison the column
-    const double t3 = t2 * t1;
-    // series: sum_{a<21} 8^-a - 2 sum_{xi_{a+1}=1} 8^-a
-    const uint64_t sp = spread3_21(delta >> 43);
-    const double ones = unit_f64(sp) * 16.0;  // sp * 2^-60
-    const double series = 1.1428571428571428571 - 2.0 * ones;
-    return -1.0 - (2.0 / 3.0) * b * x * x * x + 5.0 * (1.0 - t1) * x * x -
-           (43.0 / 9.0) * (1.0 - t2) * x + (701.0 / 294.0) * (1.0 - t3) +
-           b * (series * (1.0 / 48.0) - 1.0 / 42.0);
-}
-
-template <>
-__device__ __forceinline__ float dsi_factor<float>(int alpha, uint64_t delta)
-{
-    int beta = 0;
-    float x = 0.0f;
-    if (delta) {
-        beta = clz64(delta) + 1;
-        x = unit_f32(delta);
-    }
-    const float b = (float)beta;
-    const float t1 = beta ? ldexpf(1.0f, -beta) : 0.0f;
-    if (alpha == 1) return 1.0f - 3.0f * t1;
-    if (alpha == 2) return -1.0f - b * x + 2.5f * (1.0f - t1);
-    if (alpha < 1) return __builtin_nanf("");
-    const float t2 = t1 * t1;
-    if (alpha == 3)
-        return -1.0f + b * x * x - 5.0f * (1.0f - t1) * x + (43.0f / 18.0f) * (1.0f - t2);
-    if (alpha != 4) return __builtin_nanf("");  // unsupported order: poison the column
-    const float t3 = t2 * t1;
-    const uint64_t sp = spread3_21(delta >> 43);
-    const float ones = unit_f32(sp) * 16.0f;
-    const float series = 1.14285714285714285f - 2.0f * ones;
-    return -1.0f - (2.0f / 3.0f) * b * x * x * x + 5.0f * (1.0f - t1) * x * x -
-           (43.0f / 9.0f) * (1.0f - t2) * x + (701.0f / 294.0f) * (1.0f - t3) +
-           b * (series * (1.0f / 48.0f) - 1.0f / 42.0f);
 }
 
 template <typename R>
@@ -114,111 +77,287 @@ __device__ __forceinline__ double unit<double>(uint64_t u) { return unit_f64(u);
 template <>
 __device__ __forceinline__ float unit<float>(uint64_t u) { return unit_f32(u); }
 
+template <typename R, int ALPHA>
+__device__ __forceinline__ R dsi_factor(uint64_t delta, const DsiTables &tab)
+{
+    int beta = 0;
+    R x = (R)0;
+    if (delta) {
+        beta = clz64(delta) + 1;
+        x = unit<R>(delta);
+    }
+    const R b = (R)beta;
+    const R t1 = beta ? (R)ldexp(1.0, -beta) : (R)0;
+    if constexpr (ALPHA == 1) {
+        return (R)1 - (R)3 * t1;
+    } else if constexpr (ALPHA == 2) {
+        return (R)1.5 - (R)2.5 * t1 - b * x;
+    } else if constexpr (ALPHA == 3) {
+        const R t2 = t1 * t1;
+        return ((b * x - (R)5 * ((R)1 - t1)) * x + (R)(43.0 / 18.0) * ((R)1 - t2)) - (R)1;
+    } else {
+        const R t2 = t1 * t1, t3 = t2 * t1;
+        const R ones = (R)(tab.t[0][(delta >> 57) & 127] + tab.t[1][(delta >> 50) & 127] +
+                           tab.t[2][(delta >> 43) & 127]);
+        const R series = (R)(8.0 / 7.0) - (R)2 * ones;
+        const R poly = ((-(R)(2.0 / 3.0) * b * x + (R)5 * ((R)1 - t1)) * x -
+                        (R)(43.0 / 9.0) * ((R)1 - t2)) * x;
+        return poly + ((R)(701.0 / 294.0) * ((R)1 - t3) - (R)1) +
+               b * (series * (R)(1.0 / 48.0) - (R)(1.0 / 42.0));
+    }
+}
+template <typename R>
+__device__ __forceinline__ R dsi_factor_any(int alpha, uint64_t delta, const DsiTables &tab)
+{
+    switch (alpha) {
+    case 1: return dsi_factor<R, 1>(delta, tab);
+    case 2: return dsi_factor<R, 2>(delta, tab);
+    case 3: return dsi_factor<R, 3>(delta, tab);
+    default: return dsi_factor<R, 4>(delta, tab);
+    }
+}
+
 struct KcolArgs {
     PointsetArgs ps;
-    const int32_t *alpha;
     const double *gamma;
     double zeta;
     int64_t n_min, n_max;
     const uint64_t *pts;  // [R][cnt][d] or nullptr (regenerate)
     const uint64_t *x0;   // [R][d] anchors (pts mode), or nullptr = row 0 of pts
+    uint64_t acode[KC_CODE_WORDS];  // alpha_j - 1 in 2 bits, 32 dimensions per word
 };
 
-// Block: replication r = blockIdx.y, points tile0 + t + KC_THREADS * l.
-template <typename R>
-__global__ __launch_bounds__(KC_THREADS) void k_kernel_column(KcolArgs a, R *__restrict__ out)
+__device__ __forceinline__ int alpha_of(const KcolArgs &a, int j)
 {
-    __shared__ uint64_t ct[KC_DIM_CHUNK][64];
-    __shared__ uint64_t step[KC_DIM_CHUNK][64];
-    const int r = blockIdx.y;
-    const int t = threadIdx.x;
+    return 1 + (int)((a.acode[j >> 5] >> (2 * (j & 31))) & 3u);
+}
+
+struct NetLds {
+    uint64_t ct[KC_DIM_CHUNK][64];  // scrambled columns S_j C_j
+    union {
+        uint64_t step[KC_DIM_CHUNK][64];  // XOR steps between a thread's points
+        uint64_t srow[KC_DIM_CHUNK][64];  // rows of S_j (dead once ct is built)
+    };
+    DsiTables tab;
+};
+
+// ---------------------------------------------------------------------------
+// Regenerating lattice variant.  Block: replication r = blockIdx.y; points
+// i = tile0 + t + KC_THREADS l (l < KC_ITERS), tile0 a multiple of KC_TILE,
+// so the bits of t, l and tile0 are disjoint and
+//   natural: bitreverse(i) g = bitreverse(tile0 + t) g + bitreverse3(l) (g << 53),
+//   linear:  (i g) << (64-m) = ((tile0 + t) g) << (64-m) + l ((g << 8) << (64-m)).
+// The anchor is point 0, so delta = z(i) - z(0) = z(i): the shift cancels.
+// ---------------------------------------------------------------------------
+template <typename R, int ALPHA, int ORDER, bool FULL>
+__device__ __forceinline__ void lattice_tile(const KcolArgs &a, int64_t first, R (&prod)[KC_ITERS])
+{
+    static_assert(KC_ITERS == 8 && KC_LOG_THREADS == 8, "offset table assumes 8 x 256");
+    constexpr uint64_t br3[8] = {0, 4, 2, 6, 1, 5, 3, 7};
     const int d = a.ps.d, m = a.ps.m_max;
-    const bool net = a.ps.kind == LDK_DNET_B2;
-    const bool regen = a.pts == nullptr;
-    const int64_t cnt = a.n_max - a.n_min;
-    const int64_t tile0 = a.n_min + (int64_t)blockIdx.x * KC_THREADS * KC_ITERS;
-    const int64_t first = tile0 + t;
-    constexpr int s = 8;  // log2(KC_THREADS): index stride between a thread's points
-    static_assert((1 << s) == KC_THREADS, "stride");
-
-    R prod[KC_ITERS];
-#pragma unroll
-    for (int l = 0; l < KC_ITERS; ++l) prod[l] = (R)a.zeta;
-
-    for (int jc = 0; jc < d; jc += KC_DIM_CHUNK) {
-        const int DB = min(KC_DIM_CHUNK, d - jc);
-        if (regen && net) {
-            __syncthreads();
-            for (int w = t; w < DB * m; w += KC_THREADS) {
-                const int jj = w / m, k = w % m;
-                const uint64_t col = a.ps.gen[(size_t)(jc + jj) * m + k];
-                ct[jj][k] = a.ps.lms ? lms_column(a.ps.lms + ((size_t)r * d + jc + jj) * 64, col)
-                                     : col;
-            }
-            __syncthreads();
-            for (int w = t; w < DB * 64; w += KC_THREADS) {
-                const int jj = w / 64, c = w % 64;
-                uint64_t v = 0;
-                if (s + c < m) {
-                    if (a.ps.order == LDK_GRAY) {
-                        v = ct[jj][s + c] ^ ct[jj][s - 1];
-                    } else {
-                        for (int k = s; k <= s + c; ++k) v ^= ct[jj][k];
-                    }
-                }
-                step[jj][c] = v;
-            }
-            __syncthreads();
+    const uint64_t bfirst = ORDER == LDK_NATURAL ? brev64((uint64_t)first) : (uint64_t)first;
+    for (int j = 0; j < d; ++j) {
+        const uint64_t g = a.ps.gen[j];
+        const int alpha = ALPHA ? ALPHA : alpha_of(a, j);
+        const SiPoly cf = si_poly(alpha, a.gamma[j]);
+        const R c0 = (R)cf.c0, c1 = (R)cf.c1, c2 = (R)cf.c2, c3 = (R)cf.c3;
+        uint64_t base, G;
+        if constexpr (ORDER == LDK_NATURAL) {
+            base = bfirst * g;
+            G = g << 53;
+        } else {
+            base = m == 0 ? 0 : ((bfirst * g) << (64 - m));
+            G = m <= 8 ? 0 : ((g << 8) << (64 - m));
         }
-        for (int jj = 0; jj < DB; ++jj) {
-            const int j = jc + jj;
-            const int alpha = a.alpha[j];
-            const R gam = (R)a.gamma[j];
-            if (regen) {
-                if (net) {
-                    if (first >= a.n_max) continue;
-                    const uint64_t code =
-                        a.ps.order == LDK_GRAY ? gray_code((uint64_t)first) : (uint64_t)first;
-                    uint64_t z = net_point(ct[jj], m, code);
-                    int64_t i = first;
 #pragma unroll
-                    for (int l = 0; l < KC_ITERS; ++l) {
-                        if (i < a.n_max) {
-                            prod[l] *= (R)1 + gam * dsi_factor<R>(alpha, z);
-                            if (i + KC_THREADS < a.n_max) z ^= step[jj][ctz64(((uint64_t)i >> s) + 1)];
-                        }
-                        i += KC_THREADS;
-                    }
-                } else {
-                    const uint64_t g = a.ps.gen[j];
-#pragma unroll
-                    for (int l = 0; l < KC_ITERS; ++l) {
-                        const int64_t i = first + (int64_t)l * KC_THREADS;
-                        if (i < a.n_max) {
-                            const uint64_t delta = lattice_point(g, (uint64_t)i, a.ps.order, m);
-                            prod[l] *= (R)1 + gam * si_factor<R>(alpha, unit<R>(delta));
-                        }
-                    }
-                }
+        for (int l = 0; l < KC_ITERS; ++l) {
+            const uint64_t delta = base + (ORDER == LDK_NATURAL ? br3[l] : (uint64_t)l) * G;
+            const R f = si_weighted<R, ALPHA>(unit<R>(delta), c0, c1, c2, c3);
+            if (FULL) {
+                prod[l] *= f;
             } else {
-                const uint64_t u0 = a.x0 ? a.x0[(size_t)r * d + j] : a.pts[(size_t)r * cnt * d + j];
-#pragma unroll
-                for (int l = 0; l < KC_ITERS; ++l) {
-                    const int64_t i = first + (int64_t)l * KC_THREADS;
-                    if (i < a.n_max) {
-                        const uint64_t u = a.pts[((size_t)r * cnt + (i - a.n_min)) * d + j];
-                        const R f = net ? dsi_factor<R>(alpha, u ^ u0)
-                                        : si_factor<R>(alpha, unit<R>(u - u0));
-                        prod[l] *= (R)1 + gam * f;
-                    }
-                }
+                const int64_t i = first + (int64_t)l * KC_THREADS;
+                if (i >= a.n_min && i < a.n_max) prod[l] *= f;
             }
         }
     }
+}
+
+template <typename R, int ALPHA, int ORDER>
+__global__ __launch_bounds__(KC_THREADS) void k_kcol_lattice(KcolArgs a, int64_t tile_base,
+                                                            R *__restrict__ out)
+{
+    const int r = blockIdx.y;
+    const int64_t cnt = a.n_max - a.n_min;
+    const int64_t tile0 = tile_base + (int64_t)blockIdx.x * KC_TILE;
+    const int64_t first = tile0 + threadIdx.x;
+    R prod[KC_ITERS];
+#pragma unroll
+    for (int l = 0; l < KC_ITERS; ++l) prod[l] = (R)a.zeta;
+    if (tile0 >= a.n_min && tile0 + KC_TILE <= a.n_max)
+        lattice_tile<R, ALPHA, ORDER, true>(a, first, prod);
+    else
+        lattice_tile<R, ALPHA, ORDER, false>(a, first, prod);
 #pragma unroll
     for (int l = 0; l < KC_ITERS; ++l) {
         const int64_t i = first + (int64_t)l * KC_THREADS;
-        if (i < a.n_max) out[(size_t)r * cnt + (i - a.n_min)] = prod[l];
+        if (i >= a.n_min && i < a.n_max) out[(size_t)r * cnt + (i - a.n_min)] = prod[l];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Regenerating net variant.  The scrambled columns of a chunk of dimensions
+// sit in LDS (built from S rows staged in LDS); the step from point
+// i = tile0 + t + KC_THREADS l to the next one flips index bits
+// s .. s + ctz((tile0 >> s) + l + 1) (s = log2 KC_THREADS), a block-uniform
+// table read.  The anchor is point 0 (z = 0), so delta = z(i).
+// ---------------------------------------------------------------------------
+template <typename R, int ALPHA, bool FULL>
+__device__ __forceinline__ void net_tile(const KcolArgs &a, NetLds &L, int r, int64_t tile0,
+                                         int64_t first, R (&prod)[KC_ITERS])
+{
+    constexpr int s = KC_LOG_THREADS;
+    const int d = a.ps.d, m = a.ps.m_max, t = threadIdx.x;
+    for (int jc = 0; jc < d; jc += KC_DIM_CHUNK) {
+        const int DB = min(KC_DIM_CHUNK, d - jc);
+        __syncthreads();  // tables of the previous chunk are no longer read
+        if (a.ps.lms) {
+            for (int w = t; w < DB * 64; w += KC_THREADS)
+                L.srow[w >> 6][w & 63] = a.ps.lms[((size_t)r * d + jc + (w >> 6)) * 64 + (w & 63)];
+            __syncthreads();
+        }
+        for (int w = t; w < DB * m; w += KC_THREADS) {
+            const int jj = w / m, k = w % m;
+            const uint64_t col = a.ps.gen[(size_t)(jc + jj) * m + k];
+            L.ct[jj][k] = a.ps.lms ? lms_column(L.srow[jj], col) : col;
+        }
+        __syncthreads();  // srow is dead from here on; step reuses its storage
+        for (int w = t; w < DB * 64; w += KC_THREADS) {
+            const int jj = w >> 6, c = w & 63;
+            uint64_t v = 0;
+            if (s + c < m) {
+                if (a.ps.order == LDK_GRAY) {
+                    v = L.ct[jj][s + c] ^ L.ct[jj][s - 1];
+                } else {
+                    for (int k = s; k <= s + c; ++k) v ^= L.ct[jj][k];
+                }
+            }
+            L.step[jj][c] = v;
+        }
+        __syncthreads();
+        for (int jj = 0; jj < DB; ++jj) {
+            const int j = jc + jj;
+            const R gam = (R)a.gamma[j];
+            const int alpha = ALPHA ? ALPHA : alpha_of(a, j);
+            const uint64_t code =
+                a.ps.order == LDK_GRAY ? gray_code((uint64_t)first) : (uint64_t)first;
+            uint64_t z = net_point(L.ct[jj], m, code);
+#pragma unroll
+            for (int l = 0; l < KC_ITERS; ++l) {
+                R k;
+                if constexpr (ALPHA != 0)
+                    k = dsi_factor<R, ALPHA>(z, L.tab);
+                else
+                    k = dsi_factor_any<R>(alpha, z, L.tab);
+                const R f = (R)1 + gam * k;
+                if (FULL) {
+                    prod[l] *= f;
+                } else {
+                    const int64_t i = first + (int64_t)l * KC_THREADS;
+                    if (i >= a.n_min && i < a.n_max) prod[l] *= f;
+                }
+                const uint64_t nb = ((uint64_t)tile0 >> s) + (uint64_t)l + 1;
+                if (l + 1 < KC_ITERS && (int64_t)(nb << s) < a.n_max) z ^= L.step[jj][ctz64(nb)];
+            }
+        }
+    }
+}
+
+template <typename R, int ALPHA>
+__global__ __launch_bounds__(KC_THREADS) void k_kcol_net(KcolArgs a, int64_t tile_base,
+                                                        R *__restrict__ out)
+{
+    __shared__ NetLds L;
+    const int r = blockIdx.y;
+    const int64_t cnt = a.n_max - a.n_min;
+    const int64_t tile0 = tile_base + (int64_t)blockIdx.x * KC_TILE;
+    const int64_t first = tile0 + threadIdx.x;
+    fill_dsi_tables(L.tab, threadIdx.x, KC_THREADS);
+    R prod[KC_ITERS];
+#pragma unroll
+    for (int l = 0; l < KC_ITERS; ++l) prod[l] = (R)a.zeta;
+    if (tile0 >= a.n_min && tile0 + KC_TILE <= a.n_max)
+        net_tile<R, ALPHA, true>(a, L, r, tile0, first, prod);
+    else
+        net_tile<R, ALPHA, false>(a, L, r, tile0, first, prod);
+#pragma unroll
+    for (int l = 0; l < KC_ITERS; ++l) {
+        const int64_t i = first + (int64_t)l * KC_THREADS;
+        if (i >= a.n_min && i < a.n_max) out[(size_t)r * cnt + (i - a.n_min)] = prod[l];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Points given (any order; anchor rows x0).  Thread per point.
+// ---------------------------------------------------------------------------
+template <typename R, bool NET>
+__global__ __launch_bounds__(KC_THREADS) void k_kcol_points(KcolArgs a, R *__restrict__ out)
+{
+    __shared__ DsiTables tab;
+    if constexpr (NET) {
+        fill_dsi_tables(tab, threadIdx.x, KC_THREADS);
+        __syncthreads();
+    }
+    const int r = blockIdx.y;
+    const int d = a.ps.d;
+    const int64_t cnt = a.n_max - a.n_min;
+    const int64_t i = a.n_min + (int64_t)blockIdx.x * KC_THREADS + threadIdx.x;
+    if (i >= a.n_max) return;
+    const uint64_t *row = a.pts + ((size_t)r * cnt + (i - a.n_min)) * d;
+    R prod = (R)a.zeta;
+    for (int j = 0; j < d; ++j) {
+        const uint64_t u0 = a.x0 ? a.x0[(size_t)r * d + j] : a.pts[(size_t)r * cnt * d + j];
+        const int alpha = alpha_of(a, j);
+        if constexpr (NET) {
+            prod *= (R)1 + (R)a.gamma[j] * dsi_factor_any<R>(alpha, row[j] ^ u0, tab);
+        } else {
+            const SiPoly cf = si_poly(alpha, a.gamma[j]);
+            prod *= si_weighted<R, 0>(unit<R>(row[j] - u0), (R)cf.c0, (R)cf.c1, (R)cf.c2, (R)cf.c3);
+        }
+    }
+    out[(size_t)r * cnt + (i - a.n_min)] = prod;
+}
+
+template <typename R, int ALPHA>
+void launch_regen(const KcolArgs &a, int64_t tile_base, dim3 grid, hipStream_t s, void *out)
+{
+    if (a.ps.kind == LDK_DNET_B2)
+        hipLaunchKernelGGL((k_kcol_net<R, ALPHA>), grid, dim3(KC_THREADS), 0, s, a, tile_base, (R *)out);
+    else if (a.ps.order == LDK_LINEAR)
+        hipLaunchKernelGGL((k_kcol_lattice<R, ALPHA, LDK_LINEAR>), grid, dim3(KC_THREADS), 0, s, a,
+                           tile_base, (R *)out);
+    else
+        hipLaunchKernelGGL((k_kcol_lattice<R, ALPHA, LDK_NATURAL>), grid, dim3(KC_THREADS), 0, s, a,
+                           tile_base, (R *)out);
+}
+
+template <typename R>
+void launch_regen_alpha(int kind, int alpha, const KcolArgs &a, int64_t tile_base, dim3 grid,
+                        hipStream_t s, void *out)
+{
+    // lattice orders 1..3 and net orders 1..4 get specialised kernels; mixed
+    // orders (alpha = 0) read the per-dimension code
+    switch (alpha) {
+    case 1: launch_regen<R, 1>(a, tile_base, grid, s, out); break;
+    case 2: launch_regen<R, 2>(a, tile_base, grid, s, out); break;
+    case 3: launch_regen<R, 3>(a, tile_base, grid, s, out); break;
+    case 4:
+        if (kind == LDK_DNET_B2) {
+            hipLaunchKernelGGL((k_kcol_net<R, 4>), grid, dim3(KC_THREADS), 0, s, a, tile_base, (R *)out);
+            break;
+        }
+        [[fallthrough]];
+    default: launch_regen<R, 0>(a, tile_base, grid, s, out);
     }
 }
 
@@ -237,6 +376,23 @@ extern "C" int ldk_kernel_column(const ldk_kernel *k, const ldk_pointset *ps, co
     if (!(k->zeta > 0.0)) return LDK_EINVAL;
     if (dtype != LDK_F64 && dtype != LDK_F32) return LDK_EINVAL;
     if (n_min < 0 || n_max < n_min) return LDK_EINVAL;
+    KcolArgs a{};
+    a.ps = p;
+    a.gamma = k->gamma;
+    a.zeta = k->zeta;
+    a.n_min = n_min;
+    a.n_max = n_max;
+    a.pts = pts;
+    a.x0 = x0;
+    // orders live on the host: validate, pack 2-bit codes, detect a uniform order
+    const int amax = p.kind == LDK_LATTICE ? 3 : 4;
+    int uniform = k->alpha[0];
+    for (int j = 0; j < p.d; ++j) {
+        const int al = k->alpha[j];
+        if (al < 1 || al > amax) return LDK_EINVAL;
+        if (al != uniform) uniform = 0;
+        a.acode[j >> 5] |= (uint64_t)(al - 1) << (2 * (j & 31));
+    }
     if (pts == nullptr) {
         const int64_t lim = (p.kind == LDK_LATTICE && p.order == LDK_NATURAL)
                                 ? ((int64_t)1 << 62)
@@ -247,16 +403,31 @@ extern "C" int ldk_kernel_column(const ldk_kernel *k, const ldk_pointset *ps, co
     }
     if (n_max == n_min) return LDK_OK;  // empty window: out may be NULL
     if (!out) return LDK_EINVAL;
-    const int64_t tiles = (n_max - n_min + KC_THREADS * KC_ITERS - 1) / (KC_THREADS * KC_ITERS);
+    hipStream_t s = as_stream(stream);
+    if (pts != nullptr) {
+        const int64_t blocks = (n_max - n_min + KC_THREADS - 1) / KC_THREADS;
+        if (blocks > 0x7fffffff) return LDK_ENOTSUP;
+        dim3 grid((unsigned)blocks, (unsigned)p.R);
+        const bool net = p.kind == LDK_DNET_B2;
+        if (dtype == LDK_F64) {
+            if (net) hipLaunchKernelGGL((k_kcol_points<double, true>), grid, dim3(KC_THREADS), 0, s, a, (double *)out);
+            else hipLaunchKernelGGL((k_kcol_points<double, false>), grid, dim3(KC_THREADS), 0, s, a, (double *)out);
+        } else {
+            if (net) hipLaunchKernelGGL((k_kcol_points<float, true>), grid, dim3(KC_THREADS), 0, s, a, (float *)out);
+            else hipLaunchKernelGGL((k_kcol_points<float, false>), grid, dim3(KC_THREADS), 0, s, a, (float *)out);
+        }
+        LDK_LAUNCH_CHECK();
+        return LDK_OK;
+    }
+    // tiles aligned to absolute multiples of KC_TILE
+    const int64_t tile_base = (n_min / KC_TILE) * KC_TILE;
+    const int64_t tiles = (n_max - tile_base + KC_TILE - 1) / KC_TILE;
     if (tiles > 0x7fffffff) return LDK_ENOTSUP;
-    KcolArgs a{p, k->alpha, k->gamma, k->zeta, n_min, n_max, pts, x0};
     dim3 grid((unsigned)tiles, (unsigned)p.R);
     if (dtype == LDK_F64)
-        hipLaunchKernelGGL(k_kernel_column<double>, grid, dim3(KC_THREADS), 0, as_stream(stream), a,
-                           (double *)out);
+        launch_regen_alpha<double>(p.kind, uniform, a, tile_base, grid, s, out);
     else
-        hipLaunchKernelGGL(k_kernel_column<float>, grid, dim3(KC_THREADS), 0, as_stream(stream), a,
-                           (float *)out);
+        launch_regen_alpha<float>(p.kind, uniform, a, tile_base, grid, s, out);
     LDK_LAUNCH_CHECK();
     return LDK_OK;
 }

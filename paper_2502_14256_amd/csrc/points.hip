@@ -8,7 +8,8 @@ namespace ldk {
 namespace {
 constexpr int GEN_THREADS = 256;
 constexpr int GEN_DIM_CHUNK = 32;  // dimensions per block
-constexpr int GEN_ITERS = 32;      // points per thread
+constexpr int GEN_ITERS = 32;      // points per thread (lattices)
+constexpr int GEN_ITERS_NET = 128; // points per thread (nets: amortises the scrambling)
 }  // namespace
 
 int validate_pointset(const ldk_pointset *ps, PointsetArgs *out)
@@ -46,19 +47,28 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_net(PointsetArgs a, int64_t
                                                          uint64_t *__restrict__ out)
 {
     __shared__ uint64_t ct[GEN_DIM_CHUNK][64];
-    __shared__ uint64_t step[GEN_DIM_CHUNK][64];
+    __shared__ union {
+        uint64_t step[GEN_DIM_CHUNK][64];
+        uint64_t srow[GEN_DIM_CHUNK][64];  // rows of S_j, dead once ct is built
+    } u;
+    auto &step = u.step;
     const int r = blockIdx.z;
     const int j0 = blockIdx.y * GEN_DIM_CHUNK;
     const int DB = min(GEN_DIM_CHUNK, a.d - j0);
     const int m = a.m_max;
     const int t = threadIdx.x;
 
+    if (a.lms) {
+        for (int w = t; w < DB * 64; w += GEN_THREADS)
+            u.srow[w >> 6][w & 63] = a.lms[((size_t)r * a.d + j0 + (w >> 6)) * 64 + (w & 63)];
+        __syncthreads();
+    }
     for (int w = t; w < DB * m; w += GEN_THREADS) {
         const int jj = w / m, k = w % m;
         const uint64_t col = a.gen[(size_t)(j0 + jj) * m + k];
-        ct[jj][k] = a.lms ? lms_column(a.lms + ((size_t)r * a.d + j0 + jj) * 64, col) : col;
+        ct[jj][k] = a.lms ? lms_column(u.srow[jj], col) : col;
     }
-    __syncthreads();
+    __syncthreads();  // srow is dead from here on; step reuses its storage
     const int s = logP;
     for (int w = t; w < DB * 64; w += GEN_THREADS) {
         const int jj = w / 64, c = w % 64;
@@ -78,7 +88,7 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_net(PointsetArgs a, int64_t
     if (p >= P) return;
     const int j = j0 + jj;
     const int64_t cnt = n_max - n_min;
-    const int64_t first = n_min + (int64_t)blockIdx.x * P * GEN_ITERS + p;
+    const int64_t first = n_min + (int64_t)blockIdx.x * P * GEN_ITERS_NET + p;
     if (first >= n_max) return;
     const uint64_t delta = a.shift ? a.shift[(size_t)r * a.d + j] : 0;
     const uint64_t code0 = a.order == LDK_GRAY ? gray_code((uint64_t)first) : (uint64_t)first;
@@ -86,10 +96,10 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_net(PointsetArgs a, int64_t
     uint64_t *dst = out + ((size_t)r * cnt + (first - n_min)) * a.d + j;
     const size_t dstep = (size_t)P * a.d;
     int64_t i = first;
-    for (int k = 0; k < GEN_ITERS; ++k) {
+    for (int k = 0; k < GEN_ITERS_NET; ++k) {
         *dst = z ^ delta;
         const int64_t next = i + P;
-        if (next >= n_max || k + 1 == GEN_ITERS) break;
+        if (next >= n_max || k + 1 == GEN_ITERS_NET) break;
         z ^= step[jj][ctz64(((uint64_t)i >> s) + 1)];
         i = next;
         dst += dstep;
@@ -142,7 +152,8 @@ extern "C" int ldk_gen_points(const ldk_pointset *ps, int64_t n_min, int64_t n_m
     const int P = point_lanes(dims);
     int logP = 0;
     while ((1 << logP) < P) ++logP;
-    const int64_t tiles = (n_max - n_min + (int64_t)P * GEN_ITERS - 1) / ((int64_t)P * GEN_ITERS);
+    const int iters = a.kind == LDK_LATTICE ? GEN_ITERS : GEN_ITERS_NET;
+    const int64_t tiles = (n_max - n_min + (int64_t)P * iters - 1) / ((int64_t)P * iters);
     if (tiles > 0x7fffffff) return LDK_ENOTSUP;
     dim3 grid((unsigned)tiles, (unsigned)((a.d + GEN_DIM_CHUNK - 1) / GEN_DIM_CHUNK), (unsigned)a.R);
     if (a.kind == LDK_LATTICE)

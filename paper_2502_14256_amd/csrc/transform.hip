@@ -142,20 +142,70 @@ struct real_of<cplx<R>> {
     using type = R;
 };
 
+// Powers w^c, c = 0..E-1, by a binary product tree: w^{2^j} by squaring,
+// w^c = w^{c - 2^j} w^{2^j} (at most 2 log2(E) roundings per entry).
+template <typename R, int E>
+__device__ __forceinline__ void powers(cplx<R> w, cplx<R> (&p)[E])
+{
+    p[0] = cplx<R>{(R)1, (R)0};
+    if constexpr (E > 1) p[1] = w;
+#pragma unroll
+    for (int c = 2; c < E; ++c) {
+        const int hi = 1 << (31 - __builtin_clz(c));  // largest power of two <= c
+        p[c] = (c == hi) ? cmul(p[c >> 1], p[c >> 1]) : cmul(p[c - hi], p[hi]);
+    }
+}
+
 // Group twiddle of the FFT schedule: element with tile index q, axis index
 // r = q >> logW, group digit c at axis bit s: W_{2^{s+gs}}^{(r mod 2^s) R_gs(c)}.
-template <typename T, int E, bool CONJ>
+// For a full group every register of a thread shares r mod 2^s, so one table
+// read gives w = W^{r mod 2^s} and the twiddles are its powers.
+template <typename T, int E, int LOGE, bool CONJ>
 __device__ __forceinline__ void group_twiddle(T (&v)[E], int t, int gs, int s, int logW, int T_)
 {
     if constexpr (!std::is_floating_point<T>::value) {
         using R = typename real_of<T>::type;
         if (s == 0) return;
+        if (gs == LOGE) {
+            const int q0 = group_q(t, 0, gs, logW + s, T_);
+            const uint32_t rlow = (uint32_t)(q0 >> logW) & ((1u << s) - 1);
+            cplx<R> pw[E];
+            powers<R, E>(tw_small<R>(rlow, s + gs), pw);
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                const cplx<R> w = pw[brev_bits((uint32_t)i, LOGE)];
+                v[i] = CONJ ? cmulc(v[i], w) : cmul(v[i], w);
+            }
+            return;
+        }
 #pragma unroll
         for (int i = 0; i < E; ++i) {
             const int q = group_q(t, i, gs, logW + s, T_);
             const uint32_t rlow = (uint32_t)(q >> logW) & ((1u << s) - 1);
             const uint32_t c = (uint32_t)i & ((1u << gs) - 1);
             const cplx<R> w = tw_small<R>(rlow * brev_bits(c, gs), s + gs);
+            v[i] = CONJ ? cmulc(v[i], w) : cmul(v[i], w);
+        }
+    }
+}
+
+// Inter-pass twiddle W_{2^{b0+A}}^{k1 R_A(r)} for the coalesced pattern
+// q = t + Tn i: the column k1 is fixed per thread and
+// R_A(r) = R_{A-LOGE}(r0) 2^LOGE + R_LOGE(i), r0 = t >> logW, so the twiddles
+// are W^{k1 R_{A-LOGE}(r0) 2^LOGE} times the powers of W^{k1}.
+template <typename T, int E, int LOGE, bool CONJ>
+__device__ __forceinline__ void pass_twiddle(T (&v)[E], int t, int64_t cb, int logW, int A, int b0)
+{
+    if constexpr (!std::is_floating_point<T>::value) {
+        using R = typename real_of<T>::type;
+        const uint64_t k1 = (uint64_t)((cb << logW) + (t & ((1 << logW) - 1)));
+        const uint64_t r0 = (uint64_t)(t >> logW);
+        const cplx<R> base = tw_any<R>((k1 * brev_bits((uint32_t)r0, A - LOGE)) << LOGE, b0 + A);
+        cplx<R> pw[E];
+        powers<R, E>(tw_any<R>(k1, b0 + A), pw);
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const cplx<R> w = cmul(base, pw[brev_bits((uint32_t)i, LOGE)]);
             v[i] = CONJ ? cmulc(v[i], w) : cmul(v[i], w);
         }
     }
@@ -205,7 +255,7 @@ __device__ __forceinline__ void store_elem(void *p, int64_t idx, T v, bool dst_r
 
 // One pass over a tile: rows = 2^a along the axis, W = 2^logW columns.
 template <typename T, int LOGE, int MODE, bool SRC_REAL, bool DST_REAL, bool SRC_F32>
-__global__ __launch_bounds__(256) void k_pass(PassArgs a)
+__global__ __launch_bounds__(512) void k_pass(PassArgs a)
 {
     using R = typename real_of<T>::type;
     constexpr int E = 1 << LOGE;
@@ -246,16 +296,7 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a)
 
     if constexpr (MODE != PM_INV) {
         if constexpr (FFT) {
-            if (a.global_tw) {
-                // inter-pass twiddle W_{2^{b0+A}}^{k1 R_A(r)}, k1 = column index < 2^b0
-#pragma unroll
-                for (int i = 0; i < E; ++i) {
-                    const int q = t + Tn * i;
-                    const uint64_t k1 = (uint64_t)((cb << logW) + (q & ((1 << logW) - 1)));
-                    const uint64_t rr = brev_bits((uint32_t)(q >> logW), A);
-                    v[i] = cmul(v[i], tw_any<R>(k1 * rr, b0 + A));
-                }
-            }
+            if (a.global_tw) pass_twiddle<T, E, LOGE, false>(v, t, cb, logW, A, b0);
         }
         if (G > 1) {
             lds_write(v, lds, t, LOGE, logW + top_s, Tn);
@@ -264,7 +305,7 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a)
             for (int gidx_ = 0; gidx_ < G - 1; ++gidx_) {
                 const int gs = gidx_ == 0 ? rem : LOGE;
                 lds_read(v, lds, t, gs, logW + s, Tn);
-                group_twiddle<T, E, false>(v, t, gs, s, logW, Tn);
+                group_twiddle<T, E, LOGE, false>(v, t, gs, s, logW, Tn);
                 reg_fwd<T, E, LOGE, false>(v, gs);
                 lds_write(v, lds, t, gs, logW + s, Tn);
                 __syncthreads();
@@ -272,7 +313,7 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a)
             }
             lds_read(v, lds, t, LOGE, logW + top_s, Tn);
         }
-        group_twiddle<T, E, false>(v, t, LOGE, G > 1 ? top_s : 0, logW, Tn);
+        group_twiddle<T, E, LOGE, false>(v, t, LOGE, G > 1 ? top_s : 0, logW, Tn);
         reg_fwd<T, E, LOGE, false>(v, LOGE);
     }
 
@@ -288,7 +329,7 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a)
 
     if constexpr (MODE != PM_FWD) {
         reg_inv<T, E, LOGE>(v, LOGE);
-        group_twiddle<T, E, true>(v, t, LOGE, G > 1 ? top_s : 0, logW, Tn);
+        group_twiddle<T, E, LOGE, true>(v, t, LOGE, G > 1 ? top_s : 0, logW, Tn);
         if (G > 1) {
             if constexpr (MODE != PM_INV) __syncthreads();  // LDS reuse after the forward half
             lds_write(v, lds, t, LOGE, logW + top_s, Tn);
@@ -299,22 +340,14 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a)
                 s -= gs;
                 lds_read(v, lds, t, gs, logW + s, Tn);
                 reg_inv<T, E, LOGE>(v, gs);
-                group_twiddle<T, E, true>(v, t, gs, s, logW, Tn);
+                group_twiddle<T, E, LOGE, true>(v, t, gs, s, logW, Tn);
                 lds_write(v, lds, t, gs, logW + s, Tn);
                 __syncthreads();
             }
             lds_read(v, lds, t, LOGE, logW + top_s, Tn);
         }
         if constexpr (FFT) {
-            if (a.global_tw) {
-#pragma unroll
-                for (int i = 0; i < E; ++i) {
-                    const int q = t + Tn * i;
-                    const uint64_t k1 = (uint64_t)((cb << logW) + (q & ((1 << logW) - 1)));
-                    const uint64_t rr = brev_bits((uint32_t)(q >> logW), A);
-                    v[i] = cmulc(v[i], tw_any<R>(k1 * rr, b0 + A));
-                }
-            }
+            if (a.global_tw) pass_twiddle<T, E, LOGE, true>(v, t, cb, logW, A, b0);
         }
     }
 
@@ -334,7 +367,7 @@ int launch_t(bool src_real, bool dst_real, const PassArgs &a, hipStream_t s)
     const int S = 1 << (a.g.a + a.g.logW);
     const int threads = S >> LOGE;
     const int64_t blocks = a.rows * ((int64_t)1 << (a.m - a.g.a - a.g.logW));
-    if (blocks > 0x7fffffff || threads > 256 || threads < 1) return LDK_ENOTSUP;
+    if (blocks > 0x7fffffff || threads > 512 || threads < 1) return LDK_ENOTSUP;
     const size_t lds = (size_t)(S + (S >> LDS_PAD_SHIFT)) * sizeof(T);
     if constexpr (std::is_floating_point<T>::value) {
         hipLaunchKernelGGL((k_pass<T, LOGE, MODE, false, false, SRC_F32>), dim3((unsigned)blocks),
@@ -388,6 +421,8 @@ Plan make_plan(int m, int log_tile)
     Plan p{};
     p.m = m;
     if (m == 0) return p;
+    constexpr int LOGE_MAX = 3;    // 8 elements per thread
+    constexpr int LOG_THREADS = 9; // at most 512 threads per workgroup
     // row pass: the low a0 bits; column passes: the rest, split evenly into
     // chunks of at most 8 bits (at least 4 where possible)
     int a0 = m < log_tile ? m : log_tile;
@@ -396,17 +431,17 @@ Plan make_plan(int m, int log_tile)
         a0 = m - 4;
         r = 4;
     }
-    p.pass[0] = PassGeom{0, a0, 0, a0 < 4 ? a0 : 4};
+    p.pass[0] = PassGeom{0, a0, 0, a0 < LOGE_MAX ? a0 : LOGE_MAX};
     p.P = 1;
     const int C = (r + 7) / 8;
     int b0 = a0;
     for (int c = 0; c < C; ++c) {
         const int a = r / C + (c < r % C ? 1 : 0);
-        const int logE = a < 4 ? a : 4;
+        const int logE = a < LOGE_MAX ? a : LOGE_MAX;
         // tile 2^a rows x 2^logW columns: at most 2^log_tile elements,
-        // at most 256 threads (2^(a + logW - logE)), at most 2^b0 columns
+        // at most 2^LOG_THREADS threads (2^(a + logW - logE)), at most 2^b0 columns
         int logW = log_tile - a;
-        if (logW > 8 + logE - a) logW = 8 + logE - a;
+        if (logW > LOG_THREADS + logE - a) logW = LOG_THREADS + logE - a;
         if (logW > b0) logW = b0;
         p.pass[p.P++] = PassGeom{b0, a, logW, logE};
         b0 += a;

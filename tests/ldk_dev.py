@@ -28,8 +28,7 @@ def pointset(w, order=None):
 
 
 def kernel(w):
-    return ldk.Kernel(kind=w["kind"],
-                      alpha=torch.as_tensor(np.asarray(w["alpha"], np.int32)).cuda(),
+    return ldk.Kernel(kind=w["kind"], alpha=np.asarray(w["alpha"], np.int32),
                       gamma=torch.as_tensor(np.asarray(w["gamma"], np.float64)).cuda(),
                       zeta=float(w["zeta"]))
 

@@ -88,6 +88,29 @@ def test_kernel_column(orc, kind, src, dtype, order):
         assert err <= tol, (lo, hi, err, tol)
 
 
+@pytest.mark.parametrize("kind,alpha", [("lattice", 1), ("lattice", 2), ("lattice", 3),
+                                        ("dnet", 1), ("dnet", 2), ("dnet", 3), ("dnet", 4)])
+@pytest.mark.parametrize("dtype", [F64, F32])
+@pytest.mark.parametrize("order", ["natural", "gray_or_linear"])
+def test_kernel_column_uniform_order(orc, kind, alpha, dtype, order):
+    # one order for every dimension: the specialised kernels
+    m, d, R = 13, 9, 2
+    w = _net_or_lattice(kind, 70 + alpha, m, d, R)
+    if order != "natural":
+        w["order"] = "gray" if kind == "dnet" else "linear"
+    w.update(alpha=np.full(d, alpha, np.int32), gamma=0.8 ** np.arange(d), zeta=0.7)
+    ps, k = pointset(w), kernel(w)
+    n = 2**m
+    tol = (1e-13 if dtype == F64 else 1e-5) * kernel_scale(w)
+    allpts = orc.points(w)
+    for lo, hi in ((0, n), (1000, n - 3000), (2048, 4096), (5, 6)):
+        want = orc.kernel_column(kind, allpts[:, lo:hi], allpts[:, 0], w["alpha"], w["gamma"],
+                                 w["zeta"])
+        got = ldk.kernel_column(k, ps, lo, hi, dtype=dtype)
+        err = np.max(np.abs(got.cpu().double().numpy() - want))
+        assert err <= tol, (lo, hi, err, tol)
+
+
 # ---------------------------------------------------------------------------
 # a4 building block: the transforms
 # ---------------------------------------------------------------------------

@@ -65,16 +65,33 @@ def test_gen_points_rejects_bad_ranges():
     assert L.ldk_gen_points(C.byref(_ps()), 3, 3, FAKE, None) == 0
 
 
+def _alpha(*vals):
+    arr = (C.c_int32 * len(vals))(*vals)
+    return arr, C.cast(arr, C.c_void_p)
+
+
 def test_kernel_column_rejects_mismatch():
     L = ldk.lib()
-    k = ldk._Kernel(ldk.LATTICE, 4, FAKE, FAKE, 1.0)
+    keep, a4 = _alpha(2, 2, 2, 2)
+    k = ldk._Kernel(ldk.LATTICE, 4, a4, FAKE, 1.0)
     assert L.ldk_kernel_column(C.byref(k), C.byref(_ps()), None, None, 0, 4, 0, FAKE, None) == -1
-    k = ldk._Kernel(ldk.DNET_B2, 4, FAKE, FAKE, 0.0)  # zeta must be > 0
+    k = ldk._Kernel(ldk.DNET_B2, 4, a4, FAKE, 0.0)  # zeta must be > 0
     assert L.ldk_kernel_column(C.byref(k), C.byref(_ps()), None, None, 0, 4, 0, FAKE, None) == -1
-    k = ldk._Kernel(ldk.DNET_B2, 4, FAKE, FAKE, 1.0)
+    k = ldk._Kernel(ldk.DNET_B2, 4, a4, FAKE, 1.0)
     assert L.ldk_kernel_column(C.byref(k), C.byref(_ps()), None, None, 0, 4, 9, FAKE, None) == -1
     # pts given with n_min > 0 needs an explicit anchor
     assert L.ldk_kernel_column(C.byref(k), C.byref(_ps()), FAKE, None, 2, 4, 0, FAKE, None) == -1
+    # orders are validated on the host: nets 1..4, lattices 1..3
+    keep5, bad = _alpha(1, 2, 5, 1)
+    k = ldk._Kernel(ldk.DNET_B2, 4, bad, FAKE, 1.0)
+    assert L.ldk_kernel_column(C.byref(k), C.byref(_ps()), None, None, 0, 4, 0, FAKE, None) == -1
+    keep4, bad4 = _alpha(1, 4, 2, 1)
+    k = ldk._Kernel(ldk.LATTICE, 4, bad4, FAKE, 1.0)
+    ps = _ps(kind=ldk.LATTICE)
+    assert L.ldk_kernel_column(C.byref(k), C.byref(ps), None, None, 0, 4, 0, FAKE, None) == -1
+    keep0, bad0 = _alpha(1, 0, 2, 1)
+    k = ldk._Kernel(ldk.DNET_B2, 4, bad0, FAKE, 1.0)
+    assert L.ldk_kernel_column(C.byref(k), C.byref(_ps()), None, None, 0, 4, 0, FAKE, None) == -1
 
 
 def test_algebra_rejects_bad_arguments():
@@ -103,7 +120,7 @@ def test_workspace_sizes():
     assert ws(ldk.OP_SOLVE, ldk.LATTICE, 4, 20, 0) == 4 * 2**20 * 16
     assert ws(ldk.OP_SOLVE, ldk.LATTICE, 4, 20, 1) == 4 * 2**20 * 8
     assert ws(ldk.OP_SOLVE, ldk.LATTICE, 4, 10, 0) == 0  # one pass, no intermediate
-    assert ws(ldk.OP_LOGDET, ldk.DNET_B2, 3, 20, 0) == 3 * 64 * 8
+    assert ws(ldk.OP_LOGDET, ldk.DNET_B2, 3, 20, 0) == 3 * 512 * 8
     assert ws(ldk.OP_EIG, 9, 1, 4, 0) == 0
     # eigenvalue transforms run in FP64 whatever the input dtype
     assert ws(ldk.OP_EIG, ldk.LATTICE, 2, 20, 1) == 2 * 2**20 * 16
