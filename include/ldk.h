@@ -151,16 +151,20 @@ int ldk_transform(int kind, int dir, int B, int m, int dtype, const void *in, vo
 /* Eigenvalues lambda = sqrt(n) conj(V_m) k1 (Sec. 5.4): sqrt(n) FFTBR(k1)
  * (lattice; real since K is real symmetric) or sqrt(n) FWHT(k1) (net).
  * k1 = real dtype[R][n]; lam = double[R][n], natural frequency / Walsh
- * order.  The transform runs in FP64 for either input dtype.
- * ws: ldk_workspace_bytes(LDK_OP_EIG, ...) bytes (lattice only). */
+ * order.  The transform runs in FP64 for either input dtype; lattice
+ * lam_k = Re sqrt(n) FFTBR(k1)_k.
+ * ws: ldk_workspace_bytes(LDK_OP_EIG, ...) bytes (lattice with n > 2^12 only). */
 int ldk_eig(int kind, int R, int m, int dtype, const void *k1, double *lam, void *ws,
             ldk_stream stream);
 
 /* Solve (K + sigma^2 I) c = y:  c = V (conj(V) y (/) (lambda + sigma^2)) (Sec. 5.4).
  * lam = double[R][n]; y, c = dtype[R][nrhs][n] (y and c may alias exactly;
  * right-hand side q of replication r uses row r of lam).  sigma2 >= 0; the
- * division is done in FP64.  ws: ldk_workspace_bytes(LDK_OP_SOLVE, kind,
- * R * nrhs, m, dtype) bytes (lattice with n > 2^11 only). */
+ * division is done in FP64.  Lattice: c is the real part of that product
+ * (the whole of it when lambda_k = lambda_{n-k}, as for a real symmetric K);
+ * for n >= 4 the real rows run as packed complex rows of n/2.
+ * ws: ldk_workspace_bytes(LDK_OP_SOLVE, kind, R * nrhs, m, dtype) bytes
+ * (lattice with n > 2^12 in FP64, n > 2^13 in FP32, only). */
 int ldk_solve(int kind, int R, int nrhs, int m, int dtype, const double *lam, double sigma2,
               const void *y, void *c, void *ws, ldk_stream stream);
 

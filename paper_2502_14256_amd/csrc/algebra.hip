@@ -173,8 +173,8 @@ int forward_all(int kind, int dtype, int m, int64_t rows, const void *src, int64
         a.nrhs = 1;
         a.global_tw = p > 0;
         a.scale = last ? scale : 1.0;
-        const int st = launch_pass(kind, dtype, PM_FWD, first && src_real, last && dst_real, a, s,
-                                   first && src_f32);
+        const int st = launch_pass(kind, dtype, PM_FWD, first && src_real ? PIO_REAL : PIO_SAME,
+                                   last && dst_real ? PIO_REAL : PIO_SAME, a, s, first && src_f32);
         if (st) return st;
     }
     return LDK_OK;
@@ -202,7 +202,8 @@ int apply_all(int kind, int dtype, int mode, int m, int64_t rows, int nrhs, cons
         a.nrhs = nrhs;
         a.global_tw = p > 0;
         a.scale = 1.0;
-        const int st = launch_pass(kind, dtype, PM_FWD, lat && p == 0, false, a, s);
+        const int st = launch_pass(kind, dtype, PM_FWD, lat && p == 0 ? PIO_REAL : PIO_SAME, PIO_SAME,
+                                   a, s);
         if (st) return st;
     }
     {
@@ -219,7 +220,8 @@ int apply_all(int kind, int dtype, int mode, int m, int64_t rows, int nrhs, cons
         a.global_tw = p > 0;
         a.sigma2 = sigma2;
         a.scale = scale;
-        const int st = launch_pass(kind, dtype, mode, lat && p == 0, lat && p == 0, a, s);
+        const int io = lat && p == 0 ? PIO_REAL : PIO_SAME;
+        const int st = launch_pass(kind, dtype, mode, io, io, a, s);
         if (st) return st;
     }
     for (int p = pl.P - 2; p >= 0; --p) {
@@ -233,7 +235,111 @@ int apply_all(int kind, int dtype, int mode, int m, int64_t rows, int nrhs, cons
         a.nrhs = nrhs;
         a.global_tw = p > 0;
         a.scale = 1.0;
-        const int st = launch_pass(kind, dtype, PM_INV, false, lat && p == 0, a, s);
+        const int st = launch_pass(kind, dtype, PM_INV, PIO_SAME, lat && p == 0 ? PIO_REAL : PIO_SAME,
+                                   a, s);
+        if (st) return st;
+    }
+    return LDK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Real-input lattice transforms through the packed half-length FFTBR
+// (realfft.hip): N = n/2 complex, plan over m - 1 bits, top pass special.
+// ---------------------------------------------------------------------------
+bool real_path(int kind, int m) { return kind == LDK_LATTICE && m >= 2; }
+
+// lambda = Re FFTBR_n(k1) (unnormalised), FP64, from real k1 rows of n.
+int real_eig(int m, int64_t rows, const void *k1, bool k1_f32, double *lam, void *ws, hipStream_t s)
+{
+    const int mp = m - 1;
+    const int64_t N = (int64_t)1 << mp;
+    const Plan pl = make_plan(mp, log_tile_for(LDK_LATTICE, LDK_F64));
+    PassArgs a{};
+    a.rows = rows;
+    a.m = mp;
+    a.nrhs = 1;
+    a.half = N;
+    a.scale = 1.0;
+    if (pl.P == 1) {
+        a.src = k1;
+        a.src_row = 2 * N;
+        a.g = pl.pass[0];
+        return launch_real_top(LDK_F64, PM_FWD, a, lam, s, k1_f32);
+    }
+    for (int p = 0; p < pl.P - 1; ++p) {
+        a.src = p == 0 ? k1 : ws;
+        a.src_row = p == 0 ? 2 * N : N;
+        a.dst = ws;
+        a.dst_row = N;
+        a.g = pl.pass[p];
+        a.global_tw = p > 0;
+        const int st = launch_pass(LDK_LATTICE, LDK_F64, PM_FWD, p == 0 ? PIO_PACKED : PIO_SAME,
+                                   PIO_SAME, a, s, p == 0 && k1_f32);
+        if (st) return st;
+    }
+    a.src = ws;
+    a.src_row = N;
+    a.g = pl.pass[pl.P - 1];
+    a.global_tw = 1;
+    return launch_real_top(LDK_F64, PM_FWD, a, lam, s);
+}
+
+// c = (K + s2 I)^-1 y (PM_SOLVE) or K y (PM_MATVEC) for real rows of n.
+int real_apply(int dtype, int mode, int m, int64_t rows, int nrhs, const double *lam, double sigma2,
+               const void *y, void *c, void *ws, hipStream_t s)
+{
+    const int mp = m - 1;
+    const int64_t N = (int64_t)1 << mp;
+    const Plan pl = make_plan(mp, log_tile_for(LDK_LATTICE, dtype));
+    PassArgs a{};
+    a.rows = rows;
+    a.m = mp;
+    a.nrhs = nrhs;
+    a.half = N;
+    a.lam = lam;
+    a.sigma2 = sigma2;
+    if (pl.P == 1) {
+        a.src = y;
+        a.dst = c;
+        a.src_row = a.dst_row = 2 * N;
+        a.g = pl.pass[0];
+        a.scale = 1.0 / (double)N;
+        return launch_real_top(dtype, mode, a, nullptr, s);
+    }
+    for (int p = 0; p < pl.P - 1; ++p) {
+        PassArgs b = a;
+        b.src = p == 0 ? y : ws;
+        b.src_row = p == 0 ? 2 * N : N;
+        b.dst = ws;
+        b.dst_row = N;
+        b.g = pl.pass[p];
+        b.global_tw = p > 0;
+        b.scale = 1.0;
+        const int st = launch_pass(LDK_LATTICE, dtype, PM_FWD, p == 0 ? PIO_PACKED : PIO_SAME,
+                                   PIO_SAME, b, s);
+        if (st) return st;
+    }
+    {
+        PassArgs b = a;
+        b.src = b.dst = ws;
+        b.src_row = b.dst_row = N;
+        b.g = pl.pass[pl.P - 1];
+        b.global_tw = 1;
+        b.scale = 1.0 / (double)N;
+        const int st = launch_real_top(dtype, mode, b, nullptr, s);
+        if (st) return st;
+    }
+    for (int p = pl.P - 2; p >= 0; --p) {
+        PassArgs b = a;
+        b.src = ws;
+        b.src_row = N;
+        b.dst = p == 0 ? c : ws;
+        b.dst_row = p == 0 ? 2 * N : N;
+        b.g = pl.pass[p];
+        b.global_tw = p > 0;
+        b.scale = 1.0;
+        const int st = launch_pass(LDK_LATTICE, dtype, PM_INV, PIO_SAME,
+                                   p == 0 ? PIO_PACKED : PIO_SAME, b, s);
         if (st) return st;
     }
     return LDK_OK;
@@ -247,12 +353,22 @@ size_t ws_bytes(int op, int kind, int64_t B, int m, int dtype)
     switch (op) {
     case LDK_OP_TRANSFORM: return 0;
     case LDK_OP_EIG: {
-        // FP64 transform whatever the input dtype
+        // FP64 transform whatever the input dtype; real lattice rows of n run
+        // as packed complex rows of n/2
+        if (real_path(kind, m)) {
+            const int P64 = make_plan(m - 1, log_tile_for(kind, LDK_F64)).P;
+            return P64 > 1 ? cplx_rows_bytes(B, m - 1, LDK_F64) : 0;
+        }
         const int P64 = make_plan(m, log_tile_for(kind, LDK_F64)).P;
         return (lat && P64 > 1) ? cplx_rows_bytes(B, m, LDK_F64) : 0;
     }
     case LDK_OP_SOLVE:
-    case LDK_OP_MATVEC: return (lat && P > 1) ? cplx_rows_bytes(B, m, dtype) : 0;
+    case LDK_OP_MATVEC:
+        if (real_path(kind, m)) {
+            const int Pp = make_plan(m - 1, log_tile_for(kind, dtype)).P;
+            return Pp > 1 ? cplx_rows_bytes(B, m - 1, dtype) : 0;
+        }
+        return (lat && P > 1) ? cplx_rows_bytes(B, m, dtype) : 0;
     case LDK_OP_LOGDET: {
         const int64_t n = (int64_t)1 << m;
         const int64_t chunks = (n + LOGDET_CHUNK - 1) / LOGDET_CHUNK;
@@ -311,7 +427,7 @@ int ldk_transform(int kind, int dir, int B, int m, int dtype, const void *in, vo
         a.nrhs = 1;
         a.global_tw = p > 0;
         a.scale = p == 0 ? scale : 1.0;
-        st = launch_pass(kind, dtype, PM_INV, false, false, a, s);
+        st = launch_pass(kind, dtype, PM_INV, PIO_SAME, PIO_SAME, a, s);
         if (st) return st;
     }
     return LDK_OK;
@@ -339,6 +455,7 @@ int ldk_eig(int kind, int R, int m, int dtype, const void *k1, double *lam, void
         return LDK_OK;
     }
     const bool lat = kind == LDK_LATTICE;
+    if (real_path(kind, m)) return real_eig(m, R, k1, dtype == LDK_F32, lam, ws, s);
     // lambda = sqrt(n) * orthonormal transform = unnormalised transform, in FP64
     return forward_all(kind, LDK_F64, m, R, k1, n, lat, lam, n, lat, lat ? ws : (void *)lam, n, 1.0,
                        s, dtype == LDK_F32);
@@ -369,6 +486,7 @@ static int apply_entry(int mode, int kind, int R, int nrhs, int m, int dtype, co
         LDK_LAUNCH_CHECK();
         return LDK_OK;
     }
+    if (real_path(kind, m)) return real_apply(dtype, mode, m, rows, nrhs, lam, sigma2, y, c, ws, s);
     return apply_all(kind, dtype, mode, m, rows, nrhs, lam, sigma2, y, c, ws, s);
 }
 

@@ -13,7 +13,7 @@ namespace {
 constexpr int KC_THREADS = 256;
 constexpr int KC_LOG_THREADS = 8;
 constexpr int KC_ITERS = 8;       // points per thread (spaced KC_THREADS apart)
-constexpr int KC_DIM_CHUNK = 32;  // dimensions whose net tables sit in LDS at once
+constexpr int KC_DIM_CHUNK = 16;  // dimensions whose net tables sit in LDS at once
 constexpr int KC_TILE = KC_THREADS * KC_ITERS;
 constexpr int KC_CODE_WORDS = LDK_MAX_D / 32;  // 2-bit order codes, 32 per word
 }  // namespace
@@ -56,8 +56,10 @@ __device__ __forceinline__ R si_weighted(R x, R c0, R c1, R c2, R c3)
 // The alpha = 4 series sum_{a>=0} (-1)^{xi_{a+1}} 8^{-a} is kept to 21 digits
 // (the rest is below 2^-62) and read from three 128-entry tables of 7 digits:
 // series = 8/7 - 2 (T0[d1..d7] + T1[d8..d14] + T2[d15..d21]).
+// Each entry is a sum of at most 7 powers of 8 spanning 19 bits: exact in
+// FP32, so the tables are stored as float (half the LDS traffic).
 struct DsiTables {
-    double t[3][128];
+    float t[3][128];
 };
 __device__ __forceinline__ void fill_dsi_tables(DsiTables &tab, int t, int nthreads)
 {
@@ -66,8 +68,14 @@ __device__ __forceinline__ void fill_dsi_tables(DsiTables &tab, int t, int nthre
         double acc = 0.0;
         for (int b = 0; b < 7; ++b)  // bit 6 - b of v is digit 7 chunk + b + 1
             if ((v >> (6 - b)) & 1) acc += ldexp(1.0, -3 * (7 * chunk + b));
-        tab.t[chunk][v] = acc;
+        tab.t[chunk][v] = (float)acc;
     }
+}
+
+// 2^-beta for 1 <= beta <= 64 from its exponent bits (exact).
+__device__ __forceinline__ double pow2_neg(int beta)
+{
+    return __hiloint2double((1023 - beta) << 20, 0);
 }
 
 template <typename R>
@@ -87,7 +95,7 @@ __device__ __forceinline__ R dsi_factor(uint64_t delta, const DsiTables &tab)
         x = unit<R>(delta);
     }
     const R b = (R)beta;
-    const R t1 = beta ? (R)ldexp(1.0, -beta) : (R)0;
+    const R t1 = beta ? (R)pow2_neg(beta) : (R)0;
     if constexpr (ALPHA == 1) {
         return (R)1 - (R)3 * t1;
     } else if constexpr (ALPHA == 2) {
@@ -97,8 +105,9 @@ __device__ __forceinline__ R dsi_factor(uint64_t delta, const DsiTables &tab)
         return ((b * x - (R)5 * ((R)1 - t1)) * x + (R)(43.0 / 18.0) * ((R)1 - t2)) - (R)1;
     } else {
         const R t2 = t1 * t1, t3 = t2 * t1;
-        const R ones = (R)(tab.t[0][(delta >> 57) & 127] + tab.t[1][(delta >> 50) & 127] +
-                           tab.t[2][(delta >> 43) & 127]);
+        const uint32_t hi = (uint32_t)(delta >> 32);
+        const R ones = ((R)tab.t[0][hi >> 25] + (R)tab.t[1][(hi >> 18) & 127]) +
+                       (R)tab.t[2][(hi >> 11) & 127];
         const R series = (R)(8.0 / 7.0) - (R)2 * ones;
         const R poly = ((-(R)(2.0 / 3.0) * b * x + (R)5 * ((R)1 - t1)) * x -
                         (R)(43.0 / 9.0) * ((R)1 - t2)) * x;
@@ -132,12 +141,18 @@ __device__ __forceinline__ int alpha_of(const KcolArgs &a, int j)
     return 1 + (int)((a.acode[j >> 5] >> (2 * (j & 31))) & 3u);
 }
 
+// Net tables of a chunk of dimensions.  The start point of thread t is
+// z(code(tile0 + t)) = z(code(tile0)) ^ z(code(t)) (the index bits of tile0 and
+// t are disjoint, also after Gray coding), read as one block-uniform word
+// zb[jj] and two 16-entry nibble tables of z over the low 8 index bits.
 struct NetLds {
     uint64_t ct[KC_DIM_CHUNK][64];  // scrambled columns S_j C_j
     union {
         uint64_t step[KC_DIM_CHUNK][64];  // XOR steps between a thread's points
         uint64_t srow[KC_DIM_CHUNK][64];  // rows of S_j (dead once ct is built)
     };
+    uint64_t nib[KC_DIM_CHUNK][2][16];  // z of (nibble h of the low index byte)
+    uint64_t zb[KC_DIM_CHUNK];          // z(code(tile0))
     DsiTables tab;
 };
 
@@ -218,6 +233,9 @@ __device__ __forceinline__ void net_tile(const KcolArgs &a, NetLds &L, int r, in
 {
     constexpr int s = KC_LOG_THREADS;
     const int d = a.ps.d, m = a.ps.m_max, t = threadIdx.x;
+    const bool gray = a.ps.order == LDK_GRAY;
+    const uint64_t code_tile = gray ? gray_code((uint64_t)tile0) : (uint64_t)tile0;
+    const uint32_t code_t = gray ? (uint32_t)gray_code((uint64_t)t) : (uint32_t)t;
     for (int jc = 0; jc < d; jc += KC_DIM_CHUNK) {
         const int DB = min(KC_DIM_CHUNK, d - jc);
         __syncthreads();  // tables of the previous chunk are no longer read
@@ -226,17 +244,21 @@ __device__ __forceinline__ void net_tile(const KcolArgs &a, NetLds &L, int r, in
                 L.srow[w >> 6][w & 63] = a.ps.lms[((size_t)r * d + jc + (w >> 6)) * 64 + (w & 63)];
             __syncthreads();
         }
-        for (int w = t; w < DB * m; w += KC_THREADS) {
-            const int jj = w / m, k = w % m;
-            const uint64_t col = a.ps.gen[(size_t)(jc + jj) * m + k];
-            L.ct[jj][k] = a.ps.lms ? lms_column(L.srow[jj], col) : col;
+        for (int w = t; w < DB * 64; w += KC_THREADS) {
+            const int jj = w >> 6, k = w & 63;
+            uint64_t v = 0;  // columns k >= m are zero
+            if (k < m) {
+                const uint64_t col = a.ps.gen[(size_t)(jc + jj) * m + k];
+                v = a.ps.lms ? lms_column(L.srow[jj], col) : col;
+            }
+            L.ct[jj][k] = v;
         }
         __syncthreads();  // srow is dead from here on; step reuses its storage
         for (int w = t; w < DB * 64; w += KC_THREADS) {
             const int jj = w >> 6, c = w & 63;
             uint64_t v = 0;
             if (s + c < m) {
-                if (a.ps.order == LDK_GRAY) {
+                if (gray) {
                     v = L.ct[jj][s + c] ^ L.ct[jj][s - 1];
                 } else {
                     for (int k = s; k <= s + c; ++k) v ^= L.ct[jj][k];
@@ -244,14 +266,20 @@ __device__ __forceinline__ void net_tile(const KcolArgs &a, NetLds &L, int r, in
             }
             L.step[jj][c] = v;
         }
+        for (int w = t; w < DB * 32; w += KC_THREADS) {
+            const int jj = w >> 5, h = (w >> 4) & 1, v = w & 15;
+            uint64_t z = 0;
+            for (int k = 0; k < 4; ++k)
+                if ((v >> k) & 1) z ^= L.ct[jj][4 * h + k];
+            L.nib[jj][h][v] = z;
+        }
+        if (t < DB) L.zb[t] = net_point(L.ct[t], m, code_tile);
         __syncthreads();
         for (int jj = 0; jj < DB; ++jj) {
             const int j = jc + jj;
             const R gam = (R)a.gamma[j];
             const int alpha = ALPHA ? ALPHA : alpha_of(a, j);
-            const uint64_t code =
-                a.ps.order == LDK_GRAY ? gray_code((uint64_t)first) : (uint64_t)first;
-            uint64_t z = net_point(L.ct[jj], m, code);
+            uint64_t z = L.zb[jj] ^ L.nib[jj][0][code_t & 15] ^ L.nib[jj][1][(code_t >> 4) & 15];
 #pragma unroll
             for (int l = 0; l < KC_ITERS; ++l) {
                 R k;

@@ -1,0 +1,277 @@
+// Device building blocks of the pass kernels: element arithmetic, radix-2^g
+// register stages, tile index maps, twiddles, LDS exchange, global IO.
+#pragma once
+
+#include <type_traits>
+
+#include "transform.hpp"
+
+namespace ldk {
+namespace kit {
+
+constexpr int LDS_PAD_SHIFT = 4;  // one padding element every 16
+
+__device__ __forceinline__ int lds_idx(int q) { return q + (q >> LDS_PAD_SHIFT); }
+
+// ---- element arithmetic -------------------------------------------------
+template <typename R>
+__device__ __forceinline__ R add(R a, R b) { return a + b; }
+template <typename R>
+__device__ __forceinline__ cplx<R> add(cplx<R> a, cplx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R>
+__device__ __forceinline__ R sub(R a, R b) { return a - b; }
+template <typename R>
+__device__ __forceinline__ cplx<R> sub(cplx<R> a, cplx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R>
+__device__ __forceinline__ R scl(R a, R s) { return a * s; }
+template <typename R>
+__device__ __forceinline__ cplx<R> scl(cplx<R> a, R s) { return {a.re * s, a.im * s}; }
+
+// W_16^q = exp(-2 pi i q / 16), q = 0..7, as compile-time constants.
+template <typename R, int q>
+__device__ __forceinline__ cplx<R> mul_w16(cplx<R> v)
+{
+    constexpr double C1 = 0.92387953251128675613, S1 = 0.38268343236508977173;
+    constexpr double H = 0.70710678118654752440;
+    if constexpr (q == 0) return v;
+    if constexpr (q == 4) return {v.im, -v.re};  // * (-i)
+    if constexpr (q == 2) return {(R)H * (v.re + v.im), (R)H * (v.im - v.re)};
+    if constexpr (q == 6) return {(R)H * (v.im - v.re), -(R)H * (v.re + v.im)};
+    constexpr double c = q == 1 ? C1 : q == 3 ? S1 : q == 5 ? -S1 : -C1;
+    constexpr double sn = q == 1 ? -S1 : q == 3 ? -C1 : q == 5 ? -C1 : -S1;
+    return {(R)c * v.re - (R)sn * v.im, (R)c * v.im + (R)sn * v.re};
+}
+template <typename R, int q>
+__device__ __forceinline__ cplx<R> mulc_w16(cplx<R> v)  // * conj(W_16^q)
+{
+    const cplx<R> t = mul_w16<R, q>(cplx<R>{v.re, -v.im});
+    return {t.re, -t.im};
+}
+
+// Butterfly stage of span h = 2^b on the registers of one thread.
+// FFT forward (DIT):  (u, w) -> (u + W_{2h}^j w, u - W_{2h}^j w), j = i mod h.
+template <typename R, int E, int b, int i = 0>
+__device__ __forceinline__ void fft_stage_fwd(cplx<R> (&v)[E])
+{
+    if constexpr (i < E) {
+        constexpr int h = 1 << b;
+        if constexpr ((i & h) == 0) {
+            constexpr int j = i & (h - 1);
+            const cplx<R> w = mul_w16<R, (j * (8 / h)) & 7>(v[i + h]);
+            const cplx<R> u = v[i];
+            v[i] = add(u, w);
+            v[i + h] = sub(u, w);
+        }
+        fft_stage_fwd<R, E, b, i + 1>(v);
+    }
+}
+// FFT inverse: (x, y) -> (x + y, conj(W_{2h}^j) (x - y)).
+template <typename R, int E, int b, int i = 0>
+__device__ __forceinline__ void fft_stage_inv(cplx<R> (&v)[E])
+{
+    if constexpr (i < E) {
+        constexpr int h = 1 << b;
+        if constexpr ((i & h) == 0) {
+            constexpr int j = i & (h - 1);
+            const cplx<R> x = v[i], y = v[i + h];
+            v[i] = add(x, y);
+            v[i + h] = mulc_w16<R, (j * (8 / h)) & 7>(sub(x, y));
+        }
+        fft_stage_inv<R, E, b, i + 1>(v);
+    }
+}
+// FWHT butterfly (x, y) -> (x + y, x - y).
+template <typename T, int E, int b, int i = 0>
+__device__ __forceinline__ void wht_stage(T (&v)[E])
+{
+    if constexpr (i < E) {
+        constexpr int h = 1 << b;
+        if constexpr ((i & h) == 0) {
+            const T x = v[i], y = v[i + h];
+            v[i] = add(x, y);
+            v[i + h] = sub(x, y);
+        }
+        wht_stage<T, E, b, i + 1>(v);
+    }
+}
+
+// In-register transform over the low gs bits of the register index.
+template <typename T, int E, int LOGE, bool INV, int b = 0>
+__device__ __forceinline__ void reg_fwd(T (&v)[E], int gs)
+{
+    if constexpr (b < LOGE) {
+        if (b < gs) {
+            if constexpr (std::is_floating_point<T>::value)
+                wht_stage<T, E, b>(v);
+            else
+                fft_stage_fwd<decltype(T::re), E, b>(v);
+        }
+        reg_fwd<T, E, LOGE, INV, b + 1>(v, gs);
+    }
+}
+template <typename T, int E, int LOGE, int b = LOGE - 1>
+__device__ __forceinline__ void reg_inv(T (&v)[E], int gs)
+{
+    if constexpr (b >= 0) {
+        if (b < gs) {
+            if constexpr (std::is_floating_point<T>::value)
+                wht_stage<T, E, b>(v);
+            else
+                fft_stage_inv<decltype(T::re), E, b>(v);
+        }
+        reg_inv<T, E, LOGE, b - 1>(v, gs);
+    }
+}
+
+// Tile index of register i of thread t for a group of gs bits at tile bit
+// `pos`: the digit c = i mod 2^gs is inserted at bit pos of o = sub*T + t.
+__device__ __forceinline__ int group_q(int t, int i, int gs, int pos, int T)
+{
+    const int c = i & ((1 << gs) - 1);
+    const int o = (i >> gs) * T + t;
+    return (o & ((1 << pos) - 1)) | (c << pos) | ((o >> pos) << (pos + gs));
+}
+
+template <typename T>
+struct real_of {
+    using type = T;
+};
+template <typename R>
+struct real_of<cplx<R>> {
+    using type = R;
+};
+
+// Powers w^c, c = 0..E-1, by a binary product tree: w^{2^j} by squaring,
+// w^c = w^{c - 2^j} w^{2^j} (at most 2 log2(E) roundings per entry).
+template <typename R, int E>
+__device__ __forceinline__ void powers(cplx<R> w, cplx<R> (&p)[E])
+{
+    p[0] = cplx<R>{(R)1, (R)0};
+    if constexpr (E > 1) p[1] = w;
+#pragma unroll
+    for (int c = 2; c < E; ++c) {
+        const int hi = 1 << (31 - __builtin_clz(c));  // largest power of two <= c
+        p[c] = (c == hi) ? cmul(p[c >> 1], p[c >> 1]) : cmul(p[c - hi], p[hi]);
+    }
+}
+
+// Group twiddle of the FFT schedule: element with tile index q, axis index
+// r = q >> logW, group digit c at axis bit s: W_{2^{s+gs}}^{(r mod 2^s) R_gs(c)}.
+// For a full group every register of a thread shares r mod 2^s, so one table
+// read gives w = W^{r mod 2^s} and the twiddles are its powers.
+template <typename T, int E, int LOGE, bool CONJ>
+__device__ __forceinline__ void group_twiddle(T (&v)[E], int t, int gs, int s, int logW, int T_)
+{
+    if constexpr (!std::is_floating_point<T>::value) {
+        using R = typename real_of<T>::type;
+        if (s == 0) return;
+        if (gs == LOGE) {
+            const int q0 = group_q(t, 0, gs, logW + s, T_);
+            const uint32_t rlow = (uint32_t)(q0 >> logW) & ((1u << s) - 1);
+            cplx<R> pw[E];
+            powers<R, E>(tw_small<R>(rlow, s + gs), pw);
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                const cplx<R> w = pw[brev_bits((uint32_t)i, LOGE)];
+                v[i] = CONJ ? cmulc(v[i], w) : cmul(v[i], w);
+            }
+            return;
+        }
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int q = group_q(t, i, gs, logW + s, T_);
+            const uint32_t rlow = (uint32_t)(q >> logW) & ((1u << s) - 1);
+            const uint32_t c = (uint32_t)i & ((1u << gs) - 1);
+            const cplx<R> w = tw_small<R>(rlow * brev_bits(c, gs), s + gs);
+            v[i] = CONJ ? cmulc(v[i], w) : cmul(v[i], w);
+        }
+    }
+}
+
+// Inter-pass twiddle W_{2^{b0+A}}^{k1 R_A(r)} for the coalesced pattern
+// q = t + Tn i: the column k1 is fixed per thread and
+// R_A(r) = R_{A-LOGE}(r0) 2^LOGE + R_LOGE(i), r0 = t >> logW, so the twiddles
+// are W^{k1 R_{A-LOGE}(r0) 2^LOGE} times the powers of W^{k1}.
+template <typename T, int E, int LOGE, bool CONJ>
+__device__ __forceinline__ void pass_twiddle_k1(T (&v)[E], int t, uint64_t k1, int logW, int A, int b0)
+{
+    if constexpr (!std::is_floating_point<T>::value) {
+        using R = typename real_of<T>::type;
+        const uint64_t r0 = (uint64_t)(t >> logW);
+        const cplx<R> base = tw_any<R>((k1 * brev_bits((uint32_t)r0, A - LOGE)) << LOGE, b0 + A);
+        cplx<R> pw[E];
+        powers<R, E>(tw_any<R>(k1, b0 + A), pw);
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const cplx<R> w = cmul(base, pw[brev_bits((uint32_t)i, LOGE)]);
+            v[i] = CONJ ? cmulc(v[i], w) : cmul(v[i], w);
+        }
+    }
+}
+template <typename T, int E, int LOGE, bool CONJ>
+__device__ __forceinline__ void pass_twiddle(T (&v)[E], int t, int64_t cb, int logW, int A, int b0)
+{
+    const uint64_t k1 = (uint64_t)((cb << logW) + (t & ((1 << logW) - 1)));
+    pass_twiddle_k1<T, E, LOGE, CONJ>(v, t, k1, logW, A, b0);
+}
+
+template <typename T, int E>
+__device__ __forceinline__ void lds_read(T (&v)[E], const T *lds, int t, int gs, int pos, int T_)
+{
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[i] = lds[lds_idx(group_q(t, i, gs, pos, T_))];
+}
+template <typename T, int E>
+__device__ __forceinline__ void lds_write(const T (&v)[E], T *lds, int t, int gs, int pos, int T_)
+{
+#pragma unroll
+    for (int i = 0; i < E; ++i) lds[lds_idx(group_q(t, i, gs, pos, T_))] = v[i];
+}
+
+// Global IO modes of a pass (complex working type; real types use IO_SAME):
+//   IO_SAME    elements of the working type;
+//   IO_REAL    real array: load as (x, 0), store the real part;
+//   IO_PACKED  real array of 2 N per row holding a complex row of N as
+//              (re at e, im at e + N): z_e = y_e + i y_{e+N}.
+// SRC_F32: the source holds floats widened to the FP64 working type.
+enum IoMode { IO_SAME = 0, IO_REAL = 1, IO_PACKED = 2 };
+
+template <typename T, int LD, bool SRC_F32>
+__device__ __forceinline__ T load_elem(const void *p, int64_t idx, int64_t half)
+{
+    using R = typename real_of<T>::type;
+    using S = typename std::conditional<SRC_F32, float, R>::type;
+    if constexpr (std::is_floating_point<T>::value) {
+        return (R) static_cast<const S *>(p)[idx];
+    } else if constexpr (LD == IO_REAL) {
+        return T{(R) static_cast<const S *>(p)[idx], (R)0};
+    } else if constexpr (LD == IO_PACKED) {
+        const S *q = static_cast<const S *>(p);
+        return T{(R)q[idx], (R)q[idx + half]};
+    } else {
+        const cplx<S> v = static_cast<const cplx<S> *>(p)[idx];
+        return T{(R)v.re, (R)v.im};
+    }
+}
+template <typename T, int ST>
+__device__ __forceinline__ void store_elem(void *p, int64_t idx, T v, int64_t half)
+{
+    if constexpr (std::is_floating_point<T>::value) {
+        static_cast<T *>(p)[idx] = v;
+    } else {
+        using R = typename real_of<T>::type;
+        if constexpr (ST == IO_REAL) {
+            static_cast<R *>(p)[idx] = v.re;
+        } else if constexpr (ST == IO_PACKED) {
+            R *q = static_cast<R *>(p);
+            q[idx] = v.re;
+            q[idx + half] = v.im;
+        } else {
+            static_cast<T *>(p)[idx] = v;
+        }
+    }
+}
+
+
+}  // namespace kit
+}  // namespace ldk

@@ -1,0 +1,235 @@
+// Real-input lattice transforms (Sec. 5.2, 5.4): the first Gram column and the
+// responses are real, so a length-n FFTBR runs as a complex FFTBR of length
+// N = n/2 on the packed row z_e = y_e + i y_{e+N}.
+//
+// In natural (radical inverse) order the first half of a row holds the even
+// linear-order samples and the second half the odd ones, so FFTBR_N(z) is
+// exactly Z = E + i O with E, O the DFTs of the even and odd samples, and
+//   E_k = (Z_k + conj Z_{N-k}) / 2,   O_k = -i (Z_k - conj Z_{N-k}) / 2,
+//   Y_k = E_k + W_n^k O_k,            Y_{k+N} = E_k - W_n^k O_k
+// (Y the unnormalised length-n FFTBR of y).  The eigenvalues are
+// lambda_k = Re Y_k and lambda_{k+N} = Re Y_{k+N}.  A solve filters with the
+// symmetrised factor d_k = (f(lambda_k) + f(lambda_{n-k}))/2, which equals
+// Re IFFTBR(Y (.) f(lambda)) exactly, then re-packs
+//   E'_k = (C_k + C_{k+N}) / 2,   O'_k = conj(W_n^k) (C_k - C_{k+N}) / 2,
+//   Z'_k = E'_k + i O'_k,
+// and the inverse passes return c_e + i c_{e+N} = IFFTBR_N(Z')_e / N.
+//
+// The partner N - k of a frequency k = k1 + N1 k2 (k1 the column bits below
+// b0, k2 the top pass's axis bits) is (N1 - k1) + N1 (N2 - 1 - k2) for k1 != 0
+// and N1 ((N2 - k2) mod N2) for k1 = 0.  A top-pass tile therefore holds H
+// columns and their H mirrors: tile cb takes columns cb H + 1 .. cb H + H and
+// N1 - (cb+1) H .. N1 - cb H - 1; in the last tile the duplicate column N1/2
+// of the second run is replaced by column 0.  Both self-mirrored columns
+// (0 and N1/2) thus sit in the last tile; every element finds its partner in
+// its own tile, through LDS.
+#include "passkit.hpp"
+
+namespace ldk {
+
+extern __shared__ unsigned char g_real_lds[];
+
+using namespace kit;
+
+namespace {
+
+template <typename T, int LOGE, int MODE, int LD, int ST, bool SRC_F32>
+__global__ __launch_bounds__(512) void k_real_top(PassArgs a, double *lam_out)
+{
+    using R = typename real_of<T>::type;
+    constexpr int E = 1 << LOGE;
+    T *lds = reinterpret_cast<T *>(g_real_lds);
+
+    const int A = a.g.a, logW = a.g.logW, b0 = a.g.b0;
+    const int mp = a.m;  // log2 N
+    const int64_t N = (int64_t)1 << mp;
+    const int64_t N1 = (int64_t)1 << b0;
+    const int N2 = 1 << A;
+    const int W = 1 << logW, H = W >> 1;
+    const int S = 1 << (A + logW);
+    const int Tn = S >> LOGE;
+    const int t = threadIdx.x;
+    const int64_t cb_count = N1 >> logW;
+    const int64_t cb = blockIdx.x % cb_count;
+    const int64_t row = blockIdx.x / cb_count;
+    const bool last = cb == cb_count - 1;
+
+    auto col_of = [&](int w) -> int64_t {
+        if (W == 1) return 0;
+        if (w < H) return cb * H + w + 1;
+        if (last && w == H) return 0;
+        return N1 - (cb + 1) * H + (w - H);
+    };
+    auto gidx = [&](int q) -> int64_t { return col_of(q & (W - 1)) + (int64_t)(q >> logW) * N1; };
+
+    const int G = (A + LOGE - 1) / LOGE;
+    const int rem = A - LOGE * (G - 1);
+    const int top_s = A - LOGE;
+
+    T v[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i)
+        v[i] = load_elem<T, LD, SRC_F32>(a.src, row * a.src_row + gidx(t + Tn * i), a.half);
+    if (b0 > 0) pass_twiddle_k1<T, E, LOGE, false>(v, t, (uint64_t)col_of(t & (W - 1)), logW, A, b0);
+
+    // ---- forward transform over the axis bits (low groups first)
+    if (G > 1) {
+        lds_write(v, lds, t, LOGE, logW + top_s, Tn);
+        __syncthreads();
+        int s = 0;
+        for (int gi = 0; gi < G - 1; ++gi) {
+            const int gs = gi == 0 ? rem : LOGE;
+            lds_read(v, lds, t, gs, logW + s, Tn);
+            group_twiddle<T, E, LOGE, false>(v, t, gs, s, logW, Tn);
+            reg_fwd<T, E, LOGE, false>(v, gs);
+            lds_write(v, lds, t, gs, logW + s, Tn);
+            __syncthreads();
+            s += gs;
+        }
+        lds_read(v, lds, t, LOGE, logW + top_s, Tn);
+    }
+    group_twiddle<T, E, LOGE, false>(v, t, LOGE, G > 1 ? top_s : 0, logW, Tn);
+    reg_fwd<T, E, LOGE, false>(v, LOGE);
+
+    // ---- real-spectrum step: every element reads its partner N - k
+    __syncthreads();  // all threads are done reading the forward groups
+    lds_write(v, lds, t, LOGE, logW + top_s, Tn);
+    __syncthreads();
+    const int64_t n = 2 * N;
+    const double *lam = a.lam ? a.lam + (row / a.nrhs) * n : nullptr;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const int q = t + Tn * i;
+        const int w = q & (W - 1), k2 = q >> logW;
+        const int64_t k1 = col_of(w);
+        int wp, k2p;
+        if (k1 == 0) {
+            wp = w;
+            k2p = (N2 - k2) & (N2 - 1);
+        } else if (k1 == N1 / 2) {
+            wp = w;
+            k2p = N2 - 1 - k2;
+        } else {
+            wp = 2 * H - 1 - w;
+            k2p = N2 - 1 - k2;
+        }
+        const T zm = lds[lds_idx(k2p * W + wp)];
+        const T zk = v[i];
+        const int64_t k = k1 + N1 * k2;
+        const T ev{(zk.re + zm.re) * (R)0.5, (zk.im - zm.im) * (R)0.5};
+        const T dv{(zk.re - zm.re) * (R)0.5, (zk.im + zm.im) * (R)0.5};
+        const T od{dv.im, -dv.re};  // -i (Z_k - conj Z_{N-k}) / 2
+        const T wk = tw_any<R>((uint64_t)k, mp + 1);
+        const T wo = cmul(wk, od);
+        const T yk{ev.re + wo.re, ev.im + wo.im};
+        const T ykn{ev.re - wo.re, ev.im - wo.im};
+        if constexpr (MODE == PM_FWD) {
+            lam_out[row * n + k] = (double)yk.re;
+            lam_out[row * n + k + N] = (double)ykn.re;
+        } else {
+            const double la = lam[k], lb = lam[(n - k) & (n - 1)];
+            const double lc = lam[k + N], ld = lam[(N - k) & (n - 1)];
+            double s1, s2;
+            if constexpr (MODE == PM_SOLVE) {
+                s1 = 0.5 * (a.scale / (la + a.sigma2) + a.scale / (lb + a.sigma2));
+                s2 = 0.5 * (a.scale / (lc + a.sigma2) + a.scale / (ld + a.sigma2));
+            } else {
+                s1 = 0.5 * a.scale * (la + lb);
+                s2 = 0.5 * a.scale * (lc + ld);
+            }
+            const T c1{yk.re * (R)s1, yk.im * (R)s1};
+            const T c2{ykn.re * (R)s2, ykn.im * (R)s2};
+            const T ep{(c1.re + c2.re) * (R)0.5, (c1.im + c2.im) * (R)0.5};
+            const T op = cmulc(T{(c1.re - c2.re) * (R)0.5, (c1.im - c2.im) * (R)0.5}, wk);
+            v[i] = T{ep.re - op.im, ep.im + op.re};
+        }
+    }
+    if constexpr (MODE == PM_FWD) return;
+
+    // ---- inverse transform over the axis bits (top group first)
+    reg_inv<T, E, LOGE>(v, LOGE);
+    group_twiddle<T, E, LOGE, true>(v, t, LOGE, G > 1 ? top_s : 0, logW, Tn);
+    if (G > 1) {
+        __syncthreads();  // partner reads are done before the tile is rewritten
+        lds_write(v, lds, t, LOGE, logW + top_s, Tn);
+        __syncthreads();
+        int s = top_s;
+        for (int gi = G - 2; gi >= 0; --gi) {
+            const int gs = gi == 0 ? rem : LOGE;
+            s -= gs;
+            lds_read(v, lds, t, gs, logW + s, Tn);
+            reg_inv<T, E, LOGE>(v, gs);
+            group_twiddle<T, E, LOGE, true>(v, t, gs, s, logW, Tn);
+            lds_write(v, lds, t, gs, logW + s, Tn);
+            __syncthreads();
+        }
+        lds_read(v, lds, t, LOGE, logW + top_s, Tn);
+    }
+    if (b0 > 0) pass_twiddle_k1<T, E, LOGE, true>(v, t, (uint64_t)col_of(t & (W - 1)), logW, A, b0);
+#pragma unroll
+    for (int i = 0; i < E; ++i)
+        store_elem<T, ST>(a.dst, row * a.dst_row + gidx(t + Tn * i), v[i], a.half);
+}
+
+template <typename T, int LOGE, int MODE, int LD, int ST, bool SRC_F32>
+int launch_rt(const PassArgs &a, double *lam_out, hipStream_t s)
+{
+    const int S = 1 << (a.g.a + a.g.logW);
+    const int threads = S >> LOGE;
+    const int64_t blocks = a.rows * ((int64_t)1 << (a.g.b0 - a.g.logW));
+    if (blocks > 0x7fffffff || threads > 512 || threads < 1) return LDK_ENOTSUP;
+    if (a.g.b0 + a.g.a != a.m) return LDK_EINVAL;  // must be the top pass
+    if (a.g.b0 > 0 && a.g.logW < 1) return LDK_ENOTSUP;  // mirror runs need W >= 2
+    const size_t lds = (size_t)(S + (S >> LDS_PAD_SHIFT)) * sizeof(T);
+    hipLaunchKernelGGL((k_real_top<T, LOGE, MODE, LD, ST, SRC_F32>), dim3((unsigned)blocks),
+                       dim3(threads), lds, s, a, lam_out);
+    LDK_LAUNCH_CHECK();
+    return LDK_OK;
+}
+
+template <typename T, int MODE, int LD, int ST, bool SRC_F32>
+int launch_rt_e(const PassArgs &a, double *lam_out, hipStream_t s)
+{
+    switch (a.g.logE) {
+    case 1: return launch_rt<T, 1, MODE, LD, ST, SRC_F32>(a, lam_out, s);
+    case 2: return launch_rt<T, 2, MODE, LD, ST, SRC_F32>(a, lam_out, s);
+    case 3: return launch_rt<T, 3, MODE, LD, ST, SRC_F32>(a, lam_out, s);
+    default: return LDK_ENOTSUP;
+    }
+}
+
+template <typename T, int MODE>
+int launch_rt_io(bool single, const PassArgs &a, double *lam_out, hipStream_t s)
+{
+    // one pass: packed real rows in and out; otherwise the complex work rows
+    if (single) return launch_rt_e<T, MODE, IO_PACKED, IO_PACKED, false>(a, lam_out, s);
+    return launch_rt_e<T, MODE, IO_SAME, IO_SAME, false>(a, lam_out, s);
+}
+
+}  // namespace
+
+int launch_real_top(int dtype, int mode, const PassArgs &a, double *lam_out, hipStream_t s,
+                    bool src_f32)
+{
+    const bool single = a.g.b0 == 0;
+    if (mode == PM_FWD) {
+        // eigenvalues: FP64 working type
+        if (dtype != LDK_F64 || !lam_out) return LDK_EINVAL;
+        if (src_f32) {
+            if (!single) return LDK_EINVAL;  // float sources only feed the first pass
+            return launch_rt_e<cplx<double>, PM_FWD, IO_PACKED, IO_SAME, true>(a, lam_out, s);
+        }
+        if (single) return launch_rt_e<cplx<double>, PM_FWD, IO_PACKED, IO_SAME, false>(a, lam_out, s);
+        return launch_rt_e<cplx<double>, PM_FWD, IO_SAME, IO_SAME, false>(a, lam_out, s);
+    }
+    if (mode != PM_SOLVE && mode != PM_MATVEC) return LDK_EINVAL;
+    if (!a.lam) return LDK_EINVAL;
+    if (dtype == LDK_F64) {
+        return mode == PM_SOLVE ? launch_rt_io<cplx<double>, PM_SOLVE>(single, a, nullptr, s)
+                                : launch_rt_io<cplx<double>, PM_MATVEC>(single, a, nullptr, s);
+    }
+    return mode == PM_SOLVE ? launch_rt_io<cplx<float>, PM_SOLVE>(single, a, nullptr, s)
+                            : launch_rt_io<cplx<float>, PM_MATVEC>(single, a, nullptr, s);
+}
+
+}  // namespace ldk

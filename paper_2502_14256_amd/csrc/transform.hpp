@@ -51,17 +51,33 @@ struct PassArgs {
     const double *lam;  // eigenvalues [rows / nrhs][2^m] (solve / matvec), FP64
     int nrhs;
     int global_tw;    // apply the inter-pass FFT twiddle (column passes)
+    int64_t half;     // packed real IO: offset of the imaginary half (N), elements
     double sigma2;
     double scale;     // solve: scale / (lambda + sigma2); matvec: scale * lambda;
                       // fwd / inv: multiplies the stored values
 };
 
+// Global IO of a pass (lattice only; nets are always real):
+enum PassIo {
+    PIO_SAME = 0,    // complex rows
+    PIO_REAL = 1,    // real rows: load as (x, 0) / store the real part
+    PIO_PACKED = 2,  // real rows of 2N carrying a complex row of N: z_e = y_e + i y_{e+N}
+};
+
 // kind: LDK_LATTICE (complex FFTBR) or LDK_DNET_B2 (real FWHT).
 // dtype: working precision of the pass.
-// src_real: rows of src are real (promoted to complex) -- lattice only.
-// dst_real: keep only the real part when storing -- lattice only.
+// ld, st: PassIo of the source and destination rows.
 // src_f32: src holds floats widened to the FP64 working type (PM_FWD only).
-int launch_pass(int kind, int dtype, int mode, bool src_real, bool dst_real, const PassArgs &a,
-                hipStream_t s, bool src_f32 = false);
+int launch_pass(int kind, int dtype, int mode, int ld, int st, const PassArgs &a, hipStream_t s,
+                bool src_f32 = false);
+
+// Real-input lattice top pass (see realfft.hip): forward transform of the
+// packed half-length row's top bit group, untangling of the real spectrum,
+// and either the eigenvalues (mode PM_FWD) or the filter by 1/(lambda+s2)
+// (PM_SOLVE) / lambda (PM_MATVEC) followed by the inverse top group.
+// a.lam_out receives the eigenvalues for PM_FWD.  With one pass (b0 = 0) the
+// source and destination rows are packed real rows.
+int launch_real_top(int dtype, int mode, const PassArgs &a, double *lam_out, hipStream_t s,
+                    bool src_f32 = false);
 
 }  // namespace ldk

@@ -147,8 +147,10 @@ def test_transform(orc, kind, m, dtype):
 # ---------------------------------------------------------------------------
 # a4-a6: eig, solve, matvec, logdet on shared inputs
 # ---------------------------------------------------------------------------
-ALG_CASES = [(0, 3), (1, 2), (3, 4), (6, 3), (10, 2), (11, 3), (12, 1), (13, 2), (16, 1),
-             (19, 1), (20, 1)]
+# lattice rows run as packed half-length complex rows: m = 2, 3 (one pass of
+# n/2), 12 / 13 (one or two passes of n/2 in FP64 / FP32), 21 (three passes)
+ALG_CASES = [(0, 3), (1, 2), (2, 3), (3, 4), (6, 3), (10, 2), (11, 3), (12, 1), (13, 2),
+             (14, 2), (16, 1), (19, 1), (20, 1), (21, 1)]
 
 
 def _kcol(orc, w):
@@ -191,10 +193,11 @@ def test_eig_solve_matvec_logdet(orc, kind, m, nrhs, dtype):
     assert np.all(np.abs(ld - ld_ref) <= 1e-12 * np.maximum(1.0, np.abs(ld_ref)) + 2**m * 1e-16)
 
 
-def test_solve_aliasing_and_logdet_nan(orc):
-    kind, m = "dnet", 14
+@pytest.mark.parametrize("kind,m", [("dnet", 14), ("lattice", 14), ("lattice", 9)])
+def test_solve_aliasing_and_logdet_nan(orc, kind, m):
     w = _net_or_lattice(kind, 3, m, 4, 1, nrhs=2)
-    w.update(alpha=np.array([2, 2, 3, 4], np.int32), gamma=np.ones(4), zeta=1.0)
+    alpha = [2, 2, 3, 4] if kind == "dnet" else [2, 2, 3, 1]
+    w.update(alpha=np.array(alpha, np.int32), gamma=np.ones(4), zeta=1.0)
     k1 = _kcol(orc, w)
     lam = orc.eig(kind, k1, precise=True)
     y = torch.from_numpy(w["y"].copy()).cuda()

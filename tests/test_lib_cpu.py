@@ -117,10 +117,12 @@ def test_workspace_sizes():
     ws = L.ldk_workspace_bytes
     assert ws(ldk.OP_TRANSFORM, ldk.DNET_B2, 4, 20, 0) == 0
     assert ws(ldk.OP_SOLVE, ldk.DNET_B2, 4, 20, 0) == 0
-    assert ws(ldk.OP_SOLVE, ldk.LATTICE, 4, 20, 0) == 4 * 2**20 * 16
-    assert ws(ldk.OP_SOLVE, ldk.LATTICE, 4, 20, 1) == 4 * 2**20 * 8
+    # real lattice rows of n run as packed complex rows of n/2
+    assert ws(ldk.OP_SOLVE, ldk.LATTICE, 4, 20, 0) == 4 * 2**19 * 16
+    assert ws(ldk.OP_SOLVE, ldk.LATTICE, 4, 20, 1) == 4 * 2**19 * 8
     assert ws(ldk.OP_SOLVE, ldk.LATTICE, 4, 10, 0) == 0  # one pass, no intermediate
     assert ws(ldk.OP_LOGDET, ldk.DNET_B2, 3, 20, 0) == 3 * 512 * 8
     assert ws(ldk.OP_EIG, 9, 1, 4, 0) == 0
     # eigenvalue transforms run in FP64 whatever the input dtype
-    assert ws(ldk.OP_EIG, ldk.LATTICE, 2, 20, 1) == 2 * 2**20 * 16
+    assert ws(ldk.OP_EIG, ldk.LATTICE, 2, 20, 1) == 2 * 2**19 * 16
+    assert ws(ldk.OP_EIG, ldk.LATTICE, 2, 12, 0) == 0  # n/2 = 2^11 fits one pass
