@@ -29,6 +29,11 @@ eig                    Sec. 5.4; closed-form Walsh / Fourier aliasing sums for
 solve, matvec, logdet  Sec. 5.4; dense Gram + Cholesky (numpy) at n <= 2^10
 update_double          Sec. 5.4 / eq. (ft_next_parts); equals the fresh
                        transform of length 2n
+MLL and gradient       standard GP objective in the eigenbasis of Sec. 5.4
+                       (the paper prints none); dense GP likelihood and
+                       trace-form gradient (numpy) at n <= 2^8; central
+                       differences; adjoint dot-product identity; a factor
+                       1 + gamma K that is exactly zero
 =====================  =====================================================
 """
 from __future__ import annotations
@@ -41,7 +46,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liborc.so")
-_SRC = ["orc_points.c", "orc_kernels.c", "orc_algebra.c"]
+_SRC = ["orc_points.c", "orc_kernels.c", "orc_algebra.c", "orc_mll.c"]
 
 LATTICE, DNET = 0, 1
 NATURAL, LINEAR, GRAY = 0, 1, 2
@@ -86,6 +91,9 @@ def lib():
             "orc_logdet": [i32, i32, P, f64, P], "orc_logdet_ld": [i32, i32, P, f64, P],
             "orc_update_double": [i32, i32, i32, P, P, P],
             "orc_eig_update_double": [i32, i32, i32, P, P, P],
+            "orc_mll": [i32, i32, i32, P, f64, P, P, P, P],
+            "orc_mll_adjoint": [i32, i32, i32, P, P],
+            "orc_kernel_grad": [i32, i32, i32, i64, P, P, P, P, f64, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -321,3 +329,62 @@ def fit_solve(w: dict, y=None, precise: bool = False) -> dict:
         out["c_ld"] = solve(w["kind"], lam_ld, w["sigma2"], y, precise=True)
         out["logdet_ld"] = logdet(lam_ld, w["sigma2"], precise=True)
     return out
+
+
+# ---------------------------------------------------------------------------
+# GP marginal likelihood and gradient (one response per replication)
+# ---------------------------------------------------------------------------
+
+def mll(kind, lam, sigma2: float, y):
+    """(L[R], g[R][n] = dL/dlambda, dL/dlog sigma2 [R]) for y: [R][n]."""
+    lam = _c(lam, np.float64)
+    y = _c(y, np.float64)
+    R, n = lam.shape
+    m = n.bit_length() - 1
+    L = np.empty(R)
+    g = np.empty_like(lam)
+    ds = np.empty(R)
+    _check(lib().orc_mll(kind_code(kind), R, m, _p(lam), float(sigma2), _p(y), _p(L), _p(g),
+                         _p(ds)), "mll")
+    return L, g, ds
+
+
+def mll_adjoint(kind, g) -> np.ndarray:
+    """dL/dk1 from dL/dlambda (adjoint of lambda = sqrt(n) FT(k1))."""
+    g = _c(g, np.float64)
+    R, n = g.shape
+    a = np.empty_like(g)
+    _check(lib().orc_mll_adjoint(kind_code(kind), R, n.bit_length() - 1, _p(g), _p(a)),
+           "mll_adjoint")
+    return a
+
+
+def kernel_grad(kind, pts, x0, alpha, gamma, zeta: float, a) -> np.ndarray:
+    """[R][d + 1]: sum_i a_i dk1_i/dlog gamma_j (j < d) and sum_i a_i k1_i (log zeta)."""
+    pts = _c(pts, np.uint64)
+    x0 = _c(x0, np.uint64)
+    R, n, d = pts.shape
+    a = _c(a, np.float64)
+    out = np.empty((R, d + 1))
+    _check(lib().orc_kernel_grad(kind_code(kind), R, d, n, _p(pts), _p(x0),
+                                 _p(_c(alpha, np.int32)), _p(_c(gamma, np.float64)),
+                                 float(zeta), _p(a), _p(out)), "kernel_grad")
+    return out
+
+
+def mll_grad(w: dict, gamma=None, zeta=None, sigma2=None, y=None) -> dict:
+    """Whole gradient step for a workload: L[R] and grad[R][d + 2] in
+    (log gamma_1..d, log zeta, log sigma2); replications share the parameters."""
+    gamma = w["gamma"] if gamma is None else gamma
+    zeta = w["zeta"] if zeta is None else zeta
+    sigma2 = w["sigma2"] if sigma2 is None else sigma2
+    y = w["y"][:, 0, :] if y is None else y
+    pts = points(w)
+    x0 = points(w, 0, 1)[:, 0, :]
+    k1 = kernel_column(w["kind"], pts, x0, w["alpha"], gamma, zeta)
+    lam, _ = eig(w["kind"], k1)
+    L, g, ds = mll(w["kind"], lam, sigma2, y)
+    a = mll_adjoint(w["kind"], g)
+    kg = kernel_grad(w["kind"], pts, x0, w["alpha"], gamma, zeta, a)
+    grad = np.concatenate([kg, ds[:, None]], axis=1)
+    return dict(L=L, grad=grad, k1=k1, lam=lam, g=g, a=a)

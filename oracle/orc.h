@@ -15,7 +15,7 @@
  *
  * Conventions: a coordinate is a uint64 u holding the first 64 base-2 digits
  * of x in [0,1), digit t (weight 2^-t, t = 1..64) at bit 64 - t; its FP64
- * value is (u >> 11) * 2^-53 (exact truncation).
+ * value is u * 2^-64 rounded to nearest.
  */
 #ifndef LDK_ORACLE_ORC_H
 #define LDK_ORACLE_ORC_H
@@ -63,6 +63,15 @@ int orc_update_double(int kind, int B, int m, const double *yt_old, const double
                       double *yt_full);
 int orc_eig_update_double(int kind, int R, int m, const double *lam_old,
                           const double *k1_new, double *lam_full);
+
+/* Gaussian-process log marginal likelihood in the eigenbasis of Sec. 5.4 and
+ * its gradient (one response per replication; y: [R][n], g: [R][n]). */
+int orc_mll(int kind, int R, int m, const double *lam, double sigma2, const double *y,
+            double *L, double *g, double *dlogs2);
+int orc_mll_adjoint(int kind, int R, int m, const double *g, double *a);
+int orc_kernel_grad(int kind, int R, int d, int64_t n, const uint64_t *pts, const uint64_t *x0,
+                    const int *alpha, const double *gamma, double zeta, const double *a,
+                    double *grad);
 
 /* Long-double twins (inputs/outputs double, arithmetic in long double). */
 int orc_eig_ld(int kind, int R, int m, const double *k1, double *lam);

@@ -25,6 +25,14 @@ muts = [
  ("oracle/orc_points.c", "acc += s_ts * col_bit(C[(size_t)j * m + k], s);", "acc += (int)((S[(size_t)j * 64 + s] >> (63 - t)) & 1u) * col_bit(C[(size_t)j * m + k], s);"),
  ("oracle/orc_points.c", "out[((size_t)r * cnt + ii) * d + j] = z ^ delta;", "out[((size_t)r * cnt + ii) * d + j] = z + delta;"),
  ("oracle/orc_points.c", "uint64_t orc_gray(uint64_t i) { return i ^ (i >> 1); }", "uint64_t orc_gray(uint64_t i) { return i ^ (i << 1); }"),
+ ("oracle/orc_mll.c", "const double gk = 0.5 * p / (s * s) - 0.5 / s;", "const double gk = 0.5 * p / (s * s) + 0.5 / s;"),
+ ("oracle/orc_mll.c", "L[r] = -0.5 * quad - 0.5 * logdet", "L[r] = -0.5 * quad + 0.5 * logdet"),
+ ("oracle/orc_mll.c", "dlogs2[r] = sigma2 * gsum;", "dlogs2[r] = gsum;"),
+ ("oracle/orc_mll.c", "rc = orc_transform(kind, lat ? -1 : 1, 1, m, in, out);", "rc = orc_transform(kind, 1, 1, m, in, out);"),
+ ("oracle/orc_mll.c", "a[(size_t)r * n + j] = rn * (lat", "a[(size_t)r * n + j] = (lat"),
+ ("oracle/orc_mll.c", "gr[j] += ai * zeta * t[j] * pre[j] * suf;", "gr[j] += ai * zeta * t[j] * suf;"),
+ ("oracle/orc_mll.c", "gr[d] += ai * zeta * p;", "gr[d] += ai * p;"),
+ ("oracle/orc_mll.c", "t[j] = gamma[j] * K;", "t[j] = K;"),
 ]
 res = []
 for f, a, b in muts:
