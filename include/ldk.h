@@ -196,6 +196,49 @@ int ldk_update_double(int kind, int B, int m, int dtype, const void *yt_old,
 int ldk_eig_update_double(int kind, int R, int m, int dtype, const double *lam_old,
                           const void *k1_new, double *lam_full, void *ws, ldk_stream stream);
 
+/* Gaussian-process log marginal likelihood in the eigenbasis (Sec. 5.4; the
+ * paper motivates fitting kernel parameters by it in Sec. 3 but prints no
+ * formula, so the standard GP objective is used).  One response per
+ * replication, yt = FT(y) orthonormal:
+ *   L[r]      = -1/2 sum_k |yt_k|^2 / (lambda_k + s2) - 1/2 sum_k log(lambda_k + s2)
+ *               - (n/2) log(2 pi),
+ *   g[r][k]   = dL/dlambda_k = 1/2 |yt_k|^2 / (lambda_k + s2)^2 - 1/2 / (lambda_k + s2),
+ *   dlogs2[r] = dL/dlog s2 = s2 sum_k g[r][k]   (dlogs2 may be NULL).
+ * lam = double[R][n] (ldk_eig); y = dtype[R][n]; L, dlogs2 = device double[R];
+ * g = device double[R][n].  The transform of y runs in dtype, everything
+ * after it (|yt|^2, g, the sums) in FP64, summed in a fixed order.  A row
+ * with some lambda_k + s2 <= 0 gives L = NaN.
+ * ws: ldk_workspace_bytes(LDK_OP_MLL, kind, R, m, dtype) bytes. */
+int ldk_mll(int kind, int R, int m, int dtype, const double *lam, double sigma2, const void *y,
+            double *L, double *g, double *dlogs2, void *ws, ldk_stream stream);
+
+/* dL/dk1 from g = dL/dlambda: the adjoint of lambda = sqrt(n) FT(k1) (Sec. 5.4),
+ *   net:     a = H g (unnormalised Walsh-Hadamard; H is symmetric),
+ *   lattice: a_j = Re sum_k g_k W^{-k R_m(j)}, W = exp(-2 pi i / n).
+ * g, a = device double[R][n] (may alias exactly).  FP64.
+ * ws: ldk_workspace_bytes(LDK_OP_MLL_ADJOINT, kind, R, m, LDK_F64) bytes
+ * (lattice with n > 2^12 only). */
+int ldk_mll_adjoint(int kind, int R, int m, const double *g, double *a, void *ws,
+                    ldk_stream stream);
+
+/* Gradient of sum_i a_i k1_i in the kernel parameters (chain rule through
+ * the product kernel of ldk_kernel_column; with a = dL/dk1 it gives the
+ * marginal-likelihood gradient):
+ *   grad[r][j] = sum_i a_ri zeta t_ij prod_{l != j} (1 + t_il),  t_ij = gamma_j K_j,
+ *                (d k1_i / d log gamma_j), j < d;
+ *   grad[r][d] = sum_i a_ri k1_ri  (d k1_i / d log zeta).
+ * Points, anchors, window and kernel as for ldk_kernel_column (the same
+ * restrictions apply); dtype = precision of the factor evaluation (the
+ * products of the other factors are formed without dividing by a factor
+ * that is exactly zero); the sums are FP64, in a fixed order.
+ * a = device double[R][n_max - n_min]; grad = device double[R][d + 1].
+ * ws: ldk_kernel_grad_workspace_bytes(R, d, n_min, n_max, pts != NULL). */
+int ldk_kernel_grad(const ldk_kernel *k, const ldk_pointset *ps, const uint64_t *pts,
+                    const uint64_t *x0, int64_t n_min, int64_t n_max, int dtype, const double *a,
+                    double *grad, void *ws, ldk_stream stream);
+size_t ldk_kernel_grad_workspace_bytes(int R, int d, int64_t n_min, int64_t n_max,
+                                       int points_given);
+
 typedef enum {
     LDK_OP_TRANSFORM = 0,
     LDK_OP_EIG = 1,
@@ -203,7 +246,9 @@ typedef enum {
     LDK_OP_MATVEC = 3,
     LDK_OP_LOGDET = 4,
     LDK_OP_UPDATE_DOUBLE = 5,
-    LDK_OP_EIG_UPDATE_DOUBLE = 6
+    LDK_OP_EIG_UPDATE_DOUBLE = 6,
+    LDK_OP_MLL = 7,
+    LDK_OP_MLL_ADJOINT = 8
 } ldk_op;
 
 /* Workspace bytes needed by `op` for B rows (or R * nrhs rows) of 2^m. */

@@ -23,12 +23,14 @@ LIB_PATH = os.path.join(_HERE, "libldk.so")
 LATTICE, DNET_B2 = 0, 1
 NATURAL, LINEAR, GRAY = 0, 1, 2
 F64, F32 = 0, 1
-OP_TRANSFORM, OP_EIG, OP_SOLVE, OP_MATVEC, OP_LOGDET, OP_UPDATE_DOUBLE, OP_EIG_UPDATE_DOUBLE = range(7)
+(OP_TRANSFORM, OP_EIG, OP_SOLVE, OP_MATVEC, OP_LOGDET, OP_UPDATE_DOUBLE, OP_EIG_UPDATE_DOUBLE,
+ OP_MLL, OP_MLL_ADJOINT) = range(9)
 
 EXPORTS = [
     "ldk_init", "ldk_gen_points", "ldk_kernel_column", "ldk_transform", "ldk_eig", "ldk_solve",
     "ldk_matvec", "ldk_logdet", "ldk_update_double", "ldk_eig_update_double",
     "ldk_workspace_bytes", "ldk_strerror", "ldk_last_hip_error", "ldk_version",
+    "ldk_mll", "ldk_mll_adjoint", "ldk_kernel_grad", "ldk_kernel_grad_workspace_bytes",
 ]
 
 
@@ -73,6 +75,10 @@ def lib():
             "ldk_strerror": ([i32], C.c_char_p),
             "ldk_last_hip_error": ([], i32),
             "ldk_version": ([], C.c_char_p),
+            "ldk_mll": ([i32, i32, i32, i32, P, f64, P, P, P, P, P, P], i32),
+            "ldk_mll_adjoint": ([i32, i32, i32, P, P, P, P], i32),
+            "ldk_kernel_grad": ([P, P, P, P, i64, i64, i32, P, P, P, P], i32),
+            "ldk_kernel_grad_workspace_bytes": ([i32, i32, i64, i64, i32], C.c_size_t),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -322,4 +328,68 @@ def eig_update_double(kind, lam_old: torch.Tensor, k1_new: torch.Tensor, out=Non
     ws = _workspace(OP_EIG_UPDATE_DOUBLE, kd, R, m, dt, lam_old.device)
     _check(lib().ldk_eig_update_double(kd, R, m, dt, _ptr(lam_old), _ptr(k1_new), _ptr(out),
                                        _ptr(ws), _stream()), "ldk_eig_update_double")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# GP marginal likelihood and its gradient (one response per replication)
+# ---------------------------------------------------------------------------
+
+def mll(kind, lam: torch.Tensor, sigma2: float, y: torch.Tensor, out_g=None, ws=None):
+    """(L[R], g[R][n] = dL/dlambda, dL/dlog sigma2 [R]) for y of shape [R][n]."""
+    kd = _kind(kind)
+    _need_f64(lam, "lam")
+    _need(y, "y")
+    dt = _dtype_code(y.dtype)
+    R, n = y.shape
+    if tuple(lam.shape) != (R, n):
+        raise LdkError("lam and y must both be [R][n]")
+    m = _m_of(n)
+    dev = y.device
+    L = torch.empty(R, dtype=torch.float64, device=dev)
+    ds = torch.empty(R, dtype=torch.float64, device=dev)
+    g = torch.empty((R, n), dtype=torch.float64, device=dev) if out_g is None else out_g
+    _need_f64(g, "g")
+    if ws is None:
+        ws = _workspace(OP_MLL, kd, R, m, dt, dev)
+    _check(lib().ldk_mll(kd, R, m, dt, _ptr(lam), float(sigma2), _ptr(y), _ptr(L), _ptr(g),
+                         _ptr(ds), _ptr(ws), _stream()), "ldk_mll")
+    return L, g, ds
+
+
+def mll_adjoint(kind, g: torch.Tensor, out=None, ws=None):
+    """dL/dk1 from dL/dlambda (adjoint of lambda = sqrt(n) FT(k1)), FP64."""
+    kd = _kind(kind)
+    _need_f64(g, "g")
+    R, n = g.shape
+    m = _m_of(n)
+    out = torch.empty_like(g) if out is None else out
+    _need_f64(out, "out")
+    if ws is None:
+        ws = _workspace(OP_MLL_ADJOINT, kd, R, m, F64, g.device)
+    _check(lib().ldk_mll_adjoint(kd, R, m, _ptr(g), _ptr(out), _ptr(ws), _stream()),
+           "ldk_mll_adjoint")
+    return out
+
+
+def kernel_grad(k: Kernel, ps: PointSet, n_min: int, n_max: int, a: torch.Tensor, pts=None,
+                x0=None, dtype=torch.float64, out=None, ws=None):
+    """[R][d + 1]: sum_i a_i dk1_i/dlog gamma_j (j < d) and sum_i a_i k1_i (log zeta)."""
+    dt = _dtype_code(dtype)
+    _need_f64(a, "a")
+    dev = ps.gen.device
+    if out is None:
+        out = torch.empty((ps.R, ps.d + 1), dtype=torch.float64, device=dev)
+    _need_f64(out, "out")
+    if pts is not None:
+        _need(pts, "pts")
+    if x0 is not None:
+        _need(x0, "x0")
+    if ws is None:
+        nb = lib().ldk_kernel_grad_workspace_bytes(ps.R, ps.d, n_min, n_max,
+                                                   int(pts is not None))
+        ws = torch.empty(max(int(nb), 1), dtype=torch.uint8, device=dev)
+    _check(lib().ldk_kernel_grad(C.byref(k._c()), C.byref(ps._c()), _ptr(pts), _ptr(x0), n_min,
+                                 n_max, dt, _ptr(a), _ptr(out), _ptr(ws), _stream()),
+           "ldk_kernel_grad")
     return out

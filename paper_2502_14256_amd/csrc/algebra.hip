@@ -347,6 +347,7 @@ int real_apply(int dtype, int mode, int m, int64_t rows, int nrhs, const double 
 
 size_t ws_bytes(int op, int kind, int64_t B, int m, int dtype)
 {
+    if (op == LDK_OP_MLL || op == LDK_OP_MLL_ADJOINT) return mll_ws_bytes(op, kind, B, m, dtype);
     if (m == 0) return op == LDK_OP_LOGDET ? (size_t)B * sizeof(double) : 0;
     const bool lat = kind == LDK_LATTICE;
     const int P = make_plan(m, log_tile_for(kind, dtype)).P;

@@ -232,9 +232,10 @@ __device__ __forceinline__ void lds_write(const T (&v)[E], T *lds, int t, int gs
 //   IO_SAME    elements of the working type;
 //   IO_REAL    real array: load as (x, 0), store the real part;
 //   IO_PACKED  real array of 2 N per row holding a complex row of N as
-//              (re at e, im at e + N): z_e = y_e + i y_{e+N}.
+//              (re at e, im at e + N): z_e = y_e + i y_{e+N};
+//   IO_POWER   (store only) FP64 array receiving |x|^2, squared in FP64.
 // SRC_F32: the source holds floats widened to the FP64 working type.
-enum IoMode { IO_SAME = 0, IO_REAL = 1, IO_PACKED = 2 };
+enum IoMode { IO_SAME = 0, IO_REAL = 1, IO_PACKED = 2, IO_POWER = 3 };
 
 template <typename T, int LD, bool SRC_F32>
 __device__ __forceinline__ T load_elem(const void *p, int64_t idx, int64_t half)
@@ -256,7 +257,12 @@ __device__ __forceinline__ T load_elem(const void *p, int64_t idx, int64_t half)
 template <typename T, int ST>
 __device__ __forceinline__ void store_elem(void *p, int64_t idx, T v, int64_t half)
 {
-    if constexpr (std::is_floating_point<T>::value) {
+    if constexpr (ST == IO_POWER) {
+        if constexpr (std::is_floating_point<T>::value)
+            static_cast<double *>(p)[idx] = (double)v * (double)v;
+        else
+            static_cast<double *>(p)[idx] = (double)v.re * (double)v.re + (double)v.im * (double)v.im;
+    } else if constexpr (std::is_floating_point<T>::value) {
         static_cast<T *>(p)[idx] = v;
     } else {
         using R = typename real_of<T>::type;

@@ -23,6 +23,12 @@
 // of the second run is replaced by column 0.  Both self-mirrored columns
 // (0 and N1/2) thus sit in the last tile; every element finds its partner in
 // its own tile, through LDS.
+//
+// Two more modes serve the marginal likelihood: PM_POWER writes |Y_k|^2 (the
+// power spectrum, FP64) instead of Re Y_k, and PM_ADJ is the inverse half
+// alone: it reads a real spectrum g from a.lam, forms C = scale (g_k +
+// g_{n-k}) / 2 (so the result is Re sum_k g_k W_n^{-k R(j)} for scale 2),
+// re-packs it like the solve and runs the inverse top group.
 #include "passkit.hpp"
 
 namespace ldk {
@@ -67,34 +73,37 @@ __global__ __launch_bounds__(512) void k_real_top(PassArgs a, double *lam_out)
     const int top_s = A - LOGE;
 
     T v[E];
+    if constexpr (MODE != PM_ADJ) {
 #pragma unroll
-    for (int i = 0; i < E; ++i)
-        v[i] = load_elem<T, LD, SRC_F32>(a.src, row * a.src_row + gidx(t + Tn * i), a.half);
-    if (b0 > 0) pass_twiddle_k1<T, E, LOGE, false>(v, t, (uint64_t)col_of(t & (W - 1)), logW, A, b0);
+        for (int i = 0; i < E; ++i)
+            v[i] = load_elem<T, LD, SRC_F32>(a.src, row * a.src_row + gidx(t + Tn * i), a.half);
+        if (b0 > 0)
+            pass_twiddle_k1<T, E, LOGE, false>(v, t, (uint64_t)col_of(t & (W - 1)), logW, A, b0);
 
-    // ---- forward transform over the axis bits (low groups first)
-    if (G > 1) {
+        // ---- forward transform over the axis bits (low groups first)
+        if (G > 1) {
+            lds_write(v, lds, t, LOGE, logW + top_s, Tn);
+            __syncthreads();
+            int s = 0;
+            for (int gi = 0; gi < G - 1; ++gi) {
+                const int gs = gi == 0 ? rem : LOGE;
+                lds_read(v, lds, t, gs, logW + s, Tn);
+                group_twiddle<T, E, LOGE, false>(v, t, gs, s, logW, Tn);
+                reg_fwd<T, E, LOGE, false>(v, gs);
+                lds_write(v, lds, t, gs, logW + s, Tn);
+                __syncthreads();
+                s += gs;
+            }
+            lds_read(v, lds, t, LOGE, logW + top_s, Tn);
+        }
+        group_twiddle<T, E, LOGE, false>(v, t, LOGE, G > 1 ? top_s : 0, logW, Tn);
+        reg_fwd<T, E, LOGE, false>(v, LOGE);
+
+        // ---- real-spectrum step: every element reads its partner N - k
+        __syncthreads();  // all threads are done reading the forward groups
         lds_write(v, lds, t, LOGE, logW + top_s, Tn);
         __syncthreads();
-        int s = 0;
-        for (int gi = 0; gi < G - 1; ++gi) {
-            const int gs = gi == 0 ? rem : LOGE;
-            lds_read(v, lds, t, gs, logW + s, Tn);
-            group_twiddle<T, E, LOGE, false>(v, t, gs, s, logW, Tn);
-            reg_fwd<T, E, LOGE, false>(v, gs);
-            lds_write(v, lds, t, gs, logW + s, Tn);
-            __syncthreads();
-            s += gs;
-        }
-        lds_read(v, lds, t, LOGE, logW + top_s, Tn);
     }
-    group_twiddle<T, E, LOGE, false>(v, t, LOGE, G > 1 ? top_s : 0, logW, Tn);
-    reg_fwd<T, E, LOGE, false>(v, LOGE);
-
-    // ---- real-spectrum step: every element reads its partner N - k
-    __syncthreads();  // all threads are done reading the forward groups
-    lds_write(v, lds, t, LOGE, logW + top_s, Tn);
-    __syncthreads();
     const int64_t n = 2 * N;
     const double *lam = a.lam ? a.lam + (row / a.nrhs) * n : nullptr;
 #pragma unroll
@@ -102,6 +111,17 @@ __global__ __launch_bounds__(512) void k_real_top(PassArgs a, double *lam_out)
         const int q = t + Tn * i;
         const int w = q & (W - 1), k2 = q >> logW;
         const int64_t k1 = col_of(w);
+        if constexpr (MODE == PM_ADJ) {
+            // real spectrum g in a.lam: C = scale (g_k + g_{n-k}) / 2 at k and k + N
+            const int64_t k = k1 + N1 * k2;
+            const T wk = tw_any<R>((uint64_t)k, mp + 1);
+            const double s1 = 0.5 * a.scale * (lam[k] + lam[(n - k) & (n - 1)]);
+            const double s2 = 0.5 * a.scale * (lam[k + N] + lam[(N - k) & (n - 1)]);
+            const R ep = (R)(0.5 * (s1 + s2));
+            const T op = cmulc(T{(R)(0.5 * (s1 - s2)), (R)0}, wk);
+            v[i] = T{ep - op.im, op.re};
+            continue;
+        }
         int wp, k2p;
         if (k1 == 0) {
             wp = w;
@@ -126,6 +146,10 @@ __global__ __launch_bounds__(512) void k_real_top(PassArgs a, double *lam_out)
         if constexpr (MODE == PM_FWD) {
             lam_out[row * n + k] = (double)yk.re;
             lam_out[row * n + k + N] = (double)ykn.re;
+        } else if constexpr (MODE == PM_POWER) {
+            lam_out[row * n + k] = (double)yk.re * (double)yk.re + (double)yk.im * (double)yk.im;
+            lam_out[row * n + k + N] =
+                (double)ykn.re * (double)ykn.re + (double)ykn.im * (double)ykn.im;
         } else {
             const double la = lam[k], lb = lam[(n - k) & (n - 1)];
             const double lc = lam[k + N], ld = lam[(N - k) & (n - 1)];
@@ -144,13 +168,13 @@ __global__ __launch_bounds__(512) void k_real_top(PassArgs a, double *lam_out)
             v[i] = T{ep.re - op.im, ep.im + op.re};
         }
     }
-    if constexpr (MODE == PM_FWD) return;
+    if constexpr (MODE == PM_FWD || MODE == PM_POWER) return;
 
     // ---- inverse transform over the axis bits (top group first)
     reg_inv<T, E, LOGE>(v, LOGE);
     group_twiddle<T, E, LOGE, true>(v, t, LOGE, G > 1 ? top_s : 0, logW, Tn);
     if (G > 1) {
-        __syncthreads();  // partner reads are done before the tile is rewritten
+        if constexpr (MODE != PM_ADJ) __syncthreads();  // partner reads are done
         lds_write(v, lds, t, LOGE, logW + top_s, Tn);
         __syncthreads();
         int s = top_s;
@@ -222,8 +246,24 @@ int launch_real_top(int dtype, int mode, const PassArgs &a, double *lam_out, hip
         if (single) return launch_rt_e<cplx<double>, PM_FWD, IO_PACKED, IO_SAME, false>(a, lam_out, s);
         return launch_rt_e<cplx<double>, PM_FWD, IO_SAME, IO_SAME, false>(a, lam_out, s);
     }
-    if (mode != PM_SOLVE && mode != PM_MATVEC) return LDK_EINVAL;
+    if (src_f32) return LDK_EINVAL;
+    if (mode == PM_POWER) {
+        if (!lam_out) return LDK_EINVAL;
+        if (dtype == LDK_F64) {
+            if (single) return launch_rt_e<cplx<double>, PM_POWER, IO_PACKED, IO_SAME, false>(a, lam_out, s);
+            return launch_rt_e<cplx<double>, PM_POWER, IO_SAME, IO_SAME, false>(a, lam_out, s);
+        }
+        if (single) return launch_rt_e<cplx<float>, PM_POWER, IO_PACKED, IO_SAME, false>(a, lam_out, s);
+        return launch_rt_e<cplx<float>, PM_POWER, IO_SAME, IO_SAME, false>(a, lam_out, s);
+    }
     if (!a.lam) return LDK_EINVAL;
+    if (mode == PM_ADJ) {
+        // adjoint of the eigenvalue map: FP64, real spectrum in a.lam
+        if (dtype != LDK_F64) return LDK_EINVAL;
+        if (single) return launch_rt_e<cplx<double>, PM_ADJ, IO_SAME, IO_PACKED, false>(a, nullptr, s);
+        return launch_rt_e<cplx<double>, PM_ADJ, IO_SAME, IO_SAME, false>(a, nullptr, s);
+    }
+    if (mode != PM_SOLVE && mode != PM_MATVEC) return LDK_EINVAL;
     if (dtype == LDK_F64) {
         return mode == PM_SOLVE ? launch_rt_io<cplx<double>, PM_SOLVE>(single, a, nullptr, s)
                                 : launch_rt_io<cplx<double>, PM_MATVEC>(single, a, nullptr, s);

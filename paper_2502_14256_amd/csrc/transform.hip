@@ -131,10 +131,12 @@ int launch_t(int ld, int st, const PassArgs &a, hipStream_t s)
     const dim3 grid((unsigned)blocks), block(threads);
 #define LDK_PASS(LD_, ST_) hipLaunchKernelGGL((k_pass<T, LOGE, MODE, LD_, ST_, SRC_F32>), grid, block, lds, s, a)
     if constexpr (std::is_floating_point<T>::value) {
-        if (ld != IO_SAME || st != IO_SAME) return LDK_ENOTSUP;
-        LDK_PASS(IO_SAME, IO_SAME);
+        if (ld != IO_SAME) return LDK_ENOTSUP;
+        if (st == IO_SAME) LDK_PASS(IO_SAME, IO_SAME);
+        else if (MODE == PM_FWD && st == IO_POWER) LDK_PASS(IO_SAME, IO_POWER);
+        else return LDK_ENOTSUP;
     } else if constexpr (MODE == PM_FWD) {
-        if (st == IO_PACKED) return LDK_ENOTSUP;
+        if (st == IO_PACKED || st == IO_POWER) return LDK_ENOTSUP;
         if (ld == IO_SAME && st == IO_SAME) LDK_PASS(IO_SAME, IO_SAME);
         else if (ld == IO_SAME) LDK_PASS(IO_SAME, IO_REAL);
         else if (ld == IO_REAL && st == IO_SAME) LDK_PASS(IO_REAL, IO_SAME);
@@ -142,7 +144,7 @@ int launch_t(int ld, int st, const PassArgs &a, hipStream_t s)
         else if (st == IO_SAME) LDK_PASS(IO_PACKED, IO_SAME);
         else return LDK_ENOTSUP;
     } else if constexpr (MODE == PM_INV) {
-        if (ld != IO_SAME) return LDK_ENOTSUP;
+        if (ld != IO_SAME || st == IO_POWER) return LDK_ENOTSUP;
         if (st == IO_SAME) LDK_PASS(IO_SAME, IO_SAME);
         else if (st == IO_REAL) LDK_PASS(IO_SAME, IO_REAL);
         else LDK_PASS(IO_SAME, IO_PACKED);
@@ -226,8 +228,8 @@ int launch_pass(int kind, int dtype, int mode, int ld, int st, const PassArgs &a
         return launch_e<cplx<double>, PM_FWD, true>(ld, st, a, s);
     }
     if (kind == LDK_DNET_B2) {
-        if (dtype == LDK_F64) return launch_m<double>(mode, IO_SAME, IO_SAME, a, s);
-        return launch_m<float>(mode, IO_SAME, IO_SAME, a, s);
+        if (dtype == LDK_F64) return launch_m<double>(mode, ld, st, a, s);
+        return launch_m<float>(mode, ld, st, a, s);
     }
     if (dtype == LDK_F64) return launch_m<cplx<double>>(mode, ld, st, a, s);
     return launch_m<cplx<float>>(mode, ld, st, a, s);

@@ -21,7 +21,8 @@
 
 namespace ldk {
 
-enum PassMode { PM_FWD = 0, PM_INV = 1, PM_SOLVE = 2, PM_MATVEC = 3 };
+// PM_POWER and PM_ADJ exist only in the real-input lattice top pass.
+enum PassMode { PM_FWD = 0, PM_INV = 1, PM_SOLVE = 2, PM_MATVEC = 3, PM_POWER = 4, PM_ADJ = 5 };
 
 struct PassGeom {
     int b0;    // index bit where this pass's axis starts
@@ -62,6 +63,7 @@ enum PassIo {
     PIO_SAME = 0,    // complex rows
     PIO_REAL = 1,    // real rows: load as (x, 0) / store the real part
     PIO_PACKED = 2,  // real rows of 2N carrying a complex row of N: z_e = y_e + i y_{e+N}
+    PIO_POWER = 3,   // store only: FP64 rows receiving |x|^2 (forward passes)
 };
 
 // kind: LDK_LATTICE (complex FFTBR) or LDK_DNET_B2 (real FWHT).
@@ -75,9 +77,14 @@ int launch_pass(int kind, int dtype, int mode, int ld, int st, const PassArgs &a
 // packed half-length row's top bit group, untangling of the real spectrum,
 // and either the eigenvalues (mode PM_FWD) or the filter by 1/(lambda+s2)
 // (PM_SOLVE) / lambda (PM_MATVEC) followed by the inverse top group.
-// a.lam_out receives the eigenvalues for PM_FWD.  With one pass (b0 = 0) the
-// source and destination rows are packed real rows.
+// lam_out receives the eigenvalues for PM_FWD and the power spectrum |Y|^2
+// for PM_POWER (FP64 rows of 2N).  PM_ADJ reads a real spectrum from a.lam
+// and runs only the inverse half.  With one pass (b0 = 0) the source and
+// destination rows are packed real rows.
 int launch_real_top(int dtype, int mode, const PassArgs &a, double *lam_out, hipStream_t s,
                     bool src_f32 = false);
+
+// Workspace bytes of LDK_OP_MLL / LDK_OP_MLL_ADJOINT (mll.hip).
+size_t mll_ws_bytes(int op, int kind, int64_t R, int m, int dtype);
 
 }  // namespace ldk

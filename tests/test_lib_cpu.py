@@ -126,3 +126,60 @@ def test_workspace_sizes():
     # eigenvalue transforms run in FP64 whatever the input dtype
     assert ws(ldk.OP_EIG, ldk.LATTICE, 2, 20, 1) == 2 * 2**19 * 16
     assert ws(ldk.OP_EIG, ldk.LATTICE, 2, 12, 0) == 0  # n/2 = 2^11 fits one pass
+
+
+def test_likelihood_entry_points_reject_bad_arguments():
+    L = ldk.lib()
+    # ldk_mll(kind, R, m, dtype, lam, sigma2, y, L, g, dlogs2, ws, stream)
+    assert L.ldk_mll(7, 1, 4, 0, FAKE, 0.1, FAKE, FAKE, FAKE, None, FAKE, None) == -1
+    assert L.ldk_mll(ldk.LATTICE, 1, 4, 5, FAKE, 0.1, FAKE, FAKE, FAKE, None, FAKE, None) == -1
+    assert L.ldk_mll(ldk.LATTICE, 1, 27, 0, FAKE, 0.1, FAKE, FAKE, FAKE, None, FAKE, None) == -1
+    assert L.ldk_mll(ldk.DNET_B2, 1, 4, 0, FAKE, -1.0, FAKE, FAKE, FAKE, None, FAKE, None) == -1
+    assert L.ldk_mll(ldk.DNET_B2, 1, 4, 0, FAKE, float("nan"), FAKE, FAKE, FAKE, None, FAKE,
+                     None) == -1
+    assert L.ldk_mll(ldk.DNET_B2, 1, 4, 0, FAKE, 0.1, FAKE, FAKE, FAKE, None, None, None) == -1
+    assert L.ldk_mll(ldk.DNET_B2, 1, 4, 0, None, 0.1, FAKE, FAKE, FAKE, None, FAKE, None) == -1
+    assert L.ldk_mll(ldk.DNET_B2, 0, 4, 0, None, 0.1, None, None, None, None, None, None) == 0
+    # ldk_mll_adjoint(kind, R, m, g, a, ws, stream)
+    assert L.ldk_mll_adjoint(7, 1, 4, FAKE, FAKE, None, None) == -1
+    assert L.ldk_mll_adjoint(ldk.LATTICE, 1, 4, None, FAKE, None, None) == -1
+    assert L.ldk_mll_adjoint(ldk.LATTICE, 1, 20, FAKE, FAKE, None, None) == -1  # needs ws
+    assert L.ldk_mll_adjoint(ldk.LATTICE, 0, 20, None, None, None, None) == 0
+    # ldk_kernel_grad: the kernel-column validation, then a, grad and ws
+    keep, a4 = _alpha(2, 2, 2, 2)
+    k = ldk._Kernel(ldk.LATTICE, 4, a4, FAKE, 1.0)  # kind mismatch with the net point set
+    assert L.ldk_kernel_grad(C.byref(k), C.byref(_ps()), None, None, 0, 4, 0, FAKE, FAKE, FAKE,
+                             None) == -1
+    k = ldk._Kernel(ldk.DNET_B2, 4, a4, FAKE, 1.0)
+    assert L.ldk_kernel_grad(C.byref(k), C.byref(_ps()), None, None, 0, 4, 0, FAKE, None, FAKE,
+                             None) == -1  # grad missing
+    assert L.ldk_kernel_grad(C.byref(k), C.byref(_ps()), None, None, 0, 4, 0, None, FAKE, FAKE,
+                             None) == -1  # a missing
+    assert L.ldk_kernel_grad(C.byref(k), C.byref(_ps()), None, None, 0, 4, 0, FAKE, FAKE, None,
+                             None) == -1  # ws missing
+    assert L.ldk_kernel_grad(C.byref(k), C.byref(_ps()), None, None, 0, 2**10 + 1, 0, FAKE, FAKE,
+                             FAKE, None) == -1  # beyond 2^m_max
+    keep5, bad = _alpha(1, 2, 5, 1)
+    k = ldk._Kernel(ldk.DNET_B2, 4, bad, FAKE, 1.0)
+    assert L.ldk_kernel_grad(C.byref(k), C.byref(_ps()), None, None, 0, 4, 0, FAKE, FAKE, FAKE,
+                             None) == -1
+
+
+def test_likelihood_workspace_sizes():
+    L = ldk.lib()
+    ws = L.ldk_workspace_bytes
+    # partial sums (3 doubles per 2048 entries, 256-byte aligned) + transform scratch
+    assert ws(ldk.OP_MLL, ldk.DNET_B2, 2, 10, 0) == 256  # one pass: partials only
+    assert ws(ldk.OP_MLL, ldk.DNET_B2, 2, 20, 0) == 2 * 512 * 3 * 8 + 2 * 2**20 * 8
+    assert ws(ldk.OP_MLL, ldk.LATTICE, 2, 20, 1) == 2 * 512 * 3 * 8 + 2 * 2**19 * 8
+    assert ws(ldk.OP_MLL_ADJOINT, ldk.DNET_B2, 2, 20, 0) == 0
+    assert ws(ldk.OP_MLL_ADJOINT, ldk.LATTICE, 2, 20, 0) == 2 * 2**19 * 16
+    assert ws(ldk.OP_MLL_ADJOINT, ldk.LATTICE, 2, 12, 0) == 0
+    g = L.ldk_kernel_grad_workspace_bytes
+    # [R][tiles of 2048][4 waves][d + 1] doubles
+    assert g(3, 7, 0, 4096, 0) == 3 * 2 * 4 * 8 * 8
+    assert g(3, 7, 100, 4096, 0) == 3 * 2 * 4 * 8 * 8      # tiles aligned to 2048
+    assert g(3, 7, 100, 4097, 1) == 3 * 2 * 4 * 8 * 8      # tiles from n_min
+    assert g(3, 7, 100, 4197, 1) == 3 * 3 * 4 * 8 * 8
+    assert g(0, 7, 0, 4096, 0) == 0
+    assert ws(ldk.OP_MLL, ldk.LATTICE, 3, 0, 0) == 256  # n = 1 still sums
