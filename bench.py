@@ -8,7 +8,9 @@ The metric counts one Gram solve (K + sigma^2 I)^-1 y per step.
 
 Printed: one JSON line with the metric, per-op timings (HIP events on the
 library's stream), the roofline of the dominant kernel, the solve's own
-roofline, and the CPU oracle timed on the host as a baseline.
+roofline, the marginal-likelihood gradient workload (64 replications of a
+net with n = 2^16, d = 64) under "grad", and the CPU oracle timed on the host
+as a baseline.
 """
 from __future__ import annotations
 
@@ -35,6 +37,8 @@ def parse():
                    help="arithmetic of the per-solve data (y, c, solve transforms); the first "
                         "column and the eigenvalues stay FP64")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-grad", action="store_true",
+                   help="skip the marginal-likelihood gradient workload")
     p.add_argument("--cpu-seconds", type=float, default=10.0)
     p.add_argument("--copy-probe", action="store_true",
                    help="also run a plain device copy of known size (counter calibration)")
@@ -87,25 +91,12 @@ def main():
 
     ops = ["gen_points", "kernel_column", "eig", "solve", "logdet"]
 
-    def step(evs=None):
-        stream = torch.cuda.current_stream()
-        if evs is not None:
-            evs[0].record(stream)
+    def step():
         ldk.gen_points(ps, 0, n, out=pts)
-        if evs is not None:
-            evs[1].record(stream)
         ldk.kernel_column(kern, ps, 0, n, dtype=torch.float64, out=k1)
-        if evs is not None:
-            evs[2].record(stream)
         ldk.eig("lattice", k1, out=lam, ws=ws_eig)
-        if evs is not None:
-            evs[3].record(stream)
         ldk.solve("lattice", lam, w["sigma2"], y, out=c, ws=ws_solve)
-        if evs is not None:
-            evs[4].record(stream)
         ldk.logdet(lam, w["sigma2"], out=ld, ws=ws_ld)
-        if evs is not None:
-            evs[5].record(stream)
 
     for _ in range(args.warmup):
         step()
@@ -140,15 +131,16 @@ def main():
     wall = time.perf_counter() - t0
     total_ms = start.elapsed_time(stop)
 
-    # timed region 2: the same step launched op by op, an event between ops
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(ops) + 1)] for _ in range(K)]
-    torch.cuda.synchronize()
-    for s_ in range(K):
-        step(evs[s_])
-    torch.cuda.synchronize()
-    per_op = {op: float(np.mean([evs[s_][i].elapsed_time(evs[s_][i + 1]) for s_ in range(K)]))
-              for i, op in enumerate(ops)}
-
+    # timed region 2: each op alone, captured in its own graph and replayed K
+    # times back to back (device time per launch, no host gaps)
+    op_calls = {
+        "gen_points": lambda: ldk.gen_points(ps, 0, n, out=pts),
+        "kernel_column": lambda: ldk.kernel_column(kern, ps, 0, n, dtype=torch.float64, out=k1),
+        "eig": lambda: ldk.eig("lattice", k1, out=lam, ws=ws_eig),
+        "solve": lambda: ldk.solve("lattice", lam, w["sigma2"], y, out=c, ws=ws_solve),
+        "logdet": lambda: ldk.logdet(lam, w["sigma2"], out=ld, ws=ws_ld),
+    }
+    per_op = {op: time_graph(op_calls[op], K) for op in ops}
     # algorithmic bytes per op (one launch of each op per step)
     alg = {
         "gen_points": 8 * n * d * R,              # write the point words
@@ -192,8 +184,9 @@ def main():
                            "frac": op_rows["solve"]["hbm_frac"],
                            "solves_per_s_cached_lambda": round(1e3 / per_op["solve"], 1)},
         "ops": op_rows,
-        "timing": "value and ms_per_step: K replays of one HIP-graph-captured step; ops: the "
-                  "same step launched op by op with HIP events between ops",
+        "timing": "value and ms_per_step: K replays of one HIP-graph-captured step; ops: each "
+                  "op captured alone in a graph and replayed K times, HIP events around the "
+                  "replays on the capture stream",
         "graph_equals_eager": graph_matches,
         "wall_s_timed": round(wall, 4),
     }
@@ -215,10 +208,132 @@ def main():
                              "ms": round(ms, 5),
                              "GB_s": round(2 * src.numel() * 8 / (ms * 1e-3) / 1e9, 1)}
 
+    if not args.no_grad:
+        out["grad"] = grad_bench(K, args.warmup)
+
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
 
     print(json.dumps(out), flush=True)
+
+
+def time_graph(fn, K):
+    """Average device ms per launch of fn: captured once in a HIP graph, the
+    graph replayed K times between two events on the capture stream."""
+    import torch
+
+    fn()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    g.replay()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(K):
+        g.replay()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / K
+
+
+def grad_bench(K, warmup):
+    """Marginal-likelihood gradient of the net workload: 64 replications of
+    n = 2^16 points in d = 64 (LMS + digital shift, order-2 DSI kernel,
+    gamma_j = 1/j^2, sigma^2 = 1e-3).  A step is the whole gradient for all
+    replications: first column (FP32 factors, regenerated points) ->
+    eigenvalues (FP64) -> likelihood and dL/dlambda (FP32 transform of y,
+    FP64 after it) -> adjoint -> kernel-parameter gradient (FP32 factors,
+    FP64 sums).  The FP32 gradient's error is measured against the same
+    step in FP64."""
+    import numpy as np
+    import torch
+
+    import paper_2502_14256_amd as ldk
+    import workloads as W
+
+    w = W.workload(5)
+    m, d, R = w["m"], w["d"], w["R"]
+    n = 2 ** m
+
+    def dev_u64(a):
+        return torch.from_numpy(np.ascontiguousarray(a, np.uint64).view(np.int64).copy()).cuda()
+
+    ps = ldk.PointSet("dnet", R, d, m, dev_u64(w["gen"]), dev_u64(w["lms"]), dev_u64(w["shift"]))
+    kern = ldk.Kernel("dnet", w["alpha"],
+                      torch.tensor(w["gamma"], dtype=torch.float64, device="cuda"), w["zeta"])
+    y64 = torch.from_numpy(np.ascontiguousarray(w["y"][:, 0, :])).cuda()
+
+    def buffers(dt):
+        b = dict(k1=torch.empty((R, n), dtype=dt, device="cuda"),
+                 lam=torch.empty((R, n), dtype=torch.float64, device="cuda"),
+                 y=y64.to(dt),
+                 g=torch.empty((R, n), dtype=torch.float64, device="cuda"),
+                 a=torch.empty((R, n), dtype=torch.float64, device="cuda"),
+                 kg=torch.empty((R, d + 1), dtype=torch.float64, device="cuda"),
+                 L=torch.empty(R, dtype=torch.float64, device="cuda"),
+                 ds=torch.empty(R, dtype=torch.float64, device="cuda"))
+        code = ldk._dtype_code(dt)
+        b["ws_eig"] = ldk._workspace(ldk.OP_EIG, ldk.DNET_B2, R, m, code, "cuda")
+        b["ws_mll"] = ldk._workspace(ldk.OP_MLL, ldk.DNET_B2, R, m, code, "cuda")
+        b["ws_grad"] = torch.empty(ldk.lib().ldk_kernel_grad_workspace_bytes(R, d, 0, n, 0),
+                                   dtype=torch.uint8, device="cuda")
+        return b
+
+    def ops_of(b, dt):
+        def mll():
+            L, g, ds = b["L"], b["g"], b["ds"]
+            code = ldk._dtype_code(dt)
+            ldk._check(ldk.lib().ldk_mll(ldk.DNET_B2, R, m, code, ldk._ptr(b["lam"]), w["sigma2"],
+                                         ldk._ptr(b["y"]), ldk._ptr(L), ldk._ptr(g), ldk._ptr(ds),
+                                         ldk._ptr(b["ws_mll"]), ldk._stream()), "ldk_mll")
+        return {
+            "kernel_column": lambda: ldk.kernel_column(kern, ps, 0, n, dtype=dt, out=b["k1"]),
+            "eig": lambda: ldk.eig("dnet", b["k1"], out=b["lam"], ws=b["ws_eig"]),
+            "mll": mll,
+            "mll_adjoint": lambda: ldk.mll_adjoint("dnet", b["g"], out=b["a"]),
+            "kernel_grad": lambda: ldk.kernel_grad(kern, ps, 0, n, b["a"], dtype=dt, out=b["kg"],
+                                                   ws=b["ws_grad"]),
+        }
+
+    names = ["kernel_column", "eig", "mll", "mll_adjoint", "kernel_grad"]
+    res = {}
+    for dt in (torch.float32, torch.float64):
+        b = buffers(dt)
+        ops = ops_of(b, dt)
+
+        def step():
+            for nm in names:
+                ops[nm]()
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        ms = time_graph(step, K)
+        grad = torch.cat([b["kg"], b["ds"][:, None]], dim=1).cpu().numpy()
+        res[dt] = dict(ms=ms, grad=grad, L=b["L"].cpu().numpy(),
+                       per_op={nm: time_graph(ops[nm], K) for nm in names})
+    r32, r64 = res[torch.float32], res[torch.float64]
+    err = float(np.max(np.abs(r32["grad"] - r64["grad"])) / np.max(np.abs(r64["grad"])))
+    evals = 2 * R * n * d  # factor evaluations of the gradient kernel (two sweeps)
+    kg_ms = r32["per_op"]["kernel_grad"]
+    return {
+        "workload": "net_m16_d64_r64_dsi2_grad (64 replications of an LMS+DS base-2 net, "
+                    "n=2^16, d=64, order-2 DSI kernel, gamma_j=1/j^2, sigma^2=1e-3): "
+                    "kernel_column + eig + mll + mll_adjoint + kernel_grad per step",
+        "value": round(R / (r32["ms"] * 1e-3), 1),
+        "unit": "replication gradients/s",
+        "ms_per_step": round(r32["ms"], 5),
+        "ms_per_step_f64": round(r64["ms"], 5),
+        "ops_ms": {nm: round(r32["per_op"][nm], 5) for nm in names},
+        "ops_ms_f64": {nm: round(r64["per_op"][nm], 5) for nm in names},
+        "kernel_grad_factor_evals_per_s": round(evals / (kg_ms * 1e-3), 1),
+        "f32_grad_rel_err_vs_f64": err,
+        "dtype": "f32 kernel factors and transform of y; f64 eigenvalues, g, adjoint, sums",
+    }
 
 
 def cpu_baseline(w, budget_s):

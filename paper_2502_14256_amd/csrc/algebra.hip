@@ -51,9 +51,20 @@ __global__ __launch_bounds__(LOGDET_THREADS) void k_logdet_partial(const double 
     const int64_t lo = (int64_t)ch * LOGDET_CHUNK;
     const int64_t hi = lo + LOGDET_CHUNK < n ? lo + LOGDET_CHUNK : n;
     double acc = 0.0;
-    for (int64_t k = lo + t; k < hi; k += LOGDET_THREADS) {
-        const double s = row[k] + sigma2;
-        acc += s > 0.0 ? log(s) : __builtin_nan("");
+    static_assert(LOGDET_CHUNK % LOGDET_THREADS == 0, "whole items per thread");
+    double lv[LOGDET_CHUNK / LOGDET_THREADS];
+#pragma unroll
+    for (int it = 0; it < LOGDET_CHUNK / LOGDET_THREADS; ++it) {  // loads first
+        const int64_t k = lo + t + (int64_t)it * LOGDET_THREADS;
+        lv[it] = k < hi ? row[k] : 0.0;
+    }
+#pragma unroll
+    for (int it = 0; it < LOGDET_CHUNK / LOGDET_THREADS; ++it) {
+        const int64_t k = lo + t + (int64_t)it * LOGDET_THREADS;
+        if (k < hi) {
+            const double s = lv[it] + sigma2;
+            acc += s > 0.0 ? log(s) : __builtin_nan("");
+        }
     }
     red[t] = acc;
     __syncthreads();
@@ -159,7 +170,7 @@ int forward_all(int kind, int dtype, int m, int64_t rows, const void *src, int64
                 bool src_real, void *dst, int64_t dst_row, bool dst_real, void *tmp,
                 int64_t tmp_row, double scale, hipStream_t s, bool src_f32 = false)
 {
-    const Plan pl = make_plan(m, log_tile_for(kind, dtype));
+    const Plan pl = make_plan(m, log_tile_for(kind, dtype), rows);
     for (int p = 0; p < pl.P; ++p) {
         const bool first = p == 0, last = p == pl.P - 1;
         PassArgs a{};
@@ -185,7 +196,7 @@ int forward_all(int kind, int dtype, int m, int64_t rows, const void *src, int64
 int apply_all(int kind, int dtype, int mode, int m, int64_t rows, int nrhs, const double *lam,
               double sigma2, const void *src, void *dst, void *tmp, hipStream_t s)
 {
-    const Plan pl = make_plan(m, log_tile_for(kind, dtype));
+    const Plan pl = make_plan(m, log_tile_for(kind, dtype), rows);
     const int64_t n = (int64_t)1 << m;
     const bool lat = kind == LDK_LATTICE;
     void *work = (lat && pl.P > 1) ? tmp : dst;
@@ -253,7 +264,7 @@ int real_eig(int m, int64_t rows, const void *k1, bool k1_f32, double *lam, void
 {
     const int mp = m - 1;
     const int64_t N = (int64_t)1 << mp;
-    const Plan pl = make_plan(mp, log_tile_for(LDK_LATTICE, LDK_F64));
+    const Plan pl = make_plan(mp, log_tile_for(LDK_LATTICE, LDK_F64), rows);
     PassArgs a{};
     a.rows = rows;
     a.m = mp;
@@ -290,7 +301,7 @@ int real_apply(int dtype, int mode, int m, int64_t rows, int nrhs, const double 
 {
     const int mp = m - 1;
     const int64_t N = (int64_t)1 << mp;
-    const Plan pl = make_plan(mp, log_tile_for(LDK_LATTICE, dtype));
+    const Plan pl = make_plan(mp, log_tile_for(LDK_LATTICE, dtype), rows);
     PassArgs a{};
     a.rows = rows;
     a.m = mp;
@@ -416,7 +427,7 @@ int ldk_transform(int kind, int dir, int B, int m, int dtype, const void *in, vo
     if (kind == LDK_DNET_B2 || dir == 1)
         return forward_all(kind, dtype, m, B, in, n, false, out, n, false, out, n, scale, s);
     // inverse FFTBR: passes from the top down
-    const Plan pl = make_plan(m, log_tile_for(kind, dtype));
+    const Plan pl = make_plan(m, log_tile_for(kind, dtype), B);
     for (int p = pl.P - 1; p >= 0; --p) {
         PassArgs a{};
         a.src = p == pl.P - 1 ? in : out;

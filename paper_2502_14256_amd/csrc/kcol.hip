@@ -111,8 +111,11 @@ __device__ __forceinline__ void net_tile(const KcolArgs &a, NetLds &L, int r, in
                     const int64_t i = first + (int64_t)l * KC_THREADS;
                     if (i >= a.n_min && i < a.n_max) prod[l] *= f;
                 }
+                // step to the next point; past the last index of the net the
+                // step columns are zero and z just repeats (such points are
+                // masked), so the step needs no bounds test
                 const uint64_t nb = ((uint64_t)tile0 >> s) + (uint64_t)l + 1;
-                if (l + 1 < KC_ITERS && (int64_t)(nb << s) < a.n_max) z ^= L.step[jj][ctz64(nb)];
+                if (l + 1 < KC_ITERS) z ^= L.step[jj][ctz64(nb)];
             }
         }
     }

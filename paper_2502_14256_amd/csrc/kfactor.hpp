@@ -12,7 +12,7 @@ namespace {
 constexpr int KC_THREADS = 256;
 constexpr int KC_LOG_THREADS = 8;
 constexpr int KC_ITERS = 8;       // points per thread (spaced KC_THREADS apart)
-constexpr int KC_DIM_CHUNK = 16;  // dimensions whose net tables sit in LDS at once
+constexpr int KC_DIM_CHUNK = 8;   // dimensions whose net tables sit in LDS at once (12 KiB)
 constexpr int KC_TILE = KC_THREADS * KC_ITERS;
 constexpr int KC_CODE_WORDS = LDK_MAX_D / 32;  // 2-bit order codes, 32 per word
 }  // namespace
@@ -76,25 +76,49 @@ __device__ __forceinline__ double pow2_neg(int beta)
 {
     return __hiloint2double((1023 - beta) << 20, 0);
 }
+template <typename R>
+__device__ __forceinline__ R pow2_neg_r(int beta);
+template <>
+__device__ __forceinline__ double pow2_neg_r<double>(int beta) { return pow2_neg(beta); }
+template <>
+__device__ __forceinline__ float pow2_neg_r<float>(int beta) { return __int_as_float((127 - beta) << 23); }
 
+// A 32-bit value the optimiser cannot see through (no instruction): keeps
+// a conversion of a 32-bit word from being widened into the much longer
+// 64-bit integer-to-float sequence.
+__device__ __forceinline__ uint32_t opaque32(uint32_t v)
+{
+    asm("" : "+v"(v));
+    return v;
+}
+
+// Coordinate value x = u 2^-64.  FP64: rounded to nearest (two exact
+// conversions, one fused multiply-add).  FP32: the top 32 digits rounded to
+// 24 bits (absolute error below 2^-24 x + 2^-32, far inside the FP32
+// tolerance; one conversion and one multiply).
 template <typename R>
 __device__ __forceinline__ R unit(uint64_t u);
 template <>
-__device__ __forceinline__ double unit<double>(uint64_t u) { return unit_f64(u); }
+__device__ __forceinline__ double unit<double>(uint64_t u)
+{
+    return __fma_rn((double)opaque32((uint32_t)(u >> 32)), 4294967296.0,
+                    (double)opaque32((uint32_t)u)) * 0x1p-64;
+}
 template <>
-__device__ __forceinline__ float unit<float>(uint64_t u) { return unit_f32(u); }
+__device__ __forceinline__ float unit<float>(uint64_t u)
+{
+    return (float)opaque32((uint32_t)(u >> 32)) * 0x1p-32f;
+}
 
 template <typename R, int ALPHA>
 __device__ __forceinline__ R dsi_factor(uint64_t delta, const DsiTables &tab)
 {
-    int beta = 0;
-    R x = (R)0;
-    if (delta) {
-        beta = clz64(delta) + 1;
-        x = unit<R>(delta);
-    }
+    // beta = 1 + clz(delta) for delta != 0; beta = x = t_nu = 0 at delta = 0
+    const bool nz = delta != 0;
+    const int beta = nz ? clz64(delta) + 1 : 0;
+    const R x = unit<R>(delta);  // 0 at delta = 0
     const R b = (R)beta;
-    const R t1 = beta ? (R)pow2_neg(beta) : (R)0;
+    const R t1 = nz ? pow2_neg_r<R>(beta) : (R)0;
     if constexpr (ALPHA == 1) {
         return (R)1 - (R)3 * t1;
     } else if constexpr (ALPHA == 2) {

@@ -7,8 +7,9 @@
 // point's product of nonzero factors P and counts its exact zeros; the second
 // re-evaluates t_ij and takes the product of the other factors as P / f_ij
 // (no zero), P (the one zero is f_ij) or 0.  Per dimension, the point sum is
-// reduced across the wavefront in FP64 and parked in lane j mod 64; wave
-// partials go to a workspace and a second kernel adds them in a fixed order.
+// reduced across the wavefront in FP64 and parked in lane j mod 64; every 64
+// dimensions the block adds its waves in LDS and writes one partial per tile,
+// and a second kernel adds the tiles in a fixed order.
 #include "kfactor.hpp"
 
 namespace ldk {
@@ -19,7 +20,7 @@ constexpr int KG_WAVES = KC_THREADS / 64;
 struct KgradArgs {
     KcolArgs k;
     const double *a;  // [R][cnt], dL/dk1
-    double *part;     // [R][tiles][KG_WAVES][d + 1]
+    double *part;     // [R][tiles][d + 1]
     int64_t tile_base;
     int64_t tiles;
 };
@@ -30,6 +31,11 @@ __device__ __forceinline__ double wave_sum(double v)
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
+
+// Product of the other factors, P / f: FP32 takes the reciprocal-based
+// quotient (within 2 ulp), FP64 the correctly rounded one.
+__device__ __forceinline__ float quot(float p, float f) { return __fdividef(p, f); }
+__device__ __forceinline__ double quot(double p, double f) { return p / f; }
 
 // ---- dimension sweeps: call visit(j, t[KC_ITERS]) for j = 0 .. d-1 in order,
 // t[l] = gamma_j K_j(delta) of point tile0 + threadIdx.x + KC_THREADS l ----
@@ -90,8 +96,11 @@ __device__ __forceinline__ void net_sweep(const KcolArgs &a, NetLds &L, int r, i
                 else
                     k = dsi_factor_any<R>(alpha, z, L.tab);
                 tv[l] = gam * k;
+                // step to the next point; past the last index of the net the
+                // step columns are zero and z just repeats (such points are
+                // masked), so the step needs no bounds test
                 const uint64_t nb = ((uint64_t)tile0 >> s) + (uint64_t)l + 1;
-                if (l + 1 < KC_ITERS && (int64_t)(nb << s) < a.n_max) z ^= L.step[jj][ctz64(nb)];
+                if (l + 1 < KC_ITERS) z ^= L.step[jj][ctz64(nb)];
             }
             visit(j, tv);
         }
@@ -171,7 +180,8 @@ __global__ __launch_bounds__(KC_THREADS) void k_kernel_grad(KgradArgs g)
             else pnz[l] *= f;
         }
     });
-    double *part = g.part + (((size_t)r * g.tiles + blockIdx.x) * KG_WAVES + wave) * (d + 1);
+    __shared__ double red[KG_WAVES][64];
+    double *part = g.part + ((size_t)r * g.tiles + blockIdx.x) * (d + 1);
     {
         // d/dlog zeta: sum_i a_i k1_i
         R zs = (R)0;
@@ -179,7 +189,14 @@ __global__ __launch_bounds__(KC_THREADS) void k_kernel_grad(KgradArgs g)
         for (int l = 0; l < KC_ITERS; ++l)
             if (((valid >> l) & 1u) && nz[l] == 0) zs += av[l] * pnz[l];
         const double w = wave_sum((double)zs * a.zeta);
-        if (lane == 0) part[d] = w;
+        if (lane == 0) red[wave][0] = w;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s = 0.0;
+            for (int q = 0; q < KG_WAVES; ++q) s += red[q][0];
+            part[d] = s;
+        }
+        __syncthreads();
     }
     // sweep 2: t_ij times the product of the other factors
     double acc = 0.0;
@@ -189,30 +206,47 @@ __global__ __launch_bounds__(KC_THREADS) void k_kernel_grad(KgradArgs g)
         for (int l = 0; l < KC_ITERS; ++l) {
             const R f = (R)1 + t[l];
             R other;
-            if (nz[l] == 0) other = pnz[l] / f;
+            if (nz[l] == 0) other = quot(pnz[l], f);
             else other = (nz[l] == 1 && f == (R)0) ? pnz[l] : (R)0;
             if ((valid >> l) & 1u) ps += av[l] * (t[l] * other);
         }
         const double w = wave_sum((double)ps * a.zeta);
         if ((j & 63) == lane) acc = w;
         if ((j & 63) == 63 || j == d - 1) {
+            // block-uniform: every thread reaches these barriers
             const int j0 = j & ~63;
-            if (j0 + lane <= j) part[j0 + lane] = acc;
+            red[wave][lane] = acc;
+            __syncthreads();
+            if (threadIdx.x < 64 && j0 + (int)threadIdx.x <= j) {
+                double s = 0.0;
+                for (int q = 0; q < KG_WAVES; ++q) s += red[q][threadIdx.x];
+                part[j0 + threadIdx.x] = s;
+            }
+            __syncthreads();
         }
     });
 }
 
-// grad[r][j] = sum over tiles and waves of the partials, in a fixed order.
+// grad[r][j] = sum over tiles of the partials, in a fixed order (four
+// interleaved accumulators, combined in a fixed order).
 __global__ __launch_bounds__(256) void k_grad_final(const double *__restrict__ part, int64_t tiles,
                                                     int d, double *__restrict__ grad)
 {
     const int r = blockIdx.y;
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j > d) return;
-    const double *p = part + (size_t)r * tiles * KG_WAVES * (d + 1) + j;
-    double s = 0.0;
-    for (int64_t q = 0; q < tiles * KG_WAVES; ++q) s += p[(size_t)q * (d + 1)];
-    grad[(size_t)r * (d + 1) + j] = s;
+    const size_t stride = (size_t)(d + 1);
+    const double *p = part + (size_t)r * tiles * stride + j;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int64_t q = 0;
+    for (; q + 4 <= tiles; q += 4) {
+        s0 += p[(size_t)q * stride];
+        s1 += p[(size_t)(q + 1) * stride];
+        s2 += p[(size_t)(q + 2) * stride];
+        s3 += p[(size_t)(q + 3) * stride];
+    }
+    for (; q < tiles; ++q) s0 += p[(size_t)q * stride];
+    grad[(size_t)r * (d + 1) + j] = (s0 + s1) + (s2 + s3);
 }
 
 template <typename R, int ALPHA>
@@ -267,7 +301,7 @@ extern "C" size_t ldk_kernel_grad_workspace_bytes(int R, int d, int64_t n_min, i
     if (R < 1 || d < 1 || d > LDK_MAX_D || n_min < 0 || n_max < n_min) return 0;
     int64_t base, tiles;
     grad_tiles(points_given != 0, n_min, n_max, &base, &tiles);
-    return (size_t)R * (size_t)tiles * KG_WAVES * (size_t)(d + 1) * sizeof(double);
+    return (size_t)R * (size_t)tiles * (size_t)(d + 1) * sizeof(double);
 }
 
 extern "C" int ldk_kernel_grad(const ldk_kernel *k, const ldk_pointset *ps, const uint64_t *pts,

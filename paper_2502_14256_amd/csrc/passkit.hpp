@@ -123,6 +123,18 @@ __device__ __forceinline__ void reg_inv(T (&v)[E], int gs)
     }
 }
 
+// Workgroups are handed to the 8 XCDs (each with its own L2) round robin:
+// workgroup b runs on XCD b mod 8.  Column passes read runs of one or a few
+// cache lines per tile row, and neighbouring tiles share those lines; the
+// swizzle gives each XCD a contiguous range of tiles so that the sharing
+// stays inside one L2.  (Identity when the grid is not a multiple of 8.)
+constexpr int XCD_COUNT = 8;
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb)
+{
+    if (nb % XCD_COUNT) return b;
+    return (b % XCD_COUNT) * (nb / XCD_COUNT) + b / XCD_COUNT;
+}
+
 // Tile index of register i of thread t for a group of gs bits at tile bit
 // `pos`: the digit c = i mod 2^gs is inserted at bit pos of o = sub*T + t.
 __device__ __forceinline__ int group_q(int t, int i, int gs, int pos, int T)

@@ -56,8 +56,9 @@ __global__ __launch_bounds__(512) void k_real_top(PassArgs a, double *lam_out)
     const int Tn = S >> LOGE;
     const int t = threadIdx.x;
     const int64_t cb_count = N1 >> logW;
-    const int64_t cb = blockIdx.x % cb_count;
-    const int64_t row = blockIdx.x / cb_count;
+    const int64_t bid = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t cb = bid % cb_count;
+    const int64_t row = bid / cb_count;
     const bool last = cb == cb_count - 1;
 
     auto col_of = [&](int w) -> int64_t {
@@ -72,11 +73,42 @@ __global__ __launch_bounds__(512) void k_real_top(PassArgs a, double *lam_out)
     const int rem = A - LOGE * (G - 1);
     const int top_s = A - LOGE;
 
+    const int64_t n = 2 * N;
+    const double *lam = a.lam ? a.lam + (row / a.nrhs) * n : nullptr;
+
     T v[E];
     if constexpr (MODE != PM_ADJ) {
 #pragma unroll
         for (int i = 0; i < E; ++i)
             v[i] = load_elem<T, LD, SRC_F32>(a.src, row * a.src_row + gidx(t + Tn * i), a.half);
+    }
+    // Per-element twiddle W_n^k and spectral factors, fetched after the
+    // data loads are issued and before the transform, so that their latency
+    // overlaps the data loads and the groups.
+    T wkv[E];
+    double f1[E], f2[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const int q = t + Tn * i;
+        const int64_t k = col_of(q & (W - 1)) + N1 * (int64_t)(q >> logW);
+        wkv[i] = tw_any<R>((uint64_t)k, mp + 1);
+        if constexpr (MODE == PM_SOLVE || MODE == PM_MATVEC || MODE == PM_ADJ) {
+            const double la = lam[k], lb = lam[(n - k) & (n - 1)];
+            const double lc = lam[k + N], ld = lam[(N - k) & (n - 1)];
+            if constexpr (MODE == PM_SOLVE) {
+                // (1/(la+s2) + 1/(lb+s2)) / 2 with one division
+                const double pa = la + a.sigma2, pb = lb + a.sigma2;
+                const double pc = lc + a.sigma2, pd = ld + a.sigma2;
+                f1[i] = 0.5 * a.scale * (pa + pb) / (pa * pb);
+                f2[i] = 0.5 * a.scale * (pc + pd) / (pc * pd);
+            } else {
+                f1[i] = 0.5 * a.scale * (la + lb);
+                f2[i] = 0.5 * a.scale * (lc + ld);
+            }
+        }
+    }
+
+    if constexpr (MODE != PM_ADJ) {
         if (b0 > 0)
             pass_twiddle_k1<T, E, LOGE, false>(v, t, (uint64_t)col_of(t & (W - 1)), logW, A, b0);
 
@@ -104,8 +136,6 @@ __global__ __launch_bounds__(512) void k_real_top(PassArgs a, double *lam_out)
         lds_write(v, lds, t, LOGE, logW + top_s, Tn);
         __syncthreads();
     }
-    const int64_t n = 2 * N;
-    const double *lam = a.lam ? a.lam + (row / a.nrhs) * n : nullptr;
 #pragma unroll
     for (int i = 0; i < E; ++i) {
         const int q = t + Tn * i;
@@ -113,12 +143,9 @@ __global__ __launch_bounds__(512) void k_real_top(PassArgs a, double *lam_out)
         const int64_t k1 = col_of(w);
         if constexpr (MODE == PM_ADJ) {
             // real spectrum g in a.lam: C = scale (g_k + g_{n-k}) / 2 at k and k + N
-            const int64_t k = k1 + N1 * k2;
-            const T wk = tw_any<R>((uint64_t)k, mp + 1);
-            const double s1 = 0.5 * a.scale * (lam[k] + lam[(n - k) & (n - 1)]);
-            const double s2 = 0.5 * a.scale * (lam[k + N] + lam[(N - k) & (n - 1)]);
+            const double s1 = f1[i], s2 = f2[i];
             const R ep = (R)(0.5 * (s1 + s2));
-            const T op = cmulc(T{(R)(0.5 * (s1 - s2)), (R)0}, wk);
+            const T op = cmulc(T{(R)(0.5 * (s1 - s2)), (R)0}, wkv[i]);
             v[i] = T{ep - op.im, op.re};
             continue;
         }
@@ -139,7 +166,7 @@ __global__ __launch_bounds__(512) void k_real_top(PassArgs a, double *lam_out)
         const T ev{(zk.re + zm.re) * (R)0.5, (zk.im - zm.im) * (R)0.5};
         const T dv{(zk.re - zm.re) * (R)0.5, (zk.im + zm.im) * (R)0.5};
         const T od{dv.im, -dv.re};  // -i (Z_k - conj Z_{N-k}) / 2
-        const T wk = tw_any<R>((uint64_t)k, mp + 1);
+        const T wk = wkv[i];
         const T wo = cmul(wk, od);
         const T yk{ev.re + wo.re, ev.im + wo.im};
         const T ykn{ev.re - wo.re, ev.im - wo.im};
@@ -151,16 +178,7 @@ __global__ __launch_bounds__(512) void k_real_top(PassArgs a, double *lam_out)
             lam_out[row * n + k + N] =
                 (double)ykn.re * (double)ykn.re + (double)ykn.im * (double)ykn.im;
         } else {
-            const double la = lam[k], lb = lam[(n - k) & (n - 1)];
-            const double lc = lam[k + N], ld = lam[(N - k) & (n - 1)];
-            double s1, s2;
-            if constexpr (MODE == PM_SOLVE) {
-                s1 = 0.5 * (a.scale / (la + a.sigma2) + a.scale / (lb + a.sigma2));
-                s2 = 0.5 * (a.scale / (lc + a.sigma2) + a.scale / (ld + a.sigma2));
-            } else {
-                s1 = 0.5 * a.scale * (la + lb);
-                s2 = 0.5 * a.scale * (lc + ld);
-            }
+            const double s1 = f1[i], s2 = f2[i];
             const T c1{yk.re * (R)s1, yk.im * (R)s1};
             const T c2{ykn.re * (R)s2, ykn.im * (R)s2};
             const T ep{(c1.re + c2.re) * (R)0.5, (c1.im + c2.im) * (R)0.5};

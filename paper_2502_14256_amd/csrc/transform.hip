@@ -29,7 +29,7 @@ __global__ __launch_bounds__(512) void k_pass(PassArgs a)
     // block -> (row, outer, column block)
     const int64_t cb_count = (int64_t)1 << (b0 - logW);
     const int64_t outer_count = (int64_t)1 << (a.m - b0 - A);
-    int64_t bid = blockIdx.x;
+    int64_t bid = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t cb = bid % cb_count;
     bid /= cb_count;
     const int64_t outer = bid % outer_count;
@@ -183,13 +183,17 @@ int launch_m(int mode, int ld, int st, const PassArgs &a, hipStream_t s)
 
 }  // namespace
 
-Plan make_plan(int m, int log_tile)
+Plan make_plan(int m, int log_tile, int64_t rows)
 {
     Plan p{};
     p.m = m;
     if (m == 0) return p;
-    constexpr int LOGE_MAX = 3;    // 8 elements per thread
-    constexpr int LOG_THREADS = 9; // at most 512 threads per workgroup
+    constexpr int LOG_THREADS = 9;  // at most 512 threads per workgroup
+    // Few tiles in all (fewer than two per compute unit): 4 elements per
+    // thread instead of 8, so that twice as many waves hide the latency.
+    // The split of the index bits (and so the pass count) does not change.
+    const bool small = rows > 0 && m + 63 - __builtin_clzll((uint64_t)rows) < log_tile + 9;
+    const int LOGE_MAX = small ? 2 : 3;
     // row pass: the low a0 bits; column passes: the rest, split evenly into
     // chunks of at most 8 bits (at least 4 where possible)
     int a0 = m < log_tile ? m : log_tile;
@@ -198,7 +202,9 @@ Plan make_plan(int m, int log_tile)
         a0 = m - 4;
         r = 4;
     }
-    p.pass[0] = PassGeom{0, a0, 0, a0 < LOGE_MAX ? a0 : LOGE_MAX};
+    int logE0 = a0 < LOGE_MAX ? a0 : LOGE_MAX;
+    if (a0 - logE0 > LOG_THREADS) logE0 = a0 - LOG_THREADS;
+    p.pass[0] = PassGeom{0, a0, 0, logE0};
     p.P = 1;
     const int C = (r + 7) / 8;
     int b0 = a0;

@@ -176,10 +176,10 @@ def test_likelihood_workspace_sizes():
     assert ws(ldk.OP_MLL_ADJOINT, ldk.LATTICE, 2, 20, 0) == 2 * 2**19 * 16
     assert ws(ldk.OP_MLL_ADJOINT, ldk.LATTICE, 2, 12, 0) == 0
     g = L.ldk_kernel_grad_workspace_bytes
-    # [R][tiles of 2048][4 waves][d + 1] doubles
-    assert g(3, 7, 0, 4096, 0) == 3 * 2 * 4 * 8 * 8
-    assert g(3, 7, 100, 4096, 0) == 3 * 2 * 4 * 8 * 8      # tiles aligned to 2048
-    assert g(3, 7, 100, 4097, 1) == 3 * 2 * 4 * 8 * 8      # tiles from n_min
-    assert g(3, 7, 100, 4197, 1) == 3 * 3 * 4 * 8 * 8
+    # [R][tiles of 2048][d + 1] doubles
+    assert g(3, 7, 0, 4096, 0) == 3 * 2 * 8 * 8
+    assert g(3, 7, 100, 4096, 0) == 3 * 2 * 8 * 8      # tiles aligned to 2048
+    assert g(3, 7, 100, 4097, 1) == 3 * 2 * 8 * 8      # tiles from n_min
+    assert g(3, 7, 100, 4197, 1) == 3 * 3 * 8 * 8
     assert g(0, 7, 0, 4096, 0) == 0
     assert ws(ldk.OP_MLL, ldk.LATTICE, 3, 0, 0) == 256  # n = 1 still sums
