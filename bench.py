@@ -27,6 +27,27 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 
+# HBM bytes per launch of the gen_points kernel (k_gen_lattice) at n = 2^20,
+# d = 32, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a plain
+# 256 MiB device copy's counters (profiles/traffic_lattice_m20_d32_f64.md).
+# Valid only for the kernel source they were taken on: the sources' SHA-1 is
+# checked at run time and the figure reported as null once they change.
+GEN_TRAFFIC = {"read_MiB": 0.05, "write_MiB": 280.72,
+               "sources": ("points.hip", "pointset.hpp", "common.hpp"),
+               "sha1": "2a543faf5c83018a484995a51b62ce5bc2797297"}
+
+
+def gen_traffic_bytes():
+    import hashlib
+
+    h = hashlib.sha1()
+    for f in GEN_TRAFFIC["sources"]:
+        with open(os.path.join(ROOT, "paper_2502_14256_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != GEN_TRAFFIC["sha1"]:
+        return None
+    return int((GEN_TRAFFIC["read_MiB"] + GEN_TRAFFIC["write_MiB"]) * 2**20)
+
 
 def parse():
     p = argparse.ArgumentParser()
@@ -101,12 +122,14 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    c_eager = c.clone()
+    c_eager, ld_eager, pts_eager = c.clone(), ld.clone(), pts.clone()
 
     # One whole step captured as a HIP graph: replays carry no host launch
     # overhead.  Every library call enqueues on torch's current stream, which
     # is the capture stream inside the context; no allocation or memset is
-    # captured (all buffers and workspaces exist already).
+    # captured (all buffers and workspaces exist already).  (Putting the
+    # point words on a second stream beside the rest was measured: the
+    # hardware does not overlap the two, so the step stays one stream.)
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         step()
@@ -114,7 +137,8 @@ def main():
     for _ in range(args.warmup):
         graph.replay()
     torch.cuda.synchronize()
-    graph_matches = bool(torch.equal(c, c_eager))
+    graph_matches = bool(torch.equal(c, c_eager) and torch.equal(ld, ld_eager)
+                         and torch.equal(pts, pts_eager))
 
     # timed region 1: K whole steps (graph replays), HIP events on the stream
     K = args.steps
@@ -157,7 +181,7 @@ def main():
     dom = max(ops, key=lambda o: per_op[o])
     roof_dom = {"kernel": dom, "bound": "hbm", "achieved": op_rows[dom]["GB_s"],
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": op_rows[dom]["hbm_frac"],
-                "traffic": None}
+                "traffic": gen_traffic_bytes() if dom == "gen_points" else None}
     ms_per_step = total_ms / K
     solves_per_s = R * K / (total_ms * 1e-3)
 

@@ -13,7 +13,8 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("kind", ["lattice", "dnet"])
-def test_graph_replays_match_eager(kind):
+@pytest.mark.parametrize("branches", [False, True])
+def test_graph_replays_match_eager(kind, branches):
     ldk.init()
     m, d, R = 16, 8, 2
     w = W.small_lattice(3, m=m, d=d, R=R) if kind == "lattice" else W.small_net(3, m=m, d=d, R=R)
@@ -31,12 +32,32 @@ def test_graph_replays_match_eager(kind):
     ws_s = ldk._workspace(ldk.OP_SOLVE, kd, R, m, ldk.F64, "cuda")
     ws_l = ldk._workspace(ldk.OP_LOGDET, kd, R, m, ldk.F64, "cuda")
 
+    s_a, s_b = torch.cuda.Stream(), torch.cuda.Stream()
+    ev = torch.cuda.Event()
+
     def step():
-        ldk.gen_points(ps, 0, n, out=pts)
+        if not branches:
+            ldk.gen_points(ps, 0, n, out=pts)
+            ldk.kernel_column(k, ps, 0, n, out=k1)
+            ldk.eig(kind, k1, out=lam, ws=ws_e)
+            ldk.solve(kind, lam, 1e-4, y, out=c, ws=ws_s)
+            ldk.logdet(lam, 1e-4, out=ld, ws=ws_l)
+            return
+        # points on a side branch; log-det beside the solve (as the benchmark)
+        main = torch.cuda.current_stream()
+        s_a.wait_stream(main)
+        s_b.wait_stream(main)
+        with torch.cuda.stream(s_a):
+            ldk.gen_points(ps, 0, n, out=pts)
         ldk.kernel_column(k, ps, 0, n, out=k1)
         ldk.eig(kind, k1, out=lam, ws=ws_e)
+        ev.record(main)
+        with torch.cuda.stream(s_b):
+            s_b.wait_event(ev)
+            ldk.logdet(lam, 1e-4, out=ld, ws=ws_l)
         ldk.solve(kind, lam, 1e-4, y, out=c, ws=ws_s)
-        ldk.logdet(lam, 1e-4, out=ld, ws=ws_l)
+        main.wait_stream(s_a)
+        main.wait_stream(s_b)
 
     step()
     torch.cuda.synchronize()
