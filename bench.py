@@ -60,6 +60,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-grad", action="store_true",
                    help="skip the marginal-likelihood gradient workload")
+    p.add_argument("--no-batch", action="store_true",
+                   help="skip the batched instance-table workload")
+    p.add_argument("--batch-steps", type=int, default=10)
     p.add_argument("--cpu-seconds", type=float, default=10.0)
     p.add_argument("--copy-probe", action="store_true",
                    help="also run a plain device copy of known size (counter calibration)")
@@ -235,6 +238,9 @@ def main():
     if not args.no_grad:
         out["grad"] = grad_bench(K, args.warmup)
 
+    if not args.no_batch:
+        out["batched"] = batch_bench(args.batch_steps, args.warmup)
+
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
 
@@ -357,6 +363,66 @@ def grad_bench(K, warmup):
         "kernel_grad_factor_evals_per_s": round(evals / (kg_ms * 1e-3), 1),
         "f32_grad_rel_err_vs_f64": err,
         "dtype": "f32 kernel factors and transform of y; f64 eigenvalues, g, adjoint, sums",
+    }
+
+
+def batch_bench(K, warmup):
+    """Instance table of 256 problems of mixed kind (rank-1 lattice with SI
+    order 2, or LMS+DS net with DSI order 2) and size n = 2^12 .. 2^18, d = 16,
+    8 right-hand sides each, FP64: first column, eigenvalues, 8 solves and the
+    log-det per instance.  Batched: instances of one (kind, m) run as the
+    replications of one point set, one launch per op per group, the whole
+    table captured as one HIP graph.  Plain: the same calls instance by
+    instance (one launch per op per instance), also captured as one graph.
+    Both graphs are replayed K times between HIP events."""
+    import numpy as np
+    import torch
+
+    from paper_2502_14256_amd.batch import BatchFit, Instance
+    import workloads as W
+
+    w = W.workload(4)
+    inst = [Instance(kind=t["kind"], m=t["m"], shift=t["shift"][0],
+                     lms=None if t["lms"] is None else t["lms"][0], y=t["y"][0])
+            for t in w["instances"]]
+    b = BatchFit(inst, {"lattice": w["lattice_gen"], "dnet": w["net_gen"]}, w["m_max"],
+                 w["alpha"], w["gamma"], w["zeta"], w["sigma2"])
+    del inst
+    g_batched = b.capture()
+    g_plain = b.capture(plain=True)
+    torch.cuda.synchronize()
+    main = torch.cuda.current_stream()
+
+    def timed(g):
+        for _ in range(warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        e = torch.cuda.Event(enable_timing=True)
+        a.record(main)
+        for _ in range(K):
+            g.replay()
+        e.record(main)
+        torch.cuda.synchronize()
+        return a.elapsed_time(e) / K
+
+    ms_b, ms_p = timed(g_batched), timed(g_plain)
+    ns = np.array([2 ** t["m"] for t in w["instances"]], dtype=np.int64)
+    solves = len(ns) * w["nrhs"]
+    alg = int((2 * 8 * w["nrhs"] + 8) * ns.sum())  # read y, write c, read lambda (FP64)
+    return {
+        "workload": "batched_256_mixed_d16 (256 instances, kind lattice/net at random, "
+                    "n=2^12..2^18, d=16, 8 RHS, FP64): kernel_column + eig + solve + logdet "
+                    "per instance",
+        "value": round(solves / (ms_b * 1e-3), 1),
+        "unit": "solves/s",
+        "ms_per_step": round(ms_b, 4),
+        "plain_solves_per_s": round(solves / (ms_p * 1e-3), 1),
+        "plain_ms_per_step": round(ms_p, 4),
+        "speedup_vs_plain": round(ms_p / ms_b, 2),
+        "groups": len(b.groups),
+        "solve_alg_bytes": alg,
+        "solve_equivalent_GB_s": round(alg / (ms_b * 1e-3) / 1e9, 1),
     }
 
 

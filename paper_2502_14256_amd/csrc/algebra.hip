@@ -170,7 +170,7 @@ int forward_all(int kind, int dtype, int m, int64_t rows, const void *src, int64
                 bool src_real, void *dst, int64_t dst_row, bool dst_real, void *tmp,
                 int64_t tmp_row, double scale, hipStream_t s, bool src_f32 = false)
 {
-    const Plan pl = make_plan(m, log_tile_for(kind, dtype), rows);
+    const Plan pl = make_plan(m, log_tile_for(kind, dtype));
     for (int p = 0; p < pl.P; ++p) {
         const bool first = p == 0, last = p == pl.P - 1;
         PassArgs a{};
@@ -196,7 +196,7 @@ int forward_all(int kind, int dtype, int m, int64_t rows, const void *src, int64
 int apply_all(int kind, int dtype, int mode, int m, int64_t rows, int nrhs, const double *lam,
               double sigma2, const void *src, void *dst, void *tmp, hipStream_t s)
 {
-    const Plan pl = make_plan(m, log_tile_for(kind, dtype), rows);
+    const Plan pl = make_plan(m, log_tile_for(kind, dtype));
     const int64_t n = (int64_t)1 << m;
     const bool lat = kind == LDK_LATTICE;
     void *work = (lat && pl.P > 1) ? tmp : dst;
@@ -264,7 +264,7 @@ int real_eig(int m, int64_t rows, const void *k1, bool k1_f32, double *lam, void
 {
     const int mp = m - 1;
     const int64_t N = (int64_t)1 << mp;
-    const Plan pl = make_plan(mp, log_tile_for(LDK_LATTICE, LDK_F64), rows);
+    const Plan pl = make_plan(mp, log_tile_for(LDK_LATTICE, LDK_F64));
     PassArgs a{};
     a.rows = rows;
     a.m = mp;
@@ -301,7 +301,7 @@ int real_apply(int dtype, int mode, int m, int64_t rows, int nrhs, const double 
 {
     const int mp = m - 1;
     const int64_t N = (int64_t)1 << mp;
-    const Plan pl = make_plan(mp, log_tile_for(LDK_LATTICE, dtype), rows);
+    const Plan pl = make_plan(mp, log_tile_for(LDK_LATTICE, dtype));
     PassArgs a{};
     a.rows = rows;
     a.m = mp;
@@ -427,7 +427,7 @@ int ldk_transform(int kind, int dir, int B, int m, int dtype, const void *in, vo
     if (kind == LDK_DNET_B2 || dir == 1)
         return forward_all(kind, dtype, m, B, in, n, false, out, n, false, out, n, scale, s);
     // inverse FFTBR: passes from the top down
-    const Plan pl = make_plan(m, log_tile_for(kind, dtype), B);
+    const Plan pl = make_plan(m, log_tile_for(kind, dtype));
     for (int p = pl.P - 1; p >= 0; --p) {
         PassArgs a{};
         a.src = p == pl.P - 1 ? in : out;

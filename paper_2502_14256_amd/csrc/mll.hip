@@ -148,7 +148,7 @@ int power_spectrum(int kind, int R, int m, int dtype, const void *y, double *pw,
         // packed half-length complex rows; the real top pass writes |Y_k|^2
         const int mp = m - 1;
         const int64_t N = n / 2;
-        const Plan pl = make_plan(mp, log_tile_for(LDK_LATTICE, dtype), R);
+        const Plan pl = make_plan(mp, log_tile_for(LDK_LATTICE, dtype));
         a.m = mp;
         a.half = N;
         for (int p = 0; p < pl.P - 1; ++p) {
@@ -169,7 +169,7 @@ int power_spectrum(int kind, int R, int m, int dtype, const void *y, double *pw,
         return launch_real_top(dtype, PM_POWER, a, pw, s);
     }
     // FWHT (nets; for n = 2 the lattice FFTBR is the same 2-point butterfly)
-    const Plan pl = make_plan(m, log_tile_for(LDK_DNET_B2, dtype), R);
+    const Plan pl = make_plan(m, log_tile_for(LDK_DNET_B2, dtype));
     a.m = m;
     for (int p = 0; p < pl.P; ++p) {
         const bool last = p == pl.P - 1;
@@ -257,7 +257,7 @@ extern "C" int ldk_mll_adjoint(int kind, int R, int m, const double *g, double *
         // then the inverse column and row passes
         const int mp = m - 1;
         const int64_t N = n / 2;
-        const Plan pl = make_plan(mp, log_tile_for(LDK_LATTICE, LDK_F64), R);
+        const Plan pl = make_plan(mp, log_tile_for(LDK_LATTICE, LDK_F64));
         p.m = mp;
         p.half = N;
         p.lam = g;
@@ -285,7 +285,7 @@ extern "C" int ldk_mll_adjoint(int kind, int R, int m, const double *g, double *
         return LDK_OK;
     }
     // unnormalised FWHT (H symmetric; for n = 2 also the lattice case)
-    const Plan pl = make_plan(m, log_tile_for(LDK_DNET_B2, LDK_F64), R);
+    const Plan pl = make_plan(m, log_tile_for(LDK_DNET_B2, LDK_F64));
     p.m = m;
     p.scale = 1.0;
     for (int q = 0; q < pl.P; ++q) {

@@ -183,17 +183,13 @@ int launch_m(int mode, int ld, int st, const PassArgs &a, hipStream_t s)
 
 }  // namespace
 
-Plan make_plan(int m, int log_tile, int64_t rows)
+Plan make_plan(int m, int log_tile)
 {
     Plan p{};
     p.m = m;
     if (m == 0) return p;
     constexpr int LOG_THREADS = 9;  // at most 512 threads per workgroup
-    // Few tiles in all (fewer than two per compute unit): 4 elements per
-    // thread instead of 8, so that twice as many waves hide the latency.
-    // The split of the index bits (and so the pass count) does not change.
-    const bool small = rows > 0 && m + 63 - __builtin_clzll((uint64_t)rows) < log_tile + 9;
-    const int LOGE_MAX = small ? 2 : 3;
+    constexpr int LOGE_MAX = 3;     // 8 elements per thread
     // row pass: the low a0 bits; column passes: the rest, split evenly into
     // chunks of at most 8 bits (at least 4 where possible)
     int a0 = m < log_tile ? m : log_tile;

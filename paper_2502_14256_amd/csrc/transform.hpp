@@ -37,10 +37,9 @@ struct Plan {
     PassGeom pass[4];
 };
 
-// log_tile: log2 of the elements per workgroup tile (LDS budget).  rows:
-// batch rows the plan will run on (0 = unknown); it only changes the
-// per-thread register count of small problems, never the pass split.
-Plan make_plan(int m, int log_tile, int64_t rows = 0);
+// log_tile: log2 of the elements per workgroup tile (LDS budget).  The plan
+// depends on m and the tile only, so results do not depend on the batch size.
+Plan make_plan(int m, int log_tile);
 int log_tile_for(int kind, int dtype);
 
 struct PassArgs {

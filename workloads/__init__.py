@@ -171,6 +171,34 @@ def _w5() -> dict:
                 sigma2=1e-3, y=y, nrhs=1)
 
 
+def small_batch(seed: int, ms, kinds, d: int, nrhs: int, m_max: int) -> dict:
+    """An instance table like workload 4 with chosen sizes and kinds (same
+    draw order: generators, then per instance S (nets), shift, responses)."""
+    rng = np.random.default_rng(seed)
+    g = lattice_generating_vector(rng, d, m_max)
+    C = net_generating_matrices(rng, d, m_max)
+    inst = []
+    for m, kind in zip(ms, kinds):
+        S = lms_matrices(rng, 1, d) if kind == "dnet" else None
+        D = shifts(rng, 1, d)
+        y = rng.standard_normal((1, nrhs, 2 ** int(m)))
+        inst.append(dict(kind=kind, m=int(m), lms=S, shift=D, y=y))
+    return dict(name="batch", d=d, nrhs=nrhs, m_max=m_max, lattice_gen=g, net_gen=C,
+                alpha=np.full(d, 2, np.int32),
+                gamma=1.0 / np.arange(1, d + 1, dtype=np.float64) ** 2, zeta=1.0,
+                sigma2=1e-8, instances=inst)
+
+
+def instance_workload(table: dict, i: int) -> dict:
+    """Instance i of a table as a one-replication workload dict."""
+    ins = table["instances"][i]
+    lat = ins["kind"] == "lattice"
+    return dict(kind=ins["kind"], order="natural", m=ins["m"], m_max=table["m_max"],
+                d=table["d"], R=1, gen=table["lattice_gen"] if lat else table["net_gen"],
+                lms=ins["lms"], shift=ins["shift"], alpha=table["alpha"], gamma=table["gamma"],
+                zeta=table["zeta"], sigma2=table["sigma2"], y=ins["y"], nrhs=table["nrhs"])
+
+
 def small_net(seed: int, m: int, d: int, R: int = 1, m_max: int | None = None,
               nrhs: int = 1) -> dict:
     """A random net instance of any size (LMS + digital shift)."""
