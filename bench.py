@@ -241,6 +241,8 @@ def main():
     if not args.no_batch:
         out["batched"] = batch_bench(args.batch_steps, args.warmup)
 
+    out["fwht_split16"] = fwht_bench(K)
+
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
 
@@ -364,6 +366,36 @@ def grad_bench(K, warmup):
         "f32_grad_rel_err_vs_f64": err,
         "dtype": "f32 kernel factors and transform of y; f64 eigenvalues, g, adjoint, sums",
     }
+
+
+def fwht_bench(K):
+    """The net workload's transform at n = 2^20 (one FP32 row of responses):
+    FP32 butterfly passes against the split-FP16 matrix-core passes, device
+    time per launch (graph replays) and each one's normwise error against the
+    FP64 transform of the same row."""
+    import numpy as np
+    import torch
+
+    import paper_2502_14256_amd as ldk
+    import workloads as W
+
+    w = W.workload(3)
+    x64 = torch.from_numpy(np.ascontiguousarray(w["y"][:, 0, :])).cuda()
+    x32 = x64.float()
+    ref = ldk.transform("dnet", x64)
+    y_b, y_m = torch.empty_like(x32), torch.empty_like(x32)
+    ms_b = time_graph(lambda: ldk.transform("dnet", x32, out=y_b), K)
+    ms_m = time_graph(lambda: ldk.fwht_split16(x32, out=y_m), K)
+
+    def err(y):
+        return float(torch.linalg.norm(y.double() - ref) / torch.linalg.norm(ref))
+
+    nbytes = 2 * 4 * x32.numel()
+    return {"n": x32.numel(), "fp32_butterflies_ms": round(ms_b, 5),
+            "split16_mfma_ms": round(ms_m, 5),
+            "fp32_butterflies_GB_s": round(nbytes / (ms_b * 1e-3) / 1e9, 1),
+            "split16_mfma_GB_s": round(nbytes / (ms_m * 1e-3) / 1e9, 1),
+            "fp32_butterflies_rel_err": err(y_b), "split16_mfma_rel_err": err(y_m)}
 
 
 def batch_bench(K, warmup):

@@ -239,6 +239,16 @@ int ldk_kernel_grad(const ldk_kernel *k, const ldk_pointset *ps, const uint64_t 
 size_t ldk_kernel_grad_workspace_bytes(int R, int d, int64_t n_min, int64_t n_max,
                                        int points_given);
 
+/* Orthonormal Walsh-Hadamard transform of B FP32 rows of n = 2^m (Sec. 5.3,
+ * the recursion of H_m) on the matrix cores: each radix-16 stage is one
+ * FP16 matrix instruction [H_16 | H_16] [X_hi ; X_lo] with FP32 sums, where
+ * X_hi + X_lo is a two-term FP16 split of the (power-of-two scaled) FP32
+ * data, redone before every stage (about 22 significant bits per stage;
+ * normwise error of order 1e-6 against the exact transform).  Same result
+ * as ldk_transform(LDK_DNET_B2, ..., LDK_F32, ...) up to that rounding.
+ * in, out = device float[B][n]; may alias exactly.  No workspace. */
+int ldk_fwht_split16(int B, int m, const float *in, float *out, ldk_stream stream);
+
 typedef enum {
     LDK_OP_TRANSFORM = 0,
     LDK_OP_EIG = 1,

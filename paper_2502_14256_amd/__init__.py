@@ -31,6 +31,7 @@ EXPORTS = [
     "ldk_matvec", "ldk_logdet", "ldk_update_double", "ldk_eig_update_double",
     "ldk_workspace_bytes", "ldk_strerror", "ldk_last_hip_error", "ldk_version",
     "ldk_mll", "ldk_mll_adjoint", "ldk_kernel_grad", "ldk_kernel_grad_workspace_bytes",
+    "ldk_fwht_split16",
 ]
 
 
@@ -79,6 +80,7 @@ def lib():
             "ldk_mll_adjoint": ([i32, i32, i32, P, P, P, P], i32),
             "ldk_kernel_grad": ([P, P, P, P, i64, i64, i32, P, P, P, P], i32),
             "ldk_kernel_grad_workspace_bytes": ([i32, i32, i64, i64, i32], C.c_size_t),
+            "ldk_fwht_split16": ([i32, i32, P, P, P], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -392,4 +394,17 @@ def kernel_grad(k: Kernel, ps: PointSet, n_min: int, n_max: int, a: torch.Tensor
     _check(lib().ldk_kernel_grad(C.byref(k._c()), C.byref(ps._c()), _ptr(pts), _ptr(x0), n_min,
                                  n_max, dt, _ptr(a), _ptr(out), _ptr(ws), _stream()),
            "ldk_kernel_grad")
+    return out
+
+
+def fwht_split16(x: torch.Tensor, out=None):
+    """Orthonormal FWHT of float32 rows on the matrix cores (split FP16)."""
+    _need(x, "x")
+    if x.dtype != torch.float32:
+        raise LdkError("fwht_split16 takes float32 rows")
+    n = x.shape[-1]
+    m = _m_of(n)
+    B = x.numel() // n
+    out = torch.empty_like(x) if out is None else out
+    _check(lib().ldk_fwht_split16(B, m, _ptr(x), _ptr(out), _stream()), "ldk_fwht_split16")
     return out

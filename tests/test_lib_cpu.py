@@ -183,3 +183,11 @@ def test_likelihood_workspace_sizes():
     assert g(3, 7, 100, 4197, 1) == 3 * 3 * 8 * 8
     assert g(0, 7, 0, 4096, 0) == 0
     assert ws(ldk.OP_MLL, ldk.LATTICE, 3, 0, 0) == 256  # n = 1 still sums
+
+
+def test_fwht_split16_rejects_bad_arguments():
+    L = ldk.lib()
+    assert L.ldk_fwht_split16(-1, 4, FAKE, FAKE, None) == -1
+    assert L.ldk_fwht_split16(1, 27, FAKE, FAKE, None) == -1
+    assert L.ldk_fwht_split16(1, 4, None, FAKE, None) == -1
+    assert L.ldk_fwht_split16(0, 4, None, None, None) == 0
