@@ -200,6 +200,70 @@ __device__ __forceinline__ void group_twiddle(T (&v)[E], int t, int gs, int s, i
     }
 }
 
+// The same group twiddles with the table reads hoisted: bases[g] =
+// W_{2^{s_g+LOGE}}^{r mod 2^{s_g}} for every full group g >= 1 of an A-bit
+// axis (group 0 sits at s = 0 and needs none), read once at kernel start so
+// that the table latency overlaps the data loads instead of stalling each
+// group.  apply_group_twiddle multiplies by the powers of one base.
+constexpr int MAX_GROUPS = 4;
+template <typename R, int LOGE>
+__device__ __forceinline__ void group_bases(cplx<R> (&bases)[MAX_GROUPS], int t, int A, int logW,
+                                            int T_)
+{
+    const int G = (A + LOGE - 1) / LOGE;
+    const int rem = A - LOGE * (G - 1);
+#pragma unroll
+    for (int g = 1; g < MAX_GROUPS; ++g) {
+        if (g < G) {
+            const int s = rem + LOGE * (g - 1);
+            const int q0 = group_q(t, 0, LOGE, logW + s, T_);
+            const uint32_t rlow = (uint32_t)(q0 >> logW) & ((1u << s) - 1);
+            bases[g] = tw_small<R>(rlow, s + LOGE);
+        }
+    }
+}
+template <typename T, int E, int LOGE, bool CONJ>
+__device__ __forceinline__ void apply_group_twiddle(T (&v)[E], const T &base)
+{
+    if constexpr (!std::is_floating_point<T>::value) {
+        using R = typename real_of<T>::type;
+        cplx<R> pw[E];
+        powers<R, E>(base, pw);
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const cplx<R> w = pw[brev_bits((uint32_t)i, LOGE)];
+            v[i] = CONJ ? cmulc(v[i], w) : cmul(v[i], w);
+        }
+    }
+}
+
+// Inter-pass twiddle with its table reads hoisted (see pass_twiddle_k1).
+template <typename R>
+struct PassTw {
+    cplx<R> base, step;
+};
+template <typename R, int LOGE>
+__device__ __forceinline__ PassTw<R> pass_tw_fetch(int t, uint64_t k1, int logW, int A, int b0)
+{
+    const uint64_t r0 = (uint64_t)(t >> logW);
+    return PassTw<R>{tw_any<R>((k1 * brev_bits((uint32_t)r0, A - LOGE)) << LOGE, b0 + A),
+                     tw_any<R>(k1, b0 + A)};
+}
+template <typename T, int E, int LOGE, bool CONJ>
+__device__ __forceinline__ void pass_tw_apply(T (&v)[E], const PassTw<typename real_of<T>::type> &p)
+{
+    if constexpr (!std::is_floating_point<T>::value) {
+        using R = typename real_of<T>::type;
+        cplx<R> pw[E];
+        powers<R, E>(p.step, pw);
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const cplx<R> w = cmul(p.base, pw[brev_bits((uint32_t)i, LOGE)]);
+            v[i] = CONJ ? cmulc(v[i], w) : cmul(v[i], w);
+        }
+    }
+}
+
 // Inter-pass twiddle W_{2^{b0+A}}^{k1 R_A(r)} for the coalesced pattern
 // q = t + Tn i: the column k1 is fixed per thread and
 // R_A(r) = R_{A-LOGE}(r0) 2^LOGE + R_LOGE(i), r0 = t >> logW, so the twiddles

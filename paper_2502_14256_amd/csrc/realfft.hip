@@ -82,6 +82,11 @@ __global__ __launch_bounds__(512) void k_real_top(PassArgs a, double *lam_out)
         for (int i = 0; i < E; ++i)
             v[i] = load_elem<T, LD, SRC_F32>(a.src, row * a.src_row + gidx(t + Tn * i), a.half);
     }
+    // twiddle table reads issued right behind the data loads
+    T gb[MAX_GROUPS];
+    group_bases<R, LOGE>(gb, t, A, logW, Tn);
+    PassTw<R> ptw{};
+    if (b0 > 0) ptw = pass_tw_fetch<R, LOGE>(t, (uint64_t)col_of(t & (W - 1)), logW, A, b0);
     // Per-element twiddle W_n^k and spectral factors, fetched after the
     // data loads are issued and before the transform, so that their latency
     // overlaps the data loads and the groups.
@@ -109,8 +114,7 @@ __global__ __launch_bounds__(512) void k_real_top(PassArgs a, double *lam_out)
     }
 
     if constexpr (MODE != PM_ADJ) {
-        if (b0 > 0)
-            pass_twiddle_k1<T, E, LOGE, false>(v, t, (uint64_t)col_of(t & (W - 1)), logW, A, b0);
+        if (b0 > 0) pass_tw_apply<T, E, LOGE, false>(v, ptw);
 
         // ---- forward transform over the axis bits (low groups first)
         if (G > 1) {
@@ -120,15 +124,15 @@ __global__ __launch_bounds__(512) void k_real_top(PassArgs a, double *lam_out)
             for (int gi = 0; gi < G - 1; ++gi) {
                 const int gs = gi == 0 ? rem : LOGE;
                 lds_read(v, lds, t, gs, logW + s, Tn);
-                group_twiddle<T, E, LOGE, false>(v, t, gs, s, logW, Tn);
+                if (gi > 0) apply_group_twiddle<T, E, LOGE, false>(v, gb[gi]);
                 reg_fwd<T, E, LOGE, false>(v, gs);
                 lds_write(v, lds, t, gs, logW + s, Tn);
                 __syncthreads();
                 s += gs;
             }
             lds_read(v, lds, t, LOGE, logW + top_s, Tn);
+            apply_group_twiddle<T, E, LOGE, false>(v, gb[G - 1]);
         }
-        group_twiddle<T, E, LOGE, false>(v, t, LOGE, G > 1 ? top_s : 0, logW, Tn);
         reg_fwd<T, E, LOGE, false>(v, LOGE);
 
         // ---- real-spectrum step: every element reads its partner N - k
@@ -190,8 +194,8 @@ __global__ __launch_bounds__(512) void k_real_top(PassArgs a, double *lam_out)
 
     // ---- inverse transform over the axis bits (top group first)
     reg_inv<T, E, LOGE>(v, LOGE);
-    group_twiddle<T, E, LOGE, true>(v, t, LOGE, G > 1 ? top_s : 0, logW, Tn);
     if (G > 1) {
+        apply_group_twiddle<T, E, LOGE, true>(v, gb[G - 1]);
         if constexpr (MODE != PM_ADJ) __syncthreads();  // partner reads are done
         lds_write(v, lds, t, LOGE, logW + top_s, Tn);
         __syncthreads();
@@ -201,13 +205,13 @@ __global__ __launch_bounds__(512) void k_real_top(PassArgs a, double *lam_out)
             s -= gs;
             lds_read(v, lds, t, gs, logW + s, Tn);
             reg_inv<T, E, LOGE>(v, gs);
-            group_twiddle<T, E, LOGE, true>(v, t, gs, s, logW, Tn);
+            if (gi > 0) apply_group_twiddle<T, E, LOGE, true>(v, gb[gi]);
             lds_write(v, lds, t, gs, logW + s, Tn);
             __syncthreads();
         }
         lds_read(v, lds, t, LOGE, logW + top_s, Tn);
     }
-    if (b0 > 0) pass_twiddle_k1<T, E, LOGE, true>(v, t, (uint64_t)col_of(t & (W - 1)), logW, A, b0);
+    if (b0 > 0) pass_tw_apply<T, E, LOGE, true>(v, ptw);
 #pragma unroll
     for (int i = 0; i < E; ++i)
         store_elem<T, ST>(a.dst, row * a.dst_row + gidx(t + Tn * i), v[i], a.half);

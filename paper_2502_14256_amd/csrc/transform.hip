@@ -52,10 +52,19 @@ __global__ __launch_bounds__(512) void k_pass(PassArgs a)
 #pragma unroll
     for (int i = 0; i < E; ++i)
         v[i] = load_elem<T, LD, SRC_F32>(a.src, row * a.src_row + gidx(t + Tn * i), a.half);
+    // twiddle table reads issued right behind the data loads (one latency)
+    T gb[MAX_GROUPS];
+    PassTw<R> ptw{};
+    if constexpr (FFT) {
+        group_bases<R, LOGE>(gb, t, A, logW, Tn);
+        if (a.global_tw)
+            ptw = pass_tw_fetch<R, LOGE>(t, (uint64_t)((cb << logW) + (t & ((1 << logW) - 1))),
+                                         logW, A, b0);
+    }
 
     if constexpr (MODE != PM_INV) {
         if constexpr (FFT) {
-            if (a.global_tw) pass_twiddle<T, E, LOGE, false>(v, t, cb, logW, A, b0);
+            if (a.global_tw) pass_tw_apply<T, E, LOGE, false>(v, ptw);
         }
         if (G > 1) {
             lds_write(v, lds, t, LOGE, logW + top_s, Tn);
@@ -64,15 +73,15 @@ __global__ __launch_bounds__(512) void k_pass(PassArgs a)
             for (int gidx_ = 0; gidx_ < G - 1; ++gidx_) {
                 const int gs = gidx_ == 0 ? rem : LOGE;
                 lds_read(v, lds, t, gs, logW + s, Tn);
-                group_twiddle<T, E, LOGE, false>(v, t, gs, s, logW, Tn);
+                if (gidx_ > 0) apply_group_twiddle<T, E, LOGE, false>(v, gb[gidx_]);
                 reg_fwd<T, E, LOGE, false>(v, gs);
                 lds_write(v, lds, t, gs, logW + s, Tn);
                 __syncthreads();
                 s += gs;
             }
             lds_read(v, lds, t, LOGE, logW + top_s, Tn);
+            apply_group_twiddle<T, E, LOGE, false>(v, gb[G - 1]);
         }
-        group_twiddle<T, E, LOGE, false>(v, t, LOGE, G > 1 ? top_s : 0, logW, Tn);
         reg_fwd<T, E, LOGE, false>(v, LOGE);
     }
 
@@ -88,8 +97,8 @@ __global__ __launch_bounds__(512) void k_pass(PassArgs a)
 
     if constexpr (MODE != PM_FWD) {
         reg_inv<T, E, LOGE>(v, LOGE);
-        group_twiddle<T, E, LOGE, true>(v, t, LOGE, G > 1 ? top_s : 0, logW, Tn);
         if (G > 1) {
+            apply_group_twiddle<T, E, LOGE, true>(v, gb[G - 1]);
             if constexpr (MODE != PM_INV) __syncthreads();  // LDS reuse after the forward half
             lds_write(v, lds, t, LOGE, logW + top_s, Tn);
             __syncthreads();
@@ -99,14 +108,14 @@ __global__ __launch_bounds__(512) void k_pass(PassArgs a)
                 s -= gs;
                 lds_read(v, lds, t, gs, logW + s, Tn);
                 reg_inv<T, E, LOGE>(v, gs);
-                group_twiddle<T, E, LOGE, true>(v, t, gs, s, logW, Tn);
+                if (gi > 0) apply_group_twiddle<T, E, LOGE, true>(v, gb[gi]);
                 lds_write(v, lds, t, gs, logW + s, Tn);
                 __syncthreads();
             }
             lds_read(v, lds, t, LOGE, logW + top_s, Tn);
         }
         if constexpr (FFT) {
-            if (a.global_tw) pass_twiddle<T, E, LOGE, true>(v, t, cb, logW, A, b0);
+            if (a.global_tw) pass_tw_apply<T, E, LOGE, true>(v, ptw);
         }
     }
 
