@@ -179,6 +179,22 @@ int ldk_matvec(int kind, int R, int nrhs, int m, int dtype, const double *lam, c
 int ldk_logdet(int R, int m, const double *lam, double sigma2, double *out, void *ws,
                ldk_stream stream);
 
+/* The fit of Sec. 5.4 in one call: lam = eigenvalues of k1 (as ldk_eig),
+ * c = (K + sigma^2 I)^-1 y (as ldk_solve, nrhs right-hand sides per
+ * replication; nrhs may be 0) and, if logdet != NULL, logdet[r] (as
+ * ldk_logdet).  Lattice rows in FP64 with n >= 4 share launches: the
+ * column's and the right-hand sides' forward passes run as one launch, and
+ * the pass that forms the eigenvalues also sums their logarithms per tile,
+ * so the log-det costs one small reduction instead of a pass over lambda.
+ * Other cases run the three entry points in turn.  lam and c equal the
+ * separate calls bit for bit; the log-det to rounding (another fixed
+ * summation order).
+ * k1 = dtype[R][n]; y, c = dtype[R][nrhs][n]; lam = double[R][n];
+ * logdet = device double[R].
+ * ws: ldk_workspace_bytes(LDK_OP_FIT, kind, R * (nrhs + 1), m, dtype) bytes. */
+int ldk_fit(int kind, int R, int nrhs, int m, int dtype, const void *k1, double sigma2,
+            const void *y, double *lam, void *c, double *logdet, void *ws, ldk_stream stream);
+
 /* Transform update when n doubles (Sec. 5.4, eq. ft_next_parts and its listings):
  *   yt_full = 2^-1/2 [ yt_old + w (.) FT_m(y_new) ; yt_old - w (.) FT_m(y_new) ],
  * w_k = exp(-pi i k / n) (lattice, FT = FFTBR) or 1 (net, FT = FWHT).
@@ -258,7 +274,8 @@ typedef enum {
     LDK_OP_UPDATE_DOUBLE = 5,
     LDK_OP_EIG_UPDATE_DOUBLE = 6,
     LDK_OP_MLL = 7,
-    LDK_OP_MLL_ADJOINT = 8
+    LDK_OP_MLL_ADJOINT = 8,
+    LDK_OP_FIT = 9
 } ldk_op;
 
 /* Workspace bytes needed by `op` for B rows (or R * nrhs rows) of 2^m. */

@@ -24,14 +24,14 @@ LATTICE, DNET_B2 = 0, 1
 NATURAL, LINEAR, GRAY = 0, 1, 2
 F64, F32 = 0, 1
 (OP_TRANSFORM, OP_EIG, OP_SOLVE, OP_MATVEC, OP_LOGDET, OP_UPDATE_DOUBLE, OP_EIG_UPDATE_DOUBLE,
- OP_MLL, OP_MLL_ADJOINT) = range(9)
+ OP_MLL, OP_MLL_ADJOINT, OP_FIT) = range(10)
 
 EXPORTS = [
     "ldk_init", "ldk_gen_points", "ldk_kernel_column", "ldk_transform", "ldk_eig", "ldk_solve",
     "ldk_matvec", "ldk_logdet", "ldk_update_double", "ldk_eig_update_double",
     "ldk_workspace_bytes", "ldk_strerror", "ldk_last_hip_error", "ldk_version",
     "ldk_mll", "ldk_mll_adjoint", "ldk_kernel_grad", "ldk_kernel_grad_workspace_bytes",
-    "ldk_fwht_split16",
+    "ldk_fwht_split16", "ldk_fit",
 ]
 
 
@@ -81,6 +81,7 @@ def lib():
             "ldk_kernel_grad": ([P, P, P, P, i64, i64, i32, P, P, P, P], i32),
             "ldk_kernel_grad_workspace_bytes": ([i32, i32, i64, i64, i32], C.c_size_t),
             "ldk_fwht_split16": ([i32, i32, P, P, P], i32),
+            "ldk_fit": ([i32, i32, i32, i32, i32, P, f64, P, P, P, P, P, P], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -301,6 +302,35 @@ def logdet(lam: torch.Tensor, sigma2: float, out=None, ws=None):
     _check(lib().ldk_logdet(R, m, _ptr(lam), float(sigma2), _ptr(out), _ptr(ws), _stream()),
            "ldk_logdet")
     return out
+
+
+def fit(kind, k1: torch.Tensor, sigma2: float, y: torch.Tensor, lam=None, c=None,
+        logdet: bool | torch.Tensor = True, ws=None):
+    """Eigenvalues, solves and log-det in one call: (lam, c, logdet or None).
+    y: [R][nrhs][n] of k1's dtype."""
+    kd = _kind(kind)
+    _need(k1, "k1")
+    _need(y, "y")
+    dt = _dtype_code(k1.dtype)
+    if y.dtype != k1.dtype:
+        raise LdkError("k1 and y must share a dtype")
+    R, n = k1.shape
+    nrhs = y.shape[1]
+    m = _m_of(n)
+    dev = k1.device
+    lam = torch.empty((R, n), dtype=torch.float64, device=dev) if lam is None else lam
+    _need_f64(lam, "lam")
+    c = torch.empty_like(y) if c is None else c
+    ld = None
+    if logdet is True:
+        ld = torch.empty(R, dtype=torch.float64, device=dev)
+    elif isinstance(logdet, torch.Tensor):
+        ld = logdet
+    if ws is None:
+        ws = _workspace(OP_FIT, kd, R * (nrhs + 1), m, dt, dev)
+    _check(lib().ldk_fit(kd, R, nrhs, m, dt, _ptr(k1), float(sigma2), _ptr(y), _ptr(lam), _ptr(c),
+                         _ptr(ld), _ptr(ws), _stream()), "ldk_fit")
+    return lam, c, ld
 
 
 def update_double(kind, yt_old: torch.Tensor, y_new: torch.Tensor, out=None):

@@ -356,8 +356,18 @@ int real_apply(int dtype, int mode, int m, int64_t rows, int nrhs, const double 
     return LDK_OK;
 }
 
+// The fused fit (lattice, FP64, n >= 4): eigenvalues, every solve and the
+// log-det share the tile passes of the half-length packed transforms.
+bool fit_fused(int kind, int m, int dtype) { return kind == LDK_LATTICE && m >= 2 && dtype == LDK_F64; }
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Fit workspace for B = R (nrhs + 1) rows: [log-det partials | column rows | rhs rows].
+size_t fit_ws_bytes(int kind, int64_t B, int m, int dtype);
+
 size_t ws_bytes(int op, int kind, int64_t B, int m, int dtype)
 {
+    if (op == LDK_OP_FIT) return fit_ws_bytes(kind, B, m, dtype);
     if (op == LDK_OP_MLL || op == LDK_OP_MLL_ADJOINT) return mll_ws_bytes(op, kind, B, m, dtype);
     if (m == 0) return op == LDK_OP_LOGDET ? (size_t)B * sizeof(double) : 0;
     const bool lat = kind == LDK_LATTICE;
@@ -390,6 +400,26 @@ size_t ws_bytes(int op, int kind, int64_t B, int m, int dtype)
     case LDK_OP_EIG_UPDATE_DOUBLE: return lat ? cplx_rows_bytes(B, m, LDK_F64) : 0;
     default: return 0;
     }
+}
+
+size_t fit_ws_bytes(int kind, int64_t B, int m, int dtype)
+{
+    // eig, solve and log-det one after the other, sharing the workspace (the
+    // path taken when the fused one does not apply, and for nrhs = 0)
+    size_t w = ws_bytes(LDK_OP_EIG, kind, B, m, dtype);
+    if (fit_fused(kind, m, dtype)) {
+        const Plan pl = make_plan(m - 1, log_tile_for(LDK_LATTICE, LDK_F64));
+        const PassGeom &top = pl.pass[pl.P - 1];
+        const size_t cb = (size_t)1 << (top.b0 - top.logW);
+        const size_t rows = pl.P > 1 ? (size_t)B * ((size_t)1 << (m - 1)) * 16 : 0;
+        const size_t f = align256((size_t)B * cb * sizeof(double)) + rows;
+        if (f > w) w = f;
+    }
+    const size_t ws = ws_bytes(LDK_OP_SOLVE, kind, B, m, dtype);
+    const size_t wl = ws_bytes(LDK_OP_LOGDET, kind, B, m, dtype);
+    if (ws > w) w = ws;
+    if (wl > w) w = wl;
+    return w;
 }
 
 }  // namespace
@@ -529,6 +559,101 @@ int ldk_logdet(int R, int m, const double *lam, double sigma2, double *out, void
     LDK_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_logdet_final, dim3(R), dim3(LOGDET_THREADS), 0, s, partial, chunks, out);
     LDK_LAUNCH_CHECK();
+    return LDK_OK;
+}
+
+int ldk_fit(int kind, int R, int nrhs, int m, int dtype, const void *k1, double sigma2,
+            const void *y, double *lam, void *c, double *logdet, void *ws, ldk_stream stream)
+{
+    if (!valid_kind(kind) || !valid_dtype(dtype) || !valid_m(m) || R < 0 || R > 65535 || nrhs < 0)
+        return LDK_EINVAL;
+    if (!(sigma2 >= 0.0)) return LDK_EINVAL;
+    if (R == 0) return LDK_OK;
+    if (!k1 || !lam || (nrhs > 0 && (!y || !c))) return LDK_EINVAL;
+    const int64_t B = (int64_t)R * (nrhs + 1);
+    if (fit_ws_bytes(kind, B, m, dtype) && !ws) return LDK_EINVAL;
+    int st;
+    if (!fit_fused(kind, m, dtype) || nrhs == 0) {
+        st = ldk_eig(kind, R, m, dtype, k1, lam, ws, stream);
+        if (st) return st;
+        if (nrhs > 0) {
+            st = ldk_solve(kind, R, nrhs, m, dtype, lam, sigma2, y, c, ws, stream);
+            if (st) return st;
+        }
+        return logdet ? ldk_logdet(R, m, lam, sigma2, logdet, ws, stream) : LDK_OK;
+    }
+    st = ensure_init();
+    if (st) return st;
+    hipStream_t s = as_stream(stream);
+    const int mp = m - 1;
+    const int64_t n = (int64_t)1 << m, N = n / 2;
+    const Plan pl = make_plan(mp, log_tile_for(LDK_LATTICE, LDK_F64));
+    const PassGeom &top = pl.pass[pl.P - 1];
+    const int cb_count = 1 << (top.b0 - top.logW);
+    unsigned char *w8 = static_cast<unsigned char *>(ws);
+    double *partial = reinterpret_cast<double *>(w8);
+    void *wsK = w8 + align256((size_t)B * cb_count * sizeof(double));
+    void *wsY = static_cast<unsigned char *>(wsK) + (size_t)R * N * 16;
+    PassArgs aK{}, aY{};
+    aK.rows = R;
+    aK.nrhs = 1;
+    aY.rows = (int64_t)R * nrhs;
+    aY.nrhs = nrhs;
+    aK.m = aY.m = mp;
+    aK.half = aY.half = N;
+    aK.sigma2 = aY.sigma2 = sigma2;
+    aK.scale = 1.0;
+    aY.lam = lam;
+    // forward passes below the top one: column and right-hand sides in one launch
+    for (int p = 0; p < pl.P - 1; ++p) {
+        PassArgs k0 = aK, y0 = aY;
+        k0.src = p == 0 ? k1 : (const void *)wsK;
+        y0.src = p == 0 ? y : (const void *)wsY;
+        k0.src_row = y0.src_row = p == 0 ? n : N;
+        k0.dst = wsK;
+        y0.dst = wsY;
+        k0.dst_row = y0.dst_row = N;
+        k0.g = y0.g = pl.pass[p];
+        k0.global_tw = y0.global_tw = p > 0;
+        k0.scale = y0.scale = 1.0;
+        y0.lam = nullptr;
+        st = launch_pass2(LDK_LATTICE, LDK_F64, PM_FWD, p == 0 ? PIO_PACKED : PIO_SAME, PIO_SAME, k0,
+                          y0, s);
+        if (st) return st;
+    }
+    // top passes: eigenvalues (+ log-det partial sums), then the filtered solves
+    const bool single = pl.P == 1;
+    aK.src = single ? k1 : (const void *)wsK;
+    aK.src_row = single ? n : N;
+    aY.src = single ? y : (const void *)wsY;
+    aY.dst = single ? c : wsY;
+    aY.src_row = aY.dst_row = single ? n : N;
+    aK.g = aY.g = top;
+    aK.global_tw = aY.global_tw = !single;
+    aY.scale = 1.0 / (double)N;
+    st = launch_real_top(LDK_F64, PM_FWD, aK, lam, s, false, logdet ? partial : nullptr);
+    if (st) return st;
+    st = launch_real_top(LDK_F64, PM_SOLVE, aY, nullptr, s);
+    if (st) return st;
+    // inverse passes of the right-hand sides
+    for (int p = pl.P - 2; p >= 0; --p) {
+        PassArgs b = aY;
+        b.lam = nullptr;
+        b.src = wsY;
+        b.src_row = N;
+        b.dst = p == 0 ? c : wsY;
+        b.dst_row = p == 0 ? n : N;
+        b.g = pl.pass[p];
+        b.global_tw = p > 0;
+        b.scale = 1.0;
+        st = launch_pass(LDK_LATTICE, LDK_F64, PM_INV, PIO_SAME, p == 0 ? PIO_PACKED : PIO_SAME, b, s);
+        if (st) return st;
+    }
+    if (logdet) {
+        hipLaunchKernelGGL(k_logdet_final, dim3(R), dim3(LOGDET_THREADS), 0, s,
+                           (const double *)partial, cb_count, logdet);
+        LDK_LAUNCH_CHECK();
+    }
     return LDK_OK;
 }
 

@@ -39,8 +39,12 @@ using namespace kit;
 
 namespace {
 
+// One tile (row, column block cb) of the top pass.  ld_part (PM_FWD only,
+// may be NULL): receives this tile's sum of log(lambda + sigma2) over its 2 S
+// eigenvalues at ld_part[row * cb_count + cb] (NaN if some lambda + s2 <= 0).
 template <typename T, int LOGE, int MODE, int LD, int ST, bool SRC_F32>
-__global__ __launch_bounds__(512) void k_real_top(PassArgs a, double *lam_out)
+__device__ __forceinline__ void real_top_body(const PassArgs &a, double *lam_out, int64_t row,
+                                              int64_t cb, double *ld_part)
 {
     using R = typename real_of<T>::type;
     constexpr int E = 1 << LOGE;
@@ -56,9 +60,6 @@ __global__ __launch_bounds__(512) void k_real_top(PassArgs a, double *lam_out)
     const int Tn = S >> LOGE;
     const int t = threadIdx.x;
     const int64_t cb_count = N1 >> logW;
-    const int64_t bid = xcd_tile(blockIdx.x, gridDim.x);
-    const int64_t cb = bid % cb_count;
-    const int64_t row = bid / cb_count;
     const bool last = cb == cb_count - 1;
 
     auto col_of = [&](int w) -> int64_t {
@@ -140,6 +141,7 @@ __global__ __launch_bounds__(512) void k_real_top(PassArgs a, double *lam_out)
         lds_write(v, lds, t, LOGE, logW + top_s, Tn);
         __syncthreads();
     }
+    double lsum = 0.0;  // PM_FWD with ld_part: sum of log(lambda + s2)
 #pragma unroll
     for (int i = 0; i < E; ++i) {
         const int q = t + Tn * i;
@@ -177,6 +179,11 @@ __global__ __launch_bounds__(512) void k_real_top(PassArgs a, double *lam_out)
         if constexpr (MODE == PM_FWD) {
             lam_out[row * n + k] = (double)yk.re;
             lam_out[row * n + k + N] = (double)ykn.re;
+            if (ld_part) {
+                const double sa = (double)yk.re + a.sigma2, sb = (double)ykn.re + a.sigma2;
+                lsum += (sa > 0.0 ? log(sa) : __builtin_nan("")) +
+                        (sb > 0.0 ? log(sb) : __builtin_nan(""));
+            }
         } else if constexpr (MODE == PM_POWER) {
             lam_out[row * n + k] = (double)yk.re * (double)yk.re + (double)yk.im * (double)yk.im;
             lam_out[row * n + k + N] =
@@ -190,7 +197,23 @@ __global__ __launch_bounds__(512) void k_real_top(PassArgs a, double *lam_out)
             v[i] = T{ep.re - op.im, ep.im + op.re};
         }
     }
-    if constexpr (MODE == PM_FWD || MODE == PM_POWER) return;
+    if constexpr (MODE == PM_FWD) {
+        if (ld_part) {
+            // block sum in a fixed order: lanes, then waves
+            __shared__ double red[8];
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
+            if ((t & 63) == 0) red[t >> 6] = lsum;
+            __syncthreads();
+            if (t == 0) {
+                double s = 0.0;
+                for (int w8 = 0; w8 < (Tn + 63) / 64; ++w8) s += red[w8];
+                ld_part[row * cb_count + cb] = s;
+            }
+        }
+        return;
+    }
+    if constexpr (MODE == PM_POWER) return;
 
     // ---- inverse transform over the axis bits (top group first)
     reg_inv<T, E, LOGE>(v, LOGE);
@@ -218,7 +241,16 @@ __global__ __launch_bounds__(512) void k_real_top(PassArgs a, double *lam_out)
 }
 
 template <typename T, int LOGE, int MODE, int LD, int ST, bool SRC_F32>
-int launch_rt(const PassArgs &a, double *lam_out, hipStream_t s)
+__global__ __launch_bounds__(512) void k_real_top(PassArgs a, double *lam_out, double *ld_part)
+{
+    const int64_t cb_count = ((int64_t)1 << a.g.b0) >> a.g.logW;
+    const int64_t bid = xcd_tile(blockIdx.x, gridDim.x);
+    real_top_body<T, LOGE, MODE, LD, ST, SRC_F32>(a, lam_out, bid / cb_count, bid % cb_count,
+                                                  ld_part);
+}
+
+template <typename T, int LOGE, int MODE, int LD, int ST, bool SRC_F32>
+int launch_rt(const PassArgs &a, double *lam_out, hipStream_t s, double *ld_part = nullptr)
 {
     const int S = 1 << (a.g.a + a.g.logW);
     const int threads = S >> LOGE;
@@ -228,18 +260,18 @@ int launch_rt(const PassArgs &a, double *lam_out, hipStream_t s)
     if (a.g.b0 > 0 && a.g.logW < 1) return LDK_ENOTSUP;  // mirror runs need W >= 2
     const size_t lds = (size_t)(S + (S >> LDS_PAD_SHIFT)) * sizeof(T);
     hipLaunchKernelGGL((k_real_top<T, LOGE, MODE, LD, ST, SRC_F32>), dim3((unsigned)blocks),
-                       dim3(threads), lds, s, a, lam_out);
+                       dim3(threads), lds, s, a, lam_out, ld_part);
     LDK_LAUNCH_CHECK();
     return LDK_OK;
 }
 
 template <typename T, int MODE, int LD, int ST, bool SRC_F32>
-int launch_rt_e(const PassArgs &a, double *lam_out, hipStream_t s)
+int launch_rt_e(const PassArgs &a, double *lam_out, hipStream_t s, double *ld_part = nullptr)
 {
     switch (a.g.logE) {
-    case 1: return launch_rt<T, 1, MODE, LD, ST, SRC_F32>(a, lam_out, s);
-    case 2: return launch_rt<T, 2, MODE, LD, ST, SRC_F32>(a, lam_out, s);
-    case 3: return launch_rt<T, 3, MODE, LD, ST, SRC_F32>(a, lam_out, s);
+    case 1: return launch_rt<T, 1, MODE, LD, ST, SRC_F32>(a, lam_out, s, ld_part);
+    case 2: return launch_rt<T, 2, MODE, LD, ST, SRC_F32>(a, lam_out, s, ld_part);
+    case 3: return launch_rt<T, 3, MODE, LD, ST, SRC_F32>(a, lam_out, s, ld_part);
     default: return LDK_ENOTSUP;
     }
 }
@@ -255,7 +287,7 @@ int launch_rt_io(bool single, const PassArgs &a, double *lam_out, hipStream_t s)
 }  // namespace
 
 int launch_real_top(int dtype, int mode, const PassArgs &a, double *lam_out, hipStream_t s,
-                    bool src_f32)
+                    bool src_f32, double *ld_part)
 {
     const bool single = a.g.b0 == 0;
     if (mode == PM_FWD) {
@@ -263,11 +295,15 @@ int launch_real_top(int dtype, int mode, const PassArgs &a, double *lam_out, hip
         if (dtype != LDK_F64 || !lam_out) return LDK_EINVAL;
         if (src_f32) {
             if (!single) return LDK_EINVAL;  // float sources only feed the first pass
-            return launch_rt_e<cplx<double>, PM_FWD, IO_PACKED, IO_SAME, true>(a, lam_out, s);
+            return launch_rt_e<cplx<double>, PM_FWD, IO_PACKED, IO_SAME, true>(a, lam_out, s,
+                                                                                ld_part);
         }
-        if (single) return launch_rt_e<cplx<double>, PM_FWD, IO_PACKED, IO_SAME, false>(a, lam_out, s);
-        return launch_rt_e<cplx<double>, PM_FWD, IO_SAME, IO_SAME, false>(a, lam_out, s);
+        if (single)
+            return launch_rt_e<cplx<double>, PM_FWD, IO_PACKED, IO_SAME, false>(a, lam_out, s,
+                                                                                 ld_part);
+        return launch_rt_e<cplx<double>, PM_FWD, IO_SAME, IO_SAME, false>(a, lam_out, s, ld_part);
     }
+    if (ld_part) return LDK_EINVAL;  // log-det partials come with the eigenvalues only
     if (src_f32) return LDK_EINVAL;
     if (mode == PM_POWER) {
         if (!lam_out) return LDK_EINVAL;

@@ -14,7 +14,7 @@ namespace {
 
 // One pass over a tile: rows = 2^a along the axis, W = 2^logW columns.
 template <typename T, int LOGE, int MODE, int LD, int ST, bool SRC_F32>
-__global__ __launch_bounds__(512) void k_pass(PassArgs a)
+__device__ __forceinline__ void pass_body(const PassArgs &a, int64_t bid)
 {
     using R = typename real_of<T>::type;
     constexpr int E = 1 << LOGE;
@@ -29,7 +29,6 @@ __global__ __launch_bounds__(512) void k_pass(PassArgs a)
     // block -> (row, outer, column block)
     const int64_t cb_count = (int64_t)1 << (b0 - logW);
     const int64_t outer_count = (int64_t)1 << (a.m - b0 - A);
-    int64_t bid = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t cb = bid % cb_count;
     bid /= cb_count;
     const int64_t outer = bid % outer_count;
@@ -127,6 +126,21 @@ __global__ __launch_bounds__(512) void k_pass(PassArgs a)
         if (MODE == PM_FWD || MODE == PM_INV) o = scl(o, sc);
         store_elem<T, ST>(a.dst, row * a.dst_row + gidx(t + Tn * i), o, a.half);
     }
+}
+
+template <typename T, int LOGE, int MODE, int LD, int ST, bool SRC_F32>
+__global__ __launch_bounds__(512) void k_pass(PassArgs a)
+{
+    pass_body<T, LOGE, MODE, LD, ST, SRC_F32>(a, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+// Two jobs in one grid: the first nb0 tiles (after the XCD order) are job 0.
+template <typename T, int LOGE, int MODE, int LD, int ST, bool SRC_F32>
+__global__ __launch_bounds__(512) void k_pass2(PassArgs a0, PassArgs a1, int64_t nb0)
+{
+    const int64_t b = xcd_tile(blockIdx.x, gridDim.x);
+    if (b < nb0) pass_body<T, LOGE, MODE, LD, ST, SRC_F32>(a0, b);
+    else pass_body<T, LOGE, MODE, LD, ST, SRC_F32>(a1, b - nb0);
 }
 
 template <typename T, int LOGE, int MODE, bool SRC_F32>
@@ -244,6 +258,54 @@ int launch_pass(int kind, int dtype, int mode, int ld, int st, const PassArgs &a
     }
     if (dtype == LDK_F64) return launch_m<cplx<double>>(mode, ld, st, a, s);
     return launch_m<cplx<float>>(mode, ld, st, a, s);
+}
+
+}  // namespace ldk
+
+namespace ldk {
+
+namespace {
+template <typename T, int LOGE, int LD>
+int launch_fwd2(const PassArgs &a0, const PassArgs &a1, hipStream_t s)
+{
+    const int S = 1 << (a0.g.a + a0.g.logW);
+    const int threads = S >> LOGE;
+    const int64_t per_row = (int64_t)1 << (a0.m - a0.g.a - a0.g.logW);
+    const int64_t nb0 = a0.rows * per_row, nb1 = a1.rows * per_row;
+    if (nb0 + nb1 > 0x7fffffff || threads > 512 || threads < 1) return LDK_ENOTSUP;
+    const size_t lds = (size_t)(S + (S >> LDS_PAD_SHIFT)) * sizeof(T);
+    hipLaunchKernelGGL((k_pass2<T, LOGE, PM_FWD, LD, IO_SAME, false>), dim3((unsigned)(nb0 + nb1)),
+                       dim3(threads), lds, s, a0, a1, nb0);
+    LDK_LAUNCH_CHECK();
+    return LDK_OK;
+}
+template <typename T, int LD>
+int launch_fwd2_e(const PassArgs &a0, const PassArgs &a1, hipStream_t s)
+{
+    switch (a0.g.logE) {
+    case 1: return launch_fwd2<T, 1, LD>(a0, a1, s);
+    case 2: return launch_fwd2<T, 2, LD>(a0, a1, s);
+    case 3: return launch_fwd2<T, 3, LD>(a0, a1, s);
+    default: return LDK_ENOTSUP;
+    }
+}
+}  // namespace
+
+int launch_pass2(int kind, int dtype, int mode, int ld, int st, const PassArgs &a0,
+                 const PassArgs &a1, hipStream_t s)
+{
+    // forward FP64 passes only (the fused fit's column and right-hand sides)
+    if (mode != PM_FWD || dtype != LDK_F64 || st != IO_SAME) return LDK_ENOTSUP;
+    if (a0.m != a1.m || a0.g.b0 != a1.g.b0 || a0.g.a != a1.g.a || a0.g.logW != a1.g.logW ||
+        a0.g.logE != a1.g.logE)
+        return LDK_EINVAL;
+    if (kind == LDK_LATTICE) {
+        if (ld == IO_PACKED) return launch_fwd2_e<cplx<double>, IO_PACKED>(a0, a1, s);
+        if (ld == IO_SAME) return launch_fwd2_e<cplx<double>, IO_SAME>(a0, a1, s);
+        return LDK_ENOTSUP;
+    }
+    if (ld != IO_SAME) return LDK_ENOTSUP;
+    return launch_fwd2_e<double, IO_SAME>(a0, a1, s);
 }
 
 }  // namespace ldk

@@ -82,8 +82,14 @@ int launch_pass(int kind, int dtype, int mode, int ld, int st, const PassArgs &a
 // for PM_POWER (FP64 rows of 2N).  PM_ADJ reads a real spectrum from a.lam
 // and runs only the inverse half.  With one pass (b0 = 0) the source and
 // destination rows are packed real rows.
+// ld_part (PM_FWD only, may be NULL): per-tile sums of log(lambda + a.sigma2),
+// [rows][tiles per row], for a log-det finished by one reduction kernel.
 int launch_real_top(int dtype, int mode, const PassArgs &a, double *lam_out, hipStream_t s,
-                    bool src_f32 = false);
+                    bool src_f32 = false, double *ld_part = nullptr);
+
+// Two jobs of the same pass kind in one launch (blocks of job 0, then job 1).
+int launch_pass2(int kind, int dtype, int mode, int ld, int st, const PassArgs &a0,
+                 const PassArgs &a1, hipStream_t s);
 
 // Workspace bytes of LDK_OP_MLL / LDK_OP_MLL_ADJOINT (mll.hip).
 size_t mll_ws_bytes(int op, int kind, int64_t R, int m, int dtype);
