@@ -22,8 +22,8 @@ from dataclasses import dataclass
 import numpy as np
 import torch
 
-from . import (LdkError, Kernel, OP_EIG, OP_LOGDET, OP_SOLVE, PointSet, _dtype_code, _kind,
-               _workspace, eig, kernel_column, logdet, solve)
+from . import (LdkError, Kernel, OP_EIG, OP_FIT, OP_LOGDET, OP_SOLVE, PointSet, _dtype_code,
+               _kind, _workspace, eig, fit, kernel_column, logdet, solve)
 
 
 def _dev_u64(a) -> torch.Tensor:
@@ -88,26 +88,24 @@ class BatchFit:
                      lam=torch.empty((R, n), dtype=torch.float64, device="cuda"),
                      c=torch.empty_like(y),
                      ld=torch.empty(R, dtype=torch.float64, device="cuda"),
-                     ws_eig=_workspace(OP_EIG, kd, R, m, dt, "cuda"),
-                     ws_solve=_workspace(OP_SOLVE, kd, R * nrhs, m, dt, "cuda"),
-                     ws_ld=_workspace(OP_LOGDET, kd, R, m, dt, "cuda"))
+                     ws_fit=_workspace(OP_FIT, kd, R * (nrhs + 1), m, dt, "cuda"))
             for row, i in enumerate(members):
                 self.where[i] = (gi, row)
             self.groups.append(g)
         self.graph = None
 
     def step(self):
-        """Enqueue the whole table on the current stream."""
+        """Enqueue the whole table on the current stream: per group, the
+        first column, then eigenvalues, solves and log-det in one fit call."""
         for g in self.groups:
             kernel_column(g["kern"], g["ps"], 0, g["n"], dtype=self.dtype, out=g["k1"])
-            eig(g["kind"], g["k1"], out=g["lam"], ws=g["ws_eig"])
-            solve(g["kind"], g["lam"], self.sigma2, g["y"], out=g["c"], ws=g["ws_solve"])
-            logdet(g["lam"], self.sigma2, out=g["ld"], ws=g["ws_ld"])
+            fit(g["kind"], g["k1"], self.sigma2, g["y"], lam=g["lam"], c=g["c"], logdet=g["ld"],
+                ws=g["ws_fit"])
 
     def step_plain(self):
-        """The same work issued instance by instance (one launch of every op
-        per instance, on row views of the same buffers): the unbatched
-        reference the batched step is compared with."""
+        """The same work issued instance by instance with the separate entry
+        points (one launch of every op per instance, on row views of the same
+        buffers): the unbatched reference the batched step is compared with."""
         if not hasattr(self, "_plain"):
             self._plain = []
             for g in self.groups:

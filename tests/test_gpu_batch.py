@@ -54,7 +54,7 @@ def test_batched_equals_single_calls(table, dtype):
         c, ld = b.result(i)
         c1, ld1 = _single(table, i, dtype)
         assert torch.equal(c, c1), i
-        assert torch.equal(ld, ld1), i
+        assert torch.allclose(ld, ld1, rtol=1e-13, atol=1e-12, equal_nan=True), i
 
 
 def test_plain_step_equals_batched(table):
@@ -64,7 +64,10 @@ def test_plain_step_equals_batched(table):
     b.step_plain()
     for i in range(len(MS)):
         c, ld = b.result(i)
-        assert torch.equal(c, ref[i][0]) and torch.equal(ld, ref[i][1]), i
+        # the batched step fits with ldk_fit: the same solutions, the log-det
+        # summed in another fixed order
+        assert torch.equal(c, ref[i][0]), i
+        assert torch.allclose(ld, ref[i][1], rtol=1e-13, atol=1e-12), i
 
 
 def test_batched_matches_oracle(table):
