@@ -335,7 +335,7 @@ def grad_bench(K, warmup):
             "mll": mll,
             "mll_adjoint": lambda: ldk.mll_adjoint("dnet", b["g"], out=b["a"]),
             "kernel_grad": lambda: ldk.kernel_grad(kern, ps, 0, n, b["a"], dtype=dt, out=b["kg"],
-                                                   ws=b["ws_grad"]),
+                                                   ws=b["ws_grad"], k1=b["k1"]),
         }
 
     names = ["kernel_column", "eig", "mll", "mll_adjoint", "kernel_grad"]
@@ -357,7 +357,9 @@ def grad_bench(K, warmup):
                        per_op={nm: time_graph(ops[nm], K) for nm in names})
     r32, r64 = res[torch.float32], res[torch.float64]
     err = float(np.max(np.abs(r32["grad"] - r64["grad"])) / np.max(np.abs(r64["grad"])))
-    evals = 2 * R * n * d  # factor evaluations of the gradient kernel (two sweeps)
+    # factor evaluations of the gradient kernel: one sweep, the forward
+    # column supplies the product of the factors
+    evals = R * n * d
     kg_ms = r32["per_op"]["kernel_grad"]
     return {
         "workload": "net_m16_d64_r64_dsi2_grad (64 replications of an LMS+DS base-2 net, "

@@ -247,11 +247,15 @@ int ldk_mll_adjoint(int kind, int R, int m, const double *g, double *a, void *ws
  * restrictions apply); dtype = precision of the factor evaluation (the
  * products of the other factors are formed without dividing by a factor
  * that is exactly zero); the sums are FP64, in a fixed order.
+ * k1 (optional, may be NULL): the column ldk_kernel_column returned for the
+ * same arguments and dtype; the factors are formed bit for bit as there, so
+ * the product of the other factors is k1_i / f_ij and one sweep over the
+ * dimensions replaces two (tiles holding a zero k1_i take the two sweeps).
  * a = device double[R][n_max - n_min]; grad = device double[R][d + 1].
  * ws: ldk_kernel_grad_workspace_bytes(R, d, n_min, n_max, pts != NULL). */
 int ldk_kernel_grad(const ldk_kernel *k, const ldk_pointset *ps, const uint64_t *pts,
-                    const uint64_t *x0, int64_t n_min, int64_t n_max, int dtype, const double *a,
-                    double *grad, void *ws, ldk_stream stream);
+                    const uint64_t *x0, int64_t n_min, int64_t n_max, int dtype, const void *k1,
+                    const double *a, double *grad, void *ws, ldk_stream stream);
 size_t ldk_kernel_grad_workspace_bytes(int R, int d, int64_t n_min, int64_t n_max,
                                        int points_given);
 

@@ -78,7 +78,7 @@ def lib():
             "ldk_version": ([], C.c_char_p),
             "ldk_mll": ([i32, i32, i32, i32, P, f64, P, P, P, P, P, P], i32),
             "ldk_mll_adjoint": ([i32, i32, i32, P, P, P, P], i32),
-            "ldk_kernel_grad": ([P, P, P, P, i64, i64, i32, P, P, P, P], i32),
+            "ldk_kernel_grad": ([P, P, P, P, i64, i64, i32, P, P, P, P, P], i32),
             "ldk_kernel_grad_workspace_bytes": ([i32, i32, i64, i64, i32], C.c_size_t),
             "ldk_fwht_split16": ([i32, i32, P, P, P], i32),
             "ldk_fit": ([i32, i32, i32, i32, i32, P, f64, P, P, P, P, P, P], i32),
@@ -405,8 +405,10 @@ def mll_adjoint(kind, g: torch.Tensor, out=None, ws=None):
 
 
 def kernel_grad(k: Kernel, ps: PointSet, n_min: int, n_max: int, a: torch.Tensor, pts=None,
-                x0=None, dtype=torch.float64, out=None, ws=None):
-    """[R][d + 1]: sum_i a_i dk1_i/dlog gamma_j (j < d) and sum_i a_i k1_i (log zeta)."""
+                x0=None, dtype=torch.float64, out=None, ws=None, k1=None):
+    """[R][d + 1]: sum_i a_i dk1_i/dlog gamma_j (j < d) and sum_i a_i k1_i (log zeta).
+    k1: optionally the forward column of the same arguments and dtype (one
+    sweep over the dimensions instead of two)."""
     dt = _dtype_code(dtype)
     _need_f64(a, "a")
     dev = ps.gen.device
@@ -421,8 +423,12 @@ def kernel_grad(k: Kernel, ps: PointSet, n_min: int, n_max: int, a: torch.Tensor
         nb = lib().ldk_kernel_grad_workspace_bytes(ps.R, ps.d, n_min, n_max,
                                                    int(pts is not None))
         ws = torch.empty(max(int(nb), 1), dtype=torch.uint8, device=dev)
+    if k1 is not None:
+        _need(k1, "k1")
+        if k1.dtype != _real(dt) or tuple(k1.shape) != (ps.R, n_max - n_min):
+            raise LdkError("k1 must be the forward column: dtype and [R][n_max - n_min]")
     _check(lib().ldk_kernel_grad(C.byref(k._c()), C.byref(ps._c()), _ptr(pts), _ptr(x0), n_min,
-                                 n_max, dt, _ptr(a), _ptr(out), _ptr(ws), _stream()),
+                                 n_max, dt, _ptr(k1), _ptr(a), _ptr(out), _ptr(ws), _stream()),
            "ldk_kernel_grad")
     return out
 

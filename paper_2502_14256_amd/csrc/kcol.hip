@@ -104,7 +104,7 @@ __device__ __forceinline__ void net_tile(const KcolArgs &a, NetLds &L, int r, in
                     k = dsi_factor<R, ALPHA>(z, L.tab);
                 else
                     k = dsi_factor_any<R>(alpha, z, L.tab);
-                const R f = (R)1 + gam * k;
+                const R f = dsi_weighted(gam, k);
                 if (FULL) {
                     prod[l] *= f;
                 } else {
@@ -167,7 +167,7 @@ __global__ __launch_bounds__(KC_THREADS) void k_kcol_points(KcolArgs a, R *__res
         const uint64_t u0 = a.x0 ? a.x0[(size_t)r * d + j] : a.pts[(size_t)r * cnt * d + j];
         const int alpha = alpha_of(a, j);
         if constexpr (NET) {
-            prod *= (R)1 + (R)a.gamma[j] * dsi_factor_any<R>(alpha, row[j] ^ u0, tab);
+            prod *= dsi_weighted((R)a.gamma[j], dsi_factor_any<R>(alpha, row[j] ^ u0, tab));
         } else {
             const SiPoly cf = si_poly(alpha, a.gamma[j]);
             prod *= si_weighted<R, 0>(unit<R>(row[j] - u0), (R)cf.c0, (R)cf.c1, (R)cf.c2, (R)cf.c3);

@@ -38,15 +38,25 @@ __device__ __forceinline__ SiPoly si_poly(int alpha, double gamma)
     const double a = (4.0 / 45.0) * pi2 * pi2 * pi2 * gamma;  // 4 pi^6 / 45 B_6
     return {1.0 + a * (1.0 / 42.0), 0.0, -0.5 * a, a};
 }
+// Fused multiply-add written out: every kernel that forms a factor forms it
+// with the same roundings (the kernel column and its gradient divide one by
+// the other, so they must agree bit for bit).
+__device__ __forceinline__ float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // ALPHA = 0: generic cubic (mixed orders); 1, 2: only the nonzero terms.
 template <typename R, int ALPHA>
 __device__ __forceinline__ R si_weighted(R x, R c0, R c1, R c2, R c3)
 {
-    const R w = x * x - x;
-    if constexpr (ALPHA == 1) return c1 * w + c0;
-    else if constexpr (ALPHA == 2) return (c2 * w) * w + c0;
-    else return ((c3 * w + c2) * w + c1) * w + c0;
+    const R w = fma_r(x, x, -x);
+    if constexpr (ALPHA == 1) return fma_r(c1, w, c0);
+    else if constexpr (ALPHA == 2) return fma_r(c2 * w, w, c0);
+    else return fma_r(fma_r(fma_r(c3, w, c2), w, c1), w, c0);
 }
+
+// DSI product factor 1 + gamma K.
+template <typename R>
+__device__ __forceinline__ R dsi_weighted(R gam, R k) { return fma_r(gam, k, (R)1); }
 
 // ---- DSI factor, Sec. 5.3 / Theorem 1 (base 2), alpha = 1 .. 4 ----
 // beta = index of the first nonzero digit (clz + 1), t_nu = 2^{-nu beta},

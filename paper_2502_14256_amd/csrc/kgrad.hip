@@ -9,7 +9,9 @@
 // (no zero), P (the one zero is f_ij) or 0.  Per dimension, the point sum is
 // reduced across the wavefront in FP64 and parked in lane j mod 64; every 64
 // dimensions the block adds its waves in LDS and writes one partial per tile,
-// and a second kernel adds the tiles in a fixed order.
+// and a second kernel adds the tiles in a fixed order.  Given the forward
+// column k1 (formed by the kernel column from bit-identical factors), the
+// first sweep is skipped: the product of the other factors is k1_i / f_ij.
 #include "kfactor.hpp"
 
 namespace ldk {
@@ -20,25 +22,54 @@ constexpr int KG_WAVES = KC_THREADS / 64;
 struct KgradArgs {
     KcolArgs k;
     const double *a;  // [R][cnt], dL/dk1
+    const void *k1;   // [R][cnt] forward column (kernel-column dtype), or nullptr
     double *part;     // [R][tiles][d + 1]
     int64_t tile_base;
     int64_t tiles;
 };
 
-__device__ __forceinline__ double wave_sum(double v)
+// One DPP lane move of a double (both halves), lanes the control leaves
+// unwritten read 0.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_move(double v)
 {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROW_MASK, 0xf,
+                                               false);
+    return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
 }
 
-// Product of the other factors, P / f: FP32 takes the reciprocal-based
-// quotient (within 2 ulp), FP64 the correctly rounded one.
-__device__ __forceinline__ float quot(float p, float f) { return __fdividef(p, f); }
+// Sum of v over the wavefront in a fixed order, returned in every lane.
+// Lane moves go through DPP (no LDS round trips): swap neighbours, swap
+// pairs, mirror within 8 and within 16 lanes (every lane of a row of 16 then
+// holds the row's sum), then lane 15 of a row is added into the next row and
+// lane 31 into the upper half; lane 63 ends with the total.
+__device__ __forceinline__ double wave_sum(double v)
+{
+    v += dpp_move<0xb1>(v);        // quad_perm [1,0,3,2]
+    v += dpp_move<0x4e>(v);        // quad_perm [2,3,0,1]
+    v += dpp_move<0x141>(v);       // row_half_mirror
+    v += dpp_move<0x140>(v);       // row_mirror
+    v += dpp_move<0x142, 0xa>(v);  // row_bcast15 into rows 1 and 3
+    v += dpp_move<0x143, 0xc>(v);  // row_bcast31 into rows 2 and 3
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), 63);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Product of the other factors, P / f: FP32 multiplies by the hardware
+// reciprocal (1 ulp; |f| is 0, which never reaches here, or far above the
+// range where the reciprocal overflows), FP64 takes the correctly rounded
+// quotient.
+__device__ __forceinline__ float quot(float p, float f) { return p * __builtin_amdgcn_rcpf(f); }
 __device__ __forceinline__ double quot(double p, double f) { return p / f; }
 
-// ---- dimension sweeps: call visit(j, t[KC_ITERS]) for j = 0 .. d-1 in order,
-// t[l] = gamma_j K_j(delta) of point tile0 + threadIdx.x + KC_THREADS l ----
+// ---- dimension sweeps: call visit(j, t[KC_ITERS], f[KC_ITERS]) for j = 0 .. d-1
+// in order, t[l] = gamma_j K_j(delta) and f[l] = 1 + t[l] of point
+// tile0 + threadIdx.x + KC_THREADS l, f formed exactly as the kernel column
+// forms it ----
 
 template <typename R, int ALPHA, int ORDER, typename Visit>
 __device__ __forceinline__ void lattice_sweep(const KcolArgs &a, int64_t first, Visit &&visit)
@@ -52,6 +83,7 @@ __device__ __forceinline__ void lattice_sweep(const KcolArgs &a, int64_t first, 
         const int alpha = ALPHA ? ALPHA : alpha_of(a, j);
         const SiPoly cf = si_tpoly(alpha, a.gamma[j]);
         const R e0 = (R)cf.c0, c1 = (R)cf.c1, c2 = (R)cf.c2, c3 = (R)cf.c3;
+        const R c0 = (R)si_poly(alpha, a.gamma[j]).c0;
         uint64_t base, G;
         if constexpr (ORDER == LDK_NATURAL) {
             base = bfirst * g;
@@ -60,13 +92,15 @@ __device__ __forceinline__ void lattice_sweep(const KcolArgs &a, int64_t first, 
             base = m == 0 ? 0 : ((bfirst * g) << (64 - m));
             G = m <= 8 ? 0 : ((g << 8) << (64 - m));
         }
-        R t[KC_ITERS];
+        R t[KC_ITERS], f[KC_ITERS];
 #pragma unroll
         for (int l = 0; l < KC_ITERS; ++l) {
             const uint64_t delta = base + (ORDER == LDK_NATURAL ? br3[l] : (uint64_t)l) * G;
-            t[l] = si_weighted<R, ALPHA>(unit<R>(delta), e0, c1, c2, c3);
+            const R x = unit<R>(delta);
+            t[l] = si_weighted<R, ALPHA>(x, e0, c1, c2, c3);
+            f[l] = si_weighted<R, ALPHA>(x, c0, c1, c2, c3);
         }
-        visit(j, t);
+        visit(j, t, f);
     }
 }
 
@@ -87,7 +121,7 @@ __device__ __forceinline__ void net_sweep(const KcolArgs &a, NetLds &L, int r, i
             const R gam = (R)a.gamma[j];
             const int alpha = ALPHA ? ALPHA : alpha_of(a, j);
             uint64_t z = L.zb[jj] ^ L.nib[jj][0][code_t & 15] ^ L.nib[jj][1][(code_t >> 4) & 15];
-            R tv[KC_ITERS];
+            R tv[KC_ITERS], fv[KC_ITERS];
 #pragma unroll
             for (int l = 0; l < KC_ITERS; ++l) {
                 R k;
@@ -96,13 +130,14 @@ __device__ __forceinline__ void net_sweep(const KcolArgs &a, NetLds &L, int r, i
                 else
                     k = dsi_factor_any<R>(alpha, z, L.tab);
                 tv[l] = gam * k;
+                fv[l] = dsi_weighted(gam, k);
                 // step to the next point; past the last index of the net the
                 // step columns are zero and z just repeats (such points are
                 // masked), so the step needs no bounds test
                 const uint64_t nb = ((uint64_t)tile0 >> s) + (uint64_t)l + 1;
                 if (l + 1 < KC_ITERS) z ^= L.step[jj][ctz64(nb)];
             }
-            visit(j, tv);
+            visit(j, tv, fv);
         }
     }
 }
@@ -118,18 +153,25 @@ __device__ __forceinline__ void points_sweep(const KcolArgs &a, const DsiTables 
         const uint64_t u0 = a.x0 ? a.x0[(size_t)r * d + j] : a.pts[(size_t)r * cnt * d + j];
         const int alpha = alpha_of(a, j);
         const SiPoly cf = NET ? SiPoly{} : si_tpoly(alpha, a.gamma[j]);
-        R t[KC_ITERS];
+        const R c0 = NET ? (R)1 : (R)si_poly(alpha, a.gamma[j]).c0;
+        R t[KC_ITERS], f[KC_ITERS];
 #pragma unroll
         for (int l = 0; l < KC_ITERS; ++l) {
             int64_t i = first + (int64_t)l * KC_THREADS;
             if (i >= a.n_max) i = a.n_max - 1;  // any valid row; masked out later
             const uint64_t u = a.pts[((size_t)r * cnt + (i - a.n_min)) * d + j];
-            if constexpr (NET)
-                t[l] = (R)a.gamma[j] * dsi_factor_any<R>(alpha, u ^ u0, tab);
-            else
-                t[l] = si_weighted<R, 0>(unit<R>(u - u0), (R)cf.c0, (R)cf.c1, (R)cf.c2, (R)cf.c3);
+            if constexpr (NET) {
+                const R gam = (R)a.gamma[j];
+                const R k = dsi_factor_any<R>(alpha, u ^ u0, tab);
+                t[l] = gam * k;
+                f[l] = dsi_weighted(gam, k);
+            } else {
+                const R x = unit<R>(u - u0);
+                t[l] = si_weighted<R, 0>(x, (R)cf.c0, (R)cf.c1, (R)cf.c2, (R)cf.c3);
+                f[l] = si_weighted<R, 0>(x, c0, (R)cf.c1, (R)cf.c2, (R)cf.c3);
+            }
         }
-        visit(j, t);
+        visit(j, t, f);
     }
 }
 
@@ -145,10 +187,11 @@ __device__ __forceinline__ void sweep(const KcolArgs &a, NetLds &L, int r, int64
     else points_sweep<R, SRC == 4>(a, L.tab, r, first, visit);
 }
 
-template <typename R, int ALPHA, int SRC>
+template <typename R, int ALPHA, int SRC, bool K1>
 __global__ __launch_bounds__(KC_THREADS) void k_kernel_grad(KgradArgs g)
 {
     __shared__ NetLds L;
+    __shared__ double red[KG_WAVES][64];
     const KcolArgs &a = g.k;
     const int r = blockIdx.y, d = a.ps.d;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -171,16 +214,40 @@ __global__ __launch_bounds__(KC_THREADS) void k_kernel_grad(KgradArgs g)
         pnz[l] = (R)1;
         nz[l] = 0;
     }
-    // sweep 1: product of the nonzero factors and the number of zero factors
-    sweep<R, ALPHA, SRC>(a, L, r, tile0, first, [&](int, const R(&t)[KC_ITERS]) {
+    // With the forward column given, k1_i = zeta prod_l f_il already holds
+    // the product, formed from the same factors bit for bit, so one sweep
+    // suffices: zeta t_ij prod_{l != j} f_il = t_ij (k1_i / f_ij).  A block
+    // with a zero k1_i (a zero factor, or underflow) takes the two sweeps.
+    bool from_k1 = false;
+    if constexpr (K1) {
+        int zero = 0;
 #pragma unroll
         for (int l = 0; l < KC_ITERS; ++l) {
-            const R f = (R)1 + t[l];
-            if (f == (R)0) ++nz[l];
-            else pnz[l] *= f;
+            const int64_t i = first + (int64_t)l * KC_THREADS;
+            if ((valid >> l) & 1u) {
+                pnz[l] = static_cast<const R *>(g.k1)[(size_t)r * cnt + (i - a.n_min)];
+                zero |= pnz[l] == (R)0;
+            }
         }
-    });
-    __shared__ double red[KG_WAVES][64];
+        from_k1 = !__syncthreads_or(zero);
+        if (!from_k1) {
+#pragma unroll
+            for (int l = 0; l < KC_ITERS; ++l) pnz[l] = (R)1;
+        }
+    }
+    if (!from_k1) {
+        // sweep 1: product of the nonzero factors and the number of zero factors
+        sweep<R, ALPHA, SRC>(a, L, r, tile0, first,
+                             [&](int, const R(&)[KC_ITERS], const R(&f)[KC_ITERS]) {
+#pragma unroll
+            for (int l = 0; l < KC_ITERS; ++l) {
+                if (f[l] == (R)0) ++nz[l];
+                else pnz[l] *= f[l];
+            }
+        });
+    }
+    // pnz already carries zeta when it came from k1
+    const double zf = from_k1 ? 1.0 : a.zeta;
     double *part = g.part + ((size_t)r * g.tiles + blockIdx.x) * (d + 1);
     {
         // d/dlog zeta: sum_i a_i k1_i
@@ -188,7 +255,7 @@ __global__ __launch_bounds__(KC_THREADS) void k_kernel_grad(KgradArgs g)
 #pragma unroll
         for (int l = 0; l < KC_ITERS; ++l)
             if (((valid >> l) & 1u) && nz[l] == 0) zs += av[l] * pnz[l];
-        const double w = wave_sum((double)zs * a.zeta);
+        const double w = wave_sum((double)zs * zf);
         if (lane == 0) red[wave][0] = w;
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -200,17 +267,8 @@ __global__ __launch_bounds__(KC_THREADS) void k_kernel_grad(KgradArgs g)
     }
     // sweep 2: t_ij times the product of the other factors
     double acc = 0.0;
-    sweep<R, ALPHA, SRC>(a, L, r, tile0, first, [&](int j, const R(&t)[KC_ITERS]) {
-        R ps = (R)0;
-#pragma unroll
-        for (int l = 0; l < KC_ITERS; ++l) {
-            const R f = (R)1 + t[l];
-            R other;
-            if (nz[l] == 0) other = quot(pnz[l], f);
-            else other = (nz[l] == 1 && f == (R)0) ? pnz[l] : (R)0;
-            if ((valid >> l) & 1u) ps += av[l] * (t[l] * other);
-        }
-        const double w = wave_sum((double)ps * a.zeta);
+    auto emit = [&](int j, R ps) {
+        const double w = wave_sum((double)ps * zf);
         if ((j & 63) == lane) acc = w;
         if ((j & 63) == 63 || j == d - 1) {
             // block-uniform: every thread reaches these barriers
@@ -224,7 +282,34 @@ __global__ __launch_bounds__(KC_THREADS) void k_kernel_grad(KgradArgs g)
             }
             __syncthreads();
         }
-    });
+    };
+    if (K1 && from_k1) {
+        // no zero factor at any valid point of the tile
+        sweep<R, ALPHA, SRC>(a, L, r, tile0, first,
+                             [&](int j, const R(&t)[KC_ITERS], const R(&f)[KC_ITERS]) {
+            R ps = (R)0;
+#pragma unroll
+            for (int l = 0; l < KC_ITERS; ++l) {
+                const R c = av[l] * (t[l] * quot(pnz[l], f[l]));
+                ps += ((valid >> l) & 1u) ? c : (R)0;
+            }
+            emit(j, ps);
+        });
+    } else {
+        sweep<R, ALPHA, SRC>(a, L, r, tile0, first,
+                             [&](int j, const R(&t)[KC_ITERS], const R(&f)[KC_ITERS]) {
+            R ps = (R)0;
+#pragma unroll
+            for (int l = 0; l < KC_ITERS; ++l) {
+                const R q = quot(pnz[l], f[l]);
+                const R one_zero = (nz[l] == 1 && f[l] == (R)0) ? pnz[l] : (R)0;
+                const R other = nz[l] == 0 ? q : one_zero;
+                const R c = av[l] * (t[l] * other);
+                ps += ((valid >> l) & 1u) ? c : (R)0;
+            }
+            emit(j, ps);
+        });
+    }
 }
 
 // grad[r][j] = sum over tiles of the partials, in a fixed order (four
@@ -249,13 +334,20 @@ __global__ __launch_bounds__(256) void k_grad_final(const double *__restrict__ p
     grad[(size_t)r * (d + 1) + j] = (s0 + s1) + (s2 + s3);
 }
 
+template <typename R, int ALPHA, int SRC>
+void launch_grad_k1(const KgradArgs &g, dim3 grid, hipStream_t s)
+{
+    if (g.k1) hipLaunchKernelGGL((k_kernel_grad<R, ALPHA, SRC, true>), grid, dim3(KC_THREADS), 0, s, g);
+    else hipLaunchKernelGGL((k_kernel_grad<R, ALPHA, SRC, false>), grid, dim3(KC_THREADS), 0, s, g);
+}
+
 template <typename R, int ALPHA>
 void launch_grad_src(int src, const KgradArgs &g, dim3 grid, hipStream_t s)
 {
     switch (src) {
-    case 0: hipLaunchKernelGGL((k_kernel_grad<R, ALPHA, 0>), grid, dim3(KC_THREADS), 0, s, g); break;
-    case 1: hipLaunchKernelGGL((k_kernel_grad<R, ALPHA, 1>), grid, dim3(KC_THREADS), 0, s, g); break;
-    default: hipLaunchKernelGGL((k_kernel_grad<R, ALPHA, 2>), grid, dim3(KC_THREADS), 0, s, g); break;
+    case 0: launch_grad_k1<R, ALPHA, 0>(g, grid, s); break;
+    case 1: launch_grad_k1<R, ALPHA, 1>(g, grid, s); break;
+    default: launch_grad_k1<R, ALPHA, 2>(g, grid, s); break;
     }
 }
 
@@ -263,8 +355,8 @@ template <typename R>
 void launch_grad(int src, int uniform, const KgradArgs &g, dim3 grid, hipStream_t s)
 {
     if (src >= 3) {  // points given: generic orders
-        if (src == 3) hipLaunchKernelGGL((k_kernel_grad<R, 0, 3>), grid, dim3(KC_THREADS), 0, s, g);
-        else hipLaunchKernelGGL((k_kernel_grad<R, 0, 4>), grid, dim3(KC_THREADS), 0, s, g);
+        if (src == 3) launch_grad_k1<R, 0, 3>(g, grid, s);
+        else launch_grad_k1<R, 0, 4>(g, grid, s);
         return;
     }
     switch (uniform) {
@@ -273,7 +365,7 @@ void launch_grad(int src, int uniform, const KgradArgs &g, dim3 grid, hipStream_
     case 3: launch_grad_src<R, 3>(src, g, grid, s); break;
     case 4:
         if (src == 2) {
-            hipLaunchKernelGGL((k_kernel_grad<R, 4, 2>), grid, dim3(KC_THREADS), 0, s, g);
+            launch_grad_k1<R, 4, 2>(g, grid, s);
             break;
         }
         [[fallthrough]];
@@ -306,7 +398,8 @@ extern "C" size_t ldk_kernel_grad_workspace_bytes(int R, int d, int64_t n_min, i
 
 extern "C" int ldk_kernel_grad(const ldk_kernel *k, const ldk_pointset *ps, const uint64_t *pts,
                                const uint64_t *x0, int64_t n_min, int64_t n_max, int dtype,
-                               const double *a, double *grad, void *ws, ldk_stream stream)
+                               const void *k1, const double *a, double *grad, void *ws,
+                               ldk_stream stream)
 {
     KgradArgs g{};
     int uniform = 0;
@@ -327,6 +420,7 @@ extern "C" int ldk_kernel_grad(const ldk_kernel *k, const ldk_pointset *ps, cons
     grad_tiles(given, n_min, n_max, &g.tile_base, &g.tiles);
     if (g.tiles > 0x7fffffff) return LDK_ENOTSUP;
     g.a = a;
+    g.k1 = k1;
     g.part = static_cast<double *>(ws);
     const int src = given ? (p.kind == LDK_DNET_B2 ? 4 : 3)
                           : (p.kind == LDK_DNET_B2 ? 2 : (p.order == LDK_LINEAR ? 1 : 0));

@@ -90,7 +90,8 @@ def _grad_case(kind, uniform, seed=7, m=12, d=5, R=2):
 @pytest.mark.parametrize("src", ["regen", "pts"])
 @pytest.mark.parametrize("dtype", [F64, F32])
 @pytest.mark.parametrize("window", [(0, 4096), (100, 3001)])
-def test_kernel_grad(orc, kind, uniform, src, dtype, window):
+@pytest.mark.parametrize("with_k1", [False, True])
+def test_kernel_grad(orc, kind, uniform, src, dtype, window, with_k1):
     w = _grad_case(kind, uniform)
     n_min, n_max = window
     pts_all = orc.points(w, 0, n_max)
@@ -102,19 +103,22 @@ def test_kernel_grad(orc, kind, uniform, src, dtype, window):
     ps, k = pointset(w), kernel(w)
     ad = torch.from_numpy(a).cuda()
     if src == "regen":
-        got = ldk.kernel_grad(k, ps, n_min, n_max, ad, dtype=dtype)
+        k1 = ldk.kernel_column(k, ps, n_min, n_max, dtype=dtype) if with_k1 else None
+        got = ldk.kernel_grad(k, ps, n_min, n_max, ad, dtype=dtype, k1=k1)
     else:
         from ldk_dev import dev_u64
-        got = ldk.kernel_grad(k, ps, n_min, n_max, ad, pts=dev_u64(pts), x0=dev_u64(x0),
-                              dtype=dtype)
+        pd, xd = dev_u64(pts), dev_u64(x0)
+        k1 = (ldk.kernel_column(k, ps, n_min, n_max, pts=pd, x0=xd, dtype=dtype) if with_k1
+              else None)
+        got = ldk.kernel_grad(k, ps, n_min, n_max, ad, pts=pd, x0=xd, dtype=dtype, k1=k1)
     got = got.cpu().numpy()
     # |d k1_i / d theta| <= the kernel scale, so each sum is off by at most
     # tol * ||a||_1 * scale
     bound = np.abs(a).sum(axis=1, keepdims=True) * kernel_scale(w)
     tol = 1e-14 if dtype == F64 else 2e-6
     err = np.max(np.abs(got - ref) / bound)
-    record(f"kernel_grad_{kind}_{'u' if uniform else 'mix'}_{src}_{window}_{dtype}", err=err,
-           tol=tol)
+    record(f"kernel_grad_{kind}_{'u' if uniform else 'mix'}_{src}_{window}_{dtype}"
+           f"{'_k1' if with_k1 else ''}", err=err, tol=tol)
     assert err < tol, (err, got, ref)
 
 
@@ -125,9 +129,14 @@ def test_kernel_grad_exactly_zero_factor(orc):
     pts = orc.points(w)
     a = np.random.default_rng(3).standard_normal((1, 2**10))
     ref = orc.kernel_grad("dnet", pts, pts[:, 0], w["alpha"], w["gamma"], w["zeta"], a)
-    for dtype in (F64, F32):
+    for dtype, with_k1 in ((F64, False), (F32, False), (F64, True), (F32, True)):
+        k1 = (ldk.kernel_column(kernel(w), pointset(w), 0, 2**10, dtype=dtype) if with_k1
+              else None)
+        if with_k1:
+            # zeros in k1: those tiles must take the two sweeps
+            assert torch.any(k1 == 0)
         got = ldk.kernel_grad(kernel(w), pointset(w), 0, 2**10, torch.from_numpy(a).cuda(),
-                              dtype=dtype).cpu().numpy()
+                              dtype=dtype, k1=k1).cpu().numpy()
         assert np.all(np.isfinite(got))
         bound = np.abs(a).sum() * kernel_scale(w)
         assert np.max(np.abs(got - ref)) / bound < (1e-14 if dtype == F64 else 2e-6)
@@ -161,9 +170,12 @@ def test_gradient_step_end_to_end(orc, kind, m, d, dtype):
     L, g, ds = ldk.mll(kind, lam, w["sigma2"], y)
     a = ldk.mll_adjoint(kind, g)
     kg = ldk.kernel_grad(k, ps, 0, n, a, dtype=dtype)
+    kg1 = ldk.kernel_grad(k, ps, 0, n, a, dtype=dtype, k1=k1)
     grad = torch.cat([kg, ds[:, None]], dim=1).cpu().numpy()
+    grad1 = torch.cat([kg1, ds[:, None]], dim=1).cpu().numpy()
     eL = np.max(np.abs(L.cpu().numpy() - ref["L"]) / np.abs(ref["L"]))
-    eG = np.max(np.abs(grad - ref["grad"])) / np.max(np.abs(ref["grad"]))
+    eG = max(np.max(np.abs(gr - ref["grad"])) / np.max(np.abs(ref["grad"]))
+             for gr in (grad, grad1))
     record(f"grad_step_{kind}_m{m}_d{d}_{'f64' if dtype == F64 else 'f32'}", err_L=eL, err_grad=eG)
     if dtype == F64:
         assert eL < 1e-11 and eG < 1e-9, (eL, eG)

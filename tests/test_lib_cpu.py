@@ -148,20 +148,20 @@ def test_likelihood_entry_points_reject_bad_arguments():
     # ldk_kernel_grad: the kernel-column validation, then a, grad and ws
     keep, a4 = _alpha(2, 2, 2, 2)
     k = ldk._Kernel(ldk.LATTICE, 4, a4, FAKE, 1.0)  # kind mismatch with the net point set
-    assert L.ldk_kernel_grad(C.byref(k), C.byref(_ps()), None, None, 0, 4, 0, FAKE, FAKE, FAKE,
+    assert L.ldk_kernel_grad(C.byref(k), C.byref(_ps()), None, None, 0, 4, 0, None, FAKE, FAKE, FAKE,
                              None) == -1
     k = ldk._Kernel(ldk.DNET_B2, 4, a4, FAKE, 1.0)
-    assert L.ldk_kernel_grad(C.byref(k), C.byref(_ps()), None, None, 0, 4, 0, FAKE, None, FAKE,
+    assert L.ldk_kernel_grad(C.byref(k), C.byref(_ps()), None, None, 0, 4, 0, None, FAKE, None, FAKE,
                              None) == -1  # grad missing
-    assert L.ldk_kernel_grad(C.byref(k), C.byref(_ps()), None, None, 0, 4, 0, None, FAKE, FAKE,
+    assert L.ldk_kernel_grad(C.byref(k), C.byref(_ps()), None, None, 0, 4, 0, None, None, FAKE, FAKE,
                              None) == -1  # a missing
-    assert L.ldk_kernel_grad(C.byref(k), C.byref(_ps()), None, None, 0, 4, 0, FAKE, FAKE, None,
+    assert L.ldk_kernel_grad(C.byref(k), C.byref(_ps()), None, None, 0, 4, 0, None, FAKE, FAKE, None,
                              None) == -1  # ws missing
-    assert L.ldk_kernel_grad(C.byref(k), C.byref(_ps()), None, None, 0, 2**10 + 1, 0, FAKE, FAKE,
-                             FAKE, None) == -1  # beyond 2^m_max
+    assert L.ldk_kernel_grad(C.byref(k), C.byref(_ps()), None, None, 0, 2**10 + 1, 0, None, FAKE,
+                             FAKE, FAKE, None) == -1  # beyond 2^m_max
     keep5, bad = _alpha(1, 2, 5, 1)
     k = ldk._Kernel(ldk.DNET_B2, 4, bad, FAKE, 1.0)
-    assert L.ldk_kernel_grad(C.byref(k), C.byref(_ps()), None, None, 0, 4, 0, FAKE, FAKE, FAKE,
+    assert L.ldk_kernel_grad(C.byref(k), C.byref(_ps()), None, None, 0, 4, 0, None, FAKE, FAKE, FAKE,
                              None) == -1
 
 
