@@ -362,6 +362,22 @@ bool fit_fused(int kind, int m, int dtype) { return kind == LDK_LATTICE && m >= 
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// Top-pass geometry of the fused fit: the plan's top pass, narrowed until
+// the column and rhs tiles fit 64 KiB of LDS together, with four elements
+// per thread where the kernel takes it (twice the wavefronts of eight: at
+// one replication of n = 2^20 the pass is latency-bound, 54 us against 58
+// for the fused fit).
+PassGeom fit_top_geom(const Plan &pl)
+{
+    PassGeom g = pl.pass[pl.P - 1];
+    while (g.b0 > 0 && g.logW > 1 &&
+           2 * (((size_t)1 << (g.a + g.logW)) * 17 / 16) * 16 > 65536)
+        --g.logW;
+    PassGeom g4 = g;
+    g4.logE = 2;
+    return (g.logE == 3 && fit_top_supported(g4)) ? g4 : g;
+}
+
 // Fit workspace for B = R (nrhs + 1) rows: [log-det partials | column rows | rhs rows].
 size_t fit_ws_bytes(int kind, int64_t B, int m, int dtype);
 
@@ -409,7 +425,7 @@ size_t fit_ws_bytes(int kind, int64_t B, int m, int dtype)
     size_t w = ws_bytes(LDK_OP_EIG, kind, B, m, dtype);
     if (fit_fused(kind, m, dtype)) {
         const Plan pl = make_plan(m - 1, log_tile_for(LDK_LATTICE, LDK_F64));
-        const PassGeom &top = pl.pass[pl.P - 1];
+        const PassGeom top = fit_top_geom(pl);  // at least as many tiles as the plan's top
         const size_t cb = (size_t)1 << (top.b0 - top.logW);
         const size_t rows = pl.P > 1 ? (size_t)B * ((size_t)1 << (m - 1)) * 16 : 0;
         const size_t f = align256((size_t)B * cb * sizeof(double)) + rows;
@@ -588,7 +604,10 @@ int ldk_fit(int kind, int R, int nrhs, int m, int dtype, const void *k1, double 
     const int mp = m - 1;
     const int64_t n = (int64_t)1 << m, N = n / 2;
     const Plan pl = make_plan(mp, log_tile_for(LDK_LATTICE, LDK_F64));
-    const PassGeom &top = pl.pass[pl.P - 1];
+    // one rhs per column: both top passes in one launch (narrower tiles)
+    const PassGeom ftop = fit_top_geom(pl);
+    const bool one_top = nrhs == 1 && fit_top_supported(ftop);
+    const PassGeom top = one_top ? ftop : pl.pass[pl.P - 1];
     const int cb_count = 1 << (top.b0 - top.logW);
     unsigned char *w8 = static_cast<unsigned char *>(ws);
     double *partial = reinterpret_cast<double *>(w8);
@@ -631,11 +650,18 @@ int ldk_fit(int kind, int R, int nrhs, int m, int dtype, const void *k1, double 
     aK.g = aY.g = top;
     aK.global_tw = aY.global_tw = !single;
     aY.scale = 1.0 / (double)N;
-    st = launch_real_top(LDK_F64, PM_FWD, aK, lam, s, false, logdet ? partial : nullptr);
-    if (st) return st;
-    st = launch_real_top(LDK_F64, PM_SOLVE, aY, nullptr, s);
-    if (st) return st;
-    // inverse passes of the right-hand sides
+    if (one_top) {
+        st = launch_fit_top(aK, aY, lam, logdet ? partial : nullptr, s);
+        if (st) return st;
+    } else {
+        st = launch_real_top(LDK_F64, PM_FWD, aK, lam, s, false, logdet ? partial : nullptr);
+        if (st) return st;
+        st = launch_real_top(LDK_F64, PM_SOLVE, aY, nullptr, s);
+        if (st) return st;
+    }
+    // inverse passes of the right-hand sides; the first one also finishes
+    // the log-det when it has a full wave per tile
+    bool ld_done = false;
     for (int p = pl.P - 2; p >= 0; --p) {
         PassArgs b = aY;
         b.lam = nullptr;
@@ -646,10 +672,18 @@ int ldk_fit(int kind, int R, int nrhs, int m, int dtype, const void *k1, double 
         b.g = pl.pass[p];
         b.global_tw = p > 0;
         b.scale = 1.0;
+        const int64_t tiles = b.rows << (mp - b.g.a - b.g.logW);
+        if (logdet && !ld_done && (b.g.a + b.g.logW - b.g.logE) >= 6 && tiles >= R) {
+            b.ld_part = partial;
+            b.ld_out = logdet;
+            b.ld_rows = R;
+            b.ld_count = cb_count;
+            ld_done = true;
+        }
         st = launch_pass(LDK_LATTICE, LDK_F64, PM_INV, PIO_SAME, p == 0 ? PIO_PACKED : PIO_SAME, b, s);
         if (st) return st;
     }
-    if (logdet) {
+    if (logdet && !ld_done) {
         hipLaunchKernelGGL(k_logdet_final, dim3(R), dim3(LOGDET_THREADS), 0, s,
                            (const double *)partial, cb_count, logdet);
         LDK_LAUNCH_CHECK();

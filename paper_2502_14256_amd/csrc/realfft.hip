@@ -240,6 +240,231 @@ __device__ __forceinline__ void real_top_body(const PassArgs &a, double *lam_out
         store_elem<T, ST>(a.dst, row * a.dst_row + gidx(t + Tn * i), v[i], a.half);
 }
 
+// The fit's two top passes in one block (FP64, one right-hand side per
+// column): threads [0, Tn) take tile cb of the column's transform and produce
+// its eigenvalues (and log-det partial sum), threads [Tn, 2 Tn) take the
+// same tile of the right-hand side's transform.  A tile holds every
+// frequency's partner, so the eigenvalues the solve's filter needs at k,
+// N - k, k + N and n - k are all produced in the same block; they pass
+// through LDS (over the column half's tile, once its partner reads are
+// done).  Both halves run the same forward schedule and reach every barrier;
+// the column half idles through the inverse top group.
+//   LDS: [column tile | rhs tile], each S + S/16 elements.
+template <int LOGE, int LD, int ST>
+__global__ __launch_bounds__(512) void k_fit_top(PassArgs aK, PassArgs aY, double *lam_out,
+                                                 double *ld_part)
+{
+    using T = cplx<double>;
+    using R = double;
+    constexpr int E = 1 << LOGE;
+    __shared__ double red[8];
+
+    const int A = aK.g.a, logW = aK.g.logW, b0 = aK.g.b0;
+    const int mp = aK.m;
+    const int64_t N = (int64_t)1 << mp;
+    const int64_t N1 = (int64_t)1 << b0;
+    const int N2 = 1 << A;
+    const int W = 1 << logW, H = W >> 1;
+    const int S = 1 << (A + logW);
+    const int Tn = S >> LOGE;
+    const bool rhs = (int)threadIdx.x >= Tn;  // wave-uniform: Tn is a multiple of 64
+    const int t = rhs ? (int)threadIdx.x - Tn : (int)threadIdx.x;
+    const int64_t cb_count = N1 >> logW;
+    const int64_t bid = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t row = bid / cb_count, cb = bid % cb_count;
+    const bool last = cb == cb_count - 1;
+    const int padS = S + (S >> LDS_PAD_SHIFT);
+    T *lds = reinterpret_cast<T *>(g_real_lds) + (rhs ? padS : 0);
+    double *lam_lds = reinterpret_cast<double *>(g_real_lds);  // [2][S] after the column's reads
+
+    auto col_of = [&](int w) -> int64_t {
+        if (W == 1) return 0;
+        if (w < H) return cb * H + w + 1;
+        if (last && w == H) return 0;
+        return N1 - (cb + 1) * H + (w - H);
+    };
+    auto gidx = [&](int q) -> int64_t { return col_of(q & (W - 1)) + (int64_t)(q >> logW) * N1; };
+    // position in the tile of the partner N - k of element q (q itself for k = 0)
+    auto partner = [&](int q) -> int {
+        const int w = q & (W - 1), k2 = q >> logW;
+        const int64_t k1 = col_of(w);
+        if (k1 == 0) return ((N2 - k2) & (N2 - 1)) * W + w;
+        if (k1 == N1 / 2) return (N2 - 1 - k2) * W + w;
+        return (N2 - 1 - k2) * W + (2 * H - 1 - w);
+    };
+
+    const int G = (A + LOGE - 1) / LOGE;
+    const int rem = A - LOGE * (G - 1);
+    const int top_s = A - LOGE;
+    const int64_t n = 2 * N;
+
+    const void *src = rhs ? aY.src : aK.src;
+    const int64_t src_row = rhs ? aY.src_row : aK.src_row;
+    T v[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i)
+        v[i] = load_elem<T, LD, false>(src, row * src_row + gidx(t + Tn * i), aK.half);
+    T gb[MAX_GROUPS];
+    group_bases<R, LOGE>(gb, t, A, logW, Tn);
+    PassTw<R> ptw{};
+    if (b0 > 0) ptw = pass_tw_fetch<R, LOGE>(t, (uint64_t)col_of(t & (W - 1)), logW, A, b0);
+    T wkv[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const int q = t + Tn * i;
+        const int64_t k = col_of(q & (W - 1)) + N1 * (int64_t)(q >> logW);
+        wkv[i] = tw_any<R>((uint64_t)k, mp + 1);
+    }
+
+    // ---- forward transform over the axis bits (both halves, own tiles)
+    if (b0 > 0) pass_tw_apply<T, E, LOGE, false>(v, ptw);
+    if (G > 1) {
+        lds_write(v, lds, t, LOGE, logW + top_s, Tn);
+        __syncthreads();
+        int s = 0;
+        for (int gi = 0; gi < G - 1; ++gi) {
+            const int gs = gi == 0 ? rem : LOGE;
+            lds_read(v, lds, t, gs, logW + s, Tn);
+            if (gi > 0) apply_group_twiddle<T, E, LOGE, false>(v, gb[gi]);
+            reg_fwd<T, E, LOGE, false>(v, gs);
+            lds_write(v, lds, t, gs, logW + s, Tn);
+            __syncthreads();
+            s += gs;
+        }
+        lds_read(v, lds, t, LOGE, logW + top_s, Tn);
+        apply_group_twiddle<T, E, LOGE, false>(v, gb[G - 1]);
+    }
+    reg_fwd<T, E, LOGE, false>(v, LOGE);
+    __syncthreads();  // all forward reads are done
+    lds_write(v, lds, t, LOGE, logW + top_s, Tn);
+    __syncthreads();
+
+    // Untangled spectrum of element i: Y_k and Y_{k+N}.
+    auto untangle = [&](int i, T &yk, T &ykn) {
+        const T zm = lds[lds_idx(partner(t + Tn * i))];
+        const T zk = v[i];
+        const T ev{(zk.re + zm.re) * (R)0.5, (zk.im - zm.im) * (R)0.5};
+        const T dv{(zk.re - zm.re) * (R)0.5, (zk.im + zm.im) * (R)0.5};
+        const T od{dv.im, -dv.re};
+        const T wo = cmul(wkv[i], od);
+        yk = T{ev.re + wo.re, ev.im + wo.im};
+        ykn = T{ev.re - wo.re, ev.im - wo.im};
+    };
+
+    // ---- column half: eigenvalues (global and LDS) and the log-det partial
+    double la[E], lc[E];
+    double lsum = 0.0;
+    if (!rhs) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            T yk, ykn;
+            untangle(i, yk, ykn);
+            const int q = t + Tn * i;
+            const int64_t k = col_of(q & (W - 1)) + N1 * (int64_t)(q >> logW);
+            la[i] = yk.re;
+            lc[i] = ykn.re;
+            lam_out[row * n + k] = la[i];
+            lam_out[row * n + k + N] = lc[i];
+            if (ld_part) {
+                const double sa = la[i] + aK.sigma2, sb = lc[i] + aK.sigma2;
+                lsum += (sa > 0.0 ? log(sa) : __builtin_nan("")) +
+                        (sb > 0.0 ? log(sb) : __builtin_nan(""));
+            }
+        }
+    }
+    __syncthreads();  // the column's partner reads are done: its tile becomes lambda
+    if (!rhs) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int q = t + Tn * i;
+            lam_lds[q] = la[i];
+            lam_lds[S + q] = lc[i];
+        }
+        if (ld_part) {
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
+            if ((t & 63) == 0) red[t >> 6] = lsum;
+        }
+    }
+    __syncthreads();
+    if (!rhs) {
+        if (ld_part && t == 0) {
+            double sacc = 0.0;
+            for (int w8 = 0; w8 < (Tn + 63) / 64; ++w8) sacc += red[w8];
+            ld_part[row * cb_count + cb] = sacc;
+        }
+    } else {
+        // ---- rhs half: filter by the symmetrised 1/(lambda + s2), re-pack
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            T yk, ykn;
+            untangle(i, yk, ykn);
+            const int q = t + Tn * i;
+            const int qp = partner(q);
+            const int64_t k = col_of(q & (W - 1)) + N1 * (int64_t)(q >> logW);
+            // lambda at k, n - k, k + N and N - k; for k = 0, n - k is 0 and N - k is N
+            const double l_k = lam_lds[q], l_kN = lam_lds[S + q];
+            const double l_nk = k == 0 ? l_k : lam_lds[S + qp];
+            const double l_Nk = k == 0 ? l_kN : lam_lds[qp];
+            const double pa = l_k + aY.sigma2, pb = l_nk + aY.sigma2;
+            const double pc = l_kN + aY.sigma2, pd = l_Nk + aY.sigma2;
+            const double s1 = 0.5 * aY.scale * (pa + pb) / (pa * pb);
+            const double s2 = 0.5 * aY.scale * (pc + pd) / (pc * pd);
+            const T c1{yk.re * s1, yk.im * s1};
+            const T c2{ykn.re * s2, ykn.im * s2};
+            const T ep{(c1.re + c2.re) * (R)0.5, (c1.im + c2.im) * (R)0.5};
+            const T op = cmulc(T{(c1.re - c2.re) * (R)0.5, (c1.im - c2.im) * (R)0.5}, wkv[i]);
+            v[i] = T{ep.re - op.im, ep.im + op.re};
+        }
+        reg_inv<T, E, LOGE>(v, LOGE);
+    }
+
+    // ---- inverse transform over the axis bits (rhs half; both reach the barriers)
+    if (G > 1) {
+        if (rhs) apply_group_twiddle<T, E, LOGE, true>(v, gb[G - 1]);
+        __syncthreads();  // the rhs partner reads are done
+        if (rhs) lds_write(v, lds, t, LOGE, logW + top_s, Tn);
+        __syncthreads();
+        int s = top_s;
+        for (int gi = G - 2; gi >= 0; --gi) {
+            const int gs = gi == 0 ? rem : LOGE;
+            s -= gs;
+            if (rhs) {
+                lds_read(v, lds, t, gs, logW + s, Tn);
+                reg_inv<T, E, LOGE>(v, gs);
+                if (gi > 0) apply_group_twiddle<T, E, LOGE, true>(v, gb[gi]);
+                lds_write(v, lds, t, gs, logW + s, Tn);
+            }
+            __syncthreads();
+        }
+        if (rhs) lds_read(v, lds, t, LOGE, logW + top_s, Tn);
+    }
+    if (rhs) {
+        if (b0 > 0) pass_tw_apply<T, E, LOGE, true>(v, ptw);
+#pragma unroll
+        for (int i = 0; i < E; ++i)
+            store_elem<T, ST>(aY.dst, row * aY.dst_row + gidx(t + Tn * i), v[i], aY.half);
+    }
+}
+
+template <int LOGE, int LD, int ST>
+int launch_ft(const PassArgs &aK, const PassArgs &aY, double *lam_out, double *ld_part,
+              hipStream_t s)
+{
+    const int S = 1 << (aK.g.a + aK.g.logW);
+    const int Tn = S >> LOGE;
+    const int64_t blocks = aK.rows * ((int64_t)1 << (aK.g.b0 - aK.g.logW));
+    if (blocks > 0x7fffffff || Tn > 256 || Tn % 64 != 0) return LDK_ENOTSUP;
+    if ((aK.g.a + LOGE - 1) / LOGE > MAX_GROUPS) return LDK_ENOTSUP;
+    if (aK.g.b0 + aK.g.a != aK.m) return LDK_EINVAL;
+    if (aK.g.b0 > 0 && aK.g.logW < 1) return LDK_ENOTSUP;
+    const size_t lds = 2 * (size_t)(S + (S >> LDS_PAD_SHIFT)) * sizeof(cplx<double>);
+    hipLaunchKernelGGL((k_fit_top<LOGE, LD, ST>), dim3((unsigned)blocks), dim3(2 * Tn), lds, s, aK,
+                       aY, lam_out, ld_part);
+    LDK_LAUNCH_CHECK();
+    return LDK_OK;
+}
+
 template <typename T, int LOGE, int MODE, int LD, int ST, bool SRC_F32>
 __global__ __launch_bounds__(512) void k_real_top(PassArgs a, double *lam_out, double *ld_part)
 {
@@ -256,6 +481,7 @@ int launch_rt(const PassArgs &a, double *lam_out, hipStream_t s, double *ld_part
     const int threads = S >> LOGE;
     const int64_t blocks = a.rows * ((int64_t)1 << (a.g.b0 - a.g.logW));
     if (blocks > 0x7fffffff || threads > 512 || threads < 1) return LDK_ENOTSUP;
+    if ((a.g.a + LOGE - 1) / LOGE > MAX_GROUPS) return LDK_ENOTSUP;  // group twiddle bases
     if (a.g.b0 + a.g.a != a.m) return LDK_EINVAL;  // must be the top pass
     if (a.g.b0 > 0 && a.g.logW < 1) return LDK_ENOTSUP;  // mirror runs need W >= 2
     const size_t lds = (size_t)(S + (S >> LDS_PAD_SHIFT)) * sizeof(T);
@@ -285,6 +511,33 @@ int launch_rt_io(bool single, const PassArgs &a, double *lam_out, hipStream_t s)
 }
 
 }  // namespace
+
+bool fit_top_supported(const PassGeom &g)
+{
+    const int S = 1 << (g.a + g.logW), Tn = S >> g.logE;
+    const size_t lds = 2 * (size_t)(S + (S >> LDS_PAD_SHIFT)) * sizeof(cplx<double>);
+    return (g.logE == 2 || g.logE == 3) && Tn % 64 == 0 && Tn <= 256 && lds <= 65536 &&
+           (g.a + g.logE - 1) / g.logE <= MAX_GROUPS && (g.b0 == 0 || g.logW >= 1);
+}
+
+int launch_fit_top(const PassArgs &aK, const PassArgs &aY, double *lam_out, double *ld_part,
+                   hipStream_t s)
+{
+    if (!fit_top_supported(aK.g)) return LDK_ENOTSUP;
+    if (aK.rows != aY.rows || aK.m != aY.m || aK.half != aY.half || aK.src_row != aY.src_row ||
+        aY.nrhs != 1 || !lam_out)
+        return LDK_EINVAL;
+    const bool single = aK.g.b0 == 0;
+    switch (aK.g.logE) {
+    case 2:
+        return single ? launch_ft<2, IO_PACKED, IO_PACKED>(aK, aY, lam_out, ld_part, s)
+                      : launch_ft<2, IO_SAME, IO_SAME>(aK, aY, lam_out, ld_part, s);
+    case 3:
+        return single ? launch_ft<3, IO_PACKED, IO_PACKED>(aK, aY, lam_out, ld_part, s)
+                      : launch_ft<3, IO_SAME, IO_SAME>(aK, aY, lam_out, ld_part, s);
+    default: return LDK_ENOTSUP;
+    }
+}
 
 int launch_real_top(int dtype, int mode, const PassArgs &a, double *lam_out, hipStream_t s,
                     bool src_f32, double *ld_part)

@@ -27,6 +27,7 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int64_t bid)
     const int t = threadIdx.x;
 
     // block -> (row, outer, column block)
+    const int64_t tile = bid;
     const int64_t cb_count = (int64_t)1 << (b0 - logW);
     const int64_t outer_count = (int64_t)1 << (a.m - b0 - A);
     const int64_t cb = bid % cb_count;
@@ -126,6 +127,19 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int64_t bid)
         if (MODE == PM_FWD || MODE == PM_INV) o = scl(o, sc);
         store_elem<T, ST>(a.dst, row * a.dst_row + gidx(t + Tn * i), o, a.half);
     }
+
+    if constexpr (MODE == PM_INV) {
+        // the log-det of the fused fit: the first wave of tile r adds row r's
+        // partial sums (written by the top pass that ran before this one)
+        if (a.ld_out && tile < a.ld_rows && t < 64) {
+            const double *p = a.ld_part + tile * a.ld_count;
+            double acc = 0.0;
+            for (int64_t c = t; c < a.ld_count; c += 64) acc += p[c];
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+            if (t == 0) a.ld_out[tile] = acc;
+        }
+    }
 }
 
 template <typename T, int LOGE, int MODE, int LD, int ST, bool SRC_F32>
@@ -150,6 +164,7 @@ int launch_t(int ld, int st, const PassArgs &a, hipStream_t s)
     const int threads = S >> LOGE;
     const int64_t blocks = a.rows * ((int64_t)1 << (a.m - a.g.a - a.g.logW));
     if (blocks > 0x7fffffff || threads > 512 || threads < 1) return LDK_ENOTSUP;
+    if ((a.g.a + LOGE - 1) / LOGE > MAX_GROUPS) return LDK_ENOTSUP;  // group twiddle bases
     const size_t lds = (size_t)(S + (S >> LDS_PAD_SHIFT)) * sizeof(T);
     const dim3 grid((unsigned)blocks), block(threads);
 #define LDK_PASS(LD_, ST_) hipLaunchKernelGGL((k_pass<T, LOGE, MODE, LD_, ST_, SRC_F32>), grid, block, lds, s, a)
@@ -273,6 +288,7 @@ int launch_fwd2(const PassArgs &a0, const PassArgs &a1, hipStream_t s)
     const int64_t per_row = (int64_t)1 << (a0.m - a0.g.a - a0.g.logW);
     const int64_t nb0 = a0.rows * per_row, nb1 = a1.rows * per_row;
     if (nb0 + nb1 > 0x7fffffff || threads > 512 || threads < 1) return LDK_ENOTSUP;
+    if ((a0.g.a + LOGE - 1) / LOGE > MAX_GROUPS) return LDK_ENOTSUP;
     const size_t lds = (size_t)(S + (S >> LDS_PAD_SHIFT)) * sizeof(T);
     hipLaunchKernelGGL((k_pass2<T, LOGE, PM_FWD, LD, IO_SAME, false>), dim3((unsigned)(nb0 + nb1)),
                        dim3(threads), lds, s, a0, a1, nb0);

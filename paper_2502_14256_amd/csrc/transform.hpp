@@ -57,6 +57,12 @@ struct PassArgs {
     double sigma2;
     double scale;     // solve: scale / (lambda + sigma2); matvec: scale * lambda;
                       // fwd / inv: multiplies the stored values
+    // PM_INV only, optional: blocks 0 .. ld_rows-1 also add up ld_count
+    // log-det partial sums per row (ld_part[r][ld_count]) into ld_out[r].
+    const double *ld_part;
+    double *ld_out;
+    int64_t ld_rows;
+    int64_t ld_count;
 };
 
 // Global IO of a pass (lattice only; nets are always real):
@@ -86,6 +92,17 @@ int launch_pass(int kind, int dtype, int mode, int ld, int st, const PassArgs &a
 // [rows][tiles per row], for a log-det finished by one reduction kernel.
 int launch_real_top(int dtype, int mode, const PassArgs &a, double *lam_out, hipStream_t s,
                     bool src_f32 = false, double *ld_part = nullptr);
+
+// The fused fit's top passes (FP64 lattice, one right-hand side per column
+// row): aK's tiles give the eigenvalues (lam_out, and the log-det partial
+// sums when ld_part is set), aY's tiles the filtered solve by
+// aY.scale / (lambda + aY.sigma2), in one launch.  Same geometry for both;
+// the geometry's logE is 2 or 3 and 2^(a + logW - logE) a multiple of 64, at
+// most 256.
+int launch_fit_top(const PassArgs &aK, const PassArgs &aY, double *lam_out, double *ld_part,
+                   hipStream_t s);
+// Whether launch_fit_top takes geometry g.
+bool fit_top_supported(const PassGeom &g);
 
 // Two jobs of the same pass kind in one launch (blocks of job 0, then job 1).
 int launch_pass2(int kind, int dtype, int mode, int ld, int st, const PassArgs &a0,
