@@ -28,11 +28,12 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 
 # HBM bytes per launch of the gen_points kernel (k_gen_lattice) at n = 2^20,
-# d = 32, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a plain
-# 256 MiB device copy's counters (profiles/traffic_lattice_m20_d32_f64.md).
+# d = 32, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of `bench.py
+# --traffic-probe`, scaled by the counters of the plain 256 MiB device copy in
+# the same program (x2 reads, x1 writes; profiles/traffic_lattice_m20_d32_f64.md).
 # Valid only for the kernel source they were taken on: the sources' SHA-1 is
 # checked at run time and the figure reported as null once they change.
-GEN_TRAFFIC = {"read_MiB": 0.05, "write_MiB": 280.72,
+GEN_TRAFFIC = {"read_MiB": 0.04, "write_MiB": 256.00,
                "sources": ("points.hip", "pointset.hpp", "common.hpp"),
                "sha1": "2a543faf5c83018a484995a51b62ce5bc2797297"}
 
@@ -64,6 +65,10 @@ def parse():
                    help="skip the batched instance-table workload")
     p.add_argument("--batch-steps", type=int, default=10)
     p.add_argument("--cpu-seconds", type=float, default=10.0)
+    p.add_argument("--traffic-probe", action="store_true",
+                   help="only run the step eagerly 5 times and a 256 MiB device copy 5 times "
+                        "(a short program for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs; the "
+                        "copy calibrates the counters), then exit")
     p.add_argument("--copy-probe", action="store_true",
                    help="also run a plain device copy of known size (counter calibration)")
     return p.parse_args()
@@ -121,6 +126,17 @@ def main():
         ldk.kernel_column(kern, ps, 0, n, dtype=torch.float64, out=k1)
         # eigenvalues, solve and log-det in one call (shared tile passes)
         ldk.fit("lattice", k1, w["sigma2"], y, lam=lam, c=c, logdet=ld, ws=ws_fit)
+
+    if args.traffic_probe:
+        for _ in range(5):
+            step()
+        src = torch.empty(32 * 2**20, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"traffic_probe": True, "copy_bytes": src.numel() * 8}), flush=True)
+        return
 
     for _ in range(args.warmup):
         step()

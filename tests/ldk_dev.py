@@ -72,10 +72,11 @@ def solve_tol(lam, sigma2, y, c, m, eps):
 
 
 def record(name, **vals):
-    """Append measured errors to gpurun_out/parity_errors.jsonl (when present)."""
+    """Append measured errors as one JSON line to the file named by the
+    environment variable LDK_ERROR_LOG (nothing when it is unset)."""
     import json
     import os
-    d = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
-    if os.path.isdir(d):
-        with open(os.path.join(d, "parity_errors.jsonl"), "a") as f:
+    path = os.environ.get("LDK_ERROR_LOG")
+    if path:
+        with open(path, "a") as f:
             f.write(json.dumps({"case": name, **{k: float(v) for k, v in vals.items()}}) + "\n")
