@@ -37,10 +37,17 @@ __device__ __forceinline__ void lattice_tile(const KcolArgs &a, int64_t first, R
             base = m == 0 ? 0 : ((bfirst * g) << (64 - m));
             G = m <= 8 ? 0 : ((g << 8) << (64 - m));
         }
+        // natural order: G has no low-half bits, so the points of a thread
+        // share the low half of delta and differ in the high half only
+        const R lo_p = lo_part<R>((uint32_t)base);
 #pragma unroll
         for (int l = 0; l < KC_ITERS; ++l) {
-            const uint64_t delta = base + (ORDER == LDK_NATURAL ? br3[l] : (uint64_t)l) * G;
-            const R f = si_weighted<R, ALPHA>(unit<R>(delta), c0, c1, c2, c3);
+            R x;
+            if constexpr (ORDER == LDK_NATURAL)
+                x = unit_hl<R>((uint32_t)(base >> 32) + (uint32_t)br3[l] * (uint32_t)(G >> 32), lo_p);
+            else
+                x = unit<R>(base + (uint64_t)l * G);
+            const R f = si_weighted<R, ALPHA>(x, c0, c1, c2, c3);
             if (FULL) {
                 prod[l] *= f;
             } else {

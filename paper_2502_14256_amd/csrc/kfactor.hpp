@@ -102,6 +102,18 @@ __device__ __forceinline__ uint32_t opaque32(uint32_t v)
     return v;
 }
 
+// A double constant held in scalar registers: a three-operand multiply-add
+// cannot take a 64-bit literal, and with the literal the compiler falls back
+// to the two-operand form plus a register copy.
+__device__ __forceinline__ double scalar_const(double c)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(c);
+    uint32_t lo = (uint32_t)u, hi = (uint32_t)(u >> 32);
+    asm("" : "+s"(lo));
+    asm("" : "+s"(hi));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 // Coordinate value x = u 2^-64.  FP64: rounded to nearest (two exact
 // conversions, one fused multiply-add).  FP32: the top 32 digits rounded to
 // 24 bits (absolute error below 2^-24 x + 2^-32, far inside the FP32
@@ -111,8 +123,9 @@ __device__ __forceinline__ R unit(uint64_t u);
 template <>
 __device__ __forceinline__ double unit<double>(uint64_t u)
 {
-    return __fma_rn((double)opaque32((uint32_t)(u >> 32)), 4294967296.0,
-                    (double)opaque32((uint32_t)u)) * 0x1p-64;
+    // hi 2^-32 + lo 2^-64: both terms exact, one rounding
+    return __fma_rn((double)opaque32((uint32_t)(u >> 32)), scalar_const(0x1p-32),
+                    (double)opaque32((uint32_t)u) * scalar_const(0x1p-64));
 }
 template <>
 __device__ __forceinline__ float unit<float>(uint64_t u)
@@ -120,12 +133,54 @@ __device__ __forceinline__ float unit<float>(uint64_t u)
     return (float)opaque32((uint32_t)(u >> 32)) * 0x1p-32f;
 }
 
+// The same values from the two halves of u, with the low half's part
+// lo_part(lo) computed once where several words share their low half:
+// hi 2^-32 + lo 2^-64 rounded once is the value unit<double> returns.
+template <typename R>
+__device__ __forceinline__ R lo_part(uint32_t lo);
+template <>
+__device__ __forceinline__ double lo_part<double>(uint32_t lo)
+{
+    return (double)opaque32(lo) * scalar_const(0x1p-64);  // exact
+}
+template <>
+__device__ __forceinline__ float lo_part<float>(uint32_t)
+{
+    return 0.0f;  // FP32 takes the top 32 digits only
+}
+template <typename R>
+__device__ __forceinline__ R unit_hl(uint32_t hi, R lo_p);
+template <>
+__device__ __forceinline__ double unit_hl<double>(uint32_t hi, double lo_p)
+{
+    return __fma_rn((double)opaque32(hi), scalar_const(0x1p-32), lo_p);
+}
+template <>
+__device__ __forceinline__ float unit_hl<float>(uint32_t hi, float)
+{
+    return (float)opaque32(hi) * 0x1p-32f;
+}
+
 template <typename R, int ALPHA>
 __device__ __forceinline__ R dsi_factor(uint64_t delta, const DsiTables &tab)
 {
-    // beta = 1 + clz(delta) for delta != 0; beta = x = t_nu = 0 at delta = 0
-    const bool nz = delta != 0;
-    const int beta = nz ? clz64(delta) + 1 : 0;
+    // beta = 1 + clz(delta) for delta != 0; beta = x = t_nu = 0 at delta = 0.
+    // FP32 sees the top 32 digits only: where they are all zero, x = 0 and
+    // t_nu <= 2^-33 lies below half an ulp of every term it enters (1 - 3 t1,
+    // 1.5 - 2.5 t1, 1 - t_nu), so beta and t_nu are taken as 0 there, as at
+    // delta = 0: one 32-bit count instead of a 64-bit one.  (For alpha = 4
+    // the beta-weighted series term, exactly zero there, is then dropped
+    // instead of carrying its FP32 rounding.)
+    bool nz;
+    int beta;
+    if constexpr (std::is_same<R, float>::value) {
+        const uint32_t hi = (uint32_t)(delta >> 32);
+        nz = hi != 0;
+        beta = nz ? __clz((int)hi) + 1 : 0;
+    } else {
+        nz = delta != 0;
+        beta = nz ? clz64(delta) + 1 : 0;
+    }
     const R x = unit<R>(delta);  // 0 at delta = 0
     const R b = (R)beta;
     const R t1 = nz ? pow2_neg_r<R>(beta) : (R)0;

@@ -93,10 +93,14 @@ __device__ __forceinline__ void lattice_sweep(const KcolArgs &a, int64_t first, 
             G = m <= 8 ? 0 : ((g << 8) << (64 - m));
         }
         R t[KC_ITERS], f[KC_ITERS];
+        const R lo_p = lo_part<R>((uint32_t)base);  // shared low half (natural order)
 #pragma unroll
         for (int l = 0; l < KC_ITERS; ++l) {
-            const uint64_t delta = base + (ORDER == LDK_NATURAL ? br3[l] : (uint64_t)l) * G;
-            const R x = unit<R>(delta);
+            R x;
+            if constexpr (ORDER == LDK_NATURAL)
+                x = unit_hl<R>((uint32_t)(base >> 32) + (uint32_t)br3[l] * (uint32_t)(G >> 32), lo_p);
+            else
+                x = unit<R>(base + (uint64_t)l * G);
             t[l] = si_weighted<R, ALPHA>(x, e0, c1, c2, c3);
             f[l] = si_weighted<R, ALPHA>(x, c0, c1, c2, c3);
         }
