@@ -10,10 +10,15 @@
 // (Y the unnormalised length-n FFTBR of y).  The eigenvalues are
 // lambda_k = Re Y_k and lambda_{k+N} = Re Y_{k+N}.  A solve filters with the
 // symmetrised factor d_k = (f(lambda_k) + f(lambda_{n-k}))/2, which equals
-// Re IFFTBR(Y (.) f(lambda)) exactly, then re-packs
+// Re IFFTBR(Y (.) f(lambda)) exactly, then re-packs C_k = d_k Y_k as
 //   E'_k = (C_k + C_{k+N}) / 2,   O'_k = conj(W_n^k) (C_k - C_{k+N}) / 2,
 //   Z'_k = E'_k + i O'_k,
 // and the inverse passes return c_e + i c_{e+N} = IFFTBR_N(Z')_e / N.
+// Untangling, filtering and re-packing compose to one real-coefficient step
+// per element: with s1 = d_k, s2 = d_{k+N} and W_n^k = c + i s,
+//   Z'_k = p Z_k + i q conj(Z_{N-k}),  p = (s1+s2)/2 + s (s1-s2)/2,
+//   q = c (s1-s2)/2
+// (expand E' + i O' with conj(W) W = 1: the E + i O part is Z_k itself).
 //
 // The partner N - k of a frequency k = k1 + N1 k2 (k1 the column bits below
 // b0, k2 the top pass's axis bits) is (N1 - k1) + N1 (N2 - 1 - k2) for k1 != 0
@@ -168,6 +173,15 @@ __device__ __forceinline__ void real_top_body(const PassArgs &a, double *lam_out
         }
         const T zm = lds[lds_idx(k2p * W + wp)];
         const T zk = v[i];
+        if constexpr (MODE == PM_SOLVE || MODE == PM_MATVEC) {
+            // untangle, filter by s1 at k and s2 at k + N, re-pack, in one
+            // step: Z'_k = p Z_k + i q conj(Z_{N-k}) with real
+            // p = (s1 + s2)/2 + (s1 - s2)/2 Im W_n^k, q = (s1 - s2)/2 Re W_n^k
+            const R hs = (R)(0.5 * (f1[i] + f2[i])), hd = (R)(0.5 * (f1[i] - f2[i]));
+            const R pc = hs + hd * wkv[i].im, qc = hd * wkv[i].re;
+            v[i] = T{pc * zk.re + qc * zm.im, pc * zk.im + qc * zm.re};
+            continue;
+        }
         const int64_t k = k1 + N1 * k2;
         const T ev{(zk.re + zm.re) * (R)0.5, (zk.im - zm.im) * (R)0.5};
         const T dv{(zk.re - zm.re) * (R)0.5, (zk.im + zm.im) * (R)0.5};
@@ -188,13 +202,6 @@ __device__ __forceinline__ void real_top_body(const PassArgs &a, double *lam_out
             lam_out[row * n + k] = (double)yk.re * (double)yk.re + (double)yk.im * (double)yk.im;
             lam_out[row * n + k + N] =
                 (double)ykn.re * (double)ykn.re + (double)ykn.im * (double)ykn.im;
-        } else {
-            const double s1 = f1[i], s2 = f2[i];
-            const T c1{yk.re * (R)s1, yk.im * (R)s1};
-            const T c2{ykn.re * (R)s2, ykn.im * (R)s2};
-            const T ep{(c1.re + c2.re) * (R)0.5, (c1.im + c2.im) * (R)0.5};
-            const T op = cmulc(T{(c1.re - c2.re) * (R)0.5, (c1.im - c2.im) * (R)0.5}, wk);
-            v[i] = T{ep.re - op.im, ep.im + op.re};
         }
     }
     if constexpr (MODE == PM_FWD) {
@@ -394,11 +401,10 @@ __global__ __launch_bounds__(512) void k_fit_top(PassArgs aK, PassArgs aY, doubl
             ld_part[row * cb_count + cb] = sacc;
         }
     } else {
-        // ---- rhs half: filter by the symmetrised 1/(lambda + s2), re-pack
+        // ---- rhs half: filter by the symmetrised 1/(lambda + s2) and re-pack,
+        // as Z'_k = p Z_k + i q conj(Z_{N-k}) (see real_top_body)
 #pragma unroll
         for (int i = 0; i < E; ++i) {
-            T yk, ykn;
-            untangle(i, yk, ykn);
             const int q = t + Tn * i;
             const int qp = partner(q);
             const int64_t k = col_of(q & (W - 1)) + N1 * (int64_t)(q >> logW);
@@ -410,11 +416,10 @@ __global__ __launch_bounds__(512) void k_fit_top(PassArgs aK, PassArgs aY, doubl
             const double pc = l_kN + aY.sigma2, pd = l_Nk + aY.sigma2;
             const double s1 = 0.5 * aY.scale * (pa + pb) / (pa * pb);
             const double s2 = 0.5 * aY.scale * (pc + pd) / (pc * pd);
-            const T c1{yk.re * s1, yk.im * s1};
-            const T c2{ykn.re * s2, ykn.im * s2};
-            const T ep{(c1.re + c2.re) * (R)0.5, (c1.im + c2.im) * (R)0.5};
-            const T op = cmulc(T{(c1.re - c2.re) * (R)0.5, (c1.im - c2.im) * (R)0.5}, wkv[i]);
-            v[i] = T{ep.re - op.im, ep.im + op.re};
+            const double hs = 0.5 * (s1 + s2), hd = 0.5 * (s1 - s2);
+            const double pk = hs + hd * wkv[i].im, qk = hd * wkv[i].re;
+            const T zm = lds[lds_idx(qp)], zk = v[i];
+            v[i] = T{pk * zk.re + qk * zm.im, pk * zk.im + qk * zm.re};
         }
         reg_inv<T, E, LOGE>(v, LOGE);
     }
