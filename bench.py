@@ -2,7 +2,9 @@
 
 A step is one pass of the whole path over the rank-1 lattice workload
 (n = 2^20, d = 32, order-2 SI kernel, gamma_j = 1/j^2, sigma^2 = 1e-3):
-  gen_points -> kernel_column -> fit (eig (FFTBR), solve, logdet in one call),
+  points + first column in one call (points_column: the point words and
+  k1, the column regenerating the points in registers) -> fit (eig (FFTBR),
+  solve, logdet in one call),
 with the generating vector, shift and responses already resident in HBM.
 The metric counts one Gram solve (K + sigma^2 I)^-1 y per step.
 
@@ -27,27 +29,30 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 
-# HBM bytes per launch of the gen_points kernel (k_gen_lattice) at n = 2^20,
-# d = 32, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of `bench.py
-# --traffic-probe`, scaled by the counters of the plain 256 MiB device copy in
-# the same program (x2 reads, x1 writes; profiles/traffic_lattice_m20_d32_f64.md).
-# Valid only for the kernel source they were taken on: the sources' SHA-1 is
-# checked at run time and the figure reported as null once they change.
-GEN_TRAFFIC = {"read_MiB": 0.04, "write_MiB": 256.00,
-               "sources": ("points.hip", "pointset.hpp", "common.hpp"),
-               "sha1": "2a543faf5c83018a484995a51b62ce5bc2797297"}
+# HBM bytes per launch of the points + column kernel (k_points_kcol_lattice)
+# at n = 2^20, d = 32, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of
+# `bench.py --traffic-probe`, scaled by the counters of the plain 256 MiB
+# device copy in the same program (x2 reads, x1 writes;
+# profiles/traffic_lattice_m20_d32_f64.md).  Valid only for the kernel source
+# they were taken on: the sources' SHA-1 is checked at run time and the figure
+# reported as null once they change.
+STEP_TRAFFIC = {"read_MiB": 0.13, "write_MiB": 264.00,
+                "sources": ("kcol.hip", "kfactor.hpp", "pointset.hpp", "common.hpp"),
+                "sha1": "843fd5ad8b0db40e289860a07d24b78a5ed2d0ae"}
 
 
-def gen_traffic_bytes():
+def step_traffic_bytes():
     import hashlib
 
+    if STEP_TRAFFIC["sha1"] is None:
+        return None
     h = hashlib.sha1()
-    for f in GEN_TRAFFIC["sources"]:
+    for f in STEP_TRAFFIC["sources"]:
         with open(os.path.join(ROOT, "paper_2502_14256_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest() != GEN_TRAFFIC["sha1"]:
+    if h.hexdigest() != STEP_TRAFFIC["sha1"]:
         return None
-    return int((GEN_TRAFFIC["read_MiB"] + GEN_TRAFFIC["write_MiB"]) * 2**20)
+    return int((STEP_TRAFFIC["read_MiB"] + STEP_TRAFFIC["write_MiB"]) * 2**20)
 
 
 def parse():
@@ -119,11 +124,12 @@ def main():
     ws_eig = ldk._workspace(ldk.OP_EIG, ldk.LATTICE, R, m, ldk.F64, "cuda")
     ws_fit = ldk._workspace(ldk.OP_FIT, ldk.LATTICE, R * 2, m, ldk._dtype_code(dt), "cuda")
 
-    ops = ["gen_points", "kernel_column", "fit"]
+    ops = ["points_column", "fit"]
 
     def step():
-        ldk.gen_points(ps, 0, n, out=pts)
-        ldk.kernel_column(kern, ps, 0, n, dtype=torch.float64, out=k1)
+        # point words and first column in one launch (the column regenerates
+        # the points in registers, so the two run side by side)
+        ldk.points_column(kern, ps, 0, n, dtype=torch.float64, pts=pts, k1=k1)
         # eigenvalues, solve and log-det in one call (shared tile passes)
         ldk.fit("lattice", k1, w["sigma2"], y, lam=lam, c=c, logdet=ld, ws=ws_fit)
 
@@ -177,6 +183,8 @@ def main():
     # timed region 2: each op alone, captured in its own graph and replayed K
     # times back to back (device time per launch, no host gaps)
     op_calls = {
+        "points_column": lambda: ldk.points_column(kern, ps, 0, n, dtype=torch.float64, pts=pts,
+                                                   k1=k1),
         "gen_points": lambda: ldk.gen_points(ps, 0, n, out=pts),
         "kernel_column": lambda: ldk.kernel_column(kern, ps, 0, n, dtype=torch.float64, out=k1),
         "fit": lambda: ldk.fit("lattice", k1, w["sigma2"], y, lam=lam, c=c, logdet=ld, ws=ws_fit),
@@ -185,10 +193,12 @@ def main():
         "logdet": lambda: ldk.logdet(lam, w["sigma2"], out=ld, ws=ws_ld),
     }
     per_op = {op: time_graph(op_calls[op], K) for op in ops}
-    # the separate entry points the fit replaces, timed alone
-    unfused = {op: round(time_graph(op_calls[op], K), 5) for op in ("eig", "solve", "logdet")}
+    # the separate entry points the fused calls replace, timed alone
+    unfused = {op: round(time_graph(op_calls[op], K), 5)
+               for op in ("gen_points", "kernel_column", "eig", "solve", "logdet")}
     # algorithmic bytes per op (one launch of each op per step)
     alg = {
+        "points_column": 8 * (d + 1) * n * R,     # write the point words and k1
         "gen_points": 8 * n * d * R,              # write the point words
         "kernel_column": 8 * n * R,               # write k1 (points regenerated in registers)
         "fit": (2 * esz + 8 + 8) * n * R,         # read k1 and y, write lambda and c
@@ -201,15 +211,13 @@ def main():
                     "GB_s": round(alg[op] / (per_op[op] * 1e-3) / 1e9, 1),
                     "hbm_frac": round(alg[op] / (per_op[op] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
                for op in ops}
-    # The roofline is taken on the longest single kernel of the step: the ops
-    # that are one launch each (the fit is three kernels, the longest of
-    # them, the fused top pass, ~25 us against ~45 us for the point words).
-    single_kernel = {"gen_points": "k_gen_lattice", "kernel_column": "k_kcol_lattice"}
-    dom = max(single_kernel, key=lambda o: per_op[o])
-    roof_dom = {"kernel": f"{single_kernel[dom]} ({dom})", "bound": "hbm",
+    # The roofline is taken on the longest single kernel of the step, the
+    # points + column launch (the fit is three kernels, the longest of them,
+    # the fused top pass, ~28 us against ~52 us).
+    dom = "points_column"
+    roof_dom = {"kernel": "k_points_kcol_lattice (points_column)", "bound": "hbm",
                 "achieved": op_rows[dom]["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": op_rows[dom]["hbm_frac"],
-                "traffic": gen_traffic_bytes() if dom == "gen_points" else None}
+                "frac": op_rows[dom]["hbm_frac"], "traffic": step_traffic_bytes()}
     ms_per_step = total_ms / K
     solves_per_s = R * K / (total_ms * 1e-3)
 
@@ -227,8 +235,8 @@ def main():
         "dtype": args.dtype,
         "data": "synthetic",
         "config": {"workload": "lattice_m20_d32_si2 (rank-1 lattice n=2^20 d=32, order-2 SI "
-                               "kernel, gamma_j=1/j^2, sigma^2=1e-3, one RHS): gen_points + "
-                               "kernel_column + fit (eig, solve, logdet) per step",
+                               "kernel, gamma_j=1/j^2, sigma^2=1e-3, one RHS): points + first "
+                               "column (one call) + fit (eig, solve, logdet) per step",
                    "n": n, "d": d, "R": R, "nrhs": 1},
         "roofline": roof_dom,
         "fit_roofline": {"bound": "hbm", "kernels": 3, "achieved": op_rows["fit"]["GB_s"],

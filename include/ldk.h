@@ -138,6 +138,17 @@ int ldk_kernel_column(const ldk_kernel *k, const ldk_pointset *ps, const uint64_
                       const uint64_t *x0, int64_t n_min, int64_t n_max, int dtype,
                       void *out, ldk_stream stream);
 
+/* Points and first Gram column in one call: the outputs of
+ *   ldk_gen_points(ps, n_min, n_max, pts) and
+ *   ldk_kernel_column(k, ps, NULL, NULL, n_min, n_max, dtype, k1),
+ * bit for bit (Sec. 4.2, 4.3 and 5.4), with the same arguments, layouts and
+ * restrictions.  The column regenerates the points in registers and does
+ * not read pts, so for lattices the two run as one launch, the column's
+ * arithmetic beside the point words' stores; nets run the two calls one
+ * after the other.  pts and k1 must not overlap. */
+int ldk_points_column(const ldk_kernel *k, const ldk_pointset *ps, int64_t n_min, int64_t n_max,
+                      uint64_t *pts, int dtype, void *k1, ldk_stream stream);
+
 /* Orthonormal transform of B rows of length n = 2^m (Figure 3, Sec. 5.2-5.3).
  *  LDK_LATTICE: complex rows; dir = +1 FFTBR  y_k = n^-1/2 sum_j x_j W^{k R_m(j)},
  *               dir = -1 IFFTBR (its inverse), W = exp(-2 pi i / n).

@@ -31,7 +31,7 @@ EXPORTS = [
     "ldk_matvec", "ldk_logdet", "ldk_update_double", "ldk_eig_update_double",
     "ldk_workspace_bytes", "ldk_strerror", "ldk_last_hip_error", "ldk_version",
     "ldk_mll", "ldk_mll_adjoint", "ldk_kernel_grad", "ldk_kernel_grad_workspace_bytes",
-    "ldk_fwht_split16", "ldk_fit",
+    "ldk_fwht_split16", "ldk_fit", "ldk_points_column",
 ]
 
 
@@ -65,6 +65,7 @@ def lib():
             "ldk_init": ([], i32),
             "ldk_gen_points": ([P, i64, i64, P, P], i32),
             "ldk_kernel_column": ([P, P, P, P, i64, i64, i32, P, P], i32),
+            "ldk_points_column": ([P, P, i64, i64, P, i32, P, P], i32),
             "ldk_transform": ([i32, i32, i32, i32, i32, P, P, P, P], i32),
             "ldk_eig": ([i32, i32, i32, i32, P, P, P, P], i32),
             "ldk_solve": ([i32, i32, i32, i32, i32, P, f64, P, P, P, P], i32),
@@ -215,6 +216,21 @@ def kernel_column(k: Kernel, ps: PointSet, n_min: int, n_max: int, pts=None, x0=
     _check(lib().ldk_kernel_column(C.byref(k._c()), C.byref(ps._c()), _ptr(pts), _ptr(x0), n_min,
                                    n_max, dt, _ptr(out), _stream()), "ldk_kernel_column")
     return out
+
+
+def points_column(k: Kernel, ps: PointSet, n_min: int, n_max: int, dtype=torch.float64,
+                  pts: torch.Tensor | None = None, k1: torch.Tensor | None = None):
+    """(points, first column): gen_points and kernel_column (points
+    regenerated) in one call, bit for bit the same outputs."""
+    dt = _dtype_code(dtype)
+    dev = ps.gen.device
+    if pts is None:
+        pts = torch.empty((ps.R, n_max - n_min, ps.d), dtype=torch.int64, device=dev)
+    if k1 is None:
+        k1 = torch.empty((ps.R, n_max - n_min), dtype=_real(dt), device=dev)
+    _check(lib().ldk_points_column(C.byref(k._c()), C.byref(ps._c()), n_min, n_max, _ptr(pts), dt,
+                                   _ptr(k1), _stream()), "ldk_points_column")
+    return pts, k1
 
 
 def _m_of(n: int) -> int:

@@ -58,13 +58,13 @@ __device__ __forceinline__ void lattice_tile(const KcolArgs &a, int64_t first, R
     }
 }
 
+// Column tile bx of replication r (KC_TILE points from tile_base + bx KC_TILE).
 template <typename R, int ALPHA, int ORDER>
-__global__ __launch_bounds__(KC_THREADS) void k_kcol_lattice(KcolArgs a, int64_t tile_base,
-                                                            R *__restrict__ out)
+__device__ __forceinline__ void kcol_lattice_block(const KcolArgs &a, int64_t tile_base,
+                                                   R *__restrict__ out, int64_t bx, int r)
 {
-    const int r = blockIdx.y;
     const int64_t cnt = a.n_max - a.n_min;
-    const int64_t tile0 = tile_base + (int64_t)blockIdx.x * KC_TILE;
+    const int64_t tile0 = tile_base + bx * KC_TILE;
     const int64_t first = tile0 + threadIdx.x;
     R prod[KC_ITERS];
 #pragma unroll
@@ -78,6 +78,40 @@ __global__ __launch_bounds__(KC_THREADS) void k_kcol_lattice(KcolArgs a, int64_t
         const int64_t i = first + (int64_t)l * KC_THREADS;
         if (i >= a.n_min && i < a.n_max) out[(size_t)r * cnt + (i - a.n_min)] = prod[l];
     }
+}
+
+template <typename R, int ALPHA, int ORDER>
+__global__ __launch_bounds__(KC_THREADS) void k_kcol_lattice(KcolArgs a, int64_t tile_base,
+                                                            R *__restrict__ out)
+{
+    kcol_lattice_block<R, ALPHA, ORDER>(a, tile_base, out, blockIdx.x, blockIdx.y);
+}
+
+// Point words and first column of a lattice in one launch.  The column
+// regenerates the points in registers and never reads the words, so the
+// two halves are independent: blocks [0, kc_blocks) are column tiles (VALU
+// bound), the rest write the point words (store bound).  The column blocks
+// come first, so they start at once and the point blocks fill the slots
+// beside them, instead of the column waiting for 256 MiB of stores (two
+// launches) or for free slots (two streams: the point launch takes every
+// slot).
+static_assert(GEN_THREADS == KC_THREADS, "one block shape for both halves");
+template <typename R, int ALPHA, int ORDER>
+__global__ __launch_bounds__(KC_THREADS) void k_points_kcol_lattice(KcolArgs a, int64_t tile_base,
+                                                                   int64_t kc_tiles,
+                                                                   R *__restrict__ k1, GenGrid g,
+                                                                   uint64_t *__restrict__ pts)
+{
+    const int64_t b = blockIdx.x;
+    const int64_t kc_blocks = kc_tiles * a.ps.R;
+    if (b < kc_blocks) {
+        kcol_lattice_block<R, ALPHA, ORDER>(a, tile_base, k1, b % kc_tiles, (int)(b / kc_tiles));
+        return;
+    }
+    const int64_t q = b - kc_blocks;
+    gen_lattice_block(a.ps, a.n_min, a.n_max, g.P, g.pairs != 0, pts, q % g.tiles,
+                      (int)((q / g.tiles) % g.chunks), (int)(q / (g.tiles * g.chunks)),
+                      threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -196,6 +230,31 @@ void launch_regen(const KcolArgs &a, int64_t tile_base, dim3 grid, hipStream_t s
                            tile_base, (R *)out);
 }
 
+template <typename R, int ALPHA>
+void launch_points_kcol(const KcolArgs &a, int64_t tile_base, int64_t kc_tiles, const GenGrid &g,
+                        unsigned blocks, hipStream_t s, void *k1, uint64_t *pts)
+{
+    if (a.ps.order == LDK_LINEAR)
+        hipLaunchKernelGGL((k_points_kcol_lattice<R, ALPHA, LDK_LINEAR>), dim3(blocks),
+                           dim3(KC_THREADS), 0, s, a, tile_base, kc_tiles, (R *)k1, g, pts);
+    else
+        hipLaunchKernelGGL((k_points_kcol_lattice<R, ALPHA, LDK_NATURAL>), dim3(blocks),
+                           dim3(KC_THREADS), 0, s, a, tile_base, kc_tiles, (R *)k1, g, pts);
+}
+
+template <typename R>
+void launch_points_kcol_alpha(int alpha, const KcolArgs &a, int64_t tile_base, int64_t kc_tiles,
+                              const GenGrid &g, unsigned blocks, hipStream_t s, void *k1,
+                              uint64_t *pts)
+{
+    switch (alpha) {  // lattice orders 1..3, mixed orders 0
+    case 1: launch_points_kcol<R, 1>(a, tile_base, kc_tiles, g, blocks, s, k1, pts); break;
+    case 2: launch_points_kcol<R, 2>(a, tile_base, kc_tiles, g, blocks, s, k1, pts); break;
+    case 3: launch_points_kcol<R, 3>(a, tile_base, kc_tiles, g, blocks, s, k1, pts); break;
+    default: launch_points_kcol<R, 0>(a, tile_base, kc_tiles, g, blocks, s, k1, pts);
+    }
+}
+
 template <typename R>
 void launch_regen_alpha(int kind, int alpha, const KcolArgs &a, int64_t tile_base, dim3 grid,
                         hipStream_t s, void *out)
@@ -301,6 +360,41 @@ extern "C" int ldk_kernel_column(const ldk_kernel *k, const ldk_pointset *ps, co
         launch_regen_alpha<double>(p.kind, uniform, a, tile_base, grid, s, out);
     else
         launch_regen_alpha<float>(p.kind, uniform, a, tile_base, grid, s, out);
+    LDK_LAUNCH_CHECK();
+    return LDK_OK;
+}
+
+extern "C" int ldk_points_column(const ldk_kernel *k, const ldk_pointset *ps, int64_t n_min,
+                                 int64_t n_max, uint64_t *pts, int dtype, void *k1,
+                                 ldk_stream stream)
+{
+    KcolArgs a;
+    int uniform = 0;
+    int st = prepare_kernel_args(k, ps, nullptr, nullptr, n_min, n_max, dtype, &a, &uniform);
+    if (st) return st;
+    const PointsetArgs &p = a.ps;
+    const int64_t lim = (p.kind == LDK_LATTICE && p.order == LDK_NATURAL) ? ((int64_t)1 << 62)
+                                                                          : ((int64_t)1 << p.m_max);
+    if (n_min < 0 || n_max < n_min || n_max > lim) return LDK_EINVAL;
+    if (n_max == n_min) return LDK_OK;  // empty window: the outputs may be NULL
+    if (!pts || !k1) return LDK_EINVAL;
+    if (p.kind != LDK_LATTICE) {
+        st = ldk_gen_points(ps, n_min, n_max, pts, stream);
+        if (st) return st;
+        return ldk_kernel_column(k, ps, nullptr, nullptr, n_min, n_max, dtype, k1, stream);
+    }
+    const int64_t tile_base = (n_min / KC_TILE) * KC_TILE;
+    const int64_t kc_tiles = (n_max - tile_base + KC_TILE - 1) / KC_TILE;
+    const GenGrid g = gen_grid(p, n_min, n_max, pts);
+    const int64_t blocks = kc_tiles * p.R + g.tiles * g.chunks * g.R;
+    if (blocks > 0x7fffffff) return LDK_ENOTSUP;
+    hipStream_t s = as_stream(stream);
+    if (dtype == LDK_F64)
+        launch_points_kcol_alpha<double>(uniform, a, tile_base, kc_tiles, g, (unsigned)blocks, s, k1,
+                                         pts);
+    else
+        launch_points_kcol_alpha<float>(uniform, a, tile_base, kc_tiles, g, (unsigned)blocks, s, k1,
+                                        pts);
     LDK_LAUNCH_CHECK();
     return LDK_OK;
 }

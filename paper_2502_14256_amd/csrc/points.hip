@@ -5,13 +5,6 @@
 
 namespace ldk {
 
-namespace {
-constexpr int GEN_THREADS = 256;
-constexpr int GEN_DIM_CHUNK = 32;  // dimensions per block
-constexpr int GEN_ITERS = 32;      // points per thread (lattices)
-constexpr int GEN_ITERS_NET = 128; // points per thread (nets: amortises the scrambling)
-}  // namespace
-
 int validate_pointset(const ldk_pointset *ps, PointsetArgs *out)
 {
     if (!ps || !out) return LDK_EINVAL;
@@ -29,14 +22,6 @@ int validate_pointset(const ldk_pointset *ps, PointsetArgs *out)
     }
     *out = PointsetArgs{ps->kind, ps->order, ps->R, ps->d, ps->m_max, ps->gen, ps->lms, ps->shift};
     return LDK_OK;
-}
-
-// Largest power of two P with P * dims <= GEN_THREADS.
-static int point_lanes(int dims)
-{
-    int P = 1;
-    while (2 * P * dims <= GEN_THREADS) P *= 2;
-    return P;
 }
 
 // Block: one replication r, dims [j0, j0 + DB), points
@@ -107,28 +92,11 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_net(PointsetArgs a, int64_t
 }
 
 __global__ __launch_bounds__(GEN_THREADS) void k_gen_lattice(PointsetArgs a, int64_t n_min,
-                                                             int64_t n_max, int P,
+                                                             int64_t n_max, int P, int pairs,
                                                              uint64_t *__restrict__ out)
 {
-    const int r = blockIdx.z;
-    const int j0 = blockIdx.y * GEN_DIM_CHUNK;
-    const int DB = min(GEN_DIM_CHUNK, a.d - j0);
-    const int t = threadIdx.x;
-    const int p = t / DB, jj = t % DB;
-    if (p >= P) return;
-    const int j = j0 + jj;
-    const int64_t cnt = n_max - n_min;
-    const uint64_t g = a.gen[j];
-    const uint64_t delta = a.shift ? a.shift[(size_t)r * a.d + j] : 0;
-    const int64_t first = n_min + (int64_t)blockIdx.x * P * GEN_ITERS + p;
-    uint64_t *dst = out + ((size_t)r * cnt + (first - n_min)) * a.d + j;
-    const size_t dstep = (size_t)P * a.d;
-    int64_t i = first;
-    for (int k = 0; k < GEN_ITERS && i < n_max; ++k) {
-        *dst = lattice_point(g, (uint64_t)i, a.order, a.m_max) + delta;
-        i += P;
-        dst += dstep;
-    }
+    gen_lattice_block(a, n_min, n_max, P, pairs != 0, out, blockIdx.x, blockIdx.y, blockIdx.z,
+                      threadIdx.x);
 }
 
 }  // namespace ldk
@@ -148,20 +116,15 @@ extern "C" int ldk_gen_points(const ldk_pointset *ps, int64_t n_min, int64_t n_m
     if (n_max > lim) return LDK_EINVAL;
     if (n_max == n_min) return LDK_OK;  // empty window: out may be NULL
     if (!out) return LDK_EINVAL;
-    const int dims = a.d < GEN_DIM_CHUNK ? a.d : GEN_DIM_CHUNK;
-    const int P = point_lanes(dims);
-    int logP = 0;
-    while ((1 << logP) < P) ++logP;
-    const int iters = a.kind == LDK_LATTICE ? GEN_ITERS : GEN_ITERS_NET;
-    const int64_t tiles = (n_max - n_min + (int64_t)P * iters - 1) / ((int64_t)P * iters);
-    if (tiles > 0x7fffffff) return LDK_ENOTSUP;
-    dim3 grid((unsigned)tiles, (unsigned)((a.d + GEN_DIM_CHUNK - 1) / GEN_DIM_CHUNK), (unsigned)a.R);
+    const GenGrid g = gen_grid(a, n_min, n_max, out);
+    if (g.tiles > 0x7fffffff) return LDK_ENOTSUP;
+    dim3 grid((unsigned)g.tiles, (unsigned)g.chunks, (unsigned)g.R);
     if (a.kind == LDK_LATTICE)
         hipLaunchKernelGGL(k_gen_lattice, grid, dim3(GEN_THREADS), 0, as_stream(stream), a, n_min,
-                           n_max, P, out);
+                           n_max, g.P, g.pairs, out);
     else
         hipLaunchKernelGGL(k_gen_net, grid, dim3(GEN_THREADS), 0, as_stream(stream), a, n_min,
-                           n_max, P, logP, out);
+                           n_max, g.P, g.logP, out);
     LDK_LAUNCH_CHECK();
     return LDK_OK;
 }

@@ -57,4 +57,91 @@ __device__ __forceinline__ uint64_t lattice_point(uint64_t g, uint64_t i, int or
     return m == 0 ? 0 : ((i * g) << (64 - m));
 }
 
+// Point-word tiling (gen_points, and the point half of the fused points +
+// column launch): blocks of GEN_THREADS threads over (point tile, chunk of
+// GEN_DIM_CHUNK dimensions, replication).  Thread (p, jj) of a block writes
+// dimension j0 + jj of points tile + p + P k, P the largest power of two with
+// P * dims <= GEN_THREADS: consecutive threads write consecutive words.
+constexpr int GEN_THREADS = 256;
+constexpr int GEN_DIM_CHUNK = 32;   // dimensions per block
+constexpr int GEN_ITERS = 32;       // points per thread (lattices)
+constexpr int GEN_ITERS_NET = 128;  // points per thread (nets: amortises the scrambling)
+
+struct GenGrid {
+    int64_t tiles;  // point tiles per (chunk, replication)
+    int chunks;     // dimension chunks
+    int R;
+    int P, logP;
+    int pairs;      // lattice words written two dimensions per 16-byte store
+};
+
+// out: the destination (16-byte stores need an even d and a 16-byte aligned
+// destination).
+inline GenGrid gen_grid(const PointsetArgs &a, int64_t n_min, int64_t n_max, const void *out)
+{
+    GenGrid g{};
+    g.pairs = a.kind == LDK_LATTICE && (a.d & 1) == 0 && ((uintptr_t)out & 15) == 0;
+    int dims = a.d < GEN_DIM_CHUNK ? a.d : GEN_DIM_CHUNK;
+    if (g.pairs) dims >>= 1;
+    g.P = 1;
+    while (2 * g.P * dims <= GEN_THREADS) g.P *= 2;
+    while ((1 << g.logP) < g.P) ++g.logP;
+    const int iters = a.kind == LDK_LATTICE ? GEN_ITERS : GEN_ITERS_NET;
+    g.tiles = (n_max - n_min + (int64_t)g.P * iters - 1) / ((int64_t)g.P * iters);
+    g.chunks = (a.d + GEN_DIM_CHUNK - 1) / GEN_DIM_CHUNK;
+    g.R = a.R;
+    return g;
+}
+
+// One lattice block of the tiling: point tile bx, dimension chunk by,
+// replication r; thread t of GEN_THREADS.  With pairs (see GenGrid), a
+// thread writes dimensions j, j + 1 of its points as one 16-byte store.
+__device__ __forceinline__ void gen_lattice_block(const PointsetArgs &a, int64_t n_min,
+                                                  int64_t n_max, int P, bool pairs,
+                                                  uint64_t *__restrict__ out, int64_t bx, int by,
+                                                  int r, int t)
+{
+    if (pairs) {
+        const int j0 = by * GEN_DIM_CHUNK;
+        const int DB2 = min(GEN_DIM_CHUNK, a.d - j0) >> 1;  // dimension pairs
+        const int p = t / DB2, jj = t % DB2;
+        if (p >= P) return;
+        const int j = j0 + 2 * jj;
+        const int64_t cnt = n_max - n_min;
+        const uint64_t g0 = a.gen[j], g1 = a.gen[j + 1];
+        const uint64_t d0 = a.shift ? a.shift[(size_t)r * a.d + j] : 0;
+        const uint64_t d1 = a.shift ? a.shift[(size_t)r * a.d + j + 1] : 0;
+        const int64_t first = n_min + bx * P * GEN_ITERS + p;
+        uint64_t *dst = out + ((size_t)r * cnt + (first - n_min)) * a.d + j;
+        const size_t dstep = (size_t)P * a.d;
+        int64_t i = first;
+        for (int k = 0; k < GEN_ITERS && i < n_max; ++k) {
+            ulonglong2 w;
+            w.x = lattice_point(g0, (uint64_t)i, a.order, a.m_max) + d0;
+            w.y = lattice_point(g1, (uint64_t)i, a.order, a.m_max) + d1;
+            *reinterpret_cast<ulonglong2 *>(dst) = w;
+            i += P;
+            dst += dstep;
+        }
+        return;
+    }
+    const int j0 = by * GEN_DIM_CHUNK;
+    const int DB = min(GEN_DIM_CHUNK, a.d - j0);
+    const int p = t / DB, jj = t % DB;
+    if (p >= P) return;
+    const int j = j0 + jj;
+    const int64_t cnt = n_max - n_min;
+    const uint64_t g = a.gen[j];
+    const uint64_t delta = a.shift ? a.shift[(size_t)r * a.d + j] : 0;
+    const int64_t first = n_min + bx * P * GEN_ITERS + p;
+    uint64_t *dst = out + ((size_t)r * cnt + (first - n_min)) * a.d + j;
+    const size_t dstep = (size_t)P * a.d;
+    int64_t i = first;
+    for (int k = 0; k < GEN_ITERS && i < n_max; ++k) {
+        *dst = lattice_point(g, (uint64_t)i, a.order, a.m_max) + delta;
+        i += P;
+        dst += dstep;
+    }
+}
+
 }  // namespace ldk

@@ -1,0 +1,80 @@
+"""ldk_points_column (points and first Gram column in one call) against the
+two separate calls, ldk_gen_points and ldk_kernel_column with regenerated
+points: both outputs bit for bit (the same per-point arithmetic, one launch
+for lattices), and the points against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+import paper_2502_14256_amd as ldk
+from ldk_dev import host_u64, kernel, pointset
+
+pytestmark = pytest.mark.gpu
+
+F64, F32 = torch.float64, torch.float32
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _init():
+    ldk.init()
+
+
+def _case(kind, seed, m, d, R, alpha, order):
+    w = (W.small_net if kind == "dnet" else W.small_lattice)(seed, m=m, d=d, R=R)
+    if order != "natural":
+        w["order"] = order
+    w.update(alpha=np.asarray(alpha, np.int32), gamma=0.85 ** np.arange(d), zeta=1.1)
+    return w
+
+
+def _windows(n):
+    # whole, ragged both ends, one point, empty, and a window of whole tiles
+    a = min(100, n)
+    return sorted({(0, n), (a, max(a, n - 37)), (n - 1, n), (n // 3, n // 3),
+                   (min(2048, n), min(n, 2048 + 4096))})
+
+
+@pytest.mark.parametrize("kind,order", [("lattice", "natural"), ("lattice", "linear"),
+                                        ("dnet", "natural"), ("dnet", "gray")])
+@pytest.mark.parametrize("dtype", [F64, F32])
+@pytest.mark.parametrize("m,d,R,alpha", [(13, 7, 2, 2), (12, 33, 3, "mixed"), (5, 70, 1, 1),
+                                         (0, 3, 2, 3)])
+def test_points_column_equals_separate_calls(orc, kind, order, dtype, m, d, R, alpha):
+    amax = 4 if kind == "dnet" else 3
+    al = [1 + (j % amax) for j in range(d)] if alpha == "mixed" else [alpha] * d
+    w = _case(kind, 300 + m + d, m, d, R, al, order)
+    ps, k = pointset(w), kernel(w)
+    n = 2**m
+    for lo, hi in _windows(n):
+        pts, k1 = ldk.points_column(k, ps, lo, hi, dtype=dtype)
+        pts_ref = ldk.gen_points(ps, lo, hi)
+        k1_ref = ldk.kernel_column(k, ps, lo, hi, dtype=dtype)
+        assert torch.equal(pts, pts_ref), (lo, hi)
+        assert torch.equal(k1, k1_ref), (lo, hi)
+        assert np.array_equal(host_u64(pts), orc.points(w, lo, hi)), (lo, hi)
+
+
+def test_points_column_lattice_beyond_mmax(orc):
+    # natural-order lattices run past 2^m_max; the column anchors at point 0
+    w = _case("lattice", 9, 4, 6, 2, [2] * 6, "natural")
+    ps, k = pointset(w), kernel(w)
+    pts, k1 = ldk.points_column(k, ps, 1000, 5300)
+    assert torch.equal(pts, ldk.gen_points(ps, 1000, 5300))
+    assert torch.equal(k1, ldk.kernel_column(k, ps, 1000, 5300))
+
+
+def test_points_column_workload_size():
+    # the benchmark's shape: n = 2^20, d = 32, order-2 SI kernel
+    w = W.workload(2)
+    ps, k = pointset(w), kernel(w)
+    n = 2**w["m"]
+    pts, k1 = ldk.points_column(k, ps, 0, n)
+    assert torch.equal(pts, ldk.gen_points(ps, 0, n))
+    assert torch.equal(k1, ldk.kernel_column(k, ps, 0, n))
+
+
+def test_points_column_empty_window():
+    w = _case("lattice", 3, 6, 4, 1, [1] * 4, "natural")
+    pts, k1 = ldk.points_column(kernel(w), pointset(w), 10, 10)
+    assert pts.shape == (1, 0, 4) and k1.shape == (1, 0)

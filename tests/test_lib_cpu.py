@@ -94,6 +94,26 @@ def test_kernel_column_rejects_mismatch():
     assert L.ldk_kernel_column(C.byref(k), C.byref(_ps()), None, None, 0, 4, 0, FAKE, None) == -1
 
 
+def test_points_column_rejects_bad_arguments():
+    L = ldk.lib()
+    keep, a4 = _alpha(2, 2, 2, 2)
+    k = ldk._Kernel(ldk.DNET_B2, 4, a4, FAKE, 1.0)
+    ps = _ps()
+    f = L.ldk_points_column
+    assert f(None, C.byref(ps), 0, 4, FAKE, 0, FAKE, None) == -1
+    assert f(C.byref(k), None, 0, 4, FAKE, 0, FAKE, None) == -1
+    assert f(C.byref(k), C.byref(ps), 0, 4, FAKE, 9, FAKE, None) == -1      # dtype
+    assert f(C.byref(k), C.byref(ps), 5, 4, FAKE, 0, FAKE, None) == -1      # n_max < n_min
+    assert f(C.byref(k), C.byref(ps), -1, 4, FAKE, 0, FAKE, None) == -1
+    assert f(C.byref(k), C.byref(ps), 0, 2**10 + 1, FAKE, 0, FAKE, None) == -1  # beyond 2^m_max
+    assert f(C.byref(k), C.byref(ps), 0, 4, None, 0, FAKE, None) == -1      # no points buffer
+    assert f(C.byref(k), C.byref(ps), 0, 4, FAKE, 0, None, None) == -1      # no column buffer
+    kl = ldk._Kernel(ldk.LATTICE, 4, a4, FAKE, 1.0)
+    assert f(C.byref(kl), C.byref(ps), 0, 4, FAKE, 0, FAKE, None) == -1     # kind mismatch
+    # empty window: valid, nothing to do, the outputs may be NULL
+    assert f(C.byref(k), C.byref(ps), 3, 3, None, 0, None, None) == 0
+
+
 def test_algebra_rejects_bad_arguments():
     L = ldk.lib()
     assert L.ldk_transform(5, 1, 1, 4, 0, FAKE, FAKE, None, None) == -1
