@@ -89,12 +89,13 @@ __global__ __launch_bounds__(KC_THREADS) void k_kcol_lattice(KcolArgs a, int64_t
 
 // Point words and first column of a lattice in one launch.  The column
 // regenerates the points in registers and never reads the words, so the
-// two halves are independent: blocks [0, kc_blocks) are column tiles (VALU
-// bound), the rest write the point words (store bound).  The column blocks
-// come first, so they start at once and the point blocks fill the slots
-// beside them, instead of the column waiting for 256 MiB of stores (two
-// launches) or for free slots (two streams: the point launch takes every
-// slot).
+// two halves are independent: column tiles (VALU bound) and point-word
+// tiles (store bound).  The column tiles are spread evenly over the block
+// indices (one per ~8 point tiles at n = 2^20, d = 32), so every stretch of
+// the launch mixes the two and the column's arithmetic runs beside the
+// stores, instead of after 256 MiB of stores (two launches), before them
+// (column blocks first: 52 us against 48 here), or not at all beside them
+// (two streams: the point launch takes every slot).
 static_assert(GEN_THREADS == KC_THREADS, "one block shape for both halves");
 template <typename R, int ALPHA, int ORDER>
 __global__ __launch_bounds__(KC_THREADS) void k_points_kcol_lattice(KcolArgs a, int64_t tile_base,
@@ -104,11 +105,16 @@ __global__ __launch_bounds__(KC_THREADS) void k_points_kcol_lattice(KcolArgs a, 
 {
     const int64_t b = blockIdx.x;
     const int64_t kc_blocks = kc_tiles * a.ps.R;
-    if (b < kc_blocks) {
-        kcol_lattice_block<R, ALPHA, ORDER>(a, tile_base, k1, b % kc_tiles, (int)(b / kc_tiles));
+    const int64_t total = kc_blocks + g.tiles * g.chunks * g.R;
+    // column blocks spread evenly over the grid: block b is one iff the
+    // count floor((b+1) kc / total) of column blocks up to b steps at b
+    const int64_t before = b * kc_blocks / total, upto = (b + 1) * kc_blocks / total;
+    if (upto != before) {
+        kcol_lattice_block<R, ALPHA, ORDER>(a, tile_base, k1, before % kc_tiles,
+                                            (int)(before / kc_tiles));
         return;
     }
-    const int64_t q = b - kc_blocks;
+    const int64_t q = b - upto;
     gen_lattice_block(a.ps, a.n_min, a.n_max, g.P, g.pairs != 0, pts, q % g.tiles,
                       (int)((q / g.tiles) % g.chunks), (int)(q / (g.tiles * g.chunks)),
                       threadIdx.x);
