@@ -50,7 +50,7 @@ __global__ __launch_bounds__(LOGDET_THREADS) void k_logdet_partial(const double 
     const double *row = lam + (int64_t)r * n;
     const int64_t lo = (int64_t)ch * LOGDET_CHUNK;
     const int64_t hi = lo + LOGDET_CHUNK < n ? lo + LOGDET_CHUNK : n;
-    double acc = 0.0;
+    LogProd acc;
     static_assert(LOGDET_CHUNK % LOGDET_THREADS == 0, "whole items per thread");
     double lv[LOGDET_CHUNK / LOGDET_THREADS];
 #pragma unroll
@@ -61,12 +61,9 @@ __global__ __launch_bounds__(LOGDET_THREADS) void k_logdet_partial(const double 
 #pragma unroll
     for (int it = 0; it < LOGDET_CHUNK / LOGDET_THREADS; ++it) {
         const int64_t k = lo + t + (int64_t)it * LOGDET_THREADS;
-        if (k < hi) {
-            const double s = lv[it] + sigma2;
-            acc += s > 0.0 ? log(s) : __builtin_nan("");
-        }
+        if (k < hi) acc.add(lv[it] + sigma2);
     }
-    red[t] = acc;
+    red[t] = acc.value();
     __syncthreads();
     for (int w = LOGDET_THREADS / 2; w > 0; w >>= 1) {
         if (t < w) red[t] += red[t + w];

@@ -57,6 +57,7 @@ __global__ __launch_bounds__(MLL_THREADS) void k_mll_terms(const double *__restr
     const double *lr = lam + (size_t)r * n;
     double *gr = g + (size_t)r * n;
     double acc[3] = {0.0, 0.0, 0.0};
+    LogProd lsum;  // sum of log(lambda + s2)
     const int64_t lo = (int64_t)ch * MLL_CHUNK;
 #pragma unroll
     for (int it = 0; it < MLL_ITEMS; ++it) {
@@ -67,12 +68,13 @@ __global__ __launch_bounds__(MLL_THREADS) void k_mll_terms(const double *__restr
             const double is = 1.0 / s;
             const double q = p * is;
             acc[0] += q;
-            acc[1] += s > 0.0 ? log(s) : __builtin_nan("");
+            lsum.add(s);
             const double gk = 0.5 * (q - 1.0) * is;  // 1/2 p/s^2 - 1/2 /s
             acc[2] += gk;
             gr[k] = gk;
         }
     }
+    acc[1] = lsum.value();
     block_sum3(acc, red);
     if (threadIdx.x == 0)
         for (int c = 0; c < 3; ++c) part[((size_t)r * chunks + ch) * 3 + c] = acc[c];

@@ -146,7 +146,7 @@ __device__ __forceinline__ void real_top_body(const PassArgs &a, double *lam_out
         lds_write(v, lds, t, LOGE, logW + top_s, Tn);
         __syncthreads();
     }
-    double lsum = 0.0;  // PM_FWD with ld_part: sum of log(lambda + s2)
+    LogProd lsum;  // PM_FWD with ld_part: sum of log(lambda + s2)
 #pragma unroll
     for (int i = 0; i < E; ++i) {
         const int q = t + Tn * i;
@@ -194,9 +194,8 @@ __device__ __forceinline__ void real_top_body(const PassArgs &a, double *lam_out
             lam_out[row * n + k] = (double)yk.re;
             lam_out[row * n + k + N] = (double)ykn.re;
             if (ld_part) {
-                const double sa = (double)yk.re + a.sigma2, sb = (double)ykn.re + a.sigma2;
-                lsum += (sa > 0.0 ? log(sa) : __builtin_nan("")) +
-                        (sb > 0.0 ? log(sb) : __builtin_nan(""));
+                lsum.add((double)yk.re + a.sigma2);
+                lsum.add((double)ykn.re + a.sigma2);
             }
         } else if constexpr (MODE == PM_POWER) {
             lam_out[row * n + k] = (double)yk.re * (double)yk.re + (double)yk.im * (double)yk.im;
@@ -208,9 +207,10 @@ __device__ __forceinline__ void real_top_body(const PassArgs &a, double *lam_out
         if (ld_part) {
             // block sum in a fixed order: lanes, then waves
             __shared__ double red[8];
+            double ls = lsum.value();
 #pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
-            if ((t & 63) == 0) red[t >> 6] = lsum;
+            for (int o = 32; o >= 1; o >>= 1) ls += __shfl_xor(ls, o, 64);
+            if ((t & 63) == 0) red[t >> 6] = ls;
             __syncthreads();
             if (t == 0) {
                 double s = 0.0;
@@ -360,7 +360,7 @@ __global__ __launch_bounds__(512) void k_fit_top(PassArgs aK, PassArgs aY, doubl
 
     // ---- column half: eigenvalues (global and LDS) and the log-det partial
     double la[E], lc[E];
-    double lsum = 0.0;
+    LogProd lsum;
     if (!rhs) {
 #pragma unroll
         for (int i = 0; i < E; ++i) {
@@ -373,9 +373,8 @@ __global__ __launch_bounds__(512) void k_fit_top(PassArgs aK, PassArgs aY, doubl
             lam_out[row * n + k] = la[i];
             lam_out[row * n + k + N] = lc[i];
             if (ld_part) {
-                const double sa = la[i] + aK.sigma2, sb = lc[i] + aK.sigma2;
-                lsum += (sa > 0.0 ? log(sa) : __builtin_nan("")) +
-                        (sb > 0.0 ? log(sb) : __builtin_nan(""));
+                lsum.add(la[i] + aK.sigma2);
+                lsum.add(lc[i] + aK.sigma2);
             }
         }
     }
@@ -388,9 +387,10 @@ __global__ __launch_bounds__(512) void k_fit_top(PassArgs aK, PassArgs aY, doubl
             lam_lds[S + q] = lc[i];
         }
         if (ld_part) {
+            double ls = lsum.value();
 #pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
-            if ((t & 63) == 0) red[t >> 6] = lsum;
+            for (int o = 32; o >= 1; o >>= 1) ls += __shfl_xor(ls, o, 64);
+            if ((t & 63) == 0) red[t >> 6] = ls;
         }
     }
     __syncthreads();

@@ -108,6 +108,29 @@ bool fit_top_supported(const PassGeom &g);
 int launch_pass2(int kind, int dtype, int mode, int ld, int st, const PassArgs &a0,
                  const PassArgs &a1, hipStream_t s);
 
+// Sum of log(s) over a thread's values in product form: s = m 2^e with m in
+// [1/2, 1); the mantissas multiply and the exponents add, with one log at
+// the end (k mantissas keep the product above 2^-k, so no underflow for the
+// few dozen values a thread takes).  NaN when some s <= 0 or is NaN.  About
+// three instructions per value instead of a logarithm each.
+struct LogProd {
+    double mant = 1.0;
+    int exp = 0;
+    bool bad = false;
+    __device__ __forceinline__ void add(double s)
+    {
+        int e;
+        const double m = frexp(s, &e);
+        mant *= m;
+        exp += e;
+        bad |= !(s > 0.0);
+    }
+    __device__ __forceinline__ double value() const
+    {
+        return bad ? __builtin_nan("") : log(mant) + (double)exp * 0.69314718055994530942;
+    }
+};
+
 // Workspace bytes of LDK_OP_MLL / LDK_OP_MLL_ADJOINT (mll.hip).
 size_t mll_ws_bytes(int op, int kind, int64_t R, int m, int dtype);
 
