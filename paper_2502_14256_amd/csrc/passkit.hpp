@@ -167,44 +167,14 @@ __device__ __forceinline__ void powers(cplx<R> w, cplx<R> (&p)[E])
     }
 }
 
-// Group twiddle of the FFT schedule: element with tile index q, axis index
-// r = q >> logW, group digit c at axis bit s: W_{2^{s+gs}}^{(r mod 2^s) R_gs(c)}.
-// For a full group every register of a thread shares r mod 2^s, so one table
-// read gives w = W^{r mod 2^s} and the twiddles are its powers.
-template <typename T, int E, int LOGE, bool CONJ>
-__device__ __forceinline__ void group_twiddle(T (&v)[E], int t, int gs, int s, int logW, int T_)
-{
-    if constexpr (!std::is_floating_point<T>::value) {
-        using R = typename real_of<T>::type;
-        if (s == 0) return;
-        if (gs == LOGE) {
-            const int q0 = group_q(t, 0, gs, logW + s, T_);
-            const uint32_t rlow = (uint32_t)(q0 >> logW) & ((1u << s) - 1);
-            cplx<R> pw[E];
-            powers<R, E>(tw_small<R>(rlow, s + gs), pw);
-#pragma unroll
-            for (int i = 0; i < E; ++i) {
-                const cplx<R> w = pw[brev_bits((uint32_t)i, LOGE)];
-                v[i] = CONJ ? cmulc(v[i], w) : cmul(v[i], w);
-            }
-            return;
-        }
-#pragma unroll
-        for (int i = 0; i < E; ++i) {
-            const int q = group_q(t, i, gs, logW + s, T_);
-            const uint32_t rlow = (uint32_t)(q >> logW) & ((1u << s) - 1);
-            const uint32_t c = (uint32_t)i & ((1u << gs) - 1);
-            const cplx<R> w = tw_small<R>(rlow * brev_bits(c, gs), s + gs);
-            v[i] = CONJ ? cmulc(v[i], w) : cmul(v[i], w);
-        }
-    }
-}
-
-// The same group twiddles with the table reads hoisted: bases[g] =
-// W_{2^{s_g+LOGE}}^{r mod 2^{s_g}} for every full group g >= 1 of an A-bit
-// axis (group 0 sits at s = 0 and needs none), read once at kernel start so
-// that the table latency overlaps the data loads instead of stalling each
-// group.  apply_group_twiddle multiplies by the powers of one base.
+// Group twiddle of the FFT schedule: the element with tile index q, axis
+// index r = q >> logW and group digit c at axis bit s is multiplied by
+// W_{2^{s+g}}^{(r mod 2^s) R_g(c)}.  For a full group every register of a
+// thread shares r mod 2^s, so the twiddles are the powers of one base
+// W_{2^{s+g}}^{r mod 2^s}.  bases[g] holds that base for every full group
+// g >= 1 of an A-bit axis (group 0 sits at s = 0 and needs none), read once
+// at kernel start so that the table latency overlaps the data loads instead
+// of stalling each group; apply_group_twiddle multiplies by its powers.
 constexpr int MAX_GROUPS = 4;
 template <typename R, int LOGE>
 __device__ __forceinline__ void group_bases(cplx<R> (&bases)[MAX_GROUPS], int t, int A, int logW,
@@ -237,7 +207,12 @@ __device__ __forceinline__ void apply_group_twiddle(T (&v)[E], const T &base)
     }
 }
 
-// Inter-pass twiddle with its table reads hoisted (see pass_twiddle_k1).
+// Inter-pass twiddle W_{2^{b0+A}}^{k1 R_A(r)} for the coalesced pattern
+// q = t + Tn i: the column k1 is fixed per thread and
+// R_A(r) = R_{A-LOGE}(r0) 2^LOGE + R_LOGE(i), r0 = t >> logW, so the twiddles
+// are base = W^{k1 R_{A-LOGE}(r0) 2^LOGE} times the powers of step = W^{k1}.
+// pass_tw_fetch reads the two table products right behind the data loads,
+// pass_tw_apply multiplies.
 template <typename R>
 struct PassTw {
     cplx<R> base, step;
@@ -262,33 +237,6 @@ __device__ __forceinline__ void pass_tw_apply(T (&v)[E], const PassTw<typename r
             v[i] = CONJ ? cmulc(v[i], w) : cmul(v[i], w);
         }
     }
-}
-
-// Inter-pass twiddle W_{2^{b0+A}}^{k1 R_A(r)} for the coalesced pattern
-// q = t + Tn i: the column k1 is fixed per thread and
-// R_A(r) = R_{A-LOGE}(r0) 2^LOGE + R_LOGE(i), r0 = t >> logW, so the twiddles
-// are W^{k1 R_{A-LOGE}(r0) 2^LOGE} times the powers of W^{k1}.
-template <typename T, int E, int LOGE, bool CONJ>
-__device__ __forceinline__ void pass_twiddle_k1(T (&v)[E], int t, uint64_t k1, int logW, int A, int b0)
-{
-    if constexpr (!std::is_floating_point<T>::value) {
-        using R = typename real_of<T>::type;
-        const uint64_t r0 = (uint64_t)(t >> logW);
-        const cplx<R> base = tw_any<R>((k1 * brev_bits((uint32_t)r0, A - LOGE)) << LOGE, b0 + A);
-        cplx<R> pw[E];
-        powers<R, E>(tw_any<R>(k1, b0 + A), pw);
-#pragma unroll
-        for (int i = 0; i < E; ++i) {
-            const cplx<R> w = cmul(base, pw[brev_bits((uint32_t)i, LOGE)]);
-            v[i] = CONJ ? cmulc(v[i], w) : cmul(v[i], w);
-        }
-    }
-}
-template <typename T, int E, int LOGE, bool CONJ>
-__device__ __forceinline__ void pass_twiddle(T (&v)[E], int t, int64_t cb, int logW, int A, int b0)
-{
-    const uint64_t k1 = (uint64_t)((cb << logW) + (t & ((1 << logW) - 1)));
-    pass_twiddle_k1<T, E, LOGE, CONJ>(v, t, k1, logW, A, b0);
 }
 
 template <typename T, int E>
