@@ -38,7 +38,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # reported as null once they change.
 STEP_TRAFFIC = {"read_MiB": 0.15, "write_MiB": 264.00,
                 "sources": ("kcol.hip", "kfactor.hpp", "pointset.hpp", "common.hpp"),
-                "sha1": "290e3ba2262c17029ae0c307cfb1a41526190699"}
+                "sha1": "d2ca29a87fe187a7d453c510e9e15b0f5a5a5937"}
 
 
 def step_traffic_bytes():
@@ -281,6 +281,7 @@ def main():
         out["batched"] = batch_bench(args.batch_steps, args.warmup)
 
     out["fwht_split16"] = fwht_bench(K)
+    out["higher_order_net"] = higher_order_bench(K)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
@@ -407,6 +408,45 @@ def grad_bench(K, warmup):
         "f32_grad_rel_err_vs_f64": err,
         "dtype": "f32 kernel factors and transform of y; f64 eigenvalues, g, adjoint, sums",
     }
+
+
+def higher_order_bench(K):
+    """Order-2 higher-order LMS + digitally shifted net (Sec. 4.3, digital
+    interlacing): 64 source dimensions interlaced pairwise into d = 32,
+    n = 2^20, one replication.  Times the interlacing of the scrambled
+    columns, the point words (HBM roofline) and the order-2 DSI first column
+    on the interlaced net (points regenerated)."""
+    import numpy as np
+    import torch
+
+    import paper_2502_14256_amd as ldk
+    import workloads as W
+
+    alpha, d, m = 2, 32, 20
+    n = 2**m
+    src = W.small_net(2502, m=m, d=alpha * d, R=1)
+
+    def dev_u64(a):
+        return torch.from_numpy(np.ascontiguousarray(a, np.uint64).view(np.int64).copy()).cuda()
+
+    ps = ldk.PointSet("dnet", 1, alpha * d, m, dev_u64(src["gen"]), dev_u64(src["lms"]), None)
+    shift = dev_u64(np.random.default_rng(2503).integers(0, 2**62, size=(1, d), dtype=np.uint64))
+    cols = torch.empty((1, d, m), dtype=torch.int64, device="cuda")
+    hp = ldk.interlace(ps, alpha, shift=shift, out=cols)
+    kern = ldk.Kernel("dnet", np.full(d, alpha, np.int32),
+                      torch.from_numpy(1.0 / np.arange(1, d + 1, dtype=np.float64) ** 2).cuda(), 1.0)
+    pts = torch.empty((1, n, d), dtype=torch.int64, device="cuda")
+    k1 = torch.empty((1, n), dtype=torch.float64, device="cuda")
+    ms_il = time_graph(lambda: ldk.interlace(ps, alpha, shift=shift, out=cols), K)
+    ms_gen = time_graph(lambda: ldk.gen_points(hp, 0, n, out=pts), K)
+    ms_kc = time_graph(lambda: ldk.kernel_column(kern, hp, 0, n, out=k1), K)
+    gb = 8 * n * d / (ms_gen * 1e-3) / 1e9
+    return {"workload": "net_m20_d32_order2_interlaced (LMS on 64 source dimensions, interlaced "
+                        "pairwise into d=32, digital shift, n=2^20, order-2 DSI kernel)",
+            "interlace_ms": round(ms_il, 5), "gen_points_ms": round(ms_gen, 5),
+            "gen_points_GB_s": round(gb, 1), "gen_points_hbm_frac": round(gb / HBM_PEAK_GBS, 4),
+            "kernel_column_ms": round(ms_kc, 5),
+            "kernel_column_factor_evals_per_s": round(n * d / (ms_kc * 1e-3), 1)}
 
 
 def fwht_bench(K):

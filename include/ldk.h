@@ -85,14 +85,19 @@ typedef enum { LDK_F64 = 0, LDK_F32 = 1 } ldk_dtype;
  *        lattice shift), or NULL for none.
  *  R     number of independent randomizations (replications), >= 1.
  *  m_max points exist for indices 0 <= i < 2^m_max (nets, linear lattices);
- *        natural-order lattices accept any i < 2^62. */
+ *        natural-order lattices accept any i < 2^62.
+ *  flags 0, or LDK_GEN_PER_REPLICATION (nets only): gen holds the columns of
+ *        every replication, C[R][d][m_max] (for instance the interlaced,
+ *        scrambled columns of a higher-order net from ldk_interlace, with
+ *        lms = NULL). */
+#define LDK_GEN_PER_REPLICATION 1
 typedef struct {
     int32_t kind;
     int32_t order;
     int32_t R;
     int32_t d;
     int32_t m_max;
-    int32_t reserved;
+    int32_t flags;
     const uint64_t *gen;
     const uint64_t *lms;
     const uint64_t *shift;
@@ -126,6 +131,22 @@ int ldk_init(void);
  * nets and linear lattices, n_max <= 2^m_max. */
 int ldk_gen_points(const ldk_pointset *ps, int64_t n_min, int64_t n_max, uint64_t *out,
                    ldk_stream stream);
+
+/* Generating columns of a higher-order base-2 digital net by digital
+ * interlacing (Sec. 4.3, digital interlacing for higher-order nets, and
+ * higher-order LMS: scramble the alpha d source matrices, then interlace).
+ * src: a base-2 net of alpha d dimensions, gen = C[alpha d][m_max] (shared,
+ * flags = 0), lms = S[R][alpha d][64] or NULL; its shift and order are not
+ * used.  Output, for replication r, dimension j < d, column k < m_max:
+ *   digit t of cols[r][j][k] (bit 63 - t, t < 64) =
+ *   digit floor(t / alpha) of column k of S_s C_s, s = alpha j + (t mod alpha)
+ * (0-based j and s: row t of the interlaced matrix is row floor(t / alpha) of
+ * source matrix alpha j + (t mod alpha); 64 digits are kept, so the top
+ * 64 / alpha digits of each source column enter).  cols = uint64[R][d][m_max]
+ * device, for a net with flags = LDK_GEN_PER_REPLICATION, lms = NULL and a
+ * d-dimensional shift of its own.  alpha in 1..4; src->d must be a multiple
+ * of alpha. */
+int ldk_interlace(const ldk_pointset *src, int alpha, uint64_t *cols, ldk_stream stream);
 
 /* First Gram column k1_i = K(x_i, x_0) for i = n_min .. n_max-1 (Sec. 5.4:
  * only the first column is stored).  Points come from `pts` =

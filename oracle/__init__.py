@@ -14,6 +14,10 @@ lattice points         Sec. 4.2; natural == linear order element-wise via
 net points             Sec. 4.3; GF(2) brute force on unpacked digits;
                        stratification of the leading m digits; identity C
                        gives van der Corput; Gray order vs Table 1
+interlacing            Sec. 4.3; the printed interlacing example (every
+                       position's source entry); alpha = 1 is the identity;
+                       the interlaced net's points are the digit-interlaced
+                       points of the alpha d-dimensional net
 SI factor              Sec. 5.2; truncated Fourier series with a tail bound;
                        special values pi^2/3, -pi^2/6, pi^4/45, ...
 DSI factors a=2,3,4    Theorem 1; exact-rational Walsh series (eq. DSI_kernel)
@@ -167,6 +171,49 @@ def lms(C_, S1) -> np.ndarray:
     out = np.empty_like(C_)
     _check(lib().orc_lms(C_.shape[0], C_.shape[1], _p(C_), _p(S1), _p(out)), "lms")
     return out
+
+
+def interlace(cols, alpha: int) -> np.ndarray:
+    """Digital interlacing (Sec. 4.3, higher-order nets).  cols =
+    uint64[alpha d][m]: the columns of alpha d generating matrices (row t of
+    column k at bit 63 - t).  Returns uint64[d][m]: row t of interlaced
+    matrix j is row floor(t / alpha) of matrix alpha j + (t mod alpha)
+    (0-based j), for the 64 rows a coordinate word holds.  Written on the
+    unpacked digit matrices, entry by entry as the definition reads."""
+    cols = np.ascontiguousarray(cols, dtype=np.uint64)
+    ad, m = cols.shape
+    if ad % alpha:
+        raise ValueError("the number of matrices must be a multiple of alpha")
+    d = ad // alpha
+    shifts = (63 - np.arange(64)).astype(np.uint64)
+    A = (cols[:, None, :] >> shifts[None, :, None]) & np.uint64(1)  # A[s][t][k]
+    out = np.zeros((d, m), dtype=np.uint64)
+    for j in range(d):
+        for t in range(64):
+            row = A[alpha * j + t % alpha, t // alpha, :]
+            out[j] |= row << np.uint64(63 - t)
+    return out
+
+
+def interlace_columns(C_, S, alpha: int, R: int | None = None) -> np.ndarray:
+    """Higher-order LMS (Sec. 4.3): scramble the alpha d source matrices of
+    each replication (S[r], or none), then interlace: uint64[R][d][m]."""
+    C_ = np.ascontiguousarray(C_, dtype=np.uint64)
+    if R is None:
+        R = 1 if S is None else S.shape[0]
+    return np.stack([interlace(lms(C_, S[r]) if S is not None else C_, alpha)
+                     for r in range(R)])
+
+
+def higher_order_dnet_points(C_, S, shift, alpha: int, m_max: int, n_min: int, n_max: int,
+                             order="natural") -> np.ndarray:
+    """Points of a higher-order LMS + digitally shifted net: the d-dimensional
+    net of every replication's interlaced scrambled matrices, shifted by its
+    own shift[r] (d digits)."""
+    R = S.shape[0] if S is not None else (shift.shape[0] if shift is not None else 1)
+    cols = interlace_columns(C_, S, alpha, R)
+    return np.stack([dnet_points(cols[r], None, None if shift is None else shift[r:r + 1],
+                                 m_max, n_min, n_max, order, R=1)[0] for r in range(R)])
 
 
 def gray(i: int) -> int:

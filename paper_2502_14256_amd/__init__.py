@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libldk.so")
 LATTICE, DNET_B2 = 0, 1
 NATURAL, LINEAR, GRAY = 0, 1, 2
 F64, F32 = 0, 1
+GEN_PER_REPLICATION = 1
 (OP_TRANSFORM, OP_EIG, OP_SOLVE, OP_MATVEC, OP_LOGDET, OP_UPDATE_DOUBLE, OP_EIG_UPDATE_DOUBLE,
  OP_MLL, OP_MLL_ADJOINT, OP_FIT) = range(10)
 
@@ -31,7 +32,7 @@ EXPORTS = [
     "ldk_matvec", "ldk_logdet", "ldk_update_double", "ldk_eig_update_double",
     "ldk_workspace_bytes", "ldk_strerror", "ldk_last_hip_error", "ldk_version",
     "ldk_mll", "ldk_mll_adjoint", "ldk_kernel_grad", "ldk_kernel_grad_workspace_bytes",
-    "ldk_fwht_split16", "ldk_fit", "ldk_points_column",
+    "ldk_fwht_split16", "ldk_fit", "ldk_points_column", "ldk_interlace",
 ]
 
 
@@ -41,7 +42,7 @@ class LdkError(RuntimeError):
 
 class _Pointset(C.Structure):
     _fields_ = [("kind", C.c_int32), ("order", C.c_int32), ("R", C.c_int32), ("d", C.c_int32),
-                ("m_max", C.c_int32), ("reserved", C.c_int32), ("gen", C.c_void_p),
+                ("m_max", C.c_int32), ("flags", C.c_int32), ("gen", C.c_void_p),
                 ("lms", C.c_void_p), ("shift", C.c_void_p)]
 
 
@@ -66,6 +67,7 @@ def lib():
             "ldk_gen_points": ([P, i64, i64, P, P], i32),
             "ldk_kernel_column": ([P, P, P, P, i64, i64, i32, P, P], i32),
             "ldk_points_column": ([P, P, i64, i64, P, i32, P, P], i32),
+            "ldk_interlace": ([P, i32, P, P], i32),
             "ldk_transform": ([i32, i32, i32, i32, i32, P, P, P, P], i32),
             "ldk_eig": ([i32, i32, i32, i32, P, P, P, P], i32),
             "ldk_solve": ([i32, i32, i32, i32, i32, P, f64, P, P, P, P], i32),
@@ -149,7 +151,8 @@ def init():
 class PointSet:
     """A randomized point set (Sec. 4.2 lattice / Sec. 4.3 base-2 net).
 
-    gen: int64 device tensor, lattice g[d] or net columns C[d][m_max];
+    gen: int64 device tensor, lattice g[d] or net columns C[d][m_max]
+    (C[R][d][m_max] with per_replication, e.g. from ``interlace``);
     lms: net scrambles S[R][d][64] or None; shift: [R][d] or None."""
 
     kind: str
@@ -160,13 +163,15 @@ class PointSet:
     lms: torch.Tensor | None = None
     shift: torch.Tensor | None = None
     order: str = "natural"
+    per_replication: bool = False
 
     def _c(self) -> _Pointset:
         for name in ("gen", "lms", "shift"):
             t = getattr(self, name)
             if t is not None:
                 _need(t, name)
-        return _Pointset(_kind(self.kind), _order(self.order), self.R, self.d, self.m_max, 0,
+        return _Pointset(_kind(self.kind), _order(self.order), self.R, self.d, self.m_max,
+                         GEN_PER_REPLICATION if self.per_replication else 0,
                          _ptr(self.gen), _ptr(self.lms), _ptr(self.shift))
 
 
@@ -216,6 +221,23 @@ def kernel_column(k: Kernel, ps: PointSet, n_min: int, n_max: int, pts=None, x0=
     _check(lib().ldk_kernel_column(C.byref(k._c()), C.byref(ps._c()), _ptr(pts), _ptr(x0), n_min,
                                    n_max, dt, _ptr(out), _stream()), "ldk_kernel_column")
     return out
+
+
+def interlace(src: PointSet, alpha: int, shift: torch.Tensor | None = None, order=None,
+              out: torch.Tensor | None = None) -> PointSet:
+    """Higher-order net by digital interlacing (higher-order LMS when src has
+    scrambles): src is a net of alpha d dimensions; returns the
+    d-dimensional net whose per-replication generating columns are the
+    interlaced scrambled ones (written to ``out``, int64 [R][d][m_max]),
+    digitally shifted by ``shift`` ([R][d]) in ``order`` (src's by default)."""
+    if src.d % alpha:
+        raise LdkError("src.d must be a multiple of alpha")
+    d = src.d // alpha
+    if out is None:
+        out = torch.empty((src.R, d, src.m_max), dtype=torch.int64, device=src.gen.device)
+    _check(lib().ldk_interlace(C.byref(src._c()), alpha, _ptr(out), _stream()), "ldk_interlace")
+    return PointSet("dnet", src.R, d, src.m_max, out, None, shift, order or src.order,
+                    per_replication=True)
 
 
 def points_column(k: Kernel, ps: PointSet, n_min: int, n_max: int, dtype=torch.float64,

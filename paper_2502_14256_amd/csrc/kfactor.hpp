@@ -281,7 +281,7 @@ __device__ __forceinline__ void build_net_chunk(const KcolArgs &a, NetLds &L, in
         const int jj = w >> 6, k = w & 63;
         uint64_t v = 0;  // columns k >= m are zero
         if (k < m) {
-            const uint64_t col = a.ps.gen[(size_t)(jc + jj) * m + k];
+            const uint64_t col = net_gen_column(a.ps, r, jc + jj, k);
             v = a.ps.lms ? lms_column(L.srow[jj], col) : col;
         }
         L.ct[jj][k] = v;

@@ -10,6 +10,8 @@ int validate_pointset(const ldk_pointset *ps, PointsetArgs *out)
     if (!ps || !out) return LDK_EINVAL;
     if (ps->R < 1 || ps->R > 65535 || ps->d < 1 || ps->d > LDK_MAX_D) return LDK_EINVAL;
     if (ps->m_max < 0 || ps->m_max > 62) return LDK_EINVAL;
+    if (ps->flags != 0 && ps->flags != LDK_GEN_PER_REPLICATION) return LDK_EINVAL;
+    if (ps->flags == LDK_GEN_PER_REPLICATION && ps->kind != LDK_DNET_B2) return LDK_EINVAL;
     // a net with m_max = 0 has no generating-matrix columns
     if (!ps->gen && !(ps->kind == LDK_DNET_B2 && ps->m_max == 0)) return LDK_EINVAL;
     if (ps->kind == LDK_LATTICE) {
@@ -20,7 +22,10 @@ int validate_pointset(const ldk_pointset *ps, PointsetArgs *out)
     } else {
         return LDK_EINVAL;
     }
-    *out = PointsetArgs{ps->kind, ps->order, ps->R, ps->d, ps->m_max, ps->gen, ps->lms, ps->shift};
+    const int64_t rstride =
+        ps->flags == LDK_GEN_PER_REPLICATION ? (int64_t)ps->d * ps->m_max : 0;
+    *out = PointsetArgs{ps->kind, ps->order, ps->R, ps->d,     ps->m_max,
+                        ps->gen,  ps->lms,   ps->shift, rstride};
     return LDK_OK;
 }
 
@@ -50,7 +55,7 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_net(PointsetArgs a, int64_t
     }
     for (int w = t; w < DB * m; w += GEN_THREADS) {
         const int jj = w / m, k = w % m;
-        const uint64_t col = a.gen[(size_t)(j0 + jj) * m + k];
+        const uint64_t col = net_gen_column(a, r, j0 + jj, k);
         ct[jj][k] = a.lms ? lms_column(u.srow[jj], col) : col;
     }
     __syncthreads();  // srow is dead from here on; step reuses its storage
@@ -99,9 +104,64 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_lattice(PointsetArgs a, int
                       threadIdx.x);
 }
 
+// Interlaced, scrambled generating columns of a higher-order net (see
+// ldk_interlace): one thread per output column (r, j, k); the ALPHA source
+// columns are scrambled (64 parities each) and their digits interleaved.
+template <int ALPHA>
+__global__ __launch_bounds__(256) void k_interlace(PointsetArgs a, int d_out,
+                                                  uint64_t *__restrict__ cols)
+{
+    const int m = a.m_max;
+    const int64_t total = (int64_t)a.R * d_out * m;
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total) return;
+    const int k = (int)(idx % m);
+    const int j = (int)((idx / m) % d_out);
+    const int r = (int)(idx / ((int64_t)m * d_out));
+    uint64_t src[ALPHA];
+#pragma unroll
+    for (int q = 0; q < ALPHA; ++q) {
+        const int sd = ALPHA * j + q;
+        const uint64_t col = net_gen_column(a, r, sd, k);
+        src[q] = a.lms ? lms_column(a.lms + ((size_t)r * a.d + sd) * 64, col) : col;
+    }
+    // digit t of the output is digit t / ALPHA of source t mod ALPHA
+    uint64_t out = 0;
+#pragma unroll
+    for (int t = 0; t < 64; ++t) {
+        const uint64_t bit = (src[t % ALPHA] >> (63 - t / ALPHA)) & 1u;
+        out |= bit << (63 - t);
+    }
+    cols[idx] = out;
+}
+
 }  // namespace ldk
 
 using namespace ldk;
+
+extern "C" int ldk_interlace(const ldk_pointset *src, int alpha, uint64_t *cols, ldk_stream stream)
+{
+    PointsetArgs a;
+    const int st = validate_pointset(src, &a);
+    if (st) return st;
+    if (a.kind != LDK_DNET_B2 || src->flags != 0) return LDK_EINVAL;
+    if (alpha < 1 || alpha > 4 || a.d % alpha != 0) return LDK_EINVAL;
+    const int d_out = a.d / alpha;
+    const int64_t total = (int64_t)a.R * d_out * a.m_max;
+    if (total == 0) return LDK_OK;  // m_max = 0: a net without columns
+    if (!cols) return LDK_EINVAL;
+    const int64_t blocks = (total + 255) / 256;
+    if (blocks > 0x7fffffff) return LDK_ENOTSUP;
+    const hipStream_t s = as_stream(stream);
+    switch (alpha) {
+    case 1: hipLaunchKernelGGL(k_interlace<1>, dim3((unsigned)blocks), dim3(256), 0, s, a, d_out, cols); break;
+    case 2: hipLaunchKernelGGL(k_interlace<2>, dim3((unsigned)blocks), dim3(256), 0, s, a, d_out, cols); break;
+    case 3: hipLaunchKernelGGL(k_interlace<3>, dim3((unsigned)blocks), dim3(256), 0, s, a, d_out, cols); break;
+    default: hipLaunchKernelGGL(k_interlace<4>, dim3((unsigned)blocks), dim3(256), 0, s, a, d_out, cols); break;
+    }
+    LDK_LAUNCH_CHECK();
+    return LDK_OK;
+}
 
 extern "C" int ldk_gen_points(const ldk_pointset *ps, int64_t n_min, int64_t n_max,
                               uint64_t *out, ldk_stream stream)

@@ -9,10 +9,17 @@ namespace ldk {
 // Host-validated, device-ready description of a point set.
 struct PointsetArgs {
     int kind, order, R, d, m_max;
-    const uint64_t *gen;    // lattice g[d] | net C[d][m_max]
+    const uint64_t *gen;    // lattice g[d] | net C[d][m_max] (or C[R][d][m_max])
     const uint64_t *lms;    // S[R][d][64] or nullptr
     const uint64_t *shift;  // [R][d] or nullptr
+    int64_t gen_rstride;    // net columns: words between replications (0: shared)
 };
+
+// Column k of net dimension j in replication r (before scrambling).
+__device__ __forceinline__ uint64_t net_gen_column(const PointsetArgs &a, int r, int j, int k)
+{
+    return a.gen[(size_t)r * a.gen_rstride + (size_t)j * a.m_max + k];
+}
 
 int validate_pointset(const ldk_pointset *ps, PointsetArgs *out);
 

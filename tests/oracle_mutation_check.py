@@ -33,6 +33,8 @@ muts = [
  ("oracle/orc_mll.c", "gr[j] += ai * zeta * t[j] * pre[j] * suf;", "gr[j] += ai * zeta * t[j] * suf;"),
  ("oracle/orc_mll.c", "gr[d] += ai * zeta * p;", "gr[d] += ai * p;"),
  ("oracle/orc_mll.c", "t[j] = gamma[j] * K;", "t[j] = K;"),
+ ("oracle/__init__.py", "row = A[alpha * j + t % alpha, t // alpha, :]", "row = A[alpha * j + (t // alpha) % alpha, t % alpha, :]"),
+ ("oracle/__init__.py", "row = A[alpha * j + t % alpha, t // alpha, :]", "row = A[j + t % alpha, t // alpha, :]"),
 ]
 res = []
 for f, a, b in muts:

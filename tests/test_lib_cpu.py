@@ -39,7 +39,7 @@ FAKE = C.c_void_p(0x1000)  # never dereferenced: every call below fails validati
 
 
 def _ps(**kw):
-    base = dict(kind=ldk.DNET_B2, order=ldk.NATURAL, R=1, d=4, m_max=10, reserved=0,
+    base = dict(kind=ldk.DNET_B2, order=ldk.NATURAL, R=1, d=4, m_max=10, flags=0,
                 gen=FAKE, lms=None, shift=None)
     base.update(kw)
     return ldk._Pointset(**base)
@@ -112,6 +112,23 @@ def test_points_column_rejects_bad_arguments():
     assert f(C.byref(kl), C.byref(ps), 0, 4, FAKE, 0, FAKE, None) == -1     # kind mismatch
     # empty window: valid, nothing to do, the outputs may be NULL
     assert f(C.byref(k), C.byref(ps), 3, 3, None, 0, None, None) == 0
+
+
+def test_interlace_and_flags_reject_bad_arguments():
+    L = ldk.lib()
+    # flags: only LDK_GEN_PER_REPLICATION, and only for nets
+    assert L.ldk_gen_points(C.byref(_ps(flags=2)), 0, 4, FAKE, None) == -1
+    assert L.ldk_gen_points(C.byref(_ps(kind=ldk.LATTICE, flags=1)), 0, 4, FAKE, None) == -1
+    f = L.ldk_interlace
+    assert f(C.byref(_ps(d=4)), 0, FAKE, None) == -1        # alpha < 1
+    assert f(C.byref(_ps(d=4)), 5, FAKE, None) == -1        # alpha > 4
+    assert f(C.byref(_ps(d=6)), 4, FAKE, None) == -1        # d not a multiple of alpha
+    assert f(C.byref(_ps(kind=ldk.LATTICE)), 2, FAKE, None) == -1
+    assert f(C.byref(_ps(flags=1)), 2, FAKE, None) == -1    # source columns must be shared
+    assert f(C.byref(_ps(d=4)), 2, None, None) == -1        # no output
+    assert f(None, 2, FAKE, None) == -1
+    # a net without columns (m_max = 0): nothing to write
+    assert f(C.byref(_ps(d=4, m_max=0, gen=None)), 2, None, None) == 0
 
 
 def test_algebra_rejects_bad_arguments():
