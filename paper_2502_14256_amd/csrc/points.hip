@@ -33,7 +33,8 @@ int validate_pointset(const ldk_pointset *ps, PointsetArgs *out)
 // [n_min + blockIdx.x * P * GEN_ITERS, ...).  Thread (p, jj) walks the points
 // i = tile + p + P * k, k < GEN_ITERS.
 __global__ __launch_bounds__(GEN_THREADS) void k_gen_net(PointsetArgs a, int64_t n_min,
-                                                         int64_t n_max, int P, int logP,
+                                                         int64_t n_max, int64_t tile_base, int P,
+                                                         int logP, int pairs,
                                                          uint64_t *__restrict__ out)
 {
     __shared__ uint64_t ct[GEN_DIM_CHUNK][64];
@@ -74,25 +75,59 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_net(PointsetArgs a, int64_t
     }
     __syncthreads();
 
+    const int64_t cnt = n_max - n_min;
+    if (pairs) {
+        // two dimensions per thread, one 16-byte store per point (even d,
+        // aligned destination): half the store instructions
+        const int DB2 = DB >> 1;
+        const int p = t / DB2, jj = 2 * (t % DB2);
+        if (p >= P) return;
+        const int j = j0 + jj;
+        const int64_t first = tile_base + (int64_t)blockIdx.x * P * GEN_ITERS_NET + p;
+        if (first >= n_max) return;
+        const uint64_t blk = ((uint64_t)tile_base >> s) + (uint64_t)blockIdx.x * GEN_ITERS_NET;
+        const uint64_t d0 = a.shift ? a.shift[(size_t)r * a.d + j] : 0;
+        const uint64_t d1 = a.shift ? a.shift[(size_t)r * a.d + j + 1] : 0;
+        const uint64_t code0 = a.order == LDK_GRAY ? gray_code((uint64_t)first) : (uint64_t)first;
+        uint64_t z0 = net_point(ct[jj], m, code0), z1 = net_point(ct[jj + 1], m, code0);
+        uint64_t *const row = out + (size_t)r * cnt * a.d + j;
+        int64_t i = first;
+        for (int k = 0; k < GEN_ITERS_NET; ++k) {
+            if (i >= n_min) {
+                ulonglong2 w2;
+                w2.x = z0 ^ d0;
+                w2.y = z1 ^ d1;
+                *reinterpret_cast<ulonglong2 *>(row + (size_t)(i - n_min) * a.d) = w2;
+            }
+            const int64_t next = i + P;
+            if (next >= n_max || k + 1 == GEN_ITERS_NET) break;
+            const int c = ctz64(blk + (uint64_t)k + 1);
+            z0 ^= step[jj][c];
+            z1 ^= step[jj + 1][c];
+            i = next;
+        }
+        return;
+    }
     const int p = t / DB, jj = t % DB;
     if (p >= P) return;
     const int j = j0 + jj;
-    const int64_t cnt = n_max - n_min;
-    const int64_t first = n_min + (int64_t)blockIdx.x * P * GEN_ITERS_NET + p;
+    // tiles start at multiples of P GEN_ITERS_NET (tile_base <= n_min), so
+    // point k of every thread has i >> s = blk + k: the step index is the same
+    // for the whole block (scalar work); points below n_min are not stored
+    const int64_t first = tile_base + (int64_t)blockIdx.x * P * GEN_ITERS_NET + p;
     if (first >= n_max) return;
+    const uint64_t blk = ((uint64_t)tile_base >> s) + (uint64_t)blockIdx.x * GEN_ITERS_NET;
     const uint64_t delta = a.shift ? a.shift[(size_t)r * a.d + j] : 0;
     const uint64_t code0 = a.order == LDK_GRAY ? gray_code((uint64_t)first) : (uint64_t)first;
     uint64_t z = net_point(ct[jj], m, code0);
-    uint64_t *dst = out + ((size_t)r * cnt + (first - n_min)) * a.d + j;
-    const size_t dstep = (size_t)P * a.d;
+    uint64_t *const row = out + (size_t)r * cnt * a.d + j;
     int64_t i = first;
     for (int k = 0; k < GEN_ITERS_NET; ++k) {
-        *dst = z ^ delta;
+        if (i >= n_min) row[(size_t)(i - n_min) * a.d] = z ^ delta;
         const int64_t next = i + P;
         if (next >= n_max || k + 1 == GEN_ITERS_NET) break;
-        z ^= step[jj][ctz64(((uint64_t)i >> s) + 1)];
+        z ^= step[jj][ctz64(blk + (uint64_t)k + 1)];
         i = next;
-        dst += dstep;
     }
 }
 
@@ -184,7 +219,7 @@ extern "C" int ldk_gen_points(const ldk_pointset *ps, int64_t n_min, int64_t n_m
                            n_max, g.P, g.pairs, out);
     else
         hipLaunchKernelGGL(k_gen_net, grid, dim3(GEN_THREADS), 0, as_stream(stream), a, n_min,
-                           n_max, g.P, g.logP, out);
+                           n_max, g.tile_base, g.P, g.logP, g.pairs, out);
     LDK_LAUNCH_CHECK();
     return LDK_OK;
 }

@@ -75,11 +75,12 @@ constexpr int GEN_ITERS = 32;       // points per thread (lattices)
 constexpr int GEN_ITERS_NET = 128;  // points per thread (nets: amortises the scrambling)
 
 struct GenGrid {
-    int64_t tiles;  // point tiles per (chunk, replication)
-    int chunks;     // dimension chunks
+    int64_t tiles;      // point tiles per (chunk, replication)
+    int64_t tile_base;  // first index of tile 0 (nets: a multiple of P GEN_ITERS_NET)
+    int chunks;         // dimension chunks
     int R;
     int P, logP;
-    int pairs;      // lattice words written two dimensions per 16-byte store
+    int pairs;          // words written two dimensions per 16-byte store
 };
 
 // out: the destination (16-byte stores need an even d and a 16-byte aligned
@@ -87,14 +88,15 @@ struct GenGrid {
 inline GenGrid gen_grid(const PointsetArgs &a, int64_t n_min, int64_t n_max, const void *out)
 {
     GenGrid g{};
-    g.pairs = a.kind == LDK_LATTICE && (a.d & 1) == 0 && ((uintptr_t)out & 15) == 0;
+    g.pairs = (a.d & 1) == 0 && ((uintptr_t)out & 15) == 0;
     int dims = a.d < GEN_DIM_CHUNK ? a.d : GEN_DIM_CHUNK;
     if (g.pairs) dims >>= 1;
     g.P = 1;
     while (2 * g.P * dims <= GEN_THREADS) g.P *= 2;
     while ((1 << g.logP) < g.P) ++g.logP;
-    const int iters = a.kind == LDK_LATTICE ? GEN_ITERS : GEN_ITERS_NET;
-    g.tiles = (n_max - n_min + (int64_t)g.P * iters - 1) / ((int64_t)g.P * iters);
+    const int64_t span = (int64_t)g.P * (a.kind == LDK_LATTICE ? GEN_ITERS : GEN_ITERS_NET);
+    g.tile_base = a.kind == LDK_LATTICE ? n_min : (n_min / span) * span;
+    g.tiles = (n_max - g.tile_base + span - 1) / span;
     g.chunks = (a.d + GEN_DIM_CHUNK - 1) / GEN_DIM_CHUNK;
     g.R = a.R;
     return g;
