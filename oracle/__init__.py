@@ -38,6 +38,14 @@ MLL and gradient       standard GP objective in the eigenbasis of Sec. 5.4
                        trace-form gradient (numpy) at n <= 2^8; central
                        differences; adjoint dot-product identity; a factor
                        1 + gamma K that is exactly zero
+kernel cubature        Sec. kernel computations (worst-case error, optimal
+                       weights) and Bayesian cubature (Sec. 3; no formula
+                       printed: standard Gaussian conditioning); equal
+                       weights in d = 1 against the aliased Fourier / Walsh
+                       closed forms; each kernel factor has mean zero on
+                       fine grids (kappa_i = zeta); stationarity of the
+                       optimal weights; exact posterior mean on kernel
+                       sections; eigenvalue forms equal the dense ones
 =====================  =====================================================
 """
 from __future__ import annotations
@@ -435,3 +443,103 @@ def mll_grad(w: dict, gamma=None, zeta=None, sigma2=None, y=None) -> dict:
     kg = kernel_grad(w["kind"], pts, x0, w["alpha"], gamma, zeta, a)
     grad = np.concatenate([kg, ds[:, None]], axis=1)
     return dict(L=L, grad=grad, k1=k1, lam=lam, g=g, a=a)
+
+
+# ---------------------------------------------------------------------------
+# Kernel cubature: worst-case error, optimal weights, Bayesian cubature
+# (Sec. kernel computations; Bayesian cubature is named in Sec. 3)
+# ---------------------------------------------------------------------------
+
+def gram(kind, pts, alpha, gamma, zeta: float) -> np.ndarray:
+    """Dense Gram matrices K[r][i][l] = K(x_ri, x_rl): column l is the kernel
+    column anchored at point l (small n only)."""
+    pts = _c(pts, np.uint64)
+    R, n, d = pts.shape
+    K = np.empty((R, n, n))
+    for r in range(R):
+        for l in range(n):
+            K[r, :, l] = kernel_column(kind, pts[r:r + 1], pts[r:r + 1, l], alpha, gamma,
+                                       zeta)[0]
+    return K
+
+
+def kernel_integrals(zeta: float, n: int):
+    """kappa_i = int K(u, x_i) du (i < n) and int int K(u, v) du dv for the
+    product kernel zeta prod_j (1 + gamma_j K_alpha(x_j (-) y_j)).  Each
+    K_alpha has mean zero over [0, 1): the SI factor is a Bernoulli
+    polynomial of degree 2 alpha (a Fourier series without constant term,
+    Sec. 5.2) and the DSI factor a Walsh series without constant term
+    (eq. DSI_kernel).  Hence every factor integrates to 1, whatever the
+    other argument, and both integrals equal zeta."""
+    return np.full(n, float(zeta)), float(zeta)
+
+
+def wce2(K, kappa, I2: float, omega) -> np.ndarray:
+    """Squared worst-case error of sum_i omega_i f(x_i) as an estimate of
+    int f over the unit ball of the RKHS of K (Sec. kernel computations):
+    I2 - 2 sum_i omega_i kappa_i + sum_{i,l} omega_i omega_l K_il.
+    K: [R][n][n]; omega: [R][nw][n]; returns [R][nw]."""
+    K = np.asarray(K, np.float64)
+    omega = np.asarray(omega, np.float64)
+    kappa = np.asarray(kappa, np.float64)
+    out = np.empty(omega.shape[:2])
+    for r in range(omega.shape[0]):
+        for q in range(omega.shape[1]):
+            w = omega[r, q]
+            out[r, q] = I2 - 2.0 * np.dot(w, kappa) + np.dot(w, K[r] @ w)
+    return out
+
+
+def wce2_fast(kind, lam, zeta: float, omega) -> np.ndarray:
+    """The same squared worst-case error with K omega from the eigenvalue
+    matvec (Sec. 5.4) and kappa_i = int int K = zeta (kernel_integrals)."""
+    omega = _c(omega, np.float64)
+    Kw = matvec(kind, lam, omega)
+    return zeta - 2.0 * zeta * omega.sum(axis=-1) + (omega * Kw).sum(axis=-1)
+
+
+def bayes_cubature(K, kappa, I2: float, y, sigma2: float) -> dict:
+    """Posterior of I = int f for f ~ GP(0, s2 K) observed as y_i = f(x_i) +
+    e_i, e_i ~ N(0, s2 sigma2), given the points (Bayesian cubature, named in
+    Sec. 3; the paper prints no formula, so the Gaussian conditioning below is
+    the standard one, with the scale s2 at its maximum-likelihood value):
+      weights = (K + sigma2 I)^{-1} kappa       (the optimal cubature weights
+                                                 omega* of Sec. kernel
+                                                 computations when sigma2 = 0)
+      mean    = kappa^T (K + sigma2 I)^{-1} y  = weights . y
+      var     = I2 - kappa^T (K + sigma2 I)^{-1} kappa   (posterior variance / s2)
+      s2      = y^T (K + sigma2 I)^{-1} y / n
+      wce2    = squared worst-case error of the weights.
+    K: [R][n][n]; y: [R][n].  Dense solves (numpy)."""
+    K = np.asarray(K, np.float64)
+    y = np.asarray(y, np.float64)
+    kappa = np.asarray(kappa, np.float64)
+    R, n = y.shape
+    out = {k: np.empty(R) for k in ("mean", "var", "s2", "wce2")}
+    out["weights"] = np.empty((R, n))
+    for r in range(R):
+        A = K[r] + sigma2 * np.eye(n)
+        c = np.linalg.solve(A, y[r])
+        wk = np.linalg.solve(A, kappa)
+        out["weights"][r] = wk
+        out["mean"][r] = np.dot(kappa, c)
+        out["var"][r] = I2 - np.dot(kappa, wk)
+        out["s2"][r] = np.dot(y[r], c) / n
+    out["wce2"] = wce2(K, kappa, I2, out["weights"][:, None, :])[:, 0]
+    return out
+
+
+def bayes_cubature_fast(kind, lam, sigma2: float, zeta: float, y) -> dict:
+    """bayes_cubature with the eigenvalue solve (Sec. 5.4) in place of the
+    dense one and kappa = zeta (kernel_integrals).  lam: [R][n]; y: [R][n]."""
+    lam = _c(lam, np.float64)
+    y = _c(y, np.float64)
+    R, n = y.shape
+    kappa = np.full((R, 1, n), float(zeta))
+    c = solve(kind, lam, sigma2, y[:, None, :])[:, 0]
+    wk = solve(kind, lam, sigma2, kappa)[:, 0]
+    return dict(weights=wk,
+                mean=(kappa[:, 0] * c).sum(axis=-1),
+                var=zeta - (kappa[:, 0] * wk).sum(axis=-1),
+                s2=(y * c).sum(axis=-1) / n,
+                wce2=wce2_fast(kind, lam, zeta, wk[:, None, :])[:, 0])

@@ -35,6 +35,12 @@ muts = [
  ("oracle/orc_mll.c", "t[j] = gamma[j] * K;", "t[j] = K;"),
  ("oracle/__init__.py", "row = A[alpha * j + t % alpha, t // alpha, :]", "row = A[alpha * j + (t // alpha) % alpha, t % alpha, :]"),
  ("oracle/__init__.py", "row = A[alpha * j + t % alpha, t // alpha, :]", "row = A[j + t % alpha, t // alpha, :]"),
+ ("oracle/__init__.py", "out[r, q] = I2 - 2.0 * np.dot(w, kappa)", "out[r, q] = I2 - np.dot(w, kappa)"),
+ ("oracle/__init__.py", "return np.full(n, float(zeta)), float(zeta)", "return np.full(n, float(zeta)), 2.0 * float(zeta)"),
+ ("oracle/__init__.py", "out[\"var\"][r] = I2 - np.dot(kappa, wk)", "out[\"var\"][r] = I2 + np.dot(kappa, wk)"),
+ ("oracle/__init__.py", "out[\"s2\"][r] = np.dot(y[r], c) / n", "out[\"s2\"][r] = np.dot(y[r], c)"),
+ ("oracle/__init__.py", "return zeta - 2.0 * zeta * omega.sum(axis=-1)", "return zeta - zeta * omega.sum(axis=-1)"),
+ ("oracle/__init__.py", "s2=(y * c).sum(axis=-1) / n,", "s2=(y * c).sum(axis=-1),"),
 ]
 res = []
 for f, a, b in muts:

@@ -220,3 +220,13 @@ def small_lattice(seed: int, m: int, d: int, R: int = 1, m_max: int | None = Non
     D = shifts(rng, R, d)
     y = rng.standard_normal((R, nrhs, 2**m))
     return dict(kind="lattice", m=m, m_max=mm, d=d, R=R, gen=g, lms=None, shift=D, y=y)
+
+
+def cubature_weights(seed: int, R: int, nw: int, n: int) -> np.ndarray:
+    """Random cubature weights [R][nw][n] scattered around the equal weights
+    1/n (relative spread 1/2); row 0 of every replication is exactly 1/n."""
+    rng = np.random.default_rng(seed)
+    w = (1.0 + 0.5 * rng.standard_normal((R, nw, n))) / n
+    if nw:
+        w[:, 0, :] = 1.0 / n
+    return w
