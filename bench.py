@@ -282,6 +282,7 @@ def main():
 
     out["fwht_split16"] = fwht_bench(K)
     out["higher_order_net"] = higher_order_bench(K)
+    out["cubature"] = cubature_bench(K, lam, y[:, 0, :], w)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
@@ -447,6 +448,39 @@ def higher_order_bench(K):
             "gen_points_GB_s": round(gb, 1), "gen_points_hbm_frac": round(gb / HBM_PEAK_GBS, 4),
             "kernel_column_ms": round(ms_kc, 5),
             "kernel_column_factor_evals_per_s": round(n * d / (ms_kc * 1e-3), 1)}
+
+
+def cubature_bench(K, lam, y, w):
+    """Kernel cubature on the step's eigenvalues (lattice, n = 2^20, d = 32):
+    the Bayesian-cubature posterior of the integral from the responses, and
+    the squared worst-case errors of 16 weight vectors (Sec. kernel
+    computations).  Algorithmic bytes: each transformed row (8 n) and its
+    eigenvalue row (8 n) read once."""
+    import torch
+
+    import paper_2502_14256_amd as ldk
+    import workloads as W
+
+    R, n = y.shape
+    m = n.bit_length() - 1
+    nw = 16
+    om = torch.from_numpy(W.cubature_weights(2504, R, nw, n)).cuda()
+    e2 = torch.empty((R, nw), dtype=torch.float64, device="cuda")
+    bc = torch.empty((R, len(ldk.BC_FIELDS)), dtype=torch.float64, device="cuda")
+    ws_w = ldk._workspace(ldk.OP_WCE, ldk.LATTICE, R * nw, m, ldk.F64, "cuda")
+    ws_b = ldk._workspace(ldk.OP_BAYES_CUBATURE, ldk.LATTICE, R, m, ldk.F64, "cuda")
+    ms_bc = time_graph(lambda: ldk.bayes_cubature("lattice", lam, w["sigma2"], w["zeta"], y,
+                                                  out=bc, ws=ws_b), K)
+    ms_w = time_graph(lambda: ldk.wce("lattice", lam, om, w["zeta"], out=e2, ws=ws_w), K)
+    f = bc[0].cpu().tolist()
+    return {"workload": "lattice_m20_d32_si2 eigenvalues, responses of the step; 16 weight "
+                        "vectors around 1/n",
+            "bayes_cubature_ms": round(ms_bc, 5),
+            "bayes_cubature_GB_s": round(16 * n * R / (ms_bc * 1e-3) / 1e9, 1),
+            "wce_ms": round(ms_w, 5), "wce_rules_per_s": round(R * nw / (ms_w * 1e-3), 1),
+            "wce_GB_s": round(16 * n * R * nw / (ms_w * 1e-3) / 1e9, 1),
+            "posterior": {k: f[i] for i, k in enumerate(ldk.BC_FIELDS)},
+            "wce2_equal_weights": float(e2[0, 0].cpu())}
 
 
 def fwht_bench(K):

@@ -291,6 +291,62 @@ int ldk_kernel_grad(const ldk_kernel *k, const ldk_pointset *ps, const uint64_t 
 size_t ldk_kernel_grad_workspace_bytes(int R, int d, int64_t n_min, int64_t n_max,
                                        int points_given);
 
+/* Squared worst-case error of nw cubature rules sum_i w_i f(x_i) per
+ * replication, over the unit ball of the RKHS of the product kernel of
+ * ldk_kernel_column (Sec. kernel computations):
+ *   e2[r][q] = int int K - 2 sum_i w_rqi kappa_i + w_rq^T K_r w_rq
+ *            = zeta - 2 zeta sum_i w_rqi + sum_k lambda_rk |wt_k|^2,
+ * with kappa_i = int K(u, x_i) du.  Every factor 1 + gamma_j K_alpha of the
+ * kernel integrates to one over [0, 1) (K_alpha has mean zero), so kappa_i
+ * and the double integral both equal zeta; wt = FT(w_rq) orthonormal
+ * (Sec. 5.4), so the quadratic form costs one transform.
+ * lam = double[R][n] (ldk_eig); w = dtype[R][nw][n] in the point order of
+ * lam; e2 = device double[R][nw].  The transform of w runs in dtype, the
+ * sums in FP64 in a fixed order.  e2 is a difference of terms of size zeta:
+ * its error is absolute, of order (m + 2) u (zeta + 2 zeta sum_i |w_i| +
+ * sum_k |lambda_k| |wt_k|^2), u the unit roundoff of dtype.
+ * R * nw <= 65535.  ws: ldk_workspace_bytes(LDK_OP_WCE, kind, R * nw, m, dtype). */
+int ldk_wce(int kind, int R, int nw, int m, int dtype, const double *lam, double zeta,
+            const void *w, double *e2, void *ws, ldk_stream stream);
+
+/* Fields of one replication's ldk_bayes_cubature result. */
+enum {
+    LDK_BC_MEAN = 0,   /* posterior mean of int f */
+    LDK_BC_VAR = 1,    /* posterior variance of int f per unit GP scale */
+    LDK_BC_SCALE = 2,  /* maximum-likelihood GP scale */
+    LDK_BC_HALF = 3,   /* credible-interval half width */
+    LDK_BC_WEIGHT = 4, /* the (equal) optimal cubature weights */
+    LDK_BC_WCE2 = 5,   /* squared worst-case error of those weights */
+    LDK_BC_FIELDS = 6
+};
+
+/* Bayesian cubature (named in Sec. 3; the paper prints no formula, so the
+ * standard Gaussian conditioning is used): f ~ GP(0, s K) with the kernel
+ * of ldk_kernel_column, observed as y_i = f(x_i) + e_i, e_i ~ N(0, s sigma2),
+ * and the integral I = int f.  With kappa_i = zeta (see ldk_wce) and the
+ * constant vector an eigenvector of K with eigenvalue lambda_0 = sum_i k1_i
+ * (the points form a group under the shift or the digital sum):
+ *   WEIGHT = (K + sigma2 I)^{-1} kappa, every entry zeta / (lambda_0 + sigma2)
+ *            (the optimal weights of Sec. kernel computations at sigma2 = 0),
+ *   MEAN   = kappa^T (K + sigma2 I)^{-1} y = WEIGHT sum_i y_i,
+ *   VAR    = zeta - kappa^T (K + sigma2 I)^{-1} kappa
+ *          = zeta (lambda_0 + sigma2 - n zeta) / (lambda_0 + sigma2),
+ *   SCALE  = y^T (K + sigma2 I)^{-1} y / n = sum_k |yt_k|^2 / (lambda_k + sigma2) / n
+ *            (maximum likelihood for s; yt = FT(y) orthonormal),
+ *   HALF   = z sqrt(SCALE max(VAR, 0))  (z: the normal quantile of the
+ *            credible level, e.g. 2.5758 for 99 %),
+ *   WCE2   = zeta - 2 n zeta WEIGHT + n WEIGHT^2 lambda_0 (equals VAR at
+ *            sigma2 = 0).
+ * lam = double[R][n] (ldk_eig); y = dtype[R][n]; out = device
+ * double[R][LDK_BC_FIELDS].  The transform of y runs in dtype, the rest in
+ * FP64.  VAR and WCE2 carry the absolute rounding of lambda_0 (about
+ * (m + 1) u sum_i |k1_i| / n relative to zeta).  A replication with some
+ * lambda_k + sigma2 <= 0 gets SCALE = HALF = NaN.
+ * ws: ldk_workspace_bytes(LDK_OP_BAYES_CUBATURE, kind, R, m, dtype) bytes. */
+int ldk_bayes_cubature(int kind, int R, int m, int dtype, const double *lam, double sigma2,
+                       double zeta, const void *y, double z, double *out, void *ws,
+                       ldk_stream stream);
+
 /* Orthonormal Walsh-Hadamard transform of B FP32 rows of n = 2^m (Sec. 5.3,
  * the recursion of H_m) on the matrix cores: each radix-16 stage is one
  * FP16 matrix instruction [H_16 | H_16] [X_hi ; X_lo] with FP32 sums, where
@@ -311,7 +367,9 @@ typedef enum {
     LDK_OP_EIG_UPDATE_DOUBLE = 6,
     LDK_OP_MLL = 7,
     LDK_OP_MLL_ADJOINT = 8,
-    LDK_OP_FIT = 9
+    LDK_OP_FIT = 9,
+    LDK_OP_WCE = 10,
+    LDK_OP_BAYES_CUBATURE = 11
 } ldk_op;
 
 /* Workspace bytes needed by `op` for B rows (or R * nrhs rows) of 2^m. */

@@ -25,14 +25,16 @@ NATURAL, LINEAR, GRAY = 0, 1, 2
 F64, F32 = 0, 1
 GEN_PER_REPLICATION = 1
 (OP_TRANSFORM, OP_EIG, OP_SOLVE, OP_MATVEC, OP_LOGDET, OP_UPDATE_DOUBLE, OP_EIG_UPDATE_DOUBLE,
- OP_MLL, OP_MLL_ADJOINT, OP_FIT) = range(10)
+ OP_MLL, OP_MLL_ADJOINT, OP_FIT, OP_WCE, OP_BAYES_CUBATURE) = range(12)
+BC_FIELDS = ("mean", "var", "scale", "half", "weight", "wce2")
 
 EXPORTS = [
     "ldk_init", "ldk_gen_points", "ldk_kernel_column", "ldk_transform", "ldk_eig", "ldk_solve",
     "ldk_matvec", "ldk_logdet", "ldk_update_double", "ldk_eig_update_double",
     "ldk_workspace_bytes", "ldk_strerror", "ldk_last_hip_error", "ldk_version",
     "ldk_mll", "ldk_mll_adjoint", "ldk_kernel_grad", "ldk_kernel_grad_workspace_bytes",
-    "ldk_fwht_split16", "ldk_fit", "ldk_points_column", "ldk_interlace",
+    "ldk_fwht_split16", "ldk_fit", "ldk_points_column", "ldk_interlace", "ldk_wce",
+    "ldk_bayes_cubature",
 ]
 
 
@@ -68,6 +70,8 @@ def lib():
             "ldk_kernel_column": ([P, P, P, P, i64, i64, i32, P, P], i32),
             "ldk_points_column": ([P, P, i64, i64, P, i32, P, P], i32),
             "ldk_interlace": ([P, i32, P, P], i32),
+            "ldk_wce": ([i32, i32, i32, i32, i32, P, f64, P, P, P, P], i32),
+            "ldk_bayes_cubature": ([i32, i32, i32, i32, P, f64, f64, P, f64, P, P, P], i32),
             "ldk_transform": ([i32, i32, i32, i32, i32, P, P, P, P], i32),
             "ldk_eig": ([i32, i32, i32, i32, P, P, P, P], i32),
             "ldk_solve": ([i32, i32, i32, i32, i32, P, f64, P, P, P, P], i32),
@@ -425,6 +429,55 @@ def mll(kind, lam: torch.Tensor, sigma2: float, y: torch.Tensor, out_g=None, ws=
     _check(lib().ldk_mll(kd, R, m, dt, _ptr(lam), float(sigma2), _ptr(y), _ptr(L), _ptr(g),
                          _ptr(ds), _ptr(ws), _stream()), "ldk_mll")
     return L, g, ds
+
+
+def wce(kind, lam: torch.Tensor, w: torch.Tensor, zeta: float, out=None, ws=None):
+    """Squared worst-case errors [R][nw] of the cubature weights w [R][nw][n]
+    for the product kernel with eigenvalues lam [R][n] (ldk_wce)."""
+    kd = _kind(kind)
+    _need_f64(lam, "lam")
+    _need(w, "w")
+    dt = _dtype_code(w.dtype)
+    R, nw, n = w.shape
+    if tuple(lam.shape) != (R, n):
+        raise LdkError("lam must be [R][n] and w [R][nw][n]")
+    m = _m_of(n)
+    out = torch.empty((R, nw), dtype=torch.float64, device=w.device) if out is None else out
+    _need_f64(out, "out")
+    if ws is None:
+        ws = _workspace(OP_WCE, kd, R * nw, m, dt, w.device)
+    _check(lib().ldk_wce(kd, R, nw, m, dt, _ptr(lam), float(zeta), _ptr(w), _ptr(out), _ptr(ws),
+                         _stream()), "ldk_wce")
+    return out
+
+
+def bayes_cubature(kind, lam: torch.Tensor, sigma2: float, zeta: float, y: torch.Tensor,
+                   level: float = 0.99, out=None, ws=None):
+    """Bayesian-cubature posterior of the integral per replication (ldk_bayes_cubature):
+    a double tensor [R][6] whose columns are named by BC_FIELDS; the credible
+    interval is mean +- half at the given level."""
+    import statistics
+
+    kd = _kind(kind)
+    _need_f64(lam, "lam")
+    _need(y, "y")
+    dt = _dtype_code(y.dtype)
+    R, n = y.shape
+    if tuple(lam.shape) != (R, n):
+        raise LdkError("lam and y must both be [R][n]")
+    if not 0.0 < level < 1.0:
+        raise LdkError("level must lie in (0, 1)")
+    m = _m_of(n)
+    z = statistics.NormalDist().inv_cdf(0.5 + 0.5 * level)
+    out = torch.empty((R, len(BC_FIELDS)), dtype=torch.float64, device=y.device) \
+        if out is None else out
+    _need_f64(out, "out")
+    if ws is None:
+        ws = _workspace(OP_BAYES_CUBATURE, kd, R, m, dt, y.device)
+    _check(lib().ldk_bayes_cubature(kd, R, m, dt, _ptr(lam), float(sigma2), float(zeta), _ptr(y),
+                                    float(z), _ptr(out), _ptr(ws), _stream()),
+           "ldk_bayes_cubature")
+    return out
 
 
 def mll_adjoint(kind, g: torch.Tensor, out=None, ws=None):

@@ -382,6 +382,7 @@ size_t ws_bytes(int op, int kind, int64_t B, int m, int dtype)
 {
     if (op == LDK_OP_FIT) return fit_ws_bytes(kind, B, m, dtype);
     if (op == LDK_OP_MLL || op == LDK_OP_MLL_ADJOINT) return mll_ws_bytes(op, kind, B, m, dtype);
+    if (op == LDK_OP_WCE || op == LDK_OP_BAYES_CUBATURE) return cub_ws_bytes(kind, B, m, dtype);
     if (m == 0) return op == LDK_OP_LOGDET ? (size_t)B * sizeof(double) : 0;
     const bool lat = kind == LDK_LATTICE;
     const int P = make_plan(m, log_tile_for(kind, dtype)).P;

@@ -10,6 +10,17 @@
 // store, FP64), so yt itself is never written.  Since lambda = sqrt(n) FT(k1)
 // is linear in k1, dL/dk1 = a is the adjoint map applied to g: H g for the
 // net (H symmetric) and Re sum_k g_k W^{-k R(j)} for the lattice.
+//
+// Kernel cubature (Sec. kernel computations) uses the same power spectrum.
+// For the product kernels of ldk_kernel_column every factor 1 + gamma K_alpha
+// integrates to one over [0, 1) (K_alpha has mean zero), so
+// kappa_i = int K(u, x_i) du = zeta and int int K = zeta; then
+//   e2(w) = zeta - 2 zeta sum_i w_i + sum_k lambda_k |wt_k|^2   (wt = FT(w)).
+// The points form a group under the shift (lattice) or the digital sum
+// (net), so the constant vector is an eigenvector of K with eigenvalue
+// lambda_0 = sum_i k1_i, and (K + s2 I)^{-1} kappa = zeta / (lambda_0 + s2) 1:
+// the optimal weights are equal and the Bayesian-cubature posterior of the
+// integral needs only lambda_0, sum_i y_i and y^T (K + s2 I)^{-1} y.
 #include "transform.hpp"
 
 namespace ldk {
@@ -187,6 +198,81 @@ int power_spectrum(int kind, int R, int m, int dtype, const void *y, double *pw,
     return LDK_OK;
 }
 
+// Cubature partial sums per (row, chunk), rows = R * nw, lambda row = row / nw:
+//   BC = false: [0] sum_k lambda_k p_k,        [1] sum_i w_i
+//   BC = true:  [0] sum_k p_k / (lambda_k + s2) (NaN when some
+//               lambda_k + s2 <= 0),           [1] sum_i y_i
+template <typename R, bool BC>
+__global__ __launch_bounds__(MLL_THREADS) void k_cub_terms(const double *__restrict__ lam,
+                                                           const double *__restrict__ pw,
+                                                           const R *__restrict__ w, int64_t n,
+                                                           int nw, double sigma2, int chunks,
+                                                           double *__restrict__ part)
+{
+    __shared__ double red[MLL_THREADS / 64][3];
+    const int row = blockIdx.y, ch = blockIdx.x;
+    const double *lr = lam + (size_t)(row / nw) * n;
+    const double *pr = pw + (size_t)row * n;
+    const R *wr = w + (size_t)row * n;
+    double acc[3] = {0.0, 0.0, 0.0};
+    const int64_t lo = (int64_t)ch * MLL_CHUNK;
+#pragma unroll
+    for (int it = 0; it < MLL_ITEMS; ++it) {
+        const int64_t k = lo + threadIdx.x + (int64_t)it * MLL_THREADS;
+        if (k < n) {
+            const double p = pr[k];
+            if constexpr (BC) {
+                const double s = lr[k] + sigma2;
+                acc[0] += s > 0.0 ? p / s : __builtin_nan("");
+            } else {
+                acc[0] = fma(lr[k], p, acc[0]);
+            }
+            acc[1] += (double)wr[k];
+        }
+    }
+    block_sum3(acc, red);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 2; ++c) part[((size_t)row * chunks + ch) * 2 + c] = acc[c];
+}
+
+// Per row: e2 (BC = false) or the posterior fields (BC = true).
+template <bool BC>
+__global__ __launch_bounds__(MLL_THREADS) void k_cub_final(const double *__restrict__ part,
+                                                           int chunks, int64_t n,
+                                                           const double *__restrict__ lam,
+                                                           double sigma2, double zeta, double z,
+                                                           double *__restrict__ out)
+{
+    __shared__ double red[MLL_THREADS / 64][3];
+    const int row = blockIdx.x;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int c = threadIdx.x; c < chunks; c += MLL_THREADS)
+        for (int q = 0; q < 2; ++q) acc[q] += part[((size_t)row * chunks + c) * 2 + q];
+    block_sum3(acc, red);
+    if (threadIdx.x != 0) return;
+    const double nd = (double)n;
+    if constexpr (!BC) {
+        // zeta - 2 zeta sum w + w^T K w, the power spectrum being unnormalised
+        out[row] = fma(-2.0 * zeta, acc[1], zeta) + acc[0] / nd;
+    } else {
+        const double l0 = lam[(size_t)row * n];
+        const double s = l0 + sigma2;
+        const double t = s - nd * zeta;  // lambda_0 + s2 - n zeta
+        const double wgt = zeta / s;
+        const double var = zeta * t / s;
+        const double scale = acc[0] / (nd * nd);
+        double *o = out + (size_t)row * LDK_BC_FIELDS;
+        o[LDK_BC_MEAN] = wgt * acc[1];
+        o[LDK_BC_VAR] = var;
+        o[LDK_BC_SCALE] = scale;
+        const double sv = scale * var;  // NaN stays NaN; rounding below zero gives 0
+        o[LDK_BC_HALF] = z * sqrt(sv < 0.0 ? 0.0 : sv);
+        o[LDK_BC_WEIGHT] = wgt;
+        // zeta - 2 n zeta wgt + n wgt^2 lambda_0 = zeta (t^2 + n zeta (t - s2)) / s^2
+        o[LDK_BC_WCE2] = zeta * fma(t, t, nd * zeta * (t - sigma2)) / (s * s);
+    }
+}
+
 }  // namespace
 
 // Workspace of the likelihood ops (LDK_OP_MLL, LDK_OP_MLL_ADJOINT).
@@ -197,6 +283,15 @@ size_t mll_ws_bytes(int op, int kind, int64_t R, int m, int dtype)
                power_tmp_bytes(kind, R, m, dtype);
     // adjoint: FP64; the FWHT runs in place in the output
     return real_lattice(kind, m) ? power_tmp_bytes(kind, R, m, LDK_F64) : 0;
+}
+
+// Workspace of the cubature ops for B transformed rows: partial sums, the
+// power spectrum, the transform scratch.
+size_t cub_ws_bytes(int kind, int64_t B, int m, int dtype)
+{
+    return align256((size_t)B * chunks_of(m) * 2 * sizeof(double)) +
+           align256((size_t)B * ((size_t)1 << m) * sizeof(double)) +
+           power_tmp_bytes(kind, B, m, dtype);
 }
 
 }  // namespace ldk
@@ -300,4 +395,68 @@ extern "C" int ldk_mll_adjoint(int kind, int R, int m, const double *g, double *
         if (st) return st;
     }
     return LDK_OK;
+}
+
+namespace {
+
+template <bool BC>
+int cubature(int kind, int R, int nw, int m, int dtype, const double *lam, double sigma2,
+             double zeta, const void *w, double z, double *out, void *ws, hipStream_t s)
+{
+    const int64_t n = (int64_t)1 << m;
+    const int rows = R * nw;
+    const int chunks = chunks_of(m);
+    double *part = static_cast<double *>(ws);
+    double *pw = reinterpret_cast<double *>(static_cast<unsigned char *>(ws) +
+                                            align256((size_t)rows * chunks * 2 * sizeof(double)));
+    void *tmp = reinterpret_cast<unsigned char *>(pw) + align256((size_t)rows * n * sizeof(double));
+    int st = power_spectrum(kind, rows, m, dtype, w, pw, tmp, s);
+    if (st) return st;
+    if (dtype == LDK_F64)
+        hipLaunchKernelGGL((k_cub_terms<double, BC>), dim3(chunks, rows), dim3(MLL_THREADS), 0, s,
+                           lam, (const double *)pw, (const double *)w, n, nw, sigma2, chunks, part);
+    else
+        hipLaunchKernelGGL((k_cub_terms<float, BC>), dim3(chunks, rows), dim3(MLL_THREADS), 0, s,
+                           lam, (const double *)pw, (const float *)w, n, nw, sigma2, chunks, part);
+    LDK_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_cub_final<BC>, dim3(rows), dim3(MLL_THREADS), 0, s, (const double *)part,
+                       chunks, n, lam, sigma2, zeta, z, out);
+    LDK_LAUNCH_CHECK();
+    return LDK_OK;
+}
+
+bool finite_param(double v) { return v >= -1.0e300 && v <= 1.0e300; }
+
+}  // namespace
+
+extern "C" int ldk_wce(int kind, int R, int nw, int m, int dtype, const double *lam, double zeta,
+                       const void *w, double *e2, void *ws, ldk_stream stream)
+{
+    if ((kind != LDK_LATTICE && kind != LDK_DNET_B2) || (dtype != LDK_F64 && dtype != LDK_F32))
+        return LDK_EINVAL;
+    if (m < 0 || m > TW_MAX_LOG || R < 0 || nw < 0 || !finite_param(zeta)) return LDK_EINVAL;
+    if ((int64_t)R * nw > 65535) return LDK_EINVAL;
+    if (R == 0 || nw == 0) return LDK_OK;
+    if (!lam || !w || !e2 || !ws) return LDK_EINVAL;
+    const int st = ensure_init();
+    if (st) return st;
+    return cubature<false>(kind, R, nw, m, dtype, lam, 0.0, zeta, w, 0.0, e2, ws,
+                           as_stream(stream));
+}
+
+extern "C" int ldk_bayes_cubature(int kind, int R, int m, int dtype, const double *lam,
+                                  double sigma2, double zeta, const void *y, double z,
+                                  double *out, void *ws, ldk_stream stream)
+{
+    if ((kind != LDK_LATTICE && kind != LDK_DNET_B2) || (dtype != LDK_F64 && dtype != LDK_F32))
+        return LDK_EINVAL;
+    if (m < 0 || m > TW_MAX_LOG || R < 0 || R > 65535 || !(sigma2 >= 0.0 && sigma2 <= 1.0e300) ||
+        !finite_param(zeta) || !(z >= 0.0 && z <= 1.0e300))
+        return LDK_EINVAL;
+    if (R == 0) return LDK_OK;
+    if (!lam || !y || !out || !ws) return LDK_EINVAL;
+    const int st = ensure_init();
+    if (st) return st;
+    return cubature<true>(kind, R, 1, m, dtype, lam, sigma2, zeta, y, z, out, ws,
+                          as_stream(stream));
 }

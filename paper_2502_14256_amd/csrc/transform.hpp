@@ -133,5 +133,7 @@ struct LogProd {
 
 // Workspace bytes of LDK_OP_MLL / LDK_OP_MLL_ADJOINT (mll.hip).
 size_t mll_ws_bytes(int op, int kind, int64_t R, int m, int dtype);
+// Workspace bytes of LDK_OP_WCE / LDK_OP_BAYES_CUBATURE for B rows (mll.hip).
+size_t cub_ws_bytes(int kind, int64_t B, int m, int dtype);
 
 }  // namespace ldk

@@ -1,0 +1,204 @@
+"""GPU parity of the kernel-cubature path against the oracle (Sec. kernel
+computations): squared worst-case errors of batches of weight vectors and
+the Bayesian-cubature posterior, on the oracle's eigenvalues, at sizes from
+n = 1 through multi-pass transforms to the 2^20 workloads; plus the
+closed-form worst-case error of equal weights in one dimension through the
+whole GPU path (points -> k1 -> lambda -> e2)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+import paper_2502_14256_amd as ldk
+from ldk_dev import F32_EPS, U64_EPS, kernel, pointset, record, solve_tol
+
+pytestmark = pytest.mark.gpu
+
+F64, F32 = torch.float64, torch.float32
+Z99 = 2.5758293035489004  # normal quantile of 0.995
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.build(force=False)
+    return oracle
+
+
+def _inst(kind, seed, m, d, R, alpha, gamma, zeta, sigma2=1e-3):
+    w = W.small_lattice(seed, m, d, R) if kind == "lattice" else W.small_net(seed, m, d, R)
+    w.update(alpha=np.array(alpha, np.int32), gamma=np.array(gamma, np.float64), zeta=zeta,
+             sigma2=sigma2)
+    return w
+
+
+def _lam(orc, w):
+    pts = orc.points(w)
+    k1 = orc.kernel_column(w["kind"], pts, pts[:, 0], w["alpha"], w["gamma"], w["zeta"])
+    return orc.eig(w["kind"], k1)[0]
+
+
+def _wce_tol(m, eps, zeta, om, lam):
+    """Absolute bound on e2 = zeta - 2 zeta sum w + sum_k lambda_k |wt_k|^2
+    computed two ways (here and in the oracle): 8 (m + 2) eps times the size
+    of the terms, sum_k |lambda_k| |wt_k|^2 <= max|lambda| ||w||^2."""
+    lmax = np.abs(lam).max(axis=-1)[:, None]
+    size = zeta + 2.0 * abs(zeta) * np.abs(om).sum(axis=-1) + lmax * (om * om).sum(axis=-1)
+    return 8.0 * (m + 2) * eps * size
+
+
+CUB_M = [0, 1, 2, 3, 5, 11, 12, 13, 14, 16, 20]
+
+
+@pytest.mark.parametrize("kind", ["lattice", "dnet"])
+@pytest.mark.parametrize("m", CUB_M)
+@pytest.mark.parametrize("dtype", [F64, F32])
+def test_wce(orc, kind, m, dtype):
+    R, nw = (2, 3) if m < 16 else (1, 2)
+    alpha = [2, 1, 3] if kind == "lattice" else [2, 4, 1]
+    zeta = 1.3
+    w = _inst(kind, 60 + m, m, 3, R, alpha, [0.9, 0.5, 0.3], zeta)
+    lam = _lam(orc, w)
+    om = W.cubature_weights(70 + m, R, nw, 2**m)
+    om = om.astype(np.float64 if dtype == F64 else np.float32)
+    ref = orc.wce2_fast(kind, lam, zeta, om.astype(np.float64))
+    e2 = ldk.wce(kind, torch.from_numpy(lam).cuda(), torch.from_numpy(om).cuda(), zeta)
+    e2 = e2.cpu().numpy()
+    tol = _wce_tol(m, U64_EPS if dtype == F64 else F32_EPS, zeta, om.astype(np.float64), lam)
+    err = np.max(np.abs(e2 - ref) / tol)
+    record(f"wce_{kind}_m{m}_{'f64' if dtype == F64 else 'f32'}", err_over_tol=err)
+    assert err <= 1.0, (e2, ref, tol)
+
+
+def _bc_check(orc, kind, lam, y, sigma2, zeta, m, dtype, name):
+    R, n = y.shape
+    ref = orc.bayes_cubature_fast(kind, lam, sigma2, zeta, y.astype(np.float64))
+    out = ldk.bayes_cubature(kind, torch.from_numpy(lam).cuda(), sigma2, zeta,
+                             torch.from_numpy(y).cuda(), level=0.99).cpu().numpy()
+    f = {k: out[:, i] for i, k in enumerate(ldk.BC_FIELDS)}
+    u = U64_EPS
+    eps = U64_EPS if dtype == F64 else F32_EPS
+    y64 = y.astype(np.float64)
+    # the oracle's c = (K + s2 I)^{-1} y carries a normwise error <= tol_c ||c||
+    c_ref = orc.solve(kind, lam, sigma2, y64[:, None, :])[:, 0]
+    tol_c = solve_tol(lam, sigma2, y64, c_ref, m, u)
+    cn = np.linalg.norm(c_ref, axis=-1)
+    errs = {}
+    # mean: zeta sum_i c_i there, zeta sum_i y_i / (lambda_0 + s2) here
+    tol = abs(zeta) * (math.sqrt(n) * cn * tol_c + 8 * (m + 2) * u * np.abs(y64).sum(-1)
+                       / (lam[:, 0] + sigma2))
+    errs["mean"] = np.max(np.abs(f["mean"] - ref["mean"]) / tol)
+    # var, weight, wce2 need only lambda_0 here; the oracle solves for the
+    # constant vector kappa with two transforms whose sums are exact and
+    # whose normalisation rounds once per stage
+    tol = 8 * (m + 2) * u * abs(zeta) * (1.0 + lam[:, 0] * n * f["weight"] ** 2 / abs(zeta))
+    errs["var"] = np.max(np.abs(f["var"] - ref["var"]) / tol)
+    errs["wce2"] = np.max(np.abs(f["wce2"] - ref["wce2"]) / tol)
+    errs["weight"] = np.max(np.abs(f["weight"] - ref["weights"][:, 0]) /
+                            (8 * (m + 2) * u * np.abs(ref["weights"][:, 0])))
+    np.testing.assert_allclose(ref["weights"], np.broadcast_to(ref["weights"][:, :1],
+                                                                ref["weights"].shape), rtol=1e-12)
+    # scale: y^T c / n; here the transform of y runs in dtype (every term >= 0)
+    tol = (np.linalg.norm(y64, axis=-1) * cn * tol_c / n + 8 * (m + 2) * eps * np.abs(ref["s2"]))
+    errs["scale"] = np.max(np.abs(f["scale"] - ref["s2"]) / tol)
+    # half width from the returned fields
+    half = Z99 * np.sqrt(np.maximum(f["scale"] * f["var"], 0.0))
+    errs["half"] = np.max(np.abs(f["half"] - half) / (4 * u * np.maximum(half, 1e-300)))
+    record(name, **{f"{k}_over_tol": v for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= 1.0, (k, v, f, ref)
+    return f
+
+
+@pytest.mark.parametrize("kind", ["lattice", "dnet"])
+@pytest.mark.parametrize("m", CUB_M)
+@pytest.mark.parametrize("dtype", [F64, F32])
+def test_bayes_cubature(orc, kind, m, dtype):
+    R = 3 if m < 16 else 1
+    alpha = [1, 2, 2, 3] if kind == "lattice" else [2, 2, 3, 4]
+    zeta, sigma2 = 0.8, 1e-3
+    w = _inst(kind, 80 + m, m, 4, R, alpha, [1.0, 0.5, 0.25, 0.125], zeta, sigma2)
+    lam = _lam(orc, w)
+    y = w["y"][:, 0, :].astype(np.float64 if dtype == F64 else np.float32)
+    _bc_check(orc, kind, lam, y, sigma2, zeta, m, dtype,
+              f"bc_{kind}_m{m}_{'f64' if dtype == F64 else 'f32'}")
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_cubature_full_size(orc, k):
+    # the 2^20-point workloads: lattice d = 32 (SI order 2), net d = 32 (DSI order 4)
+    w = W.workload(k)
+    m, kind = w["m"], w["kind"]
+    lam = _lam(orc, w)
+    y = W.sine_response(W.to_unit_f64(orc.points(w)), w["eps"][:, 0, :]) if k == 2 \
+        else w["y"][:, 0, :]
+    _bc_check(orc, kind, lam, np.ascontiguousarray(y), w["sigma2"], w["zeta"], m, F64,
+              f"bc_full_{w['name']}")
+    om = W.cubature_weights(90 + k, 1, 4, 2**m)
+    ref = orc.wce2_fast(kind, lam, w["zeta"], om)
+    e2 = ldk.wce(kind, torch.from_numpy(lam).cuda(), torch.from_numpy(om).cuda(),
+                 w["zeta"]).cpu().numpy()
+    err = np.max(np.abs(e2 - ref) / _wce_tol(m, U64_EPS, w["zeta"], om, lam))
+    record(f"wce_full_{w['name']}", err_over_tol=err)
+    assert err <= 1.0
+
+
+@pytest.mark.parametrize("kind,alpha,m", [("lattice", 1, 6), ("lattice", 1, 10),
+                                          ("lattice", 2, 4), ("lattice", 2, 6),
+                                          ("dnet", 2, 6), ("dnet", 3, 8), ("dnet", 4, 10)])
+def test_equal_weights_closed_form_through_gpu(orc, kind, alpha, m):
+    # d = 1: g = 1 lattice or identity-matrix net, so the equal-weight e2 is
+    # zeta gamma (sum of the aliased Fourier / Walsh coefficients)
+    from oracle import brute
+    n, zeta, gamma = 2**m, 1.7, 0.6
+    rng = np.random.default_rng(m)
+    shift = rng.integers(0, 2**63, size=(1, 1), dtype=np.uint64)
+    if kind == "lattice":
+        gen = np.array([1], np.uint64)
+        exact = zeta * gamma * (brute.lattice_alias_sum(alpha, 0, n) - 1.0)
+    else:
+        gen = np.array([[np.uint64(1) << np.uint64(63 - k) for k in range(m)]], np.uint64)
+        exact = zeta * gamma * float(brute.net_alias_sum(alpha, 0, m) - 1)
+    w = dict(kind=kind, m=m, d=1, R=1, gen=gen, lms=None, shift=shift,
+             alpha=np.array([alpha], np.int32), gamma=np.array([gamma]), zeta=zeta)
+    pts, k1 = ldk.points_column(kernel(w), pointset(w), 0, n, F64)
+    lam = ldk.eig(kind, k1)
+    om = torch.full((1, 1, n), 1.0 / n, dtype=F64, device="cuda")
+    e2 = float(ldk.wce(kind, lam, om, zeta).cpu()[0, 0])
+    # absolute: the eigenvalue transform and the cancellation against zeta
+    tol = 16 * (m + 2) * U64_EPS * zeta * (1 + gamma * 4.0)
+    record(f"wce_closed_{kind}_a{alpha}_m{m}", err=abs(e2 - exact), tol=tol)
+    assert abs(e2 - exact) <= tol, (e2, exact)
+    # the optimal weights' posterior variance at sigma2 = 0 equals their e2
+    y = torch.zeros((1, n), dtype=F64, device="cuda")
+    f = ldk.bayes_cubature(kind, lam, 0.0, zeta, y).cpu().numpy()[0]
+    assert abs(f[ldk.BC_FIELDS.index("var")] - f[ldk.BC_FIELDS.index("wce2")]) <= tol
+    assert f[ldk.BC_FIELDS.index("wce2")] <= e2 + tol
+
+
+def test_cubature_edge_cases(orc):
+    dev = "cuda"
+    lam = torch.ones((2, 16), dtype=F64, device=dev)
+    # empty batches are no-ops
+    out = ldk.wce("dnet", lam, torch.empty((2, 0, 16), dtype=F64, device=dev), 1.0)
+    assert out.shape == (2, 0)
+    # lambda_k + sigma2 <= 0 somewhere: scale and half are NaN, the rest finite
+    bad = lam.clone()
+    bad[1, 5] = -2.0
+    y = torch.ones((2, 16), dtype=F64, device=dev)
+    f = ldk.bayes_cubature("dnet", bad, 0.5, 1.0, y).cpu().numpy()
+    s, h = ldk.BC_FIELDS.index("scale"), ldk.BC_FIELDS.index("half")
+    assert np.isfinite(f[0]).all()
+    assert np.isnan(f[1, s]) and np.isnan(f[1, h])
+    assert np.isfinite(np.delete(f[1], [s, h])).all()
+    # the workspace is reused across calls of different sizes
+    ws = torch.empty(ldk.lib().ldk_workspace_bytes(ldk.OP_WCE, ldk.LATTICE, 6, 12, ldk.F64),
+                     dtype=torch.uint8, device=dev)
+    lam12 = torch.rand((2, 2**12), dtype=F64, device=dev) + 1.0
+    om = torch.rand((2, 3, 2**12), dtype=F64, device=dev)
+    a = ldk.wce("lattice", lam12, om, 1.0, ws=ws).cpu()
+    ldk.wce("lattice", lam12[:1, :2**10].contiguous(), om[:1, :, :2**10].contiguous(), 1.0, ws=ws)
+    b = ldk.wce("lattice", lam12, om, 1.0, ws=ws).cpu()
+    assert torch.equal(a, b)

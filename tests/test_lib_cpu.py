@@ -228,3 +228,43 @@ def test_fwht_split16_rejects_bad_arguments():
     assert L.ldk_fwht_split16(1, 27, FAKE, FAKE, None) == -1
     assert L.ldk_fwht_split16(1, 4, None, FAKE, None) == -1
     assert L.ldk_fwht_split16(0, 4, None, None, None) == 0
+
+
+def test_cubature_entry_points_reject_bad_arguments():
+    L = ldk.lib()
+    nan = float("nan")
+    # ldk_wce(kind, R, nw, m, dtype, lam, zeta, w, e2, ws, stream)
+    f = L.ldk_wce
+    assert f(7, 1, 1, 4, 0, FAKE, 1.0, FAKE, FAKE, FAKE, None) == -1
+    assert f(ldk.LATTICE, 1, 1, 4, 5, FAKE, 1.0, FAKE, FAKE, FAKE, None) == -1
+    assert f(ldk.LATTICE, 1, 1, 27, 0, FAKE, 1.0, FAKE, FAKE, FAKE, None) == -1
+    assert f(ldk.DNET_B2, 1, 1, 4, 0, FAKE, nan, FAKE, FAKE, FAKE, None) == -1
+    assert f(ldk.DNET_B2, 256, 256, 4, 0, FAKE, 1.0, FAKE, FAKE, FAKE, None) == -1  # rows
+    assert f(ldk.DNET_B2, 1, -1, 4, 0, FAKE, 1.0, FAKE, FAKE, FAKE, None) == -1
+    assert f(ldk.DNET_B2, 1, 1, 4, 0, None, 1.0, FAKE, FAKE, FAKE, None) == -1
+    assert f(ldk.DNET_B2, 1, 1, 4, 0, FAKE, 1.0, FAKE, FAKE, None, None) == -1   # ws
+    assert f(ldk.DNET_B2, 1, 1, 4, 0, FAKE, 1.0, FAKE, None, FAKE, None) == -1   # e2
+    assert f(ldk.DNET_B2, 3, 0, 4, 0, None, 1.0, None, None, None, None) == 0    # nothing to do
+    assert f(ldk.DNET_B2, 0, 3, 4, 0, None, 1.0, None, None, None, None) == 0
+    # ldk_bayes_cubature(kind, R, m, dtype, lam, sigma2, zeta, y, z, out, ws, stream)
+    g = L.ldk_bayes_cubature
+    assert g(7, 1, 4, 0, FAKE, 0.1, 1.0, FAKE, 2.0, FAKE, FAKE, None) == -1
+    assert g(ldk.LATTICE, 1, 4, 0, FAKE, -1.0, 1.0, FAKE, 2.0, FAKE, FAKE, None) == -1
+    assert g(ldk.LATTICE, 1, 4, 0, FAKE, nan, 1.0, FAKE, 2.0, FAKE, FAKE, None) == -1
+    assert g(ldk.LATTICE, 1, 4, 0, FAKE, 0.1, nan, FAKE, 2.0, FAKE, FAKE, None) == -1
+    assert g(ldk.LATTICE, 1, 4, 0, FAKE, 0.1, 1.0, FAKE, -2.0, FAKE, FAKE, None) == -1
+    assert g(ldk.LATTICE, 65536, 4, 0, FAKE, 0.1, 1.0, FAKE, 2.0, FAKE, FAKE, None) == -1
+    assert g(ldk.LATTICE, 1, 4, 0, FAKE, 0.1, 1.0, None, 2.0, FAKE, FAKE, None) == -1
+    assert g(ldk.LATTICE, 1, 4, 0, FAKE, 0.1, 1.0, FAKE, 2.0, FAKE, None, None) == -1
+    assert g(ldk.LATTICE, 0, 4, 0, None, 0.1, 1.0, None, 2.0, None, None, None) == 0
+
+
+def test_cubature_workspace_sizes():
+    ws = ldk.lib().ldk_workspace_bytes
+    # partial sums (2 doubles per 2048 entries, 256-byte aligned) + power
+    # spectrum (FP64 rows) + transform scratch
+    assert ws(ldk.OP_WCE, ldk.DNET_B2, 2, 10, 0) == 256 + 2 * 2**10 * 8
+    assert ws(ldk.OP_WCE, ldk.DNET_B2, 2, 20, 0) == 2 * 512 * 2 * 8 + 2 * 2**20 * 8 * 2
+    assert ws(ldk.OP_BAYES_CUBATURE, ldk.LATTICE, 2, 20, 1) == (2 * 512 * 2 * 8 + 2 * 2**20 * 8
+                                                              + 2 * 2**19 * 8)
+    assert ws(ldk.OP_BAYES_CUBATURE, ldk.LATTICE, 3, 0, 0) == 256 + 256
