@@ -41,6 +41,11 @@ muts = [
  ("oracle/__init__.py", "out[\"s2\"][r] = np.dot(y[r], c) / n", "out[\"s2\"][r] = np.dot(y[r], c)"),
  ("oracle/__init__.py", "return zeta - 2.0 * zeta * omega.sum(axis=-1)", "return zeta - zeta * omega.sum(axis=-1)"),
  ("oracle/__init__.py", "s2=(y * c).sum(axis=-1) / n,", "s2=(y * c).sum(axis=-1),"),
+ ("oracle/__init__.py", "return (1.0 + x @ np.asarray(c, np.float64)) ** (-(d + 1))", "return (1.0 + x @ np.asarray(c, np.float64)) ** (-d)"),
+ ("oracle/__init__.py", "sigma = math.sqrt(((mu_r - mu) ** 2).sum() / (R - 1))", "sigma = math.sqrt(((mu_r - mu) ** 2).sum() / R)"),
+ ("oracle/__init__.py", "t = float(stats.t.ppf(1.0 - tau / 2.0, R - 1))", "t = float(stats.t.ppf(1.0 - tau, R - 1))"),
+ ("oracle/__init__.py", "return np.ldexp(np.asarray(words, dtype=np.uint64).astype(np.float64), -64)", "return np.ldexp(np.asarray(words, dtype=np.uint64).astype(np.float64), -63)"),
+ ("oracle/__init__.py", "return np.cos(2.0 * np.pi * u + x @ np.asarray(c, np.float64))", "return np.cos(np.pi * u + x @ np.asarray(c, np.float64))"),
 ]
 res = []
 for f, a, b in muts:

@@ -230,3 +230,10 @@ def cubature_weights(seed: int, R: int, nw: int, n: int) -> np.ndarray:
     if nw:
         w[:, 0, :] = 1.0 / n
     return w
+
+
+def corner_peak_coefficients(d: int) -> np.ndarray:
+    """Coefficients of the corner-peak test integrand of the RQMC example:
+    c_j proportional to 1/j^2, scaled to sum to 1/4."""
+    ct = 1.0 / np.arange(1, d + 1, dtype=np.float64) ** 2
+    return 0.25 * ct / ct.sum()
