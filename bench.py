@@ -283,6 +283,7 @@ def main():
     out["fwht_split16"] = fwht_bench(K)
     out["higher_order_net"] = higher_order_bench(K)
     out["cubature"] = cubature_bench(K, lam, y[:, 0, :], w)
+    out["rqmc"] = rqmc_bench(K)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
@@ -481,6 +482,52 @@ def cubature_bench(K, lam, y, w):
             "wce_GB_s": round(16 * n * R * nw / (ms_w * 1e-3) / 1e9, 1),
             "posterior": {k: f[i] for i, k in enumerate(ldk.BC_FIELDS)},
             "wce2_equal_weights": float(e2[0, 0].cpu())}
+
+
+def rqmc_bench(K):
+    """RQMC estimate + Student-t interval of the corner-peak integrand
+    (eq. RQMC), points regenerated in the kernel: the paper's example shape
+    (d = 50, n = 2^15, R = 10, order-3 interlaced LMS + shifted net) and a
+    throughput shape (d = 50, n = 2^20, R = 16; shifted lattice and LMS net).
+    Cost unit: point coordinates (n d R per estimate)."""
+    import numpy as np
+    import torch
+
+    import paper_2502_14256_amd as ldk
+    import workloads as W
+
+    def dev_u64(a):
+        return torch.from_numpy(np.ascontiguousarray(a, np.uint64).view(np.int64).copy()).cuda()
+
+    d = 50
+    coef = torch.from_numpy(W.corner_peak_coefficients(d)).cuda()
+    res = {}
+
+    def timed(name, ps, n):
+        mu_r = torch.empty(ps.R, dtype=torch.float64, device="cuda")
+        st = torch.empty(3, dtype=torch.float64, device="cuda")
+        ws = torch.empty(max(int(ldk.lib().ldk_rqmc_workspace_bytes(ps.R, n)), 1),
+                         dtype=torch.uint8, device="cuda")
+        ms = time_graph(lambda: ldk.rqmc(ps, n, "corner_peak", coef, mu_r=mu_r, stats=st,
+                                         ws=ws), K)
+        v = st.cpu().tolist()
+        res[name] = {"ms": round(ms, 5), "coords_per_s": round(n * d * ps.R / (ms * 1e-3), 1),
+                     "mean": v[0], "half_width_99": v[2]}
+
+    m, R, alpha = 15, 10, 3
+    src = W.small_net(2502, m=m, d=alpha * d, R=R)
+    shift = np.random.default_rng(7).integers(0, 2**64, size=(R, d), dtype=np.uint64)
+    ps_src = ldk.PointSet("dnet", R, alpha * d, m, dev_u64(src["gen"]), dev_u64(src["lms"]), None)
+    hp = ldk.interlace(ps_src, alpha, shift=dev_u64(shift))
+    timed("paper_shape_net_order3_m15_d50_R10", hp, 2**m)
+    m, R = 20, 16
+    wl = W.small_lattice(2506, m, d, R)
+    timed("lattice_m20_d50_R16", ldk.PointSet("lattice", R, d, m, dev_u64(wl["gen"]), None,
+                                              dev_u64(wl["shift"])), 2**m)
+    wn = W.small_net(2507, m, d, R)
+    timed("net_lms_m20_d50_R16", ldk.PointSet("dnet", R, d, m, dev_u64(wn["gen"]),
+                                              dev_u64(wn["lms"]), dev_u64(wn["shift"])), 2**m)
+    return res
 
 
 def fwht_bench(K):

@@ -347,6 +347,39 @@ int ldk_bayes_cubature(int kind, int R, int m, int dtype, const double *lam, dou
                        double zeta, const void *y, double z, double *out, void *ws,
                        ldk_stream stream);
 
+/* Test integrands of the RQMC estimate, functions of s = sum_j c_j x_j:
+ *   LDK_GENZ_CORNER_PEAK  (1 + s)^-(d+1)   (the Genz corner peak, the
+ *                                           integrand of the paper's RQMC
+ *                                           example in Sec. 6)
+ *   LDK_GENZ_OSCILLATORY  cos(2 pi u + s)  (the Genz oscillatory). */
+enum { LDK_GENZ_CORNER_PEAK = 0, LDK_GENZ_OSCILLATORY = 1 };
+
+/* Fields of ldk_rqmc's stats output. */
+enum { LDK_RQMC_MEAN = 0, LDK_RQMC_STD = 1, LDK_RQMC_HALF = 2, LDK_RQMC_FIELDS = 3 };
+
+/* RQMC estimate of int_[0,1]^d f over the R randomizations of a point set
+ * (eq. RQMC and the Student-t interval stated with it):
+ *   mu_r[r] = (1/n) sum_{i<n} f(x_ri)            (points 0 .. n-1 of
+ *                                                 replication r, as
+ *                                                 ldk_gen_points makes them)
+ *   stats[LDK_RQMC_MEAN] = mu = (1/R) sum_r mu_r
+ *   stats[LDK_RQMC_STD]  = sigma = sqrt(sum_r (mu_r - mu)^2 / (R - 1))
+ *                          (NaN when R = 1)
+ *   stats[LDK_RQMC_HALF] = t sigma / sqrt(R), t = the Student-t quantile
+ *                          t_{R-1, tau/2} of the 100(1 - tau)% interval
+ *                          mu +- HALF, passed in by the caller.
+ * The points are regenerated inside the kernel (never written to memory);
+ * coordinates are u 2^-64 rounded to the nearest double; every sum is FP64
+ * in a fixed order.  ps: any point set ldk_gen_points accepts (shifted
+ * lattice, LMS + digitally shifted net, per-replication interlaced columns);
+ * 1 <= n <= the limit of ldk_gen_points.  integrand: LDK_GENZ_*; coef =
+ * device double[d] (c_j); u: the oscillatory phase (ignored by the corner
+ * peak).  mu_r = device double[R]; stats = device double[LDK_RQMC_FIELDS].
+ * ws: ldk_rqmc_workspace_bytes(R, n) bytes. */
+int ldk_rqmc(const ldk_pointset *ps, int64_t n, int integrand, const double *coef, double u,
+             double t, double *mu_r, double *stats, void *ws, ldk_stream stream);
+size_t ldk_rqmc_workspace_bytes(int R, int64_t n);
+
 /* Orthonormal Walsh-Hadamard transform of B FP32 rows of n = 2^m (Sec. 5.3,
  * the recursion of H_m) on the matrix cores: each radix-16 stage is one
  * FP16 matrix instruction [H_16 | H_16] [X_hi ; X_lo] with FP32 sums, where

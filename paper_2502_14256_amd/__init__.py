@@ -27,6 +27,8 @@ GEN_PER_REPLICATION = 1
 (OP_TRANSFORM, OP_EIG, OP_SOLVE, OP_MATVEC, OP_LOGDET, OP_UPDATE_DOUBLE, OP_EIG_UPDATE_DOUBLE,
  OP_MLL, OP_MLL_ADJOINT, OP_FIT, OP_WCE, OP_BAYES_CUBATURE) = range(12)
 BC_FIELDS = ("mean", "var", "scale", "half", "weight", "wce2")
+GENZ_CORNER_PEAK, GENZ_OSCILLATORY = 0, 1
+RQMC_FIELDS = ("mean", "std", "half")
 
 EXPORTS = [
     "ldk_init", "ldk_gen_points", "ldk_kernel_column", "ldk_transform", "ldk_eig", "ldk_solve",
@@ -34,7 +36,7 @@ EXPORTS = [
     "ldk_workspace_bytes", "ldk_strerror", "ldk_last_hip_error", "ldk_version",
     "ldk_mll", "ldk_mll_adjoint", "ldk_kernel_grad", "ldk_kernel_grad_workspace_bytes",
     "ldk_fwht_split16", "ldk_fit", "ldk_points_column", "ldk_interlace", "ldk_wce",
-    "ldk_bayes_cubature",
+    "ldk_bayes_cubature", "ldk_rqmc", "ldk_rqmc_workspace_bytes",
 ]
 
 
@@ -72,6 +74,8 @@ def lib():
             "ldk_interlace": ([P, i32, P, P], i32),
             "ldk_wce": ([i32, i32, i32, i32, i32, P, f64, P, P, P, P], i32),
             "ldk_bayes_cubature": ([i32, i32, i32, i32, P, f64, f64, P, f64, P, P, P], i32),
+            "ldk_rqmc": ([P, i64, i32, P, f64, f64, P, P, P, P], i32),
+            "ldk_rqmc_workspace_bytes": ([i32, i64], C.c_size_t),
             "ldk_transform": ([i32, i32, i32, i32, i32, P, P, P, P], i32),
             "ldk_eig": ([i32, i32, i32, i32, P, P, P, P], i32),
             "ldk_solve": ([i32, i32, i32, i32, i32, P, f64, P, P, P, P], i32),
@@ -478,6 +482,35 @@ def bayes_cubature(kind, lam: torch.Tensor, sigma2: float, zeta: float, y: torch
                                     float(z), _ptr(out), _ptr(ws), _stream()),
            "ldk_bayes_cubature")
     return out
+
+
+def rqmc(ps: PointSet, n: int, integrand, coef: torch.Tensor, u: float = 0.0, tau: float = 0.01,
+         mu_r=None, stats=None, ws=None):
+    """RQMC estimate over the R randomizations of ps (ldk_rqmc): (mu_r [R],
+    stats [3] = mean, std, half width of the 100(1 - tau)% Student-t
+    interval).  integrand: "corner_peak" or "oscillatory" (or GENZ_*)."""
+    from scipy import stats as sst
+
+    f = {"corner_peak": GENZ_CORNER_PEAK, "oscillatory": GENZ_OSCILLATORY,
+         GENZ_CORNER_PEAK: GENZ_CORNER_PEAK, GENZ_OSCILLATORY: GENZ_OSCILLATORY}[integrand]
+    _need_f64(coef, "coef")
+    if coef.numel() != ps.d:
+        raise LdkError("coef must hold d values")
+    if not 0.0 < tau < 1.0:
+        raise LdkError("tau must lie in (0, 1)")
+    t = float(sst.t.ppf(1.0 - tau / 2.0, ps.R - 1)) if ps.R > 1 else 0.0
+    dev = ps.gen.device
+    mu_r = torch.empty(ps.R, dtype=torch.float64, device=dev) if mu_r is None else mu_r
+    stats = torch.empty(len(RQMC_FIELDS), dtype=torch.float64, device=dev) if stats is None \
+        else stats
+    _need_f64(mu_r, "mu_r")
+    _need_f64(stats, "stats")
+    if ws is None:
+        nbytes = int(lib().ldk_rqmc_workspace_bytes(ps.R, int(n)))
+        ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+    _check(lib().ldk_rqmc(C.byref(ps._c()), int(n), f, _ptr(coef), float(u), t, _ptr(mu_r),
+                          _ptr(stats), _ptr(ws), _stream()), "ldk_rqmc")
+    return mu_r, stats
 
 
 def mll_adjoint(kind, g: torch.Tensor, out=None, ws=None):

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libldk.so")
 SOURCES = ["core.hip", "points.hip", "kcol.hip", "kgrad.hip", "transform.hip", "realfft.hip",
-           "algebra.hip", "mll.hip", "fwht_mfma.hip"]
+           "algebra.hip", "mll.hip", "fwht_mfma.hip", "rqmc.hip"]
 HEADERS = ["common.hpp", "pointset.hpp", "transform.hpp", "passkit.hpp", "kfactor.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

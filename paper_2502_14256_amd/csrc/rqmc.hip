@@ -1,0 +1,248 @@
+// RQMC estimate over the R randomizations of a point set (eq. RQMC):
+//   mu_r = (1/n) sum_{i<n} f(x_ri),  mu = (1/R) sum_r mu_r,
+//   sigma^2 = sum_r (mu_r - mu)^2 / (R - 1),  half width t sigma / sqrt(R),
+// for two Genz test integrands of s = sum_j c_j x_j: the corner peak
+// (1 + s)^-(d+1) (the integrand of the paper's RQMC example) and the
+// oscillatory cos(2 pi u + s).  The points are regenerated in registers and
+// never written: a block takes KC_TILE consecutive indices of one
+// replication, accumulates s over the dimensions with the same point
+// recurrences as the regenerating kernel column (plus the randomization's
+// shift), applies the integrand and sums in FP64 in a fixed order.
+#include "kfactor.hpp"
+
+namespace ldk {
+
+namespace {
+
+constexpr int RQ_FINAL_THREADS = 256;
+
+__device__ __forceinline__ double wave_sum64(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Block sum (fixed order: lanes, then waves); the result is valid in thread 0.
+template <int THREADS>
+__device__ __forceinline__ double block_sum(double v, double *red)
+{
+    v = wave_sum64(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < THREADS / 64; ++w) s += red[w];
+    return s;
+}
+
+// s[l] += c_j x_j over every dimension for the lattice points
+// i = first + KC_THREADS l of replication r (tile-aligned first - t, so the
+// bit tricks of the regenerating column apply; the shift is added to the
+// base word before the points are split into high and low halves).
+template <int ORDER>
+__device__ __forceinline__ void lattice_dot(const PointsetArgs &ps, const double *__restrict__ coef,
+                                            int r, int64_t first, double (&s)[KC_ITERS])
+{
+    static_assert(KC_ITERS == 8 && KC_LOG_THREADS == 8, "offset table assumes 8 x 256");
+    constexpr uint64_t br3[8] = {0, 4, 2, 6, 1, 5, 3, 7};
+    const int d = ps.d, m = ps.m_max;
+    const uint64_t bfirst = ORDER == LDK_NATURAL ? brev64((uint64_t)first) : (uint64_t)first;
+    for (int j = 0; j < d; ++j) {
+        const uint64_t g = ps.gen[j];
+        const uint64_t sh = ps.shift ? ps.shift[(size_t)r * d + j] : 0;
+        const double c = coef[j];
+        uint64_t base, G;
+        if constexpr (ORDER == LDK_NATURAL) {
+            base = bfirst * g + sh;
+            G = g << 53;
+        } else {
+            base = (m == 0 ? 0 : ((bfirst * g) << (64 - m))) + sh;
+            G = m <= 8 ? 0 : ((g << 8) << (64 - m));
+        }
+        const double lo_p = lo_part<double>((uint32_t)base);
+#pragma unroll
+        for (int l = 0; l < KC_ITERS; ++l) {
+            double x;
+            if constexpr (ORDER == LDK_NATURAL)
+                x = unit_hl<double>((uint32_t)(base >> 32) + (uint32_t)br3[l] * (uint32_t)(G >> 32),
+                                    lo_p);
+            else
+                x = unit<double>(base + (uint64_t)l * G);
+            s[l] = fma(c, x, s[l]);
+        }
+    }
+}
+
+// The same for net points: scrambled columns and XOR steps from the LDS
+// tables of the regenerating column, then the digital shift.
+__device__ __forceinline__ void net_dot(const KcolArgs &a, NetLds &L, const double *__restrict__ coef,
+                                        int r, int64_t tile0, double (&s)[KC_ITERS])
+{
+    constexpr int sft = KC_LOG_THREADS;
+    const int d = a.ps.d, t = threadIdx.x;
+    const bool gray = a.ps.order == LDK_GRAY;
+    const uint64_t code_tile = gray ? gray_code((uint64_t)tile0) : (uint64_t)tile0;
+    const uint32_t code_t = gray ? (uint32_t)gray_code((uint64_t)t) : (uint32_t)t;
+    for (int jc = 0; jc < d; jc += KC_DIM_CHUNK) {
+        const int DB = min(KC_DIM_CHUNK, d - jc);
+        build_net_chunk(a, L, r, jc, DB, code_tile);
+        for (int jj = 0; jj < DB; ++jj) {
+            const int j = jc + jj;
+            const uint64_t sh = a.ps.shift ? a.ps.shift[(size_t)r * d + j] : 0;
+            const double c = coef[j];
+            uint64_t z = L.zb[jj] ^ L.nib[jj][0][code_t & 15] ^ L.nib[jj][1][(code_t >> 4) & 15];
+#pragma unroll
+            for (int l = 0; l < KC_ITERS; ++l) {
+                s[l] = fma(c, unit<double>(z ^ sh), s[l]);
+                // past the last index of the net the step columns are zero
+                // (such points are masked by the caller)
+                const uint64_t nb = ((uint64_t)tile0 >> sft) + (uint64_t)l + 1;
+                if (l + 1 < KC_ITERS) z ^= L.step[jj][ctz64(nb)];
+            }
+        }
+    }
+}
+
+template <int F>
+__device__ __forceinline__ double integrand(double s, int d, double phase)
+{
+    if constexpr (F == LDK_GENZ_CORNER_PEAK)
+        return pow(1.0 + s, -(double)(d + 1));
+    else
+        return cos(phase + s);
+}
+
+// One block per (tile of KC_TILE indices, replication): partial sums of f.
+template <int KIND, int ORDER, int F>
+__global__ __launch_bounds__(KC_THREADS) void k_rqmc_tiles(KcolArgs a, const double *__restrict__ coef,
+                                                           double phase, int64_t n,
+                                                           double *__restrict__ part)
+{
+    __shared__ double red[KC_THREADS / 64];
+    const int r = blockIdx.y;
+    const int64_t tile0 = (int64_t)blockIdx.x * KC_TILE;
+    const int64_t first = tile0 + threadIdx.x;
+    double s[KC_ITERS];
+#pragma unroll
+    for (int l = 0; l < KC_ITERS; ++l) s[l] = 0.0;
+    if constexpr (KIND == LDK_DNET_B2) {
+        __shared__ NetLds L;
+        net_dot(a, L, coef, r, tile0, s);
+    } else {
+        lattice_dot<ORDER>(a.ps, coef, r, first, s);
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int l = 0; l < KC_ITERS; ++l)
+        if (first + (int64_t)l * KC_THREADS < n) acc += integrand<F>(s[l], a.ps.d, phase);
+    const double tot = block_sum<KC_THREADS>(acc, red);
+    if (threadIdx.x == 0) part[(size_t)r * gridDim.x + blockIdx.x] = tot;
+}
+
+// mu_r per replication from its tile sums.
+__global__ __launch_bounds__(RQ_FINAL_THREADS) void k_rqmc_means(const double *__restrict__ part,
+                                                                 int tiles, double n,
+                                                                 double *__restrict__ mu_r)
+{
+    __shared__ double red[RQ_FINAL_THREADS / 64];
+    const int r = blockIdx.x;
+    double acc = 0.0;
+    for (int c = threadIdx.x; c < tiles; c += RQ_FINAL_THREADS) acc += part[(size_t)r * tiles + c];
+    const double tot = block_sum<RQ_FINAL_THREADS>(acc, red);
+    if (threadIdx.x == 0) mu_r[r] = tot / n;
+}
+
+// mu, sigma (R >= 2, else NaN) and the half width t sigma / sqrt(R).
+__global__ __launch_bounds__(RQ_FINAL_THREADS) void k_rqmc_stats(const double *__restrict__ mu_r,
+                                                                 int R, double t,
+                                                                 double *__restrict__ stats)
+{
+    __shared__ double red[RQ_FINAL_THREADS / 64];
+    __shared__ double mean_s;
+    double acc = 0.0;
+    for (int r = threadIdx.x; r < R; r += RQ_FINAL_THREADS) acc += mu_r[r];
+    const double tot = block_sum<RQ_FINAL_THREADS>(acc, red);
+    if (threadIdx.x == 0) mean_s = tot / (double)R;
+    __syncthreads();
+    const double mu = mean_s;
+    double sq = 0.0;
+    for (int r = threadIdx.x; r < R; r += RQ_FINAL_THREADS) {
+        const double e = mu_r[r] - mu;
+        sq = fma(e, e, sq);
+    }
+    const double ss = block_sum<RQ_FINAL_THREADS>(sq, red);
+    if (threadIdx.x == 0) {
+        const double sigma = R > 1 ? sqrt(ss / (double)(R - 1)) : __builtin_nan("");
+        stats[LDK_RQMC_MEAN] = mu;
+        stats[LDK_RQMC_STD] = sigma;
+        stats[LDK_RQMC_HALF] = t * sigma / sqrt((double)R);
+    }
+}
+
+int64_t tiles_of(int64_t n) { return (n + KC_TILE - 1) / KC_TILE; }
+
+template <int F>
+void launch_tiles(const KcolArgs &a, const double *coef, double phase, int64_t n, dim3 grid,
+                  hipStream_t s, double *part)
+{
+    if (a.ps.kind == LDK_DNET_B2)
+        hipLaunchKernelGGL((k_rqmc_tiles<LDK_DNET_B2, LDK_NATURAL, F>), grid, dim3(KC_THREADS), 0, s,
+                           a, coef, phase, n, part);
+    else if (a.ps.order == LDK_LINEAR)
+        hipLaunchKernelGGL((k_rqmc_tiles<LDK_LATTICE, LDK_LINEAR, F>), grid, dim3(KC_THREADS), 0, s,
+                           a, coef, phase, n, part);
+    else
+        hipLaunchKernelGGL((k_rqmc_tiles<LDK_LATTICE, LDK_NATURAL, F>), grid, dim3(KC_THREADS), 0,
+                           s, a, coef, phase, n, part);
+}
+
+}  // namespace
+
+}  // namespace ldk
+
+using namespace ldk;
+
+extern "C" size_t ldk_rqmc_workspace_bytes(int R, int64_t n)
+{
+    if (R < 0 || n < 0) return 0;
+    return (size_t)R * (size_t)tiles_of(n) * sizeof(double);
+}
+
+extern "C" int ldk_rqmc(const ldk_pointset *ps, int64_t n, int integrand, const double *coef,
+                        double u, double t, double *mu_r, double *stats, void *ws,
+                        ldk_stream stream)
+{
+    KcolArgs a{};
+    int st = validate_pointset(ps, &a.ps);
+    if (st) return st;
+    if (integrand != LDK_GENZ_CORNER_PEAK && integrand != LDK_GENZ_OSCILLATORY) return LDK_EINVAL;
+    if (!(u >= -1.0e6 && u <= 1.0e6) || !(t >= 0.0 && t <= 1.0e300)) return LDK_EINVAL;
+    const int64_t lim = (a.ps.kind == LDK_LATTICE && a.ps.order == LDK_NATURAL)
+                            ? ((int64_t)1 << 62)
+                            : ((int64_t)1 << a.ps.m_max);
+    if (n < 1 || n > lim) return LDK_EINVAL;
+    if (!coef || !mu_r || !stats || !ws) return LDK_EINVAL;
+    const int64_t tiles = tiles_of(n);
+    if (tiles > 0x7fffffff) return LDK_ENOTSUP;
+    st = ensure_init();
+    if (st) return st;
+    a.n_min = 0;
+    a.n_max = n;
+    hipStream_t s = as_stream(stream);
+    double *part = static_cast<double *>(ws);
+    const dim3 grid((unsigned)tiles, (unsigned)a.ps.R);
+    const double phase = 6.283185307179586476925286766559 * u;
+    if (integrand == LDK_GENZ_CORNER_PEAK)
+        launch_tiles<LDK_GENZ_CORNER_PEAK>(a, coef, phase, n, grid, s, part);
+    else
+        launch_tiles<LDK_GENZ_OSCILLATORY>(a, coef, phase, n, grid, s, part);
+    LDK_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_rqmc_means, dim3((unsigned)a.ps.R), dim3(RQ_FINAL_THREADS), 0, s,
+                       (const double *)part, (int)tiles, (double)n, mu_r);
+    LDK_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_rqmc_stats, dim3(1), dim3(RQ_FINAL_THREADS), 0, s, (const double *)mu_r,
+                       a.ps.R, t, stats);
+    LDK_LAUNCH_CHECK();
+    return LDK_OK;
+}

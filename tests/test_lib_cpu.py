@@ -268,3 +268,25 @@ def test_cubature_workspace_sizes():
     assert ws(ldk.OP_BAYES_CUBATURE, ldk.LATTICE, 2, 20, 1) == (2 * 512 * 2 * 8 + 2 * 2**20 * 8
                                                               + 2 * 2**19 * 8)
     assert ws(ldk.OP_BAYES_CUBATURE, ldk.LATTICE, 3, 0, 0) == 256 + 256
+
+
+def test_rqmc_rejects_bad_arguments():
+    L = ldk.lib()
+    f = L.ldk_rqmc
+    P, CP, OSC = C.byref, ldk.GENZ_CORNER_PEAK, ldk.GENZ_OSCILLATORY
+    # ldk_rqmc(ps, n, integrand, coef, u, t, mu_r, stats, ws, stream)
+    assert f(P(_ps(R=0)), 16, CP, FAKE, 0.0, 2.0, FAKE, FAKE, FAKE, None) == -1
+    assert f(P(_ps()), 16, 2, FAKE, 0.0, 2.0, FAKE, FAKE, FAKE, None) == -1       # integrand
+    assert f(P(_ps()), 0, CP, FAKE, 0.0, 2.0, FAKE, FAKE, FAKE, None) == -1       # n >= 1
+    assert f(P(_ps()), 2**10 + 1, CP, FAKE, 0.0, 2.0, FAKE, FAKE, FAKE, None) == -1  # > 2^m
+    assert f(P(_ps()), 16, OSC, FAKE, float("nan"), 2.0, FAKE, FAKE, FAKE, None) == -1
+    assert f(P(_ps()), 16, CP, FAKE, 0.0, -1.0, FAKE, FAKE, FAKE, None) == -1     # t >= 0
+    assert f(P(_ps()), 16, CP, None, 0.0, 2.0, FAKE, FAKE, FAKE, None) == -1      # coef
+    assert f(P(_ps()), 16, CP, FAKE, 0.0, 2.0, None, FAKE, FAKE, None) == -1      # mu_r
+    assert f(P(_ps()), 16, CP, FAKE, 0.0, 2.0, FAKE, None, FAKE, None) == -1      # stats
+    assert f(P(_ps()), 16, CP, FAKE, 0.0, 2.0, FAKE, FAKE, None, None) == -1      # ws
+    assert f(None, 16, CP, FAKE, 0.0, 2.0, FAKE, FAKE, FAKE, None) == -1
+    # tile sums: R x ceil(n / 2048) doubles
+    assert L.ldk_rqmc_workspace_bytes(10, 2**15) == 10 * 16 * 8
+    assert L.ldk_rqmc_workspace_bytes(3, 2049) == 3 * 2 * 8
+    assert L.ldk_rqmc_workspace_bytes(3, 0) == 0
