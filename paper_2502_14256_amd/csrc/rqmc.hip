@@ -14,7 +14,7 @@ namespace ldk {
 
 namespace {
 
-constexpr int RQ_FINAL_THREADS = 256;
+constexpr int RQ_FINAL_THREADS = 1024;
 
 __device__ __forceinline__ double wave_sum64(double v)
 {
@@ -140,26 +140,26 @@ __global__ __launch_bounds__(KC_THREADS) void k_rqmc_tiles(KcolArgs a, const dou
     if (threadIdx.x == 0) part[(size_t)r * gridDim.x + blockIdx.x] = tot;
 }
 
-// mu_r per replication from its tile sums.
-__global__ __launch_bounds__(RQ_FINAL_THREADS) void k_rqmc_means(const double *__restrict__ part,
-                                                                 int tiles, double n,
-                                                                 double *__restrict__ mu_r)
-{
-    __shared__ double red[RQ_FINAL_THREADS / 64];
-    const int r = blockIdx.x;
-    double acc = 0.0;
-    for (int c = threadIdx.x; c < tiles; c += RQ_FINAL_THREADS) acc += part[(size_t)r * tiles + c];
-    const double tot = block_sum<RQ_FINAL_THREADS>(acc, red);
-    if (threadIdx.x == 0) mu_r[r] = tot / n;
-}
-
-// mu, sigma (R >= 2, else NaN) and the half width t sigma / sqrt(R).
-__global__ __launch_bounds__(RQ_FINAL_THREADS) void k_rqmc_stats(const double *__restrict__ mu_r,
-                                                                 int R, double t,
+// One block: wave w forms mu_r for r = w, w + waves, ... from its tile
+// sums (lanes stride over the tiles, then a fixed-order wave sum); after the
+// barrier the block forms mu, sigma (R >= 2, else NaN) and t sigma / sqrt(R).
+__global__ __launch_bounds__(RQ_FINAL_THREADS) void k_rqmc_final(const double *__restrict__ part,
+                                                                 int tiles, int R, double n,
+                                                                 double t,
+                                                                 double *__restrict__ mu_r,
                                                                  double *__restrict__ stats)
 {
     __shared__ double red[RQ_FINAL_THREADS / 64];
     __shared__ double mean_s;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int WAVES = RQ_FINAL_THREADS / 64;
+    for (int r = wave; r < R; r += WAVES) {
+        double acc = 0.0;
+        for (int c = lane; c < tiles; c += 64) acc += part[(size_t)r * tiles + c];
+        acc = wave_sum64(acc);
+        if (lane == 0) mu_r[r] = acc / n;
+    }
+    __syncthreads();  // the block's own writes of mu_r are visible to it now
     double acc = 0.0;
     for (int r = threadIdx.x; r < R; r += RQ_FINAL_THREADS) acc += mu_r[r];
     const double tot = block_sum<RQ_FINAL_THREADS>(acc, red);
@@ -238,11 +238,8 @@ extern "C" int ldk_rqmc(const ldk_pointset *ps, int64_t n, int integrand, const 
     else
         launch_tiles<LDK_GENZ_OSCILLATORY>(a, coef, phase, n, grid, s, part);
     LDK_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_rqmc_means, dim3((unsigned)a.ps.R), dim3(RQ_FINAL_THREADS), 0, s,
-                       (const double *)part, (int)tiles, (double)n, mu_r);
-    LDK_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_rqmc_stats, dim3(1), dim3(RQ_FINAL_THREADS), 0, s, (const double *)mu_r,
-                       a.ps.R, t, stats);
+    hipLaunchKernelGGL(k_rqmc_final, dim3(1), dim3(RQ_FINAL_THREADS), 0, s, (const double *)part,
+                       (int)tiles, a.ps.R, (double)n, t, mu_r, stats);
     LDK_LAUNCH_CHECK();
     return LDK_OK;
 }
