@@ -73,3 +73,51 @@ def test_graph_replays_match_eager(kind, branches):
         torch.cuda.synchronize()
         for a, b in zip((pts, k1, lam, c, ld), ref):
             assert torch.equal(a, b), rep
+
+
+@pytest.mark.parametrize("kind", ["lattice", "dnet"])
+def test_graph_replays_cubature_and_rqmc(kind):
+    # the cubature and RQMC entry points captured in one graph: every replay,
+    # with eager writes between replays, equals the eager result bit for bit
+    ldk.init()
+    m, d, R, nw = 14, 6, 3, 4
+    w = W.small_lattice(5, m=m, d=d, R=R) if kind == "lattice" else W.small_net(5, m=m, d=d, R=R)
+    w.update(alpha=np.full(d, 2, np.int32), gamma=0.5 ** np.arange(d), zeta=1.2)
+    ps, k = pointset(w), kernel(w)
+    n = 2**m
+    y = torch.from_numpy(w["y"][:, 0, :]).cuda()
+    k1 = ldk.kernel_column(k, ps, 0, n)
+    lam = ldk.eig(kind, k1)
+    om = torch.from_numpy(W.cubature_weights(6, R, nw, n)).cuda()
+    coef = torch.from_numpy(W.corner_peak_coefficients(d)).cuda()
+    kd = ldk._kind(kind)
+    e2 = torch.empty((R, nw), dtype=torch.float64, device="cuda")
+    bc = torch.empty((R, len(ldk.BC_FIELDS)), dtype=torch.float64, device="cuda")
+    mu_r = torch.empty(R, dtype=torch.float64, device="cuda")
+    st = torch.empty(3, dtype=torch.float64, device="cuda")
+    ws_w = ldk._workspace(ldk.OP_WCE, kd, R * nw, m, ldk.F64, "cuda")
+    ws_b = ldk._workspace(ldk.OP_BAYES_CUBATURE, kd, R, m, ldk.F64, "cuda")
+    ws_q = torch.empty(int(ldk.lib().ldk_rqmc_workspace_bytes(R, n)), dtype=torch.uint8,
+                       device="cuda")
+
+    def step():
+        ldk.wce(kind, lam, om, 1.2, out=e2, ws=ws_w)
+        ldk.bayes_cubature(kind, lam, 1e-3, 1.2, y, out=bc, ws=ws_b)
+        ldk.rqmc(ps, n, "corner_peak", coef, mu_r=mu_r, stats=st, ws=ws_q)
+
+    step()
+    torch.cuda.synchronize()
+    outs = (e2, bc, mu_r, st)
+    ref = [t.clone() for t in outs]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    for rep in range(4):
+        for t in outs:
+            t.fill_(-1)
+        ws_w.fill_(7)  # stale workspace contents must not leak into results
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(outs, ref):
+            assert torch.equal(a, b), rep
