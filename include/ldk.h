@@ -301,8 +301,8 @@ size_t ldk_kernel_grad_workspace_bytes(int R, int d, int64_t n_min, int64_t n_ma
  * and the double integral both equal zeta; wt = FT(w_rq) orthonormal
  * (Sec. 5.4), so the quadratic form costs one transform.
  * lam = double[R][n] (ldk_eig); w = dtype[R][nw][n] in the point order of
- * lam; e2 = device double[R][nw].  The transform of w runs in dtype, the
- * sums in FP64 in a fixed order.  e2 is a difference of terms of size zeta:
+ * lam; e2 = device double[R][nw].  The transform of w runs in dtype (sum_i
+ * w_i is its zero frequency), the weighted sums in FP64 in a fixed order.  e2 is a difference of terms of size zeta:
  * its error is absolute, of order (m + 2) u (zeta + 2 zeta sum_i |w_i| +
  * sum_k |lambda_k| |wt_k|^2), u the unit roundoff of dtype.
  * R * nw <= 65535.  ws: ldk_workspace_bytes(LDK_OP_WCE, kind, R * nw, m, dtype). */
@@ -338,8 +338,8 @@ enum {
  *   WCE2   = zeta - 2 n zeta WEIGHT + n WEIGHT^2 lambda_0 (equals VAR at
  *            sigma2 = 0).
  * lam = double[R][n] (ldk_eig); y = dtype[R][n]; out = device
- * double[R][LDK_BC_FIELDS].  The transform of y runs in dtype, the rest in
- * FP64.  VAR and WCE2 carry the absolute rounding of lambda_0 (about
+ * double[R][LDK_BC_FIELDS].  The transform of y runs in dtype (sum_i y_i is
+ * its zero frequency), the rest in FP64.  VAR and WCE2 carry the absolute rounding of lambda_0 (about
  * (m + 1) u sum_i |k1_i| / n relative to zeta).  A replication with some
  * lambda_k + sigma2 <= 0 gets SCALE = HALF = NaN.
  * ws: ldk_workspace_bytes(LDK_OP_BAYES_CUBATURE, kind, R, m, dtype) bytes. */

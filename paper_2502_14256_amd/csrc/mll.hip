@@ -198,6 +198,37 @@ int power_spectrum(int kind, int R, int m, int dtype, const void *y, double *pw,
     return LDK_OK;
 }
 
+// Per-row outputs from q = sum_k w_k |W_k|^2 (unnormalised spectrum; w_k =
+// lambda_k for the worst-case error, 1 / (lambda_k + s2) for the posterior)
+// and s1 = sum_i of the row.
+template <bool BC>
+__device__ __forceinline__ void cub_row_out(int row, double q, double s1, int64_t n,
+                                                 const double *__restrict__ lam, double sigma2,
+                                                 double zeta, double z, double *__restrict__ out)
+{
+    const double nd = (double)n;
+    if constexpr (!BC) {
+        // zeta - 2 zeta sum w + w^T K w
+        out[row] = fma(-2.0 * zeta, s1, zeta) + q / nd;
+    } else {
+        const double l0 = lam[(size_t)row * n];
+        const double s = l0 + sigma2;
+        const double t = s - nd * zeta;  // lambda_0 + s2 - n zeta
+        const double wgt = zeta / s;
+        const double var = zeta * t / s;
+        const double scale = q / (nd * nd);
+        double *o = out + (size_t)row * LDK_BC_FIELDS;
+        o[LDK_BC_MEAN] = wgt * s1;
+        o[LDK_BC_VAR] = var;
+        o[LDK_BC_SCALE] = scale;
+        const double sv = scale * var;  // NaN stays NaN; rounding below zero gives 0
+        o[LDK_BC_HALF] = z * sqrt(sv < 0.0 ? 0.0 : sv);
+        o[LDK_BC_WEIGHT] = wgt;
+        // zeta - 2 n zeta wgt + n wgt^2 lambda_0 = zeta (t^2 + n zeta (t - s2)) / s^2
+        o[LDK_BC_WCE2] = zeta * fma(t, t, nd * zeta * (t - sigma2)) / (s * s);
+    }
+}
+
 // Cubature partial sums per (row, chunk), rows = R * nw, lambda row = row / nw:
 //   BC = false: [0] sum_k lambda_k p_k,        [1] sum_i w_i
 //   BC = true:  [0] sum_k p_k / (lambda_k + s2) (NaN when some
@@ -250,27 +281,27 @@ __global__ __launch_bounds__(MLL_THREADS) void k_cub_final(const double *__restr
         for (int q = 0; q < 2; ++q) acc[q] += part[((size_t)row * chunks + c) * 2 + q];
     block_sum3(acc, red);
     if (threadIdx.x != 0) return;
-    const double nd = (double)n;
-    if constexpr (!BC) {
-        // zeta - 2 zeta sum w + w^T K w, the power spectrum being unnormalised
-        out[row] = fma(-2.0 * zeta, acc[1], zeta) + acc[0] / nd;
-    } else {
-        const double l0 = lam[(size_t)row * n];
-        const double s = l0 + sigma2;
-        const double t = s - nd * zeta;  // lambda_0 + s2 - n zeta
-        const double wgt = zeta / s;
-        const double var = zeta * t / s;
-        const double scale = acc[0] / (nd * nd);
-        double *o = out + (size_t)row * LDK_BC_FIELDS;
-        o[LDK_BC_MEAN] = wgt * acc[1];
-        o[LDK_BC_VAR] = var;
-        o[LDK_BC_SCALE] = scale;
-        const double sv = scale * var;  // NaN stays NaN; rounding below zero gives 0
-        o[LDK_BC_HALF] = z * sqrt(sv < 0.0 ? 0.0 : sv);
-        o[LDK_BC_WEIGHT] = wgt;
-        // zeta - 2 n zeta wgt + n wgt^2 lambda_0 = zeta (t^2 + n zeta (t - s2)) / s^2
-        o[LDK_BC_WCE2] = zeta * fma(t, t, nd * zeta * (t - sigma2)) / (s * s);
-    }
+    cub_row_out<BC>(row, acc[0], acc[1], n, lam, sigma2, zeta, z, out);
+}
+
+// The fused lattice path: the top pass left the weighted sum of |W_k|^2 per
+// tile (qpart[row][tiles]) and the row sums W_0 (y0[row]).
+template <bool BC>
+__global__ __launch_bounds__(MLL_THREADS) void k_cub_final_q(const double *__restrict__ qpart,
+                                                             int tiles,
+                                                             const double *__restrict__ y0,
+                                                             int64_t n,
+                                                             const double *__restrict__ lam,
+                                                             double sigma2, double zeta, double z,
+                                                             double *__restrict__ out)
+{
+    __shared__ double red[MLL_THREADS / 64][3];
+    const int row = blockIdx.x;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int c = threadIdx.x; c < tiles; c += MLL_THREADS) acc[0] += qpart[(size_t)row * tiles + c];
+    block_sum3(acc, red);
+    if (threadIdx.x != 0) return;
+    cub_row_out<BC>(row, acc[0], y0[row], n, lam, sigma2, zeta, z, out);
 }
 
 }  // namespace
@@ -410,6 +441,50 @@ int cubature(int kind, int R, int nw, int m, int dtype, const double *lam, doubl
     double *pw = reinterpret_cast<double *>(static_cast<unsigned char *>(ws) +
                                             align256((size_t)rows * chunks * 2 * sizeof(double)));
     void *tmp = reinterpret_cast<unsigned char *>(pw) + align256((size_t)rows * n * sizeof(double));
+    if (real_lattice(kind, m)) {
+        // packed half-length rows; the real top pass forms the weighted sums
+        // itself (PM_QFORM), so the spectrum is never written.  Its tile sums
+        // and the row sums use the partial-sum region of the workspace.
+        const int mp = m - 1;
+        const int64_t N = n / 2;
+        const Plan pl = make_plan(mp, log_tile_for(LDK_LATTICE, dtype));
+        const PassGeom top = pl.pass[pl.P - 1];
+        const int64_t tiles = (int64_t)1 << (top.b0 - top.logW);
+        if ((tiles + 1) > 2 * (int64_t)chunks) return LDK_ENOTSUP;  // region too small
+        double *qpart = part;
+        double *y0 = part + (size_t)rows * tiles;
+        PassArgs a{};
+        a.rows = rows;
+        a.nrhs = nw;  // lambda row = row / nw
+        a.m = mp;
+        a.half = N;
+        a.scale = 1.0;
+        for (int p = 0; p < pl.P - 1; ++p) {
+            a.src = p == 0 ? w : tmp;
+            a.src_row = p == 0 ? n : N;
+            a.dst = tmp;
+            a.dst_row = N;
+            a.g = pl.pass[p];
+            a.global_tw = p > 0;
+            const int st = launch_pass(LDK_LATTICE, dtype, PM_FWD, p == 0 ? PIO_PACKED : PIO_SAME,
+                                       PIO_SAME, a, s);
+            if (st) return st;
+        }
+        a.src = pl.P == 1 ? w : tmp;
+        a.src_row = pl.P == 1 ? n : N;
+        a.g = top;
+        a.global_tw = pl.P > 1;
+        a.lam = lam;
+        a.sigma2 = sigma2;
+        a.qform_lam = BC ? 0 : 1;
+        int st = launch_real_top(dtype, PM_QFORM, a, y0, s, false, qpart);
+        if (st) return st;
+        hipLaunchKernelGGL(k_cub_final_q<BC>, dim3(rows), dim3(MLL_THREADS), 0, s,
+                           (const double *)qpart, (int)tiles, (const double *)y0, n, lam, sigma2,
+                           zeta, z, out);
+        LDK_LAUNCH_CHECK();
+        return LDK_OK;
+    }
     int st = power_spectrum(kind, rows, m, dtype, w, pw, tmp, s);
     if (st) return st;
     if (dtype == LDK_F64)

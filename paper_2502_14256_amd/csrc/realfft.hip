@@ -33,7 +33,10 @@
 // power spectrum, FP64) instead of Re Y_k, and PM_ADJ is the inverse half
 // alone: it reads a real spectrum g from a.lam, forms C = scale (g_k +
 // g_{n-k}) / 2 (so the result is Re sum_k g_k W_n^{-k R(j)} for scale 2),
-// re-packs it like the solve and runs the inverse top group.
+// re-packs it like the solve and runs the inverse top group.  PM_QFORM serves
+// the cubature: it weights |Y_k|^2 by lambda_k or 1 / (lambda_k + sigma2)
+// and sums the tile (into ld_part[row][cb]) instead of storing the spectrum,
+// and the tile holding k = 0 stores Y_0 = sum_j y_j (into lam_out[row]).
 #include "passkit.hpp"
 
 namespace ldk {
@@ -117,6 +120,17 @@ __device__ __forceinline__ void real_top_body(const PassArgs &a, double *lam_out
                 f2[i] = 0.5 * a.scale * (lc + ld);
             }
         }
+        if constexpr (MODE == PM_QFORM) {
+            const double la = lam[k], lc = lam[k + N];
+            if (a.qform_lam) {
+                f1[i] = la;
+                f2[i] = lc;
+            } else {
+                const double pa = la + a.sigma2, pc = lc + a.sigma2;
+                f1[i] = pa > 0.0 ? 1.0 / pa : __builtin_nan("");
+                f2[i] = pc > 0.0 ? 1.0 / pc : __builtin_nan("");
+            }
+        }
     }
 
     if constexpr (MODE != PM_ADJ) {
@@ -146,7 +160,8 @@ __device__ __forceinline__ void real_top_body(const PassArgs &a, double *lam_out
         lds_write(v, lds, t, LOGE, logW + top_s, Tn);
         __syncthreads();
     }
-    LogProd lsum;  // PM_FWD with ld_part: sum of log(lambda + s2)
+    LogProd lsum;       // PM_FWD with ld_part: sum of log(lambda + s2)
+    double qacc = 0.0;  // PM_QFORM: weighted sum of |Y|^2
 #pragma unroll
     for (int i = 0; i < E; ++i) {
         const int q = t + Tn * i;
@@ -201,6 +216,12 @@ __device__ __forceinline__ void real_top_body(const PassArgs &a, double *lam_out
             lam_out[row * n + k] = (double)yk.re * (double)yk.re + (double)yk.im * (double)yk.im;
             lam_out[row * n + k + N] =
                 (double)ykn.re * (double)ykn.re + (double)ykn.im * (double)ykn.im;
+        } else if constexpr (MODE == PM_QFORM) {
+            const double p1 = (double)yk.re * (double)yk.re + (double)yk.im * (double)yk.im;
+            const double p2 = (double)ykn.re * (double)ykn.re + (double)ykn.im * (double)ykn.im;
+            qacc = fma(f1[i], p1, qacc);
+            qacc = fma(f2[i], p2, qacc);
+            if (k == 0) lam_out[row] = (double)yk.re;  // Y_0: the row's sum
         }
     }
     if constexpr (MODE == PM_FWD) {
@@ -221,6 +242,26 @@ __device__ __forceinline__ void real_top_body(const PassArgs &a, double *lam_out
         return;
     }
     if constexpr (MODE == PM_POWER) return;
+    if constexpr (MODE == PM_QFORM) {
+        // block sum in a fixed order: lanes, then waves (a block of fewer
+        // than 64 threads sums its threads through LDS)
+        __shared__ double qred[64];
+        if (Tn >= 64) {
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) qacc += __shfl_xor(qacc, o, 64);
+            if ((t & 63) == 0) qred[t >> 6] = qacc;
+        } else {
+            qred[t] = qacc;
+        }
+        __syncthreads();
+        if (t == 0) {
+            double sum = 0.0;
+            const int terms = Tn >= 64 ? Tn / 64 : Tn;
+            for (int w8 = 0; w8 < terms; ++w8) sum += qred[w8];
+            ld_part[row * cb_count + cb] = sum;
+        }
+        return;
+    }
 
     // ---- inverse transform over the axis bits (top group first)
     reg_inv<T, E, LOGE>(v, LOGE);
@@ -560,6 +601,16 @@ int launch_real_top(int dtype, int mode, const PassArgs &a, double *lam_out, hip
             return launch_rt_e<cplx<double>, PM_FWD, IO_PACKED, IO_SAME, false>(a, lam_out, s,
                                                                                  ld_part);
         return launch_rt_e<cplx<double>, PM_FWD, IO_SAME, IO_SAME, false>(a, lam_out, s, ld_part);
+    }
+    if (mode == PM_QFORM) {
+        // cubature quadratic forms: tile sums into ld_part, row sums into lam_out
+        if (!lam_out || !ld_part || !a.lam || src_f32) return LDK_EINVAL;
+        if (dtype == LDK_F64) {
+            if (single) return launch_rt_e<cplx<double>, PM_QFORM, IO_PACKED, IO_SAME, false>(a, lam_out, s, ld_part);
+            return launch_rt_e<cplx<double>, PM_QFORM, IO_SAME, IO_SAME, false>(a, lam_out, s, ld_part);
+        }
+        if (single) return launch_rt_e<cplx<float>, PM_QFORM, IO_PACKED, IO_SAME, false>(a, lam_out, s, ld_part);
+        return launch_rt_e<cplx<float>, PM_QFORM, IO_SAME, IO_SAME, false>(a, lam_out, s, ld_part);
     }
     if (ld_part) return LDK_EINVAL;  // log-det partials come with the eigenvalues only
     if (src_f32) return LDK_EINVAL;

@@ -21,8 +21,16 @@
 
 namespace ldk {
 
-// PM_POWER and PM_ADJ exist only in the real-input lattice top pass.
-enum PassMode { PM_FWD = 0, PM_INV = 1, PM_SOLVE = 2, PM_MATVEC = 3, PM_POWER = 4, PM_ADJ = 5 };
+// PM_POWER, PM_ADJ and PM_QFORM exist only in the real-input lattice top pass.
+enum PassMode {
+    PM_FWD = 0,
+    PM_INV = 1,
+    PM_SOLVE = 2,
+    PM_MATVEC = 3,
+    PM_POWER = 4,
+    PM_ADJ = 5,
+    PM_QFORM = 6
+};
 
 struct PassGeom {
     int b0;    // index bit where this pass's axis starts
@@ -63,6 +71,8 @@ struct PassArgs {
     double *ld_out;
     int64_t ld_rows;
     int64_t ld_count;
+    // PM_QFORM only: weights lambda_k (1) or 1 / (lambda_k + sigma2) (0)
+    int qform_lam;
 };
 
 // Global IO of a pass (lattice only; nets are always real):

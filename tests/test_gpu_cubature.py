@@ -86,8 +86,9 @@ def _bc_check(orc, kind, lam, y, sigma2, zeta, m, dtype, name):
     tol_c = solve_tol(lam, sigma2, y64, c_ref, m, u)
     cn = np.linalg.norm(c_ref, axis=-1)
     errs = {}
-    # mean: zeta sum_i c_i there, zeta sum_i y_i / (lambda_0 + s2) here
-    tol = abs(zeta) * (math.sqrt(n) * cn * tol_c + 8 * (m + 2) * u * np.abs(y64).sum(-1)
+    # mean: zeta sum_i c_i there, zeta sum_i y_i / (lambda_0 + s2) here, the
+    # sum taken in the transform's dtype (the zero frequency)
+    tol = abs(zeta) * (math.sqrt(n) * cn * tol_c + 8 * (m + 2) * eps * np.abs(y64).sum(-1)
                        / (lam[:, 0] + sigma2))
     errs["mean"] = np.max(np.abs(f["mean"] - ref["mean"]) / tol)
     # var, weight, wce2 need only lambda_0 here; the oracle solves for the
