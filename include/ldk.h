@@ -293,7 +293,7 @@ size_t ldk_kernel_grad_workspace_bytes(int R, int d, int64_t n_min, int64_t n_ma
 
 /* Squared worst-case error of nw cubature rules sum_i w_i f(x_i) per
  * replication, over the unit ball of the RKHS of the product kernel of
- * ldk_kernel_column (Sec. kernel computations):
+ * ldk_kernel_column (Sec. 3.2):
  *   e2[r][q] = int int K - 2 sum_i w_rqi kappa_i + w_rq^T K_r w_rq
  *            = zeta - 2 zeta sum_i w_rqi + sum_k lambda_rk |wt_k|^2,
  * with kappa_i = int K(u, x_i) du.  Every factor 1 + gamma_j K_alpha of the
@@ -302,9 +302,10 @@ size_t ldk_kernel_grad_workspace_bytes(int R, int d, int64_t n_min, int64_t n_ma
  * (Sec. 5.4), so the quadratic form costs one transform.
  * lam = double[R][n] (ldk_eig); w = dtype[R][nw][n] in the point order of
  * lam; e2 = device double[R][nw].  The transform of w runs in dtype (sum_i
- * w_i is its zero frequency), the weighted sums in FP64 in a fixed order.  e2 is a difference of terms of size zeta:
- * its error is absolute, of order (m + 2) u (zeta + 2 zeta sum_i |w_i| +
- * sum_k |lambda_k| |wt_k|^2), u the unit roundoff of dtype.
+ * w_i is its zero frequency), the weighted sums in FP64 in a fixed order.
+ * e2 is a difference of terms of size zeta: its error is absolute, of
+ * order (m + 2) u (zeta + 2 zeta sum_i |w_i| + sum_k |lambda_k| |wt_k|^2),
+ * u the unit roundoff of dtype.
  * R * nw <= 65535.  ws: ldk_workspace_bytes(LDK_OP_WCE, kind, R * nw, m, dtype). */
 int ldk_wce(int kind, int R, int nw, int m, int dtype, const double *lam, double zeta,
             const void *w, double *e2, void *ws, ldk_stream stream);
@@ -320,14 +321,14 @@ enum {
     LDK_BC_FIELDS = 6
 };
 
-/* Bayesian cubature (named in Sec. 3; the paper prints no formula, so the
- * standard Gaussian conditioning is used): f ~ GP(0, s K) with the kernel
- * of ldk_kernel_column, observed as y_i = f(x_i) + e_i, e_i ~ N(0, s sigma2),
- * and the integral I = int f.  With kappa_i = zeta (see ldk_wce) and the
+/* Bayesian cubature (named in Secs. 1.1 and 1.3; the paper prints no
+ * formula, so the standard Gaussian conditioning is used): f ~ GP(0, s K)
+ * with the kernel of ldk_kernel_column, observed as y_i = f(x_i) + e_i,
+ * e_i ~ N(0, s sigma2), and the integral I = int f.  With kappa_i = zeta (see ldk_wce) and the
  * constant vector an eigenvector of K with eigenvalue lambda_0 = sum_i k1_i
  * (the points form a group under the shift or the digital sum):
  *   WEIGHT = (K + sigma2 I)^{-1} kappa, every entry zeta / (lambda_0 + sigma2)
- *            (the optimal weights of Sec. kernel computations at sigma2 = 0),
+ *            (the optimal weights of Sec. 3.2 at sigma2 = 0),
  *   MEAN   = kappa^T (K + sigma2 I)^{-1} y = WEIGHT sum_i y_i,
  *   VAR    = zeta - kappa^T (K + sigma2 I)^{-1} kappa
  *          = zeta (lambda_0 + sigma2 - n zeta) / (lambda_0 + sigma2),
@@ -339,9 +340,9 @@ enum {
  *            sigma2 = 0).
  * lam = double[R][n] (ldk_eig); y = dtype[R][n]; out = device
  * double[R][LDK_BC_FIELDS].  The transform of y runs in dtype (sum_i y_i is
- * its zero frequency), the rest in FP64.  VAR and WCE2 carry the absolute rounding of lambda_0 (about
- * (m + 1) u sum_i |k1_i| / n relative to zeta).  A replication with some
- * lambda_k + sigma2 <= 0 gets SCALE = HALF = NaN.
+ * its zero frequency), the rest in FP64.  VAR and WCE2 carry the absolute
+ * rounding of lambda_0 (about (m + 1) u sum_i |k1_i| / n relative to zeta).
+ * A replication with some lambda_k + sigma2 <= 0 gets SCALE = HALF = NaN.
  * ws: ldk_workspace_bytes(LDK_OP_BAYES_CUBATURE, kind, R, m, dtype) bytes. */
 int ldk_bayes_cubature(int kind, int R, int m, int dtype, const double *lam, double sigma2,
                        double zeta, const void *y, double z, double *out, void *ws,

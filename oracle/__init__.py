@@ -38,9 +38,9 @@ MLL and gradient       standard GP objective in the eigenbasis of Sec. 5.4
                        trace-form gradient (numpy) at n <= 2^8; central
                        differences; adjoint dot-product identity; a factor
                        1 + gamma K that is exactly zero
-kernel cubature        Sec. kernel computations (worst-case error, optimal
-                       weights) and Bayesian cubature (Sec. 3; no formula
-                       printed: standard Gaussian conditioning); equal
+kernel cubature        Sec. 3.2 (worst-case error, optimal
+                       weights) and Bayesian cubature (Secs. 1.1, 1.3; no
+                       formula printed: standard Gaussian conditioning); equal
                        weights in d = 1 against the aliased Fourier / Walsh
                        closed forms; each kernel factor has mean zero on
                        fine grids (kappa_i = zeta); stationarity of the
@@ -455,7 +455,7 @@ def mll_grad(w: dict, gamma=None, zeta=None, sigma2=None, y=None) -> dict:
 
 # ---------------------------------------------------------------------------
 # Kernel cubature: worst-case error, optimal weights, Bayesian cubature
-# (Sec. kernel computations; Bayesian cubature is named in Sec. 3)
+# (Sec. 3.2; Bayesian cubature is named in Secs. 1.1 and 1.3)
 # ---------------------------------------------------------------------------
 
 def gram(kind, pts, alpha, gamma, zeta: float) -> np.ndarray:
@@ -484,7 +484,7 @@ def kernel_integrals(zeta: float, n: int):
 
 def wce2(K, kappa, I2: float, omega) -> np.ndarray:
     """Squared worst-case error of sum_i omega_i f(x_i) as an estimate of
-    int f over the unit ball of the RKHS of K (Sec. kernel computations):
+    int f over the unit ball of the RKHS of K (Sec. 3.2):
     I2 - 2 sum_i omega_i kappa_i + sum_{i,l} omega_i omega_l K_il.
     K: [R][n][n]; omega: [R][nw][n]; returns [R][nw]."""
     K = np.asarray(K, np.float64)
@@ -509,7 +509,7 @@ def wce2_fast(kind, lam, zeta: float, omega) -> np.ndarray:
 def bayes_cubature(K, kappa, I2: float, y, sigma2: float) -> dict:
     """Posterior of I = int f for f ~ GP(0, s2 K) observed as y_i = f(x_i) +
     e_i, e_i ~ N(0, s2 sigma2), given the points (Bayesian cubature, named in
-    Sec. 3; the paper prints no formula, so the Gaussian conditioning below is
+    Secs. 1.1 and 1.3; the paper prints no formula, so the Gaussian conditioning below is
     the standard one, with the scale s2 at its maximum-likelihood value):
       weights = (K + sigma2 I)^{-1} kappa       (the optimal cubature weights
                                                  omega* of Sec. kernel

@@ -11,7 +11,7 @@
 // is linear in k1, dL/dk1 = a is the adjoint map applied to g: H g for the
 // net (H symmetric) and Re sum_k g_k W^{-k R(j)} for the lattice.
 //
-// Kernel cubature (Sec. kernel computations) uses the same power spectrum.
+// Kernel cubature (Sec. 3.2) uses the same power spectrum.
 // For the product kernels of ldk_kernel_column every factor 1 + gamma K_alpha
 // integrates to one over [0, 1) (K_alpha has mean zero), so
 // kappa_i = int K(u, x_i) du = zeta and int int K = zeta; then

@@ -4,8 +4,10 @@
 // for two Genz test integrands of s = sum_j c_j x_j: the corner peak
 // (1 + s)^-(d+1) (the integrand of the paper's RQMC example) and the
 // oscillatory cos(2 pi u + s).  The points are regenerated in registers and
-// never written: a block takes KC_TILE consecutive indices of one
-// replication, accumulates s over the dimensions with the same point
+// never written: a block takes KC_THREADS IT consecutive indices of one
+// replication (IT = 8 points per thread, or 2 when that leaves the grid
+// short of the chip's 256 compute units), accumulates s over the dimensions
+// with the same point
 // recurrences as the regenerating kernel column (plus the randomization's
 // shift), applies the integrand and sums in FP64 in a fixed order.
 #include "kfactor.hpp"
@@ -37,14 +39,15 @@ __device__ __forceinline__ double block_sum(double v, double *red)
 }
 
 // s[l] += c_j x_j over every dimension for the lattice points
-// i = first + KC_THREADS l of replication r (tile-aligned first - t, so the
-// bit tricks of the regenerating column apply; the shift is added to the
-// base word before the points are split into high and low halves).
-template <int ORDER>
+// i = first + KC_THREADS l, l < IT, of replication r (first - t a multiple of
+// KC_THREADS IT, so the bits of l are free in first and the bit tricks of the
+// regenerating column apply; the shift is added to the base word before the
+// points are split into high and low halves).
+template <int ORDER, int IT>
 __device__ __forceinline__ void lattice_dot(const PointsetArgs &ps, const double *__restrict__ coef,
-                                            int r, int64_t first, double (&s)[KC_ITERS])
+                                            int r, int64_t first, double (&s)[IT])
 {
-    static_assert(KC_ITERS == 8 && KC_LOG_THREADS == 8, "offset table assumes 8 x 256");
+    static_assert(IT <= 8 && KC_LOG_THREADS == 8, "offset table assumes up to 8 x 256");
     constexpr uint64_t br3[8] = {0, 4, 2, 6, 1, 5, 3, 7};
     const int d = ps.d, m = ps.m_max;
     const uint64_t bfirst = ORDER == LDK_NATURAL ? brev64((uint64_t)first) : (uint64_t)first;
@@ -62,7 +65,7 @@ __device__ __forceinline__ void lattice_dot(const PointsetArgs &ps, const double
         }
         const double lo_p = lo_part<double>((uint32_t)base);
 #pragma unroll
-        for (int l = 0; l < KC_ITERS; ++l) {
+        for (int l = 0; l < IT; ++l) {
             double x;
             if constexpr (ORDER == LDK_NATURAL)
                 x = unit_hl<double>((uint32_t)(base >> 32) + (uint32_t)br3[l] * (uint32_t)(G >> 32),
@@ -76,8 +79,9 @@ __device__ __forceinline__ void lattice_dot(const PointsetArgs &ps, const double
 
 // The same for net points: scrambled columns and XOR steps from the LDS
 // tables of the regenerating column, then the digital shift.
+template <int IT>
 __device__ __forceinline__ void net_dot(const KcolArgs &a, NetLds &L, const double *__restrict__ coef,
-                                        int r, int64_t tile0, double (&s)[KC_ITERS])
+                                        int r, int64_t tile0, double (&s)[IT])
 {
     constexpr int sft = KC_LOG_THREADS;
     const int d = a.ps.d, t = threadIdx.x;
@@ -93,12 +97,12 @@ __device__ __forceinline__ void net_dot(const KcolArgs &a, NetLds &L, const doub
             const double c = coef[j];
             uint64_t z = L.zb[jj] ^ L.nib[jj][0][code_t & 15] ^ L.nib[jj][1][(code_t >> 4) & 15];
 #pragma unroll
-            for (int l = 0; l < KC_ITERS; ++l) {
+            for (int l = 0; l < IT; ++l) {
                 s[l] = fma(c, unit<double>(z ^ sh), s[l]);
                 // past the last index of the net the step columns are zero
                 // (such points are masked by the caller)
                 const uint64_t nb = ((uint64_t)tile0 >> sft) + (uint64_t)l + 1;
-                if (l + 1 < KC_ITERS) z ^= L.step[jj][ctz64(nb)];
+                if (l + 1 < IT) z ^= L.step[jj][ctz64(nb)];
             }
         }
     }
@@ -113,28 +117,28 @@ __device__ __forceinline__ double integrand(double s, int d, double phase)
         return cos(phase + s);
 }
 
-// One block per (tile of KC_TILE indices, replication): partial sums of f.
-template <int KIND, int ORDER, int F>
+// One block per (tile of KC_THREADS IT indices, replication): partial sums of f.
+template <int KIND, int ORDER, int F, int IT>
 __global__ __launch_bounds__(KC_THREADS) void k_rqmc_tiles(KcolArgs a, const double *__restrict__ coef,
                                                            double phase, int64_t n,
                                                            double *__restrict__ part)
 {
     __shared__ double red[KC_THREADS / 64];
     const int r = blockIdx.y;
-    const int64_t tile0 = (int64_t)blockIdx.x * KC_TILE;
+    const int64_t tile0 = (int64_t)blockIdx.x * (KC_THREADS * IT);
     const int64_t first = tile0 + threadIdx.x;
-    double s[KC_ITERS];
+    double s[IT];
 #pragma unroll
-    for (int l = 0; l < KC_ITERS; ++l) s[l] = 0.0;
+    for (int l = 0; l < IT; ++l) s[l] = 0.0;
     if constexpr (KIND == LDK_DNET_B2) {
         __shared__ NetLds L;
-        net_dot(a, L, coef, r, tile0, s);
+        net_dot<IT>(a, L, coef, r, tile0, s);
     } else {
-        lattice_dot<ORDER>(a.ps, coef, r, first, s);
+        lattice_dot<ORDER, IT>(a.ps, coef, r, first, s);
     }
     double acc = 0.0;
 #pragma unroll
-    for (int l = 0; l < KC_ITERS; ++l)
+    for (int l = 0; l < IT; ++l)
         if (first + (int64_t)l * KC_THREADS < n) acc += integrand<F>(s[l], a.ps.d, phase);
     const double tot = block_sum<KC_THREADS>(acc, red);
     if (threadIdx.x == 0) part[(size_t)r * gridDim.x + blockIdx.x] = tot;
@@ -180,21 +184,30 @@ __global__ __launch_bounds__(RQ_FINAL_THREADS) void k_rqmc_final(const double *_
     }
 }
 
-int64_t tiles_of(int64_t n) { return (n + KC_TILE - 1) / KC_TILE; }
+constexpr int RQ_IT_FULL = 8, RQ_IT_SMALL = 2;
 
-template <int F>
+int64_t tiles_of(int64_t n, int it) { return (n + KC_THREADS * it - 1) / (KC_THREADS * it); }
+
+// Points per thread: 8, unless the grid would then hold fewer than two
+// blocks per compute unit.
+int rq_iters(int64_t n, int R)
+{
+    return tiles_of(n, RQ_IT_FULL) * R < 512 ? RQ_IT_SMALL : RQ_IT_FULL;
+}
+
+template <int F, int IT>
 void launch_tiles(const KcolArgs &a, const double *coef, double phase, int64_t n, dim3 grid,
                   hipStream_t s, double *part)
 {
     if (a.ps.kind == LDK_DNET_B2)
-        hipLaunchKernelGGL((k_rqmc_tiles<LDK_DNET_B2, LDK_NATURAL, F>), grid, dim3(KC_THREADS), 0, s,
-                           a, coef, phase, n, part);
+        hipLaunchKernelGGL((k_rqmc_tiles<LDK_DNET_B2, LDK_NATURAL, F, IT>), grid, dim3(KC_THREADS),
+                           0, s, a, coef, phase, n, part);
     else if (a.ps.order == LDK_LINEAR)
-        hipLaunchKernelGGL((k_rqmc_tiles<LDK_LATTICE, LDK_LINEAR, F>), grid, dim3(KC_THREADS), 0, s,
-                           a, coef, phase, n, part);
+        hipLaunchKernelGGL((k_rqmc_tiles<LDK_LATTICE, LDK_LINEAR, F, IT>), grid, dim3(KC_THREADS),
+                           0, s, a, coef, phase, n, part);
     else
-        hipLaunchKernelGGL((k_rqmc_tiles<LDK_LATTICE, LDK_NATURAL, F>), grid, dim3(KC_THREADS), 0,
-                           s, a, coef, phase, n, part);
+        hipLaunchKernelGGL((k_rqmc_tiles<LDK_LATTICE, LDK_NATURAL, F, IT>), grid,
+                           dim3(KC_THREADS), 0, s, a, coef, phase, n, part);
 }
 
 }  // namespace
@@ -206,7 +219,7 @@ using namespace ldk;
 extern "C" size_t ldk_rqmc_workspace_bytes(int R, int64_t n)
 {
     if (R < 0 || n < 0) return 0;
-    return (size_t)R * (size_t)tiles_of(n) * sizeof(double);
+    return (size_t)R * (size_t)tiles_of(n, RQ_IT_SMALL) * sizeof(double);
 }
 
 extern "C" int ldk_rqmc(const ldk_pointset *ps, int64_t n, int integrand, const double *coef,
@@ -223,7 +236,8 @@ extern "C" int ldk_rqmc(const ldk_pointset *ps, int64_t n, int integrand, const 
                             : ((int64_t)1 << a.ps.m_max);
     if (n < 1 || n > lim) return LDK_EINVAL;
     if (!coef || !mu_r || !stats || !ws) return LDK_EINVAL;
-    const int64_t tiles = tiles_of(n);
+    const int it = rq_iters(n, a.ps.R);
+    const int64_t tiles = tiles_of(n, it);
     if (tiles > 0x7fffffff) return LDK_ENOTSUP;
     st = ensure_init();
     if (st) return st;
@@ -233,10 +247,13 @@ extern "C" int ldk_rqmc(const ldk_pointset *ps, int64_t n, int integrand, const 
     double *part = static_cast<double *>(ws);
     const dim3 grid((unsigned)tiles, (unsigned)a.ps.R);
     const double phase = 6.283185307179586476925286766559 * u;
-    if (integrand == LDK_GENZ_CORNER_PEAK)
-        launch_tiles<LDK_GENZ_CORNER_PEAK>(a, coef, phase, n, grid, s, part);
-    else
-        launch_tiles<LDK_GENZ_OSCILLATORY>(a, coef, phase, n, grid, s, part);
+    if (integrand == LDK_GENZ_CORNER_PEAK) {
+        if (it == RQ_IT_SMALL) launch_tiles<LDK_GENZ_CORNER_PEAK, RQ_IT_SMALL>(a, coef, phase, n, grid, s, part);
+        else launch_tiles<LDK_GENZ_CORNER_PEAK, RQ_IT_FULL>(a, coef, phase, n, grid, s, part);
+    } else {
+        if (it == RQ_IT_SMALL) launch_tiles<LDK_GENZ_OSCILLATORY, RQ_IT_SMALL>(a, coef, phase, n, grid, s, part);
+        else launch_tiles<LDK_GENZ_OSCILLATORY, RQ_IT_FULL>(a, coef, phase, n, grid, s, part);
+    }
     LDK_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_rqmc_final, dim3(1), dim3(RQ_FINAL_THREADS), 0, s, (const double *)part,
                        (int)tiles, a.ps.R, (double)n, t, mu_r, stats);

@@ -286,7 +286,7 @@ def test_rqmc_rejects_bad_arguments():
     assert f(P(_ps()), 16, CP, FAKE, 0.0, 2.0, FAKE, None, FAKE, None) == -1      # stats
     assert f(P(_ps()), 16, CP, FAKE, 0.0, 2.0, FAKE, FAKE, None, None) == -1      # ws
     assert f(None, 16, CP, FAKE, 0.0, 2.0, FAKE, FAKE, FAKE, None) == -1
-    # tile sums: R x ceil(n / 2048) doubles
-    assert L.ldk_rqmc_workspace_bytes(10, 2**15) == 10 * 16 * 8
-    assert L.ldk_rqmc_workspace_bytes(3, 2049) == 3 * 2 * 8
+    # tile sums: R x ceil(n / 512) doubles (room for the small-grid tiling)
+    assert L.ldk_rqmc_workspace_bytes(10, 2**15) == 10 * 64 * 8
+    assert L.ldk_rqmc_workspace_bytes(3, 2049) == 3 * 5 * 8
     assert L.ldk_rqmc_workspace_bytes(3, 0) == 0

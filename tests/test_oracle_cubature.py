@@ -1,4 +1,4 @@
-"""Pins for the oracle's kernel cubature (Sec. kernel computations): the
+"""Pins for the oracle's kernel cubature (Sec. 3.2): the
 squared worst-case error against closed forms for equal weights in one
 dimension, the mean-zero property of every kernel factor behind
 kappa_i = zeta, optimality of the weights, and the Bayesian-cubature
@@ -88,7 +88,7 @@ def test_dsi_factor_mean_zero(orc, alpha):
 
 @pytest.mark.parametrize("kind", ["lattice", "dnet"])
 def test_optimal_weights(orc, kind):
-    # Sec. kernel computations: omega* = K^{-1} kappa minimises e^2; the
+    # Sec. 3.2: omega* = K^{-1} kappa minimises e^2; the
     # points form a group, so the constant vector is an eigenvector of K with
     # eigenvalue sum_i k1_i and all weights equal zeta / sum_i k1_i
     m, n = 6, 64
