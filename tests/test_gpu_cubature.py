@@ -203,3 +203,31 @@ def test_cubature_edge_cases(orc):
     ldk.wce("lattice", lam12[:1, :2**10].contiguous(), om[:1, :, :2**10].contiguous(), 1.0, ws=ws)
     b = ldk.wce("lattice", lam12, om, 1.0, ws=ws).cpu()
     assert torch.equal(a, b)
+
+
+@pytest.fixture(scope="module")
+def three_pass_case(orc):
+    # n = 2^22: the packed half-length transform takes two row/column passes
+    # before the top pass that forms the weighted sums
+    m, kind, zeta = 22, "lattice", 0.9
+    w = _inst(kind, 123, m, 3, 1, [2, 1, 3], [0.9, 0.5, 0.3], zeta)
+    lam = _lam(orc, w)
+    om = W.cubature_weights(124, 1, 2, 2**m)
+    return dict(m=m, kind=kind, zeta=zeta, w=w, lam=lam, om=om,
+                ref=orc.wce2_fast(kind, lam, zeta, om))
+
+
+@pytest.mark.parametrize("dtype", [F64, F32])
+def test_cubature_three_pass_lattice(orc, three_pass_case, dtype):
+    c = three_pass_case
+    m, kind, zeta, lam = c["m"], c["kind"], c["zeta"], c["lam"]
+    om = c["om"].astype(np.float64 if dtype == F64 else np.float32)
+    ref = c["ref"] if dtype == F64 else orc.wce2_fast(kind, lam, zeta, om.astype(np.float64))
+    e2 = ldk.wce(kind, torch.from_numpy(lam).cuda(), torch.from_numpy(om).cuda(), zeta)
+    tol = _wce_tol(m, U64_EPS if dtype == F64 else F32_EPS, zeta, om.astype(np.float64), lam)
+    err = np.max(np.abs(e2.cpu().numpy() - ref) / tol)
+    record(f"wce_{kind}_m{m}_{'f64' if dtype == F64 else 'f32'}", err_over_tol=err)
+    assert err <= 1.0
+    y = c["w"]["y"][:, 0, :].astype(np.float64 if dtype == F64 else np.float32)
+    _bc_check(orc, kind, lam, y, 1e-3, zeta, m, dtype,
+              f"bc_{kind}_m{m}_{'f64' if dtype == F64 else 'f32'}")
