@@ -108,11 +108,26 @@ __device__ __forceinline__ void net_dot(const KcolArgs &a, NetLds &L, const doub
     }
 }
 
+// b^-e for an integer e >= 1 by binary powering (e is block-uniform): about
+// log2 e squarings, popcount e products and one division, each rounded once,
+// so a relative error of at most about (e + 1) u, far cheaper than pow.
+__device__ __forceinline__ double inv_ipow(double b, int e)
+{
+    double r = 1.0;
+    for (;;) {
+        if (e & 1) r *= b;
+        e >>= 1;
+        if (!e) break;
+        b *= b;
+    }
+    return 1.0 / r;
+}
+
 template <int F>
 __device__ __forceinline__ double integrand(double s, int d, double phase)
 {
     if constexpr (F == LDK_GENZ_CORNER_PEAK)
-        return pow(1.0 + s, -(double)(d + 1));
+        return inv_ipow(1.0 + s, d + 1);
     else
         return cos(phase + s);
 }

@@ -33,15 +33,16 @@ def _ref(orc, pts, integrand, c, u, tau):
 
 def _check(name, mu_r, stats, ref, y, integrand, c, n):
     """Derived bounds: s = c.x summed in another order (|ds| <= 2 d u sum|c x|);
-    the corner peak's relative error (d + 1)|ds|/(1 + s) plus its power, the
-    oscillatory's absolute error |ds| plus its cosine; then the FP64 sums of n
-    terms (tree depth log2 n on both sides)."""
+    the corner peak's relative error (d + 1)|ds|/(1 + s) plus its power
+    (binary powering here, (d + 2) u; pow in the oracle), the oscillatory's
+    absolute error |ds| plus its cosine; then the FP64 sums of n terms (tree
+    depth log2 n on both sides)."""
     u = U64_EPS
     d = len(c)
     R = mu_r.shape[0]
     absf = np.abs(y).mean(axis=1)
     if integrand == "corner_peak":
-        f_err = (2 * d * (d + 1) + 8) * u * absf
+        f_err = (2 * d * (d + 1) + (d + 2) + 8) * u * absf
     else:
         f_err = (2 * d * np.abs(c).sum() + 4) * u
     tol_mu = 4 * (f_err + (2 * math.log2(max(n, 2)) + 20) * u * absf)
