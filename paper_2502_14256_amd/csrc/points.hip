@@ -37,10 +37,13 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_net(PointsetArgs a, int64_t
                                                          int logP, int pairs,
                                                          uint64_t *__restrict__ out)
 {
-    __shared__ uint64_t ct[GEN_DIM_CHUNK][64];
+    // rows padded to 65 words: the lanes of a wave read different
+    // dimensions jj at one step index, and 64-word rows would put them all
+    // in one LDS bank
+    __shared__ uint64_t ct[GEN_DIM_CHUNK][65];
     __shared__ union {
-        uint64_t step[GEN_DIM_CHUNK][64];
-        uint64_t srow[GEN_DIM_CHUNK][64];  // rows of S_j, dead once ct is built
+        uint64_t step[GEN_DIM_CHUNK][65];
+        uint64_t srow[GEN_DIM_CHUNK][65];  // rows of S_j, dead once ct is built
     } u;
     auto &step = u.step;
     const int r = blockIdx.z;
