@@ -38,7 +38,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # reported as null once they change.
 STEP_TRAFFIC = {"read_MiB": 0.15, "write_MiB": 264.00,
                 "sources": ("kcol.hip", "kfactor.hpp", "pointset.hpp", "common.hpp"),
-                "sha1": "56cf0c01be13536416dabe2d2a68f07554dcb46b"}
+                "sha1": "f0bfcb66431a54c2f5f278439dcef1b96d3267ae"}
 
 
 def step_traffic_bytes():

@@ -237,7 +237,7 @@ struct NetLds {
     uint64_t ct[KC_DIM_CHUNK][64];  // scrambled columns S_j C_j
     union {
         uint64_t step[KC_DIM_CHUNK][64];  // XOR steps between a thread's points
-        uint64_t srow[KC_DIM_CHUNK][64];  // rows of S_j (dead once ct is built)
+        uint64_t srow[KC_DIM_CHUNK][65];  // rows of S_j (dead once ct is built)
     };
     uint64_t nib[KC_DIM_CHUNK][2][16];  // z of (nibble h of the low index byte)
     uint64_t zb[KC_DIM_CHUNK];          // z(code(tile0))
@@ -277,14 +277,15 @@ __device__ __forceinline__ void build_net_chunk(const KcolArgs &a, NetLds &L, in
             L.srow[w >> 6][w & 63] = a.ps.lms[((size_t)r * d + jc + (w >> 6)) * 64 + (w & 63)];
         __syncthreads();
     }
-    for (int w = t; w < DB * 64; w += KC_THREADS) {
-        const int jj = w >> 6, k = w & 63;
-        uint64_t v = 0;  // columns k >= m are zero
-        if (k < m) {
-            const uint64_t col = net_gen_column(a.ps, r, jc + jj, k);
-            v = a.ps.lms ? lms_column(L.srow[jj], col) : col;
-        }
-        L.ct[jj][k] = v;
+    // columns k >= m are zero; the DB m scrambled columns take one item
+    // each, so no lane idles through a scrambling loop (the S rows are
+    // padded: the lanes of a wave read rows of different dimensions)
+    for (int w = t; w < DB * 64; w += KC_THREADS)
+        if ((w & 63) >= m) L.ct[w >> 6][w & 63] = 0;
+    for (int w = t; w < DB * m; w += KC_THREADS) {
+        const int jj = w / m, k = w - jj * m;
+        const uint64_t col = net_gen_column(a.ps, r, jc + jj, k);
+        L.ct[jj][k] = a.ps.lms ? lms_column(L.srow[jj], col) : col;
     }
     __syncthreads();  // srow is dead from here on; step reuses its storage
     for (int w = t; w < DB * 64; w += KC_THREADS) {
