@@ -284,6 +284,7 @@ def main():
     out["higher_order_net"] = higher_order_bench(K)
     out["cubature"] = cubature_bench(K, lam, y[:, 0, :], w)
     out["rqmc"] = rqmc_bench(K)
+    out["update_double"] = update_bench(K)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
@@ -528,6 +529,63 @@ def rqmc_bench(K):
     timed("net_lms_m20_d50_R16", ldk.PointSet("dnet", R, d, m, dev_u64(wn["gen"]),
                                               dev_u64(wn["lms"]), dev_u64(wn["shift"])), 2**m)
     return res
+
+
+def update_bench(K):
+    """Doubling n from 2^19 to 2^20 on the net workload (workload 3: LMS +
+    digitally shifted net, d = 32, order-4 DSI kernel, FP64), against fresh
+    work at 2^20: (a) the transformed responses, update_double against a
+    fresh FWHT; (b) extending a fit's inputs, i.e. the point words and first
+    column of the new half, the eigenvalue update and the ỹ update, against
+    points + column, eigenvalues and the transform of all 2^20 points."""
+    import numpy as np
+    import torch
+
+    import paper_2502_14256_amd as ldk
+    import workloads as W
+
+    w = W.workload(3)
+    m, d, R = w["m"], w["d"], w["R"]
+    n, h = 2**m, 2 ** (m - 1)
+
+    def dev_u64(a):
+        return torch.from_numpy(np.ascontiguousarray(a, np.uint64).view(np.int64).copy()).cuda()
+
+    ps = ldk.PointSet("dnet", R, d, m, dev_u64(w["gen"]), dev_u64(w["lms"]), dev_u64(w["shift"]))
+    kern = ldk.Kernel("dnet", w["alpha"], torch.from_numpy(np.asarray(w["gamma"], np.float64)).cuda(),
+                      w["zeta"])
+    y = torch.from_numpy(np.ascontiguousarray(w["y"][:, 0, :])).cuda()
+    pts_full = torch.empty((R, n, d), dtype=torch.int64, device="cuda")
+    k1_full = torch.empty((R, n), dtype=torch.float64, device="cuda")
+    pts_new = torch.empty((R, h, d), dtype=torch.int64, device="cuda")
+    k1_new = torch.empty((R, h), dtype=torch.float64, device="cuda")
+    ldk.points_column(kern, ps, 0, n, pts=pts_full, k1=k1_full)
+    lam_old = ldk.eig("dnet", k1_full[:, :h].contiguous())
+    yt_old = ldk.transform("dnet", y[:, :h].contiguous())
+    y_new = y[:, h:].contiguous()
+    yt = torch.empty((R, n), dtype=torch.float64, device="cuda")
+    lam = torch.empty((R, n), dtype=torch.float64, device="cuda")
+    ms_upd = time_graph(lambda: ldk.update_double("dnet", yt_old, y_new, out=yt), K)
+    ms_fresh = time_graph(lambda: ldk.transform("dnet", y, out=yt), K)
+
+    def extend():
+        ldk.points_column(kern, ps, h, n, pts=pts_new, k1=k1_new)
+        ldk.eig_update_double("dnet", lam_old, k1_new, out=lam)
+        ldk.update_double("dnet", yt_old, y_new, out=yt)
+
+    def fresh():
+        ldk.points_column(kern, ps, 0, n, pts=pts_full, k1=k1_full)
+        ldk.eig("dnet", k1_full, out=lam)
+        ldk.transform("dnet", y, out=yt)
+
+    ms_ext = time_graph(extend, K)
+    ms_fit = time_graph(fresh, K)
+    alg = 16 * n * R  # read the old half's transform and the new half, write 2^20 (FP64)
+    return {"workload": "net_m20_d32_dsi4 (LMS + digital shift, n = 2^19 -> 2^20, FP64)",
+            "update_double_ms": round(ms_upd, 5), "fresh_transform_ms": round(ms_fresh, 5),
+            "update_double_GB_s": round(alg / (ms_upd * 1e-3) / 1e9, 1),
+            "extend_ms": round(ms_ext, 5), "fresh_ms": round(ms_fit, 5),
+            "extend_speedup": round(ms_fit / ms_ext, 3)}
 
 
 def fwht_bench(K):

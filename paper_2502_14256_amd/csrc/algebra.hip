@@ -725,27 +725,29 @@ int ldk_update_double(int kind, int B, int m, int dtype, const void *yt_old, con
         LDK_LAUNCH_CHECK();
         return LDK_OK;
     }
-    // intermediates of a multi-pass plan also live in the output rows (stride 2n)
-    st = forward_all(kind, dtype, m, B, y_new, n, lat, u, 2 * n, false, u, 2 * n, 1.0, s);
-    if (st) return st;
-    const double c = 1.0 / std::sqrt((double)n);
-    const int64_t work = (int64_t)B * n;
-    if (lat) {
-        if (dtype == LDK_F64)
-            hipLaunchKernelGGL((k_update_combine<double, true, false>), dim3(blocks_for(work, 256)), dim3(256),
-                               0, s, yt_old, yt_full, (const void *)u, 2 * n, (int64_t)B, m, c);
-        else
-            hipLaunchKernelGGL((k_update_combine<float, true, false>), dim3(blocks_for(work, 256)), dim3(256),
-                               0, s, yt_old, yt_full, (const void *)u, 2 * n, (int64_t)B, m, c);
-    } else {
-        if (dtype == LDK_F64)
-            hipLaunchKernelGGL((k_update_combine<double, false, false>), dim3(blocks_for(work, 256)), dim3(256),
-                               0, s, yt_old, yt_full, (const void *)u, 2 * n, (int64_t)B, m, c);
-        else
-            hipLaunchKernelGGL((k_update_combine<float, false, false>), dim3(blocks_for(work, 256)), dim3(256),
-                               0, s, yt_old, yt_full, (const void *)u, 2 * n, (int64_t)B, m, c);
+    // the transform of the new half; intermediates of a multi-pass plan live
+    // in the output rows' second halves (stride 2n), and the last pass meets
+    // the old half's transform in its store (PIO_COMBINE) and writes both
+    // halves of every output row
+    const Plan pl = make_plan(m, log_tile_for(kind, dtype));
+    for (int p = 0; p < pl.P; ++p) {
+        const bool first = p == 0, last = p == pl.P - 1;
+        PassArgs a{};
+        a.src = first ? y_new : (const void *)u;
+        a.src_row = first ? n : 2 * n;
+        a.dst = last ? yt_full : u;
+        a.dst_row = 2 * n;
+        a.rows = B;
+        a.m = m;
+        a.g = pl.pass[p];
+        a.nrhs = 1;
+        a.global_tw = p > 0;
+        a.scale = last ? 1.0 / std::sqrt((double)n) : 1.0;
+        a.old = yt_old;
+        st = launch_pass(kind, dtype, PM_FWD, first && lat ? PIO_REAL : PIO_SAME,
+                         last ? PIO_COMBINE : PIO_SAME, a, s);
+        if (st) return st;
     }
-    LDK_LAUNCH_CHECK();
     return LDK_OK;
 }
 

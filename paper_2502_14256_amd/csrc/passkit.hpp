@@ -257,9 +257,10 @@ __device__ __forceinline__ void lds_write(const T (&v)[E], T *lds, int t, int gs
 //   IO_REAL    real array: load as (x, 0), store the real part;
 //   IO_PACKED  real array of 2 N per row holding a complex row of N as
 //              (re at e, im at e + N): z_e = y_e + i y_{e+N};
-//   IO_POWER   (store only) FP64 array receiving |x|^2, squared in FP64.
+//   IO_POWER   (store only) FP64 array receiving |x|^2, squared in FP64;
+//   IO_COMBINE (store only, see the pass kernel) the n -> 2n update's butterfly.
 // SRC_F32: the source holds floats widened to the FP64 working type.
-enum IoMode { IO_SAME = 0, IO_REAL = 1, IO_PACKED = 2, IO_POWER = 3 };
+enum IoMode { IO_SAME = 0, IO_REAL = 1, IO_PACKED = 2, IO_POWER = 3, IO_COMBINE = 4 };
 
 template <typename T, int LD, bool SRC_F32>
 __device__ __forceinline__ T load_elem(const void *p, int64_t idx, int64_t half)

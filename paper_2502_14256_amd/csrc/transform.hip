@@ -125,7 +125,20 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int64_t bid)
     for (int i = 0; i < E; ++i) {
         T o = v[i];
         if (MODE == PM_FWD || MODE == PM_INV) o = scl(o, sc);
-        store_elem<T, ST>(a.dst, row * a.dst_row + gidx(t + Tn * i), o, a.half);
+        if constexpr (ST == IO_COMBINE) {
+            // the doubling update: the new half's transform o meets the old
+            // half's at k (Sec. 5.4, eq. ft_next_parts)
+            const int64_t n = (int64_t)1 << a.m;
+            const int64_t k = gidx(t + Tn * i);
+            const R h = (R)0.70710678118654752440;
+            if constexpr (FFT) o = cmul(o, tw_any<R>((uint64_t)k, a.m + 1));
+            const T od = static_cast<const T *>(a.old)[row * n + k];
+            T *full = static_cast<T *>(a.dst) + row * a.dst_row;
+            full[k] = scl(add(od, o), h);
+            full[n + k] = scl(sub(od, o), h);
+        } else {
+            store_elem<T, ST>(a.dst, row * a.dst_row + gidx(t + Tn * i), o, a.half);
+        }
     }
 
     if constexpr (MODE == PM_INV) {
@@ -172,8 +185,16 @@ int launch_t(int ld, int st, const PassArgs &a, hipStream_t s)
         if (ld != IO_SAME) return LDK_ENOTSUP;
         if (st == IO_SAME) LDK_PASS(IO_SAME, IO_SAME);
         else if (MODE == PM_FWD && st == IO_POWER) LDK_PASS(IO_SAME, IO_POWER);
+        else if (MODE == PM_FWD && st == IO_COMBINE) LDK_PASS(IO_SAME, IO_COMBINE);
         else return LDK_ENOTSUP;
     } else if constexpr (MODE == PM_FWD) {
+        if (st == IO_COMBINE) {
+            if (ld == IO_SAME) LDK_PASS(IO_SAME, IO_COMBINE);
+            else if (ld == IO_REAL) LDK_PASS(IO_REAL, IO_COMBINE);
+            else return LDK_ENOTSUP;
+            LDK_LAUNCH_CHECK();
+            return LDK_OK;
+        }
         if (st == IO_PACKED || st == IO_POWER) return LDK_ENOTSUP;
         if (ld == IO_SAME && st == IO_SAME) LDK_PASS(IO_SAME, IO_SAME);
         else if (ld == IO_SAME) LDK_PASS(IO_SAME, IO_REAL);
@@ -182,7 +203,7 @@ int launch_t(int ld, int st, const PassArgs &a, hipStream_t s)
         else if (st == IO_SAME) LDK_PASS(IO_PACKED, IO_SAME);
         else return LDK_ENOTSUP;
     } else if constexpr (MODE == PM_INV) {
-        if (ld != IO_SAME || st == IO_POWER) return LDK_ENOTSUP;
+        if (ld != IO_SAME || st == IO_POWER || st == IO_COMBINE) return LDK_ENOTSUP;
         if (st == IO_SAME) LDK_PASS(IO_SAME, IO_SAME);
         else if (st == IO_REAL) LDK_PASS(IO_SAME, IO_REAL);
         else LDK_PASS(IO_SAME, IO_PACKED);

@@ -73,6 +73,10 @@ struct PassArgs {
     int64_t ld_count;
     // PM_QFORM only: weights lambda_k (1) or 1 / (lambda_k + sigma2) (0)
     int qform_lam;
+    // PIO_COMBINE only: the old half's transform [rows][2^m]; the store
+    // writes (old + w) / sqrt 2 at k and (old - w) / sqrt 2 at 2^m + k of
+    // dst rows of 2^(m+1), w the pass output (times W_{2^(m+1)}^k, lattice)
+    const void *old;
 };
 
 // Global IO of a pass (lattice only; nets are always real):
@@ -81,6 +85,7 @@ enum PassIo {
     PIO_REAL = 1,    // real rows: load as (x, 0) / store the real part
     PIO_PACKED = 2,  // real rows of 2N carrying a complex row of N: z_e = y_e + i y_{e+N}
     PIO_POWER = 3,   // store only: FP64 rows receiving |x|^2 (forward passes)
+    PIO_COMBINE = 4, // store only: the n -> 2n update's butterfly with a.old (forward)
 };
 
 // kind: LDK_LATTICE (complex FFTBR) or LDK_DNET_B2 (real FWHT).
