@@ -129,8 +129,9 @@ __global__ void k_update_combine(const void *old_, void *full_, const void *u_, 
     }
 }
 
-// U: complex double (lattice, transformed) or real U_T (net, or n = 1).
-template <bool CPLX, typename U_T>
+// n = 1 (FT_0 is the identity, w_0 = 1): lambda_full = [lambda_m + u; lambda_m - u]
+// with u the new half's k1 (widened to FP64).
+template <typename U_T>
 __global__ void k_eig_update_combine(const double *old, double *full, const void *u_, int64_t u_row,
                                      int64_t rows, int m)
 {
@@ -138,13 +139,7 @@ __global__ void k_eig_update_combine(const double *old, double *full, const void
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= rows * n) return;
     const int64_t row = gid >> m, k = gid & (n - 1);
-    double part;
-    if constexpr (CPLX) {
-        const cplx<double> u = static_cast<const cplx<double> *>(u_)[row * u_row + k];
-        part = cmul(u, tw_any<double>((uint64_t)k, m + 1)).re;
-    } else {
-        part = (double)static_cast<const U_T *>(u_)[row * u_row + k];
-    }
+    const double part = (double)static_cast<const U_T *>(u_)[row * u_row + k];
     const double o = old[row * n + k];
     full[row * 2 * n + k] = o + part;
     full[row * 2 * n + n + k] = o - part;
@@ -769,31 +764,38 @@ int ldk_eig_update_double(int kind, int R, int m, int dtype, const double *lam_o
     if (m == 0) {
         // FT_0 is the identity and w_0 = 1: the new half is k1_new itself
         if (dtype == LDK_F64)
-            hipLaunchKernelGGL((k_eig_update_combine<false, double>), grid, block, 0, s, lam_old,
+            hipLaunchKernelGGL((k_eig_update_combine<double>), grid, block, 0, s, lam_old,
                                lam_full, k1_new, (int64_t)1, (int64_t)R, 0);
         else
-            hipLaunchKernelGGL((k_eig_update_combine<false, float>), grid, block, 0, s, lam_old,
+            hipLaunchKernelGGL((k_eig_update_combine<float>), grid, block, 0, s, lam_old,
                                lam_full, k1_new, (int64_t)1, (int64_t)R, 0);
         LDK_LAUNCH_CHECK();
         return LDK_OK;
     }
-    if (lat) {
-        // complex FP64 transform of the new half in the workspace
-        st = forward_all(kind, LDK_F64, m, R, k1_new, n, true, ws, n, false, ws, n, 1.0, s,
-                         dtype == LDK_F32);
+    // FP64 transform of the new half (k1 widened when FP32); intermediates of
+    // a multi-pass plan in the workspace (lattice, complex) or in the output
+    // rows' second halves (net), and the last pass stores through the
+    // doubling step lambda_m +- Re(w_k u_k) into both halves (PIO_COMBINE)
+    const Plan pl = make_plan(m, log_tile_for(kind, LDK_F64));
+    for (int p = 0; p < pl.P; ++p) {
+        const bool first = p == 0, last = p == pl.P - 1;
+        PassArgs a{};
+        a.src = first ? k1_new : (lat ? (const void *)ws : (const void *)(lam_full + n));
+        a.src_row = first ? n : (lat ? n : 2 * n);
+        a.dst = last ? (void *)lam_full : (lat ? ws : (void *)(lam_full + n));
+        a.dst_row = last ? 2 * n : (lat ? n : 2 * n);
+        a.rows = R;
+        a.m = m;
+        a.g = pl.pass[p];
+        a.nrhs = 1;
+        a.global_tw = p > 0;
+        a.scale = 1.0;
+        a.old = lam_old;
+        a.combine_real = 1;
+        st = launch_pass(kind, LDK_F64, PM_FWD, first && lat ? PIO_REAL : PIO_SAME,
+                         last ? PIO_COMBINE : PIO_SAME, a, s, first && dtype == LDK_F32);
         if (st) return st;
-        hipLaunchKernelGGL((k_eig_update_combine<true, double>), grid, block, 0, s, lam_old, lam_full,
-                           (const void *)ws, n, (int64_t)R, m);
-    } else {
-        // real FP64 transform of the new half, staged in the second half of lam_full
-        double *dst = lam_full + n;
-        st = forward_all(kind, LDK_F64, m, R, k1_new, n, false, dst, 2 * n, false, dst, 2 * n, 1.0, s,
-                         dtype == LDK_F32);
-        if (st) return st;
-        hipLaunchKernelGGL((k_eig_update_combine<false, double>), grid, block, 0, s, lam_old,
-                           lam_full, (const void *)dst, 2 * n, (int64_t)R, m);
     }
-    LDK_LAUNCH_CHECK();
     return LDK_OK;
 }
 

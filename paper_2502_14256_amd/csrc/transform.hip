@@ -132,10 +132,21 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int64_t bid)
             const int64_t k = gidx(t + Tn * i);
             const R h = (R)0.70710678118654752440;
             if constexpr (FFT) o = cmul(o, tw_any<R>((uint64_t)k, a.m + 1));
-            const T od = static_cast<const T *>(a.old)[row * n + k];
-            T *full = static_cast<T *>(a.dst) + row * a.dst_row;
-            full[k] = scl(add(od, o), h);
-            full[n + k] = scl(sub(od, o), h);
+            if (a.combine_real) {
+                // eigenvalue update: real FP64 rows, lambda_m +- Re(w)
+                double part;
+                if constexpr (FFT) part = (double)o.re;
+                else part = (double)o;
+                const double od = static_cast<const double *>(a.old)[row * n + k];
+                double *full = static_cast<double *>(a.dst) + row * a.dst_row;
+                full[k] = od + part;
+                full[n + k] = od - part;
+            } else {
+                const T od = static_cast<const T *>(a.old)[row * n + k];
+                T *full = static_cast<T *>(a.dst) + row * a.dst_row;
+                full[k] = scl(add(od, o), h);
+                full[n + k] = scl(sub(od, o), h);
+            }
         } else {
             store_elem<T, ST>(a.dst, row * a.dst_row + gidx(t + Tn * i), o, a.half);
         }
@@ -285,7 +296,7 @@ int launch_pass(int kind, int dtype, int mode, int ld, int st, const PassArgs &a
     if (src_f32) {
         // FP64 forward transform of float data (eigenvalues from an FP32 column)
         if (dtype != LDK_F64 || mode != PM_FWD) return LDK_EINVAL;
-        if (kind == LDK_DNET_B2) return launch_e<double, PM_FWD, true>(IO_SAME, IO_SAME, a, s);
+        if (kind == LDK_DNET_B2) return launch_e<double, PM_FWD, true>(IO_SAME, st, a, s);
         return launch_e<cplx<double>, PM_FWD, true>(ld, st, a, s);
     }
     if (kind == LDK_DNET_B2) {

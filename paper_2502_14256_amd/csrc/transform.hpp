@@ -75,8 +75,10 @@ struct PassArgs {
     int qform_lam;
     // PIO_COMBINE only: the old half's transform [rows][2^m]; the store
     // writes (old + w) / sqrt 2 at k and (old - w) / sqrt 2 at 2^m + k of
-    // dst rows of 2^(m+1), w the pass output (times W_{2^(m+1)}^k, lattice)
+    // dst rows of 2^(m+1), w the pass output (times W_{2^(m+1)}^k, lattice).
+    // With combine_real: FP64 rows old +- Re w, unnormalised (eigenvalues).
     const void *old;
+    int combine_real;
 };
 
 // Global IO of a pass (lattice only; nets are always real):
