@@ -382,9 +382,9 @@ int ldk_rqmc(const ldk_pointset *ps, int64_t n, int integrand, const double *coe
 size_t ldk_rqmc_workspace_bytes(int R, int64_t n);
 
 /* Orthonormal Walsh-Hadamard transform of B FP32 rows of n = 2^m (Sec. 5.3,
- * the recursion of H_m) on the matrix cores: each radix-16 stage is one
- * FP16 matrix instruction [H_16 | H_16] [X_hi ; X_lo] with FP32 sums, where
- * X_hi + X_lo is a two-term FP16 split of the (power-of-two scaled) FP32
+ * the recursion of H_m) on the matrix cores: each radix-16 stage is two
+ * accumulating FP16 matrix instructions H_16 X_lo + H_16 X_hi with FP32
+ * sums, where X_hi + X_lo is a two-term FP16 split of the (power-of-two scaled) FP32
  * data, redone before every stage (about 22 significant bits per stage;
  * normwise error of order 1e-6 against the exact transform).  Same result
  * as ldk_transform(LDK_DNET_B2, ..., LDK_F32, ...) up to that rounding.

@@ -5,10 +5,12 @@
 // 4-bit digits of the index, in any order.  One stage on 16 vectors is the
 // product Y = H_16 X of 16x16 matrices.  The FP32 data are split into two
 // FP16 terms, X = X_hi + X_lo (X_lo = the rounding error of X_hi), and the
-// stage is one matrix instruction with K = 32:
-//   Y = [H_16 | H_16] [X_hi ; X_lo]    (v_mfma_f32_16x16x32_f16, FP32 sums),
+// stage is two accumulating matrix instructions with K = 16:
+//   Y = H_16 X_lo + H_16 X_hi    (v_mfma_f32_16x16x16_f16, FP32 sums),
 // exact in the products (H_16 is +-1) and in the FP32 accumulation up to
-// rounding.  Before every stage the tile is scaled by a power of two so that
+// rounding.  Each lane reads its four elements once and forms both terms
+// (one [H_16 | H_16] instruction with K = 32 would put the high and low
+// terms of an element in two lanes, so every element would be read twice).  Before every stage the tile is scaled by a power of two so that
 // |x| < 2^14 (the FP16 range), tracked from the tile maximum and the growth
 // bound of 16 per stage, and the split is redone from the FP32 result: about
 // 22 significant bits per stage.  A leftover of fewer than 4 index bits runs
@@ -28,7 +30,7 @@ namespace ldk {
 
 namespace {
 
-typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef _Float16 half4 __attribute__((ext_vector_type(4)));
 typedef float float4v __attribute__((ext_vector_type(4)));
 
 constexpr int FM_THREADS = 256;
@@ -121,15 +123,14 @@ __global__ __launch_bounds__(FM_THREADS) void k_fwht_mfma(FmArgs a)
 
     // ---- radix-16 stages on the matrix cores
     // A = [H_16 | H_16]: lane holds A[l % 16][8 (l / 16) + i] = H_16[l % 16][(8 (l/16) + i) % 16]
-    half8 hmat;
+    half4 hmat;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const int k = (8 * (lane >> 4) + i) & 15;
+    for (int i = 0; i < 4; ++i) {
+        const int k = 4 * (lane >> 4) + i;
         hmat[i] = (_Float16)((__popc((lane & 15) & k) & 1) ? -1.0f : 1.0f);
     }
-    const int kb = 8 * ((lane >> 4) & 1);  // digit values read by this lane: kb .. kb + 7
-    const bool lo_half = lane >= 32;       // lanes 32..63 carry the low FP16 terms
-    const int col = lane & 15;             // vector within the instruction
+    const int kb = 4 * (lane >> 4);  // digit values read by this lane: kb .. kb + 3
+    const int col = lane & 15;       // vector within the instruction
     const int ob = 4 * (lane >> 4);        // digit values written: ob .. ob + 3
     const int nvec = S >> 4;
     for (int q = 0; q * 4 + rem < A; ++q) {
@@ -144,16 +145,18 @@ __global__ __launch_bounds__(FM_THREADS) void k_fwht_mfma(FmArgs a)
             const bool live = v < nvec;
             const int w = v & (W - 1), ro = v >> logW;
             const int rlow = ro & ((1 << p) - 1), rhigh = (ro >> p) << (p + 4);
-            half8 bop;
+            half4 bhi, blo;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
+            for (int i = 0; i < 4; ++i) {
                 const int r = rlow | ((kb + i) << p) | rhigh;
                 const float x = live ? tile[pad(r * W + w)] * sc : 0.0f;
                 const _Float16 hi = (_Float16)x;
-                bop[i] = lo_half ? (_Float16)(x - (float)hi) : hi;
+                bhi[i] = hi;
+                blo[i] = (_Float16)(x - (float)hi);
             }
             const float4v zero = {0.0f, 0.0f, 0.0f, 0.0f};
-            const float4v d = __builtin_amdgcn_mfma_f32_16x16x32_f16(hmat, bop, zero, 0, 0, 0);
+            float4v d = __builtin_amdgcn_mfma_f32_16x16x16f16(hmat, blo, zero, 0, 0, 0);
+            d = __builtin_amdgcn_mfma_f32_16x16x16f16(hmat, bhi, d, 0, 0, 0);
             if (live) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
