@@ -491,6 +491,8 @@ def rqmc_bench(K):
     (d = 50, n = 2^15, R = 10, order-3 interlaced LMS + shifted net) and a
     throughput shape (d = 50, n = 2^20, R = 16; shifted lattice and LMS net).
     Cost unit: point coordinates (n d R per estimate)."""
+    import ctypes as C
+
     import numpy as np
     import torch
 
@@ -507,7 +509,7 @@ def rqmc_bench(K):
     def timed(name, ps, n):
         mu_r = torch.empty(ps.R, dtype=torch.float64, device="cuda")
         st = torch.empty(3, dtype=torch.float64, device="cuda")
-        ws = torch.empty(max(int(ldk.lib().ldk_rqmc_workspace_bytes(ps.R, n)), 1),
+        ws = torch.empty(max(int(ldk.lib().ldk_rqmc_workspace_bytes(C.byref(ps._c()), n)), 1),
                          dtype=torch.uint8, device="cuda")
         ms = time_graph(lambda: ldk.rqmc(ps, n, "corner_peak", coef, mu_r=mu_r, stats=st,
                                          ws=ws), K)

@@ -376,10 +376,11 @@ enum { LDK_RQMC_MEAN = 0, LDK_RQMC_STD = 1, LDK_RQMC_HALF = 2, LDK_RQMC_FIELDS =
  * 1 <= n <= the limit of ldk_gen_points.  integrand: LDK_GENZ_*; coef =
  * device double[d] (c_j); u: the oscillatory phase (ignored by the corner
  * peak).  mu_r = device double[R]; stats = device double[LDK_RQMC_FIELDS].
- * ws: ldk_rqmc_workspace_bytes(R, n) bytes. */
+ * ws: ldk_rqmc_workspace_bytes(ps, n) bytes (the tile sums and, for an LMS
+ * net, every replication's scrambled columns, formed once per call). */
 int ldk_rqmc(const ldk_pointset *ps, int64_t n, int integrand, const double *coef, double u,
              double t, double *mu_r, double *stats, void *ws, ldk_stream stream);
-size_t ldk_rqmc_workspace_bytes(int R, int64_t n);
+size_t ldk_rqmc_workspace_bytes(const ldk_pointset *ps, int64_t n);
 
 /* Orthonormal Walsh-Hadamard transform of B FP32 rows of n = 2^m (Sec. 5.3,
  * the recursion of H_m) on the matrix cores: each radix-16 stage is two

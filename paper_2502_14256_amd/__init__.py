@@ -75,7 +75,7 @@ def lib():
             "ldk_wce": ([i32, i32, i32, i32, i32, P, f64, P, P, P, P], i32),
             "ldk_bayes_cubature": ([i32, i32, i32, i32, P, f64, f64, P, f64, P, P, P], i32),
             "ldk_rqmc": ([P, i64, i32, P, f64, f64, P, P, P, P], i32),
-            "ldk_rqmc_workspace_bytes": ([i32, i64], C.c_size_t),
+            "ldk_rqmc_workspace_bytes": ([P, i64], C.c_size_t),
             "ldk_transform": ([i32, i32, i32, i32, i32, P, P, P, P], i32),
             "ldk_eig": ([i32, i32, i32, i32, P, P, P, P], i32),
             "ldk_solve": ([i32, i32, i32, i32, i32, P, f64, P, P, P, P], i32),
@@ -506,7 +506,7 @@ def rqmc(ps: PointSet, n: int, integrand, coef: torch.Tensor, u: float = 0.0, ta
     _need_f64(mu_r, "mu_r")
     _need_f64(stats, "stats")
     if ws is None:
-        nbytes = int(lib().ldk_rqmc_workspace_bytes(ps.R, int(n)))
+        nbytes = int(lib().ldk_rqmc_workspace_bytes(C.byref(ps._c()), int(n)))
         ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
     _check(lib().ldk_rqmc(C.byref(ps._c()), int(n), f, _ptr(coef), float(u), t, _ptr(mu_r),
                           _ptr(stats), _ptr(ws), _stream()), "ldk_rqmc")

@@ -231,10 +231,27 @@ void launch_tiles(const KcolArgs &a, const double *coef, double phase, int64_t n
 
 using namespace ldk;
 
-extern "C" size_t ldk_rqmc_workspace_bytes(int R, int64_t n)
+namespace {
+
+size_t align256_rq(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Tile sums, then (LMS nets) each replication's scrambled columns S_j C_j,
+// formed once instead of in every block of the grid.
+size_t rqmc_ws(const PointsetArgs &a, int64_t n)
 {
-    if (R < 0 || n < 0) return 0;
-    return (size_t)R * (size_t)tiles_of(n, RQ_IT_SMALL) * sizeof(double);
+    size_t b = align256_rq((size_t)a.R * (size_t)tiles_of(n, RQ_IT_SMALL) * sizeof(double));
+    if (a.kind == LDK_DNET_B2 && a.lms)
+        b += (size_t)a.R * (size_t)a.d * (size_t)a.m_max * sizeof(uint64_t);
+    return b;
+}
+
+}  // namespace
+
+extern "C" size_t ldk_rqmc_workspace_bytes(const ldk_pointset *ps, int64_t n)
+{
+    PointsetArgs a;
+    if (validate_pointset(ps, &a) || n < 0) return 0;
+    return rqmc_ws(a, n);
 }
 
 extern "C" int ldk_rqmc(const ldk_pointset *ps, int64_t n, int integrand, const double *coef,
@@ -260,6 +277,19 @@ extern "C" int ldk_rqmc(const ldk_pointset *ps, int64_t n, int integrand, const 
     a.n_max = n;
     hipStream_t s = as_stream(stream);
     double *part = static_cast<double *>(ws);
+    if (a.ps.kind == LDK_DNET_B2 && a.ps.lms && a.ps.m_max > 0) {
+        // scramble the columns once per replication (interlacing of order 1
+        // is the scrambling alone); the tiles then read per-replication
+        // columns and skip the scrambling
+        uint64_t *cols = reinterpret_cast<uint64_t *>(
+            static_cast<unsigned char *>(ws) +
+            align256_rq((size_t)a.ps.R * (size_t)tiles_of(n, RQ_IT_SMALL) * sizeof(double)));
+        st = ldk_interlace(ps, 1, cols, stream);
+        if (st) return st;
+        a.ps.gen = cols;
+        a.ps.gen_rstride = (int64_t)a.ps.d * a.ps.m_max;
+        a.ps.lms = nullptr;
+    }
     const dim3 grid((unsigned)tiles, (unsigned)a.ps.R);
     const double phase = 6.283185307179586476925286766559 * u;
     if (integrand == LDK_GENZ_CORNER_PEAK) {

@@ -1,6 +1,8 @@
 """HIP-graph capture of a whole fit + solve step: several replays, with eager
 work and synchronisations between them, each checked bit for bit against the
 eager result (the library records no memset and no allocation)."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -97,7 +99,8 @@ def test_graph_replays_cubature_and_rqmc(kind):
     st = torch.empty(3, dtype=torch.float64, device="cuda")
     ws_w = ldk._workspace(ldk.OP_WCE, kd, R * nw, m, ldk.F64, "cuda")
     ws_b = ldk._workspace(ldk.OP_BAYES_CUBATURE, kd, R, m, ldk.F64, "cuda")
-    ws_q = torch.empty(int(ldk.lib().ldk_rqmc_workspace_bytes(R, n)), dtype=torch.uint8,
+    ws_q = torch.empty(int(ldk.lib().ldk_rqmc_workspace_bytes(ctypes.byref(ps._c()), n)),
+                       dtype=torch.uint8,
                        device="cuda")
 
     def step():

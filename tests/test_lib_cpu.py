@@ -286,7 +286,11 @@ def test_rqmc_rejects_bad_arguments():
     assert f(P(_ps()), 16, CP, FAKE, 0.0, 2.0, FAKE, None, FAKE, None) == -1      # stats
     assert f(P(_ps()), 16, CP, FAKE, 0.0, 2.0, FAKE, FAKE, None, None) == -1      # ws
     assert f(None, 16, CP, FAKE, 0.0, 2.0, FAKE, FAKE, FAKE, None) == -1
-    # tile sums: R x ceil(n / 512) doubles (room for the small-grid tiling)
-    assert L.ldk_rqmc_workspace_bytes(10, 2**15) == 10 * 64 * 8
-    assert L.ldk_rqmc_workspace_bytes(3, 2049) == 3 * 5 * 8
-    assert L.ldk_rqmc_workspace_bytes(3, 0) == 0
+    # tile sums: R x ceil(n / 512) doubles (room for the small-grid tiling),
+    # 256-byte aligned, then the scrambled columns R x d x m_max of an LMS net
+    w = L.ldk_rqmc_workspace_bytes
+    assert w(P(_ps(kind=ldk.LATTICE, R=10, gen=FAKE)), 2**15) == 10 * 64 * 8
+    assert w(P(_ps(kind=ldk.LATTICE, R=3)), 2049) == 256
+    assert w(P(_ps(R=3, lms=FAKE)), 2049) == 256 + 3 * 4 * 10 * 8
+    assert w(P(_ps(R=3)), 0) == 0
+    assert w(P(_ps(R=0)), 16) == 0  # invalid point set
