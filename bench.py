@@ -338,6 +338,11 @@ def grad_bench(K, warmup):
         return torch.from_numpy(np.ascontiguousarray(a, np.uint64).view(np.int64).copy()).cuda()
 
     ps = ldk.PointSet("dnet", R, d, m, dev_u64(w["gen"]), dev_u64(w["lms"]), dev_u64(w["shift"]))
+    # each randomization's scrambled generating matrices S_j C_j, formed once
+    # (interlacing of order 1): they do not change with the kernel
+    # parameters, and the column and gradient kernels then read
+    # per-replication columns instead of scrambling in every block
+    ps = ldk.interlace(ps, 1, shift=ps.shift)
     kern = ldk.Kernel("dnet", w["alpha"],
                       torch.tensor(w["gamma"], dtype=torch.float64, device="cuda"), w["zeta"])
     y64 = torch.from_numpy(np.ascontiguousarray(w["y"][:, 0, :])).cuda()
