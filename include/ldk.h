@@ -145,7 +145,9 @@ int ldk_gen_points(const ldk_pointset *ps, int64_t n_min, int64_t n_max, uint64_
  * 64 / alpha digits of each source column enter).  cols = uint64[R][d][m_max]
  * device, for a net with flags = LDK_GEN_PER_REPLICATION, lms = NULL and a
  * d-dimensional shift of its own.  alpha in 1..4; src->d must be a multiple
- * of alpha. */
+ * of alpha.  alpha = 1 gives each replication's scrambled columns S_j C_j:
+ * with them (and the same shift) the net yields the same points as the LMS
+ * net, and the kernels that regenerate points skip the scrambling. */
 int ldk_interlace(const ldk_pointset *src, int alpha, uint64_t *cols, ldk_stream stream);
 
 /* First Gram column k1_i = K(x_i, x_0) for i = n_min .. n_max-1 (Sec. 5.4:
