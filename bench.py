@@ -8,11 +8,17 @@ A step is one pass of the whole path over the rank-1 lattice workload
 with the generating vector, shift and responses already resident in HBM.
 The metric counts one Gram solve (K + sigma^2 I)^-1 y per step.
 
-Printed: one JSON line with the metric, per-op timings (HIP events on the
-library's stream), the roofline of the longest single kernel (the point
-words), the fit's and the solve's own rooflines, the marginal-likelihood gradient workload (64 replications of a
-net with n = 2^16, d = 64) under "grad", and the CPU oracle timed on the host
-as a baseline.
+Printed: one JSON line with
+- the metric and per-op timings (HIP events on the library's stream);
+- the roofline of the longest single kernel (the point words), and the fit's
+  and the solve's own rooflines;
+- the marginal-likelihood gradient workload (64 replications of a net with
+  n = 2^16, d = 64) under "grad", and the batched instance table under
+  "batched";
+- the split-FP16 matrix-core FWHT ("fwht_split16"), the higher-order net
+  ("higher_order_net"), kernel cubature ("cubature"), the RQMC estimate
+  ("rqmc"), and the doubling update ("update_double");
+- the CPU oracle timed on the host as a baseline.
 """
 from __future__ import annotations
 
