@@ -355,15 +355,16 @@ bool fit_fused(int kind, int m, int dtype) { return kind == LDK_LATTICE && m >= 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Top-pass geometry of the fused fit: the plan's top pass, narrowed until
-// the column and rhs tiles fit 64 KiB of LDS together, with four elements
-// per thread where the kernel takes it (twice the wavefronts of eight: at
-// one replication of n = 2^20 the pass is latency-bound, 54 us against 58
-// for the fused fit).
+// the column and rhs tiles fit a workgroup's LDS together, with four
+// elements per thread where the kernel takes it.  At one replication of
+// n = 2^20 the plan's 4 + 4 columns fit (68 KiB, eight elements per thread:
+// 49.7 us for the fit against 52.0 with 2 + 2 columns in 64 KiB and four
+// elements per thread), so the tile rows are 64-byte runs.
 PassGeom fit_top_geom(const Plan &pl)
 {
     PassGeom g = pl.pass[pl.P - 1];
     while (g.b0 > 0 && g.logW > 1 &&
-           2 * (((size_t)1 << (g.a + g.logW)) * 17 / 16) * 16 > 65536)
+           2 * (((size_t)1 << (g.a + g.logW)) * 17 / 16) * 16 > LDS_PER_GROUP)
         --g.logW;
     PassGeom g4 = g;
     g4.logE = 2;

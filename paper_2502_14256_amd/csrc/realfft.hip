@@ -562,7 +562,7 @@ bool fit_top_supported(const PassGeom &g)
 {
     const int S = 1 << (g.a + g.logW), Tn = S >> g.logE;
     const size_t lds = 2 * (size_t)(S + (S >> LDS_PAD_SHIFT)) * sizeof(cplx<double>);
-    return (g.logE == 2 || g.logE == 3) && Tn % 64 == 0 && Tn <= 256 && lds <= 65536 &&
+    return (g.logE == 2 || g.logE == 3) && Tn % 64 == 0 && Tn <= 256 && lds <= LDS_PER_GROUP &&
            (g.a + g.logE - 1) / g.logE <= MAX_GROUPS && (g.b0 == 0 || g.logW >= 1);
 }
 

@@ -148,6 +148,9 @@ struct LogProd {
     }
 };
 
+// LDS of one workgroup on gfx950 (the fused fit's top pass takes up to this).
+constexpr size_t LDS_PER_GROUP = 163840;
+
 // Workspace bytes of LDK_OP_MLL / LDK_OP_MLL_ADJOINT (mll.hip).
 size_t mll_ws_bytes(int op, int kind, int64_t R, int m, int dtype);
 // Workspace bytes of LDK_OP_WCE / LDK_OP_BAYES_CUBATURE for B rows (mll.hip).
