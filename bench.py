@@ -42,7 +42,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # profiles/traffic_lattice_m20_d32_f64.md).  Valid only for the kernel source
 # they were taken on: the sources' SHA-1 is checked at run time and the figure
 # reported as null once they change.
-STEP_TRAFFIC = {"read_MiB": 0.15, "write_MiB": 264.00,
+STEP_TRAFFIC = {"read_MiB": 0.17, "write_MiB": 264.00,
                 "sources": ("kcol.hip", "kfactor.hpp", "pointset.hpp", "common.hpp"),
                 "sha1": "f0bfcb66431a54c2f5f278439dcef1b96d3267ae"}
 
