@@ -219,7 +219,7 @@ def main():
                for op in ops}
     # The roofline is taken on the longest single kernel of the step, the
     # points + column launch (the fit is three kernels, the longest of them,
-    # the fused top pass, ~28 us against ~52 us).
+    # the fused top pass, ~23 us against ~48 us).
     dom = "points_column"
     roof_dom = {"kernel": "k_points_kcol_lattice (points_column)", "bound": "hbm",
                 "achieved": op_rows[dom]["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
