@@ -23,7 +23,7 @@ import numpy as np
 import torch
 
 from . import (LdkError, Kernel, OP_EIG, OP_FIT, OP_LOGDET, OP_SOLVE, PointSet, _dtype_code,
-               _kind, _workspace, eig, fit, kernel_column, logdet, solve)
+               _kind, _workspace, eig, fit, interlace, kernel_column, logdet, solve)
 
 
 def _dev_u64(a) -> torch.Tensor:
@@ -77,6 +77,11 @@ class BatchFit:
                 lms = np.stack([instances[i].lms for i in members])
             ps = PointSet(kind, R, d, m_max, _dev_u64(gen[kind]),
                           None if lms is None else _dev_u64(lms), _dev_u64(shift))
+            if lms is not None and m_max > 0:
+                # each instance's scrambled columns S_j C_j, formed once with
+                # the plan (interlacing of order 1): the same points, and the
+                # column kernel no longer scrambles in every block
+                ps = interlace(ps, 1, shift=ps.shift)
             kern = Kernel(kind, np.asarray(alpha_of[kind], np.int32), gamma_d, zeta)
             y = torch.from_numpy(np.ascontiguousarray(
                 np.stack([instances[i].y for i in members]))).to(device="cuda", dtype=dtype)
@@ -116,8 +121,10 @@ class BatchFit:
                 ps = g["ps"]
                 for row in range(g["R"]):
                     sl = slice(row, row + 1)
-                    psr = PointSet(g["kind"], 1, ps.d, ps.m_max, ps.gen,
-                                   None if ps.lms is None else ps.lms[sl], ps.shift[sl])
+                    psr = PointSet(g["kind"], 1, ps.d, ps.m_max,
+                                   ps.gen[sl] if ps.per_replication else ps.gen,
+                                   None if ps.lms is None else ps.lms[sl], ps.shift[sl],
+                                   per_replication=ps.per_replication)
                     self._plain.append((g, sl, psr, ws))
         for g, sl, psr, ws in self._plain:
             kernel_column(g["kern"], psr, 0, g["n"], dtype=self.dtype, out=g["k1"][sl])
