@@ -80,6 +80,9 @@ def parse():
                    help="only run the step eagerly 5 times and a 256 MiB device copy 5 times "
                         "(a short program for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs; the "
                         "copy calibrates the counters), then exit")
+    p.add_argument("--valu-probe", action="store_true",
+                   help="only run the step, the FP32 gradient step and the RQMC estimates a few "
+                        "times (a short program for rocprofv3 --pmc SQ_INSTS_VALU runs), then exit")
     p.add_argument("--copy-probe", action="store_true",
                    help="also run a plain device copy of known size (counter calibration)")
     return p.parse_args()
@@ -138,6 +141,15 @@ def main():
         ldk.points_column(kern, ps, 0, n, dtype=torch.float64, pts=pts, k1=k1)
         # eigenvalues, solve and log-det in one call (shared tile passes)
         ldk.fit("lattice", k1, w["sigma2"], y, lam=lam, c=c, logdet=ld, ws=ws_fit)
+
+    if args.valu_probe:
+        for _ in range(3):
+            step()
+        grad_bench(2, 1, probe=True)
+        rqmc_bench(2)
+        torch.cuda.synchronize()
+        print(json.dumps({"valu_probe": True}), flush=True)
+        return
 
     if args.traffic_probe:
         for _ in range(5):
@@ -321,7 +333,7 @@ def time_graph(fn, K):
     return a.elapsed_time(b) / K
 
 
-def grad_bench(K, warmup):
+def grad_bench(K, warmup, probe=False):
     """Marginal-likelihood gradient of the net workload: 64 replications of
     n = 2^16 points in d = 64 (LMS + digital shift, order-2 DSI kernel,
     gamma_j = 1/j^2, sigma^2 = 1e-3).  A step is the whole gradient for all
@@ -386,6 +398,12 @@ def grad_bench(K, warmup):
         }
 
     names = ["kernel_column", "eig", "mll", "mll_adjoint", "kernel_grad"]
+    if probe:
+        ops = ops_of(buffers(torch.float32), torch.float32)
+        for _ in range(3):
+            for nm in names:
+                ops[nm]()
+        return None
     res = {}
     for dt in (torch.float32, torch.float64):
         b = buffers(dt)
