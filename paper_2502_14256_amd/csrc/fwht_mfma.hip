@@ -10,7 +10,8 @@
 // exact in the products (H_16 is +-1) and in the FP32 accumulation up to
 // rounding.  Each lane reads its four elements once and forms both terms
 // (one [H_16 | H_16] instruction with K = 32 would put the high and low
-// terms of an element in two lanes, so every element would be read twice).  Before every stage the tile is scaled by a power of two so that
+// terms of an element in two lanes, so every element would be read twice).
+// Before every stage the tile is scaled by a power of two so that
 // |x| < 2^14 (the FP16 range), tracked from the tile maximum and the growth
 // bound of 16 per stage, and the split is redone from the FP32 result: about
 // 22 significant bits per stage.  A leftover of fewer than 4 index bits runs
@@ -122,7 +123,7 @@ __global__ __launch_bounds__(FM_THREADS) void k_fwht_mfma(FmArgs a)
     }
 
     // ---- radix-16 stages on the matrix cores
-    // A = [H_16 | H_16]: lane holds A[l % 16][8 (l / 16) + i] = H_16[l % 16][(8 (l/16) + i) % 16]
+    // A = H_16: lane l holds A[l % 16][4 (l / 16) + i], i < 4 (the K = 16 operand layout)
     half4 hmat;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {

@@ -39,40 +39,60 @@ __device__ __forceinline__ double block_sum(double v, double *red)
 }
 
 // s[l] += c_j x_j over every dimension for the lattice points
-// i = first + KC_THREADS l, l < IT, of replication r (first - t a multiple of
-// KC_THREADS IT, so the bits of l are free in first and the bit tricks of the
-// regenerating column apply; the shift is added to the base word before the
-// points are split into high and low halves).
+// i = tile0 + t + KC_THREADS l, l < IT, of replication r (tile0 a multiple of
+// KC_THREADS IT, so the bits of tile0, t and l are disjoint).
+//
+// Natural order: brev(i) g = brev(tile0) g + (rev8(t) g) 2^56 + brev(256 l) g
+// (mod 2^64).  The first term plus the shift is the same for the whole block
+// and alone sets the low word; the other two only add to the high word.  So
+// x = hi 2^-32 + lo 2^-64 with lo shared by the block, and sum_j c_j x_j is
+// taken as (sum_j c_j hi_j) 2^-32 + (sum_j c_j lo_j) 2^-64: one add, one
+// conversion and one multiply-add per point and dimension, the low-word
+// terms summed once per thread.
+//
+// Linear order: the shift is added to the base word before the points are
+// split into high and low halves.
 template <int ORDER, int IT>
 __device__ __forceinline__ void lattice_dot(const PointsetArgs &ps, const double *__restrict__ coef,
-                                            int r, int64_t first, double (&s)[IT])
+                                            int r, int64_t tile0, double (&s)[IT])
 {
     static_assert(IT <= 8 && KC_LOG_THREADS == 8, "offset table assumes up to 8 x 256");
-    constexpr uint64_t br3[8] = {0, 4, 2, 6, 1, 5, 3, 7};
+    constexpr uint32_t br3[8] = {0, 4, 2, 6, 1, 5, 3, 7};
     const int d = ps.d, m = ps.m_max;
-    const uint64_t bfirst = ORDER == LDK_NATURAL ? brev64((uint64_t)first) : (uint64_t)first;
-    for (int j = 0; j < d; ++j) {
-        const uint64_t g = ps.gen[j];
-        const uint64_t sh = ps.shift ? ps.shift[(size_t)r * d + j] : 0;
-        const double c = coef[j];
-        uint64_t base, G;
-        if constexpr (ORDER == LDK_NATURAL) {
-            base = bfirst * g + sh;
-            G = g << 53;
-        } else {
-            base = (m == 0 ? 0 : ((bfirst * g) << (64 - m))) + sh;
-            G = m <= 8 ? 0 : ((g << 8) << (64 - m));
-        }
-        const double lo_p = lo_part<double>((uint32_t)base);
+    if constexpr (ORDER == LDK_NATURAL) {
+        const uint64_t btile = brev64((uint64_t)tile0);
+        const uint32_t t8 = __builtin_bitreverse32((uint32_t)threadIdx.x) >> 24;
+        // sums in units of 2^-32 (high words) and 2^-64 (low words): the
+        // powers of two are applied once at the end, exactly
+        double s_lo = 0.0;
+        for (int j = 0; j < d; ++j) {
+            const uint64_t g = ps.gen[j];
+            const uint64_t sh = ps.shift ? ps.shift[(size_t)r * d + j] : 0;
+            const double c = coef[j];
+            const uint64_t B = btile * g + sh;
+            // rev8(t) g mod 2^8 in the top byte (a 24-bit multiply: only the
+            // low 8 bits of the product are kept); one register word per
+            // thread, to which each point adds a scalar offset
+            uint32_t tg;
+            asm("v_mul_u32_u24 %0, %1, %2" : "=v"(tg) : "s"((uint32_t)g), "v"(t8));
+            const uint32_t h = opaque32((uint32_t)(B >> 32) + (tg << 24));
+            const uint32_t Gh = (uint32_t)(g << 21);  // high word of brev(256) g = g 2^53
+            s_lo = fma(c, (double)(uint32_t)B, s_lo);
 #pragma unroll
-        for (int l = 0; l < IT; ++l) {
-            double x;
-            if constexpr (ORDER == LDK_NATURAL)
-                x = unit_hl<double>((uint32_t)(base >> 32) + (uint32_t)br3[l] * (uint32_t)(G >> 32),
-                                    lo_p);
-            else
-                x = unit<double>(base + (uint64_t)l * G);
-            s[l] = fma(c, x, s[l]);
+            for (int l = 0; l < IT; ++l) s[l] = fma(c, (double)(h + br3[l] * Gh), s[l]);
+        }
+#pragma unroll
+        for (int l = 0; l < IT; ++l) s[l] = fma(s_lo, 0x1p-32, s[l]) * 0x1p-32;
+    } else {
+        const uint64_t first = (uint64_t)tile0 + threadIdx.x;
+        for (int j = 0; j < d; ++j) {
+            const uint64_t g = ps.gen[j];
+            const uint64_t sh = ps.shift ? ps.shift[(size_t)r * d + j] : 0;
+            const double c = coef[j];
+            const uint64_t base = (m == 0 ? 0 : ((first * g) << (64 - m))) + sh;
+            const uint64_t G = m <= 8 ? 0 : ((g << 8) << (64 - m));
+#pragma unroll
+            for (int l = 0; l < IT; ++l) s[l] = fma(c, unit<double>(base + (uint64_t)l * G), s[l]);
         }
     }
 }
@@ -149,7 +169,7 @@ __global__ __launch_bounds__(KC_THREADS) void k_rqmc_tiles(KcolArgs a, const dou
         __shared__ NetLds L;
         net_dot<IT>(a, L, coef, r, tile0, s);
     } else {
-        lattice_dot<ORDER, IT>(a.ps, coef, r, first, s);
+        lattice_dot<ORDER, IT>(a.ps, coef, r, tile0, s);
     }
     double acc = 0.0;
 #pragma unroll
