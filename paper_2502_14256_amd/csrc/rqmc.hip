@@ -38,6 +38,16 @@ __device__ __forceinline__ double block_sum(double v, double *red)
     return s;
 }
 
+// A 32-bit word to double as one conversion instruction (left to itself the
+// optimiser may widen it into a 64-bit conversion sequence, or copy the
+// source word first).
+__device__ __forceinline__ double cvt_u32(uint32_t v)
+{
+    double r;
+    asm("v_cvt_f64_u32 %0, %1" : "=v"(r) : "v"(v));
+    return r;
+}
+
 // s[l] += c_j x_j over every dimension for the lattice points
 // i = tile0 + t + KC_THREADS l, l < IT, of replication r (tile0 a multiple of
 // KC_THREADS IT, so the bits of tile0, t and l are disjoint).
@@ -98,7 +108,9 @@ __device__ __forceinline__ void lattice_dot(const PointsetArgs &ps, const double
 }
 
 // The same for net points: scrambled columns and XOR steps from the LDS
-// tables of the regenerating column, then the digital shift.
+// tables of the regenerating column, the digital shift folded into the
+// starting word.  The high and low words of a point are summed apart (no
+// product of the two conversions per point).
 template <int IT>
 __device__ __forceinline__ void net_dot(const KcolArgs &a, NetLds &L, const double *__restrict__ coef,
                                         int r, int64_t tile0, double (&s)[IT])
@@ -108,6 +120,11 @@ __device__ __forceinline__ void net_dot(const KcolArgs &a, NetLds &L, const doub
     const bool gray = a.ps.order == LDK_GRAY;
     const uint64_t code_tile = gray ? gray_code((uint64_t)tile0) : (uint64_t)tile0;
     const uint32_t code_t = gray ? (uint32_t)gray_code((uint64_t)t) : (uint32_t)t;
+    // sums of c_j hi_j and c_j lo_j for x = hi 2^-32 + lo 2^-64, scaled by
+    // the powers of two once at the end (exactly)
+    double s_lo[IT];
+#pragma unroll
+    for (int l = 0; l < IT; ++l) s_lo[l] = 0.0;
     for (int jc = 0; jc < d; jc += KC_DIM_CHUNK) {
         const int DB = min(KC_DIM_CHUNK, d - jc);
         build_net_chunk(a, L, r, jc, DB, code_tile);
@@ -115,10 +132,12 @@ __device__ __forceinline__ void net_dot(const KcolArgs &a, NetLds &L, const doub
             const int j = jc + jj;
             const uint64_t sh = a.ps.shift ? a.ps.shift[(size_t)r * d + j] : 0;
             const double c = coef[j];
-            uint64_t z = L.zb[jj] ^ L.nib[jj][0][code_t & 15] ^ L.nib[jj][1][(code_t >> 4) & 15];
+            // the shift enters once: XOR steps commute with it
+            uint64_t z = L.zb[jj] ^ L.nib[jj][0][code_t & 15] ^ L.nib[jj][1][(code_t >> 4) & 15] ^ sh;
 #pragma unroll
             for (int l = 0; l < IT; ++l) {
-                s[l] = fma(c, unit<double>(z ^ sh), s[l]);
+                s[l] = fma(c, cvt_u32((uint32_t)(z >> 32)), s[l]);
+                s_lo[l] = fma(c, cvt_u32((uint32_t)z), s_lo[l]);
                 // past the last index of the net the step columns are zero
                 // (such points are masked by the caller)
                 const uint64_t nb = ((uint64_t)tile0 >> sft) + (uint64_t)l + 1;
@@ -126,6 +145,8 @@ __device__ __forceinline__ void net_dot(const KcolArgs &a, NetLds &L, const doub
             }
         }
     }
+#pragma unroll
+    for (int l = 0; l < IT; ++l) s[l] = fma(s_lo[l], 0x1p-32, s[l]) * 0x1p-32;
 }
 
 // b^-e for an integer e >= 1 by binary powering (e is block-uniform): about
