@@ -98,6 +98,21 @@ def test_rqmc_parity(orc, integrand, case):
     _check(f"rqmc_{integrand}_{'-'.join(map(str, case))}", mu_r, stats, ref, y, integrand, c, n)
 
 
+# Enough tiles of 8 points per thread (n R >= 2^20) that the kernel takes
+# that form, with ragged ends of the last tile
+CASES_IT8 = [  # kind, order, lms, d, m, R, n
+    ("lattice", "natural", False, 7, 18, 5, 2**18 - 1000),
+    ("lattice", "linear", False, 3, 18, 4, 2**18),
+    ("dnet", "natural", True, 7, 18, 5, 2**18 - 1000),
+    ("dnet", "gray", True, 5, 18, 4, 2**18),
+]
+
+
+@pytest.mark.parametrize("case", CASES_IT8, ids=lambda c: "-".join(map(str, c)))
+def test_rqmc_parity_eight_per_thread(orc, case):
+    test_rqmc_parity(orc, "corner_peak", case)
+
+
 def _paper_shape(R=10, d=50, m=15, alpha=3, order="natural"):
     src = W.small_net(2502, m=m, d=alpha * d, R=R)
     shift = np.random.default_rng(7).integers(0, 2**64, size=(R, d), dtype=np.uint64)
