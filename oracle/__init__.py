@@ -66,7 +66,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liborc.so")
-_SRC = ["orc_points.c", "orc_kernels.c", "orc_algebra.c", "orc_mll.c"]
+_SRC = ["orc_points.c", "orc_kernels.c", "orc_algebra.c", "orc_mll.c", "orc_mll_ld.c"]
 
 LATTICE, DNET = 0, 1
 NATURAL, LINEAR, GRAY = 0, 1, 2
@@ -89,7 +89,7 @@ def lib():
     global _lib
     if _lib is None:
         newest_src = max(os.path.getmtime(os.path.join(_HERE, s))
-                         for s in _SRC + ["orc.h", "orc_algebra.inc"])
+                         for s in _SRC + ["orc.h", "orc_algebra.inc", "orc_kernels.inc"])
         if not os.path.exists(_SO) or os.path.getmtime(_SO) < newest_src:
             build()
         L = C.CDLL(_SO)
@@ -114,6 +114,7 @@ def lib():
             "orc_mll": [i32, i32, i32, P, f64, P, P, P, P],
             "orc_mll_adjoint": [i32, i32, i32, P, P],
             "orc_kernel_grad": [i32, i32, i32, i64, P, P, P, P, f64, P, P],
+            "orc_mll_grad_ld": [i32, i32, i32, i32, P, P, P, P, f64, f64, P, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -451,6 +452,22 @@ def mll_grad(w: dict, gamma=None, zeta=None, sigma2=None, y=None) -> dict:
     kg = kernel_grad(w["kind"], pts, x0, w["alpha"], gamma, zeta, a)
     grad = np.concatenate([kg, ds[:, None]], axis=1)
     return dict(L=L, grad=grad, k1=k1, lam=lam, g=g, a=a)
+
+
+def mll_grad_ld(w: dict, y=None) -> dict:
+    """The same step as mll_grad with every intermediate in long double (an
+    error reference only): L[R], grad[R][d + 2], rounded to double."""
+    y = _c(w["y"][:, 0, :] if y is None else y, np.float64)
+    pts = _c(points(w), np.uint64)
+    x0 = _c(points(w, 0, 1)[:, 0, :], np.uint64)
+    R, n, d = pts.shape
+    L = np.empty(R)
+    grad = np.empty((R, d + 2))
+    _check(lib().orc_mll_grad_ld(kind_code(w["kind"]), R, d, n.bit_length() - 1, _p(pts), _p(x0),
+                                 _p(_c(w["alpha"], np.int32)), _p(_c(w["gamma"], np.float64)),
+                                 float(w["zeta"]), float(w["sigma2"]), _p(y), _p(L), _p(grad)),
+           "mll_grad_ld")
+    return dict(L=L, grad=grad)
 
 
 # ---------------------------------------------------------------------------

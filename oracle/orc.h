@@ -81,6 +81,11 @@ int orc_matvec_ld(int kind, int R, int nrhs, int m, const double *lam, const dou
                   double *out);
 int orc_logdet_ld(int R, int m, const double *lam, double sigma2, double *out);
 int orc_transform_ld(int kind, int dir, int B, int m, const double *in, double *out);
+/* The whole likelihood-gradient step in long double (error reference):
+ * pts [R][n][d], x0 [R][d], y [R][n] -> L [R], grad [R][d + 2]. */
+int orc_mll_grad_ld(int kind, int R, int d, int m, const uint64_t *pts, const uint64_t *x0,
+                    const int *alpha, const double *gamma, double zeta, double sigma2,
+                    const double *y, double *L, double *grad);
 
 #ifdef __cplusplus
 }

@@ -184,3 +184,9 @@ int orc_eig_update_double(int kind, int R, int m, const double *lam_old,
     }
     return 0;
 }
+
+/* Long-double transforms on long-double data, for the extended-precision
+ * twin of the likelihood path (orc_mll_ld.c). */
+void orc_fwht_ldr(int64_t n, long double *x) { ldb_fwht(n, x); }
+void orc_fftbr_ldr(int64_t n, long double complex *x) { ldb_fftbr(n, x); }
+void orc_ifftbr_ldr(int64_t n, long double complex *x) { ldb_ifftbr(n, x); }

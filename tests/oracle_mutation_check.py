@@ -1,19 +1,28 @@
-"""Mutation check of the oracle pins (run by hand on the CPU: python tests/oracle_mutation_check.py).
+"""Mutation check of the oracle pins (run by hand on the CPU:
+python tests/oracle_mutation_check.py).  Not collected by pytest.
 
-Plants one plausible mistake at a time in the C oracle, runs the CPU test
-suite, and reports whether the pins catch it; the sources are restored after
-each run.  Not collected by pytest."""
-import subprocess, sys, os
-os.chdir(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+Copies the tree the CPU suite needs (oracle/, tests/, workloads/, the
+package with its built library, include/) into a temporary directory, checks
+that the unmutated copy passes ``pytest -m "not gpu"``, then plants one
+plausible mistake at a time in the copy's oracle and reruns that suite:
+a mistake is CAUGHT when some pin fails.  The tracked sources are never
+touched."""
+import os
+import shutil
+import subprocess
+import sys
+import tempfile
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 muts = [
- ("oracle/orc_kernels.c", "(701.0 / 294.0)", "(701.0 / 295.0)"),
- ("oracle/orc_kernels.c", "return -1.0 + b * x * x - 5.0", "return -1.0 - b * x * x - 5.0"),
- ("oracle/orc_kernels.c", "return -1.0 - b * x + 2.5 * (1.0 - t1);", "return -1.0 + b * x + 2.5 * (1.0 - t1);"),
- ("oracle/orc_kernels.c", "series / 48.0", "series / 47.0"),
- ("oracle/orc_kernels.c", "(digit(delta, a + 1) ? -1.0 : 1.0)", "(digit(delta, a + 2) ? -1.0 : 1.0)"),
- ("oracle/orc_kernels.c", "const double sign = (alpha % 2 == 1) ? 1.0 : -1.0;", "const double sign = 1.0;"),
- ("oracle/orc_kernels.c", "1.0 / 42.0};", "1.0 / 41.0};"),
- ("oracle/orc_kernels.c", "return 1.0 - 3.0 * t1;", "return 1.0 - 2.0 * t1;"),
+ ("oracle/orc_kernels.inc", "((REAL)701 / 294)", "((REAL)701 / 295)"),
+ ("oracle/orc_kernels.inc", "return -1 + b * x * x - 5", "return -1 - b * x * x - 5"),
+ ("oracle/orc_kernels.inc", "return -1 - b * x + (REAL)5 / 2 * (1 - t1);", "return -1 + b * x + (REAL)5 / 2 * (1 - t1);"),
+ ("oracle/orc_kernels.inc", "series / 48 ", "series / 47 "),
+ ("oracle/orc_kernels.inc", "(digit(delta, a + 1) ? -1 : 1)", "(digit(delta, a + 2) ? -1 : 1)"),
+ ("oracle/orc_kernels.inc", "const REAL sign = (alpha % 2 == 1) ? 1 : -1;", "const REAL sign = 1;"),
+ ("oracle/orc_kernels.inc", "(REAL)1 / 42};", "(REAL)1 / 41};"),
+ ("oracle/orc_kernels.inc", "return 1 - 3 * t1;", "return 1 - 2 * t1;"),
  ("oracle/orc_algebra.inc", "const REAL ang = -2 * PI_R", "const REAL ang = 2 * PI_R"),
  ("oracle/orc_algebra.inc", "x[k + j + half] = w * (a - b) * h;", "x[k + j + half] = (a - b) * h;"),
  ("oracle/orc_algebra.inc", "for (int64_t half = 1; half < n; half *= 2)", "for (int64_t half = 1; half < n / 2; half *= 2)"),
@@ -47,17 +56,43 @@ muts = [
  ("oracle/__init__.py", "return np.ldexp(np.asarray(words, dtype=np.uint64).astype(np.float64), -64)", "return np.ldexp(np.asarray(words, dtype=np.uint64).astype(np.float64), -63)"),
  ("oracle/__init__.py", "return np.cos(2.0 * np.pi * u + x @ np.asarray(c, np.float64))", "return np.cos(np.pi * u + x @ np.asarray(c, np.float64))"),
 ]
+
 res = []
-for f, a, b in muts:
-    src = open(f).read()
-    assert src.count(a) >= 1, (f, a)
-    open(f, 'w').write(src.replace(a, b, 1))
-    try:
-        r = subprocess.run([sys.executable, '-m', 'pytest', 'tests/', '-q', '-x', '-p', 'no:cacheprovider'], capture_output=True, text=True, timeout=600)
-        caught = r.returncode != 0
-    finally:
-        open(f, 'w').write(src)
-    res.append((caught, f, b[:60]))
-    print('CAUGHT ' if caught else 'MISSED ', f, repr(b[:70]), flush=True)
-subprocess.run([sys.executable, '-c', 'import sys; sys.path.insert(0,"."); import oracle; oracle.build()'])
-print(sum(c for c,_,_ in res), 'of', len(res), 'caught')
+
+
+def run_suite(cwd):
+    r = subprocess.run([sys.executable, "-m", "pytest", "tests/", "-q", "-x", "-m", "not gpu",
+                        "-p", "no:cacheprovider"], cwd=cwd, capture_output=True, text=True,
+                       timeout=900)
+    return r
+
+
+def main():
+    with tempfile.TemporaryDirectory(prefix="orc_mut_") as tmp:
+        ign = shutil.ignore_patterns("__pycache__", "*.pyc", "liborc.so*", "_build", "*.o")
+        for d in ("oracle", "tests", "workloads", "paper_2502_14256_amd", "include"):
+            shutil.copytree(os.path.join(ROOT, d), os.path.join(tmp, d), ignore=ign)
+        for f in ("pytest.ini",):
+            shutil.copy(os.path.join(ROOT, f), tmp)
+        base = run_suite(tmp)
+        if base.returncode != 0:
+            print(base.stdout[-3000:], base.stderr[-3000:])
+            sys.exit("the unmutated copy does not pass the CPU suite: no mutation result is valid")
+        print("baseline (unmutated copy):", base.stdout.strip().splitlines()[-1], flush=True)
+        for f, a, b in muts:
+            path = os.path.join(tmp, f)
+            src = open(path).read()
+            assert src.count(a) >= 1, (f, a)
+            open(path, "w").write(src.replace(a, b, 1))
+            try:
+                r = run_suite(tmp)
+                caught = r.returncode != 0
+            finally:
+                open(path, "w").write(src)
+            res.append((caught, f, b[:60]))
+            print("CAUGHT " if caught else "MISSED ", f, repr(b[:70]), flush=True)
+    print(sum(c for c, _, _ in res), "of", len(res), "caught")
+
+
+if __name__ == "__main__":
+    main()

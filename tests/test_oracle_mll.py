@@ -144,3 +144,94 @@ def test_mll_sigma_derivative_and_constant():
         assert np.allclose(L, -yy / (2 * s2) - 8 * math.log(s2) - 8 * math.log(2 * math.pi),
                            rtol=1e-13)
         assert np.allclose(ds, yy / (2 * s2) - 8, rtol=1e-12)
+
+
+def _pair_factors_by_columns(kind, alpha, pts_r):
+    """F[j][a][b] = K_{alpha_j}(x_a (-) x_b), column b at a time: the
+    one-dimensional kernel column anchored at point b with gamma = zeta = 1
+    is 1 + K_{alpha_j}(x_a (-) x_b)."""
+    n, d = pts_r.shape
+    F = np.empty((d, n, n))
+    for j in range(d):
+        col = np.ascontiguousarray(pts_r[None, :, j:j + 1])
+        for b in range(n):
+            F[j, :, b] = O.kernel_column(kind, col, col[:, b, :], [int(alpha[j])], [1.0],
+                                         1.0)[0] - 1.0
+    return F
+
+
+@pytest.mark.parametrize("kind", ["lattice", "dnet"])
+def test_gradient_dense_at_n256_d64(kind):
+    """The gradient workload's dense check: n = 2^8, d = 64 (order-2 kernel,
+    gamma_j = 1/j^2, sigma2 = 1e-3), dense Gram and the trace-form gradient
+    against the eigenbasis gradient.  Tolerance from the conditioning: the
+    dense solve and inverse carry about kappa u with
+    kappa = (lambda_max + s2) / (lambda_min + s2)."""
+    m, d = 8, 64
+    w = _inst(kind, 64, m, d, 1, [2] * d, 1.0 / np.arange(1, d + 1) ** 2, zeta=1.0, sigma2=1e-3)
+    y = w["y"][:, 0, :]
+    fast = O.mll_grad(w)
+    pts = O.points(w)
+    n = 2**m
+    F = _pair_factors_by_columns(kind, w["alpha"], pts[0])
+    fac = 1.0 + w["gamma"][:, None, None] * F
+    K = w["zeta"] * np.prod(fac, axis=0)
+    s2 = w["sigma2"]
+    Ks = K + s2 * np.eye(n)
+    c = np.linalg.solve(Ks, y[0])
+    Ki = np.linalg.inv(Ks)
+    sign, ld = np.linalg.slogdet(Ks)
+    assert sign > 0
+    L = -0.5 * y[0] @ c - 0.5 * ld - 0.5 * n * math.log(2 * math.pi)
+    G = []
+    # prefix / suffix products of the factors (no division by a factor)
+    pre = np.ones((d + 1, n, n))
+    for j in range(d):
+        pre[j + 1] = pre[j] * fac[j]
+    suf = np.ones((n, n))
+    dK = [None] * d
+    for j in range(d - 1, -1, -1):
+        dK[j] = w["zeta"] * w["gamma"][j] * F[j] * pre[j] * suf
+        suf = suf * fac[j]
+    dK += [K, s2 * np.eye(n)]
+    T1 = np.array([0.5 * c @ D @ c for D in dK])
+    T2 = np.array([0.5 * np.sum(Ki * D.T) for D in dK])
+    G = T1 - T2
+    lam = np.linalg.eigvalsh(Ks)
+    kappa = lam.max() / lam.min()
+    u = 2.0**-53
+    # each trace-form term carries the dense solve's / inverse's relative
+    # error (backward stable: about n u kappa) on its own magnitude, and G is
+    # their difference; the eigenbasis side is far more accurate
+    scale_t = np.abs(T1) + 0.5 * np.linalg.norm(Ki) * np.array([np.linalg.norm(D) for D in dK])
+    tol_g = 4 * n * u * kappa * scale_t
+    tol_L = 4 * n * u * kappa * (abs(L) + abs(y[0] @ c))
+    assert abs(fast["L"][0] - L) <= tol_L, (fast["L"][0], L, tol_L)
+    err = np.abs(fast["grad"][0] - G)
+    assert np.all(err <= tol_g), (np.max(err / tol_g), err[np.argmax(err / tol_g)])
+
+
+@pytest.mark.parametrize("kind,alpha", CASES)
+def test_gradient_central_differences_h1e6(kind, alpha):
+    """Central differences with the step the gradient workload states
+    (h = 1e-6).  Tolerance: twice the O(h^2) truncation estimated from the
+    same difference at 2h (FD(2h) - FD(h) = 3 c h^2), plus the objective's
+    rounding 8 (m + 4) u |L| on each evaluation, divided by 2h."""
+    m, d = 10, 3
+    w = _inst(kind, 12, m, d, 1, alpha, [0.8, 0.6, 0.4], zeta=0.7, sigma2=5e-3)
+    theta = np.concatenate([np.log(w["gamma"]), [math.log(w["zeta"]), math.log(w["sigma2"])]])
+
+    def L(th):
+        return O.mll_grad(w, gamma=np.exp(th[:d]), zeta=math.exp(th[d]),
+                          sigma2=math.exp(th[d + 1]))["L"][0]
+
+    grad = O.mll_grad(w)["grad"][0]
+    h = 1e-6
+    rnd = 8 * (m + 4) * 2.0**-53 * abs(L(theta))
+    for p in range(d + 2):
+        e = np.zeros(d + 2)
+        e[p] = h
+        fd1 = (L(theta + e) - L(theta - e)) / (2 * h)
+        fd2 = (L(theta + 2 * e) - L(theta - 2 * e)) / (4 * h)
+        tol = 2 * abs(fd2 - fd1) / 3 + 2 * rnd / (2 * h) + 2 * rnd / (4 * h)
+        assert abs(fd1 - grad[p]) <= tol, (p, fd1, grad[p], tol)
