@@ -202,6 +202,18 @@ int ldk_eig(int kind, int R, int m, int dtype, const void *k1, double *lam, void
 int ldk_solve(int kind, int R, int nrhs, int m, int dtype, const double *lam, double sigma2,
               const void *y, void *c, void *ws, ldk_stream stream);
 
+/* ldk_solve, checked: K + sigma^2 I = V (Lambda + sigma^2 I) conj(V) with V
+ * unitary (Sec. 5.4) is positive definite exactly when every
+ * lambda_k + sigma^2 > 0.  This variant first counts, on the device, the
+ * eigenvalues of every row of lam that fail that test (NaN fails), waits for
+ * the count (it SYNCHRONISES `stream`), and returns LDK_ENOTSPD without
+ * enqueueing the solve when it is not zero; otherwise it enqueues exactly
+ * what ldk_solve enqueues and returns.  Same arguments and layouts as
+ * ldk_solve.  Checked calls on one device are serialised by the library
+ * (they share one device counter). */
+int ldk_solve_checked(int kind, int R, int nrhs, int m, int dtype, const double *lam,
+                      double sigma2, const void *y, void *c, void *ws, ldk_stream stream);
+
 /* Matvec K y = V (conj(V) y (.) lambda) (Sec. 5.4); layout as ldk_solve. */
 int ldk_matvec(int kind, int R, int nrhs, int m, int dtype, const double *lam, const void *y,
                void *out, void *ws, ldk_stream stream);
@@ -212,6 +224,12 @@ int ldk_matvec(int kind, int R, int nrhs, int m, int dtype, const double *lam, c
  * lambda_k + sigma^2 <= 0 yields NaN.  ws: ldk_workspace_bytes(LDK_OP_LOGDET). */
 int ldk_logdet(int R, int m, const double *lam, double sigma2, double *out, void *ws,
                ldk_stream stream);
+
+/* ldk_logdet, checked: returns LDK_ENOTSPD (and enqueues nothing more)
+ * when some lambda_k + sigma^2 <= 0 or is NaN, instead of a NaN log-det;
+ * SYNCHRONISES `stream` (see ldk_solve_checked).  Same arguments. */
+int ldk_logdet_checked(int R, int m, const double *lam, double sigma2, double *out, void *ws,
+                       ldk_stream stream);
 
 /* The fit of Sec. 5.4 in one call: lam = eigenvalues of k1 (as ldk_eig),
  * c = (K + sigma^2 I)^-1 y (as ldk_solve, nrhs right-hand sides per
@@ -371,11 +389,18 @@ enum { LDK_RQMC_MEAN = 0, LDK_RQMC_STD = 1, LDK_RQMC_HALF = 2, LDK_RQMC_FIELDS =
  *   stats[LDK_RQMC_HALF] = t sigma / sqrt(R), t = the Student-t quantile
  *                          t_{R-1, tau/2} of the 100(1 - tau)% interval
  *                          mu +- HALF, passed in by the caller.
- * The points are regenerated inside the kernel (never written to memory);
- * coordinates are u 2^-64 rounded to the nearest double; every sum is FP64
- * in a fixed order.  ps: any point set ldk_gen_points accepts (shifted
- * lattice, LMS + digitally shifted net, per-replication interlaced columns);
- * 1 <= n <= the limit of ldk_gen_points.  integrand: LDK_GENZ_*; coef =
+ * The points are regenerated inside the kernel (never written to memory).
+ * A coordinate word u is split into its exact high and low 32-bit halves,
+ * x_j = hi 2^-32 + lo 2^-64, and s = sum_j c_j x_j is formed as
+ * 2^-32 sum_j c_j hi_j + 2^-64 sum_j c_j lo_j (each half's products summed
+ * in FP64, no coordinate rounded to 53 bits first), so |s - s_exact| is
+ * below about 2 d u sum_j |c_j x_j| (u = 2^-53); the corner peak's power is
+ * taken by binary powering of its integer exponent.  Every sum over points
+ * is FP64 in a fixed order.  ps: any point set ldk_gen_points accepts
+ * (shifted lattice, LMS + digitally shifted net, per-replication columns
+ * with or without scrambles); 1 <= n <= the limit of ldk_gen_points.  A
+ * natural-order lattice with n so large that the dispatch would exceed
+ * 2^32 work items along x (n above about 2^35) gives LDK_ENOTSUP.  integrand: LDK_GENZ_*; coef =
  * device double[d] (c_j); u: the oscillatory phase (ignored by the corner
  * peak).  mu_r = device double[R]; stats = device double[LDK_RQMC_FIELDS].
  * ws: ldk_rqmc_workspace_bytes(ps, n) bytes (the tile sums and, for an LMS
@@ -393,6 +418,21 @@ size_t ldk_rqmc_workspace_bytes(const ldk_pointset *ps, int64_t n);
  * as ldk_transform(LDK_DNET_B2, ..., LDK_F32, ...) up to that rounding.
  * in, out = device float[B][n]; may alias exactly.  No workspace. */
 int ldk_fwht_split16(int B, int m, const float *in, float *out, ldk_stream stream);
+
+/* Quantiles of the interval statistics (host functions, no device work):
+ * the standard normal quantile z_p (the credible level of
+ * ldk_bayes_cubature: z = z_{(1 + level)/2}) and the Student-t quantile
+ * t_{dof, p} (eq. RQMC's interval uses t = t_{R-1, 1 - tau/2}).
+ * Normal: start from the rational approximation 26.2.23 of Abramowitz and
+ * Stegun, then Halley steps on Phi(x) - p (Phi through erfc, tail-side
+ * residuals); relative error about 1e-15.  Student t: closed forms for
+ * dof 1 and 2; otherwise the Cornish-Fisher start (Abramowitz and Stegun
+ * 26.7.5) and Newton steps on the upper tail (1/2) I_{dof/(dof+t^2)}(dof/2, 1/2),
+ * the regularised incomplete beta function by its continued fraction.
+ * ldk_normal_quantile returns NaN unless 0 < p < 1; ldk_student_t_quantile
+ * returns LDK_EINVAL unless 0 < p < 1, dof >= 1 and out != NULL. */
+double ldk_normal_quantile(double p);
+int ldk_student_t_quantile(double p, int dof, double *out);
 
 typedef enum {
     LDK_OP_TRANSFORM = 0,

@@ -36,7 +36,8 @@ EXPORTS = [
     "ldk_workspace_bytes", "ldk_strerror", "ldk_last_hip_error", "ldk_version",
     "ldk_mll", "ldk_mll_adjoint", "ldk_kernel_grad", "ldk_kernel_grad_workspace_bytes",
     "ldk_fwht_split16", "ldk_fit", "ldk_points_column", "ldk_interlace", "ldk_wce",
-    "ldk_bayes_cubature", "ldk_rqmc", "ldk_rqmc_workspace_bytes",
+    "ldk_bayes_cubature", "ldk_rqmc", "ldk_rqmc_workspace_bytes", "ldk_solve_checked",
+    "ldk_logdet_checked", "ldk_normal_quantile", "ldk_student_t_quantile",
 ]
 
 
@@ -93,6 +94,10 @@ def lib():
             "ldk_kernel_grad_workspace_bytes": ([i32, i32, i64, i64, i32], C.c_size_t),
             "ldk_fwht_split16": ([i32, i32, P, P, P], i32),
             "ldk_fit": ([i32, i32, i32, i32, i32, P, f64, P, P, P, P, P, P], i32),
+            "ldk_solve_checked": ([i32, i32, i32, i32, i32, P, f64, P, P, P, P], i32),
+            "ldk_logdet_checked": ([i32, i32, P, f64, P, P, P], i32),
+            "ldk_normal_quantile": ([f64], f64),
+            "ldk_student_t_quantile": ([f64, i32, P], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -132,9 +137,36 @@ def _cplx(dtype_code: int):
     return torch.complex128 if dtype_code == F64 else torch.complex64
 
 
-def _need(t: torch.Tensor, name: str):
-    if not t.is_cuda or not t.is_contiguous():
+def _need(t: torch.Tensor, name: str, device=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
         raise LdkError(f"{name} must be a contiguous device tensor")
+    if device is not None and t.device != torch.device(device):
+        raise LdkError(f"{name} is on {t.device}, expected {device}")
+
+
+def _need_out(t: torch.Tensor, name: str, dtype: torch.dtype, shape, device):
+    """A caller-supplied output: contiguous, on `device`, of `dtype` and
+    exactly numel(shape) elements (the kernels write every one of them)."""
+    _need(t, name, device)
+    if t.dtype != dtype:
+        raise LdkError(f"{name} must be {dtype}, got {t.dtype}")
+    want = 1
+    for s_ in shape:
+        want *= int(s_)
+    if t.numel() != want:
+        raise LdkError(f"{name} holds {t.numel()} elements, expected {want} ({tuple(shape)})")
+
+
+def _need_ws(ws, nbytes: int, device):
+    """A workspace of at least nbytes bytes on `device` (allocated when None)."""
+    nbytes = int(nbytes)
+    if ws is None:
+        return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device) if nbytes else None
+    _need(ws, "ws", device)
+    if ws.numel() * ws.element_size() < nbytes:
+        raise LdkError(f"workspace holds {ws.numel() * ws.element_size()} bytes, "
+                       f"{nbytes} needed")
+    return ws
 
 
 def _kind(kind) -> int:
@@ -146,9 +178,8 @@ def _order(order) -> int:
             NATURAL: NATURAL, LINEAR: LINEAR, GRAY: GRAY}[order]
 
 
-def _workspace(op: int, kind: int, rows: int, m: int, dt: int, device):
-    nbytes = lib().ldk_workspace_bytes(op, kind, rows, m, dt)
-    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device) if nbytes else None
+def _workspace(op: int, kind: int, rows: int, m: int, dt: int, device, ws=None):
+    return _need_ws(ws, lib().ldk_workspace_bytes(op, kind, rows, m, dt), device)
 
 
 def init():
@@ -208,11 +239,46 @@ class Kernel:
                        float(self.zeta))
 
 
+def _dev_of(ps: PointSet):
+    return ps.gen.device
+
+
+def _ps_checked(ps: PointSet):
+    """The C struct of ps, its arrays checked for device and size."""
+    dev = _dev_of(ps)
+    per = ps.per_replication
+    _need(ps.gen, "gen", dev)
+    if ps.kind in ("lattice", LATTICE):
+        want = ps.d
+    else:
+        want = ps.d * ps.m_max * (ps.R if per else 1)
+    if ps.gen.numel() < want:
+        raise LdkError(f"gen holds {ps.gen.numel()} words, {want} needed")
+    if ps.lms is not None:
+        _need(ps.lms, "lms", dev)
+        if ps.lms.numel() < ps.R * ps.d * 64:
+            raise LdkError("lms must hold S[R][d][64]")
+    if ps.shift is not None:
+        _need(ps.shift, "shift", dev)
+        if ps.shift.numel() < ps.R * ps.d:
+            raise LdkError("shift must hold [R][d] words")
+    return ps._c()
+
+
+def _k_checked(k: Kernel, d: int, dev):
+    _need(k.gamma, "gamma", dev)
+    if k.gamma.dtype != torch.float64 or k.gamma.numel() != d or k._alpha_host.size != d:
+        raise LdkError("kernel gamma must be float64[d] and alpha hold d orders")
+    return k._c()
+
+
 def gen_points(ps: PointSet, n_min: int, n_max: int, out: torch.Tensor | None = None):
-    dev = ps.gen.device
+    dev = _dev_of(ps)
+    shape = (ps.R, n_max - n_min, ps.d)
     if out is None:
-        out = torch.empty((ps.R, n_max - n_min, ps.d), dtype=torch.int64, device=dev)
-    _check(lib().ldk_gen_points(C.byref(ps._c()), n_min, n_max, _ptr(out), _stream()),
+        out = torch.empty(shape, dtype=torch.int64, device=dev)
+    _need_out(out, "out", torch.int64, shape, dev)
+    _check(lib().ldk_gen_points(C.byref(_ps_checked(ps)), n_min, n_max, _ptr(out), _stream()),
            "ldk_gen_points")
     return out
 
@@ -220,14 +286,18 @@ def gen_points(ps: PointSet, n_min: int, n_max: int, out: torch.Tensor | None = 
 def kernel_column(k: Kernel, ps: PointSet, n_min: int, n_max: int, pts=None, x0=None,
                   dtype=torch.float64, out=None):
     dt = _dtype_code(dtype)
+    dev = _dev_of(ps)
+    shape = (ps.R, n_max - n_min)
     if out is None:
-        out = torch.empty((ps.R, n_max - n_min), dtype=_real(dt), device=ps.gen.device)
+        out = torch.empty(shape, dtype=_real(dt), device=dev)
+    _need_out(out, "out", _real(dt), shape, dev)
     if pts is not None:
-        _need(pts, "pts")
+        _need_out(pts, "pts", torch.int64, (ps.R, n_max - n_min, ps.d), dev)
     if x0 is not None:
-        _need(x0, "x0")
-    _check(lib().ldk_kernel_column(C.byref(k._c()), C.byref(ps._c()), _ptr(pts), _ptr(x0), n_min,
-                                   n_max, dt, _ptr(out), _stream()), "ldk_kernel_column")
+        _need_out(x0, "x0", torch.int64, (ps.R, ps.d), dev)
+    _check(lib().ldk_kernel_column(C.byref(_k_checked(k, ps.d, dev)), C.byref(_ps_checked(ps)),
+                                   _ptr(pts), _ptr(x0), n_min, n_max, dt, _ptr(out), _stream()),
+           "ldk_kernel_column")
     return out
 
 
@@ -241,9 +311,13 @@ def interlace(src: PointSet, alpha: int, shift: torch.Tensor | None = None, orde
     if src.d % alpha:
         raise LdkError("src.d must be a multiple of alpha")
     d = src.d // alpha
+    dev = _dev_of(src)
+    shape = (src.R, d, src.m_max)
     if out is None:
-        out = torch.empty((src.R, d, src.m_max), dtype=torch.int64, device=src.gen.device)
-    _check(lib().ldk_interlace(C.byref(src._c()), alpha, _ptr(out), _stream()), "ldk_interlace")
+        out = torch.empty(shape, dtype=torch.int64, device=dev)
+    _need_out(out, "out", torch.int64, shape, dev)
+    _check(lib().ldk_interlace(C.byref(_ps_checked(src)), alpha, _ptr(out), _stream()),
+           "ldk_interlace")
     return PointSet("dnet", src.R, d, src.m_max, out, None, shift, order or src.order,
                     per_replication=True)
 
@@ -253,19 +327,22 @@ def points_column(k: Kernel, ps: PointSet, n_min: int, n_max: int, dtype=torch.f
     """(points, first column): gen_points and kernel_column (points
     regenerated) in one call, bit for bit the same outputs."""
     dt = _dtype_code(dtype)
-    dev = ps.gen.device
+    dev = _dev_of(ps)
     if pts is None:
         pts = torch.empty((ps.R, n_max - n_min, ps.d), dtype=torch.int64, device=dev)
     if k1 is None:
         k1 = torch.empty((ps.R, n_max - n_min), dtype=_real(dt), device=dev)
-    _check(lib().ldk_points_column(C.byref(k._c()), C.byref(ps._c()), n_min, n_max, _ptr(pts), dt,
-                                   _ptr(k1), _stream()), "ldk_points_column")
+    _need_out(pts, "pts", torch.int64, (ps.R, n_max - n_min, ps.d), dev)
+    _need_out(k1, "k1", _real(dt), (ps.R, n_max - n_min), dev)
+    _check(lib().ldk_points_column(C.byref(_k_checked(k, ps.d, dev)), C.byref(_ps_checked(ps)),
+                                   n_min, n_max, _ptr(pts), dt, _ptr(k1), _stream()),
+           "ldk_points_column")
     return pts, k1
 
 
 def _m_of(n: int) -> int:
     m = n.bit_length() - 1
-    if n != 1 << m:
+    if n < 1 or n != 1 << m:
         raise LdkError(f"length {n} is not a power of two")
     return m
 
@@ -281,16 +358,19 @@ def transform(kind, x: torch.Tensor, inverse: bool = False, out=None):
     m = _m_of(n)
     B = x.numel() // n
     out = torch.empty_like(x) if out is None else out
+    _need_out(out, "out", x.dtype, x.shape, x.device)
     ws = _workspace(OP_TRANSFORM, kd, B, m, dt, x.device)
     _check(lib().ldk_transform(kd, -1 if inverse else 1, B, m, dt, _ptr(x), _ptr(out), _ptr(ws),
                                _stream()), "ldk_transform")
     return out
 
 
-def _need_f64(t: torch.Tensor, name: str):
-    _need(t, name)
+def _need_f64(t: torch.Tensor, name: str, shape=None, device=None):
+    _need(t, name, device)
     if t.dtype != torch.float64:
         raise LdkError(f"{name} must be float64 (eigenvalues are always FP64)")
+    if shape is not None:
+        _need_out(t, name, torch.float64, shape, t.device)
 
 
 def eig(kind, k1: torch.Tensor, out=None, ws=None):
@@ -300,53 +380,64 @@ def eig(kind, k1: torch.Tensor, out=None, ws=None):
     dt = _dtype_code(k1.dtype)
     R, n = k1.shape
     m = _m_of(n)
-    out = torch.empty((R, n), dtype=torch.float64, device=k1.device) if out is None else out
-    _need_f64(out, "out")
-    if ws is None:
-        ws = _workspace(OP_EIG, kd, R, m, dt, k1.device)
+    dev = k1.device
+    out = torch.empty((R, n), dtype=torch.float64, device=dev) if out is None else out
+    _need_out(out, "out", torch.float64, (R, n), dev)
+    ws = _workspace(OP_EIG, kd, R, m, dt, dev, ws)
     _check(lib().ldk_eig(kd, R, m, dt, _ptr(k1), _ptr(out), _ptr(ws), _stream()), "ldk_eig")
     return out
 
 
-def solve(kind, lam: torch.Tensor, sigma2: float, y: torch.Tensor, out=None, ws=None):
+def _apply_args(kind, lam, y, out, ws, op):
     kd = _kind(kind)
-    _need_f64(lam, "lam")
     _need(y, "y")
+    dev = y.device
     dt = _dtype_code(y.dtype)
+    if y.is_complex() or y.dim() != 3:
+        raise LdkError("y must be a real [R][nrhs][n] tensor")
     R, nrhs, n = y.shape
     m = _m_of(n)
+    _need_f64(lam, "lam", (R, n), dev)
     out = torch.empty_like(y) if out is None else out
-    if ws is None:
-        ws = _workspace(OP_SOLVE, kd, R * nrhs, m, dt, y.device)
-    _check(lib().ldk_solve(kd, R, nrhs, m, dt, _ptr(lam), float(sigma2), _ptr(y), _ptr(out),
-                           _ptr(ws), _stream()), "ldk_solve")
+    _need_out(out, "out", y.dtype, y.shape, dev)
+    ws = _workspace(op, kd, R * nrhs, m, dt, dev, ws)
+    return kd, dt, R, nrhs, m, out, ws
+
+
+def solve(kind, lam: torch.Tensor, sigma2: float, y: torch.Tensor, out=None, ws=None,
+          checked: bool = False):
+    """c = (K + sigma2 I)^-1 y for y [R][nrhs][n] (ldk_solve).  With
+    checked=True the call (ldk_solve_checked) also verifies on the device
+    that every lambda_k + sigma2 > 0 and raises LdkError (status ENOTSPD)
+    otherwise; it synchronises the stream."""
+    kd, dt, R, nrhs, m, out, ws = _apply_args(kind, lam, y, out, ws, OP_SOLVE)
+    fn = lib().ldk_solve_checked if checked else lib().ldk_solve
+    _check(fn(kd, R, nrhs, m, dt, _ptr(lam), float(sigma2), _ptr(y), _ptr(out), _ptr(ws),
+              _stream()), "ldk_solve_checked" if checked else "ldk_solve")
     return out
 
 
 def matvec(kind, lam: torch.Tensor, y: torch.Tensor, out=None, ws=None):
-    kd = _kind(kind)
-    _need_f64(lam, "lam")
-    _need(y, "y")
-    dt = _dtype_code(y.dtype)
-    R, nrhs, n = y.shape
-    m = _m_of(n)
-    out = torch.empty_like(y) if out is None else out
-    if ws is None:
-        ws = _workspace(OP_MATVEC, kd, R * nrhs, m, dt, y.device)
+    kd, dt, R, nrhs, m, out, ws = _apply_args(kind, lam, y, out, ws, OP_MATVEC)
     _check(lib().ldk_matvec(kd, R, nrhs, m, dt, _ptr(lam), _ptr(y), _ptr(out), _ptr(ws),
                             _stream()), "ldk_matvec")
     return out
 
 
-def logdet(lam: torch.Tensor, sigma2: float, out=None, ws=None):
+def logdet(lam: torch.Tensor, sigma2: float, out=None, ws=None, checked: bool = False):
+    """log det(K + sigma2 I) per replication (ldk_logdet; ldk_logdet_checked
+    with checked=True raises LdkError with status ENOTSPD instead of
+    returning NaN, and synchronises the stream)."""
     _need_f64(lam, "lam")
     R, n = lam.shape
     m = _m_of(n)
-    out = torch.empty(R, dtype=torch.float64, device=lam.device) if out is None else out
-    if ws is None:
-        ws = _workspace(OP_LOGDET, DNET_B2, R, m, F64, lam.device)
-    _check(lib().ldk_logdet(R, m, _ptr(lam), float(sigma2), _ptr(out), _ptr(ws), _stream()),
-           "ldk_logdet")
+    dev = lam.device
+    out = torch.empty(R, dtype=torch.float64, device=dev) if out is None else out
+    _need_out(out, "out", torch.float64, (R,), dev)
+    ws = _workspace(OP_LOGDET, DNET_B2, R, m, F64, dev, ws)
+    fn = lib().ldk_logdet_checked if checked else lib().ldk_logdet
+    _check(fn(R, m, _ptr(lam), float(sigma2), _ptr(out), _ptr(ws), _stream()),
+           "ldk_logdet_checked" if checked else "ldk_logdet")
     return out
 
 
@@ -356,24 +447,27 @@ def fit(kind, k1: torch.Tensor, sigma2: float, y: torch.Tensor, lam=None, c=None
     y: [R][nrhs][n] of k1's dtype."""
     kd = _kind(kind)
     _need(k1, "k1")
-    _need(y, "y")
+    dev = k1.device
+    _need(y, "y", dev)
     dt = _dtype_code(k1.dtype)
     if y.dtype != k1.dtype:
         raise LdkError("k1 and y must share a dtype")
     R, n = k1.shape
+    if y.dim() != 3 or y.shape[0] != R or y.shape[2] != n:
+        raise LdkError("y must be [R][nrhs][n]")
     nrhs = y.shape[1]
     m = _m_of(n)
-    dev = k1.device
     lam = torch.empty((R, n), dtype=torch.float64, device=dev) if lam is None else lam
-    _need_f64(lam, "lam")
+    _need_out(lam, "lam", torch.float64, (R, n), dev)
     c = torch.empty_like(y) if c is None else c
+    _need_out(c, "c", y.dtype, y.shape, dev)
     ld = None
     if logdet is True:
         ld = torch.empty(R, dtype=torch.float64, device=dev)
     elif isinstance(logdet, torch.Tensor):
         ld = logdet
-    if ws is None:
-        ws = _workspace(OP_FIT, kd, R * (nrhs + 1), m, dt, dev)
+        _need_out(ld, "logdet", torch.float64, (R,), dev)
+    ws = _workspace(OP_FIT, kd, R * (nrhs + 1), m, dt, dev, ws)
     _check(lib().ldk_fit(kd, R, nrhs, m, dt, _ptr(k1), float(sigma2), _ptr(y), _ptr(lam), _ptr(c),
                          _ptr(ld), _ptr(ws), _stream()), "ldk_fit")
     return lam, c, ld
@@ -381,14 +475,18 @@ def fit(kind, k1: torch.Tensor, sigma2: float, y: torch.Tensor, lam=None, c=None
 
 def update_double(kind, yt_old: torch.Tensor, y_new: torch.Tensor, out=None):
     kd = _kind(kind)
-    _need(yt_old, "yt_old")
     _need(y_new, "y_new")
+    dev = y_new.device
+    _need(yt_old, "yt_old", dev)
     dt = _dtype_code(y_new.dtype)
     B, n = y_new.shape
     m = _m_of(n)
+    want = _cplx(dt) if kd == LATTICE else _real(dt)
+    _need_out(yt_old, "yt_old", want, (B, n), dev)
     if out is None:
-        out = torch.empty((B, 2 * n), dtype=yt_old.dtype, device=y_new.device)
-    ws = _workspace(OP_UPDATE_DOUBLE, kd, B, m, dt, y_new.device)
+        out = torch.empty((B, 2 * n), dtype=want, device=dev)
+    _need_out(out, "out", want, (B, 2 * n), dev)
+    ws = _workspace(OP_UPDATE_DOUBLE, kd, B, m, dt, dev)
     _check(lib().ldk_update_double(kd, B, m, dt, _ptr(yt_old), _ptr(y_new), _ptr(out), _ptr(ws),
                                    _stream()), "ldk_update_double")
     return out
@@ -397,13 +495,17 @@ def update_double(kind, yt_old: torch.Tensor, y_new: torch.Tensor, out=None):
 def eig_update_double(kind, lam_old: torch.Tensor, k1_new: torch.Tensor, out=None):
     kd = _kind(kind)
     _need_f64(lam_old, "lam_old")
-    _need(k1_new, "k1_new")
+    dev = lam_old.device
+    _need(k1_new, "k1_new", dev)
     dt = _dtype_code(k1_new.dtype)
     R, n = lam_old.shape
+    if tuple(k1_new.shape) != (R, n):
+        raise LdkError("k1_new must be [R][n] like lam_old")
     m = _m_of(n)
     if out is None:
-        out = torch.empty((R, 2 * n), dtype=torch.float64, device=lam_old.device)
-    ws = _workspace(OP_EIG_UPDATE_DOUBLE, kd, R, m, dt, lam_old.device)
+        out = torch.empty((R, 2 * n), dtype=torch.float64, device=dev)
+    _need_out(out, "out", torch.float64, (R, 2 * n), dev)
+    ws = _workspace(OP_EIG_UPDATE_DOUBLE, kd, R, m, dt, dev)
     _check(lib().ldk_eig_update_double(kd, R, m, dt, _ptr(lam_old), _ptr(k1_new), _ptr(out),
                                        _ptr(ws), _stream()), "ldk_eig_update_double")
     return out
@@ -416,20 +518,17 @@ def eig_update_double(kind, lam_old: torch.Tensor, k1_new: torch.Tensor, out=Non
 def mll(kind, lam: torch.Tensor, sigma2: float, y: torch.Tensor, out_g=None, ws=None):
     """(L[R], g[R][n] = dL/dlambda, dL/dlog sigma2 [R]) for y of shape [R][n]."""
     kd = _kind(kind)
-    _need_f64(lam, "lam")
     _need(y, "y")
+    dev = y.device
     dt = _dtype_code(y.dtype)
     R, n = y.shape
-    if tuple(lam.shape) != (R, n):
-        raise LdkError("lam and y must both be [R][n]")
+    _need_f64(lam, "lam", (R, n), dev)
     m = _m_of(n)
-    dev = y.device
     L = torch.empty(R, dtype=torch.float64, device=dev)
     ds = torch.empty(R, dtype=torch.float64, device=dev)
     g = torch.empty((R, n), dtype=torch.float64, device=dev) if out_g is None else out_g
-    _need_f64(g, "g")
-    if ws is None:
-        ws = _workspace(OP_MLL, kd, R, m, dt, dev)
+    _need_out(g, "g", torch.float64, (R, n), dev)
+    ws = _workspace(OP_MLL, kd, R, m, dt, dev, ws)
     _check(lib().ldk_mll(kd, R, m, dt, _ptr(lam), float(sigma2), _ptr(y), _ptr(L), _ptr(g),
                          _ptr(ds), _ptr(ws), _stream()), "ldk_mll")
     return L, g, ds
@@ -439,20 +538,37 @@ def wce(kind, lam: torch.Tensor, w: torch.Tensor, zeta: float, out=None, ws=None
     """Squared worst-case errors [R][nw] of the cubature weights w [R][nw][n]
     for the product kernel with eigenvalues lam [R][n] (ldk_wce)."""
     kd = _kind(kind)
-    _need_f64(lam, "lam")
     _need(w, "w")
+    dev = w.device
     dt = _dtype_code(w.dtype)
     R, nw, n = w.shape
-    if tuple(lam.shape) != (R, n):
-        raise LdkError("lam must be [R][n] and w [R][nw][n]")
+    _need_f64(lam, "lam", (R, n), dev)
     m = _m_of(n)
-    out = torch.empty((R, nw), dtype=torch.float64, device=w.device) if out is None else out
-    _need_f64(out, "out")
-    if ws is None:
-        ws = _workspace(OP_WCE, kd, R * nw, m, dt, w.device)
+    out = torch.empty((R, nw), dtype=torch.float64, device=dev) if out is None else out
+    _need_out(out, "out", torch.float64, (R, nw), dev)
+    ws = _workspace(OP_WCE, kd, R * nw, m, dt, dev, ws)
     _check(lib().ldk_wce(kd, R, nw, m, dt, _ptr(lam), float(zeta), _ptr(w), _ptr(out), _ptr(ws),
                          _stream()), "ldk_wce")
     return out
+
+
+def normal_quantile(p: float) -> float:
+    """Quantile of the standard normal distribution (ldk_normal_quantile:
+    Abramowitz-Stegun 26.2.23 start, Halley steps on Phi through erfc)."""
+    if not 0.0 < p < 1.0:
+        raise LdkError("p must lie in (0, 1)")
+    return float(lib().ldk_normal_quantile(float(p)))
+
+
+def student_t_quantile(p: float, dof: int) -> float:
+    """Quantile of Student's t distribution with dof degrees of freedom
+    (ldk_student_t_quantile: Cornish-Fisher start, Newton steps on the
+    upper tail through the regularised incomplete beta function)."""
+    if not 0.0 < p < 1.0 or dof < 1:
+        raise LdkError("p must lie in (0, 1) and dof >= 1")
+    q = C.c_double(0.0)
+    _check(lib().ldk_student_t_quantile(float(p), int(dof), C.byref(q)), "ldk_student_t_quantile")
+    return q.value
 
 
 def bayes_cubature(kind, lam: torch.Tensor, sigma2: float, zeta: float, y: torch.Tensor,
@@ -460,24 +576,20 @@ def bayes_cubature(kind, lam: torch.Tensor, sigma2: float, zeta: float, y: torch
     """Bayesian-cubature posterior of the integral per replication (ldk_bayes_cubature):
     a double tensor [R][6] whose columns are named by BC_FIELDS; the credible
     interval is mean +- half at the given level."""
-    import statistics
-
     kd = _kind(kind)
-    _need_f64(lam, "lam")
     _need(y, "y")
+    dev = y.device
     dt = _dtype_code(y.dtype)
     R, n = y.shape
-    if tuple(lam.shape) != (R, n):
-        raise LdkError("lam and y must both be [R][n]")
+    _need_f64(lam, "lam", (R, n), dev)
     if not 0.0 < level < 1.0:
         raise LdkError("level must lie in (0, 1)")
     m = _m_of(n)
-    z = statistics.NormalDist().inv_cdf(0.5 + 0.5 * level)
-    out = torch.empty((R, len(BC_FIELDS)), dtype=torch.float64, device=y.device) \
+    z = normal_quantile(0.5 + 0.5 * level)
+    out = torch.empty((R, len(BC_FIELDS)), dtype=torch.float64, device=dev) \
         if out is None else out
-    _need_f64(out, "out")
-    if ws is None:
-        ws = _workspace(OP_BAYES_CUBATURE, kd, R, m, dt, y.device)
+    _need_out(out, "out", torch.float64, (R, len(BC_FIELDS)), dev)
+    ws = _workspace(OP_BAYES_CUBATURE, kd, R, m, dt, dev, ws)
     _check(lib().ldk_bayes_cubature(kd, R, m, dt, _ptr(lam), float(sigma2), float(zeta), _ptr(y),
                                     float(z), _ptr(out), _ptr(ws), _stream()),
            "ldk_bayes_cubature")
@@ -489,26 +601,21 @@ def rqmc(ps: PointSet, n: int, integrand, coef: torch.Tensor, u: float = 0.0, ta
     """RQMC estimate over the R randomizations of ps (ldk_rqmc): (mu_r [R],
     stats [3] = mean, std, half width of the 100(1 - tau)% Student-t
     interval).  integrand: "corner_peak" or "oscillatory" (or GENZ_*)."""
-    from scipy import stats as sst
-
     f = {"corner_peak": GENZ_CORNER_PEAK, "oscillatory": GENZ_OSCILLATORY,
          GENZ_CORNER_PEAK: GENZ_CORNER_PEAK, GENZ_OSCILLATORY: GENZ_OSCILLATORY}[integrand]
-    _need_f64(coef, "coef")
-    if coef.numel() != ps.d:
-        raise LdkError("coef must hold d values")
+    dev = _dev_of(ps)
+    _need_f64(coef, "coef", (ps.d,), dev)
     if not 0.0 < tau < 1.0:
         raise LdkError("tau must lie in (0, 1)")
-    t = float(sst.t.ppf(1.0 - tau / 2.0, ps.R - 1)) if ps.R > 1 else 0.0
-    dev = ps.gen.device
+    t = student_t_quantile(1.0 - tau / 2.0, ps.R - 1) if ps.R > 1 else 0.0
     mu_r = torch.empty(ps.R, dtype=torch.float64, device=dev) if mu_r is None else mu_r
     stats = torch.empty(len(RQMC_FIELDS), dtype=torch.float64, device=dev) if stats is None \
         else stats
-    _need_f64(mu_r, "mu_r")
-    _need_f64(stats, "stats")
-    if ws is None:
-        nbytes = int(lib().ldk_rqmc_workspace_bytes(C.byref(ps._c()), int(n)))
-        ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
-    _check(lib().ldk_rqmc(C.byref(ps._c()), int(n), f, _ptr(coef), float(u), t, _ptr(mu_r),
+    _need_out(mu_r, "mu_r", torch.float64, (ps.R,), dev)
+    _need_out(stats, "stats", torch.float64, (len(RQMC_FIELDS),), dev)
+    cps = _ps_checked(ps)
+    ws = _need_ws(ws, lib().ldk_rqmc_workspace_bytes(C.byref(cps), int(n)), dev)
+    _check(lib().ldk_rqmc(C.byref(cps), int(n), f, _ptr(coef), float(u), t, _ptr(mu_r),
                           _ptr(stats), _ptr(ws), _stream()), "ldk_rqmc")
     return mu_r, stats
 
@@ -519,10 +626,10 @@ def mll_adjoint(kind, g: torch.Tensor, out=None, ws=None):
     _need_f64(g, "g")
     R, n = g.shape
     m = _m_of(n)
+    dev = g.device
     out = torch.empty_like(g) if out is None else out
-    _need_f64(out, "out")
-    if ws is None:
-        ws = _workspace(OP_MLL_ADJOINT, kd, R, m, F64, g.device)
+    _need_out(out, "out", torch.float64, (R, n), dev)
+    ws = _workspace(OP_MLL_ADJOINT, kd, R, m, F64, dev, ws)
     _check(lib().ldk_mll_adjoint(kd, R, m, _ptr(g), _ptr(out), _ptr(ws), _stream()),
            "ldk_mll_adjoint")
     return out
@@ -534,26 +641,22 @@ def kernel_grad(k: Kernel, ps: PointSet, n_min: int, n_max: int, a: torch.Tensor
     k1: optionally the forward column of the same arguments and dtype (one
     sweep over the dimensions instead of two)."""
     dt = _dtype_code(dtype)
-    _need_f64(a, "a")
-    dev = ps.gen.device
+    dev = _dev_of(ps)
+    _need_f64(a, "a", (ps.R, n_max - n_min), dev)
     if out is None:
         out = torch.empty((ps.R, ps.d + 1), dtype=torch.float64, device=dev)
-    _need_f64(out, "out")
+    _need_out(out, "out", torch.float64, (ps.R, ps.d + 1), dev)
     if pts is not None:
-        _need(pts, "pts")
+        _need_out(pts, "pts", torch.int64, (ps.R, n_max - n_min, ps.d), dev)
     if x0 is not None:
-        _need(x0, "x0")
-    if ws is None:
-        nb = lib().ldk_kernel_grad_workspace_bytes(ps.R, ps.d, n_min, n_max,
-                                                   int(pts is not None))
-        ws = torch.empty(max(int(nb), 1), dtype=torch.uint8, device=dev)
+        _need_out(x0, "x0", torch.int64, (ps.R, ps.d), dev)
+    ws = _need_ws(ws, lib().ldk_kernel_grad_workspace_bytes(ps.R, ps.d, n_min, n_max,
+                                                            int(pts is not None)), dev)
     if k1 is not None:
-        _need(k1, "k1")
-        if k1.dtype != _real(dt) or tuple(k1.shape) != (ps.R, n_max - n_min):
-            raise LdkError("k1 must be the forward column: dtype and [R][n_max - n_min]")
-    _check(lib().ldk_kernel_grad(C.byref(k._c()), C.byref(ps._c()), _ptr(pts), _ptr(x0), n_min,
-                                 n_max, dt, _ptr(k1), _ptr(a), _ptr(out), _ptr(ws), _stream()),
-           "ldk_kernel_grad")
+        _need_out(k1, "k1", _real(dt), (ps.R, n_max - n_min), dev)
+    _check(lib().ldk_kernel_grad(C.byref(_k_checked(k, ps.d, dev)), C.byref(_ps_checked(ps)),
+                                 _ptr(pts), _ptr(x0), n_min, n_max, dt, _ptr(k1), _ptr(a),
+                                 _ptr(out), _ptr(ws), _stream()), "ldk_kernel_grad")
     return out
 
 
@@ -566,5 +669,6 @@ def fwht_split16(x: torch.Tensor, out=None):
     m = _m_of(n)
     B = x.numel() // n
     out = torch.empty_like(x) if out is None else out
+    _need_out(out, "out", torch.float32, x.shape, x.device)
     _check(lib().ldk_fwht_split16(B, m, _ptr(x), _ptr(out), _stream()), "ldk_fwht_split16")
     return out

@@ -311,17 +311,21 @@ extern "C" int ldk_rqmc(const ldk_pointset *ps, int64_t n, int integrand, const 
     if (!coef || !mu_r || !stats || !ws) return LDK_EINVAL;
     const int it = rq_iters(n, a.ps.R);
     const int64_t tiles = tiles_of(n, it);
-    if (tiles > 0x7fffffff) return LDK_ENOTSUP;
+    // the grid is tiles x R blocks of KC_THREADS work items; a dispatch's
+    // work-item count along x must fit 32 bits
+    if (tiles > 0x7fffffff || (uint64_t)tiles * KC_THREADS > 0xffffffffull) return LDK_ENOTSUP;
     st = ensure_init();
     if (st) return st;
     a.n_min = 0;
     a.n_max = n;
     hipStream_t s = as_stream(stream);
     double *part = static_cast<double *>(ws);
-    if (a.ps.kind == LDK_DNET_B2 && a.ps.lms && a.ps.m_max > 0) {
-        // scramble the columns once per replication (interlacing of order 1
-        // is the scrambling alone); the tiles then read per-replication
-        // columns and skip the scrambling
+    if (a.ps.kind == LDK_DNET_B2 && a.ps.lms && a.ps.m_max > 0 && ps->flags == 0) {
+        // scramble the shared columns once per replication (interlacing of
+        // order 1 is the scrambling alone); the tiles then read
+        // per-replication columns and skip the scrambling.  A net with
+        // per-replication columns and scrambles keeps lms: its tiles scramble
+        // their own columns as they build their step tables.
         uint64_t *cols = reinterpret_cast<uint64_t *>(
             static_cast<unsigned char *>(ws) +
             align256_rq((size_t)a.ps.R * (size_t)tiles_of(n, RQ_IT_SMALL) * sizeof(double)));

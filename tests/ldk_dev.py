@@ -1,5 +1,7 @@
 """Helpers for GPU tests: move workload arrays to the device and back, and the
 tolerance arithmetic used by the parity tests.  No arithmetic of the method."""
+import math
+
 import numpy as np
 import torch
 
@@ -80,3 +82,20 @@ def record(name, **vals):
     if path:
         with open(path, "a") as f:
             f.write(json.dumps({"case": name, **{k: float(v) for k, v in vals.items()}}) + "\n")
+
+
+
+def gate_vs_ld(got, ref, ref_ld, eps, floor):
+    """Conditioning-aware gate of a GPU result against the FP64 oracle: the
+    FP64 oracle's own error e_dd = |ref - ref_ld| (ref_ld: its long-double
+    twin on the same input) measures how this input amplifies rounding; a
+    GPU result computed in arithmetic of unit roundoff eps may be off by
+    10 e_dd (eps / 2^-53) (10x headroom, error linear in the unit roundoff of
+    the steps run at eps), and never needs to be better than floor * |ref|
+    (the stated tolerance).  Normwise over the last axis; returns
+    (error / gate) per row."""
+    got, ref, ref_ld = (np.atleast_2d(np.asarray(a, np.float64)) for a in (got, ref, ref_ld))
+    e_dd = np.max(np.abs(ref - ref_ld), axis=-1)
+    scale = np.max(np.abs(ref_ld), axis=-1)
+    gate = np.maximum(10.0 * e_dd * (eps / U64_EPS), floor * scale)
+    return np.max(np.abs(got - ref), axis=-1) / gate

@@ -159,3 +159,23 @@ def test_rqmc_identical_replications(orc):
     mu_r, stats = _run(pointset(w), 2**m, "corner_peak", W.corner_peak_coefficients(d))
     assert np.all(mu_r == mu_r[0])
     assert stats[1] == 0.0 and stats[2] == 0.0
+
+
+@pytest.mark.parametrize("order", ["natural", "gray"])
+def test_rqmc_per_replication_columns_with_lms(orc, order):
+    # a net whose generating columns differ per replication (flags =
+    # LDK_GEN_PER_REPLICATION) and that also carries LMS scrambles: each
+    # replication's points are the LMS net of its own columns
+    d, m, R, n = 6, 12, 3, 3000
+    rng = np.random.default_rng(88)
+    cols = np.stack([W.net_generating_matrices(rng, d, m) for _ in range(R)])
+    S = W.lms_matrices(rng, R, d)
+    shift = W.shifts(rng, R, d)
+    ps = ldk.PointSet("dnet", R, d, m, dev_u64(cols), dev_u64(S), dev_u64(shift), order=order,
+                      per_replication=True)
+    pts = np.stack([orc.dnet_points(cols[r], S[r:r + 1], shift[r:r + 1], m, 0, n, order, R=1)[0]
+                    for r in range(R)])
+    c = W.corner_peak_coefficients(d)
+    ref, y = _ref(orc, pts, "corner_peak", c, 0.0, 0.01)
+    mu_r, stats = _run(ps, n, "corner_peak", c, u=0.0)
+    _check(f"rqmc_per_rep_lms_{order}", mu_r, stats, ref, y, "corner_peak", c, n)
