@@ -92,10 +92,14 @@ def gate_vs_ld(got, ref, ref_ld, eps, floor):
     GPU result computed in arithmetic of unit roundoff eps may be off by
     10 e_dd (eps / 2^-53) (10x headroom, error linear in the unit roundoff of
     the steps run at eps), and never needs to be better than floor * |ref|
-    (the stated tolerance).  Normwise over the last axis; returns
-    (error / gate) per row."""
+    (the stated tolerance).  FP32 steps also keep only the top 32 digits of
+    each coordinate before rounding them to 24 bits, an absolute 2^-32 on
+    top of the relative 2^-24 that has no FP64 counterpart; it doubles the
+    coordinate error for x >= 2^-8, hence a factor 2 for eps > 2^-53.
+    Normwise over the last axis; returns (error / gate) per row."""
     got, ref, ref_ld = (np.atleast_2d(np.asarray(a, np.float64)) for a in (got, ref, ref_ld))
     e_dd = np.max(np.abs(ref - ref_ld), axis=-1)
     scale = np.max(np.abs(ref_ld), axis=-1)
-    gate = np.maximum(10.0 * e_dd * (eps / U64_EPS), floor * scale)
+    coord = 2.0 if eps > U64_EPS else 1.0
+    gate = np.maximum(10.0 * coord * e_dd * (eps / U64_EPS), floor * scale)
     return np.max(np.abs(got - ref), axis=-1) / gate
