@@ -61,8 +61,13 @@ typedef enum {
     LDK_EINVAL = -1,  /* bad argument (nothing enqueued) */
     LDK_ENOTSUP = -2, /* valid but unsupported combination */
     LDK_EDEVICE = -3, /* a HIP call failed; see ldk_last_hip_error() */
-    LDK_ENOTSPD = -4  /* some lambda_k + sigma^2 <= 0 (checked entry points) */
+    LDK_ENOTSPD = -4, /* some lambda_k + sigma^2 <= 0 (checked entry points) */
+    LDK_ETOOBIG = -5  /* input exceeds the fixed scratch of an allocation-free entry point */
 } ldk_status;
+
+/* Size of the fixed device scratch of ldk_solve_noalloc (per GPU, held
+ * until the process ends). */
+#define LDK_NOALLOC_SCRATCH_BYTES (16u << 20)
 
 typedef enum { LDK_LATTICE = 0, LDK_DNET_B2 = 1 } ldk_kind;
 typedef enum { LDK_NATURAL = 0, LDK_LINEAR = 1, LDK_GRAY = 2 } ldk_order;
@@ -213,6 +218,23 @@ int ldk_solve(int kind, int R, int nrhs, int m, int dtype, const double *lam, do
  * (they share one device counter). */
 int ldk_solve_checked(int kind, int R, int nrhs, int m, int dtype, const double *lam,
                       double sigma2, const void *y, void *c, void *ws, ldk_stream stream);
+
+/* ldk_solve without a workspace argument and without any allocation, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  The intermediate
+ * rows that ldk_solve keeps in `ws` live instead in a fixed device array of
+ * LDK_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends (its address is looked up once per device, by
+ * ldk_init or by this call's first use on a device).  Returns LDK_ETOOBIG,
+ * enqueueing nothing, when ldk_workspace_bytes(LDK_OP_SOLVE, kind, R * nrhs,
+ * m, dtype) exceeds that size (for instance FP64 lattice rows with
+ * R * nrhs * n > 2^22).  Otherwise the same arguments, results (bit for bit)
+ * and stream semantics as ldk_solve.  Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (other streams, other host
+ * threads) race and give wrong results; nothing in it needs clearing
+ * between calls (every intermediate is written before it is read). */
+int ldk_solve_noalloc(int kind, int R, int nrhs, int m, int dtype, const double *lam,
+                      double sigma2, const void *y, void *c, ldk_stream stream);
 
 /* Matvec K y = V (conj(V) y (.) lambda) (Sec. 5.4); layout as ldk_solve. */
 int ldk_matvec(int kind, int R, int nrhs, int m, int dtype, const double *lam, const void *y,

@@ -37,7 +37,7 @@ EXPORTS = [
     "ldk_mll", "ldk_mll_adjoint", "ldk_kernel_grad", "ldk_kernel_grad_workspace_bytes",
     "ldk_fwht_split16", "ldk_fit", "ldk_points_column", "ldk_interlace", "ldk_wce",
     "ldk_bayes_cubature", "ldk_rqmc", "ldk_rqmc_workspace_bytes", "ldk_solve_checked",
-    "ldk_logdet_checked", "ldk_normal_quantile", "ldk_student_t_quantile",
+    "ldk_logdet_checked", "ldk_normal_quantile", "ldk_student_t_quantile", "ldk_solve_noalloc",
 ]
 
 
@@ -98,6 +98,7 @@ def lib():
             "ldk_logdet_checked": ([i32, i32, P, f64, P, P, P], i32),
             "ldk_normal_quantile": ([f64], f64),
             "ldk_student_t_quantile": ([f64, i32, P], i32),
+            "ldk_solve_noalloc": ([i32, i32, i32, i32, i32, P, f64, P, P, P], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -414,6 +415,29 @@ def solve(kind, lam: torch.Tensor, sigma2: float, y: torch.Tensor, out=None, ws=
     fn = lib().ldk_solve_checked if checked else lib().ldk_solve
     _check(fn(kd, R, nrhs, m, dt, _ptr(lam), float(sigma2), _ptr(y), _ptr(out), _ptr(ws),
               _stream()), "ldk_solve_checked" if checked else "ldk_solve")
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 16 << 20  # LDK_NOALLOC_SCRATCH_BYTES
+
+
+def solve_noalloc(kind, lam: torch.Tensor, sigma2: float, y: torch.Tensor, out: torch.Tensor):
+    """ldk_solve_noalloc: the solve with its intermediates in the library's
+    fixed per-GPU scratch (no workspace, no allocation in the library; the
+    caller passes the output).  Raises LdkError (status -5) when the input
+    needs more than NOALLOC_SCRATCH_BYTES of intermediates.  Calls that
+    overlap on one GPU race."""
+    kd = _kind(kind)
+    _need(y, "y")
+    dev = y.device
+    if y.is_complex() or y.dim() != 3:
+        raise LdkError("y must be a real [R][nrhs][n] tensor")
+    R, nrhs, n = y.shape
+    m = _m_of(n)
+    _need_f64(lam, "lam", (R, n), dev)
+    _need_out(out, "out", y.dtype, y.shape, dev)
+    _check(lib().ldk_solve_noalloc(kd, R, nrhs, m, _dtype_code(y.dtype), _ptr(lam), float(sigma2),
+                                   _ptr(y), _ptr(out), _stream()), "ldk_solve_noalloc")
     return out
 
 

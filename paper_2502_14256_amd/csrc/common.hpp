@@ -15,6 +15,7 @@ namespace ldk {
 // ---------------------------------------------------------------------------
 void set_hip_error(hipError_t e);
 int ensure_init();  // builds the twiddle tables on the current device once
+int noalloc_setup();  // device address of ldk_solve_noalloc's scratch (noalloc.hip)
 
 #define LDK_HIP_CHECK(expr)                      \
     do {                                         \

@@ -53,6 +53,9 @@ int ensure_init()
     LDK_HIP_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(g_tw_hi_f32), hf.data(), sizeof(cplx<float>) * TW_SIZE));
     LDK_HIP_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(g_tw_lo_f32), lf.data(), sizeof(cplx<float>) * TW_SIZE));
     LDK_HIP_CHECK(hipDeviceSynchronize());
+    // per-device set-up of the allocation-free entry point's scratch address
+    const int st = noalloc_setup();
+    if (st) return st;
     g_ready[dev] = true;
     return LDK_OK;
 }
@@ -75,6 +78,7 @@ const char *ldk_strerror(int status)
     case LDK_ENOTSUP: return "unsupported combination of arguments";
     case LDK_EDEVICE: return "HIP runtime error (see ldk_last_hip_error)";
     case LDK_ENOTSPD: return "matrix not positive definite (lambda + sigma^2 <= 0)";
+    case LDK_ETOOBIG: return "input exceeds the fixed scratch of the allocation-free entry point";
     default: return "unknown status";
     }
 }
