@@ -6,12 +6,19 @@ A step is one pass of the whole path over the rank-1 lattice workload
   k1, the column regenerating the points in registers) -> fit (eig (FFTBR),
   solve, logdet in one call),
 with the generating vector, shift and responses already resident in HBM.
-The metric counts one Gram solve (K + sigma^2 I)^-1 y per step.
+The metric counts one Gram solve (K + sigma^2 I)^-1 y per step: `value` is
+whole steps per second (each step also forms the points, the first column,
+the eigenvalues and the log-det); `solves_per_s_cached_lambda` is the solve
+alone.
 
 Printed: one JSON line with
 - the metric and per-op timings (HIP events on the library's stream);
-- the roofline of the longest single kernel (the point words), and the fit's
-  and the solve's own rooflines;
+- `roofline`: the Gram solve with cached eigenvalues (the metric's target),
+  and the step's longest single kernel (the point writer) beside it;
+- `solve_rhs`: solves with 1 and 16 right-hand sides at n = 2^20 (lattice
+  and net), solves/s and fraction of the HBM peak;
+- `fp32_step` (the same step with FP32 responses and solve) and
+  `c1_latency` (the small net problem end to end);
 - the marginal-likelihood gradient workload (64 replications of a net with
   n = 2^16, d = 64) under "grad", and the batched instance table under
   "batched";
@@ -67,15 +74,14 @@ def parse():
     p.add_argument("--steps", type=int, default=50)
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--dtype", choices=["f64", "f32"], default="f64",
-                   help="arithmetic of the per-solve data (y, c, solve transforms); the first "
-                        "column and the eigenvalues stay FP64")
+                   help="arithmetic of the first column and the per-solve data (y, c, solve "
+                        "transforms); the eigenvalues, division and log-det stay FP64")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-grad", action="store_true",
                    help="skip the marginal-likelihood gradient workload")
     p.add_argument("--no-batch", action="store_true",
                    help="skip the batched instance-table workload")
     p.add_argument("--batch-steps", type=int, default=10)
-    p.add_argument("--cpu-seconds", type=float, default=10.0)
     p.add_argument("--traffic-probe", action="store_true",
                    help="only run the step eagerly 5 times and a 256 MiB device copy 5 times "
                         "(a short program for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs; the "
@@ -83,8 +89,6 @@ def parse():
     p.add_argument("--valu-probe", action="store_true",
                    help="only run the step, the FP32 gradient step and the RQMC estimates a few "
                         "times (a short program for rocprofv3 --pmc SQ_INSTS_VALU runs), then exit")
-    p.add_argument("--copy-probe", action="store_true",
-                   help="also run a plain device copy of known size (counter calibration)")
     return p.parse_args()
 
 
@@ -124,13 +128,13 @@ def main():
 
     # outputs and workspaces, allocated once
     pts = torch.empty((R, n, d), dtype=torch.int64, device="cuda")
-    k1 = torch.empty((R, n), dtype=torch.float64, device="cuda")
+    k1 = torch.empty((R, n), dtype=dt, device="cuda")
     lam = torch.empty((R, n), dtype=torch.float64, device="cuda")
     c = torch.empty_like(y)
     ld = torch.empty(R, dtype=torch.float64, device="cuda")
     ws_solve = ldk._workspace(ldk.OP_SOLVE, ldk.LATTICE, R, m, ldk._dtype_code(dt), "cuda")
     ws_ld = ldk._workspace(ldk.OP_LOGDET, ldk.LATTICE, R, m, ldk.F64, "cuda")
-    ws_eig = ldk._workspace(ldk.OP_EIG, ldk.LATTICE, R, m, ldk.F64, "cuda")
+    ws_eig = ldk._workspace(ldk.OP_EIG, ldk.LATTICE, R, m, ldk._dtype_code(dt), "cuda")
     ws_fit = ldk._workspace(ldk.OP_FIT, ldk.LATTICE, R * 2, m, ldk._dtype_code(dt), "cuda")
 
     ops = ["points_column", "fit"]
@@ -138,7 +142,7 @@ def main():
     def step():
         # point words and first column in one launch (the column regenerates
         # the points in registers, so the two run side by side)
-        ldk.points_column(kern, ps, 0, n, dtype=torch.float64, pts=pts, k1=k1)
+        ldk.points_column(kern, ps, 0, n, dtype=dt, pts=pts, k1=k1)
         # eigenvalues, solve and log-det in one call (shared tile passes)
         ldk.fit("lattice", k1, w["sigma2"], y, lam=lam, c=c, logdet=ld, ws=ws_fit)
 
@@ -201,10 +205,9 @@ def main():
     # timed region 2: each op alone, captured in its own graph and replayed K
     # times back to back (device time per launch, no host gaps)
     op_calls = {
-        "points_column": lambda: ldk.points_column(kern, ps, 0, n, dtype=torch.float64, pts=pts,
-                                                   k1=k1),
+        "points_column": lambda: ldk.points_column(kern, ps, 0, n, dtype=dt, pts=pts, k1=k1),
         "gen_points": lambda: ldk.gen_points(ps, 0, n, out=pts),
-        "kernel_column": lambda: ldk.kernel_column(kern, ps, 0, n, dtype=torch.float64, out=k1),
+        "kernel_column": lambda: ldk.kernel_column(kern, ps, 0, n, dtype=dt, out=k1),
         "fit": lambda: ldk.fit("lattice", k1, w["sigma2"], y, lam=lam, c=c, logdet=ld, ws=ws_fit),
         "eig": lambda: ldk.eig("lattice", k1, out=lam, ws=ws_eig),
         "solve": lambda: ldk.solve("lattice", lam, w["sigma2"], y, out=c, ws=ws_solve),
@@ -216,11 +219,11 @@ def main():
                for op in ("gen_points", "kernel_column", "eig", "solve", "logdet")}
     # algorithmic bytes per op (one launch of each op per step)
     alg = {
-        "points_column": 8 * (d + 1) * n * R,     # write the point words and k1
+        "points_column": (8 * d + esz) * n * R,   # write the point words and k1
         "gen_points": 8 * n * d * R,              # write the point words
-        "kernel_column": 8 * n * R,               # write k1 (points regenerated in registers)
-        "fit": (2 * esz + 8 + 8) * n * R,         # read k1 and y, write lambda and c
-        "eig": 2 * 8 * n * R,                     # read k1, write lambda (FP64)
+        "kernel_column": esz * n * R,             # write k1 (points regenerated in registers)
+        "fit": (3 * esz + 8) * n * R,             # read k1 and y, write lambda (FP64) and c
+        "eig": (esz + 8) * n * R,                 # read k1, write lambda (FP64)
         "solve": (2 * esz + 8) * n * R,           # read y, read lambda (FP64), write c
         "logdet": 8 * n * R,                      # read lambda
     }
@@ -229,13 +232,25 @@ def main():
                     "GB_s": round(alg[op] / (per_op[op] * 1e-3) / 1e9, 1),
                     "hbm_frac": round(alg[op] / (per_op[op] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
                for op in ops}
-    # The roofline is taken on the longest single kernel of the step, the
-    # points + column launch (the fit is three kernels, the longest of them,
-    # the fused top pass, ~23 us against ~48 us).
-    dom = "points_column"
-    roof_dom = {"kernel": "k_points_kcol_lattice (points_column)", "bound": "hbm",
-                "achieved": op_rows[dom]["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": op_rows[dom]["hbm_frac"], "traffic": step_traffic_bytes()}
+    # The headline roofline is the Gram solve with cached eigenvalues (the
+    # target of the metric): read y and lambda, write c, 24 MiB at n = 2^20
+    # in FP64, over the three kernels of one ldk_solve (row pass, top pass
+    # with the filter, inverse row pass), each captured alone in a graph and
+    # replayed K times.  The step's longest single kernel is the point
+    # writer (points + first column), reported separately.
+    t_solve = unfused["solve"]
+    roof_dom = {"kernel": "ldk_solve, lattice n=2^20 FP64, 1 RHS, cached lambda (3 kernels: "
+                          "row pass, top pass with the filter, inverse row pass)",
+                "bound": "hbm",
+                "achieved": round(alg["solve"] / (t_solve * 1e-3) / 1e9, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(alg["solve"] / (t_solve * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "traffic": None}
+    roof_points = {"kernel": "k_points_kcol_lattice (points + first column; the step's longest "
+                             "single kernel, not the solve)", "bound": "hbm",
+                   "achieved": op_rows["points_column"]["GB_s"], "peak": HBM_PEAK_GBS,
+                   "unit": "GB/s", "frac": op_rows["points_column"]["hbm_frac"],
+                   "traffic": step_traffic_bytes()}
     ms_per_step = total_ms / K
     solves_per_s = R * K / (total_ms * 1e-3)
 
@@ -257,15 +272,11 @@ def main():
                                "column (one call) + fit (eig, solve, logdet) per step",
                    "n": n, "d": d, "R": R, "nrhs": 1},
         "roofline": roof_dom,
+        "step_longest_kernel_roofline": roof_points,
         "fit_roofline": {"bound": "hbm", "kernels": 3, "achieved": op_rows["fit"]["GB_s"],
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": op_rows["fit"]["hbm_frac"]},
-        "solve_roofline": {"bound": "hbm",
-                           "achieved": round(alg["solve"] / (unfused["solve"] * 1e-3) / 1e9, 1),
-                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": round(alg["solve"] / (unfused["solve"] * 1e-3) / 1e9
-                                         / HBM_PEAK_GBS, 4),
-                           "solves_per_s_cached_lambda": round(1e3 / unfused["solve"], 1)},
+        "solves_per_s_cached_lambda": round(1e3 / unfused["solve"], 1),
         "ops": op_rows,
         "unfused_ms": unfused,
         "timing": "value and ms_per_step: K replays of one HIP-graph-captured step; ops: each "
@@ -275,22 +286,10 @@ def main():
         "wall_s_timed": round(wall, 4),
     }
 
-    if args.copy_probe:
-        stream = torch.cuda.current_stream()
-        src = torch.empty(32 * 2**20, dtype=torch.float64, device="cuda").uniform_()
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        for _ in range(10):
-            dst.copy_(src)
-        b.record(stream)
-        torch.cuda.synchronize()
-        ms = a.elapsed_time(b) / 10
-        out["copy_probe"] = {"bytes_read": src.numel() * 8, "bytes_written": dst.numel() * 8,
-                             "ms": round(ms, 5),
-                             "GB_s": round(2 * src.numel() * 8 / (ms * 1e-3) / 1e9, 1)}
+    out["solve_rhs"] = solve_rhs_bench(K, lam, w)
+    if args.dtype == "f64":
+        out["fp32_step"] = fp32_step_bench(K, kern, ps, w, y_host, c)
+    out["c1_latency"] = c1_latency_bench(K)
 
     if not args.no_grad:
         out["grad"] = grad_bench(K, args.warmup)
@@ -305,7 +304,16 @@ def main():
     out["update_double"] = update_bench(K)
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        out["cpu_baseline"], c_oracle = cpu_baseline(w, y_host)
+        # the step's result against the FP64 oracle (normwise), per dtype
+        out["err_c_vs_fp64_oracle"] = {
+            args.dtype: float(np.linalg.norm(c.double().cpu().numpy() - c_oracle)
+                              / np.linalg.norm(c_oracle))}
+        if "fp32_step" in out:
+            out["err_c_vs_fp64_oracle"]["f32"] = float(
+                np.linalg.norm(out["fp32_step"].pop("_c") - c_oracle) / np.linalg.norm(c_oracle))
+    elif "fp32_step" in out:
+        out["fp32_step"].pop("_c")
 
     print(json.dumps(out), flush=True)
 
@@ -709,34 +717,191 @@ def batch_bench(K, warmup):
     }
 
 
-def cpu_baseline(w, budget_s):
-    """The oracle (single-threaded C, FP64) running the same whole step on the
-    host until about budget_s seconds have passed (at least one step).  The
-    responses y are synthesised once, outside the timed loop."""
+def solve_rhs_bench(K, lam_lat, w_lat):
+    """Gram solves with cached eigenvalues at n = 2^20 in FP64, one and 16
+    right-hand sides, on the lattice workload's eigenvalues and on the net
+    workload's (n = 2^20, d = 32, order-4 DSI kernel): solves per second and
+    the fraction of the 8 TB/s HBM peak, with algorithmic bytes 16 n per
+    right-hand side (read y, write c) plus 8 n for lambda, read once."""
+    import numpy as np
+    import torch
+
+    import paper_2502_14256_amd as ldk
+    import workloads as W
+
+    w3 = W.workload(3)
+    n = 2 ** w3["m"]
+
+    def dev_u64(a):
+        return torch.from_numpy(np.ascontiguousarray(a, np.uint64).view(np.int64).copy()).cuda()
+
+    ps3 = ldk.PointSet("dnet", 1, w3["d"], w3["m"], dev_u64(w3["gen"]), dev_u64(w3["lms"]),
+                       dev_u64(w3["shift"]))
+    k3 = ldk.Kernel("dnet", w3["alpha"],
+                    torch.tensor(w3["gamma"], dtype=torch.float64, device="cuda"), w3["zeta"])
+    lam_net = ldk.eig("dnet", ldk.kernel_column(k3, ps3, 0, n))
+    rng = np.random.default_rng(99)
+    res = {}
+    for kind, lam, s2 in (("lattice", lam_lat, w_lat["sigma2"]), ("net", lam_net, w3["sigma2"])):
+        kd = "lattice" if kind == "lattice" else "dnet"
+        row = {}
+        for nrhs in (1, 16):
+            y = torch.from_numpy(rng.standard_normal((1, nrhs, n))).cuda()
+            c = torch.empty_like(y)
+            ws = ldk._workspace(ldk.OP_SOLVE, ldk._kind(kd), nrhs, w3["m"], ldk.F64, "cuda")
+            ms = time_graph(lambda: ldk.solve(kd, lam, s2, y, out=c, ws=ws), K)
+            alg = (16 * nrhs + 8) * n
+            gbs = alg / (ms * 1e-3) / 1e9
+            row[f"rhs{nrhs}"] = {"ms": round(ms, 5), "solves_per_s": round(nrhs / (ms * 1e-3), 1),
+                                 "GB_s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+            del y, c, ws
+        res[kind] = row
+    res["bytes"] = "algorithmic: 16 n per right-hand side (read y, write c) + 8 n (lambda, read once)"
+    return res
+
+
+def fp32_step_bench(K, kern, ps, w, y_host, c64):
+    """The same step in FP32: the first column, the responses, the solution
+    and the solve transforms in FP32 (the eigenvalues, the division by
+    lambda + sigma^2 and the log-det stay FP64): time per step and the
+    solution's normwise difference from the FP64 step's."""
+    import numpy as np
+    import torch
+
+    import paper_2502_14256_amd as ldk
+
+    n, R = 2 ** w["m"], w["R"]
+    y = torch.from_numpy(y_host).to(device="cuda", dtype=torch.float32)
+    pts = torch.empty((R, n, w["d"]), dtype=torch.int64, device="cuda")
+    k1 = torch.empty((R, n), dtype=torch.float32, device="cuda")
+    lam = torch.empty((R, n), dtype=torch.float64, device="cuda")
+    c = torch.empty_like(y)
+    ld = torch.empty(R, dtype=torch.float64, device="cuda")
+    ws = ldk._workspace(ldk.OP_FIT, ldk.LATTICE, 2 * R, w["m"], ldk.F32, "cuda")
+
+    def step():
+        ldk.points_column(kern, ps, 0, n, dtype=torch.float32, pts=pts, k1=k1)
+        ldk.fit("lattice", k1, w["sigma2"], y, lam=lam, c=c, logdet=ld, ws=ws)
+
+    ms = time_graph(step, K)
+    ch = c.double().cpu().numpy()
+    c64h = c64.double().cpu().numpy()
+    return {"ms_per_step": round(ms, 5), "solves_per_s": round(R / (ms * 1e-3), 2),
+            "rel_c_vs_fp64_gpu_step": float(np.linalg.norm(ch - c64h) / np.linalg.norm(c64h)),
+            "dtype": "f32 first column, responses, solution and solve transforms; f64 "
+                     "eigenvalues, division and log-det", "_c": ch}
+
+
+def c1_latency_bench(K):
+    """The plain small problem (net n = 1024, d = 4, order-1 DSI kernel,
+    sigma^2 = 1e-8): points, first column, eigenvalues, solve and log-det,
+    as one captured graph (device time per replay) and issued eagerly from
+    the host (wall time per call, synchronised)."""
+    import numpy as np
+    import torch
+
+    import paper_2502_14256_amd as ldk
+    import workloads as W
+
+    w = W.workload(1)
+    n = 2 ** w["m"]
+
+    def dev_u64(a):
+        return torch.from_numpy(np.ascontiguousarray(a, np.uint64).view(np.int64).copy()).cuda()
+
+    ps = ldk.PointSet("dnet", 1, w["d"], w["m"], dev_u64(w["gen"]), dev_u64(w["lms"]),
+                      dev_u64(w["shift"]))
+    kern = ldk.Kernel("dnet", w["alpha"],
+                      torch.tensor(w["gamma"], dtype=torch.float64, device="cuda"), w["zeta"])
+    y = torch.from_numpy(np.ascontiguousarray(w["y"])).cuda()
+    pts = torch.empty((1, n, w["d"]), dtype=torch.int64, device="cuda")
+    k1 = torch.empty((1, n), dtype=torch.float64, device="cuda")
+    lam = torch.empty((1, n), dtype=torch.float64, device="cuda")
+    c = torch.empty_like(y)
+    ld = torch.empty(1, dtype=torch.float64, device="cuda")
+    ws = ldk._workspace(ldk.OP_FIT, ldk.DNET_B2, 2, w["m"], ldk.F64, "cuda")
+
+    def step():
+        ldk.points_column(kern, ps, 0, n, pts=pts, k1=k1)
+        ldk.fit("dnet", k1, w["sigma2"], y, lam=lam, c=c, logdet=ld, ws=ws)
+
+    ms_graph = time_graph(step, K)
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        step()
+        torch.cuda.synchronize()
+    eager_us = (time.perf_counter() - t0) / K * 1e6
+    return {"workload": "net_m10_d4_dsi1 (LMS + shift, n=1024, d=4, order-1 DSI, "
+                        "sigma^2=1e-8)", "graph_us": round(ms_graph * 1e3, 2),
+            "eager_synchronised_us": round(eager_us, 1)}
+
+
+def cpu_baseline(w, y):
+    """The oracle (plain C, FP64) timed on this host on the same whole step
+    (points, first column, FFTBR eigenvalues, solve, log-det at n = 2^20,
+    d = 32).  Built here with -O3 -march=native -ffp-contract=off -fopenmp
+    (bit for bit the results of the test build; the OpenMP pragmas share out
+    points, kernel-column entries and each transform stage's butterflies).
+    Two legs: one thread, and every thread the host offers this process
+    (OMP_NUM_THREADS when set, else the CPU count); each the median of 5
+    steps after 1 warm-up.  The responses y are synthesised outside the timed
+    steps.  Returns (record, the oracle's solution c)."""
+    import statistics
+    import tempfile
+
     import numpy as np
 
     import oracle
-    import workloads as W
 
-    oracle.lib()
-    pts = oracle.points(w)
-    y = np.ascontiguousarray(W.sine_response(W.to_unit_f64(pts), w["eps"][:, 0, :])[:, None, :])
-    del pts
-    steps, t0 = 0, time.perf_counter()
-    while True:
+    tmp = tempfile.mkdtemp(prefix="orc_baseline_")
+    so = oracle.build(path=os.path.join(tmp, "liborc_baseline.so"),
+                      flags=("-O3", "-march=native", "-ffp-contract=off", "-fopenmp"))
+    oracle.use_library(so)
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    nproc = os.cpu_count()
+    all_threads = int(os.environ.get("OMP_NUM_THREADS") or nproc)
+    c_out = None
+
+    def step():
+        nonlocal c_out
         pts = oracle.points(w)
         k1 = oracle.kernel_column("lattice", pts, pts[:, 0], w["alpha"], w["gamma"], w["zeta"])
         lam, _ = oracle.eig("lattice", k1)
-        oracle.solve("lattice", lam, w["sigma2"], y)
+        c_out = oracle.solve("lattice", lam, w["sigma2"], y)
         oracle.logdet(lam, w["sigma2"])
-        steps += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s:
-            break
-    return {"value": round(steps / el, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} whole step(s) of the same workload (points, first column, "
-                      f"FFTBR eigenvalues, solve, log-det at n=2^20, d=32) in the "
-                      f"single-threaded C oracle, FP64, {el:.1f} s"}
+
+    legs = {}
+    for name, threads in (("single", 1), ("all", all_threads)):
+        oracle.lib().orc_set_threads(threads)
+        used = oracle.lib().orc_threads()
+        step()  # warm-up
+        times = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            step()
+            times.append(time.perf_counter() - t0)
+        legs[name] = {"threads": used, "median_s": round(statistics.median(times), 4),
+                      "solves_per_s": round(1.0 / statistics.median(times), 5)}
+    oracle.use_library(None)
+    rec = {"value": legs["all"]["solves_per_s"], "unit": "solves/s",
+           "cores": legs["all"]["threads"], "kind": "oracle",
+           "sample": "median of 5 whole steps after 1 warm-up (points, first column, FFTBR "
+                     "eigenvalues, solve, log-det at n=2^20, d=32, FP64), C oracle built on "
+                     "this host with -O3 -march=native -ffp-contract=off -fopenmp",
+           "single_thread": legs["single"], "all_threads": legs["all"],
+           "nproc": nproc, "cpu_model": model}
+    return rec, c_out[:, 0, :] if c_out.ndim == 3 else c_out
 
 
 if __name__ == "__main__":

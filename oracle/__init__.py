@@ -72,17 +72,32 @@ LATTICE, DNET = 0, 1
 NATURAL, LINEAR, GRAY = 0, 1, 2
 
 
-def build(force: bool = True) -> str:
-    """Compile the C oracle with gcc into oracle/liborc.so."""
-    if force or not os.path.exists(_SO):
-        cmd = ["gcc", "-O2", "-std=gnu11", "-Wall", "-fPIC", "-shared", "-o", _SO + ".tmp"]
+def build(force: bool = True, path: str | None = None, flags=("-O2",)) -> str:
+    """Compile the C oracle with gcc into oracle/liborc.so (or `path`).
+    flags: optimisation flags; the CPU-baseline timing builds a copy with
+    -O3 -march=native -fopenmp on the host that times it (the OpenMP
+    pragmas only share out independent loops: results are bit for bit the
+    same)."""
+    out = path or _SO
+    if force or not os.path.exists(out):
+        cmd = ["gcc", *flags, "-std=gnu11", "-Wall", "-Wno-unknown-pragmas", "-fPIC", "-shared",
+               "-o", out + ".tmp"]
         cmd += [os.path.join(_HERE, s) for s in _SRC] + ["-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(_SO + ".tmp", _SO)
-    return _SO
+        os.replace(out + ".tmp", out)
+    return out
 
 
 _lib = None
+
+
+def use_library(path: str | None):
+    """Bind this module's functions to another build of the oracle (for the
+    CPU-baseline timing); None returns to oracle/liborc.so."""
+    global _lib
+    _lib = None
+    if path is not None:
+        _lib = _load(path)
 
 
 def lib():
@@ -92,7 +107,14 @@ def lib():
                          for s in _SRC + ["orc.h", "orc_algebra.inc", "orc_kernels.inc"])
         if not os.path.exists(_SO) or os.path.getmtime(_SO) < newest_src:
             build()
-        L = C.CDLL(_SO)
+        _lib = _load(_SO)
+    return _lib
+
+
+def _load(path: str):
+    """Load one build of the oracle and declare its signatures."""
+    if True:
+        L = C.CDLL(path)
         P = C.c_void_p
         i32, i64, f64 = C.c_int, C.c_int64, C.c_double
         sig = {
@@ -126,8 +148,11 @@ def lib():
         L.orc_dsi_factor.restype = f64
         L.orc_gray.argtypes = [C.c_uint64]
         L.orc_gray.restype = C.c_uint64
-        _lib = L
-    return _lib
+        L.orc_threads.argtypes = []
+        L.orc_threads.restype = i32
+        L.orc_set_threads.argtypes = [i32]
+        L.orc_set_threads.restype = None
+        return L
 
 
 def _p(a: np.ndarray | None):

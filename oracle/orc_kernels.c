@@ -37,6 +37,16 @@ double orc_dsi_factor(int alpha, uint64_t delta) { return dbl_dsi_factor(alpha, 
 long double orc_si_factor_ld(int alpha, uint64_t delta) { return ldb_si_factor(alpha, delta); }
 long double orc_dsi_factor_ld(int alpha, uint64_t delta) { return ldb_dsi_factor(alpha, delta); }
 
+/* Threads the OpenMP loops may use (1 unless built with -fopenmp). */
+#ifdef _OPENMP
+#include <omp.h>
+int orc_threads(void) { return omp_get_max_threads(); }
+void orc_set_threads(int t) { omp_set_num_threads(t > 0 ? t : 1); }
+#else
+int orc_threads(void) { return 1; }
+void orc_set_threads(int t) { (void)t; }
+#endif
+
 /* First column of the product-weight Gram matrix, eq. (K_SI_prod) and its
  * DSI analogue in Sec. 5.3:  k1_i = zeta prod_j (1 + gamma_j K_{alpha_j}(x_ij (-) x0_j)).
  * pts: [R][n][d]; x0: [R][d] (the anchor point); k1: [R][n]. */
@@ -48,6 +58,8 @@ int orc_kernel_column(int kind, int R, int d, int64_t n, const uint64_t *pts,
         if (kind == ORC_LATTICE && (alpha[j] < 1 || alpha[j] > 3)) return -1;
         if (kind == ORC_DNET && (alpha[j] < 1 || alpha[j] > 4)) return -1;
     }
+    /* every entry is independent (OpenMP in the CPU-baseline build only) */
+#pragma omp parallel for collapse(2) schedule(static)
     for (int r = 0; r < R; ++r)
         for (int64_t i = 0; i < n; ++i) {
             double prod = zeta;

@@ -21,6 +21,8 @@ int orc_lattice_points(int R, int d, int m, int order, int64_t n_min, int64_t n_
     if (order == ORC_LINEAR && n_max > ((int64_t)1 << m)) return -1;
     if (order != ORC_NATURAL && order != ORC_LINEAR) return -1;
     const int64_t cnt = n_max - n_min;
+    /* points are independent (OpenMP in the CPU-baseline build only) */
+#pragma omp parallel for collapse(2) schedule(static)
     for (int r = 0; r < R; ++r)
         for (int64_t ii = 0; ii < cnt; ++ii) {
             const uint64_t i = (uint64_t)(n_min + ii);
@@ -92,6 +94,7 @@ int orc_dnet_points(int R, int d, int m_max, int order, int64_t n_min, int64_t n
             orc_lms(d, m_max, C, S + (size_t)r * d * 64, Ct);
         else
             memcpy(Ct, C, sizeof(uint64_t) * (size_t)d * m_max);
+#pragma omp parallel for schedule(static)
         for (int64_t ii = 0; ii < cnt; ++ii) {
             const uint64_t i = (uint64_t)(n_min + ii);
             const uint64_t code = (order == ORC_GRAY) ? orc_gray(i) : i;

@@ -101,3 +101,55 @@ def test_batched_graph_replays(table):
         for i in range(len(MS)):
             c, ld = b.result(i)
             assert torch.equal(c, ref[i][0]) and torch.equal(ld, ref[i][1]), (rep, i)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_workload4_full_table_subset_against_oracle(dtype):
+    """The batched workload at its configured size (256 instances, kind
+    lattice or net at random, n = 2^12..2^18, d = 16, 8 right-hand sides),
+    run whole as the benchmark runs it; a seeded subset of instances that
+    includes the largest size of both kinds is checked against the oracle
+    (FP64: 10x the oracle's own error against its long-double twin; FP32:
+    the same gates as the single-instance FP32 solves, against the oracle
+    run on the GPU's rounded column)."""
+    import oracle
+    from ldk_dev import F32_EPS, solve_tol
+    t = W.workload(4)
+    b = BatchFit([Instance(kind=ins["kind"], m=ins["m"], shift=ins["shift"][0],
+                           lms=None if ins["lms"] is None else ins["lms"][0],
+                           y=ins["y"][0]) for ins in t["instances"]],
+                 {"lattice": t["lattice_gen"], "dnet": t["net_gen"]}, t["m_max"], t["alpha"],
+                 t["gamma"], t["zeta"], t["sigma2"], dtype=dtype)
+    b.step()
+    torch.cuda.synchronize()
+    ms = [ins["m"] for ins in t["instances"]]
+    kinds = [ins["kind"] for ins in t["instances"]]
+    pick = set()
+    for kind in ("lattice", "dnet"):
+        for m in (18, 12, 15):
+            pick.add(next(i for i in range(len(ms)) if ms[i] == m and kinds[i] == kind))
+    pick |= set(np.random.default_rng(44).choice(len(ms), 6, replace=False).tolist())
+    for i in sorted(pick):
+        w = W.instance_workload(t, i)
+        c, ld = b.result(i)
+        c = c.cpu().double().numpy()[None]
+        if dtype == torch.float64:
+            ref = oracle.fit_solve(w, y=w["y"], precise=True)
+            e64 = rel(ref["c"], ref["c_ld"])
+            err = rel(c, ref["c_ld"])
+            assert err < max(1e-12, 10 * e64), (i, err, e64)
+            e64_ld = abs(ref["logdet"][0] - ref["logdet_ld"][0])
+            assert abs(ld.item() - ref["logdet_ld"][0]) <= max(
+                1e-12 * abs(ref["logdet_ld"][0]), 10 * e64_ld), i
+        else:
+            gi, row = b.where[i]
+            k1r = b.groups[gi]["k1"][row:row + 1].cpu().double().numpy()
+            lam_r = oracle.eig(w["kind"], k1r, precise=True)
+            y = w["y"].astype(np.float32).astype(np.float64)
+            c_ref = oracle.solve(w["kind"], lam_r, w["sigma2"], y, precise=True)
+            lam64, _ = oracle.eig(w["kind"], k1r)
+            e64 = rel(oracle.solve(w["kind"], lam64, w["sigma2"], y), c_ref)
+            tol = max(1e-5, 10 * e64, solve_tol(lam_r, w["sigma2"], y, c_ref, w["m"], F32_EPS))
+            err = rel(c, c_ref)
+            assert err < tol, (i, err, tol)

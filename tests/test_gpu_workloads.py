@@ -30,9 +30,21 @@ def _fit_on_gpu(w, y, dtype):
     return pts, k1, lam, c, ld
 
 
-def _check(orc, w, y_host, dtype=torch.float64, name=""):
+def _bench_path_on_gpu(w, y, dtype):
+    """The benchmark's timed step, call for call: ldk_points_column (point
+    words and first column in one call), then ldk_fit (eigenvalues, the
+    solve and the log-det in one call)."""
+    ps, k = pointset(w), kernel(w)
+    n = 2 ** w["m"]
+    pts, k1 = ldk.points_column(k, ps, 0, n, dtype=dtype)
+    lam, c, ld = ldk.fit(w["kind"], k1, w["sigma2"], y.to(dtype).contiguous())
+    torch.cuda.synchronize()
+    return pts, k1, lam, c, ld
+
+
+def _check(orc, w, y_host, dtype=torch.float64, name="", gpu=_fit_on_gpu):
     ref = orc.fit_solve(w, y=y_host, precise=True)
-    pts, k1, lam, c, ld = _fit_on_gpu(w, torch.from_numpy(y_host).cuda(), dtype)
+    pts, k1, lam, c, ld = gpu(w, torch.from_numpy(y_host).cuda(), dtype)
     assert np.array_equal(host_u64(pts), ref["pts"])
     eps = U64_EPS if dtype == torch.float64 else F32_EPS
     tol_k = (1e-13 if dtype == torch.float64 else 1e-5) * kernel_scale(w)
@@ -88,6 +100,27 @@ def test_workload2_lattice_full(orc, dtype):
     x = W.to_unit_f64(orc.points(w))
     y = W.sine_response(x, w["eps"][:, 0, :])[:, None, :]
     _check(orc, w, np.ascontiguousarray(y), dtype, name=w["name"] + "_" + str(dtype)[-7:])
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_workload2_benchmark_call_sequence(orc, dtype):
+    """The exact calls bench.py times on the n = 2^20, d = 32 lattice
+    workload (points_column, then fit), against the oracle with the same
+    gates as the separate entry points."""
+    w = W.workload(2)
+    x = W.to_unit_f64(orc.points(w))
+    y = W.sine_response(x, w["eps"][:, 0, :])[:, None, :]
+    _check(orc, w, np.ascontiguousarray(y), dtype,
+           name=w["name"] + "_bench_calls_" + str(dtype)[-7:], gpu=_bench_path_on_gpu)
+
+
+def test_workload3_benchmark_call_sequence(orc):
+    """The same call sequence on the n = 2^20, d = 32 net workload (FP64:
+    with sigma^2 = 1e-8 an FP32 column's rounding leaves some
+    lambda_k + sigma^2 <= 0, on the GPU and in the oracle alike)."""
+    w = W.workload(3)
+    _check(orc, w, w["y"], torch.float64, name=w["name"] + "_bench_calls_float64",
+           gpu=_bench_path_on_gpu)
 
 
 def test_workload3_net_full_and_update(orc):
