@@ -41,6 +41,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+# transform plans chosen by paper_2502_14256_amd/tune.py on an MI355X
+TUNED_TABLE = os.path.join(ROOT, "paper_2502_14256_amd", "tuned_mi355x.txt")
 
 # HBM bytes per launch of the points + column kernel (k_points_kcol_lattice)
 # at n = 2^20, d = 32, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of
@@ -77,6 +79,9 @@ def parse():
                    help="arithmetic of the first column and the per-solve data (y, c, solve "
                         "transforms); the eigenvalues, division and log-det stay FP64")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-tuned", action="store_true",
+                   help="use the default transform plans, not the tuned table "
+                        "(paper_2502_14256_amd/tuned_mi355x.txt)")
     p.add_argument("--no-grad", action="store_true",
                    help="skip the marginal-likelihood gradient workload")
     p.add_argument("--no-batch", action="store_true",
@@ -86,6 +91,11 @@ def parse():
                    help="only run the step eagerly 5 times and a 256 MiB device copy 5 times "
                         "(a short program for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs; the "
                         "copy calibrates the counters), then exit")
+    p.add_argument("--solve-probe", action="store_true",
+                   help="only run the cached-lambda Gram solve (lattice n=2^20, FP64, 1 RHS) 20 "
+                        "times eagerly, then a 32 MiB device copy 5 times (a short graph-free "
+                        "program for rocprofv3 kernel traces and FETCH_SIZE / WRITE_SIZE runs; "
+                        "the copy calibrates the counters), then exit")
     p.add_argument("--valu-probe", action="store_true",
                    help="only run the step, the FP32 gradient step and the RQMC estimates a few "
                         "times (a short program for rocprofv3 --pmc SQ_INSTS_VALU runs), then exit")
@@ -106,7 +116,10 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
-    ldk.init()
+    tuned = None if args.no_tuned else TUNED_TABLE
+    if tuned is not None and not os.path.exists(tuned):
+        tuned = None
+    ldk.init(tuned=tuned)
     dt = torch.float64 if args.dtype == "f64" else torch.float32
     esz = 8 if args.dtype == "f64" else 4
 
@@ -153,6 +166,20 @@ def main():
         rqmc_bench(2)
         torch.cuda.synchronize()
         print(json.dumps({"valu_probe": True}), flush=True)
+        return
+
+    if args.solve_probe:
+        # eigenvalues once (untimed), then the solve alone, no graphs
+        ldk.points_column(kern, ps, 0, n, dtype=dt, pts=pts, k1=k1)
+        ldk.eig("lattice", k1, out=lam, ws=ws_eig)
+        for _ in range(20):
+            ldk.solve("lattice", lam, w["sigma2"], y, out=c, ws=ws_solve)
+        src = torch.empty(4 * 2**20, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"solve_probe": True, "copy_bytes": src.numel() * 8}), flush=True)
         return
 
     if args.traffic_probe:
@@ -283,6 +310,7 @@ def main():
                   "op captured alone in a graph and replayed K times, HIP events around the "
                   "replays on the capture stream",
         "graph_equals_eager": graph_matches,
+        "tuned_plans": os.path.relpath(tuned, ROOT) if tuned else None,
         "wall_s_timed": round(wall, 4),
     }
 
@@ -661,11 +689,12 @@ def batch_bench(K, warmup):
     """Instance table of 256 problems of mixed kind (rank-1 lattice with SI
     order 2, or LMS+DS net with DSI order 2) and size n = 2^12 .. 2^18, d = 16,
     8 right-hand sides each, FP64: first column, eigenvalues, 8 solves and the
-    log-det per instance.  Batched: instances of one (kind, m) run as the
-    replications of one point set, one launch per op per group, the whole
-    table captured as one HIP graph.  Plain: the same calls instance by
-    instance (one launch per op per instance), also captured as one graph.
-    Both graphs are replayed K times between HIP events."""
+    log-det per instance.  Batched: the library's batch plan (instances of
+    one (kind, m) run as the replications of one point set, one first-column
+    launch and one fit per group, groups over 1 or 4 streams), captured once
+    as a HIP graph.  Plain: the same calls instance by instance (one launch
+    per op per instance), also captured as one graph.  Graphs are replayed K
+    times between HIP events."""
     import numpy as np
     import torch
 
@@ -676,28 +705,39 @@ def batch_bench(K, warmup):
     inst = [Instance(kind=t["kind"], m=t["m"], shift=t["shift"][0],
                      lms=None if t["lms"] is None else t["lms"][0], y=t["y"][0])
             for t in w["instances"]]
-    b = BatchFit(inst, {"lattice": w["lattice_gen"], "dnet": w["net_gen"]}, w["m_max"],
-                 w["alpha"], w["gamma"], w["zeta"], w["sigma2"])
-    del inst
-    g_batched = b.capture()
-    g_plain = b.capture(plain=True)
-    torch.cuda.synchronize()
     main = torch.cuda.current_stream()
 
-    def timed(g):
+    def timed(fn):
         for _ in range(warmup):
-            g.replay()
+            fn()
         torch.cuda.synchronize()
         a = torch.cuda.Event(enable_timing=True)
         e = torch.cuda.Event(enable_timing=True)
         a.record(main)
         for _ in range(K):
-            g.replay()
+            fn()
         e.record(main)
         torch.cuda.synchronize()
         return a.elapsed_time(e) / K
 
-    ms_b, ms_p = timed(g_batched), timed(g_plain)
+    res = {}
+    for streams in (1, 4):
+        b = BatchFit(inst, {"lattice": w["lattice_gen"], "dnet": w["net_gen"]}, w["m_max"],
+                     w["alpha"], w["gamma"], w["zeta"], w["sigma2"], streams=streams)
+        b.capture()
+        torch.cuda.synchronize()
+        res[streams] = (timed(b.step), b.kernel_nodes(), b.n_groups)
+        if streams == 1:
+            # the plain reference: every instance with the separate entry points
+            g = torch.cuda.CUDAGraph()
+            b.step_plain()
+            torch.cuda.synchronize()
+            with torch.cuda.graph(g):
+                b.step_plain()
+            ms_p = timed(g.replay)
+        del b
+    best = min(res, key=lambda k: res[k][0])
+    ms_b = res[best][0]
     ns = np.array([2 ** t["m"] for t in w["instances"]], dtype=np.int64)
     solves = len(ns) * w["nrhs"]
     alg = int((2 * 8 * w["nrhs"] + 8) * ns.sum())  # read y, write c, read lambda (FP64)
@@ -708,12 +748,17 @@ def batch_bench(K, warmup):
         "value": round(solves / (ms_b * 1e-3), 1),
         "unit": "solves/s",
         "ms_per_step": round(ms_b, 4),
+        "streams": best,
+        "ms_per_step_by_streams": {str(k): round(v[0], 4) for k, v in res.items()},
+        "kernel_launches_per_step": res[best][1],
+        "groups": res[best][2],
         "plain_solves_per_s": round(solves / (ms_p * 1e-3), 1),
         "plain_ms_per_step": round(ms_p, 4),
+        "plain_launches_per_step": 4 * len(ns),
         "speedup_vs_plain": round(ms_p / ms_b, 2),
-        "groups": len(b.groups),
         "solve_alg_bytes": alg,
         "solve_equivalent_GB_s": round(alg / (ms_b * 1e-3) / 1e9, 1),
+        "solve_equivalent_hbm_frac": round(alg / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
     }
 
 

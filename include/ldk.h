@@ -131,6 +131,32 @@ typedef struct {
  * Synchronous.  Returns LDK_OK or LDK_EDEVICE. */
 int ldk_init(void);
 
+/* Tuned plan parameters.  The transform passes of ldk_transform, ldk_eig,
+ * ldk_solve, ldk_matvec and ldk_fit use a tile of 2^log_tile elements per
+ * workgroup and in-register butterfly groups of radix r (2, 4 or 8); the
+ * defaults (2^11 complex FP64 elements, 2^12 otherwise; radix 8) can be
+ * replaced per (kind, working dtype, log2 n, number of rows) by a table
+ * that the project's tuner (paper_2502_14256_amd/tune.py) writes after
+ * timing the candidates on the device.  File format: one entry per line,
+ *     kind dtype m rows_log2 log_tile log2_radix
+ * (kind and dtype as the enums below; '#' starts a comment line).  For a
+ * call with `rows` rows (R * nrhs for solves) the entry with the largest
+ * rows_log2 <= floor(log2 rows) applies.  ldk_init_tuned(path) builds the
+ * twiddle tables (as ldk_init) and replaces the table; path = NULL clears it.
+ * Returns LDK_EINVAL, leaving the table unchanged, when the file cannot be
+ * read or names a plan the pass kernels cannot run.  Results of a call
+ * depend on the plan (the rounding order of the passes), within the
+ * tolerances the tests state; workspace sizes (ldk_workspace_bytes) cover
+ * every plan the table may select.  Not to be called while other threads
+ * enqueue transform calls. */
+int ldk_init_tuned(const char *path);
+
+/* The plan a call of (kind, dtype, log2 n = m, rows) would use: *log_tile,
+ * *radix (2, 4 or 8) and *passes (HBM round trips of one transform).
+ * Any output pointer may be NULL. */
+int ldk_plan_info(int kind, int dtype, int m, int64_t rows, int *log_tile, int *radix,
+                  int *passes);
+
 /* Points i = n_min .. n_max-1 of every replication (Sec. 4.2, 4.3).
  * out = uint64[R][n_max - n_min][d].  Requires 0 <= n_min <= n_max and, for
  * nets and linear lattices, n_max <= 2^m_max. */
@@ -389,6 +415,89 @@ enum {
 int ldk_bayes_cubature(int kind, int R, int m, int dtype, const double *lam, double sigma2,
                        double zeta, const void *y, double z, double *out, void *ws,
                        ldk_stream stream);
+
+/* ---------------------------------------------------------------------
+ * Batched fit of an instance table (Sec. 6 runs many randomizations and
+ * right-hand sides together, vectorised over them).  An instance is one
+ * randomized point set -- a shifted rank-1 lattice or an (LMS-scrambled,)
+ * digitally shifted base-2 net, over the table's one generating vector or
+ * matrix per kind -- with n = 2^m points and nrhs responses; its fit is the
+ * first column, the eigenvalues, every solve (K + sigma^2 I) c = y and the
+ * log-det (as ldk_kernel_column followed by ldk_fit).
+ *
+ * The plan groups instances by (kind, m, nrhs, scrambled): the instances of
+ * a group are the replications of one point set, so each group is one
+ * first-column launch and one fit, and groups are shared out over
+ * desc->streams streams (1..8; forked from and joined back to the caller's
+ * stream through events; default priority).  Data live in five
+ * caller-owned device arenas whose sizes the plan gives
+ * (ldk_plan_arena_bytes): responses Y and solutions C (dtype), eigenvalues
+ * LAM and log-dets LOGDET (double), and the workspace WS (the groups'
+ * shifts, scrambles and scrambled columns, first columns and fit
+ * workspaces).  Instance i's rows start at ldk_plan_instance_offset(i, ...)
+ * elements into Y / C ([nrhs][n]), LAM ([n]), LOGDET ([1]) and, for K1
+ * (its first column, dtype [n]), into WS.  Plans allocate no device
+ * memory; creation and binding are not for hot loops (binding gathers the
+ * instances' shifts and scrambles with device copies and forms each net
+ * replication's scrambled columns once, on `stream`). */
+typedef struct {
+    int32_t d;            /* dimensions of every instance */
+    int32_t m_max;        /* net generating columns per dimension; every m <= m_max */
+    int32_t dtype;        /* LDK_F64 or LDK_F32 (first columns, y, c) */
+    int32_t streams;      /* 1..8 */
+    double sigma2;        /* nugget of every solve */
+    const uint64_t *lattice_gen;  /* device g[d] (when the table has lattices) */
+    const uint64_t *net_gen;      /* device C[d][m_max] (when it has nets) */
+    ldk_kernel lattice_kernel;    /* SI kernel (kind LDK_LATTICE) */
+    ldk_kernel net_kernel;        /* DSI kernel (kind LDK_DNET_B2) */
+} ldk_batch_desc;
+
+typedef struct {
+    int32_t kind;   /* LDK_LATTICE or LDK_DNET_B2 */
+    int32_t m;      /* n = 2^m, m <= m_max */
+    int32_t nrhs;   /* >= 1 */
+    int32_t reserved;
+    const uint64_t *shift;  /* device [d] (read by ldk_plan_bind) */
+    const uint64_t *lms;    /* device [d][64] or NULL (nets only; read by ldk_plan_bind) */
+} ldk_instance;
+
+enum {
+    LDK_ARENA_Y = 0,
+    LDK_ARENA_C = 1,
+    LDK_ARENA_LAM = 2,
+    LDK_ARENA_LOGDET = 3,
+    LDK_ARENA_WS = 4,
+    LDK_ARENA_COUNT = 5,
+    LDK_ARENA_K1 = 5 /* instance offsets only: the first column, in WS */
+};
+
+typedef struct ldk_plan_s *ldk_plan;
+
+/* Validates the table and lays out the arenas (host work only).
+ * LDK_EINVAL for a bad description or instance; LDK_ENOTSUP for a group of
+ * more than 65535 instances. */
+int ldk_plan_create(const ldk_batch_desc *desc, int n_inst, const ldk_instance *inst,
+                    ldk_plan *out);
+/* Arena size in bytes (0 for a bad argument). */
+size_t ldk_plan_arena_bytes(ldk_plan p, int which);
+/* Instance i's first element in arena `which` (elements of the arena's type). */
+int ldk_plan_instance_offset(ldk_plan p, int i, int which, size_t *offset);
+/* Binds the arenas (logdet may be NULL) and enqueues the one-time gathers on
+ * `stream`; drops a graph captured for an earlier binding. */
+int ldk_plan_bind(ldk_plan p, void *y, void *c, double *lam, double *logdet, void *ws,
+                  ldk_stream stream);
+/* Enqueues the whole table on `stream` (replays the captured graph when
+ * there is one).  Outputs are valid once the stream reaches this point. */
+int ldk_batch_launch(ldk_plan p, ldk_stream stream);
+/* Captures the table's launch sequence on `stream` (not the null stream)
+ * as one HIP graph kept by the plan; later ldk_batch_launch calls replay
+ * it.  Nothing runs during the capture. */
+int ldk_batch_capture(ldk_plan p, ldk_stream stream);
+/* Number of groups, and kernel nodes of the captured graph (-1 before a
+ * capture). */
+int ldk_plan_stats(ldk_plan p, int *groups, int *kernel_nodes);
+/* Frees the plan's host memory, streams, events and graph. */
+int ldk_plan_destroy(ldk_plan p);
 
 /* Test integrands of the RQMC estimate, functions of s = sum_j c_j x_j:
  *   LDK_GENZ_CORNER_PEAK  (1 + s)^-(d+1)   (the Genz corner peak, the

@@ -38,6 +38,9 @@ EXPORTS = [
     "ldk_fwht_split16", "ldk_fit", "ldk_points_column", "ldk_interlace", "ldk_wce",
     "ldk_bayes_cubature", "ldk_rqmc", "ldk_rqmc_workspace_bytes", "ldk_solve_checked",
     "ldk_logdet_checked", "ldk_normal_quantile", "ldk_student_t_quantile", "ldk_solve_noalloc",
+    "ldk_init_tuned", "ldk_plan_info", "ldk_plan_create", "ldk_plan_arena_bytes",
+    "ldk_plan_instance_offset", "ldk_plan_bind", "ldk_batch_launch", "ldk_batch_capture",
+    "ldk_plan_stats", "ldk_plan_destroy",
 ]
 
 
@@ -99,6 +102,8 @@ def lib():
             "ldk_normal_quantile": ([f64], f64),
             "ldk_student_t_quantile": ([f64, i32, P], i32),
             "ldk_solve_noalloc": ([i32, i32, i32, i32, i32, P, f64, P, P, P], i32),
+            "ldk_init_tuned": ([C.c_char_p], i32),
+            "ldk_plan_info": ([i32, i32, i32, i64, P, P, P], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -183,8 +188,26 @@ def _workspace(op: int, kind: int, rows: int, m: int, dt: int, device, ws=None):
     return _need_ws(ws, lib().ldk_workspace_bytes(op, kind, rows, m, dt), device)
 
 
-def init():
+def init(tuned: str | None = None):
+    """Build the twiddle tables; with `tuned`, also load that tuned-plan
+    table (see ldk_init_tuned)."""
     _check(lib().ldk_init(), "ldk_init")
+    if tuned is not None:
+        load_tuned(tuned)
+
+
+def load_tuned(path: str | None):
+    """Replace the tuned-plan table with the file at `path` (None clears it)."""
+    _check(lib().ldk_init_tuned(None if path is None else os.fsencode(path)), "ldk_init_tuned")
+
+
+def plan_info(kind, dtype, m: int, rows: int) -> dict:
+    """The plan a transform call would use: log_tile, radix, passes."""
+    lt, rx, ps = C.c_int(), C.c_int(), C.c_int()
+    dt = dtype if isinstance(dtype, int) else _dtype_code(dtype)
+    _check(lib().ldk_plan_info(_kind(kind), dt, m, rows, C.byref(lt), C.byref(rx), C.byref(ps)),
+           "ldk_plan_info")
+    return {"log_tile": lt.value, "radix": rx.value, "passes": ps.value}
 
 
 @dataclass

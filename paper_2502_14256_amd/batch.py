@@ -1,29 +1,43 @@
-"""Batched fit over an instance table of mixed kind and size.
+"""Batched fit of an instance table of mixed kind and size, through the
+library's batch plan (ldk_plan_create / ldk_plan_bind / ldk_batch_launch /
+ldk_batch_capture).
 
-An instance is one randomized point set with its own responses: a rank-1
-lattice or a base-2 net (one shared generating vector or matrix per kind, a
-scramble and shift of its own), n = 2^m points, nrhs responses.  Solving
-instance after instance launches every op once per instance, and at n = 2^12
-one launch is a few workgroups.  Here instances of the same kind and size
-are the replications of one point set (Sec. 4: R independent randomizations
-of one sequence), so each op runs once per (kind, m) group over all its
-instances: the first column (points regenerated in registers), the
-eigenvalues, the solve of every right-hand side and the log-det.  All the
-groups' launches are enqueued on one stream and can be captured as one HIP
-graph (`capture`), which replays the whole table with one host call.
+An instance is one randomized point set (a rank-1 lattice or a base-2 net,
+one shared generating vector or matrix per kind, a scramble and shift of its
+own) with n = 2^m points and nrhs responses.  The plan groups the table by
+(kind, m, nrhs): a group's instances are the replications of one point set,
+so each group is one first-column launch and one fit (eigenvalues, every
+solve and the log-det), and groups are shared out over the plan's streams.
+Captured once, the whole table replays as one HIP graph.
 
-This module only arranges buffers and issues library calls; every step of
-the computation runs in the library's kernels.
+This module only arranges the arenas the plan lays out (torch tensors) and
+issues library calls; every step of the computation runs in the library's
+kernels.
 """
 from __future__ import annotations
 
+import ctypes as C
 from dataclasses import dataclass
 
 import numpy as np
 import torch
 
-from . import (LdkError, Kernel, OP_EIG, OP_FIT, OP_LOGDET, OP_SOLVE, PointSet, _dtype_code,
-               _kind, _workspace, eig, fit, interlace, kernel_column, logdet, solve)
+from . import (DNET_B2, LATTICE, OP_EIG, OP_LOGDET, OP_SOLVE, Kernel, LdkError, PointSet,
+               _Kernel, _check, _dtype_code, _kind, _stream, _workspace, eig, kernel_column, lib,
+               logdet, solve)
+
+ARENA_Y, ARENA_C, ARENA_LAM, ARENA_LOGDET, ARENA_WS, ARENA_K1 = 0, 1, 2, 3, 4, 5
+
+
+class _BatchDesc(C.Structure):
+    _fields_ = [("d", C.c_int32), ("m_max", C.c_int32), ("dtype", C.c_int32),
+                ("streams", C.c_int32), ("sigma2", C.c_double), ("lattice_gen", C.c_void_p),
+                ("net_gen", C.c_void_p), ("lattice_kernel", _Kernel), ("net_kernel", _Kernel)]
+
+
+class _Instance(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("m", C.c_int32), ("nrhs", C.c_int32),
+                ("reserved", C.c_int32), ("shift", C.c_void_p), ("lms", C.c_void_p)]
 
 
 def _dev_u64(a) -> torch.Tensor:
@@ -45,107 +59,181 @@ class Instance:
     lms: np.ndarray | None = None
 
 
+_SIGS = {
+    "ldk_plan_create": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p], C.c_int),
+    "ldk_plan_arena_bytes": ([C.c_void_p, C.c_int], C.c_size_t),
+    "ldk_plan_instance_offset": ([C.c_void_p, C.c_int, C.c_int, C.c_void_p], C.c_int),
+    "ldk_plan_bind": ([C.c_void_p] * 6 + [C.c_void_p], C.c_int),
+    "ldk_batch_launch": ([C.c_void_p, C.c_void_p], C.c_int),
+    "ldk_batch_capture": ([C.c_void_p, C.c_void_p], C.c_int),
+    "ldk_plan_stats": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "ldk_plan_destroy": ([C.c_void_p], C.c_int),
+}
+
+
+def _L():
+    L = lib()
+    if not getattr(L, "_batch_sigs", False):
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        L._batch_sigs = True
+    return L
+
+
 class BatchFit:
     """Fit (first column, eigenvalues, solves, log-det) of every instance.
 
     gen: {"lattice": g[d], "dnet": C[d][m_max]} shared generators;
-    alpha, gamma, zeta: the product kernel per kind ({"lattice": ..., "dnet": ...}
-    for alpha, or one sequence for both), sigma2: the nugget."""
+    alpha: the orders (one sequence for both kinds, or {"lattice": ..., "dnet":
+    ...}); gamma, zeta: the product weights; sigma2: the nugget; streams:
+    the plan's streams (1..8)."""
 
     def __init__(self, instances, gen: dict, m_max: int, alpha, gamma, zeta: float,
-                 sigma2: float, dtype=torch.float64):
+                 sigma2: float, dtype=torch.float64, streams: int = 1):
         if not instances:
             raise LdkError("empty instance table")
+        L = _L()
         self.n_inst = len(instances)
-        self.sigma2 = float(sigma2)
         self.dtype = dtype
+        self.sigma2 = float(sigma2)
         d = len(instances[0].shift)
-        nrhs = instances[0].y.shape[0]
-        self.nrhs = nrhs
-        keys = sorted({(ins.kind, ins.m) for ins in instances})
-        self.groups = []
-        # (group index, row) of every instance, in table order
-        self.where = [None] * self.n_inst
+        self.d, self.m_max = d, m_max
         alpha_of = alpha if isinstance(alpha, dict) else {"lattice": alpha, "dnet": alpha}
-        gamma_d = torch.as_tensor(np.asarray(gamma, np.float64)).cuda()
-        for gi, (kind, m) in enumerate(keys):
-            members = [i for i, ins in enumerate(instances) if ins.kind == kind and ins.m == m]
-            R, n = len(members), 2 ** m
-            shift = np.stack([instances[i].shift for i in members])
-            lms = None
-            if kind == "dnet" and instances[members[0]].lms is not None:
-                lms = np.stack([instances[i].lms for i in members])
-            ps = PointSet(kind, R, d, m_max, _dev_u64(gen[kind]),
-                          None if lms is None else _dev_u64(lms), _dev_u64(shift))
-            if lms is not None and m_max > 0:
-                # each instance's scrambled columns S_j C_j, formed once with
-                # the plan (interlacing of order 1): the same points, and the
-                # column kernel no longer scrambles in every block
-                ps = interlace(ps, 1, shift=ps.shift)
-            kern = Kernel(kind, np.asarray(alpha_of[kind], np.int32), gamma_d, zeta)
-            y = torch.from_numpy(np.ascontiguousarray(
-                np.stack([instances[i].y for i in members]))).to(device="cuda", dtype=dtype)
-            if y.shape != (R, nrhs, n):
-                raise LdkError("every instance needs nrhs x 2^m responses")
-            kd, dt = _kind(kind), _dtype_code(dtype)
-            g = dict(kind=kind, m=m, n=n, R=R, members=members, ps=ps, kern=kern, y=y,
-                     k1=torch.empty((R, n), dtype=dtype, device="cuda"),
-                     lam=torch.empty((R, n), dtype=torch.float64, device="cuda"),
-                     c=torch.empty_like(y),
-                     ld=torch.empty(R, dtype=torch.float64, device="cuda"),
-                     ws_fit=_workspace(OP_FIT, kd, R * (nrhs + 1), m, dt, "cuda"))
-            for row, i in enumerate(members):
-                self.where[i] = (gi, row)
-            self.groups.append(g)
-        self.graph = None
+        self._gamma = torch.as_tensor(np.asarray(gamma, np.float64)).cuda()
+        self._kern = {k: Kernel(k, np.asarray(alpha_of[k], np.int32), self._gamma, zeta)
+                      for k in ("lattice", "dnet")}
+        self._gen = {k: _dev_u64(gen[k]) for k in ("lattice", "dnet") if k in gen}
+        self._inst = instances
+        # per-instance device copies the plan gathers at bind
+        self._shift = [_dev_u64(ins.shift) for ins in instances]
+        self._lms = [None if ins.lms is None else _dev_u64(ins.lms) for ins in instances]
+        arr = (_Instance * self.n_inst)()
+        for i, ins in enumerate(instances):
+            arr[i] = _Instance(_kind(ins.kind), int(ins.m), int(ins.y.shape[0]), 0,
+                               self._shift[i].data_ptr(),
+                               None if self._lms[i] is None else self._lms[i].data_ptr())
+        self._desc = _BatchDesc(d, m_max, _dtype_code(dtype), int(streams), self.sigma2,
+                                self._gen["lattice"].data_ptr() if "lattice" in self._gen else None,
+                                self._gen["dnet"].data_ptr() if "dnet" in self._gen else None,
+                                self._kern["lattice"]._c(), self._kern["dnet"]._c())
+        plan = C.c_void_p()
+        _check(L.ldk_plan_create(C.byref(self._desc), self.n_inst, arr, C.byref(plan)),
+               "ldk_plan_create")
+        self._plan = plan
+        nb = [int(L.ldk_plan_arena_bytes(plan, w)) for w in range(5)]
+        self._y = torch.empty(max(nb[ARENA_Y], 1), dtype=torch.uint8, device="cuda").view(dtype)
+        self._c = torch.empty(max(nb[ARENA_C], 1), dtype=torch.uint8, device="cuda").view(dtype)
+        self._lam = torch.empty(max(nb[ARENA_LAM] // 8, 1), dtype=torch.float64, device="cuda")
+        self._ld = torch.empty(max(nb[ARENA_LOGDET] // 8, 1), dtype=torch.float64, device="cuda")
+        self._ws = torch.empty(max(nb[ARENA_WS], 256), dtype=torch.uint8, device="cuda")
+        self.arena_bytes = dict(zip(("y", "c", "lam", "logdet", "ws"), nb))
+        # responses into their rows
+        for i, ins in enumerate(instances):
+            self.y(i).copy_(torch.from_numpy(np.ascontiguousarray(ins.y)).to(dtype))
+        _check(L.ldk_plan_bind(plan, self._y.data_ptr(), self._c.data_ptr(),
+                               self._lam.data_ptr(), self._ld.data_ptr(), self._ws.data_ptr(),
+                               _stream()), "ldk_plan_bind")
+        g = C.c_int()
+        _check(L.ldk_plan_stats(plan, C.byref(g), None), "ldk_plan_stats")
+        self.n_groups = g.value
 
+    # ---- views into the arenas -------------------------------------------
+    def _off(self, i, which):
+        o = C.c_size_t()
+        _check(_L().ldk_plan_instance_offset(self._plan, i, which, C.byref(o)),
+               "ldk_plan_instance_offset")
+        return o.value
+
+    def _shape(self, i):
+        ins = self._inst[i]
+        return int(ins.y.shape[0]), 2 ** int(ins.m)
+
+    def y(self, i):
+        nrhs, n = self._shape(i)
+        o = self._off(i, ARENA_Y)
+        return self._y[o:o + nrhs * n].view(nrhs, n)
+
+    def c(self, i):
+        nrhs, n = self._shape(i)
+        o = self._off(i, ARENA_C)
+        return self._c[o:o + nrhs * n].view(nrhs, n)
+
+    def lam(self, i):
+        _, n = self._shape(i)
+        o = self._off(i, ARENA_LAM)
+        return self._lam[o:o + n]
+
+    def logdet(self, i):
+        o = self._off(i, ARENA_LOGDET)
+        return self._ld[o]
+
+    def k1(self, i):
+        """Instance i's first column (in the workspace arena)."""
+        _, n = self._shape(i)
+        o = self._off(i, ARENA_K1)
+        return self._ws.view(self.dtype)[o:o + n]
+
+    def result(self, i):
+        """(c[nrhs][n], log-det) of instance i, as device views."""
+        return self.c(i), self.logdet(i)
+
+    # ---- execution ------------------------------------------------------------
     def step(self):
-        """Enqueue the whole table on the current stream: per group, the
-        first column, then eigenvalues, solves and log-det in one fit call."""
-        for g in self.groups:
-            kernel_column(g["kern"], g["ps"], 0, g["n"], dtype=self.dtype, out=g["k1"])
-            fit(g["kind"], g["k1"], self.sigma2, g["y"], lam=g["lam"], c=g["c"], logdet=g["ld"],
-                ws=g["ws_fit"])
+        """Enqueue the whole table on the current stream (replays the
+        captured graph after capture())."""
+        _check(_L().ldk_batch_launch(self._plan, _stream()), "ldk_batch_launch")
+
+    def capture(self):
+        """Capture the table's launches as one HIP graph kept by the plan
+        (on a side stream: the null stream cannot be captured); later
+        step() calls replay it."""
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            _check(_L().ldk_batch_capture(self._plan, _stream()), "ldk_batch_capture")
+        torch.cuda.current_stream().wait_stream(s)
+        return self
+
+    def kernel_nodes(self) -> int:
+        k = C.c_int()
+        _check(_L().ldk_plan_stats(self._plan, None, C.byref(k)), "ldk_plan_stats")
+        return k.value
 
     def step_plain(self):
         """The same work issued instance by instance with the separate entry
-        points (one launch of every op per instance, on row views of the same
-        buffers): the unbatched reference the batched step is compared with."""
+        points (first column, eigenvalues, solve, log-det of one instance per
+        call), into the same arenas: the unbatched reference."""
         if not hasattr(self, "_plain"):
             self._plain = []
-            for g in self.groups:
-                kd, dt = _kind(g["kind"]), _dtype_code(self.dtype)
-                ws = dict(eig=_workspace(OP_EIG, kd, 1, g["m"], dt, "cuda"),
-                          solve=_workspace(OP_SOLVE, kd, self.nrhs, g["m"], dt, "cuda"),
-                          ld=_workspace(OP_LOGDET, kd, 1, g["m"], dt, "cuda"))
-                ps = g["ps"]
-                for row in range(g["R"]):
-                    sl = slice(row, row + 1)
-                    psr = PointSet(g["kind"], 1, ps.d, ps.m_max,
-                                   ps.gen[sl] if ps.per_replication else ps.gen,
-                                   None if ps.lms is None else ps.lms[sl], ps.shift[sl],
-                                   per_replication=ps.per_replication)
-                    self._plain.append((g, sl, psr, ws))
-        for g, sl, psr, ws in self._plain:
-            kernel_column(g["kern"], psr, 0, g["n"], dtype=self.dtype, out=g["k1"][sl])
-            eig(g["kind"], g["k1"][sl], out=g["lam"][sl], ws=ws["eig"])
-            solve(g["kind"], g["lam"][sl], self.sigma2, g["y"][sl], out=g["c"][sl], ws=ws["solve"])
-            logdet(g["lam"][sl], self.sigma2, out=g["ld"][sl], ws=ws["ld"])
+            for i, ins in enumerate(self._inst):
+                kd, dt = _kind(ins.kind), _dtype_code(self.dtype)
+                nrhs, n = self._shape(i)
+                m = int(ins.m)
+                gen = self._gen[ins.kind]
+                lms = self._lms[i]
+                ps = PointSet(ins.kind, 1, self.d, self.m_max, gen,
+                              None if lms is None else lms.view(1, self.d, 64),
+                              self._shift[i].view(1, self.d))
+                k1 = torch.empty((1, n), dtype=self.dtype, device="cuda")
+                ws = dict(eig=_workspace(OP_EIG, kd, 1, m, dt, "cuda"),
+                          solve=_workspace(OP_SOLVE, kd, nrhs, m, dt, "cuda"),
+                          ld=_workspace(OP_LOGDET, kd, 1, m, dt, "cuda"))
+                self._plain.append((i, ins.kind, ps, k1, ws, n))
+        for i, kind, ps, k1, ws, n in self._plain:
+            kernel_column(self._kern[kind], ps, 0, n, dtype=self.dtype, out=k1)
+            lam = self.lam(i).view(1, n)
+            eig(kind, k1, out=lam, ws=ws["eig"])
+            solve(kind, lam, self.sigma2, self.y(i)[None], out=self.c(i)[None], ws=ws["solve"])
+            logdet(lam, self.sigma2, out=self._ld[self._off(i, ARENA_LOGDET):][:1],
+                   ws=ws["ld"])
 
-    def capture(self, plain: bool = False) -> torch.cuda.CUDAGraph:
-        """Capture step() (or step_plain()) as one HIP graph, after one eager run."""
-        fn = self.step_plain if plain else self.step
-        fn()
-        torch.cuda.synchronize()
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            fn()
-        if not plain:
-            self.graph = graph
-        return graph
-
-    def result(self, i: int):
-        """(c[nrhs][n], log-det) of instance i, as device views."""
-        gi, row = self.where[i]
-        g = self.groups[gi]
-        return g["c"][row], g["ld"][row]
+    def __del__(self):
+        try:
+            if getattr(self, "_plan", None):
+                torch.cuda.synchronize()
+                _L().ldk_plan_destroy(self._plan)
+                self._plan = None
+        except Exception:
+            pass

@@ -24,6 +24,25 @@ bool valid_m(int m) { return m >= 0 && m <= TW_MAX_LOG; }
 // Workspace for the complex intermediate of the lattice transforms.
 size_t cplx_rows_bytes(int64_t rows, int m, int dtype) { return (size_t)rows * ((size_t)2 << m) * esize(dtype); }
 
+// The plan over mp index bits of a transform of length 2^m_key, with the
+// parameters plan_params gives (kind, dtype, m_key, rows).
+Plan tuned_plan(int kind, int dtype, int m_key, int mp, int64_t rows)
+{
+    const PlanParams p = plan_params(kind, dtype, m_key, rows);
+    return make_plan(mp, p.log_tile, p.loge_max);
+}
+
+// Whether any plan that may be chosen for (kind, dtype, m_key) over mp bits
+// has more than one pass (the workspace must then hold the intermediate).
+bool any_multipass(int kind, int dtype, int m_key, int mp)
+{
+    PlanParams c[16];
+    const int nc = plan_candidates(kind, dtype, m_key, c, 16);
+    for (int i = 0; i < nc; ++i)
+        if (make_plan(mp, c[i].log_tile, c[i].loge_max).P > 1) return true;
+    return false;
+}
+
 // ---------------------------------------------------------------------------
 // n = 1 (m = 0): every transform is the identity.
 // ---------------------------------------------------------------------------
@@ -162,7 +181,7 @@ int forward_all(int kind, int dtype, int m, int64_t rows, const void *src, int64
                 bool src_real, void *dst, int64_t dst_row, bool dst_real, void *tmp,
                 int64_t tmp_row, double scale, hipStream_t s, bool src_f32 = false)
 {
-    const Plan pl = make_plan(m, log_tile_for(kind, dtype));
+    const Plan pl = tuned_plan(kind, dtype, m, m, rows);
     for (int p = 0; p < pl.P; ++p) {
         const bool first = p == 0, last = p == pl.P - 1;
         PassArgs a{};
@@ -188,7 +207,7 @@ int forward_all(int kind, int dtype, int m, int64_t rows, const void *src, int64
 int apply_all(int kind, int dtype, int mode, int m, int64_t rows, int nrhs, const double *lam,
               double sigma2, const void *src, void *dst, void *tmp, hipStream_t s)
 {
-    const Plan pl = make_plan(m, log_tile_for(kind, dtype));
+    const Plan pl = tuned_plan(kind, dtype, m, m, rows);
     const int64_t n = (int64_t)1 << m;
     const bool lat = kind == LDK_LATTICE;
     void *work = (lat && pl.P > 1) ? tmp : dst;
@@ -256,7 +275,7 @@ int real_eig(int m, int64_t rows, const void *k1, bool k1_f32, double *lam, void
 {
     const int mp = m - 1;
     const int64_t N = (int64_t)1 << mp;
-    const Plan pl = make_plan(mp, log_tile_for(LDK_LATTICE, LDK_F64));
+    const Plan pl = tuned_plan(LDK_LATTICE, LDK_F64, m, mp, rows);
     PassArgs a{};
     a.rows = rows;
     a.m = mp;
@@ -293,7 +312,7 @@ int real_apply(int dtype, int mode, int m, int64_t rows, int nrhs, const double 
 {
     const int mp = m - 1;
     const int64_t N = (int64_t)1 << mp;
-    const Plan pl = make_plan(mp, log_tile_for(LDK_LATTICE, dtype));
+    const Plan pl = tuned_plan(LDK_LATTICE, dtype, m, mp, rows);
     PassArgs a{};
     a.rows = rows;
     a.m = mp;
@@ -381,26 +400,21 @@ size_t ws_bytes(int op, int kind, int64_t B, int m, int dtype)
     if (op == LDK_OP_WCE || op == LDK_OP_BAYES_CUBATURE) return cub_ws_bytes(kind, B, m, dtype);
     if (m == 0) return op == LDK_OP_LOGDET ? (size_t)B * sizeof(double) : 0;
     const bool lat = kind == LDK_LATTICE;
-    const int P = make_plan(m, log_tile_for(kind, dtype)).P;
+    // sizes hold for every plan the tuned table may select (any rows)
     switch (op) {
     case LDK_OP_TRANSFORM: return 0;
     case LDK_OP_EIG: {
         // FP64 transform whatever the input dtype; real lattice rows of n run
         // as packed complex rows of n/2
-        if (real_path(kind, m)) {
-            const int P64 = make_plan(m - 1, log_tile_for(kind, LDK_F64)).P;
-            return P64 > 1 ? cplx_rows_bytes(B, m - 1, LDK_F64) : 0;
-        }
-        const int P64 = make_plan(m, log_tile_for(kind, LDK_F64)).P;
-        return (lat && P64 > 1) ? cplx_rows_bytes(B, m, LDK_F64) : 0;
+        if (real_path(kind, m))
+            return any_multipass(kind, LDK_F64, m, m - 1) ? cplx_rows_bytes(B, m - 1, LDK_F64) : 0;
+        return (lat && any_multipass(kind, LDK_F64, m, m)) ? cplx_rows_bytes(B, m, LDK_F64) : 0;
     }
     case LDK_OP_SOLVE:
     case LDK_OP_MATVEC:
-        if (real_path(kind, m)) {
-            const int Pp = make_plan(m - 1, log_tile_for(kind, dtype)).P;
-            return Pp > 1 ? cplx_rows_bytes(B, m - 1, dtype) : 0;
-        }
-        return (lat && P > 1) ? cplx_rows_bytes(B, m, dtype) : 0;
+        if (real_path(kind, m))
+            return any_multipass(kind, dtype, m, m - 1) ? cplx_rows_bytes(B, m - 1, dtype) : 0;
+        return (lat && any_multipass(kind, dtype, m, m)) ? cplx_rows_bytes(B, m, dtype) : 0;
     case LDK_OP_LOGDET: {
         const int64_t n = (int64_t)1 << m;
         const int64_t chunks = (n + LOGDET_CHUNK - 1) / LOGDET_CHUNK;
@@ -418,12 +432,16 @@ size_t fit_ws_bytes(int kind, int64_t B, int m, int dtype)
     // path taken when the fused one does not apply, and for nrhs = 0)
     size_t w = ws_bytes(LDK_OP_EIG, kind, B, m, dtype);
     if (fit_fused(kind, m, dtype)) {
-        const Plan pl = make_plan(m - 1, log_tile_for(LDK_LATTICE, LDK_F64));
-        const PassGeom top = fit_top_geom(pl);  // at least as many tiles as the plan's top
-        const size_t cb = (size_t)1 << (top.b0 - top.logW);
-        const size_t rows = pl.P > 1 ? (size_t)B * ((size_t)1 << (m - 1)) * 16 : 0;
-        const size_t f = align256((size_t)B * cb * sizeof(double)) + rows;
-        if (f > w) w = f;
+        PlanParams cand[16];
+        const int nc = plan_candidates(LDK_LATTICE, LDK_F64, m, cand, 16);
+        for (int i = 0; i < nc; ++i) {
+            const Plan pl = make_plan(m - 1, cand[i].log_tile, cand[i].loge_max);
+            const PassGeom top = fit_top_geom(pl);  // at least as many tiles as the plan's top
+            const size_t cb = (size_t)1 << (top.b0 - top.logW);
+            const size_t rows = pl.P > 1 ? (size_t)B * ((size_t)1 << (m - 1)) * 16 : 0;
+            const size_t f = align256((size_t)B * cb * sizeof(double)) + rows;
+            if (f > w) w = f;
+        }
     }
     const size_t ws = ws_bytes(LDK_OP_SOLVE, kind, B, m, dtype);
     const size_t wl = ws_bytes(LDK_OP_LOGDET, kind, B, m, dtype);
@@ -467,7 +485,7 @@ int ldk_transform(int kind, int dir, int B, int m, int dtype, const void *in, vo
     if (kind == LDK_DNET_B2 || dir == 1)
         return forward_all(kind, dtype, m, B, in, n, false, out, n, false, out, n, scale, s);
     // inverse FFTBR: passes from the top down
-    const Plan pl = make_plan(m, log_tile_for(kind, dtype));
+    const Plan pl = tuned_plan(kind, dtype, m, m, B);
     for (int p = pl.P - 1; p >= 0; --p) {
         PassArgs a{};
         a.src = p == pl.P - 1 ? in : out;
@@ -597,7 +615,7 @@ int ldk_fit(int kind, int R, int nrhs, int m, int dtype, const void *k1, double 
     hipStream_t s = as_stream(stream);
     const int mp = m - 1;
     const int64_t n = (int64_t)1 << m, N = n / 2;
-    const Plan pl = make_plan(mp, log_tile_for(LDK_LATTICE, LDK_F64));
+    const Plan pl = tuned_plan(LDK_LATTICE, LDK_F64, m, mp, B);
     // one rhs per column: both top passes in one launch (narrower tiles)
     const PassGeom ftop = fit_top_geom(pl);
     const bool one_top = nrhs == 1 && fit_top_supported(ftop);

@@ -1,5 +1,8 @@
 // Pass kernels of the FWHT / FFTBR / IFFTBR engine (see transform.hpp).
+#include <cstdio>
+#include <mutex>
 #include <type_traits>
+#include <vector>
 
 #include "passkit.hpp"
 
@@ -253,13 +256,13 @@ int launch_m(int mode, int ld, int st, const PassArgs &a, hipStream_t s)
 
 }  // namespace
 
-Plan make_plan(int m, int log_tile)
+Plan make_plan(int m, int log_tile, int loge_max)
 {
     Plan p{};
     p.m = m;
     if (m == 0) return p;
     constexpr int LOG_THREADS = 9;  // at most 512 threads per workgroup
-    constexpr int LOGE_MAX = 3;     // 8 elements per thread
+    const int LOGE_MAX = loge_max < 1 ? 1 : (loge_max > 3 ? 3 : loge_max);  // elements per thread
     // row pass: the low a0 bits; column passes: the rest, split evenly into
     // chunks of at most 8 bits (at least 4 where possible)
     int a0 = m < log_tile ? m : log_tile;
@@ -289,6 +292,109 @@ Plan make_plan(int m, int log_tile)
 }
 
 int log_tile_for(int kind, int dtype) { return (kind == LDK_LATTICE && dtype == LDK_F64) ? 11 : 12; }
+
+bool plan_ok(const Plan &pl)
+{
+    for (int p = 0; p < pl.P; ++p) {
+        const PassGeom &g = pl.pass[p];
+        const int lt = g.a + g.logW - g.logE;  // log2 threads
+        if (g.logE < 1 || g.logE > 3 || lt < 0 || lt > 9) return false;
+        if ((g.a + g.logE - 1) / g.logE > MAX_GROUPS) return false;
+        if (g.logW > g.b0) return false;
+    }
+    return true;
+}
+
+namespace {
+struct TuneEntry {
+    int kind, dtype, m, rows_log2, log_tile, loge_max;
+};
+std::mutex g_tune_mutex;
+std::vector<TuneEntry> g_tune;
+
+int floor_log2(int64_t v)
+{
+    int r = 0;
+    while (v > 1) {
+        v >>= 1;
+        ++r;
+    }
+    return r;
+}
+}  // namespace
+
+PlanParams plan_params(int kind, int dtype, int m, int64_t rows)
+{
+    PlanParams p{log_tile_for(kind, dtype), 3};
+    const int rl = floor_log2(rows < 1 ? 1 : rows);
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    int best = -1;
+    for (const TuneEntry &e : g_tune)
+        if (e.kind == kind && e.dtype == dtype && e.m == m && e.rows_log2 <= rl && e.rows_log2 > best) {
+            best = e.rows_log2;
+            p = PlanParams{e.log_tile, e.loge_max};
+        }
+    return p;
+}
+
+int plan_candidates(int kind, int dtype, int m, PlanParams *out, int cap)
+{
+    int c = 0;
+    if (c < cap) out[c++] = PlanParams{log_tile_for(kind, dtype), 3};
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    for (const TuneEntry &e : g_tune)
+        if (e.kind == kind && e.dtype == dtype && e.m == m && c < cap)
+            out[c++] = PlanParams{e.log_tile, e.loge_max};
+    return c;
+}
+
+// Replaces the table (empty for path == nullptr); a file that does not parse
+// or names a plan the pass kernels cannot run leaves the table unchanged.
+int load_tune_table(const char *path)
+{
+    std::vector<TuneEntry> t;
+    if (path) {
+        FILE *f = std::fopen(path, "r");
+        if (!f) return LDK_EINVAL;
+        char line[256];
+        int bad = 0;
+        while (std::fgets(line, sizeof line, f)) {
+            const char *q = line;
+            while (*q == ' ' || *q == '\t') ++q;
+            if (*q == '#' || *q == '\n' || *q == 0) continue;
+            TuneEntry e{};
+            if (std::sscanf(q, "%d %d %d %d %d %d", &e.kind, &e.dtype, &e.m, &e.rows_log2,
+                            &e.log_tile, &e.loge_max) != 6) {
+                bad = 1;
+                break;
+            }
+            const bool ok_key = (e.kind == LDK_LATTICE || e.kind == LDK_DNET_B2) &&
+                                (e.dtype == LDK_F64 || e.dtype == LDK_F32) && e.m >= 1 &&
+                                e.m <= LDK_MAX_M && e.rows_log2 >= 0 && e.rows_log2 < 63;
+            // LDS: the largest tile is 2^12 complex FP64 (68 KiB with padding)
+            if (!ok_key || e.log_tile < 6 || e.log_tile > 12 || e.loge_max < 1 || e.loge_max > 3) {
+                bad = 1;
+                break;
+            }
+            // the plan it selects (real lattice rows run as complex rows of n/2)
+            const int mp = (e.kind == LDK_LATTICE && e.m >= 2) ? e.m - 1 : e.m;
+            const Plan pl = make_plan(mp, e.log_tile, e.loge_max);
+            // the real-data top pass pairs mirror columns: at least 2 per tile
+            const bool mirror_ok = !(e.kind == LDK_LATTICE && e.m >= 2 && pl.P > 1 &&
+                                     pl.pass[pl.P - 1].logW < 1);
+            if (!plan_ok(pl) || !mirror_ok) {
+                bad = 1;
+                break;
+            }
+            t.push_back(e);
+        }
+        std::fclose(f);
+        if (bad) return LDK_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_tune.swap(t);
+    return LDK_OK;
+}
 
 int launch_pass(int kind, int dtype, int mode, int ld, int st, const PassArgs &a, hipStream_t s,
                 bool src_f32)
@@ -357,3 +463,26 @@ int launch_pass2(int kind, int dtype, int mode, int ld, int st, const PassArgs &
 }
 
 }  // namespace ldk
+
+extern "C" int ldk_init_tuned(const char *path)
+{
+    const int st = ldk::ensure_init();
+    if (st) return st;
+    return ldk::load_tune_table(path);
+}
+
+extern "C" int ldk_plan_info(int kind, int dtype, int m, int64_t rows, int *log_tile,
+                             int *radix, int *passes)
+{
+    if ((kind != LDK_LATTICE && kind != LDK_DNET_B2) || (dtype != LDK_F64 && dtype != LDK_F32) ||
+        m < 0 || m > LDK_MAX_M || rows < 1)
+        return LDK_EINVAL;
+    const ldk::PlanParams p = ldk::plan_params(kind, dtype, m, rows);
+    const int mp = (kind == LDK_LATTICE && m >= 2) ? m - 1 : m;
+    const ldk::Plan pl = ldk::make_plan(mp, p.log_tile, p.loge_max);
+    if (log_tile) *log_tile = p.log_tile;
+    if (radix) *radix = 1 << p.loge_max;
+    if (passes) *passes = pl.P;
+    return LDK_OK;
+}
+

@@ -45,10 +45,30 @@ struct Plan {
     PassGeom pass[4];
 };
 
-// log_tile: log2 of the elements per workgroup tile (LDS budget).  The plan
-// depends on m and the tile only, so results do not depend on the batch size.
-Plan make_plan(int m, int log_tile);
+// log_tile: log2 of the elements per workgroup tile (LDS budget); loge_max:
+// log2 of the largest register group (the butterfly radix of the in-register
+// stages).  The plan depends on m and these two only, so for given
+// parameters results do not depend on the batch size.
+Plan make_plan(int m, int log_tile, int loge_max = 3);
 int log_tile_for(int kind, int dtype);
+// Whether every pass of a plan fits the pass kernels (threads per
+// workgroup, register groups per axis).
+bool plan_ok(const Plan &pl);
+
+// Plan parameters of the eigenvalue, solve, matvec, fit and transform
+// paths.  Defaults: log_tile_for(kind, dtype) and radix 8.  A table written
+// by the tuner (ldk_init_tuned) may replace them per (kind, working dtype,
+// log2 n, rows): the entry with the largest rows_log2 <= log2(rows) applies.
+struct PlanParams {
+    int log_tile;
+    int loge_max;
+};
+PlanParams plan_params(int kind, int dtype, int m, int64_t rows);
+// Every parameter set plan_params may return for (kind, dtype, m), whatever
+// the rows (workspace sizes are the largest over them).  Returns the count.
+int plan_candidates(int kind, int dtype, int m, PlanParams *out, int cap);
+// Loads (path) or clears (nullptr) the tuned-parameter table.
+int load_tune_table(const char *path);
 
 struct PassArgs {
     const void *src;

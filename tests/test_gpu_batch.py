@@ -48,7 +48,7 @@ def _single(t, i, dtype=torch.float64):
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_batched_equals_single_calls(table, dtype):
     b = _batch(table, dtype)
-    assert len(b.groups) == len(set(zip(MS, KINDS)))
+    assert b.n_groups == len(set(zip(MS, KINDS)))
     b.step()
     for i in range(len(MS)):
         c, ld = b.result(i)
@@ -86,21 +86,40 @@ def test_batched_matches_oracle(table):
                                                            10 * e64_ld), i
 
 
-def test_batched_graph_replays(table):
-    b = _batch(table)
-    g = b.capture()
+@pytest.mark.parametrize("streams", [1, 4])
+def test_batched_graph_replays(table, streams):
+    b = BatchFit(_instances(table), {"lattice": table["lattice_gen"], "dnet": table["net_gen"]},
+                 table["m_max"], table["alpha"], table["gamma"], table["zeta"], table["sigma2"],
+                 streams=streams)
+    b.step()
     torch.cuda.synchronize()
     ref = [tuple(t.clone() for t in b.result(i)) for i in range(len(MS))]
+    b.capture()
+    assert b.kernel_nodes() > 0
     for rep in range(3):
-        for grp in b.groups:
-            grp["c"].fill_(-1)
-            grp["ld"].fill_(-1)
+        b._c.fill_(-1)
+        b._ld.fill_(-1)
         torch.cuda.synchronize()
-        g.replay()
+        b.step()  # replays the captured graph
         torch.cuda.synchronize()
         for i in range(len(MS)):
             c, ld = b.result(i)
             assert torch.equal(c, ref[i][0]) and torch.equal(ld, ref[i][1]), (rep, i)
+
+
+def test_plan_refuses_bad_tables(table):
+    from paper_2502_14256_amd.batch import _BatchDesc, _Instance, _L
+    import ctypes as C
+    L = _L()
+    ok = _BatchDesc(5, 13, ldk.F64, 1, 1e-8, None, None)
+    arr = (_Instance * 1)()
+    arr[0] = _Instance(ldk.DNET_B2, 9, 2, 0, 0x1000, None)
+    plan = C.c_void_p()
+    assert L.ldk_plan_create(C.byref(ok), 1, arr, C.byref(plan)) == -1  # no net generator
+    arr[0] = _Instance(ldk.LATTICE, 14, 2, 0, 0x1000, None)  # m > m_max
+    assert L.ldk_plan_create(C.byref(ok), 1, arr, C.byref(plan)) == -1
+    bad = _BatchDesc(5, 13, ldk.F64, 9, 1e-8, None, None)  # 9 streams
+    assert L.ldk_plan_create(C.byref(bad), 1, arr, C.byref(plan)) == -1
 
 
 @pytest.mark.slow
@@ -143,8 +162,7 @@ def test_workload4_full_table_subset_against_oracle(dtype):
             assert abs(ld.item() - ref["logdet_ld"][0]) <= max(
                 1e-12 * abs(ref["logdet_ld"][0]), 10 * e64_ld), i
         else:
-            gi, row = b.where[i]
-            k1r = b.groups[gi]["k1"][row:row + 1].cpu().double().numpy()
+            k1r = b.k1(i)[None].cpu().double().numpy()
             lam_r = oracle.eig(w["kind"], k1r, precise=True)
             y = w["y"].astype(np.float32).astype(np.float64)
             c_ref = oracle.solve(w["kind"], lam_r, w["sigma2"], y, precise=True)
