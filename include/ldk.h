@@ -138,8 +138,13 @@ int ldk_init(void);
  * replaced per (kind, working dtype, log2 n, number of rows) by a table
  * that the project's tuner (paper_2502_14256_amd/tune.py) writes after
  * timing the candidates on the device.  File format: one entry per line,
- *     kind dtype m rows_log2 log_tile log2_radix
- * (kind and dtype as the enums below; '#' starts a comment line).  For a
+ *     kind dtype m rows_log2 log_tile log2_radix [engine]
+ * (kind and dtype as the enums below; '#' starts a comment line).  The
+ * optional engine field selects the Walsh-Hadamard passes of FP32
+ * digital-net solves and matvecs: 0 (the default) the FP32 butterflies, 1
+ * the split-FP16 matrix-core passes of ldk_fwht_split16 (allowed only for
+ * kind LDK_DNET_B2, dtype LDK_F32 and m >= 12; normwise error of order 1e-7
+ * per transform, like the butterflies; the eigenvalues stay FP64).  For a
  * call with `rows` rows (R * nrhs for solves) the entry with the largest
  * rows_log2 <= floor(log2 rows) applies.  ldk_init_tuned(path) builds the
  * twiddle tables (as ldk_init) and replaces the table; path = NULL clears it.
@@ -152,10 +157,11 @@ int ldk_init(void);
 int ldk_init_tuned(const char *path);
 
 /* The plan a call of (kind, dtype, log2 n = m, rows) would use: *log_tile,
- * *radix (2, 4 or 8) and *passes (HBM round trips of one transform).
- * Any output pointer may be NULL. */
+ * *radix (2, 4 or 8), *passes (HBM round trips of one transform) and
+ * *engine (0 butterflies, 1 split-FP16 matrix cores).  Any output pointer
+ * may be NULL. */
 int ldk_plan_info(int kind, int dtype, int m, int64_t rows, int *log_tile, int *radix,
-                  int *passes);
+                  int *passes, int *engine);
 
 /* Points i = n_min .. n_max-1 of every replication (Sec. 4.2, 4.3).
  * out = uint64[R][n_max - n_min][d].  Requires 0 <= n_min <= n_max and, for

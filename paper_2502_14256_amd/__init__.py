@@ -103,7 +103,7 @@ def lib():
             "ldk_student_t_quantile": ([f64, i32, P], i32),
             "ldk_solve_noalloc": ([i32, i32, i32, i32, i32, P, f64, P, P, P], i32),
             "ldk_init_tuned": ([C.c_char_p], i32),
-            "ldk_plan_info": ([i32, i32, i32, i64, P, P, P], i32),
+            "ldk_plan_info": ([i32, i32, i32, i64, P, P, P, P], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -202,12 +202,13 @@ def load_tuned(path: str | None):
 
 
 def plan_info(kind, dtype, m: int, rows: int) -> dict:
-    """The plan a transform call would use: log_tile, radix, passes."""
-    lt, rx, ps = C.c_int(), C.c_int(), C.c_int()
+    """The plan a transform call would use: log_tile, radix, passes and
+    engine (0 FP32/FP64 butterflies, 1 split-FP16 matrix cores)."""
+    lt, rx, ps, en = C.c_int(), C.c_int(), C.c_int(), C.c_int()
     dt = dtype if isinstance(dtype, int) else _dtype_code(dtype)
-    _check(lib().ldk_plan_info(_kind(kind), dt, m, rows, C.byref(lt), C.byref(rx), C.byref(ps)),
-           "ldk_plan_info")
-    return {"log_tile": lt.value, "radix": rx.value, "passes": ps.value}
+    _check(lib().ldk_plan_info(_kind(kind), dt, m, rows, C.byref(lt), C.byref(rx), C.byref(ps),
+                               C.byref(en)), "ldk_plan_info")
+    return {"log_tile": lt.value, "radix": rx.value, "passes": ps.value, "engine": en.value}
 
 
 @dataclass

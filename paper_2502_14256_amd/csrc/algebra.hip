@@ -557,6 +557,10 @@ static int apply_entry(int mode, int kind, int R, int nrhs, int m, int dtype, co
         return LDK_OK;
     }
     if (real_path(kind, m)) return real_apply(dtype, mode, m, rows, nrhs, lam, sigma2, y, c, ws, s);
+    if (kind == LDK_DNET_B2 && dtype == LDK_F32 && m >= 12 &&
+        plan_params(kind, dtype, m, rows).engine == ENGINE_SPLIT16)
+        return fwht16_apply(mode, m, rows, nrhs, lam, sigma2, static_cast<const float *>(y),
+                            static_cast<float *>(c), s);
     return apply_all(kind, dtype, mode, m, rows, nrhs, lam, sigma2, y, c, ws, s);
 }
 

@@ -307,7 +307,7 @@ bool plan_ok(const Plan &pl)
 
 namespace {
 struct TuneEntry {
-    int kind, dtype, m, rows_log2, log_tile, loge_max;
+    int kind, dtype, m, rows_log2, log_tile, loge_max, engine;
 };
 std::mutex g_tune_mutex;
 std::vector<TuneEntry> g_tune;
@@ -325,14 +325,14 @@ int floor_log2(int64_t v)
 
 PlanParams plan_params(int kind, int dtype, int m, int64_t rows)
 {
-    PlanParams p{log_tile_for(kind, dtype), 3};
+    PlanParams p{log_tile_for(kind, dtype), 3, ENGINE_BUTTERFLY};
     const int rl = floor_log2(rows < 1 ? 1 : rows);
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     int best = -1;
     for (const TuneEntry &e : g_tune)
         if (e.kind == kind && e.dtype == dtype && e.m == m && e.rows_log2 <= rl && e.rows_log2 > best) {
             best = e.rows_log2;
-            p = PlanParams{e.log_tile, e.loge_max};
+            p = PlanParams{e.log_tile, e.loge_max, e.engine};
         }
     return p;
 }
@@ -340,11 +340,11 @@ PlanParams plan_params(int kind, int dtype, int m, int64_t rows)
 int plan_candidates(int kind, int dtype, int m, PlanParams *out, int cap)
 {
     int c = 0;
-    if (c < cap) out[c++] = PlanParams{log_tile_for(kind, dtype), 3};
+    if (c < cap) out[c++] = PlanParams{log_tile_for(kind, dtype), 3, ENGINE_BUTTERFLY};
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     for (const TuneEntry &e : g_tune)
         if (e.kind == kind && e.dtype == dtype && e.m == m && c < cap)
-            out[c++] = PlanParams{e.log_tile, e.loge_max};
+            out[c++] = PlanParams{e.log_tile, e.loge_max, e.engine};
     return c;
 }
 
@@ -363,8 +363,17 @@ int load_tune_table(const char *path)
             while (*q == ' ' || *q == '\t') ++q;
             if (*q == '#' || *q == '\n' || *q == 0) continue;
             TuneEntry e{};
-            if (std::sscanf(q, "%d %d %d %d %d %d", &e.kind, &e.dtype, &e.m, &e.rows_log2,
-                            &e.log_tile, &e.loge_max) != 6) {
+            // six fields, and an optional seventh: the engine (0 when absent)
+            const int got = std::sscanf(q, "%d %d %d %d %d %d %d", &e.kind, &e.dtype, &e.m,
+                                        &e.rows_log2, &e.log_tile, &e.loge_max, &e.engine);
+            if (got != 6 && got != 7) {
+                bad = 1;
+                break;
+            }
+            if (got == 6) e.engine = ENGINE_BUTTERFLY;
+            // the matrix-core passes: FP32 net rows of at least 2^12
+            if (e.engine != ENGINE_BUTTERFLY &&
+                (e.engine != ENGINE_SPLIT16 || e.kind != LDK_DNET_B2 || e.dtype != LDK_F32 || e.m < 12)) {
                 bad = 1;
                 break;
             }
@@ -472,7 +481,7 @@ extern "C" int ldk_init_tuned(const char *path)
 }
 
 extern "C" int ldk_plan_info(int kind, int dtype, int m, int64_t rows, int *log_tile,
-                             int *radix, int *passes)
+                             int *radix, int *passes, int *engine)
 {
     if ((kind != LDK_LATTICE && kind != LDK_DNET_B2) || (dtype != LDK_F64 && dtype != LDK_F32) ||
         m < 0 || m > LDK_MAX_M || rows < 1)
@@ -483,6 +492,7 @@ extern "C" int ldk_plan_info(int kind, int dtype, int m, int64_t rows, int *log_
     if (log_tile) *log_tile = p.log_tile;
     if (radix) *radix = 1 << p.loge_max;
     if (passes) *passes = pl.P;
+    if (engine) *engine = p.engine;
     return LDK_OK;
 }
 

@@ -59,10 +59,14 @@ bool plan_ok(const Plan &pl);
 // paths.  Defaults: log_tile_for(kind, dtype) and radix 8.  A table written
 // by the tuner (ldk_init_tuned) may replace them per (kind, working dtype,
 // log2 n, rows): the entry with the largest rows_log2 <= log2(rows) applies.
+// engine: the FWHT of FP32 digital-net solves and matvecs (m >= 12):
+// 0 = the FP32 butterfly passes, 1 = the split-FP16 matrix-core passes.
 struct PlanParams {
     int log_tile;
     int loge_max;
+    int engine;
 };
+enum { ENGINE_BUTTERFLY = 0, ENGINE_SPLIT16 = 1 };
 PlanParams plan_params(int kind, int dtype, int m, int64_t rows);
 // Every parameter set plan_params may return for (kind, dtype, m), whatever
 // the rows (workspace sizes are the largest over them).  Returns the count.
@@ -144,6 +148,13 @@ bool fit_top_supported(const PassGeom &g);
 // Two jobs of the same pass kind in one launch (blocks of job 0, then job 1).
 int launch_pass2(int kind, int dtype, int mode, int ld, int st, const PassArgs &a0,
                  const PassArgs &a1, hipStream_t s);
+
+// Solve (PM_SOLVE) or matvec (PM_MATVEC) of FP32 digital-net rows on the
+// matrix-core FWHT (fwht_mfma.hip): rows = R nrhs rows of n = 2^m, m >= 12
+// (LDK_ENOTSUP below); lam = FP64 [R][n]; c may alias y; no workspace (the
+// intermediate lives in c).
+int fwht16_apply(int mode, int m, int64_t rows, int nrhs, const double *lam, double sigma2,
+                 const float *y, float *c, hipStream_t s);
 
 // Sum of log(s) over a thread's values in product form: s = m 2^e with m in
 // [1/2, 1); the mantissas multiply and the exponents add, with one log at

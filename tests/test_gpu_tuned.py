@@ -109,7 +109,7 @@ def test_table_rules(tmp_path):
     _load(tmp_path, [_line("dnet", ldk.F64, 16, 1, 10, 3), _line("dnet", ldk.F64, 16, 16, 12, 2)])
     assert ldk.plan_info("dnet", ldk.F64, 16, 1)["log_tile"] == 10
     assert ldk.plan_info("dnet", ldk.F64, 16, 15)["log_tile"] == 10
-    assert ldk.plan_info("dnet", ldk.F64, 16, 16) == {"log_tile": 12, "radix": 4,
+    assert ldk.plan_info("dnet", ldk.F64, 16, 16) == {"log_tile": 12, "radix": 4, "engine": 0,
                                                        "passes": ldk.plan_info("dnet", ldk.F64,
                                                                                16, 16)["passes"]}
     assert ldk.plan_info("dnet", ldk.F64, 17, 16)["log_tile"] == 12  # default elsewhere
