@@ -119,6 +119,8 @@ def main():
     tuned = None if args.no_tuned else TUNED_TABLE
     if tuned is not None and not os.path.exists(tuned):
         tuned = None
+    global _TUNED_PATH
+    _TUNED_PATH = tuned
     ldk.init(tuned=tuned)
     dt = torch.float64 if args.dtype == "f64" else torch.float32
     esz = 8 if args.dtype == "f64" else 4
@@ -325,6 +327,27 @@ def main():
     if not args.no_batch:
         out["batched"] = batch_bench(args.batch_steps, args.warmup)
 
+    if "batched" in out and "grad" in out:
+        bt, f, gr = out["batched"], out["batched"]["f32"], out["grad"]
+        out["batched_mfma_grad_vs_plain"] = {
+            "table_solves_per_s": {
+                "batched_f32_split16_nets": f["batched_split16"]["solves_per_s"],
+                "batched_f32_butterflies": f["batched_butterflies"]["solves_per_s"],
+                "batched_f64": bt["value"],
+                "plain_f32": f["plain_butterflies"]["solves_per_s"],
+                "plain_f64": bt["plain_solves_per_s"]},
+            "table_err_c_vs_f64_max": {
+                "batched_f32_split16_nets": f["batched_split16"]["err_c_vs_f64_max"],
+                "batched_f32_butterflies": f["batched_butterflies"]["err_c_vs_f64_max"],
+                "plain_f32": f["plain_butterflies"]["err_c_vs_f64_max"]},
+            "gradient_replications_per_s": {"batched_f32": gr["value"],
+                                            "plain_f32": gr["plain_per_replication"]["value"]},
+            "gradient_err_vs_f64": {"batched_f32": gr["f32_grad_rel_err_vs_f64"],
+                                    "plain_f32": gr["plain_per_replication"]["grad_rel_err_vs_f64"]},
+            "note": "the instance table (256 instances, n = 2^12..2^18, 8 RHS) and the gradient "
+                    "workload (64 replications, n = 2^16, d = 64); FP32 errors against the "
+                    "FP64 results of the same GPU path"}
+
     out["fwht_split16"] = fwht_bench(K)
     out["higher_order_net"] = higher_order_bench(K)
     out["cubature"] = cubature_bench(K, lam, y[:, 0, :], w)
@@ -344,6 +367,39 @@ def main():
         out["fp32_step"].pop("_c")
 
     print(json.dumps(out), flush=True)
+
+
+_TUNED_PATH = None
+
+
+def engine_table(engine):
+    """A copy of the loaded tuned table in which every FP32 digital-net entry
+    is replaced by one engine (0 FP32 butterflies, 1 split-FP16 matrix
+    cores) for every m >= 12 and row count; returns its path."""
+    import tempfile
+
+    lines = []
+    if _TUNED_PATH:
+        with open(_TUNED_PATH) as f:
+            lines = [ln for ln in f if not ln.split()[:2] == ["1", "1"]]
+    lines += [f"1 1 {m} 0 12 3 {engine}\n" for m in range(12, 27)]
+    fd, path = tempfile.mkstemp(prefix="ldk_engine_", suffix=".txt")
+    with os.fdopen(fd, "w") as f:
+        f.writelines(lines)
+    return path
+
+
+def with_engine(engine, fn):
+    """fn() with the FP32 net engine forced; the tuned table afterwards."""
+    import paper_2502_14256_amd as ldk
+
+    path = engine_table(engine)
+    try:
+        ldk.load_tuned(path)
+        return fn()
+    finally:
+        ldk.load_tuned(_TUNED_PATH)
+        os.unlink(path)
 
 
 def time_graph(fn, K):
@@ -440,8 +496,8 @@ def grad_bench(K, warmup, probe=False):
             for nm in names:
                 ops[nm]()
         return None
-    res = {}
-    for dt in (torch.float32, torch.float64):
+
+    def run(dt, per_op=True):
         b = buffers(dt)
         ops = ops_of(b, dt)
 
@@ -454,10 +510,50 @@ def grad_bench(K, warmup, probe=False):
         torch.cuda.synchronize()
         ms = time_graph(step, K)
         grad = torch.cat([b["kg"], b["ds"][:, None]], dim=1).cpu().numpy()
-        res[dt] = dict(ms=ms, grad=grad, L=b["L"].cpu().numpy(),
-                       per_op={nm: time_graph(ops[nm], K) for nm in names})
-    r32, r64 = res[torch.float32], res[torch.float64]
-    err = float(np.max(np.abs(r32["grad"] - r64["grad"])) / np.max(np.abs(r64["grad"])))
+        return dict(ms=ms, grad=grad, L=b["L"].cpu().numpy(),
+                    per_op={nm: time_graph(ops[nm], K) for nm in names} if per_op else None)
+
+    def run_plain(dt):
+        # the unbatched form: the same calls one replication at a time
+        b = buffers(dt)
+        code = ldk._dtype_code(dt)
+        ws_eig = ldk._workspace(ldk.OP_EIG, ldk.DNET_B2, 1, m, code, "cuda")
+        ws_mll = ldk._workspace(ldk.OP_MLL, ldk.DNET_B2, 1, m, code, "cuda")
+        ws_grad = torch.empty(ldk.lib().ldk_kernel_grad_workspace_bytes(1, d, 0, n, 0),
+                              dtype=torch.uint8, device="cuda")
+        reps = []
+        for r in range(R):
+            ps_r = ldk.PointSet("dnet", 1, d, m, ps.gen[r:r + 1], None, ps.shift[r:r + 1],
+                                per_replication=True)
+            reps.append((ps_r, *(b[k][r:r + 1] for k in ("k1", "lam", "y", "g", "a", "kg", "L",
+                                                           "ds"))))
+
+        def step():
+            for ps_r, k1, lam, y, g, a, kg, L, ds in reps:
+                ldk.kernel_column(kern, ps_r, 0, n, dtype=dt, out=k1)
+                ldk.eig("dnet", k1, out=lam, ws=ws_eig)
+                ldk._check(ldk.lib().ldk_mll(ldk.DNET_B2, 1, m, code, ldk._ptr(lam), w["sigma2"],
+                                             ldk._ptr(y), ldk._ptr(L), ldk._ptr(g), ldk._ptr(ds),
+                                             ldk._ptr(ws_mll), ldk._stream()), "ldk_mll")
+                ldk.mll_adjoint("dnet", g, out=a)
+                ldk.kernel_grad(kern, ps_r, 0, n, a, dtype=dt, out=kg, ws=ws_grad, k1=k1)
+
+        step()
+        torch.cuda.synchronize()
+        ms = time_graph(step, K)
+        grad = torch.cat([b["kg"], b["ds"][:, None]], dim=1).cpu().numpy()
+        return dict(ms=ms, grad=grad)
+
+    r32 = run(torch.float32)
+    r32_b = with_engine(0, lambda: run(torch.float32, per_op=False))
+    r32_m = with_engine(1, lambda: run(torch.float32, per_op=False))
+    r64 = run(torch.float64)
+    p32 = run_plain(torch.float32)
+
+    def gerr(r):
+        return float(np.max(np.abs(r["grad"] - r64["grad"])) / np.max(np.abs(r64["grad"])))
+
+    err = gerr(r32)
     # factor evaluations of the gradient kernel: one sweep, the forward
     # column supplies the product of the factors
     evals = R * n * d
@@ -474,6 +570,16 @@ def grad_bench(K, warmup, probe=False):
         "ops_ms_f64": {nm: round(r64["per_op"][nm], 5) for nm in names},
         "kernel_grad_factor_evals_per_s": round(evals / (kg_ms * 1e-3), 1),
         "f32_grad_rel_err_vs_f64": err,
+        "f32_transform_of_y": {
+            "butterflies": {"ms_per_step": round(r32_b["ms"], 5),
+                            "grad_rel_err_vs_f64": gerr(r32_b)},
+            "split16": {"ms_per_step": round(r32_m["ms"], 5), "grad_rel_err_vs_f64": gerr(r32_m)}},
+        "plain_per_replication": {"ms_per_step": round(p32["ms"], 5),
+                                  "value": round(R / (p32["ms"] * 1e-3), 1),
+                                  "grad_rel_err_vs_f64": gerr(p32),
+                                  "note": "FP32, the same five calls for one replication at a "
+                                          "time (64 x 5 launches per step)"},
+        "speedup_vs_plain": round(p32["ms"] / r32["ms"], 2),
         "dtype": "f32 kernel factors and transform of y; f64 eigenvalues, g, adjoint, sums",
     }
 
@@ -656,10 +762,11 @@ def update_bench(K):
 
 
 def fwht_bench(K):
-    """The net workload's transform at n = 2^20 (one FP32 row of responses):
-    FP32 butterfly passes against the split-FP16 matrix-core passes, device
-    time per launch (graph replays) and each one's normwise error against the
-    FP64 transform of the same row."""
+    """The net workload's transform at n = 2^20: one FP32 row of responses,
+    and 16 rows (the workload's response with 15 seeded normal rows): FP32
+    butterfly passes against the split-FP16 matrix-core passes, device time
+    per launch (graph replays) and each one's normwise error against the
+    FP64 transform of the same rows."""
     import numpy as np
     import torch
 
@@ -667,22 +774,31 @@ def fwht_bench(K):
     import workloads as W
 
     w = W.workload(3)
-    x64 = torch.from_numpy(np.ascontiguousarray(w["y"][:, 0, :])).cuda()
-    x32 = x64.float()
-    ref = ldk.transform("dnet", x64)
-    y_b, y_m = torch.empty_like(x32), torch.empty_like(x32)
-    ms_b = time_graph(lambda: ldk.transform("dnet", x32, out=y_b), K)
-    ms_m = time_graph(lambda: ldk.fwht_split16(x32, out=y_m), K)
+    row = np.ascontiguousarray(w["y"][:, 0, :])
+    extra = np.random.default_rng(20260).standard_normal((15, row.shape[1]))
+    res = {}
+    for B in (1, 16):
+        x64 = torch.from_numpy(np.concatenate([row, extra[:B - 1]])).cuda()
+        x32 = x64.float()
+        ref = ldk.transform("dnet", x64)
+        y_b, y_m = torch.empty_like(x32), torch.empty_like(x32)
+        ms_b = time_graph(lambda: ldk.transform("dnet", x32, out=y_b), K)
+        ms_m = time_graph(lambda: ldk.fwht_split16(x32, out=y_m), K)
 
-    def err(y):
-        return float(torch.linalg.norm(y.double() - ref) / torch.linalg.norm(ref))
+        def err(y):
+            return float(torch.linalg.norm(y.double() - ref) / torch.linalg.norm(ref))
 
-    nbytes = 2 * 4 * x32.numel()
-    return {"n": x32.numel(), "fp32_butterflies_ms": round(ms_b, 5),
+        nbytes = 2 * 4 * x32.numel()
+        res[f"rows{B}"] = {
+            "n": x32.shape[1], "rows": B, "fp32_butterflies_ms": round(ms_b, 5),
             "split16_mfma_ms": round(ms_m, 5),
             "fp32_butterflies_GB_s": round(nbytes / (ms_b * 1e-3) / 1e9, 1),
             "split16_mfma_GB_s": round(nbytes / (ms_m * 1e-3) / 1e9, 1),
+            "split16_over_butterflies": round(ms_m / ms_b, 3),
             "fp32_butterflies_rel_err": err(y_b), "split16_mfma_rel_err": err(y_m)}
+        del x64, x32, y_b, y_m, ref
+    res["bytes"] = "read + write of the FP32 rows once (each engine makes two passes at 2^20)"
+    return res
 
 
 def batch_bench(K, warmup):
@@ -741,6 +857,49 @@ def batch_bench(K, warmup):
     ns = np.array([2 ** t["m"] for t in w["instances"]], dtype=np.int64)
     solves = len(ns) * w["nrhs"]
     alg = int((2 * 8 * w["nrhs"] + 8) * ns.sum())  # read y, write c, read lambda (FP64)
+
+    # FP32: first column, responses, solutions and solve transforms in FP32
+    # (eigenvalues, division and log-det in FP64); net solves on the FP32
+    # butterflies or the split-FP16 matrix cores; per-instance errors
+    # against the FP64 batched results (themselves held to the FP64 oracle
+    # by the parity tests)
+    gens = {"lattice": w["lattice_gen"], "dnet": w["net_gen"]}
+    b64 = BatchFit(inst, gens, w["m_max"], w["alpha"], w["gamma"], w["zeta"], w["sigma2"],
+                   streams=best)
+    b64.step()
+    torch.cuda.synchronize()
+    c64 = [b64.c(i).cpu().numpy() for i in range(len(inst))]
+    ld64 = np.array([b64.logdet(i).item() for i in range(len(inst))])
+    del b64
+
+    def f32_leg(plain):
+        b = BatchFit(inst, gens, w["m_max"], w["alpha"], w["gamma"], w["zeta"], w["sigma2"],
+                     dtype=torch.float32, streams=best)
+        if plain:
+            g = torch.cuda.CUDAGraph()
+            b.step_plain()
+            torch.cuda.synchronize()
+            with torch.cuda.graph(g):
+                b.step_plain()
+            ms = timed(g.replay)
+        else:
+            b.capture()
+            torch.cuda.synchronize()
+            ms = timed(b.step)
+        ec = np.array([np.linalg.norm(b.c(i).double().cpu().numpy() - c64[i])
+                       / np.linalg.norm(c64[i]) for i in range(len(inst))])
+        eld = np.array([abs(b.logdet(i).item() - ld64[i]) / abs(ld64[i])
+                        for i in range(len(inst))])
+        del b
+        return {"ms_per_step": round(ms, 4), "solves_per_s": round(solves / (ms * 1e-3), 1),
+                "err_c_vs_f64_max": float(ec.max()), "err_c_vs_f64_median": float(np.median(ec)),
+                "err_c_vs_f64_net_max": float(max(e for e, t in zip(ec, w["instances"])
+                                                  if t["kind"] == "dnet")),
+                "err_logdet_vs_f64_max": float(eld.max())}
+
+    f32 = {"batched_split16": with_engine(1, lambda: f32_leg(False)),
+           "batched_butterflies": with_engine(0, lambda: f32_leg(False)),
+           "plain_butterflies": with_engine(0, lambda: f32_leg(True))}
     return {
         "workload": "batched_256_mixed_d16 (256 instances, kind lattice/net at random, "
                     "n=2^12..2^18, d=16, 8 RHS, FP64): kernel_column + eig + solve + logdet "
@@ -759,6 +918,10 @@ def batch_bench(K, warmup):
         "solve_alg_bytes": alg,
         "solve_equivalent_GB_s": round(alg / (ms_b * 1e-3) / 1e9, 1),
         "solve_equivalent_hbm_frac": round(alg / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "f32": f32,
+        "f32_note": "FP32 column, responses, solutions and solve transforms; FP64 eigenvalues, "
+                    "division and log-det; errors per instance against the FP64 batched "
+                    "results (normwise c; relative log-det)",
     }
 
 

@@ -6,14 +6,12 @@
 // product Y = H_16 X of 16x16 matrices.  The FP32 data are split into two
 // FP16 terms, X = X_hi + X_lo (X_lo = the rounding error of X_hi), and the
 // stage is one matrix instruction with K = 32 over both terms,
-//   Y = [H_16 | H_16] [X_hi ; X_lo]     (v_mfma_f32_16x16x32_f16, FP32 sums),
-// exact in the products (H_16 is +-1) and in the FP32 accumulation up to
-// rounding.  The K order of the instruction is free as long as both operands
-// use the same one, so each lane keeps the high and low terms of its own four
-// elements in one 8-wide operand and every element is read once.  Before
-// every stage the values are scaled by a power of two so that |x| < 2^14 (the
-// FP16 range), from the current maximum of the elements the stage mixes
-// (about 22 significant bits per stage).
+//   Y = [H | H] [X_hi ; X_lo]     (v_mfma_f32_16x16x32_f16, FP32 sums),
+// exact in the products (the entries of H are +-2^-k) and in the FP32
+// accumulation up to rounding.  The K order of the instruction is free as
+// long as both operands use the same one, so each lane keeps the high and low
+// terms of its own four elements in one 8-wide operand and every element is
+// read once.
 //
 // Register-resident stages (m >= 12): a workgroup of 4 waves takes a tile of
 // 2^12 elements, 16 per lane.  Lane l holds, for each of its four 16x16
@@ -25,11 +23,14 @@
 // 8 bits of a row tile take two stages with no data movement, and each further
 // digit costs one LDS exchange of the tile.  Partial digits (pass axes that
 // are not a multiple of 4 bits) use a masked H_16 (H_2^k on the masked bits,
-// the identity on the others).
+// the identity on the others).  The matrix is H / 2^k (k digit bits), so a
+// stage never increases the largest magnitude: the tile is scaled once per
+// pass by a power of two that puts its maximum just below 2^14 (the FP16
+// range), and the store multiplies by 2^(pass bits) over that scale.
 //
 // Passes (m >= 12): a row pass over the low 12 bits (contiguous tiles), then
 // column passes of a <= 8 axis bits over tiles of 2^a strided rows x
-// 2^(12 - a) contiguous columns; the 16 lowest column bits of a tile are the
+// 2^(12 - a) contiguous columns; the 4 lowest column bits of a tile are the
 // N digit, so global loads and stores move 64-byte runs.  The solve and
 // matvec (filter by scale / (lambda + sigma^2) or scale * lambda) run the top
 // pass as forward stages, the filter in FP64 on the register values, and the
@@ -337,6 +338,8 @@ struct F16Args {
     int mode;
     double sigma2;
     double fscale;
+    // plain passes, optional: store |x|^2 in FP64 here instead of x in dst
+    double *pow;
 };
 
 // ROW: the row pass (a = 12, logW = 0); TOP: forward stages, filter, inverse
@@ -462,6 +465,13 @@ __global__ __launch_bounds__(256) void k_fwht16(F16Args a)
 #pragma unroll
             for (int i = 0; i < 4; ++i) x[i] = v[4 * beta + i] * gain;
             *reinterpret_cast<float4v *>(p + lo) = x;
+        } else if (!TOP && a.pow) {
+            double *pw = a.pow + tbase;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const double x = (double)(v[4 * beta + i] * gain);
+                (pw + phi(q_of(lay, kb, 0, w, beta, i), logW, b0))[lo] = x * x;
+            }
         } else {
 #pragma unroll
             for (int i = 0; i < 4; ++i)
@@ -518,8 +528,10 @@ static int launch_f16(const F16Plan &pl, int p, F16Args a, int64_t rows, bool ve
 
 static bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
 
-// Plain transform of `rows` rows, m >= 12; the last pass scales by `scale`.
-static int f16_transform(int m, int64_t rows, const float *in, float *out, float scale, hipStream_t s)
+// Plain transform of `rows` rows, m >= 12; the last pass scales by `scale`
+// and, with pow, stores the squares there (FP64) instead of in out.
+static int f16_transform(int m, int64_t rows, const float *in, float *out, float scale, hipStream_t s,
+                         double *pow = nullptr)
 {
     const F16Plan pl = f16_plan(m);
     const bool vec = aligned16(in) && aligned16(out);
@@ -530,10 +542,17 @@ static int f16_transform(int m, int64_t rows, const float *in, float *out, float
         a.m = m;
         a.scale = p == pl.P - 1 ? scale : 1.0f;
         a.neg1 = -1.0f;
+        a.pow = p == pl.P - 1 ? pow : nullptr;
         const int st = launch_f16<false>(pl, p, a, rows, vec, s);
         if (st) return st;
     }
     return LDK_OK;
+}
+
+int fwht16_power(int m, int64_t rows, const float *y, float *tmp, double *pw, hipStream_t s)
+{
+    if (m < 12) return LDK_ENOTSUP;
+    return f16_transform(m, rows, y, tmp, 1.0f, s, pw);
 }
 
 int fwht16_apply(int mode, int m, int64_t rows, int nrhs, const double *lam, double sigma2,

@@ -182,6 +182,9 @@ int power_spectrum(int kind, int R, int m, int dtype, const void *y, double *pw,
         return launch_real_top(dtype, PM_POWER, a, pw, s);
     }
     // FWHT (nets; for n = 2 the lattice FFTBR is the same 2-point butterfly)
+    if (kind == LDK_DNET_B2 && dtype == LDK_F32 && m >= 12 &&
+        plan_params(kind, dtype, m, R).engine == ENGINE_SPLIT16)
+        return fwht16_power(m, R, static_cast<const float *>(y), static_cast<float *>(tmp), pw, s);
     const Plan pl = make_plan(m, log_tile_for(LDK_DNET_B2, dtype));
     a.m = m;
     for (int p = 0; p < pl.P; ++p) {

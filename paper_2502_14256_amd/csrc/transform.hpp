@@ -156,6 +156,11 @@ int launch_pass2(int kind, int dtype, int mode, int ld, int st, const PassArgs &
 int fwht16_apply(int mode, int m, int64_t rows, int nrhs, const double *lam, double sigma2,
                  const float *y, float *c, hipStream_t s);
 
+// |H y|^2 (unnormalised) of FP32 digital-net rows, FP64 into pw [rows][n],
+// on the matrix-core FWHT; m >= 12; tmp = FP32 [rows][n] for the passes
+// before the last (unused when m = 12).
+int fwht16_power(int m, int64_t rows, const float *y, float *tmp, double *pw, hipStream_t s);
+
 // Sum of log(s) over a thread's values in product form: s = m 2^e with m in
 // [1/2, 1); the mantissas multiply and the exponents add, with one log at
 // the end (k mantissas keep the product above 2^-k, so no underflow for the

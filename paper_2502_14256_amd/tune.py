@@ -1,9 +1,11 @@
-"""Tuner of the transform plans (tile size and butterfly radix).
+"""Tuner of the transform plans (tile size, butterfly radix and, for FP32
+digital-net rows of 2^12 and more, the engine: FP32 butterflies or the
+split-FP16 matrix-core passes).
 
 For each case (kind, working dtype, log2 n, rows, op) it loads, one at a
-time, a one-entry table for every candidate (log_tile, radix) that the
-library accepts, times the op captured in a HIP graph and replayed K times,
-and keeps the fastest.  The chosen entries are written in the format
+time, a one-entry table for every candidate (log_tile, radix, engine) that
+the library accepts, times the op captured in a HIP graph and replayed K
+times, and keeps the fastest.  The chosen entries are written in the format
 ldk_init_tuned reads; every timing is returned too.
 
 Run on the GPU the table is for:
@@ -41,6 +43,13 @@ def default_cases():
             cases.append((kind, ldk.F64, m, 18, "eig"))
     cases.append(("lattice", ldk.F64, 20, 2, "fit"))
     cases.append(("dnet", ldk.F64, 16, 64, "eig"))
+    # FP32 nets: the same solve shapes, and the gradient workload's
+    # likelihood (64 rows of 2^16)
+    for rows in (1, 16):
+        cases.append(("dnet", ldk.F32, 20, rows, "solve"))
+    for m in range(12, 19):
+        cases.append(("dnet", ldk.F32, m, 144, "solve"))
+    cases.append(("dnet", ldk.F32, 16, 64, "mll"))
     return cases
 
 
@@ -89,16 +98,23 @@ def _op(kind, dtype, m, rows, op, seed=0):
         ld = torch.empty(R, dtype=torch.float64, device="cuda")
         ws = ldk._workspace(ldk.OP_FIT, kd, 2 * R, m, dtype, "cuda")
         return lambda: ldk.fit(kind, k1, 1e-3, y, lam=lam, c=c, logdet=ld, ws=ws)
+    if op == "mll":
+        lam = torch.from_numpy(1.0 + rng.random((rows, n))).cuda()
+        y = torch.from_numpy(rng.standard_normal((rows, n))).to(dt).cuda()
+        g = torch.empty((rows, n), dtype=torch.float64, device="cuda")
+        ws = ldk._workspace(ldk.OP_MLL, kd, rows, m, dtype, "cuda")
+        return lambda: ldk.mll(kind, lam, 1e-3, y, out_g=g, ws=ws)
     raise ValueError(op)
 
 
-def _table_line(kind, dtype, m, rows, log_tile, log_radix):
-    return f"{KINDS[kind]} {dtype} {m} {int(math.log2(rows))} {log_tile} {log_radix}\n"
+def _table_line(kind, dtype, m, rows, log_tile, log_radix, engine=0):
+    return f"{KINDS[kind]} {dtype} {m} {int(math.log2(rows))} {log_tile} {log_radix} {engine}\n"
 
 
 def tune(cases=None, K: int = 20, out: str | None = None, verbose: bool = True):
     """Time every accepted candidate for every case; write the fastest to
-    `out` (when given).  Returns [(case, [(log_tile, log_radix, ms)], best)]."""
+    `out` (when given).  Returns [(case, [(log_tile, log_radix, engine, ms)],
+    best)]."""
     ldk.init()
     cases = cases or default_cases()
     results, lines = [], []
@@ -106,42 +122,46 @@ def tune(cases=None, K: int = 20, out: str | None = None, verbose: bool = True):
     path = os.path.join(tmpdir, "candidate.txt")
     def load(entries):
         with open(path, "w") as f:
-            f.writelines(_table_line(kind, dtype, m, rows, lt, lr) for lt, lr in entries)
+            f.writelines(_table_line(kind, dtype, m, rows, *e) for e in entries)
         ldk.load_tuned(path)
 
     for case in cases:
         kind, dtype, m, rows, op = case
         accepted = []
-        for lt in LOG_TILES:
-            for lr in LOG_RADIX:
-                try:
-                    load([(lt, lr)])
-                    accepted.append((lt, lr))
-                except ldk.LdkError:
-                    pass  # a plan the pass kernels cannot run
+        cands = [(lt, lr, 0) for lt in LOG_TILES for lr in LOG_RADIX]
+        if kind == "dnet" and dtype == ldk.F32 and m >= 12:
+            cands.append((12, 3, 1))  # the matrix-core passes (tile and radix unused)
+        for e in cands:
+            try:
+                load([e])
+                accepted.append(e)
+            except ldk.LdkError:
+                pass  # a plan the pass kernels cannot run
         # workspaces sized while every candidate is in the table (the size
         # covers every plan the table may select), then one candidate at a time
         load(accepted)
         fn = _op(kind, dtype, m, rows, op)
         timings = []
-        for lt, lr in accepted:
-            load([(lt, lr)])
-            timings.append((lt, lr, _time(fn, K)))
+        for e in accepted:
+            load([e])
+            timings.append((*e, _time(fn, K)))
         ldk.load_tuned(None)
-        best = min(timings, key=lambda t: t[2])
-        lines.append(_table_line(kind, dtype, m, rows, best[0], best[1]))
+        best = min(timings, key=lambda t: t[3])
+        lines.append(_table_line(kind, dtype, m, rows, best[0], best[1], best[2]))
         results.append((case, timings, best))
         if verbose:
             dflt = ldk.plan_info(kind, dtype, m, rows)
-            print(f"{kind:8s} dtype={dtype} m={m:2d} rows={rows:4d} {op:5s}: best tile 2^{best[0]} "
-                  f"radix {2 ** best[1]} {best[2] * 1e3:8.2f} us (default tile 2^{dflt['log_tile']}"
-                  f": {dict(((t[0], t[1]), t[2]) for t in timings).get((dflt['log_tile'], 3), float('nan')) * 1e3:8.2f} us)",
-                  flush=True)
+            t_dflt = dict(((t[0], t[1], t[2]), t[3]) for t in timings).get(
+                (dflt["log_tile"], 3, 0), float("nan"))
+            what = "split16 matrix cores" if best[2] else f"tile 2^{best[0]} radix {2 ** best[1]}"
+            print(f"{kind:8s} dtype={dtype} m={m:2d} rows={rows:4d} {op:5s}: best {what} "
+                  f"{best[3] * 1e3:8.2f} us (default tile 2^{dflt['log_tile']}: "
+                  f"{t_dflt * 1e3:8.2f} us)", flush=True)
         del fn
     if out:
         with open(out, "w") as f:
-            f.write("# kind dtype m rows_log2 log_tile log2_radix  (ldk_init_tuned; written by "
-                    "paper_2502_14256_amd/tune.py)\n")
+            f.write("# kind dtype m rows_log2 log_tile log2_radix engine  (ldk_init_tuned; "
+                    "written by paper_2502_14256_amd/tune.py)\n")
             f.writelines(lines)
     return results
 

@@ -114,3 +114,53 @@ def test_split16_solve_and_matvec_match_oracle(orc, split16_table, m, R, nrhs):
            tol=tol, err_matvec=err_v, err_matvec_butterflies=rel(v_b, v_ref), tol_matvec=tol_v)
     assert err < tol, (err, tol, rel(c_b, c_ref))
     assert err_v < tol_v, (err_v, tol_v, rel(v_b, v_ref))
+
+
+@pytest.mark.parametrize("m", [12, 13, 16, 20])
+def test_split16_likelihood_matches_oracle(orc, split16_table, m):
+    # the likelihood's |H y|^2 for FP32 net rows on the matrix-core passes:
+    # the FP32 gate of the butterfly path
+    import workloads as W
+    R = 2 if m < 16 else 1
+    w = W.small_net(40 + m, m, 3, R)
+    w.update(alpha=np.array([2, 4, 1], np.int32), gamma=np.array([0.9, 0.5, 0.3]), zeta=1.0,
+             sigma2=1e-2)
+    assert ldk.plan_info("dnet", ldk.F32, m, R)["engine"] == 1
+    pts = orc.points(w)
+    k1 = orc.kernel_column("dnet", pts, pts[:, 0], w["alpha"], w["gamma"], w["zeta"])
+    lam = orc.eig("dnet", k1)[0]
+    y = w["y"][:, 0, :].astype(np.float32)
+    L_ref, g_ref, ds_ref = orc.mll("dnet", lam, w["sigma2"], y.astype(np.float64))
+    L, g, ds = (t.cpu().numpy() for t in ldk.mll("dnet", torch.from_numpy(lam).cuda(), w["sigma2"],
+                                                  torch.from_numpy(y).cuda()))
+    tol = 4e-6 * m
+    eL = np.max(np.abs(L - L_ref) / np.maximum(1.0, np.abs(L_ref)))
+    eg = rel(g, g_ref)
+    eds = np.max(np.abs(ds - ds_ref) / np.maximum(1.0, np.abs(ds_ref)))
+    record(f"split16_mll_dnet_m{m}", err_L=eL, err_g=eg, err_ds=eds, tol=tol)
+    assert eL < tol and eg < tol and eds < tol, (eL, eg, eds, tol)
+
+
+def test_split16_gradient_step_matches_oracle(orc, split16_table):
+    # the FP32 gradient step with the matrix-core transform of y, gated like
+    # the butterfly path (10x the FP64 oracle's own error, FP32 unit roundoff)
+    import workloads as W
+    from ldk_dev import F32_EPS, gate_vs_ld, kernel, pointset
+    m, d, R = 13, 6, 3
+    w = W.small_net(76, m, d, R)
+    w.update(alpha=np.full(d, 2, np.int32), gamma=1.0 / np.arange(1, d + 1) ** 2, zeta=1.0,
+             sigma2=1e-3)
+    ref, ref_ld = orc.mll_grad(w), orc.mll_grad_ld(w)
+    n = 2**m
+    ps, k = pointset(w), kernel(w)
+    k1 = ldk.kernel_column(k, ps, 0, n, dtype=torch.float32)
+    lam = ldk.eig("dnet", k1)
+    y = torch.from_numpy(w["y"][:, 0, :]).cuda().float()
+    L, g, ds = ldk.mll("dnet", lam, w["sigma2"], y)
+    kg = ldk.kernel_grad(k, ps, 0, n, ldk.mll_adjoint("dnet", g), dtype=torch.float32, k1=k1)
+    grad = torch.cat([kg, ds[:, None]], dim=1).cpu().numpy()
+    Lh = L.cpu().numpy()
+    oL = gate_vs_ld(Lh[:, None], ref["L"][:, None], ref_ld["L"][:, None], F32_EPS, 1e-5).max()
+    oG = gate_vs_ld(grad, ref["grad"], ref_ld["grad"], F32_EPS, 1e-5).max()
+    record("split16_grad_step_dnet_m13_d6", L_over_gate=oL, grad_over_gate=oG)
+    assert oL <= 1.0 and oG <= 1.0, (oL, oG)

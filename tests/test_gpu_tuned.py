@@ -134,13 +134,19 @@ def test_table_rules(tmp_path):
 def test_tuner_writes_a_loadable_table(tmp_path):
     from paper_2502_14256_amd import tune
     out = tmp_path / "tuned.txt"
-    res = tune.tune([("dnet", ldk.F64, 14, 4, "solve"), ("lattice", ldk.F64, 13, 2, "eig")],
+    res = tune.tune([("dnet", ldk.F64, 14, 4, "solve"), ("lattice", ldk.F64, 13, 2, "eig"),
+                     ("dnet", ldk.F32, 13, 4, "solve"), ("dnet", ldk.F32, 12, 2, "mll")],
                     K=3, out=str(out), verbose=False)
-    assert len(res) == 2 and all(len(r[1]) >= 2 for r in res)
+    assert len(res) == 4 and all(len(r[1]) >= 2 for r in res)
+    # the FP32 net cases time the matrix-core engine as one candidate
+    assert all(any(t[2] == 1 for t in r[1]) for r in res[2:])
     ldk.load_tuned(str(out))
     for (case, timings, best) in res:
         kind, dt, m, rows, _ = case
-        assert ldk.plan_info(kind, dt, m, rows)["log_tile"] == best[0]
+        info = ldk.plan_info(kind, dt, m, rows)
+        assert info["engine"] == best[2]
+        if best[2] == 0:
+            assert info["log_tile"] == best[0]
 
 
 def test_committed_table_loads():
