@@ -44,30 +44,34 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # transform plans chosen by paper_2502_14256_amd/tune.py on an MI355X
 TUNED_TABLE = os.path.join(ROOT, "paper_2502_14256_amd", "tuned_mi355x.txt")
 
-# HBM bytes per launch of the points + column kernel (k_points_kcol_lattice)
-# at n = 2^20, d = 32, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of
-# `bench.py --traffic-probe`, scaled by the counters of the plain 256 MiB
-# device copy in the same program (x2 reads, x1 writes;
-# profiles/traffic_lattice_m20_d32_f64.md).  Valid only for the kernel source
-# they were taken on: the sources' SHA-1 is checked at run time and the figure
-# reported as null once they change.
-STEP_TRAFFIC = {"read_MiB": 0.17, "write_MiB": 264.00,
-                "sources": ("kcol.hip", "kfactor.hpp", "pointset.hpp", "common.hpp"),
-                "sha1": "f0bfcb66431a54c2f5f278439dcef1b96d3267ae"}
+# HBM bytes per call, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of the
+# graph-free probes (`bench.py --traffic-probe`: the points + column kernel
+# k_points_kcol_lattice at n = 2^20, d = 32; `bench.py --solve-probe`: the
+# three kernels of one FP64 lattice solve at n = 2^20, one RHS), each scaled
+# by the counters of a plain device copy of known size in the same program
+# (x2 reads, x1 writes; profiles/traffic_lattice_m20_d32_f64.md).  Valid only
+# for the kernel sources they were taken on: the sources' SHA-1 is checked at
+# run time and the figure reported as null once they change.
+STEP_TRAFFIC = {"read_MiB": 0.15, "write_MiB": 264.00,
+                "sources": ('kcol.hip', 'kfactor.hpp', 'pointset.hpp', 'common.hpp'),
+                "sha1": "3fb4f06736c33f6c238f51be1cc2145f0fc5a353"}
+SOLVE_TRAFFIC = {"read_MiB": 41.51, "write_MiB": 34.56,
+                 "sources": ('transform.hip', 'realfft.hip', 'passkit.hpp', 'transform.hpp', 'common.hpp'),
+                 "sha1": "e3a6a6e4abda23d2e908edb8ebfde957fe3b1e38"}
 
 
-def step_traffic_bytes():
+def traffic_bytes(rec):
     import hashlib
 
-    if STEP_TRAFFIC["sha1"] is None:
+    if rec["sha1"] is None:
         return None
     h = hashlib.sha1()
-    for f in STEP_TRAFFIC["sources"]:
+    for f in rec["sources"]:
         with open(os.path.join(ROOT, "paper_2502_14256_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest() != STEP_TRAFFIC["sha1"]:
+    if h.hexdigest() != rec["sha1"]:
         return None
-    return int((STEP_TRAFFIC["read_MiB"] + STEP_TRAFFIC["write_MiB"]) * 2**20)
+    return int((rec["read_MiB"] + rec["write_MiB"]) * 2**20)
 
 
 def parse():
@@ -274,12 +278,12 @@ def main():
                 "achieved": round(alg["solve"] / (t_solve * 1e-3) / 1e9, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(alg["solve"] / (t_solve * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                "traffic": None}
+                "traffic": traffic_bytes(SOLVE_TRAFFIC)}
     roof_points = {"kernel": "k_points_kcol_lattice (points + first column; the step's longest "
                              "single kernel, not the solve)", "bound": "hbm",
                    "achieved": op_rows["points_column"]["GB_s"], "peak": HBM_PEAK_GBS,
                    "unit": "GB/s", "frac": op_rows["points_column"]["hbm_frac"],
-                   "traffic": step_traffic_bytes()}
+                   "traffic": traffic_bytes(STEP_TRAFFIC)}
     ms_per_step = total_ms / K
     solves_per_s = R * K / (total_ms * 1e-3)
 
