@@ -357,6 +357,7 @@ def main():
     out["cubature"] = cubature_bench(K, lam, y[:, 0, :], w)
     out["rqmc"] = rqmc_bench(K)
     out["update_double"] = update_bench(K)
+    out["structure_free"] = structure_free_bench(K)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"], c_oracle = cpu_baseline(w, y_host)
@@ -706,6 +707,62 @@ def rqmc_bench(K):
     timed("net_lms_m20_d50_R16", ldk.PointSet("dnet", R, d, m, dev_u64(wn["gen"]),
                                               dev_u64(wn["lms"]), dev_u64(wn["shift"])), 2**m)
     return res
+
+
+def structure_free_bench(K):
+    """The point sets without fast-transform structure (they feed QMC means):
+    Halton and Faure (b = 53) with LMS and digit permutations, and a base-2
+    net under nested uniform scrambling, d = 52 and R = 16 as in the paper's
+    listings, at n = 2^16: coordinate generation and the RQMC corner-peak
+    estimate over the generated points, device time per launch (graph
+    replays)."""
+    import numpy as np
+    import torch
+
+    import paper_2502_14256_amd as ldk
+    import workloads as W
+
+    R, d, m = 16, 52, 16
+    n = 2**m
+    coef = torch.from_numpy(W.corner_peak_coefficients(d)).cuda()
+    out = {}
+    for name, kind, base in (("halton_lms_dp", "halton", 0), ("faure53_lms_dp", "faure", 53),
+                             ("net_nus", "nus", 0)):
+        if kind == "nus":
+            t = W.small_net(31, m, d, 1)
+            ps = ldk.BPointSet("nus", R, d, m=m,
+                               gen=torch.from_numpy(t["gen"].view(np.int64).copy()).cuda(),
+                               seed=torch.from_numpy(W.nus_seeds(31, R, d).view(np.int64)).cuda())
+        else:
+            inp = W.bpoint_inputs(31, kind, R, d, base=base)
+            ps = ldk.BPointSet(kind, R, d, base=base, flags=ldk.BR_LMS | ldk.BR_DP,
+                               **{k: torch.from_numpy(v).cuda() for k, v in inp.items()})
+        x = torch.empty((R, n, d), dtype=torch.float64, device="cuda")
+        ws = torch.empty(max(ldk.lib().ldk_bpoints_workspace_bytes(C_ref(ps)), 256),
+                         dtype=torch.uint8, device="cuda")
+        ms_gen = time_graph(lambda: ldk.gen_bpoints(ps, 0, n, out=x, ws=ws), K)
+        mu_r = torch.empty(R, dtype=torch.float64, device="cuda")
+        st = torch.empty(3, dtype=torch.float64, device="cuda")
+        wsr = torch.empty(ldk.lib().ldk_rqmc_points_workspace_bytes(R, n), dtype=torch.uint8,
+                          device="cuda")
+        ms_rq = time_graph(lambda: ldk.rqmc_points(x, "corner_peak", coef, mu_r=mu_r, stats=st,
+                                                   ws=wsr), K)
+        stats = st.cpu().numpy()
+        out[name] = {"gen_ms": round(ms_gen, 5), "coords_per_s": round(R * n * d / (ms_gen * 1e-3), 1),
+                     "gen_GB_s": round(8 * R * n * d / (ms_gen * 1e-3) / 1e9, 1),
+                     "rqmc_ms": round(ms_rq, 5),
+                     "rqmc_GB_s": round(8 * R * n * d / (ms_rq * 1e-3) / 1e9, 1),
+                     "mean": float(stats[0]), "half_width_99": float(stats[2])}
+        del x
+    out["workload"] = (f"R={R} randomizations, d={d}, n=2^{m} points each; corner-peak "
+                       "integrand of the RQMC example over the generated coordinates")
+    return out
+
+
+def C_ref(ps):
+    import ctypes as C
+
+    return C.byref(ps._c())
 
 
 def update_bench(K):

@@ -546,6 +546,73 @@ int ldk_rqmc(const ldk_pointset *ps, int64_t n, int integrand, const double *coe
              double t, double *mu_r, double *stats, void *ws, ldk_stream stream);
 size_t ldk_rqmc_workspace_bytes(const ldk_pointset *ps, int64_t n);
 
+/* Point sets without the fast-transform structure; they feed QMC means only
+ * (the RQMC estimate over given coordinates, ldk_rqmc_points).
+ *
+ *  kind LDK_HALTON (Sec. 4.4): dimension j (from 0) has the (j+1)-th prime
+ *        b_j as its base and the identity generating matrix: the radical
+ *        inverse of i; 1 <= d <= 54 (bases below 256).
+ *  kind LDK_FAURE (Sec. 4.3, a digital sequence in prime base b): one
+ *        prime base b with d <= b <= 251; dimension j uses C = P^j mod b, P
+ *        the upper-triangular Pascal matrix (entries binom(k, t) j^(k-t)).
+ *     Digits: the base-b digits a_k of i give z_t = sum_k C[t][k] a_k mod b
+ *     (digit t weighs b^-(t+1)); then, each when its flag is set and in this
+ *     order: LDK_BR_LMS z <- S z mod b (S lower triangular, nonzero
+ *     diagonal), LDK_BR_DP z_t <- pi_t(z_t) (a permutation of the digit
+ *     values per position), LDK_BR_DS z_t <- z_t + delta_t mod b.  T digits
+ *     are kept, the largest T with b^T <= 2^53, and the coordinate is the
+ *     integer sum_t z_t b^(T-1-t) divided by b^T, rounded once to FP64.
+ *     Scrambles (device, uint8, for every replication r and dimension j; only
+ *     the first T rows and the first b values of each row are read):
+ *       lms   [R][d][53][53]  S[t][k] at [r][j][t][k];
+ *       perm  [R][d][53][256] pi_t(v) at [r][j][t][v];
+ *       shift [R][d][53]      delta_t at [r][j][t].
+ *  kind LDK_DNET_NUS (Sec. 4.3, nested uniform scrambling of a base-2 net):
+ *        gen = device uint64 [d][m] generating columns (as for LDK_DNET_B2,
+ *        digit t at bit 64 - t), 0 <= m <= 32; seed = device uint64 [R][d].
+ *        Point word z = C_j i, then digit t = 1..64 is flipped when the top
+ *        bit of mix64(key XOR seed_rj) is set, key = 2^(t-1) + the digits
+ *        above t as an integer; mix64 is the SplitMix64 finaliser
+ *        (Steele, Lea and Flood 2014; Stafford's Mix13 constants).  The
+ *        coordinate is the word times 2^-64 rounded to the nearest double.
+ *        flags, base, lms, perm and shift are ignored.
+ * R <= 65535 replications; indices below 2^32. */
+typedef enum { LDK_HALTON = 2, LDK_FAURE = 3, LDK_DNET_NUS = 4 } ldk_bkind;
+#define LDK_BDIGITS_MAX 53
+#define LDK_BR_LMS 1
+#define LDK_BR_DP 2
+#define LDK_BR_DS 4
+typedef struct {
+    int32_t kind;
+    int32_t R;
+    int32_t d;
+    int32_t base;  /* LDK_FAURE */
+    int32_t flags; /* LDK_HALTON, LDK_FAURE: OR of LDK_BR_* */
+    int32_t m;     /* LDK_DNET_NUS */
+    const uint8_t *lms;
+    const uint8_t *perm;
+    const uint8_t *shift;
+    const uint64_t *gen;  /* LDK_DNET_NUS */
+    const uint64_t *seed; /* LDK_DNET_NUS */
+} ldk_bpointset;
+
+/* Coordinates of points i = n_min .. n_max-1 of every replication: out =
+ * device double [R][n_max - n_min][d], d fastest.  ws:
+ * ldk_bpoints_workspace_bytes(ps) bytes (the Faure matrices, formed on every
+ * call; 0 for the other kinds).  LDK_EINVAL for an invalid set or a missing
+ * scramble its flags ask for; LDK_ENOTSUP for n_max > 2^32. */
+int ldk_gen_bpoints(const ldk_bpointset *ps, int64_t n_min, int64_t n_max, double *out, void *ws,
+                    ldk_stream stream);
+size_t ldk_bpoints_workspace_bytes(const ldk_bpointset *ps);
+
+/* eq. RQMC over given points: x = device double [R][n][d] (any of the point
+ * sets above, or any coordinates), 1 <= d <= 128, with the integrands,
+ * outputs and interval of ldk_rqmc.  ws: ldk_rqmc_points_workspace_bytes(R,
+ * n) bytes. */
+int ldk_rqmc_points(int R, int64_t n, int d, const double *x, int integrand, const double *coef,
+                    double u, double t, double *mu_r, double *stats, void *ws, ldk_stream stream);
+size_t ldk_rqmc_points_workspace_bytes(int R, int64_t n);
+
 /* Orthonormal Walsh-Hadamard transform of B FP32 rows of n = 2^m (Sec. 5.3,
  * the recursion of H_m) on the matrix cores: each radix-16 stage is two
  * accumulating FP16 matrix instructions H_16 X_lo + H_16 X_hi with FP32

@@ -46,6 +46,16 @@ kernel cubature        Sec. 3.2 (worst-case error, optimal
                        fine grids (kappa_i = zeta); stationarity of the
                        optimal weights; exact posterior mean on kernel
                        sections; eigenvalue forms equal the dense ones
+Halton / Faure points  Secs. 4.3 (prime base) and 4.4; exact-rational radical
+                       inverse; the (0, m, s)-net property of Faure (every
+                       elementary interval of volume b^-m holds one point)
+                       by brute force, kept by LMS; Faure's first dimension
+                       is van der Corput; DS and DP undone by their
+                       inverses give the unrandomized digits
+NUS (base 2)           Sec. 4.3; digit t depends only on the digits before
+                       it (points sharing a prefix share the scrambled
+                       prefix), every level is a bijection, and the net's
+                       stratification survives; the flips are balanced
 RQMC estimate + CI     eq. (RQMC); Genz corner peak against its exact
                        integral (a one-dimensional Laplace-transform
                        quadrature, itself checked against inclusion-
@@ -66,7 +76,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liborc.so")
-_SRC = ["orc_points.c", "orc_kernels.c", "orc_algebra.c", "orc_mll.c", "orc_mll_ld.c"]
+_SRC = ["orc_points.c", "orc_kernels.c", "orc_algebra.c", "orc_mll.c", "orc_mll_ld.c",
+        "orc_bpoints.c"]
 
 LATTICE, DNET = 0, 1
 NATURAL, LINEAR, GRAY = 0, 1, 2
@@ -137,6 +148,9 @@ def _load(path: str):
             "orc_mll_adjoint": [i32, i32, i32, P, P],
             "orc_kernel_grad": [i32, i32, i32, i64, P, P, P, P, f64, P, P],
             "orc_mll_grad_ld": [i32, i32, i32, i32, P, P, P, P, f64, f64, P, P, P],
+            "orc_bpoints": [i32, i32, i32, i32, i32, i64, i64, P, P, P, P],
+            "orc_nus_points": [i32, i32, i32, i64, i64, P, P, P],
+            "orc_bdigits": [i32], "orc_nth_prime": [i32],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -148,6 +162,8 @@ def _load(path: str):
         L.orc_dsi_factor.restype = f64
         L.orc_gray.argtypes = [C.c_uint64]
         L.orc_gray.restype = C.c_uint64
+        L.orc_mix64.argtypes = [C.c_uint64]
+        L.orc_mix64.restype = C.c_uint64
         L.orc_threads.argtypes = []
         L.orc_threads.restype = i32
         L.orc_set_threads.argtypes = [i32]
@@ -634,3 +650,49 @@ def rqmc(y, tau: float = 0.01) -> dict:
     sigma = math.sqrt(((mu_r - mu) ** 2).sum() / (R - 1)) if R > 1 else float("nan")
     t = float(stats.t.ppf(1.0 - tau / 2.0, R - 1)) if R > 1 else float("nan")
     return dict(mu_r=mu_r, mean=mu, std=sigma, t=t, half=t * sigma / math.sqrt(R))
+
+
+# ---------------------------------------------------------------------------
+# Point sets without FWHT structure (orc_bpoints.c)
+# ---------------------------------------------------------------------------
+BR_LMS, BR_DP, BR_DS = 1, 2, 4
+BT_MAX = 53
+_BKIND = {"halton": 2, "faure": 3}
+
+
+def bdigits(b: int) -> int:
+    """Digits kept in base b: the largest T with b^T <= 2^53."""
+    return int(lib().orc_bdigits(int(b)))
+
+
+def nth_prime(j: int) -> int:
+    return int(lib().orc_nth_prime(int(j)))
+
+
+def bpoints(kind: str, R: int, d: int, n_min: int, n_max: int, base: int = 0, flags: int = 0,
+            lms=None, perm=None, shift=None) -> np.ndarray:
+    """Coordinates [R][n][d] (FP64) of a Halton or Faure point set with the
+    randomizations in `flags` (BR_LMS, then BR_DP, then BR_DS)."""
+    cnt = n_max - n_min
+    out = np.empty((R, cnt, d), np.float64)
+    lms_ = None if lms is None else _c(lms, np.uint8)
+    perm_ = None if perm is None else _c(perm, np.uint8)
+    shift_ = None if shift is None else _c(shift, np.uint8)
+    _check(lib().orc_bpoints(_BKIND[kind], R, d, int(base), int(flags), n_min, n_max,
+                             _p(lms_), _p(perm_), _p(shift_), _p(out)), "bpoints")
+    return out
+
+
+def mix64(z: int) -> int:
+    return int(lib().orc_mix64(C.c_uint64(int(z) & (2**64 - 1))))
+
+
+def nus_points(C_, seed, m: int, n_min: int, n_max: int) -> np.ndarray:
+    """Point words [R][n][d] of a base-2 net with generating columns C_ [d][m]
+    under nested uniform scrambling with seeds [R][d]."""
+    C_ = _c(C_, np.uint64)
+    seed = _c(seed, np.uint64)
+    R, d = seed.shape
+    out = np.empty((R, n_max - n_min, d), np.uint64)
+    _check(lib().orc_nus_points(R, d, m, n_min, n_max, _p(C_), _p(seed), _p(out)), "nus_points")
+    return out

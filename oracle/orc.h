@@ -38,6 +38,23 @@ int orc_dnet_points(int R, int d, int m_max, int order, int64_t n_min, int64_t n
 int orc_lms(int d, int m, const uint64_t *C, const uint64_t *S, uint64_t *Ct);
 uint64_t orc_gray(uint64_t i);
 
+/* Point sets without FWHT structure (orc_bpoints.c): digital sequences in a
+ * prime base (Faure: one base b, C_j = Pascal^(j-1); Halton, Sec. 4.4: the
+ * j-th prime, C_j = I) with optional LMS, digit permutations and digital
+ * shift, as FP64 coordinates [R][n][d]; and nested uniform scrambling of a
+ * base-2 net (Sec. 4.3) as point words [R][n][d].
+ * lms: uint8 [R][d][53][53] (row t, column k); perm: uint8 [R][d][53][256];
+ * shift: uint8 [R][d][53]; seed: uint64 [R][d]. */
+enum { ORC_HALTON = 2, ORC_FAURE = 3 };
+enum { ORC_BR_LMS = 1, ORC_BR_DP = 2, ORC_BR_DS = 4 };
+int orc_bdigits(int b);
+int orc_nth_prime(int j);
+int orc_bpoints(int kind, int R, int d, int base, int flags, int64_t n_min, int64_t n_max,
+                const uint8_t *lms, const uint8_t *perm, const uint8_t *shift, double *out);
+uint64_t orc_mix64(uint64_t z);
+int orc_nus_points(int R, int d, int m, int64_t n_min, int64_t n_max, const uint64_t *C,
+                   const uint64_t *seed, uint64_t *out);
+
 /* Sec. 5.2 (Bernoulli SI factor) and Sec. 5.3 / Theorem 1 (DSI factor) */
 double orc_si_factor(int alpha, uint64_t delta);
 double orc_dsi_factor(int alpha, uint64_t delta);

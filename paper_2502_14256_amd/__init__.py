@@ -40,7 +40,8 @@ EXPORTS = [
     "ldk_logdet_checked", "ldk_normal_quantile", "ldk_student_t_quantile", "ldk_solve_noalloc",
     "ldk_init_tuned", "ldk_plan_info", "ldk_plan_create", "ldk_plan_arena_bytes",
     "ldk_plan_instance_offset", "ldk_plan_bind", "ldk_batch_launch", "ldk_batch_capture",
-    "ldk_plan_stats", "ldk_plan_destroy",
+    "ldk_plan_stats", "ldk_plan_destroy", "ldk_gen_bpoints", "ldk_bpoints_workspace_bytes",
+    "ldk_rqmc_points", "ldk_rqmc_points_workspace_bytes",
 ]
 
 
@@ -52,6 +53,12 @@ class _Pointset(C.Structure):
     _fields_ = [("kind", C.c_int32), ("order", C.c_int32), ("R", C.c_int32), ("d", C.c_int32),
                 ("m_max", C.c_int32), ("flags", C.c_int32), ("gen", C.c_void_p),
                 ("lms", C.c_void_p), ("shift", C.c_void_p)]
+
+
+class _BPointset(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("R", C.c_int32), ("d", C.c_int32), ("base", C.c_int32),
+                ("flags", C.c_int32), ("m", C.c_int32), ("lms", C.c_void_p), ("perm", C.c_void_p),
+                ("shift", C.c_void_p), ("gen", C.c_void_p), ("seed", C.c_void_p)]
 
 
 class _Kernel(C.Structure):
@@ -104,6 +111,10 @@ def lib():
             "ldk_solve_noalloc": ([i32, i32, i32, i32, i32, P, f64, P, P, P], i32),
             "ldk_init_tuned": ([C.c_char_p], i32),
             "ldk_plan_info": ([i32, i32, i32, i64, P, P, P, P], i32),
+            "ldk_gen_bpoints": ([P, i64, i64, P, P, P], i32),
+            "ldk_bpoints_workspace_bytes": ([P], C.c_size_t),
+            "ldk_rqmc_points": ([i32, i64, i32, P, i32, P, f64, f64, P, P, P, P], i32),
+            "ldk_rqmc_points_workspace_bytes": ([i32, i64], C.c_size_t),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -665,6 +676,85 @@ def rqmc(ps: PointSet, n: int, integrand, coef: torch.Tensor, u: float = 0.0, ta
     ws = _need_ws(ws, lib().ldk_rqmc_workspace_bytes(C.byref(cps), int(n)), dev)
     _check(lib().ldk_rqmc(C.byref(cps), int(n), f, _ptr(coef), float(u), t, _ptr(mu_r),
                           _ptr(stats), _ptr(ws), _stream()), "ldk_rqmc")
+    return mu_r, stats
+
+
+HALTON, FAURE, DNET_NUS = 2, 3, 4
+BR_LMS, BR_DP, BR_DS = 1, 2, 4
+BDIGITS_MAX = 53
+
+
+@dataclass
+class BPointSet:
+    """A point set without fast-transform structure (ldk_gen_bpoints):
+    kind "halton" (the j-th prime per dimension), "faure" (one prime base)
+    or "nus" (nested uniform scrambling of a base-2 net with generating
+    columns gen [d][m] and seeds [R][d]).  flags: OR of BR_LMS, BR_DP, BR_DS
+    (Halton / Faure) with the uint8 scrambles lms [R][d][53][53], perm
+    [R][d][53][256] and shift [R][d][53] on the device."""
+
+    kind: str
+    R: int
+    d: int
+    base: int = 0
+    flags: int = 0
+    lms: torch.Tensor | None = None
+    perm: torch.Tensor | None = None
+    shift: torch.Tensor | None = None
+    gen: torch.Tensor | None = None
+    seed: torch.Tensor | None = None
+    m: int = 0
+
+    def _c(self) -> _BPointset:
+        kd = {"halton": HALTON, "faure": FAURE, "nus": DNET_NUS}[self.kind]
+        R, d = self.R, self.d
+        shapes = {"lms": ((R, d, BDIGITS_MAX, BDIGITS_MAX), torch.uint8),
+                  "perm": ((R, d, BDIGITS_MAX, 256), torch.uint8),
+                  "shift": ((R, d, BDIGITS_MAX), torch.uint8),
+                  "gen": ((d, self.m), torch.int64), "seed": ((R, d), torch.int64)}
+        for name, (shape, dt) in shapes.items():
+            t = getattr(self, name)
+            if t is not None:
+                _need(t, name)
+                if t.dtype != dt or tuple(t.shape) != shape:
+                    raise LdkError(f"{name} must be {dt} of shape {shape}")
+        return _BPointset(kd, R, d, int(self.base), int(self.flags), int(self.m), _ptr(self.lms),
+                          _ptr(self.perm), _ptr(self.shift), _ptr(self.gen), _ptr(self.seed))
+
+
+def gen_bpoints(ps: BPointSet, n_min: int, n_max: int, out=None, ws=None, device="cuda"):
+    """Coordinates [R][n_max - n_min][d] (FP64) of a BPointSet (ldk_gen_bpoints)."""
+    cps = ps._c()
+    shape = (ps.R, n_max - n_min, ps.d)
+    out = torch.empty(shape, dtype=torch.float64, device=device) if out is None else out
+    _need_out(out, "out", torch.float64, shape, out.device)
+    ws = _need_ws(ws, lib().ldk_bpoints_workspace_bytes(C.byref(cps)), out.device)
+    _check(lib().ldk_gen_bpoints(C.byref(cps), int(n_min), int(n_max), _ptr(out), _ptr(ws),
+                                 _stream()), "ldk_gen_bpoints")
+    return out
+
+
+def rqmc_points(x: torch.Tensor, integrand, coef: torch.Tensor, u: float = 0.0, tau: float = 0.01,
+                mu_r=None, stats=None, ws=None):
+    """RQMC estimate over given coordinates x [R][n][d] (ldk_rqmc_points):
+    (mu_r [R], stats [3]) as rqmc."""
+    f = {"corner_peak": GENZ_CORNER_PEAK, "oscillatory": GENZ_OSCILLATORY,
+         GENZ_CORNER_PEAK: GENZ_CORNER_PEAK, GENZ_OSCILLATORY: GENZ_OSCILLATORY}[integrand]
+    _need_f64(x, "x")
+    R, n, d = x.shape
+    dev = x.device
+    _need_f64(coef, "coef", (d,), dev)
+    if not 0.0 < tau < 1.0:
+        raise LdkError("tau must lie in (0, 1)")
+    t = student_t_quantile(1.0 - tau / 2.0, R - 1) if R > 1 else 0.0
+    mu_r = torch.empty(R, dtype=torch.float64, device=dev) if mu_r is None else mu_r
+    stats = torch.empty(len(RQMC_FIELDS), dtype=torch.float64, device=dev) if stats is None \
+        else stats
+    _need_out(mu_r, "mu_r", torch.float64, (R,), dev)
+    _need_out(stats, "stats", torch.float64, (len(RQMC_FIELDS),), dev)
+    ws = _need_ws(ws, lib().ldk_rqmc_points_workspace_bytes(R, n), dev)
+    _check(lib().ldk_rqmc_points(R, n, d, _ptr(x), f, _ptr(coef), float(u), t, _ptr(mu_r),
+                                 _ptr(stats), _ptr(ws), _stream()), "ldk_rqmc_points")
     return mu_r, stats
 
 

@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libldk.so")
 INCLUDE = os.path.join(HERE, "..", "include")
 SOURCES = ["core.hip", "points.hip", "kcol.hip", "kgrad.hip", "transform.hip", "realfft.hip",
            "algebra.hip", "mll.hip", "fwht_mfma.hip", "rqmc.hip", "checked.hip", "batch.hip",
-           "noalloc.hip"]
+           "noalloc.hip", "bpoints.hip"]
 HEADERS = ["common.hpp", "pointset.hpp", "transform.hpp", "passkit.hpp", "kfactor.hpp",
            "passbody.hpp", "batch.hpp"]
 

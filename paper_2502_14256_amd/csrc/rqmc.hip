@@ -240,6 +240,46 @@ __global__ __launch_bounds__(RQ_FINAL_THREADS) void k_rqmc_final(const double *_
     }
 }
 
+// Given points: one block per (tile of RQ_PTS_TILE points, replication).
+// The tile's coordinate rows are contiguous, so the block stages them in
+// chunks of RQ_PTS_CHUNK points through LDS with coalesced loads; then four
+// threads share a point (dimensions j = q, q + 4, ...), their partial sums
+// of c_j x_ij combine in a fixed order, and the first of them applies f.
+constexpr int RQ_PTS_CHUNK = KC_THREADS / 4;
+constexpr int RQ_PTS_TILE = 4 * RQ_PTS_CHUNK;
+constexpr int RQ_PTS_MAX_D = 128;  // LDS: RQ_PTS_CHUNK x d doubles
+
+template <int F>
+__global__ __launch_bounds__(KC_THREADS) void k_rqmc_pts(const double *__restrict__ x, int d,
+                                                         int64_t n, const double *__restrict__ coef,
+                                                         double phase, double *__restrict__ part)
+{
+    __shared__ double red[KC_THREADS / 64];
+    __shared__ double rows[RQ_PTS_CHUNK * RQ_PTS_MAX_D];
+    __shared__ double sc[RQ_PTS_MAX_D];
+    const int r = blockIdx.y, t = threadIdx.x;
+    const int p = t >> 2, q = t & 3;
+    for (int j = t; j < d; j += KC_THREADS) sc[j] = coef[j];
+    double acc = 0.0;
+    for (int c = 0; c < RQ_PTS_TILE / RQ_PTS_CHUNK; ++c) {
+        const int64_t first = (int64_t)blockIdx.x * RQ_PTS_TILE + (int64_t)c * RQ_PTS_CHUNK;
+        const int64_t cnt64 = n - first;
+        const int cnt = cnt64 < RQ_PTS_CHUNK ? (int)(cnt64 > 0 ? cnt64 : 0) : RQ_PTS_CHUNK;
+        __syncthreads();  // the previous chunk's reads are done
+        const double *src = x + ((size_t)r * n + first) * d;
+        for (int e = t; e < cnt * d; e += KC_THREADS) rows[e] = src[e];
+        __syncthreads();
+        double s = 0.0;
+        if (p < cnt)
+            for (int j = q; j < d; j += 4) s = fma(sc[j], rows[p * d + j], s);
+        s += __shfl_xor(s, 1, 64);
+        s += __shfl_xor(s, 2, 64);
+        if (q == 0 && p < cnt) acc += integrand<F>(s, d, phase);
+    }
+    const double tot = block_sum<KC_THREADS>(acc, red);
+    if (threadIdx.x == 0) part[(size_t)r * gridDim.x + blockIdx.x] = tot;
+}
+
 constexpr int RQ_IT_FULL = 8, RQ_IT_SMALL = 2;
 
 int64_t tiles_of(int64_t n, int it) { return (n + KC_THREADS * it - 1) / (KC_THREADS * it); }
@@ -347,6 +387,40 @@ extern "C" int ldk_rqmc(const ldk_pointset *ps, int64_t n, int integrand, const 
     LDK_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_rqmc_final, dim3(1), dim3(RQ_FINAL_THREADS), 0, s, (const double *)part,
                        (int)tiles, a.ps.R, (double)n, t, mu_r, stats);
+    LDK_LAUNCH_CHECK();
+    return LDK_OK;
+}
+
+extern "C" size_t ldk_rqmc_points_workspace_bytes(int R, int64_t n)
+{
+    if (R < 1 || n < 1) return 0;
+    return (size_t)R * (size_t)((n + RQ_PTS_TILE - 1) / RQ_PTS_TILE) * sizeof(double);
+}
+
+extern "C" int ldk_rqmc_points(int R, int64_t n, int d, const double *x, int integrand,
+                               const double *coef, double u, double t, double *mu_r, double *stats,
+                               void *ws, ldk_stream stream)
+{
+    if (R < 1 || R > 65535 || n < 1 || d < 1 || d > RQ_PTS_MAX_D || !x || !coef || !mu_r ||
+        !stats || !ws)
+        return LDK_EINVAL;
+    if (integrand != LDK_GENZ_CORNER_PEAK && integrand != LDK_GENZ_OSCILLATORY) return LDK_EINVAL;
+    if (!(u >= -1.0e6 && u <= 1.0e6) || !(t >= 0.0 && t <= 1.0e300)) return LDK_EINVAL;
+    const int64_t tiles = (n + RQ_PTS_TILE - 1) / RQ_PTS_TILE;
+    if (tiles > 0x7fffffff || (uint64_t)tiles * KC_THREADS > 0xffffffffull) return LDK_ENOTSUP;
+    hipStream_t s = as_stream(stream);
+    double *part = static_cast<double *>(ws);
+    const dim3 grid((unsigned)tiles, (unsigned)R);
+    const double phase = 6.283185307179586476925286766559 * u;
+    if (integrand == LDK_GENZ_CORNER_PEAK)
+        hipLaunchKernelGGL(k_rqmc_pts<LDK_GENZ_CORNER_PEAK>, grid, dim3(KC_THREADS), 0, s, x, d, n,
+                           coef, phase, part);
+    else
+        hipLaunchKernelGGL(k_rqmc_pts<LDK_GENZ_OSCILLATORY>, grid, dim3(KC_THREADS), 0, s, x, d, n,
+                           coef, phase, part);
+    LDK_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_rqmc_final, dim3(1), dim3(RQ_FINAL_THREADS), 0, s, (const double *)part,
+                       (int)tiles, R, (double)n, t, mu_r, stats);
     LDK_LAUNCH_CHECK();
     return LDK_OK;
 }

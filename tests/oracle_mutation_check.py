@@ -55,6 +55,13 @@ muts = [
  ("oracle/__init__.py", "t = float(stats.t.ppf(1.0 - tau / 2.0, R - 1))", "t = float(stats.t.ppf(1.0 - tau, R - 1))"),
  ("oracle/__init__.py", "return np.ldexp(np.asarray(words, dtype=np.uint64).astype(np.float64), -64)", "return np.ldexp(np.asarray(words, dtype=np.uint64).astype(np.float64), -63)"),
  ("oracle/__init__.py", "return np.cos(2.0 * np.pi * u + x @ np.asarray(c, np.float64))", "return np.cos(np.pi * u + x @ np.asarray(c, np.float64))"),
+ ("oracle/orc_bpoints.c", "for (int k = 1; k < j; ++k) {", "for (int k = 0; k < j; ++k) {"),
+ ("oracle/orc_bpoints.c", "for (int t = 0; t < T; ++t) v = v * (uint64_t)b + (uint64_t)z[t];", "for (int t = 0; t < T; ++t) v = v * (uint64_t)b + (uint64_t)z[T - 1 - t];"),
+ ("oracle/orc_bpoints.c", "s += (long)S[t * BT_MAX + k] * z[k];", "s += (long)S[k * BT_MAX + t] * z[k];"),
+ ("oracle/orc_bpoints.c", "z[t] = (z[t] + dl[t]) % b;", "z[t] = (z[t] + b - dl[t]) % b;"),
+ ("oracle/orc_bpoints.c", "const uint64_t prefix = t == 1 ? 0 : z >> (65 - t);", "const uint64_t prefix = t == 1 ? 0 : z >> (64 - t);"),
+ ("oracle/orc_bpoints.c", "const int b = kind == ORC_HALTON ? orc_nth_prime(j + 1) : base;", "const int b = kind == ORC_HALTON ? orc_nth_prime(j + 2) : base;"),
+ ("oracle/orc_bpoints.c", "P[r * T + c] = (r == 0 || r == c) ? 1 % b : (P[(r - 1) * T + (c - 1)] + P[r * T + (c - 1)]) % b;", "P[r * T + c] = (r == 0 || r == c) ? 1 % b : (P[(r - 1) * T + (c - 1)] + 2 * P[r * T + (c - 1)]) % b;"),
 ]
 
 res = []

@@ -237,3 +237,55 @@ def corner_peak_coefficients(d: int) -> np.ndarray:
     c_j proportional to 1/j^2, scaled to sum to 1/4."""
     ct = 1.0 / np.arange(1, d + 1, dtype=np.float64) ** 2
     return 0.25 * ct / ct.sum()
+
+
+# ---------------------------------------------------------------------------
+# Point sets in prime bases (Halton, Faure) and nested uniform scrambling
+# ---------------------------------------------------------------------------
+B_TMAX = 53  # digits per coordinate in the scramble layouts (2^53 >= b^T)
+
+
+def _primes(count: int) -> list:
+    """The first `count` primes (to size the random digits of each base)."""
+    out, c = [], 2
+    while len(out) < count:
+        if all(c % p for p in out if p * p <= c):
+            out.append(c)
+        c += 1
+    return out
+
+
+def bpoint_inputs(seed: int, kind: str, R: int, d: int, base: int = 0) -> dict:
+    """Random scrambles for a Halton (base of dimension j = the j-th prime)
+    or Faure (one prime `base`) point set, drawn for all 53 digit rows of
+    every (replication, dimension) in the order LMS, permutations, shifts:
+
+    * lms ``uint8[R][d][53][53]``: lower triangular, diagonal uniform in
+      {1..b-1}, below it uniform in {0..b-1} (Matousek's scrambling, Sec. 4.3);
+    * perm ``uint8[R][d][53][256]``: row t holds a uniform random permutation
+      of {0..b-1} in its first b entries (digit permutations, Sec. 4.3);
+    * shift ``uint8[R][d][53]``: uniform digits in {0..b-1}."""
+    rng = np.random.default_rng(seed)
+    bases = _primes(d) if kind == "halton" else [base] * d
+    lms = np.zeros((R, d, B_TMAX, B_TMAX), np.uint8)
+    perm = np.zeros((R, d, B_TMAX, 256), np.uint8)
+    shift = np.zeros((R, d, B_TMAX), np.uint8)
+    for r in range(R):
+        for j in range(d):
+            b = bases[j]
+            low = rng.integers(0, b, size=(B_TMAX, B_TMAX))
+            lms[r, j] = np.tril(low, -1) + np.diag(rng.integers(1, b, size=B_TMAX))
+    for r in range(R):
+        for j in range(d):
+            b = bases[j]
+            for t in range(B_TMAX):
+                perm[r, j, t, :b] = rng.permutation(b)
+    for r in range(R):
+        for j in range(d):
+            shift[r, j] = rng.integers(0, bases[j], size=B_TMAX)
+    return dict(lms=lms, perm=perm, shift=shift)
+
+
+def nus_seeds(seed: int, R: int, d: int) -> np.ndarray:
+    """Seeds [R][d] of the nested uniform scrambling's counter-based flips."""
+    return _u64(np.random.default_rng(seed), (R, d))
