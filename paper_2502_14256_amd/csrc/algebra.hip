@@ -23,6 +23,7 @@ bool valid_m(int m) { return m >= 0 && m <= TW_MAX_LOG; }
 
 // Workspace for the complex intermediate of the lattice transforms.
 size_t cplx_rows_bytes(int64_t rows, int m, int dtype) { return (size_t)rows * ((size_t)2 << m) * esize(dtype); }
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // The plan over mp index bits of a transform of length 2^m_key, with the
 // parameters plan_params gives (kind, dtype, m_key, rows).
@@ -348,6 +349,14 @@ int real_apply(int dtype, int mode, int m, int64_t rows, int nrhs, const double 
         b.g = pl.pass[pl.P - 1];
         b.global_tw = 1;
         b.scale = 1.0 / (double)N;
+        if (nrhs >= 2) {
+            // every eigenvalue row serves nrhs rows: form its filter once
+            void *coef = static_cast<unsigned char *>(ws) + align256(cplx_rows_bytes(rows, mp, dtype));
+            const int st = launch_filter_coef(dtype, mode, mp, rows / nrhs, lam, sigma2, b.scale,
+                                              coef, s);
+            if (st) return st;
+            b.coef = coef;
+        }
         const int st = launch_real_top(dtype, mode, b, nullptr, s);
         if (st) return st;
     }
@@ -371,7 +380,6 @@ int real_apply(int dtype, int mode, int m, int64_t rows, int nrhs, const double 
 // log-det share the tile passes of the half-length packed transforms.
 bool fit_fused(int kind, int m, int dtype) { return kind == LDK_LATTICE && m >= 2 && dtype == LDK_F64; }
 
-size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Top-pass geometry of the fused fit: the plan's top pass, narrowed until
 // the column and rhs tiles fit a workgroup's LDS together, with four
@@ -412,8 +420,13 @@ size_t ws_bytes(int op, int kind, int64_t B, int m, int dtype)
     }
     case LDK_OP_SOLVE:
     case LDK_OP_MATVEC:
+        // real lattice rows: the complex intermediate, then room for the
+        // filter coefficients of up to B / 2 eigenvalue rows (formed when
+        // every eigenvalue row serves two or more right-hand sides)
         if (real_path(kind, m))
-            return any_multipass(kind, dtype, m, m - 1) ? cplx_rows_bytes(B, m - 1, dtype) : 0;
+            return any_multipass(kind, dtype, m, m - 1)
+                       ? align256(cplx_rows_bytes(B, m - 1, dtype)) + cplx_rows_bytes(B / 2, m - 1, dtype)
+                       : 0;
         return (lat && any_multipass(kind, dtype, m, m)) ? cplx_rows_bytes(B, m, dtype) : 0;
     case LDK_OP_LOGDET: {
         const int64_t n = (int64_t)1 << m;
@@ -439,7 +452,9 @@ size_t fit_ws_bytes(int kind, int64_t B, int m, int dtype)
             const PassGeom top = fit_top_geom(pl);  // at least as many tiles as the plan's top
             const size_t cb = (size_t)1 << (top.b0 - top.logW);
             const size_t rows = pl.P > 1 ? (size_t)B * ((size_t)1 << (m - 1)) * 16 : 0;
-            const size_t f = align256((size_t)B * cb * sizeof(double)) + rows;
+            // + the solve filter's coefficients (nrhs >= 2: at most B / 3 rows)
+            const size_t coef = pl.P > 1 ? align256(cplx_rows_bytes(B / 2, m - 1, LDK_F64)) : 0;
+            const size_t f = align256((size_t)B * cb * sizeof(double)) + align256(rows) + coef;
             if (f > w) w = f;
         }
     }
@@ -672,6 +687,14 @@ int ldk_fit(int kind, int R, int nrhs, int m, int dtype, const void *k1, double 
     } else {
         st = launch_real_top(LDK_F64, PM_FWD, aK, lam, s, false, logdet ? partial : nullptr);
         if (st) return st;
+        if (!single && nrhs >= 2) {
+            // the filter once per eigenvalue row, as ldk_solve forms it
+            void *coef = w8 + align256((size_t)B * cb_count * sizeof(double)) +
+                         align256((size_t)R * N * 16 + (size_t)R * nrhs * N * 16);
+            st = launch_filter_coef(LDK_F64, PM_SOLVE, mp, R, lam, sigma2, aY.scale, coef, s);
+            if (st) return st;
+            aY.coef = coef;
+        }
         st = launch_real_top(LDK_F64, PM_SOLVE, aY, nullptr, s);
         if (st) return st;
     }

@@ -47,10 +47,51 @@ using namespace kit;
 
 namespace {
 
+// The real solve's (or matvec's) filter for frequency k < N of one
+// eigenvalue row lam [2N]: s1 = (f(lambda_k) + f(lambda_{n-k}))/2 and s2 the
+// same at k + N (f = scale / (lambda + sigma2) or scale lambda), combined
+// with W_n^k into Z'_k = p Z_k + i q conj(Z_{N-k}), returned as (p, q).
+template <typename T, int MODE>
+__device__ __forceinline__ T filter_pq(const double *lam, int64_t k, int mp, double sigma2,
+                                       double scale)
+{
+    using R = typename real_of<T>::type;
+    const int64_t N = (int64_t)1 << mp, n = 2 * N;
+    const T wk = tw_any<R>((uint64_t)k, mp + 1);
+    const double la = lam[k], lb = lam[(n - k) & (n - 1)];
+    const double lc = lam[k + N], ld = lam[(N - k) & (n - 1)];
+    double s1, s2;
+    if constexpr (MODE == PM_SOLVE) {
+        // (1/(la+s2) + 1/(lb+s2)) / 2 with one division
+        const double pa = la + sigma2, pb = lb + sigma2;
+        const double pc = lc + sigma2, pd = ld + sigma2;
+        s1 = 0.5 * scale * (pa + pb) / (pa * pb);
+        s2 = 0.5 * scale * (pc + pd) / (pc * pd);
+    } else {
+        s1 = 0.5 * scale * (la + lb);
+        s2 = 0.5 * scale * (lc + ld);
+    }
+    const R hs = (R)(0.5 * (s1 + s2)), hd = (R)(0.5 * (s1 - s2));
+    // one explicit fused multiply-add: the same bits in every kernel
+    return T{fma(hd, wk.im, hs), hd * wk.re};
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_filter_coef(const double *__restrict__ lam, int mp,
+                                                     int64_t count, double sigma2, double scale,
+                                                     T *__restrict__ coef)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= count) return;
+    const int64_t N = (int64_t)1 << mp;
+    const int64_t r = idx >> mp, k = idx & (N - 1);
+    coef[idx] = filter_pq<T, MODE>(lam + r * 2 * N, k, mp, sigma2, scale);
+}
+
 // One tile (row, column block cb) of the top pass.  ld_part (PM_FWD only,
 // may be NULL): receives this tile's sum of log(lambda + sigma2) over its 2 S
 // eigenvalues at ld_part[row * cb_count + cb] (NaN if some lambda + s2 <= 0).
-template <typename T, int LOGE, int MODE, int LD, int ST, bool SRC_F32>
+template <typename T, int LOGE, int MODE, int LD, int ST, bool SRC_F32, bool CF = false>
 __device__ __forceinline__ void real_top_body(const PassArgs &a, double *lam_out, int64_t row,
                                               int64_t cb, double *ld_part)
 {
@@ -98,27 +139,27 @@ __device__ __forceinline__ void real_top_body(const PassArgs &a, double *lam_out
     if (b0 > 0) ptw = pass_tw_fetch<R, LOGE>(t, (uint64_t)col_of(t & (W - 1)), logW, A, b0);
     // Per-element twiddle W_n^k and spectral factors, fetched after the
     // data loads are issued and before the transform, so that their latency
-    // overlaps the data loads and the groups.
+    // overlaps the data loads and the groups.  The solve and matvec form
+    // them after the forward transform instead, next to their one use: held
+    // across the transform (with the eigenvalue loads in flight) they took
+    // every register and spilled.
+    constexpr bool LATE = MODE == PM_SOLVE || MODE == PM_MATVEC;
     T wkv[E];
     double f1[E], f2[E];
+    // precomputed filter coefficients (p, q), when given: one pair per
+    // element, read next to their use (held across the transform they would
+    // cost 4 E registers)
+    const T *crow = CF ? static_cast<const T *>(a.coef) + (row / a.nrhs) * N : nullptr;
 #pragma unroll
-    for (int i = 0; i < E; ++i) {
+    for (int i = 0; i < E && !LATE; ++i) {
         const int q = t + Tn * i;
         const int64_t k = col_of(q & (W - 1)) + N1 * (int64_t)(q >> logW);
         wkv[i] = tw_any<R>((uint64_t)k, mp + 1);
-        if constexpr (MODE == PM_SOLVE || MODE == PM_MATVEC || MODE == PM_ADJ) {
+        if constexpr (MODE == PM_ADJ) {
             const double la = lam[k], lb = lam[(n - k) & (n - 1)];
             const double lc = lam[k + N], ld = lam[(N - k) & (n - 1)];
-            if constexpr (MODE == PM_SOLVE) {
-                // (1/(la+s2) + 1/(lb+s2)) / 2 with one division
-                const double pa = la + a.sigma2, pb = lb + a.sigma2;
-                const double pc = lc + a.sigma2, pd = ld + a.sigma2;
-                f1[i] = 0.5 * a.scale * (pa + pb) / (pa * pb);
-                f2[i] = 0.5 * a.scale * (pc + pd) / (pc * pd);
-            } else {
-                f1[i] = 0.5 * a.scale * (la + lb);
-                f2[i] = 0.5 * a.scale * (lc + ld);
-            }
+            f1[i] = 0.5 * a.scale * (la + lb);
+            f2[i] = 0.5 * a.scale * (lc + ld);
         }
         if constexpr (MODE == PM_QFORM) {
             const double la = lam[k], lc = lam[k + N];
@@ -192,8 +233,16 @@ __device__ __forceinline__ void real_top_body(const PassArgs &a, double *lam_out
             // untangle, filter by s1 at k and s2 at k + N, re-pack, in one
             // step: Z'_k = p Z_k + i q conj(Z_{N-k}) with real
             // p = (s1 + s2)/2 + (s1 - s2)/2 Im W_n^k, q = (s1 - s2)/2 Re W_n^k
-            const R hs = (R)(0.5 * (f1[i] + f2[i])), hd = (R)(0.5 * (f1[i] - f2[i]));
-            const R pc = hs + hd * wkv[i].im, qc = hd * wkv[i].re;
+            R pc, qc;
+            if constexpr (CF) {
+                const T c2 = crow[k1 + N1 * (int64_t)k2];
+                pc = c2.re;
+                qc = c2.im;
+            } else {
+                const T c2 = filter_pq<T, MODE>(lam, k1 + N1 * (int64_t)k2, mp, a.sigma2, a.scale);
+                pc = c2.re;
+                qc = c2.im;
+            }
             v[i] = T{pc * zk.re + qc * zm.im, pc * zk.im + qc * zm.re};
             continue;
         }
@@ -511,16 +560,16 @@ int launch_ft(const PassArgs &aK, const PassArgs &aY, double *lam_out, double *l
     return LDK_OK;
 }
 
-template <typename T, int LOGE, int MODE, int LD, int ST, bool SRC_F32>
+template <typename T, int LOGE, int MODE, int LD, int ST, bool SRC_F32, bool CF>
 __global__ __launch_bounds__(512) void k_real_top(PassArgs a, double *lam_out, double *ld_part)
 {
     const int64_t cb_count = ((int64_t)1 << a.g.b0) >> a.g.logW;
     const int64_t bid = xcd_tile(blockIdx.x, gridDim.x);
-    real_top_body<T, LOGE, MODE, LD, ST, SRC_F32>(a, lam_out, bid / cb_count, bid % cb_count,
-                                                  ld_part);
+    real_top_body<T, LOGE, MODE, LD, ST, SRC_F32, CF>(a, lam_out, bid / cb_count, bid % cb_count,
+                                                      ld_part);
 }
 
-template <typename T, int LOGE, int MODE, int LD, int ST, bool SRC_F32>
+template <typename T, int LOGE, int MODE, int LD, int ST, bool SRC_F32, bool CF = false>
 int launch_rt(const PassArgs &a, double *lam_out, hipStream_t s, double *ld_part = nullptr)
 {
     const int S = 1 << (a.g.a + a.g.logW);
@@ -531,19 +580,19 @@ int launch_rt(const PassArgs &a, double *lam_out, hipStream_t s, double *ld_part
     if (a.g.b0 + a.g.a != a.m) return LDK_EINVAL;  // must be the top pass
     if (a.g.b0 > 0 && a.g.logW < 1) return LDK_ENOTSUP;  // mirror runs need W >= 2
     const size_t lds = (size_t)(S + (S >> LDS_PAD_SHIFT)) * sizeof(T);
-    hipLaunchKernelGGL((k_real_top<T, LOGE, MODE, LD, ST, SRC_F32>), dim3((unsigned)blocks),
+    hipLaunchKernelGGL((k_real_top<T, LOGE, MODE, LD, ST, SRC_F32, CF>), dim3((unsigned)blocks),
                        dim3(threads), lds, s, a, lam_out, ld_part);
     LDK_LAUNCH_CHECK();
     return LDK_OK;
 }
 
-template <typename T, int MODE, int LD, int ST, bool SRC_F32>
+template <typename T, int MODE, int LD, int ST, bool SRC_F32, bool CF = false>
 int launch_rt_e(const PassArgs &a, double *lam_out, hipStream_t s, double *ld_part = nullptr)
 {
     switch (a.g.logE) {
-    case 1: return launch_rt<T, 1, MODE, LD, ST, SRC_F32>(a, lam_out, s, ld_part);
-    case 2: return launch_rt<T, 2, MODE, LD, ST, SRC_F32>(a, lam_out, s, ld_part);
-    case 3: return launch_rt<T, 3, MODE, LD, ST, SRC_F32>(a, lam_out, s, ld_part);
+    case 1: return launch_rt<T, 1, MODE, LD, ST, SRC_F32, CF>(a, lam_out, s, ld_part);
+    case 2: return launch_rt<T, 2, MODE, LD, ST, SRC_F32, CF>(a, lam_out, s, ld_part);
+    case 3: return launch_rt<T, 3, MODE, LD, ST, SRC_F32, CF>(a, lam_out, s, ld_part);
     default: return LDK_ENOTSUP;
     }
 }
@@ -551,8 +600,10 @@ int launch_rt_e(const PassArgs &a, double *lam_out, hipStream_t s, double *ld_pa
 template <typename T, int MODE>
 int launch_rt_io(bool single, const PassArgs &a, double *lam_out, hipStream_t s)
 {
-    // one pass: packed real rows in and out; otherwise the complex work rows
+    // one pass: packed real rows in and out; otherwise the complex work
+    // rows, with the filter coefficients precomputed when given
     if (single) return launch_rt_e<T, MODE, IO_PACKED, IO_PACKED, false>(a, lam_out, s);
+    if (a.coef) return launch_rt_e<T, MODE, IO_SAME, IO_SAME, false, true>(a, lam_out, s);
     return launch_rt_e<T, MODE, IO_SAME, IO_SAME, false>(a, lam_out, s);
 }
 
@@ -583,6 +634,33 @@ int launch_fit_top(const PassArgs &aK, const PassArgs &aY, double *lam_out, doub
                       : launch_ft<3, IO_SAME, IO_SAME>(aK, aY, lam_out, ld_part, s);
     default: return LDK_ENOTSUP;
     }
+}
+
+int launch_filter_coef(int dtype, int mode, int mp, int64_t lam_rows, const double *lam,
+                       double sigma2, double scale, void *coef, hipStream_t s)
+{
+    if (mp < 1 || lam_rows < 1 || !lam || !coef) return LDK_EINVAL;
+    const int64_t count = lam_rows << mp;
+    const int64_t blocks = (count + 255) / 256;
+    if (blocks > 0x7fffffff) return LDK_ENOTSUP;
+    const dim3 g((unsigned)blocks), b(256);
+    if (dtype == LDK_F64) {
+        if (mode == PM_SOLVE)
+            hipLaunchKernelGGL((k_filter_coef<cplx<double>, PM_SOLVE>), g, b, 0, s, lam, mp, count,
+                               sigma2, scale, static_cast<cplx<double> *>(coef));
+        else
+            hipLaunchKernelGGL((k_filter_coef<cplx<double>, PM_MATVEC>), g, b, 0, s, lam, mp, count,
+                               sigma2, scale, static_cast<cplx<double> *>(coef));
+    } else {
+        if (mode == PM_SOLVE)
+            hipLaunchKernelGGL((k_filter_coef<cplx<float>, PM_SOLVE>), g, b, 0, s, lam, mp, count,
+                               sigma2, scale, static_cast<cplx<float> *>(coef));
+        else
+            hipLaunchKernelGGL((k_filter_coef<cplx<float>, PM_MATVEC>), g, b, 0, s, lam, mp, count,
+                               sigma2, scale, static_cast<cplx<float> *>(coef));
+    }
+    LDK_LAUNCH_CHECK();
+    return LDK_OK;
 }
 
 int launch_real_top(int dtype, int mode, const PassArgs &a, double *lam_out, hipStream_t s,

@@ -97,6 +97,11 @@ struct PassArgs {
     int64_t ld_count;
     // PM_QFORM only: weights lambda_k (1) or 1 / (lambda_k + sigma2) (0)
     int qform_lam;
+    // Real-input lattice top pass, PM_SOLVE / PM_MATVEC, optional: the
+    // filter's per-frequency coefficients (p, q) as working-type complex
+    // pairs [rows / nrhs][N] (launch_filter_coef); NULL forms them from lam
+    // in the pass itself.
+    const void *coef;
     // PIO_COMBINE only: the old half's transform [rows][2^m]; the store
     // writes (old + w) / sqrt 2 at k and (old - w) / sqrt 2 at 2^m + k of
     // dst rows of 2^(m+1), w the pass output (times W_{2^(m+1)}^k, lattice).
@@ -133,6 +138,13 @@ int launch_pass(int kind, int dtype, int mode, int ld, int st, const PassArgs &a
 // [rows][tiles per row], for a log-det finished by one reduction kernel.
 int launch_real_top(int dtype, int mode, const PassArgs &a, double *lam_out, hipStream_t s,
                     bool src_f32 = false, double *ld_part = nullptr);
+
+// The real-input lattice solve's (PM_SOLVE) or matvec's (PM_MATVEC) filter
+// coefficients, one (p, q) pair per frequency k < N = 2^mp of each of the
+// lam_rows eigenvalue rows [lam_rows][2N], into coef (dtype complex pairs
+// [lam_rows][N]); scale as the top pass's.
+int launch_filter_coef(int dtype, int mode, int mp, int64_t lam_rows, const double *lam,
+                       double sigma2, double scale, void *coef, hipStream_t s);
 
 // The fused fit's top passes (FP64 lattice, one right-hand side per column
 // row): aK's tiles give the eigenvalues (lam_out, and the log-det partial

@@ -154,9 +154,11 @@ def test_workspace_sizes():
     ws = L.ldk_workspace_bytes
     assert ws(ldk.OP_TRANSFORM, ldk.DNET_B2, 4, 20, 0) == 0
     assert ws(ldk.OP_SOLVE, ldk.DNET_B2, 4, 20, 0) == 0
-    # real lattice rows of n run as packed complex rows of n/2
-    assert ws(ldk.OP_SOLVE, ldk.LATTICE, 4, 20, 0) == 4 * 2**19 * 16
-    assert ws(ldk.OP_SOLVE, ldk.LATTICE, 4, 20, 1) == 4 * 2**19 * 8
+    # real lattice rows of n run as packed complex rows of n/2, plus the
+    # solve filter's coefficients for up to B / 2 eigenvalue rows
+    assert ws(ldk.OP_SOLVE, ldk.LATTICE, 4, 20, 0) == (4 + 2) * 2**19 * 16
+    assert ws(ldk.OP_SOLVE, ldk.LATTICE, 4, 20, 1) == (4 + 2) * 2**19 * 8
+    assert ws(ldk.OP_SOLVE, ldk.LATTICE, 1, 20, 0) == 2**19 * 16
     assert ws(ldk.OP_SOLVE, ldk.LATTICE, 4, 10, 0) == 0  # one pass, no intermediate
     assert ws(ldk.OP_LOGDET, ldk.DNET_B2, 3, 20, 0) == 3 * 512 * 8
     assert ws(ldk.OP_EIG, 9, 1, 4, 0) == 0
