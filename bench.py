@@ -55,9 +55,9 @@ TUNED_TABLE = os.path.join(ROOT, "paper_2502_14256_amd", "tuned_mi355x.txt")
 STEP_TRAFFIC = {"read_MiB": 0.15, "write_MiB": 264.00,
                 "sources": ('kcol.hip', 'kfactor.hpp', 'pointset.hpp', 'common.hpp'),
                 "sha1": "3fb4f06736c33f6c238f51be1cc2145f0fc5a353"}
-SOLVE_TRAFFIC = {"read_MiB": 41.51, "write_MiB": 34.56,
+SOLVE_TRAFFIC = {"read_MiB": 39.09, "write_MiB": 32.06,
                  "sources": ('transform.hip', 'realfft.hip', 'passkit.hpp', 'transform.hpp', 'common.hpp'),
-                 "sha1": "e3a6a6e4abda23d2e908edb8ebfde957fe3b1e38"}
+                 "sha1": "8c29a7b87f3ab5a92acb75e008b39effa1d7f3ae"}
 
 
 def traffic_bytes(rec):
