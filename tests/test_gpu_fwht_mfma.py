@@ -164,3 +164,20 @@ def test_split16_gradient_step_matches_oracle(orc, split16_table):
     oG = gate_vs_ld(grad, ref["grad"], ref_ld["grad"], F32_EPS, 1e-5).max()
     record("split16_grad_step_dnet_m13_d6", L_over_gate=oL, grad_over_gate=oG)
     assert oL <= 1.0 and oG <= 1.0, (oL, oG)
+
+
+@pytest.mark.parametrize("m", [12, 16])
+def test_split16_solve_unaligned_rows(split16_table, m):
+    # rows 4 bytes past a 16-byte boundary: the row passes load and store
+    # element by element; same arithmetic, so the same bits as aligned rows
+    rng = np.random.default_rng(70 + m)
+    R, nrhs, n = 2, 3, 2**m
+    lam = torch.from_numpy(1.0 + rng.random((R, n))).cuda()
+    y = torch.from_numpy(rng.standard_normal((R, nrhs, n))).float().cuda()
+    want = ldk.solve("dnet", lam, 1e-3, y)
+    yb = torch.zeros(R * nrhs * n + 1, dtype=torch.float32, device="cuda")[1:].view(R, nrhs, n)
+    cb = torch.zeros(R * nrhs * n + 1, dtype=torch.float32, device="cuda")[1:].view(R, nrhs, n)
+    yb.copy_(y)
+    assert yb.data_ptr() % 16 == 4 and cb.data_ptr() % 16 == 4
+    got = ldk.solve("dnet", lam, 1e-3, yb, out=cb)
+    assert torch.equal(got, want)
