@@ -62,6 +62,29 @@ def test_halton_largest_dimension_and_large_index(orc):
     assert np.array_equal(got, orc.bpoints("halton", R, d, lo, hi, flags=7, **inp))
 
 
+@pytest.mark.parametrize("flags", [0, 7])
+@pytest.mark.parametrize("kind,base,d", [("halton", 0, 8), ("faure", 3, 3), ("faure", 251, 3)])
+def test_indices_below_two_to_32(orc, kind, base, d, flags):
+    # the top of the index range: 32 base-2 digits (the longest packed digit
+    # vector), 21 base-3 digits, 5 base-251 digits; the 32-bit division at
+    # its largest arguments
+    R = 2
+    inp, ps = _bps(kind, R, d, base=base, flags=flags, seed=41)
+    lo, hi = 2**32 - 700, 2**32
+    got = ldk.gen_bpoints(ps, lo, hi).cpu().numpy()
+    assert np.array_equal(got, orc.bpoints(kind, R, d, lo, hi, base=base, flags=flags, **inp))
+
+
+@pytest.mark.parametrize("b,d", [(61, 60), (97, 90)])
+def test_faure_more_dimensions_than_halton(orc, b, d):
+    # Faure allows d up to its base (251): more dimensions than the Halton
+    # bases, every one sharing the base
+    R = 2
+    inp, ps = _bps("faure", R, d, base=b, flags=7, seed=43)
+    got = ldk.gen_bpoints(ps, 11, 320).cpu().numpy()
+    assert np.array_equal(got, orc.bpoints("faure", R, d, 11, 320, base=b, flags=7, **inp))
+
+
 @pytest.mark.parametrize("window", [(0, 4096), (100, 3001)])
 def test_nus_bit_exact(orc, window):
     m, d, R = 12, 5, 3
