@@ -240,42 +240,56 @@ __global__ __launch_bounds__(RQ_FINAL_THREADS) void k_rqmc_final(const double *_
     }
 }
 
-// Given points: one block per (tile of RQ_PTS_TILE points, replication).
-// The tile's coordinate rows are contiguous, so the block stages them in
-// chunks of RQ_PTS_CHUNK points through LDS with coalesced loads; then four
-// threads share a point (dimensions j = q, q + 4, ...), their partial sums
-// of c_j x_ij combine in a fixed order, and the first of them applies f.
-constexpr int RQ_PTS_CHUNK = KC_THREADS / 4;
-constexpr int RQ_PTS_TILE = 4 * RQ_PTS_CHUNK;
-constexpr int RQ_PTS_MAX_D = 128;  // LDS: RQ_PTS_CHUNK x d doubles
+// Given points: one block per (tile of RQ_PTS_TILE points, replication),
+// read straight from HBM: sixteen lanes share a point (dimensions j = q,
+// q + 16, ...), their partial sums of c_j x_ij combine in a fixed order, and
+// f is applied once per point.
+constexpr int RQ_PTS_W = 16;                    // lanes per point
+constexpr int RQ_PTS_GROUPS = KC_THREADS / RQ_PTS_W;  // point groups of a block
+constexpr int RQ_PTS_TILE = RQ_PTS_GROUPS * RQ_PTS_W; // points per block: each group takes 16
+constexpr int RQ_PTS_MAX_D = 128;               // coefficients per lane: d / 16 <= 8
 
+// Group g of 16 lanes reads the rows of points first + g + 16 it (it < 16):
+// lane q takes coordinates q, q + 16, ..., so a wave's four groups read four
+// consecutive rows, whole cache lines per load.  The 16-lane sum of each
+// dot product lands in every lane of the group; lane q keeps the one of
+// it == q, and every lane then evaluates one integrand.
 template <int F>
 __global__ __launch_bounds__(KC_THREADS) void k_rqmc_pts(const double *__restrict__ x, int d,
                                                          int64_t n, const double *__restrict__ coef,
                                                          double phase, double *__restrict__ part)
 {
     __shared__ double red[KC_THREADS / 64];
-    __shared__ double rows[RQ_PTS_CHUNK * RQ_PTS_MAX_D];
-    __shared__ double sc[RQ_PTS_MAX_D];
     const int r = blockIdx.y, t = threadIdx.x;
-    const int p = t >> 2, q = t & 3;
-    for (int j = t; j < d; j += KC_THREADS) sc[j] = coef[j];
-    double acc = 0.0;
-    for (int c = 0; c < RQ_PTS_TILE / RQ_PTS_CHUNK; ++c) {
-        const int64_t first = (int64_t)blockIdx.x * RQ_PTS_TILE + (int64_t)c * RQ_PTS_CHUNK;
-        const int64_t cnt64 = n - first;
-        const int cnt = cnt64 < RQ_PTS_CHUNK ? (int)(cnt64 > 0 ? cnt64 : 0) : RQ_PTS_CHUNK;
-        __syncthreads();  // the previous chunk's reads are done
-        const double *src = x + ((size_t)r * n + first) * d;
-        for (int e = t; e < cnt * d; e += KC_THREADS) rows[e] = src[e];
-        __syncthreads();
+    const int q = t & (RQ_PTS_W - 1), g = t / RQ_PTS_W;
+    double c[RQ_PTS_MAX_D / RQ_PTS_W];
+#pragma unroll
+    for (int k = 0; k < RQ_PTS_MAX_D / RQ_PTS_W; ++k) {
+        const int j = q + RQ_PTS_W * k;
+        c[k] = j < d ? coef[j] : 0.0;
+    }
+    const int64_t first = (int64_t)blockIdx.x * RQ_PTS_TILE + g;
+    double mine = 0.0;
+#pragma unroll 2
+    for (int it = 0; it < RQ_PTS_W; ++it) {
+        const int64_t p = first + (int64_t)RQ_PTS_W * it;
         double s = 0.0;
-        if (p < cnt)
-            for (int j = q; j < d; j += 4) s = fma(sc[j], rows[p * d + j], s);
+        if (p < n) {
+            const double *row = x + ((size_t)r * n + p) * d;
+#pragma unroll
+            for (int k = 0; k < RQ_PTS_MAX_D / RQ_PTS_W; ++k) {
+                const int j = q + RQ_PTS_W * k;
+                if (j < d) s = fma(c[k], row[j], s);
+            }
+        }
         s += __shfl_xor(s, 1, 64);
         s += __shfl_xor(s, 2, 64);
-        if (q == 0 && p < cnt) acc += integrand<F>(s, d, phase);
+        s += __shfl_xor(s, 4, 64);
+        s += __shfl_xor(s, 8, 64);
+        if (it == q) mine = s;
     }
+    const int64_t pm = first + (int64_t)RQ_PTS_W * q;
+    const double acc = pm < n ? integrand<F>(mine, d, phase) : 0.0;
     const double tot = block_sum<KC_THREADS>(acc, red);
     if (threadIdx.x == 0) part[(size_t)r * gridDim.x + blockIdx.x] = tot;
 }

@@ -139,3 +139,21 @@ def test_rqmc_over_points_matches_oracle(orc, integrand, kind):
     mu_r, stats = ldk.rqmc_points(x, integrand, torch.from_numpy(c).cuda(), u=0.3, tau=0.01)
     _check(f"rqmc_points_{kind}_{integrand}", mu_r.cpu().numpy(), stats.cpu().numpy(), ref, y,
            integrand, c, n)
+
+
+@pytest.mark.parametrize("integrand", ["corner_peak", "oscillatory"])
+@pytest.mark.parametrize("R,n,d", [(1, 1, 1), (3, 255, 17), (2, 257, 52), (4, 5000, 52), (2, 700, 128),
+                                   (2, 4099, 16)])
+def test_rqmc_points_shapes(orc, integrand, R, n, d):
+    # any coordinates in [0, 1): ragged tiles (n not a multiple of 256 points),
+    # d from 1 to the largest (128), one replication (no interval)
+    from test_gpu_rqmc import _check
+    rng = np.random.default_rng(1000 * d + n)
+    xh = rng.random((R, n, d))
+    c = W.corner_peak_coefficients(d)
+    y = orc.genz_corner_peak(xh, c) if integrand == "corner_peak" else orc.genz_oscillatory(xh, c, 0.3)
+    ref = orc.rqmc(y, tau=0.01)
+    mu_r, stats = ldk.rqmc_points(torch.from_numpy(xh).cuda(), integrand, torch.from_numpy(c).cuda(), u=0.3,
+                                  tau=0.01)
+    _check(f"rqmc_points_R{R}_n{n}_d{d}_{integrand}", mu_r.cpu().numpy(), stats.cpu().numpy(), ref, y,
+           integrand, c, n)
