@@ -40,7 +40,6 @@ namespace ldk {
 namespace {
 
 constexpr int BP_T = LDK_BDIGITS_MAX;  // digit rows of the scramble layouts
-constexpr int BP_THREADS = 256;
 constexpr int BP_MAX_D = 54;    // the first 54 primes are below 256
 constexpr int BP_KMAX = 32;     // index digits (i < 2^32)
 constexpr int BP_QW = BP_KMAX / 4;  // words of a packed digit row
@@ -236,20 +235,21 @@ __device__ __forceinline__ double coordinate(const BpArgs &a, const uint32_t *__
     return v / bT;
 }
 
-// Write a finished tile: rows p < valid of dimensions j0 .. j0+dch-1.  With
-// every dimension in the tile the rows are one contiguous run.
-__device__ __forceinline__ void flush_tile(const BpArgs &a, double *__restrict__ out, const double *tile,
+// Write a finished tile: rows p < valid of dimensions j0 .. j0+dch-1 of the
+// [R][cnt][d] output.  With every dimension in the tile the rows are one
+// contiguous run.
+__device__ __forceinline__ void flush_tile(double *__restrict__ out, const double *tile, int64_t cnt, int d,
                                            int r, int64_t i0, int j0, int dch, int tid)
 {
-    const int64_t rest = a.cnt - i0;
+    const int64_t rest = cnt - i0;
     const int valid = rest < BP_P ? (int)rest : BP_P;
-    double *dst = out + ((size_t)r * a.cnt + i0) * a.d + j0;
-    if (dch == a.d) {
+    double *dst = out + ((size_t)r * cnt + i0) * d + j0;
+    if (dch == d) {
         for (int e = tid; e < valid * dch; e += BP_TT) dst[e] = tile[e];
     } else {
         for (int e = tid; e < valid * dch; e += BP_TT) {
             const int p = e / dch;
-            dst[(size_t)p * a.d + (e - p * dch)] = tile[e];
+            dst[(size_t)p * d + (e - p * dch)] = tile[e];
         }
     }
 }
@@ -300,7 +300,7 @@ __global__ __launch_bounds__(BP_TT) void k_gen_halton(BpArgs a, const uint32_t *
         tile[lane * a.d + j] = x;
     }
     __syncthreads();
-    flush_tile(a, out, tile, r, i0, 0, a.d, tid);
+    flush_tile(out, tile, a.cnt, a.d, r, i0, 0, a.d, tid);
 }
 
 // Faure: one base for every dimension, so a lane forms its index digits (MJ
@@ -343,7 +343,7 @@ __global__ __launch_bounds__(BP_TT) void k_gen_faure(BpArgs a, const uint32_t *_
                                                       L, a.bT[0], lane);
         }
         __syncthreads();
-        flush_tile(a, out, tile, r, i0, j0, dch, tid);
+        flush_tile(out, tile, a.cnt, a.d, r, i0, j0, dch, tid);
         __syncthreads();  // the tile is free for the next dimensions
     }
 }
@@ -355,28 +355,39 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z)
     return z ^ (z >> 31);
 }
 
-__global__ __launch_bounds__(BP_THREADS) void k_gen_nus(int d, int m, int64_t n_min, int64_t cnt,
-                                                         const uint64_t *__restrict__ gen,
-                                                         const uint64_t *__restrict__ seed,
-                                                         double *__restrict__ out)
+// NUS: a block takes 64 consecutive indices of one replication, one per
+// lane; its eight waves split the dimensions of each tile of up to 64 and
+// the block stores the tile's rows (contiguous when d <= 64).
+__global__ __launch_bounds__(BP_TT) void k_gen_nus(int d, int m, int64_t n_min, int64_t cnt,
+                                                   const uint64_t *__restrict__ gen,
+                                                   const uint64_t *__restrict__ seed, double *__restrict__ out)
 {
-    const int r = blockIdx.y;
-    const int64_t ii = (int64_t)blockIdx.x * BP_THREADS + threadIdx.x;
-    if (ii >= cnt) return;
-    const uint64_t i = (uint64_t)(n_min + ii);
-    for (int j = 0; j < d; ++j) {
-        uint64_t z = 0;
-        for (int k = 0; k < m; ++k)
-            if ((i >> k) & 1u) z ^= gen[(size_t)j * m + k];
-        const uint64_t s = seed[(size_t)r * d + j];
-        // the flip of digit t keyed by the digits above it; the bit position
-        // of digit t is 64 - t
-        uint64_t flips = mix64(1ull ^ s) & 0x8000000000000000ull;
-        for (int t = 2; t <= 64; ++t) {
-            const uint64_t key = (1ull << (t - 1)) | (z >> (65 - t));
-            flips |= (mix64(key ^ s) >> 63) << (64 - t);
+    double *tile = reinterpret_cast<double *>(g_bp_lds);  // [64][min(d, 64)]
+    const int tid = threadIdx.x, lane = tid & 63, r = blockIdx.y;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t i0 = (int64_t)blockIdx.x * BP_P;
+    const int64_t ii = i0 + lane;
+    const uint64_t i = (uint64_t)(n_min + (ii < cnt ? ii : 0));
+    for (int j0 = 0; j0 < d; j0 += BP_DCH) {
+        const int dch = d - j0 < BP_DCH ? d - j0 : BP_DCH;
+        for (int jj = wave; jj < dch; jj += BP_WAVES) {
+            const int j = j0 + jj;
+            uint64_t z = 0;
+            for (int k = 0; k < m; ++k)
+                if ((i >> k) & 1u) z ^= gen[(size_t)j * m + k];
+            const uint64_t s = seed[(size_t)r * d + j];
+            // the flip of digit t keyed by the digits above it; the bit
+            // position of digit t is 64 - t
+            uint64_t flips = mix64(1ull ^ s) & 0x8000000000000000ull;
+            for (int t = 2; t <= 64; ++t) {
+                const uint64_t key = (1ull << (t - 1)) | (z >> (65 - t));
+                flips |= (mix64(key ^ s) >> 63) << (64 - t);
+            }
+            tile[lane * dch + jj] = unit_f64(z ^ flips);
         }
-        out[((size_t)r * cnt + ii) * d + j] = unit_f64(z ^ flips);
+        __syncthreads();
+        flush_tile(out, tile, cnt, d, r, i0, j0, dch, tid);
+        __syncthreads();  // the tile is free for the next dimensions
     }
 }
 
@@ -462,10 +473,11 @@ extern "C" int ldk_gen_bpoints(const ldk_bpointset *ps, int64_t n_min, int64_t n
     if (st) return st;
     hipStream_t s = as_stream(stream);
     if (ps->kind == LDK_DNET_NUS) {
-        const int64_t blocks = (cnt + BP_THREADS - 1) / BP_THREADS;
+        const int64_t blocks = (cnt + BP_P - 1) / BP_P;
         if (blocks > 0x7fffffff) return LDK_ENOTSUP;
-        hipLaunchKernelGGL(k_gen_nus, dim3((unsigned)blocks, (unsigned)ps->R), dim3(BP_THREADS), 0, s,
-                           ps->d, ps->m, n_min, cnt, ps->gen, ps->seed, out);
+        const size_t lds = (size_t)BP_P * (ps->d < BP_DCH ? ps->d : BP_DCH) * sizeof(double);
+        hipLaunchKernelGGL(k_gen_nus, dim3((unsigned)blocks, (unsigned)ps->R), dim3(BP_TT), lds, s, ps->d,
+                           ps->m, n_min, cnt, ps->gen, ps->seed, out);
         LDK_LAUNCH_CHECK();
         return LDK_OK;
     }

@@ -85,9 +85,11 @@ def test_faure_more_dimensions_than_halton(orc, b, d):
     assert np.array_equal(got, orc.bpoints("faure", R, d, 11, 320, base=b, flags=7, **inp))
 
 
+@pytest.mark.parametrize("d", [1, 5, 70])
 @pytest.mark.parametrize("window", [(0, 4096), (100, 3001)])
-def test_nus_bit_exact(orc, window):
-    m, d, R = 12, 5, 3
+def test_nus_bit_exact(orc, window, d):
+    # d = 70: two output tiles of dimensions
+    m, R = 12, 3
     t = W.small_net(8, m, d, R)
     seed = W.nus_seeds(8, R, d)
     ps = ldk.BPointSet("nus", R, d, gen=dev_u64(t["gen"]), seed=dev_u64(seed), m=m)
