@@ -203,9 +203,8 @@ int ldk_kernel_column(const ldk_kernel *k, const ldk_pointset *ps, const uint64_
  *   ldk_kernel_column(k, ps, NULL, NULL, n_min, n_max, dtype, k1),
  * bit for bit (Sec. 4.2, 4.3 and 5.4), with the same arguments, layouts and
  * restrictions.  The column regenerates the points in registers and does
- * not read pts, so for lattices the two run as one launch, the column's
- * arithmetic beside the point words' stores; nets run the two calls one
- * after the other.  pts and k1 must not overlap. */
+ * not read pts, so the two run as one launch, the column's arithmetic
+ * beside the point words' stores.  pts and k1 must not overlap. */
 int ldk_points_column(const ldk_kernel *k, const ldk_pointset *ps, int64_t n_min, int64_t n_max,
                       uint64_t *pts, int dtype, void *k1, ldk_stream stream);
 

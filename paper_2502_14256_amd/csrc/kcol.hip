@@ -168,14 +168,13 @@ __device__ __forceinline__ void net_tile(const KcolArgs &a, NetLds &L, int r, in
     }
 }
 
+// Column tile bx of replication r of a net (every thread of the block calls it).
 template <typename R, int ALPHA>
-__global__ __launch_bounds__(KC_THREADS) void k_kcol_net(KcolArgs a, int64_t tile_base,
-                                                        R *__restrict__ out)
+__device__ __forceinline__ void kcol_net_block(const KcolArgs &a, NetLds &L, int64_t tile_base,
+                                               R *__restrict__ out, int64_t bx, int r)
 {
-    __shared__ NetLds L;
-    const int r = blockIdx.y;
     const int64_t cnt = a.n_max - a.n_min;
-    const int64_t tile0 = tile_base + (int64_t)blockIdx.x * KC_TILE;
+    const int64_t tile0 = tile_base + bx * KC_TILE;
     const int64_t first = tile0 + threadIdx.x;
     fill_dsi_tables(L.tab, threadIdx.x, KC_THREADS);
     R prod[KC_ITERS];
@@ -190,6 +189,40 @@ __global__ __launch_bounds__(KC_THREADS) void k_kcol_net(KcolArgs a, int64_t til
         const int64_t i = first + (int64_t)l * KC_THREADS;
         if (i >= a.n_min && i < a.n_max) out[(size_t)r * cnt + (i - a.n_min)] = prod[l];
     }
+}
+
+template <typename R, int ALPHA>
+__global__ __launch_bounds__(KC_THREADS) void k_kcol_net(KcolArgs a, int64_t tile_base,
+                                                        R *__restrict__ out)
+{
+    __shared__ NetLds L;
+    kcol_net_block<R, ALPHA>(a, L, tile_base, out, blockIdx.x, blockIdx.y);
+}
+
+// Point words and first column of a net in one launch: column blocks and
+// point-word blocks interleaved as for lattices (the column regenerates the
+// points and never reads the words), one LDS region shared by the two
+// block kinds.
+template <typename R, int ALPHA>
+__global__ __launch_bounds__(KC_THREADS) void k_points_kcol_net(KcolArgs a, int64_t tile_base,
+                                                               int64_t kc_tiles, R *__restrict__ k1,
+                                                               GenGrid g, uint64_t *__restrict__ pts)
+{
+    __shared__ union {
+        NetLds k;
+        GenNetLds g;
+    } L;
+    const int64_t b = blockIdx.x;
+    const int64_t kc_blocks = kc_tiles * a.ps.R;
+    const int64_t total = kc_blocks + g.tiles * g.chunks * g.R;
+    const int64_t before = b * kc_blocks / total, upto = (b + 1) * kc_blocks / total;
+    if (upto != before) {
+        kcol_net_block<R, ALPHA>(a, L.k, tile_base, k1, before % kc_tiles, (int)(before / kc_tiles));
+        return;
+    }
+    const int64_t q = b - upto;
+    gen_net_block(a.ps, a.n_min, a.n_max, g.tile_base, g.P, g.logP, g.pairs, pts, q % g.tiles,
+                  (int)((q / g.tiles) % g.chunks), (int)(q / (g.tiles * g.chunks)), threadIdx.x, L.g);
 }
 
 // ---------------------------------------------------------------------------
@@ -240,7 +273,10 @@ template <typename R, int ALPHA>
 void launch_points_kcol(const KcolArgs &a, int64_t tile_base, int64_t kc_tiles, const GenGrid &g,
                         unsigned blocks, hipStream_t s, void *k1, uint64_t *pts)
 {
-    if (a.ps.order == LDK_LINEAR)
+    if (a.ps.kind == LDK_DNET_B2)
+        hipLaunchKernelGGL((k_points_kcol_net<R, ALPHA>), dim3(blocks), dim3(KC_THREADS), 0, s, a,
+                           tile_base, kc_tiles, (R *)k1, g, pts);
+    else if (a.ps.order == LDK_LINEAR)
         hipLaunchKernelGGL((k_points_kcol_lattice<R, ALPHA, LDK_LINEAR>), dim3(blocks),
                            dim3(KC_THREADS), 0, s, a, tile_base, kc_tiles, (R *)k1, g, pts);
     else
@@ -253,10 +289,17 @@ void launch_points_kcol_alpha(int alpha, const KcolArgs &a, int64_t tile_base, i
                               const GenGrid &g, unsigned blocks, hipStream_t s, void *k1,
                               uint64_t *pts)
 {
-    switch (alpha) {  // lattice orders 1..3, mixed orders 0
+    switch (alpha) {  // lattice orders 1..3 and net orders 1..4; mixed orders 0
     case 1: launch_points_kcol<R, 1>(a, tile_base, kc_tiles, g, blocks, s, k1, pts); break;
     case 2: launch_points_kcol<R, 2>(a, tile_base, kc_tiles, g, blocks, s, k1, pts); break;
     case 3: launch_points_kcol<R, 3>(a, tile_base, kc_tiles, g, blocks, s, k1, pts); break;
+    case 4:
+        if (a.ps.kind == LDK_DNET_B2) {
+            hipLaunchKernelGGL((k_points_kcol_net<R, 4>), dim3(blocks), dim3(KC_THREADS), 0, s, a,
+                               tile_base, kc_tiles, (R *)k1, g, pts);
+            break;
+        }
+        [[fallthrough]];
     default: launch_points_kcol<R, 0>(a, tile_base, kc_tiles, g, blocks, s, k1, pts);
     }
 }
@@ -384,11 +427,6 @@ extern "C" int ldk_points_column(const ldk_kernel *k, const ldk_pointset *ps, in
     if (n_min < 0 || n_max < n_min || n_max > lim) return LDK_EINVAL;
     if (n_max == n_min) return LDK_OK;  // empty window: the outputs may be NULL
     if (!pts || !k1) return LDK_EINVAL;
-    if (p.kind != LDK_LATTICE) {
-        st = ldk_gen_points(ps, n_min, n_max, pts, stream);
-        if (st) return st;
-        return ldk_kernel_column(k, ps, nullptr, nullptr, n_min, n_max, dtype, k1, stream);
-    }
     const int64_t tile_base = (n_min / KC_TILE) * KC_TILE;
     const int64_t kc_tiles = (n_max - tile_base + KC_TILE - 1) / KC_TILE;
     const GenGrid g = gen_grid(p, n_min, n_max, pts);

@@ -102,6 +102,18 @@ inline GenGrid gen_grid(const PointsetArgs &a, int64_t n_min, int64_t n_max, con
     return g;
 }
 
+// LDS of a net block: the scrambled columns S_j C_j of a chunk of
+// dimensions, then the XOR steps between a thread's points (rows padded to
+// 65 words: the lanes of a wave read different dimensions jj at one step
+// index, and 64-word rows would put them all in one LDS bank).
+struct GenNetLds {
+    uint64_t ct[GEN_DIM_CHUNK][65];
+    union {
+        uint64_t step[GEN_DIM_CHUNK][65];
+        uint64_t srow[GEN_DIM_CHUNK][65];  // rows of S_j, dead once ct is built
+    } u;
+};
+
 // One lattice block of the tiling: point tile bx, dimension chunk by,
 // replication r; thread t of GEN_THREADS.  With pairs (see GenGrid), a
 // thread writes dimensions j, j + 1 of its points as one 16-byte store.
@@ -150,6 +162,104 @@ __device__ __forceinline__ void gen_lattice_block(const PointsetArgs &a, int64_t
         *dst = lattice_point(g, (uint64_t)i, a.order, a.m_max) + delta;
         i += P;
         dst += dstep;
+    }
+}
+
+// One net block of the tiling: point tile bx, dimension chunk by,
+// replication r; thread t of GEN_THREADS walks the points
+// i = tile + p + P * k, k < GEN_ITERS_NET, of dimension j0 + jj.  Every
+// thread of the block calls it (it synchronises the block).
+__device__ __forceinline__ void gen_net_block(const PointsetArgs &a, int64_t n_min, int64_t n_max,
+                                              int64_t tile_base, int P, int logP, int pairs,
+                                              uint64_t *__restrict__ out, int64_t bx, int by, int r,
+                                              int t, GenNetLds &L)
+{
+    auto &ct = L.ct;
+    auto &u = L.u;
+    auto &step = u.step;
+    const int j0 = by * GEN_DIM_CHUNK;
+    const int DB = min(GEN_DIM_CHUNK, a.d - j0);
+    const int m = a.m_max;
+
+    if (a.lms) {
+        for (int w = t; w < DB * 64; w += GEN_THREADS)
+            u.srow[w >> 6][w & 63] = a.lms[((size_t)r * a.d + j0 + (w >> 6)) * 64 + (w & 63)];
+        __syncthreads();
+    }
+    for (int w = t; w < DB * m; w += GEN_THREADS) {
+        const int jj = w / m, k = w % m;
+        const uint64_t col = net_gen_column(a, r, j0 + jj, k);
+        ct[jj][k] = a.lms ? lms_column(u.srow[jj], col) : col;
+    }
+    __syncthreads();  // srow is dead from here on; step reuses its storage
+    const int s = logP;
+    for (int w = t; w < DB * 64; w += GEN_THREADS) {
+        const int jj = w / 64, c = w % 64;
+        uint64_t v = 0;
+        if (s + c < m) {
+            if (a.order == LDK_GRAY) {
+                v = ct[jj][s + c] ^ (s >= 1 ? ct[jj][s - 1] : 0);
+            } else {
+                for (int k = s; k <= s + c; ++k) v ^= ct[jj][k];
+            }
+        }
+        step[jj][c] = v;
+    }
+    __syncthreads();
+
+    const int64_t cnt = n_max - n_min;
+    if (pairs) {
+        // two dimensions per thread, one 16-byte store per point (even d,
+        // aligned destination): half the store instructions
+        const int DB2 = DB >> 1;
+        const int p = t / DB2, jj = 2 * (t % DB2);
+        if (p >= P) return;
+        const int j = j0 + jj;
+        const int64_t first = tile_base + bx * P * GEN_ITERS_NET + p;
+        if (first >= n_max) return;
+        const uint64_t blk = ((uint64_t)tile_base >> s) + (uint64_t)bx * GEN_ITERS_NET;
+        const uint64_t d0 = a.shift ? a.shift[(size_t)r * a.d + j] : 0;
+        const uint64_t d1 = a.shift ? a.shift[(size_t)r * a.d + j + 1] : 0;
+        const uint64_t code0 = a.order == LDK_GRAY ? gray_code((uint64_t)first) : (uint64_t)first;
+        uint64_t z0 = net_point(ct[jj], m, code0), z1 = net_point(ct[jj + 1], m, code0);
+        uint64_t *const row = out + (size_t)r * cnt * a.d + j;
+        int64_t i = first;
+        for (int k = 0; k < GEN_ITERS_NET; ++k) {
+            if (i >= n_min) {
+                ulonglong2 w2;
+                w2.x = z0 ^ d0;
+                w2.y = z1 ^ d1;
+                *reinterpret_cast<ulonglong2 *>(row + (size_t)(i - n_min) * a.d) = w2;
+            }
+            const int64_t next = i + P;
+            if (next >= n_max || k + 1 == GEN_ITERS_NET) break;
+            const int c = ctz64(blk + (uint64_t)k + 1);
+            z0 ^= step[jj][c];
+            z1 ^= step[jj + 1][c];
+            i = next;
+        }
+        return;
+    }
+    const int p = t / DB, jj = t % DB;
+    if (p >= P) return;
+    const int j = j0 + jj;
+    // tiles start at multiples of P GEN_ITERS_NET (tile_base <= n_min), so
+    // point k of every thread has i >> s = blk + k: the step index is the same
+    // for the whole block (scalar work); points below n_min are not stored
+    const int64_t first = tile_base + bx * P * GEN_ITERS_NET + p;
+    if (first >= n_max) return;
+    const uint64_t blk = ((uint64_t)tile_base >> s) + (uint64_t)bx * GEN_ITERS_NET;
+    const uint64_t delta = a.shift ? a.shift[(size_t)r * a.d + j] : 0;
+    const uint64_t code0 = a.order == LDK_GRAY ? gray_code((uint64_t)first) : (uint64_t)first;
+    uint64_t z = net_point(ct[jj], m, code0);
+    uint64_t *const row = out + (size_t)r * cnt * a.d + j;
+    int64_t i = first;
+    for (int k = 0; k < GEN_ITERS_NET; ++k) {
+        if (i >= n_min) row[(size_t)(i - n_min) * a.d] = z ^ delta;
+        const int64_t next = i + P;
+        if (next >= n_max || k + 1 == GEN_ITERS_NET) break;
+        z ^= step[jj][ctz64(blk + (uint64_t)k + 1)];
+        i = next;
     }
 }
 

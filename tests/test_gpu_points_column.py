@@ -1,7 +1,7 @@
 """ldk_points_column (points and first Gram column in one call) against the
 two separate calls, ldk_gen_points and ldk_kernel_column with regenerated
-points: both outputs bit for bit (the same per-point arithmetic, one launch
-for lattices), and the points against the oracle."""
+points: both outputs bit for bit (the same per-point arithmetic, one
+launch), and the points against the oracle."""
 import numpy as np
 import pytest
 import torch
