@@ -620,6 +620,38 @@ int ldk_fit(int kind, int R, int nrhs, int m, int dtype, const void *k1, double 
     const int64_t B = (int64_t)R * (nrhs + 1);
     if (fit_ws_bytes(kind, B, m, dtype) && !ws) return LDK_EINVAL;
     int st;
+    if (kind == LDK_DNET_B2 && dtype == LDK_F64 && nrhs > 0 && m >= 1) {
+        // a net whose eigenvalue and solve plans are both one pass: the
+        // whole fit in one launch, with the separate calls' pass arguments
+        const Plan pe = tuned_plan(LDK_DNET_B2, LDK_F64, m, m, R);
+        const Plan pq = tuned_plan(LDK_DNET_B2, LDK_F64, m, m, (int64_t)R * nrhs);
+        if (pe.P == 1 && pq.P == 1) {
+            st = ensure_init();
+            if (st) return st;
+            const int64_t n = (int64_t)1 << m;
+            PassArgs aE{}, aS{};
+            aE.src = k1;
+            aE.dst = lam;
+            aE.src_row = aE.dst_row = n;
+            aE.rows = R;
+            aE.m = m;
+            aE.g = pe.pass[0];
+            aE.nrhs = 1;
+            aE.scale = 1.0;
+            aS.src = y;
+            aS.dst = c;
+            aS.src_row = aS.dst_row = n;
+            aS.rows = (int64_t)R * nrhs;
+            aS.m = m;
+            aS.g = pq.pass[0];
+            aS.lam = lam;
+            aS.nrhs = nrhs;
+            aS.sigma2 = sigma2;
+            aS.scale = 1.0 / (double)n;
+            st = launch_fit_net_one(aE, aS, logdet, as_stream(stream));
+            if (st != LDK_ENOTSUP) return st;
+        }
+    }
     if (!fit_fused(kind, m, dtype) || nrhs == 0) {
         st = ldk_eig(kind, R, m, dtype, k1, lam, ws, stream);
         if (st) return st;

@@ -184,6 +184,39 @@ __global__ __launch_bounds__(512) void k_pass2(PassArgs a0, PassArgs a1, int64_t
     else pass_body<T, LOGE, MODE, LD, ST, SRC_F32>(a1, b - nb0);
 }
 
+// The fit of a net whose transform is one pass (the whole row in one tile),
+// FP64: workgroup r runs replication r's eigenvalue tile, then its
+// right-hand sides' solve tiles, with the pass bodies and arguments of
+// ldk_eig and ldk_solve (so lambda and c are theirs bit for bit; the solve
+// reads the eigenvalues this workgroup has just stored), then the log-det
+// of the row: per-thread products of the values (LogProd) and a
+// fixed-order tree.
+template <int LOGE>
+__global__ __launch_bounds__(512) void k_fit_net_one(PassArgs aE, PassArgs aS, double *logdet)
+{
+    const int64_t r = blockIdx.x;
+    pass_body<double, LOGE, PM_FWD, IO_SAME, IO_SAME, false>(aE, r);
+    __syncthreads();  // the row's eigenvalues are stored (and visible to the workgroup)
+    for (int q = 0; q < aS.nrhs; ++q) {
+        pass_body<double, LOGE, PM_SOLVE, IO_SAME, IO_SAME, false>(aS, r * aS.nrhs + q);
+        __syncthreads();  // the LDS is free for the next tile
+    }
+    if (!logdet) return;
+    const int64_t n = (int64_t)1 << aE.m;
+    const double *lam = static_cast<const double *>(aE.dst) + r * n;
+    const int t = threadIdx.x, T = blockDim.x;
+    LogProd acc;
+    for (int64_t k = t; k < n; k += T) acc.add(lam[k] + aS.sigma2);
+    double *red = reinterpret_cast<double *>(g_pass_lds);
+    red[t] = acc.value();
+    __syncthreads();
+    for (int w = T / 2; w > 0; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    if (t == 0) logdet[r] = red[0];
+}
+
 template <typename T, int LOGE, int MODE, bool SRC_F32>
 int launch_t(int ld, int st, const PassArgs &a, hipStream_t s)
 {
@@ -425,6 +458,37 @@ int launch_pass(int kind, int dtype, int mode, int ld, int st, const PassArgs &a
 }  // namespace ldk
 
 namespace ldk {
+
+int launch_fit_net_one(const PassArgs &aE, const PassArgs &aS, double *logdet, hipStream_t s)
+{
+    const PassGeom &g = aE.g;
+    const int S = 1 << (g.a + g.logW);
+    if (g.a + g.logW != aE.m || g.b0 != 0 || aS.g.a != g.a || aS.g.logW != g.logW || aS.g.logE != g.logE ||
+        aS.g.b0 != 0 || aS.m != aE.m)
+        return LDK_ENOTSUP;  // not one pass, or the two plans differ
+    const int threads = S >> g.logE;
+    if (threads > 512 || threads < 1 || (threads & (threads - 1)) || aE.rows > 0x7fffffff)
+        return LDK_ENOTSUP;
+    const size_t lds = (size_t)(S + (S >> LDS_PAD_SHIFT)) * sizeof(double);
+    const dim3 grid((unsigned)aE.rows), block(threads);
+    switch (g.logE) {
+    case 1:
+        if ((g.a + 1 - 1) / 1 > MAX_GROUPS) return LDK_ENOTSUP;
+        hipLaunchKernelGGL(k_fit_net_one<1>, grid, block, lds, s, aE, aS, logdet);
+        break;
+    case 2:
+        if ((g.a + 2 - 1) / 2 > MAX_GROUPS) return LDK_ENOTSUP;
+        hipLaunchKernelGGL(k_fit_net_one<2>, grid, block, lds, s, aE, aS, logdet);
+        break;
+    case 3:
+        if ((g.a + 3 - 1) / 3 > MAX_GROUPS) return LDK_ENOTSUP;
+        hipLaunchKernelGGL(k_fit_net_one<3>, grid, block, lds, s, aE, aS, logdet);
+        break;
+    default: return LDK_ENOTSUP;
+    }
+    LDK_LAUNCH_CHECK();
+    return LDK_OK;
+}
 
 namespace {
 template <typename T, int LOGE, int LD>

@@ -152,6 +152,10 @@ int launch_filter_coef(int dtype, int mode, int mp, int64_t lam_rows, const doub
 // aY.scale / (lambda + aY.sigma2), in one launch.  Same geometry for both;
 // the geometry's logE is 2 or 3 and 2^(a + logW - logE) a multiple of 64, at
 // most 256.
+// The whole fit of a one-pass FP64 net, one workgroup per replication:
+// eigenvalue pass aE, then the solve passes aS (nrhs >= 1), then the
+// log-det.  LDK_ENOTSUP when the geometry is not one pass shared by both.
+int launch_fit_net_one(const PassArgs &aE, const PassArgs &aS, double *logdet, hipStream_t s);
 int launch_fit_top(const PassArgs &aK, const PassArgs &aY, double *lam_out, double *ld_part,
                    hipStream_t s);
 // Whether launch_fit_top takes geometry g.
