@@ -272,7 +272,10 @@ int apply_all(int kind, int dtype, int mode, int m, int64_t rows, int nrhs, cons
 bool real_path(int kind, int m) { return kind == LDK_LATTICE && m >= 2; }
 
 // lambda = Re FFTBR_n(k1) (unnormalised), FP64, from real k1 rows of n.
-int real_eig(int m, int64_t rows, const void *k1, bool k1_f32, double *lam, void *ws, hipStream_t s)
+// With ld_part, the top pass also leaves each row's log-det partial sums
+// there (*ld_count per row, at ld_part + row * *ld_count), sigma2 added.
+int real_eig(int m, int64_t rows, const void *k1, bool k1_f32, double *lam, void *ws, hipStream_t s,
+             double *ld_part = nullptr, double sigma2 = 0.0, int *ld_count = nullptr)
 {
     const int mp = m - 1;
     const int64_t N = (int64_t)1 << mp;
@@ -283,11 +286,14 @@ int real_eig(int m, int64_t rows, const void *k1, bool k1_f32, double *lam, void
     a.nrhs = 1;
     a.half = N;
     a.scale = 1.0;
+    a.sigma2 = sigma2;
+    const PassGeom &top = pl.pass[pl.P - 1];
+    if (ld_count) *ld_count = 1 << (top.b0 - top.logW);
     if (pl.P == 1) {
         a.src = k1;
         a.src_row = 2 * N;
         a.g = pl.pass[0];
-        return launch_real_top(LDK_F64, PM_FWD, a, lam, s, k1_f32);
+        return launch_real_top(LDK_F64, PM_FWD, a, lam, s, k1_f32, ld_part);
     }
     for (int p = 0; p < pl.P - 1; ++p) {
         a.src = p == 0 ? k1 : ws;
@@ -304,13 +310,18 @@ int real_eig(int m, int64_t rows, const void *k1, bool k1_f32, double *lam, void
     a.src_row = N;
     a.g = pl.pass[pl.P - 1];
     a.global_tw = 1;
-    return launch_real_top(LDK_F64, PM_FWD, a, lam, s);
+    return launch_real_top(LDK_F64, PM_FWD, a, lam, s, false, ld_part);
 }
 
 // c = (K + s2 I)^-1 y (PM_SOLVE) or K y (PM_MATVEC) for real rows of n.
+// With ld_out, the first inverse pass also sums each of ld_rows rows'
+// ld_count log-det partials (left by real_eig) into ld_out when it has a full
+// wave per tile; *ld_done says whether it did.
 int real_apply(int dtype, int mode, int m, int64_t rows, int nrhs, const double *lam, double sigma2,
-               const void *y, void *c, void *ws, hipStream_t s)
+               const void *y, void *c, void *ws, hipStream_t s, const double *ld_part = nullptr,
+               int ld_count = 0, double *ld_out = nullptr, int64_t ld_rows = 0, bool *ld_done = nullptr)
 {
+    if (ld_done) *ld_done = false;
     const int mp = m - 1;
     const int64_t N = (int64_t)1 << mp;
     const Plan pl = tuned_plan(LDK_LATTICE, dtype, m, mp, rows);
@@ -369,6 +380,14 @@ int real_apply(int dtype, int mode, int m, int64_t rows, int nrhs, const double 
         b.g = pl.pass[p];
         b.global_tw = p > 0;
         b.scale = 1.0;
+        const int64_t tiles = b.rows << (mp - b.g.a - b.g.logW);
+        if (ld_out && ld_done && !*ld_done && (b.g.a + b.g.logW - b.g.logE) >= 6 && tiles >= ld_rows) {
+            b.ld_part = ld_part;
+            b.ld_out = ld_out;
+            b.ld_rows = ld_rows;
+            b.ld_count = ld_count;
+            *ld_done = true;
+        }
         const int st = launch_pass(LDK_LATTICE, dtype, PM_INV, PIO_SAME,
                                    p == 0 ? PIO_PACKED : PIO_SAME, b, s);
         if (st) return st;
@@ -462,6 +481,21 @@ size_t fit_ws_bytes(int kind, int64_t B, int m, int dtype)
     const size_t wl = ws_bytes(LDK_OP_LOGDET, kind, B, m, dtype);
     if (ws > w) w = ws;
     if (wl > w) w = wl;
+    if (real_path(kind, m) && !fit_fused(kind, m, dtype)) {
+        // the log-det partials of the eigenvalue pass, kept through the solve
+        size_t cbmax = 1;
+        PlanParams cand[16];
+        const int nc = plan_candidates(LDK_LATTICE, LDK_F64, m, cand, 16);
+        for (int i = 0; i < nc; ++i) {
+            const Plan pl = make_plan(m - 1, cand[i].log_tile, cand[i].loge_max);
+            const PassGeom &top = pl.pass[pl.P - 1];
+            const size_t cb = (size_t)1 << (top.b0 - top.logW);
+            if (cb > cbmax) cbmax = cb;
+        }
+        const size_t e = ws_bytes(LDK_OP_EIG, kind, B, m, dtype);
+        const size_t f = align256((size_t)B * cbmax * sizeof(double)) + (e > ws ? e : ws);
+        if (f > w) w = f;
+    }
     return w;
 }
 
@@ -651,6 +685,32 @@ int ldk_fit(int kind, int R, int nrhs, int m, int dtype, const void *k1, double 
             st = launch_fit_net_one(aE, aS, logdet, as_stream(stream));
             if (st != LDK_ENOTSUP) return st;
         }
+    }
+    if (real_path(kind, m) && !fit_fused(kind, m, dtype) && nrhs > 0 && logdet) {
+        // FP32 lattice: the eigenvalue pass leaves the log-det partials, the
+        // solve's first inverse pass sums them (no separate log-det read of
+        // lambda); the partials sit below the passes' own workspace
+        st = ensure_init();
+        if (st) return st;
+        hipStream_t s = as_stream(stream);
+        const Plan pe = tuned_plan(LDK_LATTICE, LDK_F64, m, m - 1, R);
+        const PassGeom &top = pe.pass[pe.P - 1];
+        double *partial = static_cast<double *>(ws);
+        void *rest = static_cast<unsigned char *>(ws) +
+                     align256((size_t)R * ((size_t)1 << (top.b0 - top.logW)) * sizeof(double));
+        int cb = 0;
+        st = real_eig(m, R, k1, dtype == LDK_F32, lam, rest, s, partial, sigma2, &cb);
+        if (st) return st;
+        bool done = false;
+        st = real_apply(dtype, PM_SOLVE, m, (int64_t)R * nrhs, nrhs, lam, sigma2, y, c, rest, s, partial, cb,
+                        logdet, R, &done);
+        if (st) return st;
+        if (!done) {
+            hipLaunchKernelGGL(k_logdet_final, dim3(R), dim3(LOGDET_THREADS), 0, s, (const double *)partial,
+                               cb, logdet);
+            LDK_LAUNCH_CHECK();
+        }
+        return LDK_OK;
     }
     if (!fit_fused(kind, m, dtype) || nrhs == 0) {
         st = ldk_eig(kind, R, m, dtype, k1, lam, ws, stream);
