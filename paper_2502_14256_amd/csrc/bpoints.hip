@@ -49,7 +49,7 @@ constexpr int BP_P = 64;        // points per tile block, one per lane
 constexpr int BP_DCH = 64;      // dimensions per output tile
 
 struct BpArgs {
-    int R, d, flags;
+    int d, flags;
     int64_t n_min, cnt;
     uint32_t lms_off;  // byte offset of lms within its first word
     // per dimension (Halton; Faure uses entry 0 for every dimension), 32-bit
@@ -485,7 +485,6 @@ extern "C" int ldk_gen_bpoints(const ldk_bpointset *ps, int64_t n_min, int64_t n
     if (blocks > 0x7fffffff) return LDK_ENOTSUP;
     const dim3 grid((unsigned)blocks, (unsigned)ps->R);
     BpArgs a{};
-    a.R = ps->R;
     a.d = ps->d;
     a.flags = ps->flags;
     a.n_min = n_min;
