@@ -55,3 +55,21 @@ def test_fit_equals_separate_calls(kind, m, dtype, nrhs):
             assert err <= tol + 2 * pert, (r, err, tol, pert)
     ld_ref = ldk.logdet(lam_ref, s2)
     assert torch.allclose(ld, ld_ref, rtol=1e-13, atol=1e-13 * n, equal_nan=True)
+
+
+@pytest.mark.parametrize("kind,dtype", [("dnet", torch.float64), ("lattice", torch.float32),
+                                        ("lattice", torch.float64)])
+@pytest.mark.parametrize("m", [4, 10, 12, 16])
+def test_fit_without_logdet(kind, dtype, m):
+    # no log-det output (a NULL pointer): the one-launch net fit and the
+    # FP32 lattice fit that carries log-det partials must give the same
+    # eigenvalues and solutions bit for bit as with it
+    R, d, nrhs = 2, 5, 2
+    w = (W.small_lattice if kind == "lattice" else W.small_net)(90 + m, m, d, R, nrhs=nrhs)
+    w.update(alpha=np.full(d, 2, np.int32), gamma=0.7 ** np.arange(1, d + 1), zeta=1.0)
+    k1 = ldk.kernel_column(kernel(w), pointset(w), 0, 2**m, dtype=dtype)
+    y = torch.from_numpy(w["y"][:, :nrhs]).cuda().to(dtype).contiguous()
+    lam, c, ld = ldk.fit(kind, k1, 1e-3, y)
+    lam0, c0, ld0 = ldk.fit(kind, k1, 1e-3, y, logdet=False)
+    assert ld0 is None and ld is not None
+    assert torch.equal(lam0, lam) and torch.equal(c0, c)
