@@ -101,7 +101,7 @@ def parse():
                         "program for rocprofv3 kernel traces and FETCH_SIZE / WRITE_SIZE runs; "
                         "the copy calibrates the counters), then exit")
     p.add_argument("--valu-probe", action="store_true",
-                   help="only run the step, the FP32 gradient step and the RQMC estimates a few "
+                   help="only run the step, the FP32 gradient step, the RQMC estimates and the structure-free generators a few "
                         "times (a short program for rocprofv3 --pmc SQ_INSTS_VALU runs), then exit")
     return p.parse_args()
 
@@ -169,7 +169,8 @@ def main():
         for _ in range(3):
             step()
         grad_bench(2, 1, probe=True)
-        rqmc_bench(2)
+        rqmc_bench(3, probe=True)
+        structure_free_probe()
         torch.cuda.synchronize()
         print(json.dumps({"valu_probe": True}), flush=True)
         return
@@ -717,12 +718,13 @@ def cubature_bench(K, lam, y, w):
             "wce2_equal_weights": float(e2[0, 0].cpu())}
 
 
-def rqmc_bench(K):
+def rqmc_bench(K, probe=False):
     """RQMC estimate + Student-t interval of the corner-peak integrand
     (eq. RQMC), points regenerated in the kernel: the paper's example shape
     (d = 50, n = 2^15, R = 10, order-3 interlaced LMS + shifted net) and a
     throughput shape (d = 50, n = 2^20, R = 16; shifted lattice and LMS net).
-    Cost unit: point coordinates (n d R per estimate)."""
+    Cost unit: point coordinates (n d R per estimate).  probe: K eager calls
+    of each, no graphs and no timing (for counter runs)."""
     import ctypes as C
 
     import numpy as np
@@ -743,8 +745,14 @@ def rqmc_bench(K):
         st = torch.empty(3, dtype=torch.float64, device="cuda")
         ws = torch.empty(max(int(ldk.lib().ldk_rqmc_workspace_bytes(C.byref(ps._c()), n)), 1),
                          dtype=torch.uint8, device="cuda")
-        ms = time_graph(lambda: ldk.rqmc(ps, n, "corner_peak", coef, mu_r=mu_r, stats=st,
-                                         ws=ws), K)
+        def call():
+            ldk.rqmc(ps, n, "corner_peak", coef, mu_r=mu_r, stats=st, ws=ws)
+
+        if probe:
+            for _ in range(K):
+                call()
+            return
+        ms = time_graph(call, K)
         v = st.cpu().tolist()
         res[name] = {"ms": round(ms, 5), "coords_per_s": round(n * d * ps.R / (ms * 1e-3), 1),
                      "mean": v[0], "half_width_99": v[2]}
@@ -813,6 +821,38 @@ def structure_free_bench(K):
     out["workload"] = (f"R={R} randomizations, d={d}, n=2^{m} points each; corner-peak "
                        "integrand of the RQMC example over the generated coordinates")
     return out
+
+
+def structure_free_probe():
+    """The structure-free generators and the RQMC estimate over their
+    coordinates (the shapes of structure_free_bench), three eager calls each
+    and no graphs, for counter runs."""
+    import numpy as np
+    import torch
+
+    import paper_2502_14256_amd as ldk
+    import workloads as W
+
+    R, d, m = 16, 52, 16
+    n = 2**m
+    coef = torch.from_numpy(W.corner_peak_coefficients(d)).cuda()
+    x = torch.empty((R, n, d), dtype=torch.float64, device="cuda")
+    for kind, base in (("halton", 0), ("faure", 53), ("nus", 0)):
+        if kind == "nus":
+            t = W.small_net(31, m, d, 1)
+            ps = ldk.BPointSet("nus", R, d, m=m,
+                               gen=torch.from_numpy(t["gen"].view(np.int64).copy()).cuda(),
+                               seed=torch.from_numpy(W.nus_seeds(31, R, d).view(np.int64)).cuda())
+        else:
+            inp = W.bpoint_inputs(31, kind, R, d, base=base)
+            ps = ldk.BPointSet(kind, R, d, base=base, flags=ldk.BR_LMS | ldk.BR_DP,
+                               **{k: torch.from_numpy(v).cuda() for k, v in inp.items()})
+        ws = torch.empty(max(ldk.lib().ldk_bpoints_workspace_bytes(C_ref(ps)), 256),
+                         dtype=torch.uint8, device="cuda")
+        for _ in range(3):
+            ldk.gen_bpoints(ps, 0, n, out=x, ws=ws)
+            ldk.rqmc_points(x, "corner_peak", coef)
+    torch.cuda.synchronize()
 
 
 def C_ref(ps):
