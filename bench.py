@@ -1083,10 +1083,11 @@ def batch_bench(K, warmup):
 
 
 def solve_rhs_bench(K, lam_lat, w_lat):
-    """Gram solves with cached eigenvalues at n = 2^20 in FP64, one and 16
+    """Gram solves with cached eigenvalues at n = 2^20 in FP64 and FP32
+    (responses, solution and transforms; lambda FP64), one and 16
     right-hand sides, on the lattice workload's eigenvalues and on the net
     workload's (n = 2^20, d = 32, order-4 DSI kernel): solves per second and
-    the fraction of the 8 TB/s HBM peak, with algorithmic bytes 16 n per
+    the fraction of the 8 TB/s HBM peak, with algorithmic bytes 2 s n per
     right-hand side (read y, write c) plus 8 n for lambda, read once."""
     import numpy as np
     import torch
@@ -1109,19 +1110,23 @@ def solve_rhs_bench(K, lam_lat, w_lat):
     res = {}
     for kind, lam, s2 in (("lattice", lam_lat, w_lat["sigma2"]), ("net", lam_net, w3["sigma2"])):
         kd = "lattice" if kind == "lattice" else "dnet"
-        row = {}
-        for nrhs in (1, 16):
-            y = torch.from_numpy(rng.standard_normal((1, nrhs, n))).cuda()
-            c = torch.empty_like(y)
-            ws = ldk._workspace(ldk.OP_SOLVE, ldk._kind(kd), nrhs, w3["m"], ldk.F64, "cuda")
-            ms = time_graph(lambda: ldk.solve(kd, lam, s2, y, out=c, ws=ws), K)
-            alg = (16 * nrhs + 8) * n
-            gbs = alg / (ms * 1e-3) / 1e9
-            row[f"rhs{nrhs}"] = {"ms": round(ms, 5), "solves_per_s": round(nrhs / (ms * 1e-3), 1),
-                                 "GB_s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
-            del y, c, ws
-        res[kind] = row
-    res["bytes"] = "algorithmic: 16 n per right-hand side (read y, write c) + 8 n (lambda, read once)"
+        for dt, sfx in ((torch.float64, ""), (torch.float32, "_f32")):
+            row = {}
+            esz = 8 if dt == torch.float64 else 4
+            for nrhs in (1, 16):
+                y = torch.from_numpy(rng.standard_normal((1, nrhs, n))).cuda().to(dt)
+                c = torch.empty_like(y)
+                ws = ldk._workspace(ldk.OP_SOLVE, ldk._kind(kd), nrhs, w3["m"], ldk._dtype_code(dt),
+                                    "cuda")
+                ms = time_graph(lambda: ldk.solve(kd, lam, s2, y, out=c, ws=ws), K)
+                alg = (2 * esz * nrhs + 8) * n
+                gbs = alg / (ms * 1e-3) / 1e9
+                row[f"rhs{nrhs}"] = {"ms": round(ms, 5), "solves_per_s": round(nrhs / (ms * 1e-3), 1),
+                                     "GB_s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+                del y, c, ws
+            res[kind + sfx] = row
+    res["bytes"] = ("algorithmic: 2 s n per right-hand side (read y, write c; s = 8 FP64, 4 FP32) "
+                    "+ 8 n (lambda, FP64, read once)")
     return res
 
 
