@@ -287,8 +287,8 @@ def main():
                    "traffic": traffic_bytes(STEP_TRAFFIC)}
     ms_per_step = total_ms / K
     solves_per_s = R * K / (total_ms * 1e-3)
-    # the survey's timing protocol: median and minimum over runs of graph
-    # replays, and the fractions against the measured copy rate as well
+    # the median and minimum over runs of graph replays, and the fractions
+    # against a measured device copy rate beside those against 8 TB/s
     copy_gbs = copy_bandwidth(K)
     stats = {"step_ms": time_graph_stats(step, K), "solve_ms": time_graph_stats(op_calls["solve"], K),
              "fit_ms": time_graph_stats(op_calls["fit"], K),
