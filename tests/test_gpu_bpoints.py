@@ -159,3 +159,26 @@ def test_rqmc_points_shapes(orc, integrand, R, n, d):
                                   tau=0.01)
     _check(f"rqmc_points_R{R}_n{n}_d{d}_{integrand}", mu_r.cpu().numpy(), stats.cpu().numpy(), ref, y,
            integrand, c, n)
+
+
+@pytest.mark.parametrize("kind,base", [("halton", 0), ("faure", 53), ("nus", 0)])
+def test_bench_shape_sampled(orc, kind, base):
+    # the benchmark's shape and launch (R = 16, d = 52, the whole window
+    # [0, 2^16) in one call, LMS + digit permutations for Halton and Faure),
+    # rows sampled at the start, across a tile boundary and at the end, each
+    # bit for bit against the oracle's window
+    R, d, m = 16, 52, 16
+    n = 2**m
+    if kind == "nus":
+        t = W.small_net(31, m, d, 1)
+        seed = W.nus_seeds(31, R, d)
+        ps = ldk.BPointSet("nus", R, d, m=m, gen=dev_u64(t["gen"]), seed=dev_u64(seed))
+    else:
+        inp, ps = _bps(kind, R, d, base=base, flags=ldk.BR_LMS | ldk.BR_DP, seed=31)
+    x = ldk.gen_bpoints(ps, 0, n).cpu().numpy()
+    for lo, hi in ((0, 70), (4070, 4170), (n - 90, n)):
+        if kind == "nus":
+            ref = orc.unit_points(orc.nus_points(t["gen"], seed, m, lo, hi))
+        else:
+            ref = orc.bpoints(kind, R, d, lo, hi, base=base, flags=ldk.BR_LMS | ldk.BR_DP, **inp)
+        assert np.array_equal(x[:, lo:hi], ref), (lo, hi)
