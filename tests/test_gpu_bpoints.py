@@ -182,3 +182,17 @@ def test_bench_shape_sampled(orc, kind, base):
         else:
             ref = orc.bpoints(kind, R, d, lo, hi, base=base, flags=ldk.BR_LMS | ldk.BR_DP, **inp)
         assert np.array_equal(x[:, lo:hi], ref), (lo, hi)
+
+
+def test_rqmc_points_bench_shape(orc):
+    # the benchmark's RQMC-over-points shape and launch (R = 16, n = 2^16,
+    # d = 52, 436 MB of coordinates), seeded coordinates in [0, 1)
+    from test_gpu_rqmc import _check
+    R, n, d = 16, 2**16, 52
+    xh = np.random.default_rng(52).random((R, n, d))
+    c = W.corner_peak_coefficients(d)
+    y = orc.genz_corner_peak(xh, c)
+    ref = orc.rqmc(y, tau=0.01)
+    mu_r, stats = ldk.rqmc_points(torch.from_numpy(xh).cuda(), "corner_peak", torch.from_numpy(c).cuda(),
+                                  tau=0.01)
+    _check("rqmc_points_bench_shape", mu_r.cpu().numpy(), stats.cpu().numpy(), ref, y, "corner_peak", c, n)
