@@ -171,26 +171,42 @@ __device__ __forceinline__ void powers(cplx<R> w, cplx<R> (&p)[E])
 // index r = q >> logW and group digit c at axis bit s is multiplied by
 // W_{2^{s+g}}^{(r mod 2^s) R_g(c)}.  For a full group every register of a
 // thread shares r mod 2^s, so the twiddles are the powers of one base
-// W_{2^{s+g}}^{r mod 2^s}.  bases[g] holds that base for every full group
-// g >= 1 of an A-bit axis (group 0 sits at s = 0 and needs none), read once
+// W_{2^{s+g}}^{r mod 2^s}.  Each full group g >= 1 of an A-bit axis has
+// that base (group 0 sits at s = 0 and needs none), read once
 // at kernel start so that the table latency overlaps the data loads instead
 // of stalling each group; apply_group_twiddle multiplies by its powers.
 constexpr int MAX_GROUPS = 4;
+// The bases of groups 1 .. 3, as named fields.  Held in an array indexed by a
+// group number known only at run time, they landed in scratch memory: each
+// base load then waited for its data (and the scratch store) before the
+// tile's own loads were issued, several memory latencies in a row at the
+// start of every complex pass.
+template <typename T>
+struct GroupBases {
+    T b1, b2, b3;
+};
+// The base of group g = 1 .. 3 (a run-time index), chosen among values:
+// selecting among the fields through a reference let the compiler turn the
+// choice back into an address, and the fields went back to scratch memory.
+template <typename T>
+__device__ __forceinline__ T pick_base(int g, T b1, T b2, T b3)
+{
+    return g == 1 ? b1 : (g == 2 ? b2 : b3);
+}
 template <typename R, int LOGE>
-__device__ __forceinline__ void group_bases(cplx<R> (&bases)[MAX_GROUPS], int t, int A, int logW,
-                                            int T_)
+__device__ __forceinline__ void group_bases(GroupBases<cplx<R>> &B, int t, int A, int logW, int T_)
 {
     const int G = (A + LOGE - 1) / LOGE;
     const int rem = A - LOGE * (G - 1);
-#pragma unroll
-    for (int g = 1; g < MAX_GROUPS; ++g) {
-        if (g < G) {
-            const int s = rem + LOGE * (g - 1);
-            const int q0 = group_q(t, 0, LOGE, logW + s, T_);
-            const uint32_t rlow = (uint32_t)(q0 >> logW) & ((1u << s) - 1);
-            bases[g] = tw_small<R>(rlow, s + LOGE);
-        }
-    }
+    auto base = [&](int g) {
+        const int s = rem + LOGE * (g - 1);
+        const int q0 = group_q(t, 0, LOGE, logW + s, T_);
+        const uint32_t rlow = (uint32_t)(q0 >> logW) & ((1u << s) - 1);
+        return tw_small<R>(rlow, s + LOGE);
+    };
+    if (G > 1) B.b1 = base(1);
+    if (G > 2) B.b2 = base(2);
+    if (G > 3) B.b3 = base(3);
 }
 template <typename T, int E, int LOGE, bool CONJ>
 __device__ __forceinline__ void apply_group_twiddle(T (&v)[E], const T &base)

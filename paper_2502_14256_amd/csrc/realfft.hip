@@ -133,7 +133,7 @@ __device__ __forceinline__ void real_top_body(const PassArgs &a, double *lam_out
             v[i] = load_elem<T, LD, SRC_F32>(a.src, row * a.src_row + gidx(t + Tn * i), a.half);
     }
     // twiddle table reads issued right behind the data loads
-    T gb[MAX_GROUPS];
+    GroupBases<T> gb{};
     group_bases<R, LOGE>(gb, t, A, logW, Tn);
     PassTw<R> ptw{};
     if (b0 > 0) ptw = pass_tw_fetch<R, LOGE>(t, (uint64_t)col_of(t & (W - 1)), logW, A, b0);
@@ -185,14 +185,14 @@ __device__ __forceinline__ void real_top_body(const PassArgs &a, double *lam_out
             for (int gi = 0; gi < G - 1; ++gi) {
                 const int gs = gi == 0 ? rem : LOGE;
                 lds_read(v, lds, t, gs, logW + s, Tn);
-                if (gi > 0) apply_group_twiddle<T, E, LOGE, false>(v, gb[gi]);
+                if (gi > 0) apply_group_twiddle<T, E, LOGE, false>(v, pick_base(gi, gb.b1, gb.b2, gb.b3));
                 reg_fwd<T, E, LOGE, false>(v, gs);
                 lds_write(v, lds, t, gs, logW + s, Tn);
                 __syncthreads();
                 s += gs;
             }
             lds_read(v, lds, t, LOGE, logW + top_s, Tn);
-            apply_group_twiddle<T, E, LOGE, false>(v, gb[G - 1]);
+            apply_group_twiddle<T, E, LOGE, false>(v, pick_base(G - 1, gb.b1, gb.b2, gb.b3));
         }
         reg_fwd<T, E, LOGE, false>(v, LOGE);
 
@@ -315,7 +315,7 @@ __device__ __forceinline__ void real_top_body(const PassArgs &a, double *lam_out
     // ---- inverse transform over the axis bits (top group first)
     reg_inv<T, E, LOGE>(v, LOGE);
     if (G > 1) {
-        apply_group_twiddle<T, E, LOGE, true>(v, gb[G - 1]);
+        apply_group_twiddle<T, E, LOGE, true>(v, pick_base(G - 1, gb.b1, gb.b2, gb.b3));
         if constexpr (MODE != PM_ADJ) __syncthreads();  // partner reads are done
         lds_write(v, lds, t, LOGE, logW + top_s, Tn);
         __syncthreads();
@@ -325,7 +325,7 @@ __device__ __forceinline__ void real_top_body(const PassArgs &a, double *lam_out
             s -= gs;
             lds_read(v, lds, t, gs, logW + s, Tn);
             reg_inv<T, E, LOGE>(v, gs);
-            if (gi > 0) apply_group_twiddle<T, E, LOGE, true>(v, gb[gi]);
+            if (gi > 0) apply_group_twiddle<T, E, LOGE, true>(v, pick_base(gi, gb.b1, gb.b2, gb.b3));
             lds_write(v, lds, t, gs, logW + s, Tn);
             __syncthreads();
         }
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(512) void k_fit_top(PassArgs aK, PassArgs aY, doubl
 #pragma unroll
     for (int i = 0; i < E; ++i)
         v[i] = load_elem<T, LD, false>(src, row * src_row + gidx(t + Tn * i), aK.half);
-    T gb[MAX_GROUPS];
+    GroupBases<T> gb{};
     group_bases<R, LOGE>(gb, t, A, logW, Tn);
     PassTw<R> ptw{};
     if (b0 > 0) ptw = pass_tw_fetch<R, LOGE>(t, (uint64_t)col_of(t & (W - 1)), logW, A, b0);
@@ -422,14 +422,14 @@ __global__ __launch_bounds__(512) void k_fit_top(PassArgs aK, PassArgs aY, doubl
         for (int gi = 0; gi < G - 1; ++gi) {
             const int gs = gi == 0 ? rem : LOGE;
             lds_read(v, lds, t, gs, logW + s, Tn);
-            if (gi > 0) apply_group_twiddle<T, E, LOGE, false>(v, gb[gi]);
+            if (gi > 0) apply_group_twiddle<T, E, LOGE, false>(v, pick_base(gi, gb.b1, gb.b2, gb.b3));
             reg_fwd<T, E, LOGE, false>(v, gs);
             lds_write(v, lds, t, gs, logW + s, Tn);
             __syncthreads();
             s += gs;
         }
         lds_read(v, lds, t, LOGE, logW + top_s, Tn);
-        apply_group_twiddle<T, E, LOGE, false>(v, gb[G - 1]);
+        apply_group_twiddle<T, E, LOGE, false>(v, pick_base(G - 1, gb.b1, gb.b2, gb.b3));
     }
     reg_fwd<T, E, LOGE, false>(v, LOGE);
     __syncthreads();  // all forward reads are done
@@ -516,7 +516,7 @@ __global__ __launch_bounds__(512) void k_fit_top(PassArgs aK, PassArgs aY, doubl
 
     // ---- inverse transform over the axis bits (rhs half; both reach the barriers)
     if (G > 1) {
-        if (rhs) apply_group_twiddle<T, E, LOGE, true>(v, gb[G - 1]);
+        if (rhs) apply_group_twiddle<T, E, LOGE, true>(v, pick_base(G - 1, gb.b1, gb.b2, gb.b3));
         __syncthreads();  // the rhs partner reads are done
         if (rhs) lds_write(v, lds, t, LOGE, logW + top_s, Tn);
         __syncthreads();
@@ -527,7 +527,7 @@ __global__ __launch_bounds__(512) void k_fit_top(PassArgs aK, PassArgs aY, doubl
             if (rhs) {
                 lds_read(v, lds, t, gs, logW + s, Tn);
                 reg_inv<T, E, LOGE>(v, gs);
-                if (gi > 0) apply_group_twiddle<T, E, LOGE, true>(v, gb[gi]);
+                if (gi > 0) apply_group_twiddle<T, E, LOGE, true>(v, pick_base(gi, gb.b1, gb.b2, gb.b3));
                 lds_write(v, lds, t, gs, logW + s, Tn);
             }
             __syncthreads();

@@ -56,7 +56,7 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int64_t bid)
     for (int i = 0; i < E; ++i)
         v[i] = load_elem<T, LD, SRC_F32>(a.src, row * a.src_row + gidx(t + Tn * i), a.half);
     // twiddle table reads issued right behind the data loads (one latency)
-    T gb[MAX_GROUPS];
+    GroupBases<T> gb{};
     PassTw<R> ptw{};
     if constexpr (FFT) {
         group_bases<R, LOGE>(gb, t, A, logW, Tn);
@@ -76,14 +76,14 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int64_t bid)
             for (int gidx_ = 0; gidx_ < G - 1; ++gidx_) {
                 const int gs = gidx_ == 0 ? rem : LOGE;
                 lds_read(v, lds, t, gs, logW + s, Tn);
-                if (gidx_ > 0) apply_group_twiddle<T, E, LOGE, false>(v, gb[gidx_]);
+                if (gidx_ > 0) apply_group_twiddle<T, E, LOGE, false>(v, pick_base(gidx_, gb.b1, gb.b2, gb.b3));
                 reg_fwd<T, E, LOGE, false>(v, gs);
                 lds_write(v, lds, t, gs, logW + s, Tn);
                 __syncthreads();
                 s += gs;
             }
             lds_read(v, lds, t, LOGE, logW + top_s, Tn);
-            apply_group_twiddle<T, E, LOGE, false>(v, gb[G - 1]);
+            apply_group_twiddle<T, E, LOGE, false>(v, pick_base(G - 1, gb.b1, gb.b2, gb.b3));
         }
         reg_fwd<T, E, LOGE, false>(v, LOGE);
     }
@@ -101,7 +101,7 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int64_t bid)
     if constexpr (MODE != PM_FWD) {
         reg_inv<T, E, LOGE>(v, LOGE);
         if (G > 1) {
-            apply_group_twiddle<T, E, LOGE, true>(v, gb[G - 1]);
+            apply_group_twiddle<T, E, LOGE, true>(v, pick_base(G - 1, gb.b1, gb.b2, gb.b3));
             if constexpr (MODE != PM_INV) __syncthreads();  // LDS reuse after the forward half
             lds_write(v, lds, t, LOGE, logW + top_s, Tn);
             __syncthreads();
@@ -111,7 +111,7 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int64_t bid)
                 s -= gs;
                 lds_read(v, lds, t, gs, logW + s, Tn);
                 reg_inv<T, E, LOGE>(v, gs);
-                if (gi > 0) apply_group_twiddle<T, E, LOGE, true>(v, gb[gi]);
+                if (gi > 0) apply_group_twiddle<T, E, LOGE, true>(v, pick_base(gi, gb.b1, gb.b2, gb.b3));
                 lds_write(v, lds, t, gs, logW + s, Tn);
                 __syncthreads();
             }
