@@ -55,9 +55,9 @@ TUNED_TABLE = os.path.join(ROOT, "paper_2502_14256_amd", "tuned_mi355x.txt")
 STEP_TRAFFIC = {"read_MiB": 0.15, "write_MiB": 264.00,
                 "sources": ('kcol.hip', 'kfactor.hpp', 'pointset.hpp', 'common.hpp'),
                 "sha1": "0151ebed02b6bdcfccb574a4a06f49f9d26b7863"}
-SOLVE_TRAFFIC = {"read_MiB": 39.10, "write_MiB": 32.06,
+SOLVE_TRAFFIC = {"read_MiB": 34.48, "write_MiB": 24.06,
                  "sources": ('transform.hip', 'realfft.hip', 'passkit.hpp', 'transform.hpp', 'common.hpp'),
-                 "sha1": "d91452e05f6db89e7c8eebe428c61d89042cd7cb"}
+                 "sha1": "407c072aa72e6f5008757b80bc557b3bfee5cb16"}
 
 
 def traffic_bytes(rec):
