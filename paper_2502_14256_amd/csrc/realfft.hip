@@ -91,7 +91,11 @@ __global__ __launch_bounds__(256) void k_filter_coef(const double *__restrict__ 
 // One tile (row, column block cb) of the top pass.  ld_part (PM_FWD only,
 // may be NULL): receives this tile's sum of log(lambda + sigma2) over its 2 S
 // eigenvalues at ld_part[row * cb_count + cb] (NaN if some lambda + s2 <= 0).
-template <typename T, int LOGE, int MODE, int LD, int ST, bool SRC_F32, bool CF = false>
+// CA, CLW >= 0: the axis bits and log2 tile width fixed at compile time (they
+// must equal a.g.a and a.g.logW); the index maps, group loops and twiddle
+// choices then fold to constants.
+template <typename T, int LOGE, int MODE, int LD, int ST, bool SRC_F32, bool CF = false,
+          int CA = -1, int CLW = -1>
 __device__ __forceinline__ void real_top_body(const PassArgs &a, double *lam_out, int64_t row,
                                               int64_t cb, double *ld_part)
 {
@@ -99,7 +103,7 @@ __device__ __forceinline__ void real_top_body(const PassArgs &a, double *lam_out
     constexpr int E = 1 << LOGE;
     T *lds = reinterpret_cast<T *>(g_real_lds);
 
-    const int A = a.g.a, logW = a.g.logW, b0 = a.g.b0;
+    const int A = CA >= 0 ? CA : a.g.a, logW = CLW >= 0 ? CLW : a.g.logW, b0 = a.g.b0;
     const int mp = a.m;  // log2 N
     const int64_t N = (int64_t)1 << mp;
     const int64_t N1 = (int64_t)1 << b0;
@@ -347,16 +351,18 @@ __device__ __forceinline__ void real_top_body(const PassArgs &a, double *lam_out
 // done).  Both halves run the same forward schedule and reach every barrier;
 // the column half idles through the inverse top group.
 //   LDS: [column tile | rhs tile], each S + S/16 elements.
-template <int LOGE, int LD, int ST>
-__global__ __launch_bounds__(512) void k_fit_top(PassArgs aK, PassArgs aY, double *lam_out,
-                                                 double *ld_part)
+// CA, CLW >= 0: the axis bits and log2 tile width fixed at compile time (as
+// for real_top_body).
+template <int LOGE, int LD, int ST, int CA = -1, int CLW = -1>
+__global__ __launch_bounds__(CA >= 0 ? (2 << (CA + CLW - LOGE)) : 512) void k_fit_top(
+    PassArgs aK, PassArgs aY, double *lam_out, double *ld_part)
 {
     using T = cplx<double>;
     using R = double;
     constexpr int E = 1 << LOGE;
     __shared__ double red[8];
 
-    const int A = aK.g.a, logW = aK.g.logW, b0 = aK.g.b0;
+    const int A = CA >= 0 ? CA : aK.g.a, logW = CLW >= 0 ? CLW : aK.g.logW, b0 = aK.g.b0;
     const int mp = aK.m;
     const int64_t N = (int64_t)1 << mp;
     const int64_t N1 = (int64_t)1 << b0;
@@ -419,6 +425,7 @@ __global__ __launch_bounds__(512) void k_fit_top(PassArgs aK, PassArgs aY, doubl
         lds_write(v, lds, t, LOGE, logW + top_s, Tn);
         __syncthreads();
         int s = 0;
+#pragma nounroll
         for (int gi = 0; gi < G - 1; ++gi) {
             const int gs = gi == 0 ? rem : LOGE;
             lds_read(v, lds, t, gs, logW + s, Tn);
@@ -521,6 +528,7 @@ __global__ __launch_bounds__(512) void k_fit_top(PassArgs aK, PassArgs aY, doubl
         if (rhs) lds_write(v, lds, t, LOGE, logW + top_s, Tn);
         __syncthreads();
         int s = top_s;
+#pragma nounroll
         for (int gi = G - 2; gi >= 0; --gi) {
             const int gs = gi == 0 ? rem : LOGE;
             s -= gs;
@@ -554,19 +562,30 @@ int launch_ft(const PassArgs &aK, const PassArgs &aY, double *lam_out, double *l
     if (aK.g.b0 + aK.g.a != aK.m) return LDK_EINVAL;
     if (aK.g.b0 > 0 && aK.g.logW < 1) return LDK_ENOTSUP;
     const size_t lds = 2 * (size_t)(S + (S >> LDS_PAD_SHIFT)) * sizeof(cplx<double>);
+    if constexpr (LOGE == 3 && LD == IO_SAME && ST == IO_SAME) {
+        // the fit's top pass at n = 2^19 .. 2^20 (8 axis bits, 8-column tiles)
+        if (aK.g.a == 8 && aK.g.logW == 3) {
+            hipLaunchKernelGGL((k_fit_top<LOGE, LD, ST, 8, 3>), dim3((unsigned)blocks), dim3(2 * Tn),
+                               lds, s, aK, aY, lam_out, ld_part);
+            LDK_LAUNCH_CHECK();
+            return LDK_OK;
+        }
+    }
     hipLaunchKernelGGL((k_fit_top<LOGE, LD, ST>), dim3((unsigned)blocks), dim3(2 * Tn), lds, s, aK,
                        aY, lam_out, ld_part);
     LDK_LAUNCH_CHECK();
     return LDK_OK;
 }
 
-template <typename T, int LOGE, int MODE, int LD, int ST, bool SRC_F32, bool CF>
-__global__ __launch_bounds__(512) void k_real_top(PassArgs a, double *lam_out, double *ld_part)
+template <typename T, int LOGE, int MODE, int LD, int ST, bool SRC_F32, bool CF, int CA = -1,
+          int CLW = -1>
+__global__ __launch_bounds__(CA >= 0 ? (1 << (CA + CLW - LOGE)) : 512) void k_real_top(
+    PassArgs a, double *lam_out, double *ld_part)
 {
     const int64_t cb_count = ((int64_t)1 << a.g.b0) >> a.g.logW;
     const int64_t bid = xcd_tile(blockIdx.x, gridDim.x);
-    real_top_body<T, LOGE, MODE, LD, ST, SRC_F32, CF>(a, lam_out, bid / cb_count, bid % cb_count,
-                                                      ld_part);
+    real_top_body<T, LOGE, MODE, LD, ST, SRC_F32, CF, CA, CLW>(a, lam_out, bid / cb_count,
+                                                               bid % cb_count, ld_part);
 }
 
 template <typename T, int LOGE, int MODE, int LD, int ST, bool SRC_F32, bool CF = false>
@@ -580,6 +599,16 @@ int launch_rt(const PassArgs &a, double *lam_out, hipStream_t s, double *ld_part
     if (a.g.b0 + a.g.a != a.m) return LDK_EINVAL;  // must be the top pass
     if (a.g.b0 > 0 && a.g.logW < 1) return LDK_ENOTSUP;  // mirror runs need W >= 2
     const size_t lds = (size_t)(S + (S >> LDS_PAD_SHIFT)) * sizeof(T);
+    if constexpr (MODE == PM_SOLVE && LD == IO_SAME && ST == IO_SAME && !SRC_F32 && LOGE == 3) {
+        // the top pass of the plans at n = 2^19 .. 2^20 (8 axis bits, 8-column
+        // tiles): geometry fixed at compile time
+        if (a.g.a == 8 && a.g.logW == 3) {
+            hipLaunchKernelGGL((k_real_top<T, LOGE, MODE, LD, ST, SRC_F32, CF, 8, 3>),
+                               dim3((unsigned)blocks), dim3(threads), lds, s, a, lam_out, ld_part);
+            LDK_LAUNCH_CHECK();
+            return LDK_OK;
+        }
+    }
     hipLaunchKernelGGL((k_real_top<T, LOGE, MODE, LD, ST, SRC_F32, CF>), dim3((unsigned)blocks),
                        dim3(threads), lds, s, a, lam_out, ld_part);
     LDK_LAUNCH_CHECK();

@@ -16,7 +16,10 @@ using namespace kit;
 namespace {
 
 // One pass over a tile: rows = 2^a along the axis, W = 2^logW columns.
-template <typename T, int LOGE, int MODE, int LD, int ST, bool SRC_F32>
+// CA, CLW >= 0: a and logW fixed at compile time (they must equal a.g.a and
+// a.g.logW); the index maps, group loops and twiddle choices then fold to
+// constants.
+template <typename T, int LOGE, int MODE, int LD, int ST, bool SRC_F32, int CA = -1, int CLW = -1>
 __device__ __forceinline__ void pass_body(const PassArgs &a, int64_t bid)
 {
     using R = typename real_of<T>::type;
@@ -24,7 +27,7 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int64_t bid)
     constexpr bool FFT = !std::is_floating_point<T>::value;
     T *lds = reinterpret_cast<T *>(g_pass_lds);
 
-    const int A = a.g.a, logW = a.g.logW, b0 = a.g.b0;
+    const int A = CA >= 0 ? CA : a.g.a, logW = CLW >= 0 ? CLW : a.g.logW, b0 = a.g.b0;
     const int S = 1 << (A + logW);
     const int Tn = S >> LOGE;  // threads
     const int t = threadIdx.x;
@@ -169,19 +172,30 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int64_t bid)
     }
 }
 
-template <typename T, int LOGE, int MODE, int LD, int ST, bool SRC_F32>
-__global__ __launch_bounds__(512) void k_pass(PassArgs a)
+template <typename T, int LOGE, int MODE, int LD, int ST, bool SRC_F32, int CA = -1, int CLW = -1>
+__global__ __launch_bounds__(CA >= 0 ? (1 << (CA + CLW - LOGE)) : 512) void k_pass(PassArgs a)
 {
-    pass_body<T, LOGE, MODE, LD, ST, SRC_F32>(a, xcd_tile(blockIdx.x, gridDim.x));
+    pass_body<T, LOGE, MODE, LD, ST, SRC_F32, CA, CLW>(a, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // Two jobs in one grid: the first nb0 tiles (after the XCD order) are job 0.
-template <typename T, int LOGE, int MODE, int LD, int ST, bool SRC_F32>
-__global__ __launch_bounds__(512) void k_pass2(PassArgs a0, PassArgs a1, int64_t nb0)
+template <typename T, int LOGE, int MODE, int LD, int ST, bool SRC_F32, int CA = -1, int CLW = -1>
+__global__ __launch_bounds__(CA >= 0 ? (1 << (CA + CLW - LOGE)) : 512) void k_pass2(
+    PassArgs a0, PassArgs a1, int64_t nb0)
 {
     const int64_t b = xcd_tile(blockIdx.x, gridDim.x);
-    if (b < nb0) pass_body<T, LOGE, MODE, LD, ST, SRC_F32>(a0, b);
-    else pass_body<T, LOGE, MODE, LD, ST, SRC_F32>(a1, b - nb0);
+    if (b < nb0) pass_body<T, LOGE, MODE, LD, ST, SRC_F32, CA, CLW>(a0, b);
+    else pass_body<T, LOGE, MODE, LD, ST, SRC_F32, CA, CLW>(a1, b - nb0);
+}
+
+// The row passes of the FP64 lattice plans at n = 2^19 .. 2^20 (the packed
+// half-length row, 11 axis bits in one contiguous tile) get kernels with
+// that geometry fixed at compile time.
+constexpr int ROW_A = 11;
+template <typename T, int LOGE, bool SRC_F32>
+constexpr bool row_specialised()
+{
+    return std::is_same<T, cplx<double>>::value && LOGE == 3 && !SRC_F32;
 }
 
 // The fit of a net whose transform is one pass (the whole row in one tile),
@@ -227,6 +241,18 @@ int launch_t(int ld, int st, const PassArgs &a, hipStream_t s)
     if ((a.g.a + LOGE - 1) / LOGE > MAX_GROUPS) return LDK_ENOTSUP;  // group twiddle bases
     const size_t lds = (size_t)(S + (S >> LDS_PAD_SHIFT)) * sizeof(T);
     const dim3 grid((unsigned)blocks), block(threads);
+    if constexpr (row_specialised<T, LOGE, SRC_F32>() && (MODE == PM_FWD || MODE == PM_INV)) {
+        if (a.g.a == ROW_A && a.g.logW == 0) {
+            constexpr int LDs = MODE == PM_FWD ? IO_PACKED : IO_SAME;
+            constexpr int STs = MODE == PM_FWD ? IO_SAME : IO_PACKED;
+            if (ld == LDs && st == STs) {
+                hipLaunchKernelGGL((k_pass<T, LOGE, MODE, LDs, STs, SRC_F32, ROW_A, 0>), grid, block,
+                                   lds, s, a);
+                LDK_LAUNCH_CHECK();
+                return LDK_OK;
+            }
+        }
+    }
 #define LDK_PASS(LD_, ST_) hipLaunchKernelGGL((k_pass<T, LOGE, MODE, LD_, ST_, SRC_F32>), grid, block, lds, s, a)
     if constexpr (std::is_floating_point<T>::value) {
         if (ld != IO_SAME) return LDK_ENOTSUP;
@@ -501,6 +527,14 @@ int launch_fwd2(const PassArgs &a0, const PassArgs &a1, hipStream_t s)
     if (nb0 + nb1 > 0x7fffffff || threads > 512 || threads < 1) return LDK_ENOTSUP;
     if ((a0.g.a + LOGE - 1) / LOGE > MAX_GROUPS) return LDK_ENOTSUP;
     const size_t lds = (size_t)(S + (S >> LDS_PAD_SHIFT)) * sizeof(T);
+    if constexpr (row_specialised<T, LOGE, false>() && LD == IO_PACKED) {
+        if (a0.g.a == ROW_A && a0.g.logW == 0) {
+            hipLaunchKernelGGL((k_pass2<T, LOGE, PM_FWD, LD, IO_SAME, false, ROW_A, 0>),
+                               dim3((unsigned)(nb0 + nb1)), dim3(threads), lds, s, a0, a1, nb0);
+            LDK_LAUNCH_CHECK();
+            return LDK_OK;
+        }
+    }
     hipLaunchKernelGGL((k_pass2<T, LOGE, PM_FWD, LD, IO_SAME, false>), dim3((unsigned)(nb0 + nb1)),
                        dim3(threads), lds, s, a0, a1, nb0);
     LDK_LAUNCH_CHECK();
