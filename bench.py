@@ -55,9 +55,9 @@ TUNED_TABLE = os.path.join(ROOT, "paper_2502_14256_amd", "tuned_mi355x.txt")
 STEP_TRAFFIC = {"read_MiB": 0.15, "write_MiB": 264.00,
                 "sources": ('kcol.hip', 'kfactor.hpp', 'pointset.hpp', 'common.hpp'),
                 "sha1": "0151ebed02b6bdcfccb574a4a06f49f9d26b7863"}
-SOLVE_TRAFFIC = {"read_MiB": 34.48, "write_MiB": 24.06,
+SOLVE_TRAFFIC = {"read_MiB": 34.33, "write_MiB": 24.06,
                  "sources": ('transform.hip', 'realfft.hip', 'passkit.hpp', 'transform.hpp', 'common.hpp'),
-                 "sha1": "407c072aa72e6f5008757b80bc557b3bfee5cb16"}
+                 "sha1": "a307aae1bdd1dba12e5a6be96ef1cfb7b9fe093e"}
 
 
 def traffic_bytes(rec):
@@ -266,13 +266,22 @@ def main():
                     "GB_s": round(alg[op] / (per_op[op] * 1e-3) / 1e9, 1),
                     "hbm_frac": round(alg[op] / (per_op[op] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
                for op in ops}
+    # the median and minimum over runs of graph replays, and the fractions
+    # against a measured device copy rate beside those against 8 TB/s
+    copy_gbs = copy_bandwidth(K)
+    stats = {"step_ms": time_graph_stats(step, K), "solve_ms": time_graph_stats(op_calls["solve"], K),
+             "fit_ms": time_graph_stats(op_calls["fit"], K),
+             "copy_GB_s": copy_gbs,
+             "note": "each: 5 runs of K graph replays after 3 warm-up replays; median and min of the "
+                     "per-run means; copy_GB_s: a 256 MiB device copy (bytes read + written)"}
     # The headline roofline is the Gram solve with cached eigenvalues (the
     # target of the metric): read y and lambda, write c, 24 MiB at n = 2^20
     # in FP64, over the three kernels of one ldk_solve (row pass, top pass
-    # with the filter, inverse row pass), each captured alone in a graph and
-    # replayed K times.  The step's longest single kernel is the point
-    # writer (points + first column), reported separately.
-    t_solve = unfused["solve"]
+    # with the filter, inverse row pass), captured alone in a graph: the
+    # average launch over 5 runs of K replays (the mean of stats["solve_ms"]).
+    # The step's longest single kernel is the point writer (points + first
+    # column), reported separately.
+    t_solve = stats["solve_ms"]["mean"]
     roof_dom = {"kernel": "ldk_solve, lattice n=2^20 FP64, 1 RHS, cached lambda (3 kernels: "
                           "row pass, top pass with the filter, inverse row pass)",
                 "bound": "hbm",
@@ -287,14 +296,6 @@ def main():
                    "traffic": traffic_bytes(STEP_TRAFFIC)}
     ms_per_step = total_ms / K
     solves_per_s = R * K / (total_ms * 1e-3)
-    # the median and minimum over runs of graph replays, and the fractions
-    # against a measured device copy rate beside those against 8 TB/s
-    copy_gbs = copy_bandwidth(K)
-    stats = {"step_ms": time_graph_stats(step, K), "solve_ms": time_graph_stats(op_calls["solve"], K),
-             "fit_ms": time_graph_stats(op_calls["fit"], K),
-             "copy_GB_s": copy_gbs,
-             "note": "each: 5 runs of K graph replays after 3 warm-up replays; median and min of the "
-                     "per-run means; copy_GB_s: a 256 MiB device copy (bytes read + written)"}
     for r_ in (roof_dom, roof_points):
         r_["copy_GB_s"] = copy_gbs
         r_["frac_of_copy"] = round(r_["achieved"] / copy_gbs, 4)
@@ -323,7 +324,7 @@ def main():
                          "frac": op_rows["fit"]["hbm_frac"], "copy_GB_s": copy_gbs,
                          "frac_of_copy": round(op_rows["fit"]["GB_s"] / copy_gbs, 4)},
         "timing_stats": stats,
-        "solves_per_s_cached_lambda": round(1e3 / unfused["solve"], 1),
+        "solves_per_s_cached_lambda": round(1e3 / t_solve, 1),
         "ops": op_rows,
         "unfused_ms": unfused,
         "timing": "value and ms_per_step: K replays of one HIP-graph-captured step; ops: each "
@@ -422,8 +423,9 @@ def with_engine(engine, fn):
 
 
 def time_graph(fn, K):
-    """Average device ms per launch of fn: captured once in a HIP graph, the
-    graph replayed K times between two events on the capture stream."""
+    """Average device ms per launch of fn: captured once in a HIP graph, three
+    warm-up replays, then the graph replayed K times between two events on
+    the capture stream."""
     import torch
 
     fn()
@@ -431,7 +433,8 @@ def time_graph(fn, K):
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
         fn()
-    g.replay()
+    for _ in range(3):
+        g.replay()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     a = torch.cuda.Event(enable_timing=True)
