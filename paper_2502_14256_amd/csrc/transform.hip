@@ -188,14 +188,23 @@ __global__ __launch_bounds__(CA >= 0 ? (1 << (CA + CLW - LOGE)) : 512) void k_pa
     else pass_body<T, LOGE, MODE, LD, ST, SRC_F32, CA, CLW>(a1, b - nb0);
 }
 
-// The row passes of the FP64 lattice plans at n = 2^19 .. 2^20 (the packed
-// half-length row, 11 axis bits in one contiguous tile) get kernels with
-// that geometry fixed at compile time.
+// The passes of the plans at n = 2^20 get kernels with their geometry
+// fixed at compile time: the FP64 lattice row passes (the packed
+// half-length row, 11 axis bits in one contiguous tile; also the row pass of
+// every FP64 lattice plan from n = 2^13), and the digital-net passes (FP64
+// and FP32: 12 row bits, and the top pass with the filter over 8 bits in
+// 16-column tiles).
 constexpr int ROW_A = 11;
 template <typename T, int LOGE, bool SRC_F32>
 constexpr bool row_specialised()
 {
     return std::is_same<T, cplx<double>>::value && LOGE == 3 && !SRC_F32;
+}
+constexpr int NET_ROW_A = 12, NET_TOP_A = 8, NET_TOP_LOGW = 4;
+template <typename T, int LOGE, bool SRC_F32>
+constexpr bool net_specialised()
+{
+    return std::is_floating_point<T>::value && LOGE == 3 && !SRC_F32;
 }
 
 // The fit of a net whose transform is one pass (the whole row in one tile),
@@ -241,6 +250,23 @@ int launch_t(int ld, int st, const PassArgs &a, hipStream_t s)
     if ((a.g.a + LOGE - 1) / LOGE > MAX_GROUPS) return LDK_ENOTSUP;  // group twiddle bases
     const size_t lds = (size_t)(S + (S >> LDS_PAD_SHIFT)) * sizeof(T);
     const dim3 grid((unsigned)blocks), block(threads);
+    if constexpr (net_specialised<T, LOGE, SRC_F32>() && (MODE == PM_FWD || MODE == PM_INV)) {
+        if (ld == IO_SAME && st == IO_SAME && a.g.a == NET_ROW_A && a.g.logW == 0) {
+            hipLaunchKernelGGL((k_pass<T, LOGE, MODE, IO_SAME, IO_SAME, SRC_F32, NET_ROW_A, 0>), grid,
+                               block, lds, s, a);
+            LDK_LAUNCH_CHECK();
+            return LDK_OK;
+        }
+    }
+    if constexpr (net_specialised<T, LOGE, SRC_F32>() && MODE == PM_SOLVE) {
+        if (ld == IO_SAME && st == IO_SAME && a.g.a == NET_TOP_A && a.g.logW == NET_TOP_LOGW) {
+            hipLaunchKernelGGL(
+                (k_pass<T, LOGE, MODE, IO_SAME, IO_SAME, SRC_F32, NET_TOP_A, NET_TOP_LOGW>), grid,
+                block, lds, s, a);
+            LDK_LAUNCH_CHECK();
+            return LDK_OK;
+        }
+    }
     if constexpr (row_specialised<T, LOGE, SRC_F32>() && (MODE == PM_FWD || MODE == PM_INV)) {
         if (a.g.a == ROW_A && a.g.logW == 0) {
             constexpr int LDs = MODE == PM_FWD ? IO_PACKED : IO_SAME;
