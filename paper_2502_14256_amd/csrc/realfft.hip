@@ -189,7 +189,10 @@ __device__ __forceinline__ void real_top_body(const PassArgs &a, double *lam_out
             for (int gi = 0; gi < G - 1; ++gi) {
                 const int gs = gi == 0 ? rem : LOGE;
                 lds_read(v, lds, t, gs, logW + s, Tn);
-                if (gi > 0) apply_group_twiddle<T, E, LOGE, false>(v, pick_base(gi, gb.b1, gb.b2, gb.b3));
+                if (gi > 0) {
+                    const auto gbase = pick_base(gi, gb.b1, gb.b2, gb.b3);
+                    apply_group_twiddle<T, E, LOGE, false>(v, gbase);
+                }
                 reg_fwd<T, E, LOGE, false>(v, gs);
                 lds_write(v, lds, t, gs, logW + s, Tn);
                 __syncthreads();
@@ -329,7 +332,10 @@ __device__ __forceinline__ void real_top_body(const PassArgs &a, double *lam_out
             s -= gs;
             lds_read(v, lds, t, gs, logW + s, Tn);
             reg_inv<T, E, LOGE>(v, gs);
-            if (gi > 0) apply_group_twiddle<T, E, LOGE, true>(v, pick_base(gi, gb.b1, gb.b2, gb.b3));
+            if (gi > 0) {
+                const auto gbase = pick_base(gi, gb.b1, gb.b2, gb.b3);
+                apply_group_twiddle<T, E, LOGE, true>(v, gbase);
+            }
             lds_write(v, lds, t, gs, logW + s, Tn);
             __syncthreads();
         }
@@ -425,11 +431,17 @@ __global__ __launch_bounds__(CA >= 0 ? (2 << (CA + CLW - LOGE)) : 512) void k_fi
         lds_write(v, lds, t, LOGE, logW + top_s, Tn);
         __syncthreads();
         int s = 0;
+        // kept rolled: unrolled with the geometry fixed at compile time, the
+        // 512-thread workgroup's 256 registers per wave no longer hold the
+        // hoisted twiddle products and the kernel spills
 #pragma nounroll
         for (int gi = 0; gi < G - 1; ++gi) {
             const int gs = gi == 0 ? rem : LOGE;
             lds_read(v, lds, t, gs, logW + s, Tn);
-            if (gi > 0) apply_group_twiddle<T, E, LOGE, false>(v, pick_base(gi, gb.b1, gb.b2, gb.b3));
+            if (gi > 0) {
+                const auto gbase = pick_base(gi, gb.b1, gb.b2, gb.b3);
+                apply_group_twiddle<T, E, LOGE, false>(v, gbase);
+            }
             reg_fwd<T, E, LOGE, false>(v, gs);
             lds_write(v, lds, t, gs, logW + s, Tn);
             __syncthreads();
@@ -528,14 +540,17 @@ __global__ __launch_bounds__(CA >= 0 ? (2 << (CA + CLW - LOGE)) : 512) void k_fi
         if (rhs) lds_write(v, lds, t, LOGE, logW + top_s, Tn);
         __syncthreads();
         int s = top_s;
-#pragma nounroll
+#pragma nounroll  // (as the forward groups)
         for (int gi = G - 2; gi >= 0; --gi) {
             const int gs = gi == 0 ? rem : LOGE;
             s -= gs;
             if (rhs) {
                 lds_read(v, lds, t, gs, logW + s, Tn);
                 reg_inv<T, E, LOGE>(v, gs);
-                if (gi > 0) apply_group_twiddle<T, E, LOGE, true>(v, pick_base(gi, gb.b1, gb.b2, gb.b3));
+                if (gi > 0) {
+                    const auto gbase = pick_base(gi, gb.b1, gb.b2, gb.b3);
+                    apply_group_twiddle<T, E, LOGE, true>(v, gbase);
+                }
                 lds_write(v, lds, t, gs, logW + s, Tn);
             }
             __syncthreads();

@@ -79,7 +79,10 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int64_t bid)
             for (int gidx_ = 0; gidx_ < G - 1; ++gidx_) {
                 const int gs = gidx_ == 0 ? rem : LOGE;
                 lds_read(v, lds, t, gs, logW + s, Tn);
-                if (gidx_ > 0) apply_group_twiddle<T, E, LOGE, false>(v, pick_base(gidx_, gb.b1, gb.b2, gb.b3));
+                if (gidx_ > 0) {
+                    const auto gbase = pick_base(gidx_, gb.b1, gb.b2, gb.b3);
+                    apply_group_twiddle<T, E, LOGE, false>(v, gbase);
+                }
                 reg_fwd<T, E, LOGE, false>(v, gs);
                 lds_write(v, lds, t, gs, logW + s, Tn);
                 __syncthreads();
@@ -114,7 +117,10 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int64_t bid)
                 s -= gs;
                 lds_read(v, lds, t, gs, logW + s, Tn);
                 reg_inv<T, E, LOGE>(v, gs);
-                if (gi > 0) apply_group_twiddle<T, E, LOGE, true>(v, pick_base(gi, gb.b1, gb.b2, gb.b3));
+                if (gi > 0) {
+                    const auto gbase = pick_base(gi, gb.b1, gb.b2, gb.b3);
+                    apply_group_twiddle<T, E, LOGE, true>(v, gbase);
+                }
                 lds_write(v, lds, t, gs, logW + s, Tn);
                 __syncthreads();
             }
