@@ -195,16 +195,20 @@ __global__ __launch_bounds__(CA >= 0 ? (1 << (CA + CLW - LOGE)) : 512) void k_pa
 }
 
 // The passes of the plans at n = 2^20 get kernels with their geometry
-// fixed at compile time: the FP64 lattice row passes (the packed
-// half-length row, 11 axis bits in one contiguous tile; also the row pass of
-// every FP64 lattice plan from n = 2^13), and the digital-net passes (FP64
-// and FP32: 12 row bits, and the top pass with the filter over 8 bits in
-// 16-column tiles).
-constexpr int ROW_A = 11;
+// fixed at compile time: the lattice row passes (the packed half-length row
+// in one contiguous tile: 11 axis bits in FP64, also the row pass of every
+// FP64 lattice plan from n = 2^13; 12 in FP32), and the digital-net passes
+// (FP64 and FP32: 12 row bits, and the top pass with the filter over 8 bits
+// in 16-column tiles).
+template <typename T>
+constexpr int row_a()
+{
+    return std::is_same<T, cplx<double>>::value ? 11 : 12;
+}
 template <typename T, int LOGE, bool SRC_F32>
 constexpr bool row_specialised()
 {
-    return std::is_same<T, cplx<double>>::value && LOGE == 3 && !SRC_F32;
+    return !std::is_floating_point<T>::value && LOGE == 3 && !SRC_F32;
 }
 constexpr int NET_ROW_A = 12, NET_TOP_A = 8, NET_TOP_LOGW = 4;
 template <typename T, int LOGE, bool SRC_F32>
@@ -274,11 +278,12 @@ int launch_t(int ld, int st, const PassArgs &a, hipStream_t s)
         }
     }
     if constexpr (row_specialised<T, LOGE, SRC_F32>() && (MODE == PM_FWD || MODE == PM_INV)) {
-        if (a.g.a == ROW_A && a.g.logW == 0) {
+        constexpr int RA = row_a<T>();
+        if (a.g.a == RA && a.g.logW == 0) {
             constexpr int LDs = MODE == PM_FWD ? IO_PACKED : IO_SAME;
             constexpr int STs = MODE == PM_FWD ? IO_SAME : IO_PACKED;
             if (ld == LDs && st == STs) {
-                hipLaunchKernelGGL((k_pass<T, LOGE, MODE, LDs, STs, SRC_F32, ROW_A, 0>), grid, block,
+                hipLaunchKernelGGL((k_pass<T, LOGE, MODE, LDs, STs, SRC_F32, RA, 0>), grid, block,
                                    lds, s, a);
                 LDK_LAUNCH_CHECK();
                 return LDK_OK;
@@ -560,8 +565,9 @@ int launch_fwd2(const PassArgs &a0, const PassArgs &a1, hipStream_t s)
     if ((a0.g.a + LOGE - 1) / LOGE > MAX_GROUPS) return LDK_ENOTSUP;
     const size_t lds = (size_t)(S + (S >> LDS_PAD_SHIFT)) * sizeof(T);
     if constexpr (row_specialised<T, LOGE, false>() && LD == IO_PACKED) {
-        if (a0.g.a == ROW_A && a0.g.logW == 0) {
-            hipLaunchKernelGGL((k_pass2<T, LOGE, PM_FWD, LD, IO_SAME, false, ROW_A, 0>),
+        constexpr int RA = row_a<T>();
+        if (a0.g.a == RA && a0.g.logW == 0) {
+            hipLaunchKernelGGL((k_pass2<T, LOGE, PM_FWD, LD, IO_SAME, false, RA, 0>),
                                dim3((unsigned)(nb0 + nb1)), dim3(threads), lds, s, a0, a1, nb0);
             LDK_LAUNCH_CHECK();
             return LDK_OK;
