@@ -614,10 +614,11 @@ int launch_rt(const PassArgs &a, double *lam_out, hipStream_t s, double *ld_part
     if (a.g.b0 + a.g.a != a.m) return LDK_EINVAL;  // must be the top pass
     if (a.g.b0 > 0 && a.g.logW < 1) return LDK_ENOTSUP;  // mirror runs need W >= 2
     const size_t lds = (size_t)(S + (S >> LDS_PAD_SHIFT)) * sizeof(T);
-    if constexpr (MODE == PM_SOLVE && LD == IO_SAME && ST == IO_SAME && !SRC_F32 && LOGE == 3) {
-        // the top pass of the plans at n = 2^20 (FP64: 8 axis bits, 8-column
-        // tiles; FP32: 7 axis bits, 32-column tiles): geometry fixed at compile
-        // time
+    if constexpr ((MODE == PM_SOLVE || (MODE == PM_FWD && !CF)) && LD == IO_SAME && ST == IO_SAME &&
+                  !SRC_F32 && LOGE == 3) {
+        // the solve's and the eigenvalues' top pass of the plans at n = 2^20
+        // (FP64: 8 axis bits, 8-column tiles; FP32: 7 axis bits, 32-column
+        // tiles): geometry fixed at compile time
         constexpr bool F64 = std::is_same<T, cplx<double>>::value;
         constexpr int TA = F64 ? 8 : 7, TLW = F64 ? 3 : 5;
         if (a.g.a == TA && a.g.logW == TLW) {
