@@ -148,9 +148,12 @@ def test_transform(orc, kind, m, dtype):
 # a4-a6: eig, solve, matvec, logdet on shared inputs
 # ---------------------------------------------------------------------------
 # lattice rows run as packed half-length complex rows: m = 2, 3 (one pass of
-# n/2), 12 / 13 (one or two passes of n/2 in FP64 / FP32), 21 (three passes)
+# n/2), 12 / 13 (one or two passes of n/2 in FP64 / FP32), 21 (three passes);
+# at m = 20 the passes run the kernels with their tile geometry fixed at
+# compile time, the top pass forming the filter itself (one RHS) or reading
+# precomputed coefficients (two RHS)
 ALG_CASES = [(0, 3), (1, 2), (2, 3), (3, 4), (6, 3), (10, 2), (11, 3), (12, 1), (13, 2),
-             (14, 2), (16, 1), (19, 1), (20, 1), (21, 1)]
+             (14, 2), (16, 1), (19, 1), (20, 1), (20, 2), (21, 1)]
 
 
 def _kcol(orc, w):
