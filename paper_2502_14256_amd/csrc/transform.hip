@@ -18,10 +18,15 @@ namespace {
 // One pass over a tile: rows = 2^a along the axis, W = 2^logW columns.
 // CA, CLW >= 0: a and logW fixed at compile time (they must equal a.g.a and
 // a.g.logW); the index maps, group loops and twiddle choices then fold to
-// constants.
-template <typename T, int LOGE, int MODE, int LD, int ST, bool SRC_F32, int CA = -1, int CLW = -1>
-__device__ __forceinline__ void pass_body(const PassArgs &a, int64_t bid)
+// constants.  REGLAM (real rows only): the E values a thread stores at tile
+// positions t + Tn i go to regl[i] too (PM_FWD), or the filter takes its
+// eigenvalues from regl[i] instead of a.lam (PM_SOLVE / PM_MATVEC) -- the
+// same elements, when both passes have the same geometry.
+template <typename T, int LOGE, int MODE, int LD, int ST, bool SRC_F32, int CA = -1, int CLW = -1,
+          bool REGLAM = false>
+__device__ __forceinline__ void pass_body(const PassArgs &a, int64_t bid, double *regl = nullptr)
 {
+    static_assert(!REGLAM || std::is_floating_point<T>::value, "eigenvalues in registers: real rows");
     using R = typename real_of<T>::type;
     constexpr int E = 1 << LOGE;
     constexpr bool FFT = !std::is_floating_point<T>::value;
@@ -98,7 +103,7 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int64_t bid)
         const double *lam = a.lam + (row / a.nrhs) * ((int64_t)1 << a.m);
 #pragma unroll
         for (int i = 0; i < E; ++i) {
-            const double l = lam[gidx(t + Tn * i)];
+            const double l = REGLAM ? regl[i] : lam[gidx(t + Tn * i)];
             const double f = MODE == PM_SOLVE ? a.scale / (l + a.sigma2) : a.scale * l;
             v[i] = scl(v[i], (R)f);
         }
@@ -137,6 +142,7 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int64_t bid)
     for (int i = 0; i < E; ++i) {
         T o = v[i];
         if (MODE == PM_FWD || MODE == PM_INV) o = scl(o, sc);
+        if constexpr (REGLAM && MODE == PM_FWD) regl[i] = (double)o;
         if constexpr (ST == IO_COMBINE) {
             // the doubling update: the new half's transform o meets the old
             // half's at k (Sec. 5.4, eq. ft_next_parts)
@@ -221,25 +227,32 @@ constexpr bool net_specialised()
 // FP64: workgroup r runs replication r's eigenvalue tile, then its
 // right-hand sides' solve tiles, with the pass bodies and arguments of
 // ldk_eig and ldk_solve (so lambda and c are theirs bit for bit; the solve
-// reads the eigenvalues this workgroup has just stored), then the log-det
-// of the row: per-thread products of the values (LogProd) and a
+// takes the eigenvalues this workgroup has just computed from registers),
+// then the log-det of the row: per-thread products of the values (LogProd,
+// each thread's values in the order of ldk_logdet's partial loop) and a
 // fixed-order tree.
 template <int LOGE>
 __global__ __launch_bounds__(512) void k_fit_net_one(PassArgs aE, PassArgs aS, double *logdet)
 {
     const int64_t r = blockIdx.x;
-    pass_body<double, LOGE, PM_FWD, IO_SAME, IO_SAME, false>(aE, r);
-    __syncthreads();  // the row's eigenvalues are stored (and visible to the workgroup)
+    // thread t keeps the eigenvalues at positions t + T i of the row (the
+    // tile is the whole row, and the solve tiles have the same geometry):
+    // the solves and the log-det take them from registers, not back from
+    // memory
+    constexpr int E = 1 << LOGE;
+    double lam_t[E];
+    pass_body<double, LOGE, PM_FWD, IO_SAME, IO_SAME, false, -1, -1, true>(aE, r, lam_t);
+    __syncthreads();  // the LDS is free for the solve tiles
     for (int q = 0; q < aS.nrhs; ++q) {
-        pass_body<double, LOGE, PM_SOLVE, IO_SAME, IO_SAME, false>(aS, r * aS.nrhs + q);
+        pass_body<double, LOGE, PM_SOLVE, IO_SAME, IO_SAME, false, -1, -1, true>(
+            aS, r * aS.nrhs + q, lam_t);
         __syncthreads();  // the LDS is free for the next tile
     }
     if (!logdet) return;
-    const int64_t n = (int64_t)1 << aE.m;
-    const double *lam = static_cast<const double *>(aE.dst) + r * n;
     const int t = threadIdx.x, T = blockDim.x;
     LogProd acc;
-    for (int64_t k = t; k < n; k += T) acc.add(lam[k] + aS.sigma2);
+#pragma unroll
+    for (int i = 0; i < E; ++i) acc.add(lam_t[i] + aS.sigma2);
     double *red = reinterpret_cast<double *>(g_pass_lds);
     red[t] = acc.value();
     __syncthreads();
