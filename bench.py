@@ -57,7 +57,7 @@ STEP_TRAFFIC = {"read_MiB": 0.15, "write_MiB": 264.00,
                 "sha1": "0151ebed02b6bdcfccb574a4a06f49f9d26b7863"}
 SOLVE_TRAFFIC = {"read_MiB": 34.33, "write_MiB": 24.06,
                  "sources": ('transform.hip', 'realfft.hip', 'passkit.hpp', 'transform.hpp', 'common.hpp'),
-                 "sha1": "1b8173eed0cef6a0dcd3e3eb7952e031bf5a292c"}
+                 "sha1": "a4dac344348027eea527a83dcc7b69db19496155"}
 
 
 def traffic_bytes(rec):
