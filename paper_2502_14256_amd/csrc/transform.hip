@@ -214,7 +214,9 @@ constexpr int row_a()
 template <typename T, int LOGE, bool SRC_F32>
 constexpr bool row_specialised()
 {
-    return !std::is_floating_point<T>::value && LOGE == 3 && !SRC_F32;
+    // float sources: the FP64 eigenvalue transform of an FP32 column
+    return !std::is_floating_point<T>::value && LOGE == 3 &&
+           (!SRC_F32 || std::is_same<T, cplx<double>>::value);
 }
 constexpr int NET_ROW_A = 12, NET_TOP_A = 8, NET_TOP_LOGW = 4;
 template <typename T, int LOGE, bool SRC_F32>
