@@ -592,15 +592,24 @@ int launch_ft(const PassArgs &aK, const PassArgs &aY, double *lam_out, double *l
     return LDK_OK;
 }
 
+// NR > 1 (with precomputed coefficients, nrhs a multiple of NR): a block
+// runs the same tile of NR consecutive rows, which share an eigenvalue row,
+// one after the other, so the later rows read the tile's coefficients from
+// the L2 lines the first one brought in.
 template <typename T, int LOGE, int MODE, int LD, int ST, bool SRC_F32, bool CF, int CA = -1,
-          int CLW = -1>
+          int CLW = -1, int NR = 1>
 __global__ __launch_bounds__(CA >= 0 ? (1 << (CA + CLW - LOGE)) : 512) void k_real_top(
     PassArgs a, double *lam_out, double *ld_part)
 {
     const int64_t cb_count = ((int64_t)1 << a.g.b0) >> a.g.logW;
     const int64_t bid = xcd_tile(blockIdx.x, gridDim.x);
-    real_top_body<T, LOGE, MODE, LD, ST, SRC_F32, CF, CA, CLW>(a, lam_out, bid / cb_count,
-                                                               bid % cb_count, ld_part);
+    const int64_t row0 = (bid / cb_count) * NR, cb = bid % cb_count;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        if (q > 0) __syncthreads();  // the tile's LDS is free again
+        real_top_body<T, LOGE, MODE, LD, ST, SRC_F32, CF, CA, CLW>(a, lam_out, row0 + q, cb,
+                                                                   ld_part);
+    }
 }
 
 template <typename T, int LOGE, int MODE, int LD, int ST, bool SRC_F32, bool CF = false>
@@ -622,8 +631,18 @@ int launch_rt(const PassArgs &a, double *lam_out, hipStream_t s, double *ld_part
         constexpr bool F64 = std::is_same<T, cplx<double>>::value;
         constexpr int TA = F64 ? 8 : 7, TLW = F64 ? 3 : 5;
         if (a.g.a == TA && a.g.logW == TLW) {
-            hipLaunchKernelGGL((k_real_top<T, LOGE, MODE, LD, ST, SRC_F32, CF, TA, TLW>),
-                               dim3((unsigned)blocks), dim3(threads), lds, s, a, lam_out, ld_part);
+            bool pair = false;
+            if constexpr (CF) pair = a.nrhs % 2 == 0;
+            if constexpr (CF) {
+                if (pair)
+                    hipLaunchKernelGGL((k_real_top<T, LOGE, MODE, LD, ST, SRC_F32, CF, TA, TLW, 2>),
+                                       dim3((unsigned)(blocks / 2)), dim3(threads), lds, s, a,
+                                       lam_out, ld_part);
+            }
+            if (!pair)
+                hipLaunchKernelGGL((k_real_top<T, LOGE, MODE, LD, ST, SRC_F32, CF, TA, TLW>),
+                                   dim3((unsigned)blocks), dim3(threads), lds, s, a, lam_out,
+                                   ld_part);
             LDK_LAUNCH_CHECK();
             return LDK_OK;
         }
