@@ -55,9 +55,9 @@ TUNED_TABLE = os.path.join(ROOT, "paper_2502_14256_amd", "tuned_mi355x.txt")
 STEP_TRAFFIC = {"read_MiB": 0.15, "write_MiB": 264.00,
                 "sources": ('kcol.hip', 'kfactor.hpp', 'pointset.hpp', 'common.hpp'),
                 "sha1": "0151ebed02b6bdcfccb574a4a06f49f9d26b7863"}
-SOLVE_TRAFFIC = {"read_MiB": 34.36, "write_MiB": 24.06,
+SOLVE_TRAFFIC = {"read_MiB": 34.33, "write_MiB": 24.06,
                  "sources": ('transform.hip', 'realfft.hip', 'passkit.hpp', 'transform.hpp', 'common.hpp'),
-                 "sha1": "7a001833dc2c41158755baedb9773717e307a3ff"}
+                 "sha1": "ef2fd51aed0b23c8e166cde8b2a124cbd6c938a5"}
 
 
 def traffic_bytes(rec):
