@@ -115,9 +115,9 @@ __global__ __launch_bounds__(KC_THREADS) void k_points_kcol_lattice(KcolArgs a, 
         return;
     }
     const int64_t q = b - upto;
-    gen_lattice_block(a.ps, a.n_min, a.n_max, g.P, g.pairs != 0, pts, q % g.tiles,
-                      (int)((q / g.tiles) % g.chunks), (int)(q / (g.tiles * g.chunks)),
-                      threadIdx.x);
+    gen_lattice_block<ORDER>(a.ps, a.n_min, a.n_max, g.P, g.pairs != 0, pts, q % g.tiles,
+                             (int)((q / g.tiles) % g.chunks), (int)(q / (g.tiles * g.chunks)),
+                             threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------

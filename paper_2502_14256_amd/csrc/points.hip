@@ -39,12 +39,13 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_net(PointsetArgs a, int64_t
                   threadIdx.x, L);
 }
 
+template <int ORDER>
 __global__ __launch_bounds__(GEN_THREADS) void k_gen_lattice(PointsetArgs a, int64_t n_min,
                                                              int64_t n_max, int P, int pairs,
                                                              uint64_t *__restrict__ out)
 {
-    gen_lattice_block(a, n_min, n_max, P, pairs != 0, out, blockIdx.x, blockIdx.y, blockIdx.z,
-                      threadIdx.x);
+    gen_lattice_block<ORDER>(a, n_min, n_max, P, pairs != 0, out, blockIdx.x, blockIdx.y,
+                             blockIdx.z, threadIdx.x);
 }
 
 // Interlaced, scrambled generating columns of a higher-order net (see
@@ -122,9 +123,12 @@ extern "C" int ldk_gen_points(const ldk_pointset *ps, int64_t n_min, int64_t n_m
     const GenGrid g = gen_grid(a, n_min, n_max, out);
     if (g.tiles > 0x7fffffff) return LDK_ENOTSUP;
     dim3 grid((unsigned)g.tiles, (unsigned)g.chunks, (unsigned)g.R);
-    if (a.kind == LDK_LATTICE)
-        hipLaunchKernelGGL(k_gen_lattice, grid, dim3(GEN_THREADS), 0, as_stream(stream), a, n_min,
-                           n_max, g.P, g.pairs, out);
+    if (a.kind == LDK_LATTICE && a.order == LDK_LINEAR)
+        hipLaunchKernelGGL(k_gen_lattice<LDK_LINEAR>, grid, dim3(GEN_THREADS), 0,
+                           as_stream(stream), a, n_min, n_max, g.P, g.pairs, out);
+    else if (a.kind == LDK_LATTICE)
+        hipLaunchKernelGGL(k_gen_lattice<LDK_NATURAL>, grid, dim3(GEN_THREADS), 0,
+                           as_stream(stream), a, n_min, n_max, g.P, g.pairs, out);
     else
         hipLaunchKernelGGL(k_gen_net, grid, dim3(GEN_THREADS), 0, as_stream(stream), a, n_min,
                            n_max, g.tile_base, g.P, g.logP, g.pairs, out);

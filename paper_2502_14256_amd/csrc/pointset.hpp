@@ -117,11 +117,15 @@ struct GenNetLds {
 // One lattice block of the tiling: point tile bx, dimension chunk by,
 // replication r; thread t of GEN_THREADS.  With pairs (see GenGrid), a
 // thread writes dimensions j, j + 1 of its points as one 16-byte store.
+// ORDER >= 0 fixes the point order at compile time (it must equal a.order);
+// a tile whose last point is below n_max stores with no per-point test.
+template <int ORDER = -1>
 __device__ __forceinline__ void gen_lattice_block(const PointsetArgs &a, int64_t n_min,
                                                   int64_t n_max, int P, bool pairs,
                                                   uint64_t *__restrict__ out, int64_t bx, int by,
                                                   int r, int t)
 {
+    const int order = ORDER >= 0 ? ORDER : a.order;
     if (pairs) {
         const int j0 = by * GEN_DIM_CHUNK;
         const int DB2 = min(GEN_DIM_CHUNK, a.d - j0) >> 1;  // dimension pairs
@@ -135,14 +139,18 @@ __device__ __forceinline__ void gen_lattice_block(const PointsetArgs &a, int64_t
         const int64_t first = n_min + bx * P * GEN_ITERS + p;
         uint64_t *dst = out + ((size_t)r * cnt + (first - n_min)) * a.d + j;
         const size_t dstep = (size_t)P * a.d;
-        int64_t i = first;
-        for (int k = 0; k < GEN_ITERS && i < n_max; ++k) {
+        auto put = [&](int64_t i, uint64_t *dp) {
             ulonglong2 w;
-            w.x = lattice_point(g0, (uint64_t)i, a.order, a.m_max) + d0;
-            w.y = lattice_point(g1, (uint64_t)i, a.order, a.m_max) + d1;
-            *reinterpret_cast<ulonglong2 *>(dst) = w;
-            i += P;
-            dst += dstep;
+            w.x = lattice_point(g0, (uint64_t)i, order, a.m_max) + d0;
+            w.y = lattice_point(g1, (uint64_t)i, order, a.m_max) + d1;
+            *reinterpret_cast<ulonglong2 *>(dp) = w;
+        };
+        if (first + (int64_t)P * (GEN_ITERS - 1) < n_max) {
+#pragma unroll
+            for (int k = 0; k < GEN_ITERS; ++k) put(first + (int64_t)P * k, dst + dstep * k);
+        } else {
+            int64_t i = first;
+            for (int k = 0; k < GEN_ITERS && i < n_max; ++k, i += P, dst += dstep) put(i, dst);
         }
         return;
     }
@@ -159,7 +167,7 @@ __device__ __forceinline__ void gen_lattice_block(const PointsetArgs &a, int64_t
     const size_t dstep = (size_t)P * a.d;
     int64_t i = first;
     for (int k = 0; k < GEN_ITERS && i < n_max; ++k) {
-        *dst = lattice_point(g, (uint64_t)i, a.order, a.m_max) + delta;
+        *dst = lattice_point(g, (uint64_t)i, order, a.m_max) + delta;
         i += P;
         dst += dstep;
     }

@@ -38,8 +38,9 @@ def _windows(n):
 @pytest.mark.parametrize("kind,order", [("lattice", "natural"), ("lattice", "linear"),
                                         ("dnet", "natural"), ("dnet", "gray")])
 @pytest.mark.parametrize("dtype", [F64, F32])
+# d = 32 (even): 16-byte stores of dimension pairs, whole tiles of 512 points
 @pytest.mark.parametrize("m,d,R,alpha", [(13, 7, 2, 2), (12, 33, 3, "mixed"), (5, 70, 1, 1),
-                                         (0, 3, 2, 3)])
+                                         (0, 3, 2, 3), (11, 32, 2, 2)])
 def test_points_column_equals_separate_calls(orc, kind, order, dtype, m, d, R, alpha):
     amax = 4 if kind == "dnet" else 3
     al = [1 + (j % amax) for j in range(d)] if alpha == "mixed" else [alpha] * d
