@@ -1168,8 +1168,9 @@ def fp32_step_bench(K, kern, ps, w, y_host, c64):
 def c1_latency_bench(K):
     """The plain small problem (net n = 1024, d = 4, order-1 DSI kernel,
     sigma^2 = 1e-8): points, first column, eigenvalues, solve and log-det,
-    as one captured graph (device time per replay) and issued eagerly from
-    the host (wall time per call, synchronised)."""
+    as one captured graph (device time per replay, median and minimum over
+    five runs of K replays) and issued eagerly from the host (wall time per
+    call, synchronised)."""
     import numpy as np
     import torch
 
@@ -1198,7 +1199,9 @@ def c1_latency_bench(K):
         ldk.points_column(kern, ps, 0, n, pts=pts, k1=k1)
         ldk.fit("dnet", k1, w["sigma2"], y, lam=lam, c=c, logdet=ld, ws=ws)
 
-    ms_graph = time_graph(step, K)
+    # a replay takes about 20 us, so single runs of K replays scatter:
+    # the median of five runs is the figure
+    st = time_graph_stats(step, K)
     for _ in range(3):
         step()
     torch.cuda.synchronize()
@@ -1208,7 +1211,8 @@ def c1_latency_bench(K):
         torch.cuda.synchronize()
     eager_us = (time.perf_counter() - t0) / K * 1e6
     return {"workload": "net_m10_d4_dsi1 (LMS + shift, n=1024, d=4, order-1 DSI, "
-                        "sigma^2=1e-8)", "graph_us": round(ms_graph * 1e3, 2),
+                        "sigma^2=1e-8)", "graph_us": round(st["median"] * 1e3, 2),
+            "graph_us_min": round(st["min"] * 1e3, 2), "graph_runs": st["runs"],
             "eager_synchronised_us": round(eager_us, 1)}
 
 

@@ -231,6 +231,22 @@ __device__ __forceinline__ void gen_net_block(const PointsetArgs &a, int64_t n_m
         const uint64_t code0 = a.order == LDK_GRAY ? gray_code((uint64_t)first) : (uint64_t)first;
         uint64_t z0 = net_point(ct[jj], m, code0), z1 = net_point(ct[jj + 1], m, code0);
         uint64_t *const row = out + (size_t)r * cnt * a.d + j;
+        if (first >= n_min && first + (int64_t)P * (GEN_ITERS_NET - 1) < n_max) {
+            // the whole tile is inside the window: every point is stored
+            uint64_t *dst = row + (size_t)(first - n_min) * a.d;
+            const size_t dstep = (size_t)P * a.d;
+#pragma unroll 4
+            for (int k = 0; k < GEN_ITERS_NET; ++k) {
+                *reinterpret_cast<ulonglong2 *>(dst) = ulonglong2{z0 ^ d0, z1 ^ d1};
+                if (k + 1 < GEN_ITERS_NET) {
+                    const int c = ctz64(blk + (uint64_t)k + 1);
+                    z0 ^= step[jj][c];
+                    z1 ^= step[jj + 1][c];
+                }
+                dst += dstep;
+            }
+            return;
+        }
         int64_t i = first;
         for (int k = 0; k < GEN_ITERS_NET; ++k) {
             if (i >= n_min) {
